@@ -1,0 +1,135 @@
+/*
+ * pfch.h - C ABI of libpfch, a gfx950 (MI355X) implementation of the
+ * preconditioned Nesterov accelerated gradient descent (PAGD) solve inside
+ * each fully implicit second-order step of the phase field crystal (PFC) and
+ * functionalized Cahn-Hilliard (FCH) equations with periodic Fourier
+ * collocation (Park, Salgado & Wise, arXiv 2204.07247).
+ *
+ * Conventions
+ *  - All floating point is IEEE float64.  Fields are C-order real arrays
+ *    [Ny][Nx] (2D) with x fastest; n[0] = Nx, n[1] = Ny.
+ *  - Field pointers passed to pfch_set_state, pfch_get_state and pfch_solve
+ *    are DEVICE pointers to contiguous arrays of Nx*Ny doubles owned by the
+ *    caller.  The library never keeps a caller pointer after a call returns.
+ *  - All device work is ordered on the HIP stream given to pfch_create.
+ *    Calls that report statistics synchronise that stream before returning.
+ *  - Functions return PFCH_OK (0) or a negative error code; argument errors
+ *    are detected on the host before any device work is queued.
+ *  - One context per stream; calls on one context are not thread-safe.
+ */
+#ifndef PFCH_H
+#define PFCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PFCH_VERSION 1
+
+enum {
+  PFCH_OK = 0,
+  PFCH_E_INVAL = -1,       /* invalid argument or descriptor */
+  PFCH_E_NOMEM = -2,       /* device or host allocation failed */
+  PFCH_E_HIP = -3,         /* a HIP runtime call failed */
+  PFCH_E_NOCONV = -4,      /* PAGD reached max_iter without ||d||_inf < tol */
+  PFCH_E_NONFINITE = -5,   /* ||d||_inf became Inf or NaN */
+  PFCH_E_PRECOND = -6,     /* averaged-Newton symbol not positive on some mode */
+  PFCH_E_UNSUPPORTED = -7  /* valid but not supported (grid size, ndim) */
+};
+
+enum { PFCH_PFC = 0, PFCH_FCH = 1 };  /* model */
+enum { PFCH_BDF2 = 0, PFCH_MP = 1 };  /* fully implicit scheme */
+
+/*
+ * One simulation instance.  Model (Sec. 2 of the paper):
+ *   PFC: E = int u^4/4 + (1-eps) u^2/2 - |grad u|^2 + (Delta u)^2/2
+ *   FCH: E = int (eps^2 Delta u - F'(u))^2/2 - (eps^2 eta1 |grad u|^2/2 + eta2 F(u)),
+ *        F(z) = (z+1)^2 ((z-1)^2/2 + (2/3) tau (z-2)) / 2
+ * with d_t u = M Delta mu, M = mobility.  eta1 and eta2 are the
+ * coefficients as they stand in the energy (e.g. 1.45 eps and 2 eps).
+ * Scheme (Sec. 3.1): PFCH_BDF2 (variable-step BDF2, backward Euler on the
+ * first step) or PFCH_MP (implicit midpoint).
+ * Solver (Alg. 2): step size s, friction sweep eta[0..n_eta-1], stop when
+ * ||d_i||_inf < tol, at most max_iter iterations.  theta_l weights the
+ * beta_0/beta_2/beta_4 part of the averaged-Newton preconditioner
+ * (Sec. 3.4.1); 1.0 is the operator as printed.
+ * guess: 0 = extrapolated initial guess (the only value accepted so far).
+ * reserved must be 0.
+ */
+typedef struct pfch_instance_desc {
+  double len[3]; /* periods per axis, x first */
+  double eps, eta1, eta2, tau, mobility;
+  double s, tol, theta_l;
+  double eta[8];
+  int32_t model, scheme, ndim, n_eta, max_iter, guess;
+  int32_t n[3]; /* points per axis, x first; n[2] ignored for ndim = 2 */
+  int32_t reserved;
+} pfch_instance_desc;
+
+/* Per-instance result of one step or solve. */
+typedef struct pfch_stats {
+  double dnorm_inf; /* ||d||_inf of the last iteration */
+  double beta[4];   /* beta_-2, beta_0, beta_2, beta_4 used for this step */
+  double mass;      /* mean of the accepted solution (NaN if not computed) */
+  int32_t iters;    /* PAGD iterations */
+  int32_t fft_pairs;/* 2D transform pairs of real fields used (setup + iterations) */
+  int32_t status;   /* PFCH_OK or the error of this instance */
+  int32_t reserved;
+} pfch_stats;
+
+typedef struct pfch_ctx pfch_ctx; /* opaque; owned by the library */
+
+/* Host-only check of a descriptor; needs no GPU.  Returns PFCH_OK,
+ * PFCH_E_INVAL or PFCH_E_UNSUPPORTED. */
+int pfch_validate_desc(const pfch_instance_desc* desc);
+
+/* Create a context holding n_inst instances that advance together in each
+ * pfch_step.  `hip_stream` is a hipStream_t (NULL = default stream).  All
+ * workspaces, transform tables and launch graphs are allocated here and
+ * owned by the context.  The initial state of every instance is undefined
+ * until pfch_set_state. */
+int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_stream,
+                pfch_ctx** out);
+
+/* Set u^n (and u^{n-1}, or NULL when there is no history yet) of instance
+ * `inst` from device arrays; t, dt_prev (step that produced u^n, ignored when
+ * u_nm1 is NULL) and the step index n are host values.  The data are copied. */
+int pfch_set_state(pfch_ctx* ctx, int32_t inst, const double* u_n, const double* u_nm1,
+                   double t, double dt_prev, int32_t step_index);
+
+/* Copy the state of instance `inst` out; any pointer may be NULL.  u_nm1 is
+ * left untouched when the instance has no history. */
+int pfch_get_state(pfch_ctx* ctx, int32_t inst, double* u_n, double* u_nm1, double* t,
+                   double* dt_prev, int32_t* step_index);
+
+/* Advance every instance by one step of size dt[i] (host array of n_inst).
+ * Each step: coefficients (eq. obj:BDF2 / obj:MP), initial guess
+ * u^n + rho (u^n - u^{n-1}) with rho = dt/dt_prev (u^n on the first step),
+ * averaged-Newton constants at the guess, PAGD to ||d||_inf < tol.  An
+ * instance whose solve fails keeps its state (the step is transactional per
+ * instance); the return value is the first failing instance's code.
+ * `st` is a host array of n_inst or NULL. */
+int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st);
+
+/* Solve one step problem of instance `inst` with caller-given coefficients
+ * (a, b, c) of a u + b u^n + c u^{n-1} = M Delta mu(u_breve)
+ * (eq. eqn:FCH-fulldis-implicit); u_breve follows the instance's scheme.
+ * `x` holds the initial guess on entry and the solution on return (the last
+ * iterate on PFCH_E_NOCONV).  u_nm1 may be NULL when c == 0.  The instance's
+ * own state is not changed. */
+int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const double* u_n,
+               const double* u_nm1, double* x, pfch_stats* st);
+
+/* 0 disables the mass reduction that pfch_step performs when st != NULL. */
+int pfch_set_mass_stats(pfch_ctx* ctx, int32_t enabled);
+
+void pfch_destroy(pfch_ctx* ctx);
+const char* pfch_strerror(int code);
+int pfch_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFCH_H */

@@ -1,0 +1,234 @@
+// FP64 complex FFT building blocks for gfx950: register radix-2/3/4/8/16
+// butterflies and LDS-staged Stockham autosort passes.
+//
+// A transform of length N is carried out by a "team" of T = N / RMAX
+// threads.  Team thread t owns the elements k = t + m*T, m = 0..RMAX-1, both
+// on input (natural order, held in registers v[m]) and on output (natural
+// order, again in v[m]).  Between passes the data lives in LDS; the first
+// pass reads registers and the last pass writes registers, so a plan of P
+// passes costs P-1 LDS round trips.
+//
+// Pass with radix R after earlier passes of total length Ns (Stockham):
+//   butterfly j in [0, N/R) reads  x[j + r*N/R], r = 0..R-1,
+//   multiplies input r by w_N^{(j mod Ns) * r * N/(Ns*R)},  w_N = exp(-2 pi i/N),
+//   applies the R-point DFT and writes y[(j/Ns)*Ns*R + (j mod Ns) + r*Ns].
+// Thread t processes the butterflies j = t + q*T, q = 0..RMAX/R-1.
+//
+// Twiddles come from a per-length table tw[k] = exp(-2 pi i k / N) computed
+// on the host in long double; inverse transforms use conjugates.  Neither
+// direction is normalised.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace pfch {
+
+struct c2 {
+  double x, y;
+};
+
+__device__ __forceinline__ c2 cadd(c2 a, c2 b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ c2 csub(c2 a, c2 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ c2 cmul(c2 a, c2 b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ c2 cconj(c2 a) { return {a.x, -a.y}; }
+__device__ __forceinline__ c2 cscale(c2 a, double s) { return {a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ c2 mul_mi(c2 a) {
+  return INV ? c2{-a.y, a.x} : c2{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers.  Forward: X[k] = sum_n x[n] exp(-2 pi i n k / R).
+// ---------------------------------------------------------------------------
+template <bool INV>
+__device__ __forceinline__ void dft2(c2& a, c2& b) {
+  c2 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(c2* x) {
+  constexpr double H = 0.86602540378443864676372317075294;  // sqrt(3)/2
+  c2 t1 = cadd(x[1], x[2]);
+  c2 t2 = csub(x[1], x[2]);
+  c2 m = {x[0].x - 0.5 * t1.x, x[0].y - 0.5 * t1.y};
+  x[0] = cadd(x[0], t1);
+  // forward: X1 = m - i H t2, X2 = m + i H t2
+  c2 s = mul_mi<INV>(cscale(t2, H));
+  x[1] = cadd(m, s);
+  x[2] = csub(m, s);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(c2* x) {
+  c2 a0 = cadd(x[0], x[2]);
+  c2 a1 = csub(x[0], x[2]);
+  c2 b0 = cadd(x[1], x[3]);
+  c2 b1 = mul_mi<INV>(csub(x[1], x[3]));
+  x[0] = cadd(a0, b0);
+  x[2] = csub(a0, b0);
+  x[1] = cadd(a1, b1);
+  x[3] = csub(a1, b1);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(c2* x) {
+  constexpr double R = 0.70710678118654752440084436210485;  // sqrt(1/2)
+  c2 e[4] = {x[0], x[2], x[4], x[6]};
+  c2 o[4] = {x[1], x[3], x[5], x[7]};
+  dft4<INV>(e);
+  dft4<INV>(o);
+  // twiddles w8^k, k = 0..3 (forward w8 = exp(-i pi/4))
+  const double sg = INV ? 1.0 : -1.0;
+  c2 w1 = {R, sg * R}, w3 = {-R, sg * R};
+  o[1] = cmul(o[1], w1);
+  o[2] = mul_mi<INV>(o[2]);
+  o[3] = cmul(o[3], w3);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    x[k] = cadd(e[k], o[k]);
+    x[k + 4] = csub(e[k], o[k]);
+  }
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft16(c2* x) {
+  constexpr double C1 = 0.92387953251128675612818318939679;  // cos(pi/8)
+  constexpr double S1 = 0.38268343236508977172845998403040;  // sin(pi/8)
+  constexpr double R = 0.70710678118654752440084436210485;
+  c2 e[8], o[8];
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+    e[n] = x[2 * n];
+    o[n] = x[2 * n + 1];
+  }
+  dft8<INV>(e);
+  dft8<INV>(o);
+  const double sg = INV ? 1.0 : -1.0;
+  // w16^k = cos(k pi/8) + sg i sin(k pi/8)
+  const c2 w[8] = {{1.0, 0.0},      {C1, sg * S1},   {R, sg * R},     {S1, sg * C1},
+                   {0.0, sg * 1.0}, {-S1, sg * C1},  {-R, sg * R},    {-C1, sg * S1}};
+#pragma unroll
+  for (int k = 1; k < 8; ++k) o[k] = cmul(o[k], w[k]);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    x[k] = cadd(e[k], o[k]);
+    x[k + 8] = csub(e[k], o[k]);
+  }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(c2* x) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    dft2<INV>(x[0], x[1]);
+  } else if constexpr (R == 3) {
+    dft3<INV>(x);
+  } else if constexpr (R == 4) {
+    dft4<INV>(x);
+  } else if constexpr (R == 8) {
+    dft8<INV>(x);
+  } else if constexpr (R == 16) {
+    dft16<INV>(x);
+  } else {
+    static_assert(R == 16, "unsupported radix");
+  }
+}
+
+// LDS index with one pad element per 16 to break power-of-two strides.
+__device__ __forceinline__ int lds_idx(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_len(int n) { return n + (n >> 4) + 1; }
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// Plan: up to four passes; unused trailing radices are 1.
+template <int N_, int R1, int R2 = 1, int R3 = 1, int R4 = 1>
+struct Plan {
+  static constexpr int N = N_;
+  static constexpr int RMAX = cmax(cmax(R1, R2), cmax(R3, R4));
+  static constexpr int T = N / RMAX;
+  static constexpr int NPASS = (R2 == 1) ? 1 : (R3 == 1) ? 2 : (R4 == 1) ? 3 : 4;
+  static_assert(R1 * R2 * R3 * R4 == N, "radices must multiply to N");
+  static_assert(N % RMAX == 0, "bad plan");
+  static constexpr int radix(int p) { return p == 0 ? R1 : p == 1 ? R2 : p == 2 ? R3 : R4; }
+  static constexpr int ns(int p) {
+    return p == 0 ? 1 : p == 1 ? R1 : p == 2 ? R1 * R2 : R1 * R2 * R3;
+  }
+};
+
+// One Stockham pass.  FROM_REG / TO_REG select registers or LDS as source
+// and destination.  `lds` is the team's buffer of lds_len(N) elements.
+template <class P, int PASS, bool INV, bool FROM_REG, bool TO_REG>
+__device__ __forceinline__ void stockham_pass(c2 (&v)[P::RMAX], c2* lds, const c2* __restrict__ tw,
+                                              int t) {
+  constexpr int N = P::N, T = P::T, RMAX = P::RMAX;
+  constexpr int R = P::radix(PASS);
+  constexpr int NS = P::ns(PASS);
+  constexpr int QN = RMAX / R;  // butterflies per thread
+  constexpr int STRIDE = N / R;
+  c2 x[RMAX];
+  // gather inputs
+#pragma unroll
+  for (int q = 0; q < QN; ++q) {
+    const int j = t + q * T;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if constexpr (FROM_REG) {
+        x[q * R + r] = v[q + r * QN];
+      } else {
+        x[q * R + r] = lds[lds_idx(j + r * STRIDE)];
+      }
+    }
+  }
+  if constexpr (!FROM_REG && !TO_REG) __syncthreads();  // all reads before in-place writes
+#pragma unroll
+  for (int q = 0; q < QN; ++q) {
+    const int j = t + q * T;
+    if constexpr (NS > 1) {
+      const int jm = j % NS;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        c2 w = tw[jm * r * (N / (NS * R))];
+        if (INV) w.y = -w.y;
+        x[q * R + r] = cmul(x[q * R + r], w);
+      }
+    }
+    dft<R, INV>(&x[q * R]);
+    if constexpr (TO_REG) {
+      // last pass: outputs at j + r*N/R, i.e. register q + r*QN
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q + r * QN] = x[q * R + r];
+    } else {
+      const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lds_idx(base + r * NS)] = x[q * R + r];
+    }
+  }
+}
+
+// Full transform: registers in, registers out.  Every thread of the block
+// must call this (it contains block-wide barriers).
+template <class P, bool INV>
+__device__ __forceinline__ void fft(c2 (&v)[P::RMAX], c2* lds, const c2* __restrict__ tw, int t) {
+  if constexpr (P::NPASS == 1) {
+    stockham_pass<P, 0, INV, true, true>(v, lds, tw, t);
+  } else {
+    stockham_pass<P, 0, INV, true, false>(v, lds, tw, t);
+    __syncthreads();
+    if constexpr (P::NPASS >= 3) {
+      stockham_pass<P, 1, INV, false, false>(v, lds, tw, t);
+      __syncthreads();
+    }
+    if constexpr (P::NPASS >= 4) {
+      stockham_pass<P, 2, INV, false, false>(v, lds, tw, t);
+      __syncthreads();
+    }
+    stockham_pass<P, P::NPASS - 1, INV, false, true>(v, lds, tw, t);
+    __syncthreads();  // LDS free for reuse on return
+  }
+}
+
+}  // namespace pfch

@@ -1,0 +1,59 @@
+// Device-side instance descriptor shared by the kernels and the host runtime.
+#pragma once
+#include <cstdint>
+
+#include "fft.hpp"
+
+namespace pfch {
+
+enum { MODEL_PFC = 0, MODEL_FCH = 1 };
+enum { SCHEME_BDF2 = 0, SCHEME_MP = 1 };
+enum { FLAG_PRECOND = 1 };
+
+constexpr uint64_t INF_BITS = 0x7ff0000000000000ull;
+
+// Per-instance stop record, written by the chunk-end kernel.
+struct StopRec {
+  int32_t stop_iter;   // -1 while running; j when ||d_j|| decided the stop;
+                       // max_iter when the iteration cap was reached
+  int32_t flags;       // FLAG_PRECOND
+  uint64_t norm_bits;  // ||d_j||_inf as IEEE bits at the stop
+};
+
+struct InstDev {
+  // geometry (2D: nz = 1)
+  int32_t nx, ny, nz, nh;  // nh = nx/2 + 1
+  int32_t model, scheme;
+  int32_t rows;            // ny * nz: number of x-rows
+  int32_t nparts;          // partial-sum slots written by the setup row kernel
+  double kx_scale, ky_scale, kz_scale;  // 2 pi / L per axis
+  double inv_p;            // 1 / (nx ny nz)
+  // model
+  double eps, eta1, eta2, tau, mobility;
+  // solver
+  double s, theta_l;
+  double lam[8];
+  int32_t n_eta, max_iter;
+  uint64_t tol_bits;
+  // per step (written by the setup kernel, read by the iteration kernels)
+  double a, theta, a_over_theta;
+  const double* un;        // u^n used by the midpoint blend
+  // state buffers
+  double* X[3];            // iterate ring x_j at X[j % 3]
+  double* DX[3];           // FCH: Laplacian of the iterate, same ring
+  double* dun;             // FCH midpoint: Laplacian of u^n
+  c2* S;                   // spectral rows [field][rows][nh]
+  c2* G;                   // setup spectral rows [field][rows][nh]
+  c2* ghat;                // transformed step constant g, [rows][nh]
+  double* part;            // setup partial sums [nparts][2]
+  uint64_t* norms;         // ||d_j||_inf bits, [max_iter]
+  int32_t* iter_base;      // first iteration index of the current chunk
+  int32_t* flags;          // FLAG_* bits raised by kernels
+  StopRec* rec;
+  const c2* tw_x;          // twiddles for the x length
+  const c2* tw_y;          // twiddles for the y length
+  const c2* tw_z;          // twiddles for the z length (3D)
+  int64_t field_stride;    // rows * nh
+};
+
+}  // namespace pfch

@@ -1,0 +1,218 @@
+"""ctypes binding of libpfch (include/pfch.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Device arrays are torch tensors (float64, contiguous, on the GPU); their
+``data_ptr()`` and the current torch stream are handed to the C ABI.
+"""
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpfch.so")
+
+PFCH_OK = 0
+PFCH_E_INVAL = -1
+PFCH_E_NOMEM = -2
+PFCH_E_HIP = -3
+PFCH_E_NOCONV = -4
+PFCH_E_NONFINITE = -5
+PFCH_E_PRECOND = -6
+PFCH_E_UNSUPPORTED = -7
+
+PFC, FCH = 0, 1
+BDF2, MP = 0, 1
+
+PAPER_ETAS = tuple(math.sqrt(v) for v in (0.1, 0.575, 1.05, 1.525, 2.0))
+
+EXPORTED = (
+    "pfch_validate_desc", "pfch_create", "pfch_set_state", "pfch_get_state",
+    "pfch_step", "pfch_solve", "pfch_set_mass_stats", "pfch_destroy",
+    "pfch_strerror", "pfch_version",
+)
+
+
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [
+        ("len", ctypes.c_double * 3),
+        ("eps", ctypes.c_double), ("eta1", ctypes.c_double), ("eta2", ctypes.c_double),
+        ("tau", ctypes.c_double), ("mobility", ctypes.c_double),
+        ("s", ctypes.c_double), ("tol", ctypes.c_double), ("theta_l", ctypes.c_double),
+        ("eta", ctypes.c_double * 8),
+        ("model", ctypes.c_int32), ("scheme", ctypes.c_int32), ("ndim", ctypes.c_int32),
+        ("n_eta", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("guess", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("dnorm_inf", ctypes.c_double),
+        ("beta", ctypes.c_double * 4),
+        ("mass", ctypes.c_double),
+        ("iters", ctypes.c_int32),
+        ("fft_pairs", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return dict(iters=self.iters, status=self.status, dnorm=self.dnorm_inf,
+                    betas=tuple(self.beta), mass=self.mass, fft_pairs=self.fft_pairs)
+
+
+class PfchError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libpfch.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2204_07247_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.pfch_validate_desc.argtypes = [ctypes.POINTER(InstanceDesc)]
+        L.pfch_create.argtypes = [ctypes.POINTER(InstanceDesc), i32, vp, ctypes.POINTER(vp)]
+        L.pfch_set_state.argtypes = [vp, i32, vp, vp, dbl, dbl, i32]
+        L.pfch_get_state.argtypes = [vp, i32, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                     ctypes.POINTER(i32)]
+        L.pfch_step.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(Stats)]
+        L.pfch_solve.argtypes = [vp, i32, dbl, dbl, dbl, vp, vp, vp, ctypes.POINTER(Stats)]
+        L.pfch_set_mass_stats.argtypes = [vp, i32]
+        L.pfch_destroy.argtypes = [vp]
+        L.pfch_destroy.restype = None
+        L.pfch_strerror.argtypes = [ctypes.c_int]
+        L.pfch_strerror.restype = ctypes.c_char_p
+        L.pfch_version.argtypes = []
+        for name in ("pfch_validate_desc", "pfch_create", "pfch_set_state", "pfch_get_state",
+                     "pfch_step", "pfch_solve", "pfch_set_mass_stats", "pfch_version"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    return lib().pfch_strerror(int(code)).decode()
+
+
+def make_desc(model, scheme, shape, lengths, eps, eta1=0.0, eta2=0.0, tau=0.0,
+              mobility=1.0, s=0.9, etas=PAPER_ETAS, tol=1e-10, max_iter=1000,
+              theta_l=1.0):
+    """Descriptor from plain values.  ``shape``/``lengths`` are in array
+    order ((Ny, Nx) in 2D); the C struct stores them x first."""
+    d = InstanceDesc()
+    nd = len(shape)
+    for a in range(nd):
+        d.n[a] = int(shape[nd - 1 - a])
+        d.len[a] = float(lengths[nd - 1 - a])
+    d.ndim = nd
+    d.model = {"pfc": PFC, "fch": FCH}.get(model, model)
+    d.scheme = {"bdf2": BDF2, "mp": MP}.get(scheme, scheme)
+    d.eps, d.eta1, d.eta2, d.tau, d.mobility = eps, eta1, eta2, tau, mobility
+    d.s, d.tol, d.theta_l = s, tol, theta_l
+    etas = tuple(etas)
+    d.n_eta = len(etas)
+    for i, e in enumerate(etas):
+        d.eta[i] = e
+    d.max_iter = int(max_iter)
+    d.guess = 0
+    d.reserved = 0
+    return d
+
+
+def validate_desc(desc):
+    return lib().pfch_validate_desc(ctypes.byref(desc))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError("expected a contiguous GPU tensor")
+    import torch
+    if t.dtype != torch.float64:
+        raise ValueError("expected float64")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A set of instances that advance together (pfch_create ... pfch_destroy)."""
+
+    def __init__(self, descs, stream=None):
+        L = lib()
+        if isinstance(descs, InstanceDesc):
+            descs = [descs]
+        self.n = len(descs)
+        arr = (InstanceDesc * self.n)(*descs)
+        self._descs = arr
+        h = ctypes.c_void_p()
+        s = _stream_handle() if stream is None else ctypes.c_void_p(stream)
+        rc = L.pfch_create(arr, self.n, s, ctypes.byref(h))
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pfch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_mass_stats(self, enabled):
+        lib().pfch_set_mass_stats(self._h, int(bool(enabled)))
+
+    def set_state(self, inst, u_n, u_nm1=None, t=0.0, dt_prev=0.0, step_index=0):
+        rc = lib().pfch_set_state(self._h, inst, _ptr(u_n), _ptr(u_nm1), float(t),
+                                  float(dt_prev), int(step_index))
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_set_state")
+
+    def get_state(self, inst, u_n=None, u_nm1=None):
+        t = ctypes.c_double()
+        dtp = ctypes.c_double()
+        n = ctypes.c_int32()
+        rc = lib().pfch_get_state(self._h, inst, _ptr(u_n), _ptr(u_nm1), ctypes.byref(t),
+                                  ctypes.byref(dtp), ctypes.byref(n))
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_get_state")
+        return t.value, dtp.value, n.value
+
+    def step(self, dt, stats=True):
+        """One step of every instance; returns (code, [stats dict per instance])."""
+        if isinstance(dt, (int, float)):
+            dt = [float(dt)] * self.n
+        dts = (ctypes.c_double * self.n)(*dt)
+        st = (Stats * self.n)() if stats else None
+        rc = lib().pfch_step(self._h, dts, st)
+        if rc in (PFCH_E_INVAL, PFCH_E_NOMEM, PFCH_E_HIP, PFCH_E_UNSUPPORTED):
+            raise PfchError(rc, "pfch_step")
+        return rc, ([s.as_dict() for s in st] if stats else None)
+
+    def solve(self, inst, a, b, c, u_n, u_nm1, x):
+        st = Stats()
+        rc = lib().pfch_solve(self._h, inst, float(a), float(b), float(c), _ptr(u_n),
+                              _ptr(u_nm1), _ptr(x), ctypes.byref(st))
+        if rc in (PFCH_E_INVAL, PFCH_E_NOMEM, PFCH_E_HIP, PFCH_E_UNSUPPORTED):
+            raise PfchError(rc, "pfch_solve")
+        return rc, st.as_dict()

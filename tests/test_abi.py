@@ -1,0 +1,91 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared
+symbol and validates descriptors without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfch.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pfch_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2204_07247_amd import pfch
+    L = pfch.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(pfch.EXPORTED)
+
+
+def test_version_and_strerror():
+    from paper_2204_07247_amd import pfch
+    assert pfch.lib().pfch_version() == 1
+    assert "max_iter" in pfch.strerror(pfch.PFCH_E_NOCONV)
+    assert pfch.strerror(12345) == "unknown error"
+
+
+def test_struct_sizes_match_header_layout():
+    from paper_2204_07247_amd import pfch
+    # 3 + 5 + 3 + 8 doubles, then 6 + 3 + 1 int32
+    assert ctypes.sizeof(pfch.InstanceDesc) == 19 * 8 + 10 * 4
+    assert ctypes.sizeof(pfch.Stats) == 6 * 8 + 4 * 4
+
+
+def _desc(**kw):
+    from paper_2204_07247_amd import pfch
+    base = dict(model="pfc", scheme="mp", shape=(64, 64), lengths=(64.0, 64.0), eps=0.25)
+    base.update(kw)
+    return pfch.make_desc(**base)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(), 0),
+    (dict(model="fch", eps=0.1, eta1=0.145, eta2=0.2), 0),
+    (dict(shape=(2048, 8), lengths=(1.0, 1.0)), 0),
+    (dict(shape=(64, 100)), -7),
+    (dict(shape=(4096, 64)), -7),
+    (dict(shape=(8, 8, 8), lengths=(1.0, 1.0, 1.0)), -7),
+    (dict(s=0.0), -1),
+    (dict(tol=-1.0), -1),
+    (dict(max_iter=0), -1),
+    (dict(etas=()), -1),
+    (dict(lengths=(0.0, 1.0)), -1),
+    (dict(model="fch", eps=0.0), -1),
+    (dict(mobility=float("nan")), -1),
+])
+def test_descriptor_validation(kw, code):
+    from paper_2204_07247_amd import pfch
+    assert pfch.validate_desc(_desc(**kw)) == code
+
+
+def test_invalid_model_and_reserved_fields():
+    from paper_2204_07247_amd import pfch
+    d = _desc()
+    d.model = 7
+    assert pfch.validate_desc(d) == pfch.PFCH_E_INVAL
+    d = _desc()
+    d.reserved = 1
+    assert pfch.validate_desc(d) == pfch.PFCH_E_INVAL
+    d = _desc()
+    d.guess = 1
+    assert pfch.validate_desc(d) == pfch.PFCH_E_UNSUPPORTED
+
+
+def test_create_rejects_bad_arguments_before_device_work():
+    from paper_2204_07247_amd import pfch
+    L = pfch.lib()
+    h = ctypes.c_void_p()
+    d = _desc(s=-1.0)
+    assert L.pfch_create(ctypes.byref(d), 1, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
+    assert L.pfch_create(ctypes.byref(_desc()), 0, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
+    assert L.pfch_step(None, None, None) == pfch.PFCH_E_INVAL
+    assert L.pfch_set_mass_stats(None, 1) == pfch.PFCH_E_INVAL

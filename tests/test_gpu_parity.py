@@ -1,0 +1,128 @@
+"""GPU path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Bar: per-step PAGD iteration counts identical, relative L2 difference of the
+solution <= 1e-9 (the tolerance the method's description fixes for FP64).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import pagd as opagd
+from oracle import schemes as oschemes
+from tests._common import desc_for, oracle_run, oracle_sim, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def run_gpu(w, u0, nsteps, descs=None, **over):
+    torch = _torch()
+    from paper_2204_07247_amd import pfch
+    ctx = pfch.Context([desc_for(w, **over)])
+    u = torch.from_numpy(u0).cuda()
+    ctx.set_state(0, u)
+    iters = []
+    for _ in range(nsteps):
+        rc, st = ctx.step(w.dt)
+        assert rc == pfch.PFCH_OK, (rc, st)
+        iters.append(st[0]["iters"])
+    out = torch.empty_like(u)
+    ctx.get_state(0, out)
+    ctx.close()
+    return out.cpu().numpy(), iters
+
+
+SOLVE_CASES = [
+    # (workload, shape override, lengths override)
+    (W.PFC64_MP, (64, 64), (64.0, 64.0)),
+    (W.PFC64_MP, (32, 64), (32.0, 64.0)),
+    (W.PFC64_MP, (16, 8), (16.0, 8.0)),
+    (W.PFC64_MP, (128, 256), (128.0, 256.0)),
+    (W.FCH256_BDF2, (256, 256), None),
+    (W.FCH256_BDF2, (64, 32), None),
+    (dataclasses.replace(W.FCH256_BDF2, scheme="mp"), (32, 64), None),
+    (dataclasses.replace(W.PFC64_MP, scheme="bdf2"), (64, 128), (64.0, 128.0)),
+]
+
+
+@pytest.mark.parametrize("w,shape,lengths", SOLVE_CASES, ids=lambda v: str(v) if not hasattr(v, "name") else v.name)
+def test_single_solve_matches_oracle(w, shape, lengths):
+    """pfch_solve with the oracle's coefficients and initial guess."""
+    torch = _torch()
+    from paper_2204_07247_amd import pfch
+    w = dataclasses.replace(w, shape=shape, lengths=lengths or w.lengths)
+    print(f"case {w.name} {shape}", flush=True)
+    g, m, sim = oracle_sim(w)
+    u0 = W.initial_condition(w)
+    dt = w.dt
+    a, b, c, th = oschemes.coefficients(w.scheme, dt, None)
+    ref = sim.step(u0, None, dt, None)
+    assert ref["status"] == opagd.OK
+    ctx = pfch.Context([desc_for(w)])
+    un = torch.from_numpy(u0).cuda()
+    x = un.clone()
+    rc, st = ctx.solve(0, a, b, c, un, None, x)
+    ctx.close()
+    assert rc == pfch.PFCH_OK
+    assert st["iters"] == ref["iters"]
+    got = x.cpu().numpy()
+    assert rel_l2(got, ref["x"]) <= 1e-9
+    assert np.allclose(st["betas"], ref["betas"], rtol=1e-12, atol=0)
+    assert abs(np.mean(got) - np.mean(u0)) < 1e-13
+
+
+@pytest.mark.parametrize("w,nsteps", [(W.PFC64_MP, 20), (W.FCH256_BDF2, 20)], ids=["pfc64_mp", "fch256_bdf2"])
+def test_trajectory_matches_oracle(w, nsteps):
+    """Twenty steps through pfch_step: identical iteration counts, rel L2 <= 1e-9."""
+    u0 = W.initial_condition(w)
+    print(f"case {w.name} steps={nsteps}", flush=True)
+    ref, ref_iters = oracle_run(w, u0, nsteps)
+    got, iters = run_gpu(w, u0, nsteps)
+    assert iters == ref_iters
+    assert rel_l2(got, ref) <= 1e-9
+
+
+def test_two_runs_are_bitwise_identical():
+    w = W.FCH256_BDF2
+    u0 = W.initial_condition(w, seed=3)
+    a, _ = run_gpu(w, u0, 4)
+    b, _ = run_gpu(w, u0, 4)
+    assert np.array_equal(a, b)
+
+
+def test_failure_modes_leave_state_untouched():
+    torch = _torch()
+    from paper_2204_07247_amd import pfch
+    w = dataclasses.replace(W.PFC64_MP, shape=(16, 16), lengths=(2 * np.pi, 2 * np.pi))
+    u0 = 0.01 * np.random.default_rng(0).uniform(-1, 1, (16, 16))
+    # iteration cap
+    ctx = pfch.Context([desc_for(w, max_iter=1)])
+    u = torch.from_numpy(u0).cuda()
+    ctx.set_state(0, u)
+    rc, st = ctx.step(0.1)
+    assert rc == pfch.PFCH_E_NOCONV and st[0]["status"] == pfch.PFCH_E_NOCONV
+    out = torch.empty_like(u)
+    t, _, n = ctx.get_state(0, out)
+    assert n == 0 and t == 0.0 and torch.equal(out, u)
+    ctx.close()
+    # averaged-Newton symbol not positive (BDF2/BE with a = 0.01)
+    w2 = dataclasses.replace(w, scheme="bdf2")
+    ctx = pfch.Context([desc_for(w2)])
+    ctx.set_state(0, u)
+    rc, st = ctx.step(100.0)
+    assert rc == pfch.PFCH_E_PRECOND
+    ctx.close()
+    # non-finite data
+    bad = u0.copy()
+    bad[3, 4] = np.nan
+    ctx = pfch.Context([desc_for(w)])
+    ctx.set_state(0, torch.from_numpy(bad).cuda())
+    rc, st = ctx.step(0.1)
+    assert rc in (pfch.PFCH_E_NONFINITE, pfch.PFCH_E_PRECOND)
+    ctx.close()
