@@ -1,0 +1,185 @@
+"""Throughput of the PAGD-solved fully implicit steps on one MI355X.
+
+Default workload: FCH 2D 256 x 256 on [0, 4 pi)^2, eps = 0.1, eta1 = 0.145,
+eta2 = 0.2, tau = 0, u0 = -0.6 + 0.01 U(-1, 1) (seed 0), BDF2 (backward Euler
+first step), dt = 1e-3, PAGD to ||d||_inf < 1e-10; one bench step = one time
+step.  The timed region runs `--steps` consecutive time steps from u0 with all
+data resident on the GPU, bracketed by torch.cuda.synchronize().
+
+Prints one JSON line (metric, value in time-steps/s, iterations per step,
+roofline of the dominant kernel from HIP-event timings, CPU-oracle baseline).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+METRIC = "time-steps/sec & PAGD iters/step at 1e-10 residual: plain vs batched+learned"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "fch256": W.FCH256_BDF2,
+    "pfc64": W.PFC64_MP,
+    "pfc1024": W.Workload(
+        name="pfc2d_1024_mp", model="pfc", scheme="mp", shape=(1024, 1024),
+        lengths=(1024.0, 1024.0), dt=0.2, steps=500, mean=-0.25, amp=0.05, eps=0.25),
+    "fch2048": W.scaled(W.FCH256_BDF2, name="fch2d_2048_bdf2", shape=(2048, 2048), steps=300),
+    "fch1024": W.scaled(W.FCH256_BDF2, name="fch2d_1024_bdf2", shape=(1024, 1024), steps=300),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(w):
+    """Compulsory HBM bytes per launch of the two iteration kernels.
+
+    Real field: Ny*Nx doubles.  Spectral field: Ny*(Nx/2+1) complex doubles.
+    PFC row kernel: read 1 spectral + x_j, x_{j-1} (+ u^n for MP), write
+    x_{j+1} + 2 spectral.  PFC column kernel: read 2 spectral + g^, write 1.
+    FCH row kernel: read 2 spectral + x_j, x_{j-1}, Lx_j, Lx_{j-1} (+ u^n,
+    Lu^n for MP), write x_{j+1}, Lx_{j+1} + 3 spectral.  FCH column kernel:
+    read 3 spectral + g^, write 2 spectral.
+    """
+    ny, nx = w.shape
+    real = 8 * nx * ny
+    spec = 16 * ny * (nx // 2 + 1)
+    mp = w.scheme == "mp"
+    if w.model == "pfc":
+        row = spec + 2 * real + (real if mp else 0) + real + 2 * spec
+        col = 2 * spec + spec + spec
+    else:
+        row = 2 * spec + 4 * real + (2 * real if mp else 0) + 2 * real + 3 * spec
+        col = 3 * spec + spec + 2 * spec
+    return dict(row=row, col=col)
+
+
+def gpu_run(w, steps, warmup, kernel_timing):
+    import torch
+    from paper_2204_07247_amd import pfch
+
+    d = pfch.make_desc(w.model, w.scheme, w.shape, w.lengths, eps=w.eps, eta1=w.eta1,
+                       eta2=w.eta2, tau=w.tau, mobility=w.mobility, s=w.s, etas=w.etas,
+                       tol=w.tol, max_iter=w.max_iter)
+    ctx = pfch.Context([d])
+    ctx.set_stats_detail(0)
+    u0 = torch.from_numpy(W.initial_condition(w)).cuda()
+
+    def run(n):
+        ctx.set_state(0, u0)
+        iters = []
+        for _ in range(n):
+            rc, st = ctx.step(w.dt)
+            if rc != pfch.PFCH_OK:
+                raise RuntimeError(f"step failed: {pfch.strerror(rc)}")
+            iters.append(st[0]["iters"])
+        return iters
+
+    log(f"[bench] warmup {warmup} steps")
+    run(warmup)
+    torch.cuda.synchronize()
+    log(f"[bench] timed region: {steps} steps")
+    t0 = time.perf_counter()
+    iters = run(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"[bench] timed region done: {elapsed:.4f} s")
+    timing = None
+    if kernel_timing:
+        log("[bench] kernel timing pass (HIP events around each iteration kernel)")
+        ctx.set_kernel_timing(True)
+        run(steps)
+        torch.cuda.synchronize()
+        timing = ctx.kernel_timing()
+        ctx.set_kernel_timing(False)
+    cfg = ctx.launch_config()
+    ctx.close()
+    return elapsed, iters, timing, cfg
+
+
+def cpu_baseline(w, max_steps, budget_s):
+    """The CPU oracle on the same workload, first steps of the same trajectory."""
+    from oracle import driver, models, spectral
+    g = spectral.Grid(w.shape, w.lengths)
+    m = models.make_model(w.model, **w.params())
+    sim = driver.Simulation(g, m, w.scheme, s=w.s, etas=w.etas, tol=w.tol, max_iter=w.max_iter)
+    u, up, dto = W.initial_condition(w), None, None
+    t0 = time.perf_counter()
+    n = 0
+    while n < max_steps and time.perf_counter() - t0 < budget_s:
+        out = sim.step(u, up, w.dt, dto)
+        up, u, dto = u, out["x"], w.dt
+        n += 1
+    el = time.perf_counter() - t0
+    return dict(value=n / el, unit="time-steps/s", cores=1, kind="oracle",
+                sample=f"first {n} of {max_steps} steps of {w.name} (seed {w.seeds[0]}), "
+                       f"{el:.1f} s, NumPy float64 pocketfft, single thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="fch256", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); independent "
+              "instances shard across GPUs without communication, see DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+    w = WORKLOADS[args.workload]
+    elapsed, iters, timing, cfg = gpu_run(w, args.steps, args.warmup, not args.no_kernel_timing)
+    value = args.steps / elapsed
+    ab = algorithmic_bytes(w)
+    roof = None
+    kernels = {}
+    if timing:
+        for k in ("row", "col"):
+            n = timing[f"{k}_launches"]
+            if n:
+                avg = timing[f"{k}_ms"] / n * 1e-3
+                kernels[k] = dict(avg_us=avg * 1e6, launches=n, alg_bytes=ab[k],
+                                  achieved_gbs=ab[k] / avg / 1e9)
+        if kernels:
+            dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+            kd = kernels[dom]
+            roof = dict(bound="hbm", kernel=f"k_{dom}_iter", achieved=round(kd["achieved_gbs"], 2),
+                        peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4), traffic=None)
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(w, w.steps, args.cpu_budget)
+    it = np.array(iters)
+    fft_pairs = {"pfc": 1.5, "fch": 2.5}[w.model]
+    out = dict(
+        metric=METRIC, value=round(value, 3), unit="time-steps/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(1e3 * elapsed / args.steps, 4),
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=w.name, grid=list(w.shape), lengths=list(w.lengths),
+                    scheme=w.scheme, dt=w.dt, tol=w.tol, s=w.s, seed=w.seeds[0]),
+        iters_per_step=dict(mean=round(float(it.mean()), 3), min=int(it.min()), max=int(it.max())),
+        fft_pairs_per_iter=fft_pairs,
+        roofline=roof, kernels=kernels, launch=cfg, cpu_baseline=cpu,
+    )
+    if cpu:
+        out["gpu_over_cpu"] = round(value / cpu["value"], 2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -122,8 +122,24 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st);
 int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const double* u_n,
                const double* u_nm1, double* x, pfch_stats* st);
 
-/* 0 disables the mass reduction that pfch_step performs when st != NULL. */
-int pfch_set_mass_stats(pfch_ctx* ctx, int32_t enabled);
+/* Statistics detail of pfch_step when st != NULL: 0 = iterations, status and
+ * ||d||_inf only (read from the convergence records, no extra
+ * synchronisation); 1 (default) = also beta and the mass of the accepted
+ * solution (one extra reduction and synchronisation per step). */
+int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail);
+
+/* Kernel timing for measurement.  While enabled, the iteration graphs carry
+ * HIP event nodes around every column and row kernel of instance 0, and each
+ * iteration that did work adds its two kernel durations to running totals.
+ * pfch_get_kernel_timing returns {column total ms, column launches, row total
+ * ms, row launches} and resets the totals.  Enabling costs a few microseconds
+ * per kernel; leave it off for throughput measurements. */
+int pfch_set_kernel_timing(pfch_ctx* ctx, int32_t enabled);
+int pfch_get_kernel_timing(pfch_ctx* ctx, double out[4]);
+
+/* Launch geometry of instance `inst` for reporting: {row grid, row block,
+ * row LDS bytes, column grid, column block, column LDS bytes}. */
+int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]);
 
 void pfch_destroy(pfch_ctx* ctx);
 const char* pfch_strerror(int code);

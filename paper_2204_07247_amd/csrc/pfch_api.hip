@@ -191,9 +191,12 @@ struct pfch_ctx {
   StopRec* h_recs = nullptr;   // pinned
   double* h_mass = nullptr;    // pinned [n]
   std::map<int, c2*> twiddles;
-  std::map<int, hipGraphExec_t> graphs;
+  std::map<int, hipGraphExec_t> graphs;       // key: chunk length K (negative: timed)
+  std::map<int, std::vector<hipEvent_t>> graph_events;  // timed graphs' event nodes
   std::vector<hipGraph_t> graph_defs;
-  bool mass_stats = true;
+  int stats_detail = 1;
+  bool timing = false;
+  double time_tot[4] = {0, 0, 0, 0};  // column ms, column launches, row ms, row launches
   std::vector<void*> allocs;
 };
 
@@ -381,9 +384,11 @@ int launch(const void* f, dim3 g, dim3 b, size_t lds, void** args, hipStream_t s
 }
 
 // Build (once per chunk length) a graph running `K` iterations of every
-// instance, then the chunk-end bookkeeping.
-int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
-  auto it = ctx->graphs.find(K);
+// instance, then the chunk-end bookkeeping.  A timed graph also records an
+// event before, between and after instance 0's kernels of every iteration.
+int get_graph(pfch_ctx* ctx, int K, bool timed, hipGraphExec_t* out) {
+  const int key = timed ? -K : K;
+  auto it = ctx->graphs.find(key);
   if (it != ctx->graphs.end()) {
     *out = it->second;
     return PFCH_OK;
@@ -391,9 +396,23 @@ int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
   hipGraph_t g;
   HIPCHK(hipGraphCreate(&g, 0));
   std::vector<hipGraphNode_t> tails;
+  std::vector<hipEvent_t> events;
+  auto add_event = [&](hipGraphNode_t* prev) -> int {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    events.push_back(e);
+    hipGraphNode_t node;
+    HIPCHK(hipGraphAddEventRecordNode(&node, g, *prev ? prev : nullptr, *prev ? 1 : 0, e));
+    *prev = node;
+    return PFCH_OK;
+  };
   // Kernel arguments are copied into the node at creation time.
-  for (auto& I : ctx->inst) {
+  for (size_t ii = 0; ii < ctx->inst.size(); ++ii) {
+    Instance& I = ctx->inst[ii];
+    const bool ev = timed && ii == 0;
     hipGraphNode_t prev = nullptr;
+    int rc;
+    if (ev && (rc = add_event(&prev))) return rc;
     for (int l = 0; l < K; ++l) {
       for (int half = 0; half < 2; ++half) {
         hipKernelNodeParams p{};
@@ -409,6 +428,7 @@ int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
         hipGraphNode_t node;
         HIPCHK(hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p));
         prev = node;
+        if (ev && (rc = add_event(&prev))) return rc;
       }
     }
     tails.push_back(prev);
@@ -430,7 +450,8 @@ int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
   hipGraphExec_t ex;
   HIPCHK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
   ctx->graph_defs.push_back(g);
-  ctx->graphs[K] = ex;
+  ctx->graphs[key] = ex;
+  if (timed) ctx->graph_events[key] = events;
   *out = ex;
   return PFCH_OK;
 }
@@ -481,14 +502,34 @@ int run_iterations(pfch_ctx* ctx, const std::vector<int>& active) {
   for (int i : active) predicted = std::max(predicted, ctx->inst[i].last_iters + 1);
   int K = chunk_len(predicted);
   const int n = (int)ctx->inst.size();
+  const bool timed = ctx->timing && !active.empty() && active[0] == 0;
+  int base0 = 0;  // host copy of instance 0's iteration base
   for (;;) {
     hipGraphExec_t ex;
-    int rc = get_graph(ctx, K, &ex);
+    int rc = get_graph(ctx, K, timed, &ex);
     if (rc) return rc;
     HIPCHK(hipGraphLaunch(ex, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->h_recs, ctx->d_recs, sizeof(StopRec) * n, hipMemcpyDeviceToHost,
                           ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (timed) {
+      const std::vector<hipEvent_t>& ev = ctx->graph_events[-K];
+      const StopRec& r = ctx->h_recs[0];
+      const int maxit = ctx->inst[0].d.max_iter;
+      for (int l = 0; l < K; ++l) {
+        const int j = base0 + l;
+        const bool ran = j < maxit && !(r.flags & FLAG_PRECOND) && (r.stop_iter < 0 || j <= r.stop_iter);
+        if (!ran) break;
+        float t0 = 0.f, t1 = 0.f;
+        HIPCHK(hipEventElapsedTime(&t0, ev[2 * l], ev[2 * l + 1]));
+        HIPCHK(hipEventElapsedTime(&t1, ev[2 * l + 1], ev[2 * l + 2]));
+        ctx->time_tot[0] += t0;
+        ctx->time_tot[1] += 1;
+        ctx->time_tot[2] += t1;
+        ctx->time_tot[3] += 1;
+      }
+      base0 += K;
+    }
     bool all = true;
     for (int i : active) {
       const StopRec& r = ctx->h_recs[i];
@@ -602,6 +643,8 @@ void pfch_destroy(pfch_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : ctx->graph_events)
+    for (auto e : kv.second) (void)hipEventDestroy(e);
   for (auto g : ctx->graph_defs) (void)hipGraphDestroy(g);
   for (auto& I : ctx->inst)
     for (void* p : I.allocs) (void)hipFree(p);
@@ -681,9 +724,37 @@ fail:
   return rc;
 }
 
-int pfch_set_mass_stats(pfch_ctx* ctx, int32_t enabled) {
+int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail) {
+  if (!ctx || detail < 0 || detail > 1) return PFCH_E_INVAL;
+  ctx->stats_detail = detail;
+  return PFCH_OK;
+}
+
+int pfch_set_kernel_timing(pfch_ctx* ctx, int32_t enabled) {
   if (!ctx) return PFCH_E_INVAL;
-  ctx->mass_stats = enabled != 0;
+  ctx->timing = enabled != 0;
+  for (double& v : ctx->time_tot) v = 0.0;
+  return PFCH_OK;
+}
+
+int pfch_get_kernel_timing(pfch_ctx* ctx, double out[4]) {
+  if (!ctx || !out) return PFCH_E_INVAL;
+  for (int i = 0; i < 4; ++i) {
+    out[i] = ctx->time_tot[i];
+    ctx->time_tot[i] = 0.0;
+  }
+  return PFCH_OK;
+}
+
+int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]) {
+  if (!ctx || !out || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
+  const Instance& I = ctx->inst[inst];
+  out[0] = I.row_grid.x;
+  out[1] = I.row_block.x;
+  out[2] = (int64_t)I.row_lds;
+  out[3] = I.col_grid.x;
+  out[4] = I.col_block.x;
+  out[5] = (int64_t)I.col_lds;
   return PFCH_OK;
 }
 
@@ -758,7 +829,7 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
   int first_err = PFCH_OK;
   std::vector<int> status(n), iters(n);
   std::vector<double> dn(n);
-  const bool want_mass = st && ctx->mass_stats;
+  const bool want_mass = st && ctx->stats_detail > 0;
   for (int i = 0; i < n; ++i) {
     Instance& I = ctx->inst[i];
     status[i] = status_of(I, ctx->h_recs[i], &iters[i], &dn[i]);
@@ -791,7 +862,7 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
     I.last_iters = iters[i];
   }
   if (st) {
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (want_mass) HIPCHK(hipStreamSynchronize(ctx->stream));
     for (int i = 0; i < n; ++i) {
       Instance& I = ctx->inst[i];
       pfch_stats& s = st[i];
@@ -801,7 +872,11 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
       s.dnorm_inf = dn[i];
       s.fft_pairs = fft_pairs_of(I, iters[i]);
       s.mass = (want_mass && status[i] == PFCH_OK) ? ctx->h_mass[i] : NAN;
-      if ((rc = betas_host(ctx, I, as[i], s.beta))) return rc;
+      if (ctx->stats_detail > 0) {
+        if ((rc = betas_host(ctx, I, as[i], s.beta))) return rc;
+      } else {
+        for (double& b : s.beta) b = NAN;
+      }
     }
   }
   return first_err;

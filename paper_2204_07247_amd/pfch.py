@@ -27,7 +27,8 @@ PAPER_ETAS = tuple(math.sqrt(v) for v in (0.1, 0.575, 1.05, 1.525, 2.0))
 
 EXPORTED = (
     "pfch_validate_desc", "pfch_create", "pfch_set_state", "pfch_get_state",
-    "pfch_step", "pfch_solve", "pfch_set_mass_stats", "pfch_destroy",
+    "pfch_step", "pfch_solve", "pfch_set_stats_detail", "pfch_set_kernel_timing",
+    "pfch_get_kernel_timing", "pfch_get_launch_config", "pfch_destroy",
     "pfch_strerror", "pfch_version",
 )
 
@@ -87,14 +88,18 @@ def lib():
                                      ctypes.POINTER(i32)]
         L.pfch_step.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(Stats)]
         L.pfch_solve.argtypes = [vp, i32, dbl, dbl, dbl, vp, vp, vp, ctypes.POINTER(Stats)]
-        L.pfch_set_mass_stats.argtypes = [vp, i32]
+        L.pfch_set_stats_detail.argtypes = [vp, i32]
+        L.pfch_set_kernel_timing.argtypes = [vp, i32]
+        L.pfch_get_kernel_timing.argtypes = [vp, ctypes.POINTER(dbl)]
+        L.pfch_get_launch_config.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
         L.pfch_destroy.argtypes = [vp]
         L.pfch_destroy.restype = None
         L.pfch_strerror.argtypes = [ctypes.c_int]
         L.pfch_strerror.restype = ctypes.c_char_p
         L.pfch_version.argtypes = []
         for name in ("pfch_validate_desc", "pfch_create", "pfch_set_state", "pfch_get_state",
-                     "pfch_step", "pfch_solve", "pfch_set_mass_stats", "pfch_version"):
+                     "pfch_step", "pfch_solve", "pfch_set_stats_detail", "pfch_set_kernel_timing",
+                     "pfch_get_kernel_timing", "pfch_get_launch_config", "pfch_version"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -179,8 +184,28 @@ class Context:
     def __exit__(self, *exc):
         self.close()
 
-    def set_mass_stats(self, enabled):
-        lib().pfch_set_mass_stats(self._h, int(bool(enabled)))
+    def set_stats_detail(self, detail):
+        rc = lib().pfch_set_stats_detail(self._h, int(detail))
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_set_stats_detail")
+
+    def set_kernel_timing(self, enabled):
+        lib().pfch_set_kernel_timing(self._h, int(bool(enabled)))
+
+    def kernel_timing(self):
+        """{col_ms, col_launches, row_ms, row_launches} since the last call."""
+        out = (ctypes.c_double * 4)()
+        lib().pfch_get_kernel_timing(self._h, out)
+        return dict(col_ms=out[0], col_launches=int(out[1]), row_ms=out[2],
+                    row_launches=int(out[3]))
+
+    def launch_config(self, inst=0):
+        out = (ctypes.c_int64 * 6)()
+        rc = lib().pfch_get_launch_config(self._h, inst, out)
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_get_launch_config")
+        return dict(row_grid=out[0], row_block=out[1], row_lds=out[2], col_grid=out[3],
+                    col_block=out[4], col_lds=out[5])
 
     def set_state(self, inst, u_n, u_nm1=None, t=0.0, dt_prev=0.0, step_index=0):
         rc = lib().pfch_set_state(self._h, inst, _ptr(u_n), _ptr(u_nm1), float(t),

@@ -88,4 +88,5 @@ def test_create_rejects_bad_arguments_before_device_work():
     assert L.pfch_create(ctypes.byref(d), 1, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
     assert L.pfch_create(ctypes.byref(_desc()), 0, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
     assert L.pfch_step(None, None, None) == pfch.PFCH_E_INVAL
-    assert L.pfch_set_mass_stats(None, 1) == pfch.PFCH_E_INVAL
+    assert L.pfch_set_stats_detail(None, 1) == pfch.PFCH_E_INVAL
+    assert L.pfch_set_kernel_timing(None, 1) == pfch.PFCH_E_INVAL
