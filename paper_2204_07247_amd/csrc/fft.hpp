@@ -15,16 +15,44 @@
 // Thread t processes the butterflies j = t + q*T, q = 0..RMAX/R-1.
 //
 // Twiddles come from a per-length table tw[k] = exp(-2 pi i k / N) computed
-// on the host in long double; inverse transforms use conjugates.  Neither
-// direction is normalised.
+// on the host in long double; each thread reads the ones its butterflies
+// need once per kernel (Twiddles).  Inverse transforms use conjugates.
+// Neither direction is normalised.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace pfch {
 
+// Device pointers kept in memory are generic; kernels cast them to the
+// global address space so that accesses compile to global_load/store
+// (generic "flat" accesses also count against the LDS wait counter, which
+// every LDS barrier drains).
+#define GLB __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLB T* gp(T* p) {
+  return (GLB T*)p;
+}
+template <class T>
+__device__ __forceinline__ const GLB T* gp(const T* p) {
+  return (const GLB T*)p;
+}
+
 struct c2 {
   double x, y;
 };
+
+// 16-byte loads and stores of complex values through global pointers.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ c2 gload(const GLB c2* p) {
+  const f64x2 v = *(const GLB f64x2*)p;
+  return c2{v.x, v.y};
+}
+__device__ __forceinline__ void gstore(GLB c2* p, c2 a) {
+  f64x2 v;
+  v.x = a.x;
+  v.y = a.y;
+  *(GLB f64x2*)p = v;
+}
 
 __device__ __forceinline__ c2 cadd(c2 a, c2 b) { return {a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ c2 csub(c2 a, c2 b) { return {a.x - b.x, a.y - b.y}; }
@@ -32,6 +60,16 @@ __device__ __forceinline__ c2 cmul(c2 a, c2 b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 __device__ __forceinline__ c2 cconj(c2 a) { return {a.x, -a.y}; }
+
+// 1/x for positive normal x: hardware reciprocal estimate refined by two
+// Newton steps (relative error below one ulp); avoids the long IEEE
+// division sequence and its register footprint.
+__device__ __forceinline__ double rcp_pos(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
 __device__ __forceinline__ c2 cscale(c2 a, double s) { return {a.x * s, a.y * s}; }
 // multiply by -i (forward) or +i (inverse)
 template <bool INV>
@@ -144,33 +182,61 @@ __host__ __device__ constexpr int lds_len(int n) { return n + (n >> 4) + 1; }
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-// Plan: up to four passes; unused trailing radices are 1.
-template <int N_, int R1, int R2 = 1, int R3 = 1, int R4 = 1>
+// Plan: up to five passes; unused trailing radices are 1.  Every radix
+// must divide RMAX so that each thread handles whole butterflies.
+template <int N_, int R1, int R2 = 1, int R3 = 1, int R4 = 1, int R5 = 1>
 struct Plan {
   static constexpr int N = N_;
-  static constexpr int RMAX = cmax(cmax(R1, R2), cmax(R3, R4));
+  static constexpr int RMAX = cmax(cmax(cmax(R1, R2), cmax(R3, R4)), R5);
   static constexpr int T = N / RMAX;
-  static constexpr int NPASS = (R2 == 1) ? 1 : (R3 == 1) ? 2 : (R4 == 1) ? 3 : 4;
-  static_assert(R1 * R2 * R3 * R4 == N, "radices must multiply to N");
-  static_assert(N % RMAX == 0, "bad plan");
-  static constexpr int radix(int p) { return p == 0 ? R1 : p == 1 ? R2 : p == 2 ? R3 : R4; }
+  static constexpr int NPASS = (R2 == 1) ? 1 : (R3 == 1) ? 2 : (R4 == 1) ? 3 : (R5 == 1) ? 4 : 5;
+  static_assert(R1 * R2 * R3 * R4 * R5 == N, "radices must multiply to N");
+  static_assert(RMAX % R1 == 0 && RMAX % R2 == 0 && RMAX % R3 == 0 && RMAX % R4 == 0 &&
+                    RMAX % R5 == 0,
+                "every radix must divide RMAX");
+  static constexpr int radix(int p) {
+    return p == 0 ? R1 : p == 1 ? R2 : p == 2 ? R3 : p == 3 ? R4 : R5;
+  }
   static constexpr int ns(int p) {
-    return p == 0 ? 1 : p == 1 ? R1 : p == 2 ? R1 * R2 : R1 * R2 * R3;
+    return p == 0 ? 1 : p == 1 ? R1 : p == 2 ? R1 * R2 : p == 3 ? R1 * R2 * R3 : R1 * R2 * R3 * R4;
   }
 };
+
+// Per-thread twiddles w1 = w_N^{(j mod Ns) * N/(Ns*R)} of every butterfly
+// j = t + q*T of passes 1..NPASS-1 (pass 0 needs none).  They are read once
+// per kernel; the powers w1^r of a butterfly are formed by repeated complex
+// multiplication (at most 15 products, error a few ulps).
+template <class P>
+struct Twiddles {
+  c2 w[P::NPASS > 1 ? P::NPASS - 1 : 1][P::RMAX];
+};
+
+template <class P>
+__device__ __forceinline__ void load_twiddles(Twiddles<P>& tw, const c2* __restrict__ table_, int t) {
+  const GLB c2* table = gp(table_);
+#pragma unroll
+  for (int p = 1; p < P::NPASS; ++p) {
+    const int R = P::radix(p), NS = P::ns(p), QN = P::RMAX / R;
+#pragma unroll
+    for (int q = 0; q < P::RMAX; ++q) {
+      if (q < QN) {
+        const int j = t + q * P::T;
+        tw.w[p - 1][q] = gload(table + (j % NS) * (P::N / (NS * R)));
+      }
+    }
+  }
+}
 
 // One Stockham pass.  FROM_REG / TO_REG select registers or LDS as source
 // and destination.  `lds` is the team's buffer of lds_len(N) elements.
 template <class P, int PASS, bool INV, bool FROM_REG, bool TO_REG>
-__device__ __forceinline__ void stockham_pass(c2 (&v)[P::RMAX], c2* lds, const c2* __restrict__ tw,
-                                              int t) {
+__device__ __forceinline__ void stockham_pass(c2 (&v)[P::RMAX], c2* lds, const Twiddles<P>& tw, int t) {
   constexpr int N = P::N, T = P::T, RMAX = P::RMAX;
   constexpr int R = P::radix(PASS);
   constexpr int NS = P::ns(PASS);
   constexpr int QN = RMAX / R;  // butterflies per thread
   constexpr int STRIDE = N / R;
   c2 x[RMAX];
-  // gather inputs
 #pragma unroll
   for (int q = 0; q < QN; ++q) {
     const int j = t + q * T;
@@ -188,12 +254,13 @@ __device__ __forceinline__ void stockham_pass(c2 (&v)[P::RMAX], c2* lds, const c
   for (int q = 0; q < QN; ++q) {
     const int j = t + q * T;
     if constexpr (NS > 1) {
-      const int jm = j % NS;
+      c2 w1 = tw.w[PASS - 1][q];
+      if (INV) w1.y = -w1.y;
+      c2 w = w1;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        c2 w = tw[jm * r * (N / (NS * R))];
-        if (INV) w.y = -w.y;
         x[q * R + r] = cmul(x[q * R + r], w);
+        if (r + 1 < R) w = cmul(w, w1);
       }
     }
     dft<R, INV>(&x[q * R]);
@@ -209,10 +276,33 @@ __device__ __forceinline__ void stockham_pass(c2 (&v)[P::RMAX], c2* lds, const c
   }
 }
 
+// Opaque copies: the compiler may not merge work that depends on them
+// across transforms.  Without this, the twiddle powers and LDS addresses of
+// every transform in a kernel are computed once and kept live across all
+// barriers, which costs more registers than recomputing them.
+__device__ __forceinline__ int opaque_i(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ double opaque_d(double v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Full transform: registers in, registers out.  Every thread of the block
-// must call this (it contains block-wide barriers).
+// must call this (it contains block-wide barriers when NPASS > 1).
 template <class P, bool INV>
-__device__ __forceinline__ void fft(c2 (&v)[P::RMAX], c2* lds, const c2* __restrict__ tw, int t) {
+__device__ __forceinline__ void fft(c2 (&v)[P::RMAX], c2* lds, const Twiddles<P>& tw_in, int t_in) {
+  const int t = opaque_i(t_in);
+  Twiddles<P> tw;
+#pragma unroll
+  for (int p = 1; p < P::NPASS; ++p) {
+#pragma unroll
+    for (int q = 0; q < P::RMAX / P::radix(p); ++q) {
+      tw.w[p - 1][q].x = opaque_d(tw_in.w[p - 1][q].x);
+      tw.w[p - 1][q].y = opaque_d(tw_in.w[p - 1][q].y);
+    }
+  }
   if constexpr (P::NPASS == 1) {
     stockham_pass<P, 0, INV, true, true>(v, lds, tw, t);
   } else {
@@ -224,6 +314,10 @@ __device__ __forceinline__ void fft(c2 (&v)[P::RMAX], c2* lds, const c2* __restr
     }
     if constexpr (P::NPASS >= 4) {
       stockham_pass<P, 2, INV, false, false>(v, lds, tw, t);
+      __syncthreads();
+    }
+    if constexpr (P::NPASS >= 5) {
+      stockham_pass<P, 3, INV, false, false>(v, lds, tw, t);
       __syncthreads();
     }
     stockham_pass<P, P::NPASS - 1, INV, false, true>(v, lds, tw, t);

@@ -16,15 +16,35 @@
 // constant g = (b - a (1-theta)/theta) u^n + c u^{n-1} is transformed once
 // per step (a y + b u^n + c u^{n-1} = (a/theta) v_breve + g).
 //
-// Row layout: real fields are [rows][nx] (x fastest); spectral rows are
-// [field][rows][nh], nh = nx/2 + 1, complex FP64.
+// Layouts.  Real fields are [rows][nx] (x fastest).  A row's half spectrum
+// has nx/2 + 1 entries of which the first (kx = 0) and the last (kx = nx/2)
+// are real for real data; they share physical column 0 as (A[0], A[nx/2]),
+// so a spectral row has exactly H = nx/2 complex entries.  Spectral fields
+// are stored in column tiles of TW = 4 columns: element (row, kp) lives at
+// ((kp / 4) * rows + row) * 4 + kp % 4.  A column tile is one contiguous
+// block (what the column kernel streams), and a row pair writes whole
+// 128-byte lines into every tile.
 #pragma once
 #include "fft.hpp"
 #include "pfch_dev.hpp"
 
 namespace pfch {
 
+constexpr int TW = 4;
+
 __device__ __forceinline__ uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
+
+// Element offset of (row, kp) in a spectral field.  32-bit: a field holds
+// at most rows * H <= 2^31 / 16 elements, which keeps the base pointer in
+// scalar registers and one offset register per access.
+__device__ __forceinline__ uint32_t sidx(int rows, int row, int kp) {
+  return ((uint32_t)(kp >> 2) * (uint32_t)rows + (uint32_t)row) * TW + (uint32_t)(kp & 3);
+}
+
+// An opaque copy of v: keeps the compiler from hoisting work that depends
+// on it out of a rarely taken branch (and holding the results live across
+// barriers).
+__device__ __forceinline__ int opaque(int v) { return opaque_i(v); }
 
 // True when iteration j must not run: the cap is reached, or iteration j-1
 // met the tolerance or produced a non-finite norm.  Iterations that were
@@ -83,17 +103,31 @@ __device__ __forceinline__ uint64_t block_max_bits(uint64_t v, uint64_t* red) {
   return m;
 }
 
-// Z[k] = A[k] + i B[k] over the full length from two Hermitian half spectra.
+// ---------------------------------------------------------------------------
+// Row-side packing.
+// ---------------------------------------------------------------------------
+// Half-spectrum entry A[k], 0 <= k <= N/2, of `row` of field F.
+template <int N>
+__device__ __forceinline__ c2 spec_get(const GLB c2* __restrict__ F, int rows, int row, int k) {
+  if (k == 0 || k == N / 2) {
+    const c2 p = gload(F + sidx(rows, row, 0));
+    return c2{k == 0 ? p.x : p.y, 0.0};
+  }
+  return gload(F + sidx(rows, row, k));
+}
+
+// Z[k] = A[k] + i B[k] over the full length from two Hermitian half spectra
+// (row ra of FA and row rb of FB).
 template <class P>
-__device__ __forceinline__ void load_pack(c2 (&v)[P::RMAX], const c2* __restrict__ A,
-                                          const c2* __restrict__ B, int t) {
+__device__ __forceinline__ void load_pack(c2 (&v)[P::RMAX], const GLB c2* __restrict__ FA, int ra,
+                                          const GLB c2* __restrict__ FB, int rb, int rows, int t) {
   constexpr int N = P::N, T = P::T;
 #pragma unroll
   for (int m = 0; m < P::RMAX; ++m) {
     const int k = t + m * T;
     const bool hi = k > N / 2;
     const int kk = hi ? N - k : k;
-    c2 a = A[kk], b = B[kk];
+    c2 a = spec_get<N>(FA, rows, ra, kk), b = spec_get<N>(FB, rows, rb, kk);
     if (hi) {
       a.y = -a.y;
       b.y = -b.y;
@@ -102,191 +136,262 @@ __device__ __forceinline__ void load_pack(c2 (&v)[P::RMAX], const c2* __restrict
   }
 }
 
-// After the forward transform of Z = a + i b (a, b real): store the half
-// spectra A[k] = (Z[k] + conj Z[N-k]) / 2 and B[k] = -i (Z[k] - conj Z[N-k]) / 2.
+// After the forward transform of Z = a + i b (a, b real rows): store the half
+// spectra A[k] = (Z[k] + conj Z[N-k]) / 2 and B[k] = -i (Z[k] - conj Z[N-k]) / 2
+// into row ra of FA and row rb of FB (k = 0 and N/2 packed in column 0).
 template <class P>
-__device__ __forceinline__ void unpack_store(const c2 (&v)[P::RMAX], c2* lds, c2* __restrict__ A,
-                                             c2* __restrict__ B, int t) {
+__device__ __forceinline__ void unpack_store(const c2 (&v)[P::RMAX], c2* lds, GLB c2* __restrict__ FA,
+                                             int ra, GLB c2* __restrict__ FB, int rb, int rows, int t) {
   constexpr int N = P::N, T = P::T;
 #pragma unroll
   for (int m = 0; m < P::RMAX; ++m) lds[lds_idx(t + m * T)] = v[m];
   __syncthreads();
 #pragma unroll
-  for (int m = 0; m <= P::RMAX / 2; ++m) {
+  for (int m = 0; m < P::RMAX / 2; ++m) {
     const int k = t + m * T;
-    if (k <= N / 2) {
-      const c2 z = lds[lds_idx(k)];
-      const c2 w = lds[lds_idx(k == 0 ? 0 : N - k)];
-      // conj(w) = (w.x, -w.y)
-      A[k] = c2{0.5 * (z.x + w.x), 0.5 * (z.y - w.y)};
-      const double dx = z.x - w.x, dy = z.y + w.y;  // z - conj(w)
-      B[k] = c2{0.5 * dy, -0.5 * dx};
+    const c2 z = lds[lds_idx(k)];
+    const c2 w = lds[lds_idx(k == 0 ? N / 2 : N - k)];
+    c2 A, B;
+    if (k == 0) {
+      A = c2{z.x, w.x};  // (Re Z[0], Re Z[N/2])
+      B = c2{z.y, w.y};  // (Im Z[0], Im Z[N/2])
+    } else {
+      A = c2{0.5 * (z.x + w.x), 0.5 * (z.y - w.y)};
+      B = c2{0.5 * (z.y + w.y), -0.5 * (z.x - w.x)};
     }
+    gstore(FA + sidx(rows, ra, k), A);
+    gstore(FB + sidx(rows, rb, k), B);
   }
   __syncthreads();
 }
 
-// |k|^2 for column kx and row index ky of a 2D half spectrum.
+// ---------------------------------------------------------------------------
+// Column-side helpers.
+// ---------------------------------------------------------------------------
+// |k|^2 for logical column kx and row index ky.
 __device__ __forceinline__ double wavenum2(const InstDev* I, int kx, int ky, int ny) {
   const int kyp = ky <= ny / 2 ? ky : ky - ny;
   const double ax = kx * I->kx_scale, ay = kyp * I->ky_scale;
   return ax * ax + ay * ay;
 }
 
-// Averaged-Newton constants (beta_-2, beta_0, beta_2, beta_4) from the setup
-// partial sums, summed in a fixed order so every block gets the same values.
+// Averaged-Newton constants (beta_-2, beta_0, beta_2, beta_4).  beta_0 and
+// beta_2 are the grid means of Sec. 3.4.1 at the step's initial guess,
+// summed once per step in a fixed order by the setup column kernel.
 __device__ __forceinline__ void betas(const InstDev* I, double& bm2, double& b0, double& b2,
                                       double& b4) {
+  bm2 = I->a / I->mobility;
+  b0 = I->beta0;
+  if (I->model == MODEL_PFC) {
+    b2 = -2.0;
+    b4 = 1.0;
+  } else {
+    const double e2 = I->eps * I->eps;
+    b2 = I->beta2;
+    b4 = e2 * e2;
+  }
+}
+
+__device__ __forceinline__ void finish_betas(InstDev* I) {
   double s0 = 0.0, s1 = 0.0;
   for (int i = 0; i < I->nparts; ++i) {
     s0 += I->part[2 * i];
     s1 += I->part[2 * i + 1];
   }
-  bm2 = I->a / I->mobility;
-  if (I->model == MODEL_PFC) {
-    b0 = fabs(s0 * I->inv_p);
-    b2 = -2.0;
-    b4 = 1.0;
+  I->beta0 = fabs(s0 * I->inv_p);
+  I->beta2 = fabs(s1 * I->inv_p);
+}
+
+// Column block geometry: `cb` physical columns per block (1, 2 or 4 of a
+// tile).  Blocks sharing a tile are placed on the same XCD (block ids go
+// round-robin over the 8 XCDs) when the tile count allows it.
+struct ColPos {
+  int c, t, kp;
+};
+__device__ __forceinline__ ColPos col_pos(int T, int ntiles) {
+  const int cb = blockDim.x / T;
+  ColPos p;
+  p.c = threadIdx.x % cb;
+  p.t = threadIdx.x / cb;
+  const int per_tile = TW / cb;
+  int tile, sub;
+  if (per_tile > 1 && (ntiles & 7) == 0) {
+    const int g = blockIdx.x / (8 * per_tile), r = blockIdx.x % (8 * per_tile);
+    tile = g * 8 + (r & 7);
+    sub = r >> 3;
   } else {
-    const double e2 = I->eps * I->eps;
-    b0 = fabs(s0 * I->inv_p);
-    b2 = fabs(s1 * I->inv_p);
-    b4 = e2 * e2;
+    tile = blockIdx.x / per_tile;
+    sub = blockIdx.x % per_tile;
   }
+  p.kp = tile * TW + sub * cb + p.c;
+  return p;
+}
+
+// Physical column 0 packs the logical columns kx = 0 and kx = N/2:
+// P^(ky) = F0^(ky) + i FN^(ky), both transforms of real sequences.  A real
+// symbol applied per logical column, c0(ky) to F0^ and cN(ky) to FN^, acts
+// on the packed values as
+//   c0 F0^ + i cN FN^ = (c0 + cN)/2 P^(ky) + (c0 - cN)/2 conj(P^(-ky)).
+// col0_mirror hands conj(P^(-ky)) of column 0's own values to `use`.  Every
+// thread of the block must call it; only column 0's team (`mine`) calls
+// `use`.
+template <class P, class F>
+__device__ __forceinline__ void col0_mirror(const c2 (&v)[P::RMAX], c2* lds0, bool mine, int t, F use) {
+  constexpr int N = P::N, T = P::T;
+  if (mine) {
+#pragma unroll
+    for (int m = 0; m < P::RMAX; ++m) lds0[lds_idx(t + m * T)] = v[m];
+  }
+  __syncthreads();
+  if (mine) {
+#pragma unroll
+    for (int m = 0; m < P::RMAX; ++m) {
+      const int ky = t + m * T;
+      const c2 w = lds0[lds_idx(ky == 0 ? 0 : N - ky)];
+      use(m, c2{w.x, -w.y});
+    }
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // Column kernel of one PAGD iteration.
+//
+// With q = |k|^2 > 0 and L the averaged-Newton symbol, Lq = q L =
+// beta_-2 + theta_l q (beta_0 + beta_2 q + beta_4 q^2), the preconditioned
+// residual is
+//   d^ = -(1/(P Lq)) [ (a/theta v^ + g^)/M + q mu~^ ],
+//   PFC: q mu~^ = q N^ + q (1 - eps - 2q + q^2) v^,
+//   FCH: q mu~^ = eps^2 q^2 F'^ + q p^ + q (eps^4 q^2 - eps^2 eta1 q) v^,
+// and d^ = 0 at k = 0.  The bracket is accumulated field by field as it
+// comes out of its y-transform.
 // ---------------------------------------------------------------------------
 template <class PY, int MODEL>
-__global__ __launch_bounds__(256) void k_col_iter(const InstDev* __restrict__ I, int l) {
+__global__ __launch_bounds__(512) void k_col_iter(const InstDev* __restrict__ I, int l) {
   extern __shared__ c2 smem[];
   const int j = *I->iter_base + l;
   if (stopped_before(I, j)) return;
   constexpr int N = PY::N, T = PY::T, RM = PY::RMAX;
-  const int cb = blockDim.x / T;
-  const int c = threadIdx.x % cb, t = threadIdx.x / cb;
-  const int nh = I->nh;
-  const int kx = blockIdx.x * cb + c;
-  const bool valid = kx < nh;
-  const int kxc = valid ? kx : nh - 1;
-  c2* lds = smem + c * lds_len(N);
-  const int64_t fs = I->field_stride;
-  c2* __restrict__ S = I->S;
+  const int rows = N;
+  const ColPos pos = col_pos(T, I->nh / TW);
+  const int t = pos.t, kp = pos.kp;
+  c2* lds = smem + pos.c * lds_len(N);
+  const bool special = kp == 0;  // this thread's column holds kx = 0 and kx = nx/2
+  const bool blk0 = blockIdx.x == 0;  // the block holding physical column 0
+  const uint32_t fs = (uint32_t)I->field_stride;
+  GLB c2* S = gp(I->S);
+  Twiddles<PY> tw;
+  load_twiddles<PY>(tw, I->tw_y, t);
 
   double bm2, b0, b2, b4;
   betas(I, bm2, b0, b2, b4);
-  const double thl = I->theta_l, inv_m = 1.0 / I->mobility, aot = I->a_over_theta;
+  const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
   const double inv_p = I->inv_p;
+  const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
+  const double kx2 = (kp * I->kx_scale) * (kp * I->kx_scale);
+  auto q_of = [&](int m) {  // |k|^2 of this thread's logical column (kx = 0 for column 0)
+    const int ky = t + m * T;
+    const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
+    return kx2 + a * a;
+  };
+  auto q_col0 = [&](int ky) {  // |k|^2 at kx = 0
+    const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
+    return a * a;
+  };
+  constexpr int NF = MODEL == MODEL_PFC ? 2 : 3;  // transformed fields; the last is v_breve
+  const double e2 = I->eps * I->eps, e4 = e2 * e2, e2h1 = e2 * I->eta1, e1 = 1.0 - I->eps;
+  auto coef = [&](int f, double q) -> double {
+    if (f == NF - 1) {
+      const double lin = MODEL == MODEL_PFC ? e1 - 2.0 * q + q * q : e4 * q * q - e2h1 * q;
+      return inv_m * aot + q * lin;
+    }
+    if (MODEL == MODEL_FCH && f == 0) return e2 * q * q;
+    return q;
+  };
 
-  c2 v[RM], acc[RM];
-  int bad = 0;
-  if constexpr (MODEL == MODEL_PFC) {
-    // field 0: N^ = FFT(v_breve^3); field 1: v_breve^
+  c2 v[RM], nxt[RM], acc[RM];
 #pragma unroll
-    for (int m = 0; m < RM; ++m) v[m] = S[(int64_t)(t + m * T) * nh + kxc];
-    fft<PY, false>(v, lds, I->tw_y, t);
+  for (int m = 0; m < RM; ++m) {
+    v[m] = gload(S + sidx(rows, t + m * T, kp));
+    acc[m] = c2{0.0, 0.0};
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+#pragma unroll
+    for (int m = 0; m < RM; ++m)  // prefetch the next field, then g^
+      nxt[m] = f + 1 < NF ? gload(S + (f + 1) * fs + sidx(rows, t + m * T, kp))
+                          : gload(gp(I->ghat) + sidx(rows, t + m * T, kp));
+    fft<PY, false>(v, lds, tw, t);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      const double q = q_of(m);
+      const double c = special ? 0.5 * (coef(f, q) + coef(f, q + kxn2)) : coef(f, q);
+      acc[m] = cadd(acc[m], cscale(v[m], c));
+    }
+    if (blk0)
+      col0_mirror<PY>(v, smem, special, t, [&](int m, c2 w) {
+        const double q = q_col0(opaque(t + m * T));
+        acc[m] = cadd(acc[m], cscale(w, 0.5 * (coef(f, q) - coef(f, q + kxn2))));
+      });
+#pragma unroll
+    for (int m = 0; m < RM; ++m) v[m] = nxt[m];
+  }
+  // g^ enters with the same coefficient 1/M on both logical columns.
+#pragma unroll
+  for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(v[m], inv_m));
+
+  // scale by -1/(P Lq), zero at k = 0
+  int bad = 0;
+  auto scale = [&](double q) -> double {
+    if (!(q > 0.0)) return 0.0;
+    const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
+    bad |= !(Lq > 0.0);
+    return -inv_p * rcp_pos(Lq);
+  };
+#pragma unroll
+  for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], scale(q_of(m)));
+  if (blk0)
+    col0_mirror<PY>(acc, smem, special, t, [&](int m, c2 w) {
+      const double q = q_col0(opaque(t + m * T));
+      const double s0 = scale(q), sn = scale(q + kxn2);
+      v[m] = cadd(cscale(acc[m], 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn)));
+    });
+  if constexpr (MODEL == MODEL_FCH) {
+    // keep d^ for the Laplacian field: acc <- d^ (packed for column 0)
 #pragma unroll
     for (int m = 0; m < RM; ++m) acc[m] = v[m];
-#pragma unroll
-    for (int m = 0; m < RM; ++m) v[m] = S[fs + (int64_t)(t + m * T) * nh + kxc];
-    fft<PY, false>(v, lds, I->tw_y, t);
-    const double e1 = 1.0 - I->eps;
-#pragma unroll
-    for (int m = 0; m < RM; ++m) {
-      const int ky = t + m * T;
-      const double k2 = wavenum2(I, kxc, ky, N);
-      c2 d = {0.0, 0.0};
-      if (k2 > 0.0) {
-        const c2 g = I->ghat[(int64_t)ky * nh + kxc];
-        const double lin = e1 - 2.0 * k2 + k2 * k2;
-        const double ik2 = inv_m / k2;
-        // G'^ = (a/theta v^ + g^)/(M k^2) + N^ + lin v^ ; r^ = -G'^
-        const double gx = (aot * v[m].x + g.x) * ik2 + acc[m].x + lin * v[m].x;
-        const double gy = (aot * v[m].y + g.y) * ik2 + acc[m].y + lin * v[m].y;
-        const double L = bm2 / k2 + thl * (b0 + b2 * k2 + b4 * k2 * k2);
-        bad |= !(L > 0.0);
-        const double sc = -inv_p / L;
-        d = c2{gx * sc, gy * sc};
-      }
-      v[m] = d;
-    }
-    fft<PY, true>(v, lds, I->tw_y, t);
-    if (valid) {
-#pragma unroll
-      for (int m = 0; m < RM; ++m) S[(int64_t)(t + m * T) * nh + kx] = v[m];
-    }
-  } else {
-    // fields: 0 F'^, 1 p^, 2 v_breve^
-    const double e2 = I->eps * I->eps, e4 = e2 * e2, e2h1 = e2 * I->eta1;
-#pragma unroll
-    for (int m = 0; m < RM; ++m) v[m] = S[(int64_t)(t + m * T) * nh + kxc];
-    fft<PY, false>(v, lds, I->tw_y, t);
-#pragma unroll
-    for (int m = 0; m < RM; ++m) {
-      const double k2 = wavenum2(I, kxc, t + m * T, N);
-      acc[m] = cscale(v[m], e2 * k2);
-    }
-#pragma unroll
-    for (int m = 0; m < RM; ++m) v[m] = S[fs + (int64_t)(t + m * T) * nh + kxc];
-    fft<PY, false>(v, lds, I->tw_y, t);
-#pragma unroll
-    for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], v[m]);
-#pragma unroll
-    for (int m = 0; m < RM; ++m) v[m] = S[2 * fs + (int64_t)(t + m * T) * nh + kxc];
-    fft<PY, false>(v, lds, I->tw_y, t);
-#pragma unroll
-    for (int m = 0; m < RM; ++m) {
-      const int ky = t + m * T;
-      const double k2 = wavenum2(I, kxc, ky, N);
-      c2 d = {0.0, 0.0};
-      if (k2 > 0.0) {
-        const c2 g = I->ghat[(int64_t)ky * nh + kxc];
-        const double lin = e4 * k2 * k2 - e2h1 * k2;
-        const double ik2 = inv_m / k2;
-        // mu^ = eps^2 k^2 F'^ + p^ + (eps^4 k^4 - eps^2 eta1 k^2) v^
-        const double gx = (aot * v[m].x + g.x) * ik2 + acc[m].x + lin * v[m].x;
-        const double gy = (aot * v[m].y + g.y) * ik2 + acc[m].y + lin * v[m].y;
-        const double L = bm2 / k2 + thl * (b0 + b2 * k2 + b4 * k2 * k2);
-        bad |= !(L > 0.0);
-        const double sc = -inv_p / L;
-        d = c2{gx * sc, gy * sc};
-      }
-      acc[m] = d;
-      v[m] = d;
-    }
-    fft<PY, true>(v, lds, I->tw_y, t);
-    if (valid) {
-#pragma unroll
-      for (int m = 0; m < RM; ++m) S[(int64_t)(t + m * T) * nh + kx] = v[m];
-    }
-#pragma unroll
-    for (int m = 0; m < RM; ++m) {
-      const double k2 = wavenum2(I, kxc, t + m * T, N);
-      v[m] = cscale(acc[m], -k2);
-    }
-    fft<PY, true>(v, lds, I->tw_y, t);
-    if (valid) {
-#pragma unroll
-      for (int m = 0; m < RM; ++m) S[fs + (int64_t)(t + m * T) * nh + kx] = v[m];
-    }
   }
-  if (bad && valid) atomicOr(I->flags, FLAG_PRECOND);
+  fft<PY, true>(v, lds, tw, t);
+#pragma unroll
+  for (int m = 0; m < RM; ++m) gstore(S + sidx(rows, t + m * T, kp), v[m]);
+  if constexpr (MODEL == MODEL_FCH) {
+    // Delta d: symbol -q on each logical column
+#pragma unroll
+    for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], -q_of(m));
+    if (blk0)
+      col0_mirror<PY>(acc, smem, special, t, [&](int m, c2 w) {
+        const double q = q_col0(opaque(t + m * T));
+        v[m] = cadd(cscale(acc[m], -(q + 0.5 * kxn2)), cscale(w, 0.5 * kxn2));
+      });
+    fft<PY, true>(v, lds, tw, t);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) gstore(S + fs + sidx(rows, t + m * T, kp), v[m]);
+  }
+  if (bad) atomicOr(I->flags, FLAG_PRECOND);
 }
 
 // ---------------------------------------------------------------------------
 // Row kernel of one PAGD iteration (end of j, start of j+1).
 // ---------------------------------------------------------------------------
 template <class PX>
-__device__ __forceinline__ void pfc_forward_row(const InstDev* I, const double (&vb)[PX::RMAX], c2* lds,
-                                                int row, int t) {
+__device__ __forceinline__ void pfc_forward_row(const InstDev* I, const double (&vb)[PX::RMAX],
+                                                const Twiddles<PX>& tw, c2* lds, int row, int t) {
   constexpr int RM = PX::RMAX;
   c2 z[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) z[m] = c2{vb[m] * vb[m] * vb[m], vb[m]};
-  fft<PX, false>(z, lds, I->tw_x, t);
-  const int nh = I->nh;
-  unpack_store<PX>(z, lds, I->S + (int64_t)row * nh, I->S + I->field_stride + (int64_t)row * nh, t);
+  fft<PX, false>(z, lds, tw, t);
+  unpack_store<PX>(z, lds, gp(I->S), row, gp(I->S) + I->field_stride, row, I->rows, t);
 }
 
 // FCH pointwise terms at v_breve with Laplacian lv:
@@ -294,7 +399,8 @@ __device__ __forceinline__ void pfc_forward_row(const InstDev* I, const double (
 //   p = -F'' omega - eta2 F'.
 template <class PX>
 __device__ __forceinline__ void fch_forward_row(const InstDev* I, const double (&vb)[PX::RMAX],
-                                                const double (&lv)[PX::RMAX], c2* lds, int row, int t) {
+                                                const double (&lv)[PX::RMAX], const Twiddles<PX>& tw,
+                                                c2* lds, int row, int t) {
   constexpr int RM = PX::RMAX;
   const double e2 = I->eps * I->eps, tau = I->tau, eta2 = I->eta2;
   c2 z[RM];
@@ -306,20 +412,20 @@ __device__ __forceinline__ void fch_forward_row(const InstDev* I, const double (
     const double om = e2 * lv[m] - f1;
     z[m] = c2{f1, -f2 * om - eta2 * f1};
   }
-  fft<PX, false>(z, lds, I->tw_x, t);
-  const int nh = I->nh;
-  unpack_store<PX>(z, lds, I->S + (int64_t)row * nh, I->S + I->field_stride + (int64_t)row * nh, t);
+  fft<PX, false>(z, lds, tw, t);
+  unpack_store<PX>(z, lds, gp(I->S), row, gp(I->S) + I->field_stride, row, I->rows, t);
 }
 
 template <class PX>
-__device__ __forceinline__ void pair_forward(const InstDev* I, const double (&a)[PX::RMAX],
-                                             const double (&b)[PX::RMAX], c2* lds, c2* A, c2* B, int t) {
+__device__ __forceinline__ void pair_forward(const double (&a)[PX::RMAX], const double (&b)[PX::RMAX],
+                                             const Twiddles<PX>& tw, c2* lds, GLB c2* FA, int ra,
+                                             GLB c2* FB, int rb, int rows, int t) {
   constexpr int RM = PX::RMAX;
   c2 z[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) z[m] = c2{a[m], b[m]};
-  fft<PX, false>(z, lds, I->tw_x, t);
-  unpack_store<PX>(z, lds, A, B, t);
+  fft<PX, false>(z, lds, tw, t);
+  unpack_store<PX>(z, lds, FA, ra, FB, rb, rows, t);
 }
 
 template <class PX, int MODEL>
@@ -333,76 +439,96 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* __restrict__ I,
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;
   c2* lds = smem + team * lds_len(N);
   const int r0 = 2 * (blockIdx.x * teams + team);
-  const int nh = I->nh;
-  const int64_t fs = I->field_stride;
+  const int rows = I->rows;
+  const uint32_t fs = (uint32_t)I->field_stride;
   const int ne = I->n_eta;
   const double lam = I->lam[j % ne], lamn = I->lam[(j + 1) % ne];
   const double s = I->s, th = I->theta;
   const bool mp = th != 1.0;
-  const double* __restrict__ xj = I->X[j % 3];
-  const double* __restrict__ xm = I->X[(j + 2) % 3];
-  double* __restrict__ xn = I->X[(j + 1) % 3];
-  const double* __restrict__ un = I->un;
+  const auto xj = gp(I->X[j % 3]);
+  const auto xm = gp(I->X[(j + 2) % 3]);
+  auto xn = gp(I->X[(j + 1) % 3]);
+  const auto un = gp(I->un);
   uint64_t dmax = 0;
+  Twiddles<PX> tw;
+  load_twiddles<PX>(tw, I->tw_x, t);
 
   if constexpr (MODEL == MODEL_PFC) {
+    double a[2][RM], b[2][RM], uu[2][RM];
+#pragma unroll
+    for (int row = 0; row < 2; ++row) {
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+        a[row][m] = xj[idx];
+        b[row][m] = xm[idx];
+        uu[row][m] = mp ? un[idx] : 0.0;
+      }
+    }
     c2 v[RM];
-    load_pack<PX>(v, I->S + (int64_t)r0 * nh, I->S + (int64_t)(r0 + 1) * nh, t);
-    fft<PX, true>(v, lds, I->tw_x, t);
+    load_pack<PX>(v, gp(I->S), r0, gp(I->S), r0 + 1, rows, t);
+    fft<PX, true>(v, lds, tw, t);
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
       double vb[RM];
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const int64_t idx = (int64_t)(r0 + row) * N + t + m * T;
+        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
         const double d = row ? v[m].y : v[m].x;
-        const double a = xj[idx], b = xm[idx];
-        const double y = a + lam * (a - b);
+        const double y = a[row][m] + lam * (a[row][m] - b[row][m]);
         const double x1 = y + s * d;
         xn[idx] = x1;
         const uint64_t db = dbits(fabs(d));
         dmax = db > dmax ? db : dmax;
-        const double yn = x1 + lamn * (x1 - a);
-        vb[m] = mp ? th * yn + (1.0 - th) * un[idx] : yn;
+        const double yn = x1 + lamn * (x1 - a[row][m]);
+        vb[m] = mp ? th * yn + (1.0 - th) * uu[row][m] : yn;
       }
-      pfc_forward_row<PX>(I, vb, lds, r0 + row, t);
+      pfc_forward_row<PX>(I, vb, tw, lds, r0 + row, t);
     }
   } else {
-    const double* __restrict__ dxj = I->DX[j % 3];
-    const double* __restrict__ dxm = I->DX[(j + 2) % 3];
-    double* __restrict__ dxn = I->DX[(j + 1) % 3];
-    const double* __restrict__ dun = I->dun;
+    const auto dxj = gp(I->DX[j % 3]);
+    const auto dxm = gp(I->DX[(j + 2) % 3]);
+    auto dxn = gp(I->DX[(j + 1) % 3]);
+    const auto dun = gp(I->dun);
     double vbs[2][RM];
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
       const int r = r0 + row;
+      double a[RM], b[RM], la[RM], lb[RM], uu[RM], lu[RM];
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const uint32_t idx = (uint32_t)r * N + t + m * T;
+        a[m] = xj[idx];
+        b[m] = xm[idx];
+        la[m] = dxj[idx];
+        lb[m] = dxm[idx];
+        uu[m] = mp ? un[idx] : 0.0;
+        lu[m] = mp ? dun[idx] : 0.0;
+      }
       c2 v[RM];
-      load_pack<PX>(v, I->S + (int64_t)r * nh, I->S + fs + (int64_t)r * nh, t);
-      fft<PX, true>(v, lds, I->tw_x, t);
+      load_pack<PX>(v, gp(I->S), r, gp(I->S) + fs, r, rows, t);
+      fft<PX, true>(v, lds, tw, t);
       double lv[RM];
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const int64_t idx = (int64_t)r * N + t + m * T;
+        const uint32_t idx = (uint32_t)r * N + t + m * T;
         const double d = v[m].x, ld = v[m].y;
-        const double a = xj[idx], b = xm[idx];
-        const double la = dxj[idx], lb = dxm[idx];
-        const double y = a + lam * (a - b);
-        const double ly = la + lam * (la - lb);
+        const double y = a[m] + lam * (a[m] - b[m]);
+        const double ly = la[m] + lam * (la[m] - lb[m]);
         const double x1 = y + s * d;
         const double lx1 = ly + s * ld;
         xn[idx] = x1;
         dxn[idx] = lx1;
         const uint64_t db = dbits(fabs(d));
         dmax = db > dmax ? db : dmax;
-        const double yn = x1 + lamn * (x1 - a);
-        const double lyn = lx1 + lamn * (lx1 - la);
-        vbs[row][m] = mp ? th * yn + (1.0 - th) * un[idx] : yn;
-        lv[m] = mp ? th * lyn + (1.0 - th) * dun[idx] : lyn;
+        const double yn = x1 + lamn * (x1 - a[m]);
+        const double lyn = lx1 + lamn * (lx1 - la[m]);
+        vbs[row][m] = mp ? th * yn + (1.0 - th) * uu[m] : yn;
+        lv[m] = mp ? th * lyn + (1.0 - th) * lu[m] : lyn;
       }
-      fch_forward_row<PX>(I, vbs[row], lv, lds, r, t);
+      fch_forward_row<PX>(I, vbs[row], lv, tw, lds, r, t);
     }
-    pair_forward<PX>(I, vbs[0], vbs[1], lds, I->S + 2 * fs + (int64_t)r0 * nh,
-                     I->S + 2 * fs + (int64_t)(r0 + 1) * nh, t);
+    pair_forward<PX>(vbs[0], vbs[1], tw, lds, gp(I->S) + 2 * fs, r0, gp(I->S) + 2 * fs, r0 + 1, rows, t);
   }
   const uint64_t bm = block_max_bits(dmax, red);
   if (threadIdx.x == 0) atomicMax((unsigned long long*)&I->norms[j], (unsigned long long)bm);
@@ -431,11 +557,13 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* __restrict__ I, Step
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;
   c2* lds = smem + team * lds_len(N);
   const int r0 = 2 * (blockIdx.x * teams + team);
-  const int nh = I->nh;
-  const int64_t fs = I->field_stride;
+  const int rows = I->rows;
+  const uint32_t fs = (uint32_t)I->field_stride;
   const double th = sa.theta;
-  double* __restrict__ x0a = I->X[0];
-  double* __restrict__ x0b = I->X[2];
+  auto x0a = gp(I->X[0]);
+  auto x0b = gp(I->X[2]);
+  Twiddles<PX> tw;
+  load_twiddles<PX>(tw, I->tw_x, t);
 
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     I->a = sa.a;
@@ -454,18 +582,19 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* __restrict__ I, Step
   }
 
   double s0 = 0.0, s1 = 0.0;
-  double x0v[2][RM], gv[2][RM];
+  double x0v[2][RM], gv[2][RM], uv[2][RM];
   const double eps = I->eps, tau = I->tau, e2 = eps * eps;
 #pragma unroll
   for (int row = 0; row < 2; ++row) {
 #pragma unroll
     for (int m = 0; m < RM; ++m) {
-      const int64_t idx = (int64_t)(r0 + row) * N + t + m * T;
-      const double u = sa.un[idx], um = sa.unm1[idx];
-      const double x0 = sa.xin ? sa.xin[idx] : u + sa.rho * (u - um);
+      const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+      const double u = gp(sa.un)[idx], um = gp(sa.unm1)[idx];
+      const double x0 = sa.xin ? gp(sa.xin)[idx] : u + sa.rho * (u - um);
       x0a[idx] = x0;
       x0b[idx] = x0;
       x0v[row][m] = x0;
+      uv[row][m] = u;
       gv[row][m] = sa.gu * u + sa.gm * um;
       const double vb = th * x0 + (1.0 - th) * u;
       if constexpr (MODEL == MODEL_PFC) {
@@ -480,80 +609,73 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* __restrict__ I, Step
     }
   }
   if constexpr (MODEL == MODEL_PFC) {
-    pair_forward<PX>(I, gv[0], gv[1], lds, I->G + (int64_t)r0 * nh, I->G + (int64_t)(r0 + 1) * nh, t);
+    pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, gp(I->G), r0 + 1, rows, t);
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
       double vb[RM];
 #pragma unroll
-      for (int m = 0; m < RM; ++m) {
-        const int64_t idx = (int64_t)(r0 + row) * N + t + m * T;
-        vb[m] = th * x0v[row][m] + (1.0 - th) * sa.un[idx];
-      }
-      pfc_forward_row<PX>(I, vb, lds, r0 + row, t);
+      for (int m = 0; m < RM; ++m) vb[m] = th * x0v[row][m] + (1.0 - th) * uv[row][m];
+      pfc_forward_row<PX>(I, vb, tw, lds, r0 + row, t);
     }
   } else {
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
       const int r = r0 + row;
-      pair_forward<PX>(I, gv[row], x0v[row], lds, I->G + (int64_t)r * nh, I->G + fs + (int64_t)r * nh, t);
+      pair_forward<PX>(gv[row], x0v[row], tw, lds, gp(I->G), r, gp(I->G) + fs, r, rows, t);
     }
-    if (th != 1.0) {
-      double ua[RM], ub[RM];
-#pragma unroll
-      for (int m = 0; m < RM; ++m) {
-        ua[m] = sa.un[(int64_t)r0 * N + t + m * T];
-        ub[m] = sa.un[(int64_t)(r0 + 1) * N + t + m * T];
-      }
-      pair_forward<PX>(I, ua, ub, lds, I->G + 2 * fs + (int64_t)r0 * nh,
-                       I->G + 2 * fs + (int64_t)(r0 + 1) * nh, t);
-    }
+    if (th != 1.0) pair_forward<PX>(uv[0], uv[1], tw, lds, gp(I->G) + 2 * fs, r0, gp(I->G) + 2 * fs, r0 + 1, rows, t);
   }
   const double bs0 = block_sum(s0, red);
   const double bs1 = block_sum(s1, red);
   if (threadIdx.x == 0) {
-    I->part[2 * blockIdx.x] = bs0;
-    I->part[2 * blockIdx.x + 1] = bs1;
+    gp(I->part)[2 * blockIdx.x] = bs0;
+    gp(I->part)[2 * blockIdx.x + 1] = bs1;
   }
 }
 
-// Step setup, column part: g^ (stored for the whole step); FCH also the
-// Laplacians of x0 (and of u^n for the midpoint rule) as spectral rows.
+// Step setup, column part: g^ (stored for the whole step, column 0 packed
+// like every spectral field); FCH also the Laplacians of x0 (and of u^n for
+// the midpoint rule) back as spectral rows.  Block 0 sums the averaged-Newton
+// partial sums.
 template <class PY, int MODEL>
-__global__ __launch_bounds__(256) void k_col_setup(const InstDev* __restrict__ I) {
+__global__ __launch_bounds__(512) void k_col_setup(InstDev* __restrict__ I) {
   extern __shared__ c2 smem[];
   constexpr int N = PY::N, T = PY::T, RM = PY::RMAX;
-  const int cb = blockDim.x / T;
-  const int c = threadIdx.x % cb, t = threadIdx.x / cb;
-  const int nh = I->nh;
-  const int kx = blockIdx.x * cb + c;
-  const bool valid = kx < nh;
-  const int kxc = valid ? kx : nh - 1;
-  c2* lds = smem + c * lds_len(N);
-  const int64_t fs = I->field_stride;
+  const int rows = N;
+  const ColPos pos = col_pos(T, I->nh / TW);
+  const int t = pos.t, kp = pos.kp;
+  c2* lds = smem + pos.c * lds_len(N);
+  const bool special = kp == 0;
+  const bool blk0 = blockIdx.x == 0;
+  const uint32_t fs = (uint32_t)I->field_stride;
+  GLB c2* G = gp(I->G);
+  Twiddles<PY> tw;
+  load_twiddles<PY>(tw, I->tw_y, t);
+  const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
+  if (blk0 && threadIdx.x == 0) finish_betas(I);
   c2 v[RM];
 #pragma unroll
-  for (int m = 0; m < RM; ++m) v[m] = I->G[(int64_t)(t + m * T) * nh + kxc];
-  fft<PY, false>(v, lds, I->tw_y, t);
-  if (valid) {
+  for (int m = 0; m < RM; ++m) v[m] = gload(G + sidx(rows, t + m * T, kp));
+  fft<PY, false>(v, lds, tw, t);
 #pragma unroll
-    for (int m = 0; m < RM; ++m) I->ghat[(int64_t)(t + m * T) * nh + kx] = v[m];
-  }
+  for (int m = 0; m < RM; ++m) gstore(gp(I->ghat) + sidx(rows, t + m * T, kp), v[m]);
   if constexpr (MODEL == MODEL_FCH) {
     const int nlap = I->theta != 1.0 ? 2 : 1;
     for (int f = 1; f <= nlap; ++f) {
 #pragma unroll
-      for (int m = 0; m < RM; ++m) v[m] = I->G[f * fs + (int64_t)(t + m * T) * nh + kxc];
-      fft<PY, false>(v, lds, I->tw_y, t);
+      for (int m = 0; m < RM; ++m) v[m] = gload(G + f * fs + sidx(rows, t + m * T, kp));
+      fft<PY, false>(v, lds, tw, t);
+      c2 o[RM];
 #pragma unroll
-      for (int m = 0; m < RM; ++m) {
-        const double k2 = wavenum2(I, kxc, t + m * T, N);
-        v[m] = cscale(v[m], -k2 * I->inv_p);
-      }
-      fft<PY, true>(v, lds, I->tw_y, t);
-      if (valid) {
+      for (int m = 0; m < RM; ++m) o[m] = cscale(v[m], -wavenum2(I, kp, t + m * T, N) * I->inv_p);
+      if (blk0)
+        col0_mirror<PY>(v, smem, special, t, [&](int m, c2 w) {
+          const double q = wavenum2(I, 0, opaque(t + m * T), N);
+          o[m] = cadd(cscale(v[m], -(q + 0.5 * kxn2) * I->inv_p), cscale(w, 0.5 * kxn2 * I->inv_p));
+        });
+      fft<PY, true>(o, lds, tw, t);
 #pragma unroll
-        for (int m = 0; m < RM; ++m) I->G[f * fs + (int64_t)(t + m * T) * nh + kx] = v[m];
-      }
+      for (int m = 0; m < RM; ++m) gstore(G + f * fs + sidx(rows, t + m * T, kp), o[m]);
     }
   }
 }
@@ -568,15 +690,17 @@ __global__ __launch_bounds__(256) void k_row_start_fch(const InstDev* __restrict
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;
   c2* lds = smem + team * lds_len(N);
   const int r0 = 2 * (blockIdx.x * teams + team);
-  const int nh = I->nh;
-  const int64_t fs = I->field_stride;
+  const int rows = I->rows;
+  const uint32_t fs = (uint32_t)I->field_stride;
   const double th = I->theta;
   const bool mp = th != 1.0;
+  Twiddles<PX> tw;
+  load_twiddles<PX>(tw, I->tw_x, t);
   double lx[2][RM], lu[2][RM];
   if (!mp) {
     c2 v[RM];
-    load_pack<PX>(v, I->G + fs + (int64_t)r0 * nh, I->G + fs + (int64_t)(r0 + 1) * nh, t);
-    fft<PX, true>(v, lds, I->tw_x, t);
+    load_pack<PX>(v, gp(I->G) + fs, r0, gp(I->G) + fs, r0 + 1, rows, t);
+    fft<PX, true>(v, lds, tw, t);
 #pragma unroll
     for (int m = 0; m < RM; ++m) {
       lx[0][m] = v[m].x;
@@ -589,8 +713,8 @@ __global__ __launch_bounds__(256) void k_row_start_fch(const InstDev* __restrict
     for (int row = 0; row < 2; ++row) {
       c2 v[RM];
       const int r = r0 + row;
-      load_pack<PX>(v, I->G + fs + (int64_t)r * nh, I->G + 2 * fs + (int64_t)r * nh, t);
-      fft<PX, true>(v, lds, I->tw_x, t);
+      load_pack<PX>(v, gp(I->G) + fs, r, gp(I->G) + 2 * fs, r, rows, t);
+      fft<PX, true>(v, lds, tw, t);
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
         lx[row][m] = v[m].x;
@@ -604,18 +728,17 @@ __global__ __launch_bounds__(256) void k_row_start_fch(const InstDev* __restrict
     double lv[RM];
 #pragma unroll
     for (int m = 0; m < RM; ++m) {
-      const int64_t idx = (int64_t)(r0 + row) * N + t + m * T;
-      I->DX[0][idx] = lx[row][m];
-      I->DX[2][idx] = lx[row][m];
-      if (mp) I->dun[idx] = lu[row][m];
-      const double x0 = I->X[0][idx];
-      vbs[row][m] = mp ? th * x0 + (1.0 - th) * I->un[idx] : x0;
+      const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+      gp(I->DX[0])[idx] = lx[row][m];
+      gp(I->DX[2])[idx] = lx[row][m];
+      if (mp) gp(I->dun)[idx] = lu[row][m];
+      const double x0 = gp(I->X[0])[idx];
+      vbs[row][m] = mp ? th * x0 + (1.0 - th) * gp(I->un)[idx] : x0;
       lv[m] = mp ? th * lx[row][m] + (1.0 - th) * lu[row][m] : lx[row][m];
     }
-    fch_forward_row<PX>(I, vbs[row], lv, lds, r0 + row, t);
+    fch_forward_row<PX>(I, vbs[row], lv, tw, lds, r0 + row, t);
   }
-  pair_forward<PX>(I, vbs[0], vbs[1], lds, I->S + 2 * fs + (int64_t)r0 * nh,
-                   I->S + 2 * fs + (int64_t)(r0 + 1) * nh, t);
+  pair_forward<PX>(vbs[0], vbs[1], tw, lds, gp(I->S) + 2 * fs, r0, gp(I->S) + 2 * fs, r0 + 1, rows, t);
 }
 
 }  // namespace pfch

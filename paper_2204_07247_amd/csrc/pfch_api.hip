@@ -53,14 +53,14 @@ ColK make_col() {
 }
 
 using P8 = Plan<8, 8>;
-using P16 = Plan<16, 16>;
+using P16 = Plan<16, 8, 2>;
 using P32 = Plan<32, 8, 4>;
 using P64 = Plan<64, 8, 8>;
-using P128 = Plan<128, 16, 8>;
-using P256 = Plan<256, 16, 16>;
+using P128 = Plan<128, 8, 8, 2>;
+using P256 = Plan<256, 8, 8, 4>;
 using P512 = Plan<512, 8, 8, 8>;
-using P1024 = Plan<1024, 16, 16, 4>;
-using P2048 = Plan<2048, 16, 16, 8>;
+using P1024 = Plan<1024, 8, 8, 4, 4>;
+using P2048 = Plan<2048, 8, 8, 8, 4>;
 
 template <int MODEL>
 bool row_kernels(int n, RowK& k) {
@@ -245,19 +245,18 @@ double double_of(uint64_t b) {
   return v;
 }
 
-// Teams (row pairs) per row block: aim at ~128 threads, divide rows/2.
+// Row pairs per row block: the most (up to 256 threads) that still leave
+// at least 256 blocks; at least one.
 int pick_teams(int T, int pairs) {
-  int teams = 128 / T;
-  if (teams < 1) teams = 1;
-  while (teams > 1 && (pairs % teams) != 0) teams >>= 1;
-  if (teams > pairs) teams = pairs;
+  int teams = 1;
+  while (teams * 2 * T <= 256 && pairs % (teams * 2) == 0 && pairs / (teams * 2) >= 256) teams *= 2;
   return teams;
 }
-int pick_cols(int T) {
-  int cb = 256 / T;
-  if (cb < 2) cb = 2;
-  if (cb > 16) cb = 16;
-  if (cb * T > 512) cb = 512 / T;
+// Physical columns per column block (1, 2 or 4 of a 4-wide tile): the
+// widest that keeps >= 256 blocks and <= 512 threads.
+int pick_cols(int T, int H) {
+  int cb = 4;
+  while (cb > 1 && (cb * T > 512 || H / cb < 256)) cb >>= 1;
   return cb;
 }
 
@@ -265,7 +264,7 @@ int setup_instance(pfch_ctx* ctx, Instance& I) {
   const pfch_instance_desc& d = I.d;
   I.nx = d.n[0];
   I.ny = d.n[1];
-  I.nh = I.nx / 2 + 1;
+  I.nh = I.nx / 2;
   I.rows = I.ny;
   I.npts = (int64_t)I.nx * I.ny;
   bool ok = d.model == PFCH_PFC ? row_kernels<MODEL_PFC>(I.nx, I.rk) && col_kernels<MODEL_PFC>(I.ny, I.ck)
@@ -276,9 +275,9 @@ int setup_instance(pfch_ctx* ctx, Instance& I) {
   I.row_block = dim3(I.rk.T * teams);
   I.row_grid = dim3(pairs / teams);
   I.row_lds = (size_t)teams * I.rk.lds_elems * sizeof(c2);
-  const int cb = pick_cols(I.ck.T);
+  const int cb = pick_cols(I.ck.T, I.nh);
   I.col_block = dim3(I.ck.T * cb);
-  I.col_grid = dim3((I.nh + cb - 1) / cb);
+  I.col_grid = dim3(I.nh / cb);
   I.col_lds = (size_t)cb * I.ck.lds_elems * sizeof(c2);
   if (I.row_lds > 160 * 1024 || I.col_lds > 160 * 1024) return PFCH_E_UNSUPPORTED;
 
@@ -306,6 +305,7 @@ int setup_instance(pfch_ctx* ctx, Instance& I) {
   h.eta2 = d.eta2;
   h.tau = d.tau;
   h.mobility = d.mobility;
+  h.inv_mobility = 1.0 / d.mobility;
   h.s = d.s;
   h.theta_l = d.theta_l;
   const double rs = std::sqrt(d.s);

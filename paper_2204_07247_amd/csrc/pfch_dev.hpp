@@ -22,14 +22,14 @@ struct StopRec {
 
 struct InstDev {
   // geometry (2D: nz = 1)
-  int32_t nx, ny, nz, nh;  // nh = nx/2 + 1
+  int32_t nx, ny, nz, nh;  // nh = nx/2 physical spectral columns
   int32_t model, scheme;
   int32_t rows;            // ny * nz: number of x-rows
   int32_t nparts;          // partial-sum slots written by the setup row kernel
   double kx_scale, ky_scale, kz_scale;  // 2 pi / L per axis
   double inv_p;            // 1 / (nx ny nz)
   // model
-  double eps, eta1, eta2, tau, mobility;
+  double eps, eta1, eta2, tau, mobility, inv_mobility;
   // solver
   double s, theta_l;
   double lam[8];
@@ -37,14 +37,15 @@ struct InstDev {
   uint64_t tol_bits;
   // per step (written by the setup kernel, read by the iteration kernels)
   double a, theta, a_over_theta;
+  double beta0, beta2;     // averaged-Newton constants (setup column kernel)
   const double* un;        // u^n used by the midpoint blend
   // state buffers
   double* X[3];            // iterate ring x_j at X[j % 3]
   double* DX[3];           // FCH: Laplacian of the iterate, same ring
   double* dun;             // FCH midpoint: Laplacian of u^n
-  c2* S;                   // spectral rows [field][rows][nh]
-  c2* G;                   // setup spectral rows [field][rows][nh]
-  c2* ghat;                // transformed step constant g, [rows][nh]
+  c2* S;                   // spectral fields [field][tile][rows][4]
+  c2* G;                   // setup spectral fields, same layout
+  c2* ghat;                // transformed step constant g, tiled like S
   double* part;            // setup partial sums [nparts][2]
   uint64_t* norms;         // ||d_j||_inf bits, [max_iter]
   int32_t* iter_base;      // first iteration index of the current chunk
