@@ -44,7 +44,8 @@ def log(msg):
 def algorithmic_bytes(w):
     """Compulsory HBM bytes per launch of the two iteration kernels.
 
-    Real field: Ny*Nx doubles.  Spectral field: Ny*(Nx/2+1) complex doubles.
+    Real field: Ny*Nx doubles.  Spectral field: Ny*Nx/2 complex doubles (the
+    half spectrum's two real columns kx = 0 and kx = Nx/2 share one).
     PFC row kernel: read 1 spectral + x_j, x_{j-1} (+ u^n for MP), write
     x_{j+1} + 2 spectral.  PFC column kernel: read 2 spectral + g^, write 1.
     FCH row kernel: read 2 spectral + x_j, x_{j-1}, Lx_j, Lx_{j-1} (+ u^n,
@@ -53,7 +54,7 @@ def algorithmic_bytes(w):
     """
     ny, nx = w.shape
     real = 8 * nx * ny
-    spec = 16 * ny * (nx // 2 + 1)
+    spec = 16 * ny * (nx // 2)
     mp = w.scheme == "mp"
     if w.model == "pfc":
         row = spec + 2 * real + (real if mp else 0) + real + 2 * spec
@@ -62,6 +63,30 @@ def algorithmic_bytes(w):
         row = 2 * spec + 4 * real + (2 * real if mp else 0) + 2 * real + 3 * spec
         col = 3 * spec + spec + 2 * spec
     return dict(row=row, col=col)
+
+
+def measured_traffic(w, kernel):
+    """HBM bytes per launch from the committed PMC summary, if it was taken on
+    the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    ent = rec.get(w.name, {}).get(f"k_{kernel}_iter")
+    if not ent or ent.get("source_sha256") != kernel_source_hash():
+        return None
+    return ent["traffic_bytes"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2204_07247_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
 
 
 def gpu_run(w, steps, warmup, kernel_timing):
@@ -96,12 +121,10 @@ def gpu_run(w, steps, warmup, kernel_timing):
     log(f"[bench] timed region done: {elapsed:.4f} s")
     timing = None
     if kernel_timing:
-        log("[bench] kernel timing pass (HIP events around each iteration kernel)")
-        ctx.set_kernel_timing(True)
-        run(steps)
-        torch.cuda.synchronize()
-        timing = ctx.kernel_timing()
-        ctx.set_kernel_timing(False)
+        reps = 50
+        log(f"[bench] kernel timing: HIP events around {reps} back-to-back launches per kernel")
+        timing = ctx.time_kernels(w.dt, reps)
+        timing["reps"] = reps
     cfg = ctx.launch_config()
     ctx.close()
     return elapsed, iters, timing, cfg
@@ -135,6 +158,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the run, copy a MIB-sized float64 buffer three times "
+                         "(a plain copy kernel of known traffic for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); independent "
@@ -142,6 +168,16 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     w = WORKLOADS[args.workload]
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: 3 x {args.copy_calibration} MiB read + write")
+        del src, dst
     elapsed, iters, timing, cfg = gpu_run(w, args.steps, args.warmup, not args.no_kernel_timing)
     value = args.steps / elapsed
     ab = algorithmic_bytes(w)
@@ -149,17 +185,15 @@ def main():
     kernels = {}
     if timing:
         for k in ("row", "col"):
-            n = timing[f"{k}_launches"]
-            if n:
-                avg = timing[f"{k}_ms"] / n * 1e-3
-                kernels[k] = dict(avg_us=avg * 1e6, launches=n, alg_bytes=ab[k],
-                                  achieved_gbs=ab[k] / avg / 1e9)
-        if kernels:
-            dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
-            kd = kernels[dom]
-            roof = dict(bound="hbm", kernel=f"k_{dom}_iter", achieved=round(kd["achieved_gbs"], 2),
-                        peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4), traffic=None)
+            avg = timing[f"{k}_us"] * 1e-6
+            kernels[k] = dict(avg_us=round(avg * 1e6, 3), launches=timing["reps"], alg_bytes=ab[k],
+                              achieved_gbs=round(ab[k] / avg / 1e9, 2))
+        dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
+        kd = kernels[dom]
+        roof = dict(bound="hbm", kernel=f"k_{dom}_iter", achieved=kd["achieved_gbs"],
+                    peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic(w, dom))
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")

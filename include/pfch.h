@@ -128,14 +128,14 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
  * solution (one extra reduction and synchronisation per step). */
 int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail);
 
-/* Kernel timing for measurement.  While enabled, the iteration graphs carry
- * HIP event nodes around every column and row kernel of instance 0, and each
- * iteration that did work adds its two kernel durations to running totals.
- * pfch_get_kernel_timing returns {column total ms, column launches, row total
- * ms, row launches} and resets the totals.  Enabling costs a few microseconds
- * per kernel; leave it off for throughput measurements. */
-int pfch_set_kernel_timing(pfch_ctx* ctx, int32_t enabled);
-int pfch_get_kernel_timing(pfch_ctx* ctx, double out[4]);
+/* Kernel timing for measurement.  Sets up one step of instance 0 from its
+ * current state (as pfch_step would, with step size dt), then launches its
+ * column and row iteration kernels `reps` times each, back to back on the
+ * context's stream, every launch doing the full work of an iteration, with
+ * one HIP event pair around each batch.  out = {column us per launch, row us
+ * per launch}.  The instance's state (u^n, u^{n-1}, t, step index) is not
+ * changed; its iteration workspaces are. */
+int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[2]);
 
 /* Launch geometry of instance `inst` for reporting: {row grid, row block,
  * row LDS bytes, column grid, column block, column LDS bytes}. */

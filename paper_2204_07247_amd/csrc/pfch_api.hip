@@ -191,12 +191,9 @@ struct pfch_ctx {
   StopRec* h_recs = nullptr;   // pinned
   double* h_mass = nullptr;    // pinned [n]
   std::map<int, c2*> twiddles;
-  std::map<int, hipGraphExec_t> graphs;       // key: chunk length K (negative: timed)
-  std::map<int, std::vector<hipEvent_t>> graph_events;  // timed graphs' event nodes
+  std::map<int, hipGraphExec_t> graphs;       // key: chunk length K
   std::vector<hipGraph_t> graph_defs;
   int stats_detail = 1;
-  bool timing = false;
-  double time_tot[4] = {0, 0, 0, 0};  // column ms, column launches, row ms, row launches
   std::vector<void*> allocs;
 };
 
@@ -384,11 +381,9 @@ int launch(const void* f, dim3 g, dim3 b, size_t lds, void** args, hipStream_t s
 }
 
 // Build (once per chunk length) a graph running `K` iterations of every
-// instance, then the chunk-end bookkeeping.  A timed graph also records an
-// event before, between and after instance 0's kernels of every iteration.
-int get_graph(pfch_ctx* ctx, int K, bool timed, hipGraphExec_t* out) {
-  const int key = timed ? -K : K;
-  auto it = ctx->graphs.find(key);
+// instance, then the chunk-end bookkeeping.
+int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
+  auto it = ctx->graphs.find(K);
   if (it != ctx->graphs.end()) {
     *out = it->second;
     return PFCH_OK;
@@ -396,23 +391,9 @@ int get_graph(pfch_ctx* ctx, int K, bool timed, hipGraphExec_t* out) {
   hipGraph_t g;
   HIPCHK(hipGraphCreate(&g, 0));
   std::vector<hipGraphNode_t> tails;
-  std::vector<hipEvent_t> events;
-  auto add_event = [&](hipGraphNode_t* prev) -> int {
-    hipEvent_t e;
-    HIPCHK(hipEventCreate(&e));
-    events.push_back(e);
-    hipGraphNode_t node;
-    HIPCHK(hipGraphAddEventRecordNode(&node, g, *prev ? prev : nullptr, *prev ? 1 : 0, e));
-    *prev = node;
-    return PFCH_OK;
-  };
   // Kernel arguments are copied into the node at creation time.
-  for (size_t ii = 0; ii < ctx->inst.size(); ++ii) {
-    Instance& I = ctx->inst[ii];
-    const bool ev = timed && ii == 0;
+  for (auto& I : ctx->inst) {
     hipGraphNode_t prev = nullptr;
-    int rc;
-    if (ev && (rc = add_event(&prev))) return rc;
     for (int l = 0; l < K; ++l) {
       for (int half = 0; half < 2; ++half) {
         hipKernelNodeParams p{};
@@ -428,7 +409,6 @@ int get_graph(pfch_ctx* ctx, int K, bool timed, hipGraphExec_t* out) {
         hipGraphNode_t node;
         HIPCHK(hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p));
         prev = node;
-        if (ev && (rc = add_event(&prev))) return rc;
       }
     }
     tails.push_back(prev);
@@ -450,16 +430,21 @@ int get_graph(pfch_ctx* ctx, int K, bool timed, hipGraphExec_t* out) {
   hipGraphExec_t ex;
   HIPCHK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
   ctx->graph_defs.push_back(g);
-  ctx->graphs[key] = ex;
-  if (timed) ctx->graph_events[key] = events;
+  ctx->graphs[K] = ex;
   *out = ex;
   return PFCH_OK;
 }
 
-int chunk_len(int predicted) {
-  int k = 2;
-  while (k < predicted && k < 64) k <<= 1;
-  return k;
+// Iterations per graph launch.  Every launch ends with one host
+// synchronisation, and iterations past the stop still cost their (empty)
+// launches, so the first chunk covers the predicted count exactly and
+// further chunks are short.  Lengths are rounded to a small set so few
+// graphs get built.
+int chunk_len(int want) {
+  static const int lens[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 64};
+  for (int k : lens)
+    if (k >= want) return k;
+  return 64;
 }
 
 struct StepSetup {
@@ -468,6 +453,34 @@ struct StepSetup {
   const double* xin;
   double a, b, c, theta, rho;
 };
+
+// Coefficients (eq. obj:BDF2 with backward Euler first, eq. obj:MP) and
+// extrapolation factor for the next step of size dt.
+StepSetup step_setup_for(const Instance& I, double dt) {
+  StepSetup ss{};
+  ss.un = I.U[I.ucur];
+  ss.unm1 = I.has_prev ? I.U[1 - I.ucur] : I.U[I.ucur];
+  ss.xin = nullptr;
+  if (I.d.scheme == PFCH_MP) {
+    ss.a = 1.0 / dt;
+    ss.b = -1.0 / dt;
+    ss.c = 0.0;
+    ss.theta = 0.5;
+  } else if (!I.has_prev) {
+    ss.a = 1.0 / dt;
+    ss.b = -1.0 / dt;
+    ss.c = 0.0;
+    ss.theta = 1.0;
+  } else {
+    const double dp = I.dt_prev;
+    ss.a = 1.0 / dt + 1.0 / (dt + dp);
+    ss.b = -1.0 / dt - 1.0 / dp;
+    ss.c = 1.0 / dp - 1.0 / (dt + dp);
+    ss.theta = 1.0;
+  }
+  ss.rho = I.has_prev ? dt / I.dt_prev : 0.0;
+  return ss;
+}
 
 int launch_setup(pfch_ctx* ctx, Instance& I, const StepSetup& ss) {
   StepArgs sa;
@@ -498,45 +511,25 @@ int launch_setup(pfch_ctx* ctx, Instance& I, const StepSetup& ss) {
 
 // Replay iteration chunks until every instance in `active` has stopped.
 int run_iterations(pfch_ctx* ctx, const std::vector<int>& active) {
-  int predicted = 2;
-  for (int i : active) predicted = std::max(predicted, ctx->inst[i].last_iters + 1);
-  int K = chunk_len(predicted);
+  int predicted = 1;
+  for (int i : active) predicted = std::max(predicted, ctx->inst[i].last_iters);
+  int K = chunk_len(ctx->inst[active[0]].last_iters > 0 ? predicted : 16);
   const int n = (int)ctx->inst.size();
-  const bool timed = ctx->timing && !active.empty() && active[0] == 0;
-  int base0 = 0;  // host copy of instance 0's iteration base
   for (;;) {
     hipGraphExec_t ex;
-    int rc = get_graph(ctx, K, timed, &ex);
+    int rc = get_graph(ctx, K, &ex);
     if (rc) return rc;
     HIPCHK(hipGraphLaunch(ex, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->h_recs, ctx->d_recs, sizeof(StopRec) * n, hipMemcpyDeviceToHost,
                           ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    if (timed) {
-      const std::vector<hipEvent_t>& ev = ctx->graph_events[-K];
-      const StopRec& r = ctx->h_recs[0];
-      const int maxit = ctx->inst[0].d.max_iter;
-      for (int l = 0; l < K; ++l) {
-        const int j = base0 + l;
-        const bool ran = j < maxit && !(r.flags & FLAG_PRECOND) && (r.stop_iter < 0 || j <= r.stop_iter);
-        if (!ran) break;
-        float t0 = 0.f, t1 = 0.f;
-        HIPCHK(hipEventElapsedTime(&t0, ev[2 * l], ev[2 * l + 1]));
-        HIPCHK(hipEventElapsedTime(&t1, ev[2 * l + 1], ev[2 * l + 2]));
-        ctx->time_tot[0] += t0;
-        ctx->time_tot[1] += 1;
-        ctx->time_tot[2] += t1;
-        ctx->time_tot[3] += 1;
-      }
-      base0 += K;
-    }
     bool all = true;
     for (int i : active) {
       const StopRec& r = ctx->h_recs[i];
       if (r.stop_iter < 0 && !(r.flags & FLAG_PRECOND)) all = false;
     }
     if (all) return PFCH_OK;
-    K = 16;
+    K = chunk_len(2);
   }
 }
 
@@ -643,8 +636,6 @@ void pfch_destroy(pfch_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
-  for (auto& kv : ctx->graph_events)
-    for (auto e : kv.second) (void)hipEventDestroy(e);
   for (auto g : ctx->graph_defs) (void)hipGraphDestroy(g);
   for (auto& I : ctx->inst)
     for (void* p : I.allocs) (void)hipFree(p);
@@ -730,19 +721,34 @@ int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail) {
   return PFCH_OK;
 }
 
-int pfch_set_kernel_timing(pfch_ctx* ctx, int32_t enabled) {
-  if (!ctx) return PFCH_E_INVAL;
-  ctx->timing = enabled != 0;
-  for (double& v : ctx->time_tot) v = 0.0;
-  return PFCH_OK;
-}
-
-int pfch_get_kernel_timing(pfch_ctx* ctx, double out[4]) {
-  if (!ctx || !out) return PFCH_E_INVAL;
-  for (int i = 0; i < 4; ++i) {
-    out[i] = ctx->time_tot[i];
-    ctx->time_tot[i] = 0.0;
-  }
+int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[2]) {
+  if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
+  Instance& I = ctx->inst[0];
+  int rc;
+  if ((rc = launch_setup(ctx, I, step_setup_for(I, dt)))) return rc;
+  hipEvent_t e[3];
+  for (auto& ev : e) HIPCHK(hipEventCreate(&ev));
+  InstDev* dev = I.dev;
+  int l0 = 0;  // iteration 0 after setup: every launch does full work
+  void* args[] = {&dev, &l0};
+  HIPCHK(hipEventRecord(e[0], ctx->stream));
+  for (int r = 0; r < reps; ++r)
+    if ((rc = launch(I.ck.iter, I.col_grid, I.col_block, I.col_lds, args, ctx->stream))) return rc;
+  HIPCHK(hipEventRecord(e[1], ctx->stream));
+  for (int r = 0; r < reps; ++r)
+    if ((rc = launch(I.rk.iter, I.row_grid, I.row_block, I.row_lds, args, ctx->stream))) return rc;
+  HIPCHK(hipEventRecord(e[2], ctx->stream));
+  HIPCHK(hipEventSynchronize(e[2]));
+  float t0 = 0.f, t1 = 0.f;
+  HIPCHK(hipEventElapsedTime(&t0, e[0], e[1]));
+  HIPCHK(hipEventElapsedTime(&t1, e[1], e[2]));
+  for (auto& ev : e) (void)hipEventDestroy(ev);
+  out[0] = 1e3 * t0 / reps;
+  out[1] = 1e3 * t1 / reps;
+  // park the instance so later chunk launches leave it alone
+  int32_t park = I.d.max_iter + 1;
+  HIPCHK(hipMemcpyAsync(I.h.iter_base, &park, sizeof(park), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   return PFCH_OK;
 }
 
@@ -800,28 +806,7 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
   for (int i = 0; i < n; ++i) {
     Instance& I = ctx->inst[i];
     active[i] = i;
-    StepSetup ss{};
-    ss.un = I.U[I.ucur];
-    ss.unm1 = I.has_prev ? I.U[1 - I.ucur] : I.U[I.ucur];
-    ss.xin = nullptr;
-    if (I.d.scheme == PFCH_MP) {
-      ss.a = 1.0 / dt[i];
-      ss.b = -1.0 / dt[i];
-      ss.c = 0.0;
-      ss.theta = 0.5;
-    } else if (!I.has_prev) {
-      ss.a = 1.0 / dt[i];
-      ss.b = -1.0 / dt[i];
-      ss.c = 0.0;
-      ss.theta = 1.0;
-    } else {
-      const double dn = dt[i], dp = I.dt_prev;
-      ss.a = 1.0 / dn + 1.0 / (dn + dp);
-      ss.b = -1.0 / dn - 1.0 / dp;
-      ss.c = 1.0 / dp - 1.0 / (dn + dp);
-      ss.theta = 1.0;
-    }
-    ss.rho = I.has_prev ? dt[i] / I.dt_prev : 0.0;
+    const StepSetup ss = step_setup_for(I, dt[i]);
     as[i] = ss.a;
     if ((rc = launch_setup(ctx, I, ss))) return rc;
   }

@@ -27,8 +27,8 @@ PAPER_ETAS = tuple(math.sqrt(v) for v in (0.1, 0.575, 1.05, 1.525, 2.0))
 
 EXPORTED = (
     "pfch_validate_desc", "pfch_create", "pfch_set_state", "pfch_get_state",
-    "pfch_step", "pfch_solve", "pfch_set_stats_detail", "pfch_set_kernel_timing",
-    "pfch_get_kernel_timing", "pfch_get_launch_config", "pfch_destroy",
+    "pfch_step", "pfch_solve", "pfch_set_stats_detail", "pfch_time_kernels",
+    "pfch_get_launch_config", "pfch_destroy",
     "pfch_strerror", "pfch_version",
 )
 
@@ -89,8 +89,7 @@ def lib():
         L.pfch_step.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(Stats)]
         L.pfch_solve.argtypes = [vp, i32, dbl, dbl, dbl, vp, vp, vp, ctypes.POINTER(Stats)]
         L.pfch_set_stats_detail.argtypes = [vp, i32]
-        L.pfch_set_kernel_timing.argtypes = [vp, i32]
-        L.pfch_get_kernel_timing.argtypes = [vp, ctypes.POINTER(dbl)]
+        L.pfch_time_kernels.argtypes = [vp, dbl, i32, ctypes.POINTER(dbl)]
         L.pfch_get_launch_config.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
         L.pfch_destroy.argtypes = [vp]
         L.pfch_destroy.restype = None
@@ -98,8 +97,8 @@ def lib():
         L.pfch_strerror.restype = ctypes.c_char_p
         L.pfch_version.argtypes = []
         for name in ("pfch_validate_desc", "pfch_create", "pfch_set_state", "pfch_get_state",
-                     "pfch_step", "pfch_solve", "pfch_set_stats_detail", "pfch_set_kernel_timing",
-                     "pfch_get_kernel_timing", "pfch_get_launch_config", "pfch_version"):
+                     "pfch_step", "pfch_solve", "pfch_set_stats_detail", "pfch_time_kernels",
+                     "pfch_get_launch_config", "pfch_version"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -189,15 +188,14 @@ class Context:
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_set_stats_detail")
 
-    def set_kernel_timing(self, enabled):
-        lib().pfch_set_kernel_timing(self._h, int(bool(enabled)))
-
-    def kernel_timing(self):
-        """{col_ms, col_launches, row_ms, row_launches} since the last call."""
-        out = (ctypes.c_double * 4)()
-        lib().pfch_get_kernel_timing(self._h, out)
-        return dict(col_ms=out[0], col_launches=int(out[1]), row_ms=out[2],
-                    row_launches=int(out[3]))
+    def time_kernels(self, dt, reps):
+        """Average microseconds per launch of instance 0's column and row
+        iteration kernels (HIP events around `reps` back-to-back launches)."""
+        out = (ctypes.c_double * 2)()
+        rc = lib().pfch_time_kernels(self._h, float(dt), int(reps), out)
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_time_kernels")
+        return dict(col_us=out[0], row_us=out[1])
 
     def launch_config(self, inst=0):
         out = (ctypes.c_int64 * 6)()

@@ -89,4 +89,4 @@ def test_create_rejects_bad_arguments_before_device_work():
     assert L.pfch_create(ctypes.byref(_desc()), 0, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
     assert L.pfch_step(None, None, None) == pfch.PFCH_E_INVAL
     assert L.pfch_set_stats_detail(None, 1) == pfch.PFCH_E_INVAL
-    assert L.pfch_set_kernel_timing(None, 1) == pfch.PFCH_E_INVAL
+    assert L.pfch_time_kernels(None, 0.1, 1, None) == pfch.PFCH_E_INVAL
