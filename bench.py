@@ -130,6 +130,71 @@ def gpu_run(w, steps, warmup, kernel_timing):
     return elapsed, iters, timing, cfg
 
 
+def _desc(w):
+    from paper_2204_07247_amd import pfch
+    return pfch.make_desc(w.model, w.scheme, w.shape, w.lengths, eps=w.eps, eta1=w.eta1,
+                          eta2=w.eta2, tau=w.tau, mobility=w.mobility, s=w.s, etas=w.etas,
+                          tol=w.tol, max_iter=w.max_iter)
+
+
+def batched_comparison(count, steps, solo_steps):
+    """The PFC ensemble (Nx, Ny from {128, 256, 512}, eps, mean drawn per
+    instance) advanced in one context (grouped launches, one iteration graph)
+    against the same instances advanced one context at a time."""
+    import torch
+    from paper_2204_07247_amd import pfch
+    ens = W.pfc_ensemble(count=count)
+    u0 = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ens]
+    ctx = pfch.Context([_desc(w) for w in ens])
+    ctx.set_stats_detail(0)
+
+    def run(n):
+        for i, u in enumerate(u0):
+            ctx.set_state(i, u)
+        its = []
+        for _ in range(n):
+            rc, st = ctx.step([w.dt for w in ens])
+            if rc != pfch.PFCH_OK:
+                raise RuntimeError(f"batched step failed: {pfch.strerror(rc)}")
+            its.append(np.mean([x["iters"] for x in st]))
+        return its
+
+    log(f"[bench] batched ensemble: {count} instances, {steps} steps")
+    run(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = run(steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    ctx.close()
+    log(f"[bench] the same instances one context at a time, {solo_steps} steps each")
+    ts = 0.0
+    for w, u in zip(ens, u0):
+        c = pfch.Context([_desc(w)])
+        c.set_stats_detail(0)
+        c.set_state(0, u)
+        c.step(w.dt)
+        c.set_state(0, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(solo_steps):
+            rc, _ = c.step(w.dt)
+            if rc != pfch.PFCH_OK:
+                raise RuntimeError(f"solo step failed: {pfch.strerror(rc)}")
+        torch.cuda.synchronize()
+        ts += time.perf_counter() - t0
+        c.close()
+    npts = int(sum(w.npoints for w in ens))
+    batched = count * steps / tb
+    plain = count * solo_steps / ts
+    return dict(workload=f"pfc2d_ensemble{count}", instances=count, points=npts,
+                batched_instance_steps_per_s=round(batched, 2),
+                plain_instance_steps_per_s=round(plain, 2),
+                batched_over_plain=round(batched / plain, 3),
+                batched_steps=steps, plain_steps_per_instance=solo_steps,
+                iters_per_step_mean=round(float(np.mean(its)), 3))
+
+
 def cpu_baseline(w, max_steps, budget_s):
     """The CPU oracle on the same workload, first steps of the same trajectory."""
     from oracle import driver, models, spectral
@@ -158,6 +223,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the batched-ensemble comparison")
+    ap.add_argument("--ensemble", type=int, default=64, help="instances in the batched comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the run, copy a MIB-sized float64 buffer three times "
                          "(a plain copy kernel of known traffic for counter calibration)")
@@ -194,6 +262,9 @@ def main():
                     peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4),
                     traffic=measured_traffic(w, dom))
+    batched = None
+    if not args.no_compare:
+        batched = batched_comparison(args.ensemble, steps=10, solo_steps=4)
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
@@ -208,7 +279,7 @@ def main():
                     scheme=w.scheme, dt=w.dt, tol=w.tol, s=w.s, seed=w.seeds[0]),
         iters_per_step=dict(mean=round(float(it.mean()), 3), min=int(it.min()), max=int(it.max())),
         fft_pairs_per_iter=fft_pairs,
-        roofline=roof, kernels=kernels, launch=cfg, cpu_baseline=cpu,
+        roofline=roof, kernels=kernels, launch=cfg, cpu_baseline=cpu, batched=batched,
     )
     if cpu:
         out["gpu_over_cpu"] = round(value / cpu["value"], 2)

@@ -46,6 +46,17 @@ __device__ __forceinline__ uint32_t sidx(int rows, int row, int kp) {
 // barriers).
 __device__ __forceinline__ int opaque(int v) { return opaque_i(v); }
 
+// Grouped launches: one launch covers every instance of a group (same model
+// and grid); block b works on instance b / bpi as its local block b % bpi.
+struct GroupPos {
+  const InstDev* I;
+  int lb;  // block index within the instance
+};
+__device__ __forceinline__ GroupPos group_pos(const InstDev* const* __restrict__ grp, int bpi) {
+  const int gi = blockIdx.x / bpi;
+  return GroupPos{grp[gi], (int)blockIdx.x - gi * bpi};
+}
+
 // True when iteration j must not run: the cap is reached, or iteration j-1
 // met the tolerance or produced a non-finite norm.  Iterations that were
 // skipped leave their norm slot at 0, which also reads as "stopped".
@@ -208,7 +219,7 @@ __device__ __forceinline__ void finish_betas(InstDev* I) {
 struct ColPos {
   int c, t, kp;
 };
-__device__ __forceinline__ ColPos col_pos(int T, int ntiles) {
+__device__ __forceinline__ ColPos col_pos(int T, int ntiles, int lb) {
   const int cb = blockDim.x / T;
   ColPos p;
   p.c = threadIdx.x % cb;
@@ -216,12 +227,12 @@ __device__ __forceinline__ ColPos col_pos(int T, int ntiles) {
   const int per_tile = TW / cb;
   int tile, sub;
   if (per_tile > 1 && (ntiles & 7) == 0) {
-    const int g = blockIdx.x / (8 * per_tile), r = blockIdx.x % (8 * per_tile);
+    const int g = lb / (8 * per_tile), r = lb % (8 * per_tile);
     tile = g * 8 + (r & 7);
     sub = r >> 3;
   } else {
-    tile = blockIdx.x / per_tile;
-    sub = blockIdx.x % per_tile;
+    tile = lb / per_tile;
+    sub = lb % per_tile;
   }
   p.kp = tile * TW + sub * cb + p.c;
   return p;
@@ -267,17 +278,20 @@ __device__ __forceinline__ void col0_mirror(const c2 (&v)[P::RMAX], c2* lds0, bo
 // comes out of its y-transform.
 // ---------------------------------------------------------------------------
 template <class PY, int MODEL>
-__global__ __launch_bounds__(512) void k_col_iter(const InstDev* __restrict__ I, int l) {
+__global__ __launch_bounds__(512) void k_col_iter(const InstDev* const* __restrict__ grp, int bpi,
+                                                  int l) {
   extern __shared__ c2 smem[];
+  const GroupPos gpos = group_pos(grp, bpi);
+  const InstDev* __restrict__ I = gpos.I;
   const int j = *I->iter_base + l;
   if (stopped_before(I, j)) return;
   constexpr int N = PY::N, T = PY::T, RM = PY::RMAX;
   const int rows = N;
-  const ColPos pos = col_pos(T, I->nh / TW);
+  const ColPos pos = col_pos(T, I->nh / TW, gpos.lb);
   const int t = pos.t, kp = pos.kp;
   c2* lds = smem + pos.c * lds_len(N);
   const bool special = kp == 0;  // this thread's column holds kx = 0 and kx = nx/2
-  const bool blk0 = blockIdx.x == 0;  // the block holding physical column 0
+  const bool blk0 = gpos.lb == 0;  // the block holding physical column 0
   const uint32_t fs = (uint32_t)I->field_stride;
   GLB c2* S = gp(I->S);
   Twiddles<PY> tw;
@@ -429,16 +443,19 @@ __device__ __forceinline__ void pair_forward(const double (&a)[PX::RMAX], const 
 }
 
 template <class PX, int MODEL>
-__global__ __launch_bounds__(256) void k_row_iter(const InstDev* __restrict__ I, int l) {
+__global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restrict__ grp, int bpi,
+                                                  int l) {
   extern __shared__ c2 smem[];
   __shared__ uint64_t red[4];
+  const GroupPos gpos = group_pos(grp, bpi);
+  const InstDev* __restrict__ I = gpos.I;
   const int j = *I->iter_base + l;
   if (stopped_before(I, j)) return;
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
   const int teams = blockDim.x / T;
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;
   c2* lds = smem + team * lds_len(N);
-  const int r0 = 2 * (blockIdx.x * teams + team);
+  const int r0 = 2 * (gpos.lb * teams + team);
   const int rows = I->rows;
   const uint32_t fs = (uint32_t)I->field_stride;
   const int ne = I->n_eta;
@@ -549,14 +566,18 @@ struct StepArgs {
 };
 
 template <class PX, int MODEL>
-__global__ __launch_bounds__(256) void k_row_setup(InstDev* __restrict__ I, StepArgs sa) {
+__global__ __launch_bounds__(256) void k_row_setup(InstDev* const* __restrict__ grp,
+                                                   const StepArgs* __restrict__ args, int bpi) {
   extern __shared__ c2 smem[];
   __shared__ double red[4];
+  const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
+  InstDev* __restrict__ I = grp[gi];
+  const StepArgs sa = args[gi];
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
   const int teams = blockDim.x / T;
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;
   c2* lds = smem + team * lds_len(N);
-  const int r0 = 2 * (blockIdx.x * teams + team);
+  const int r0 = 2 * (lb * teams + team);
   const int rows = I->rows;
   const uint32_t fs = (uint32_t)I->field_stride;
   const double th = sa.theta;
@@ -565,7 +586,7 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* __restrict__ I, Step
   Twiddles<PX> tw;
   load_twiddles<PX>(tw, I->tw_x, t);
 
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (lb == 0 && threadIdx.x == 0) {
     I->a = sa.a;
     I->theta = sa.theta;
     I->a_over_theta = sa.a / sa.theta;
@@ -577,8 +598,8 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* __restrict__ I, Step
     I->rec->norm_bits = 0;
   }
   {  // clear the per-iteration norm slots
-    const int nthreads = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < I->max_iter; i += nthreads) I->norms[i] = 0;
+    const int nthreads = bpi * blockDim.x;
+    for (int i = lb * blockDim.x + threadIdx.x; i < I->max_iter; i += nthreads) I->norms[i] = 0;
   }
 
   double s0 = 0.0, s1 = 0.0;
@@ -628,8 +649,8 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* __restrict__ I, Step
   const double bs0 = block_sum(s0, red);
   const double bs1 = block_sum(s1, red);
   if (threadIdx.x == 0) {
-    gp(I->part)[2 * blockIdx.x] = bs0;
-    gp(I->part)[2 * blockIdx.x + 1] = bs1;
+    gp(I->part)[2 * lb] = bs0;
+    gp(I->part)[2 * lb + 1] = bs1;
   }
 }
 
@@ -638,15 +659,17 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* __restrict__ I, Step
 // the midpoint rule) back as spectral rows.  Block 0 sums the averaged-Newton
 // partial sums.
 template <class PY, int MODEL>
-__global__ __launch_bounds__(512) void k_col_setup(InstDev* __restrict__ I) {
+__global__ __launch_bounds__(512) void k_col_setup(InstDev* const* __restrict__ grp, int bpi) {
   extern __shared__ c2 smem[];
+  const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
+  InstDev* __restrict__ I = grp[gi];
   constexpr int N = PY::N, T = PY::T, RM = PY::RMAX;
   const int rows = N;
-  const ColPos pos = col_pos(T, I->nh / TW);
+  const ColPos pos = col_pos(T, I->nh / TW, lb);
   const int t = pos.t, kp = pos.kp;
   c2* lds = smem + pos.c * lds_len(N);
   const bool special = kp == 0;
-  const bool blk0 = blockIdx.x == 0;
+  const bool blk0 = lb == 0;
   const uint32_t fs = (uint32_t)I->field_stride;
   GLB c2* G = gp(I->G);
   Twiddles<PY> tw;
@@ -683,13 +706,15 @@ __global__ __launch_bounds__(512) void k_col_setup(InstDev* __restrict__ I) {
 // FCH step setup, second row part: Laplacians of x0 (and u^n) in real
 // space, then the forward transforms that start iteration 0 (y_0 = x_0).
 template <class PX>
-__global__ __launch_bounds__(256) void k_row_start_fch(const InstDev* __restrict__ I) {
+__global__ __launch_bounds__(256) void k_row_start_fch(const InstDev* const* __restrict__ grp, int bpi) {
   extern __shared__ c2 smem[];
+  const GroupPos gpos = group_pos(grp, bpi);
+  const InstDev* __restrict__ I = gpos.I;
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
   const int teams = blockDim.x / T;
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;
   c2* lds = smem + team * lds_len(N);
-  const int r0 = 2 * (blockIdx.x * teams + team);
+  const int r0 = 2 * (gpos.lb * teams + team);
   const int rows = I->rows;
   const uint32_t fs = (uint32_t)I->field_stride;
   const double th = I->theta;

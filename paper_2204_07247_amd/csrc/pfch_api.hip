@@ -1,11 +1,18 @@
-// Host runtime of libpfch: context, workspaces, launch graphs and the C ABI.
+// Host runtime of libpfch: context, workspaces, grouped launches, iteration
+// graphs and the C ABI.
+//
+// Instances that share (model, Nx, Ny) form a group; every kernel launch
+// covers a whole group (block b works on member b / bpi).  One iteration
+// graph holds, per group, a chain of column/row kernels for K iterations;
+// the chains of different groups are independent and may run concurrently.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
-#include <memory>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pfch.h"
@@ -93,9 +100,7 @@ bool col_kernels(int n, ColK& k) {
   }
 }
 
-bool supported_len(int n) {
-  return n >= 8 && n <= 2048 && (n & (n - 1)) == 0;
-}
+bool supported_len(int n) { return n >= 8 && n <= 2048 && (n & (n - 1)) == 0; }
 
 // ---------------------------------------------------------------------------
 // Small kernels: end of a chunk of iterations, accept, mass reduction.
@@ -126,37 +131,49 @@ __global__ void k_chunk_end(InstDev* const* insts, int n, int K) {
   *I->iter_base = stop ? I->max_iter + 1 : base + K;
 }
 
-constexpr int ACC_BLOCKS = 256, ACC_THREADS = 256;
+constexpr int ACC_BLOCKS = 64, ACC_THREADS = 256;
 
-__global__ __launch_bounds__(ACC_THREADS) void k_copy_sum(const double* __restrict__ src,
-                                                          double* __restrict__ dst, int64_t n,
-                                                          double* __restrict__ part) {
+// Accept: copy every converged instance's solution x_{stop+1} to its new
+// u^n slot (dsts[i]; null = not accepted) and, if part is given, write
+// ACC_BLOCKS partial sums of it per instance (fixed order).
+__global__ __launch_bounds__(ACC_THREADS) void k_accept(InstDev* const* __restrict__ insts,
+                                                        double* const* __restrict__ dsts,
+                                                        double* __restrict__ part) {
   __shared__ double red[ACC_THREADS / 64];
+  const int i = blockIdx.y;
+  double* dst = dsts[i];
+  if (!dst) return;
+  const InstDev* I = insts[i];
+  const int slot = (I->rec->stop_iter + 1) % 3;
+  const GLB double* src = gp((const double*)I->X[slot]);
+  GLB double* d = gp(dst);
+  const int64_t n = (int64_t)I->nx * I->ny * I->nz;
   double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = src[i];
-    if (dst) dst[i] = v;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const double v = src[k];
+    d[k] = v;
     s += v;
   }
   const double b = block_sum(s, red);
-  if (threadIdx.x == 0 && part) part[blockIdx.x] = b;
+  if (threadIdx.x == 0 && part) part[(int64_t)i * gridDim.x + blockIdx.x] = b;
 }
 
-__global__ void k_sum_parts(const double* __restrict__ part, int n, double scale, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s * scale;
-  }
+__global__ void k_sum_parts(const double* __restrict__ part, int nb, int n, const double* scale,
+                            double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < nb; ++k) s += part[(int64_t)i * nb + k];
+  out[i] = s * scale[i];
 }
 
 // ---------------------------------------------------------------------------
 // Host structures.
 // ---------------------------------------------------------------------------
-#define HIPCHK(x)                         \
-  do {                                    \
-    hipError_t e_ = (x);                  \
+#define HIPCHK(x)                            \
+  do {                                       \
+    hipError_t e_ = (x);                     \
     if (e_ != hipSuccess) return PFCH_E_HIP; \
   } while (0)
 
@@ -164,21 +181,31 @@ struct Instance {
   pfch_instance_desc d{};
   int nx = 0, ny = 0, nh = 0, rows = 0;
   int64_t npts = 0;
-  RowK rk;
-  ColK ck;
-  dim3 row_grid, row_block, col_grid, col_block;
-  size_t row_lds = 0, col_lds = 0;
-  InstDev h{};            // host mirror of the device descriptor
-  InstDev* dev = nullptr; // device descriptor
+  int group = -1;
+  InstDev h{};             // host mirror of the device descriptor
+  InstDev* dev = nullptr;  // device descriptor
+  InstDev** d_solo = nullptr;  // device array {dev}: single-instance launches
+  StepArgs* d_solo_args = nullptr;
   double* U[2] = {nullptr, nullptr};
   int ucur = 0;
   bool has_prev = false;
   double t = 0.0, dt_prev = 0.0;
   int step_index = 0;
   int last_iters = 0;
-  double* mass_part = nullptr;  // [ACC_BLOCKS]
-  double* mass_out = nullptr;   // device scalar
   std::vector<void*> allocs;
+};
+
+struct Group {
+  int model = 0, nx = 0, ny = 0;
+  RowK rk;
+  ColK ck;
+  dim3 row_block, col_block;
+  int row_bpi = 0, col_bpi = 0;  // blocks per instance
+  size_t row_lds = 0, col_lds = 0;
+  std::vector<int> members;
+  InstDev** d_members = nullptr;
+  StepArgs* d_args = nullptr;
+  StepArgs* h_args = nullptr;  // pinned
 };
 
 }  // namespace
@@ -186,15 +213,22 @@ struct Instance {
 struct pfch_ctx {
   hipStream_t stream = nullptr;
   std::vector<Instance> inst;
-  InstDev** d_ptrs = nullptr;
+  std::vector<Group> groups;
+  InstDev** d_ptrs = nullptr;  // all instances
   StopRec* d_recs = nullptr;
   StopRec* h_recs = nullptr;   // pinned
-  double* h_mass = nullptr;    // pinned [n]
+  double** d_dsts = nullptr;   // accept destinations
+  double** h_dsts = nullptr;   // pinned
+  double* d_part = nullptr;    // [n][ACC_BLOCKS]
+  double* d_scale = nullptr;   // 1/P per instance
+  double* d_mass = nullptr;
+  double* h_mass = nullptr;    // pinned
   std::map<int, c2*> twiddles;
-  std::map<int, hipGraphExec_t> graphs;       // key: chunk length K
+  std::map<int, hipGraphExec_t> graphs;  // key: chunk length K
   std::vector<hipGraph_t> graph_defs;
   int stats_detail = 1;
   std::vector<void*> allocs;
+  std::vector<void*> host_allocs;
 };
 
 namespace {
@@ -202,6 +236,15 @@ namespace {
 int dalloc(std::vector<void*>& list, void** p, size_t bytes) {
   if (bytes == 0) bytes = 8;
   if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return PFCH_E_NOMEM;
+  }
+  list.push_back(*p);
+  return PFCH_OK;
+}
+
+int halloc(std::vector<void*>& list, void** p, size_t bytes) {
+  if (hipHostMalloc(p, bytes, 0) != hipSuccess) {
     *p = nullptr;
     return PFCH_E_NOMEM;
   }
@@ -242,42 +285,27 @@ double double_of(uint64_t b) {
   return v;
 }
 
+// Launch geometry depends on the grid shape only (not on how many
+// instances share a launch), so an instance computes bitwise the same
+// result alone or in a batch (the averaged-Newton partial sums are per
+// block).
 // Row pairs per row block: the most (up to 256 threads) that still leave
-// at least 256 blocks; at least one.
+// at least 256 blocks per instance; at least one.
 int pick_teams(int T, int pairs) {
   int teams = 1;
   while (teams * 2 * T <= 256 && pairs % (teams * 2) == 0 && pairs / (teams * 2) >= 256) teams *= 2;
   return teams;
 }
 // Physical columns per column block (1, 2 or 4 of a 4-wide tile): the
-// widest that keeps >= 256 blocks and <= 512 threads.
+// widest that keeps >= 256 blocks per instance and <= 512 threads.
 int pick_cols(int T, int H) {
   int cb = 4;
   while (cb > 1 && (cb * T > 512 || H / cb < 256)) cb >>= 1;
   return cb;
 }
 
-int setup_instance(pfch_ctx* ctx, Instance& I) {
+int setup_instance(pfch_ctx* ctx, Instance& I, int nparts) {
   const pfch_instance_desc& d = I.d;
-  I.nx = d.n[0];
-  I.ny = d.n[1];
-  I.nh = I.nx / 2;
-  I.rows = I.ny;
-  I.npts = (int64_t)I.nx * I.ny;
-  bool ok = d.model == PFCH_PFC ? row_kernels<MODEL_PFC>(I.nx, I.rk) && col_kernels<MODEL_PFC>(I.ny, I.ck)
-                                : row_kernels<MODEL_FCH>(I.nx, I.rk) && col_kernels<MODEL_FCH>(I.ny, I.ck);
-  if (!ok) return PFCH_E_UNSUPPORTED;
-  const int pairs = I.rows / 2;
-  const int teams = pick_teams(I.rk.T, pairs);
-  I.row_block = dim3(I.rk.T * teams);
-  I.row_grid = dim3(pairs / teams);
-  I.row_lds = (size_t)teams * I.rk.lds_elems * sizeof(c2);
-  const int cb = pick_cols(I.ck.T, I.nh);
-  I.col_block = dim3(I.ck.T * cb);
-  I.col_grid = dim3(I.nh / cb);
-  I.col_lds = (size_t)cb * I.ck.lds_elems * sizeof(c2);
-  if (I.row_lds > 160 * 1024 || I.col_lds > 160 * 1024) return PFCH_E_UNSUPPORTED;
-
   const bool fch = d.model == PFCH_FCH;
   const int nfs = fch ? 3 : 2;  // spectral fields in S
   const int nfg = fch ? 3 : 1;  // spectral fields in G
@@ -291,7 +319,7 @@ int setup_instance(pfch_ctx* ctx, Instance& I) {
   h.model = fch ? MODEL_FCH : MODEL_PFC;
   h.scheme = d.scheme == PFCH_MP ? SCHEME_MP : SCHEME_BDF2;
   h.rows = I.rows;
-  h.nparts = (int)I.row_grid.x;
+  h.nparts = nparts;
   const double two_pi = 6.283185307179586476925286766559;
   h.kx_scale = two_pi / d.len[0];
   h.ky_scale = two_pi / d.len[1];
@@ -342,17 +370,13 @@ int setup_instance(pfch_ctx* ctx, Instance& I) {
   h.G = (c2*)p;
   if ((rc = dalloc(I.allocs, &p, sbytes))) return rc;
   h.ghat = (c2*)p;
-  if ((rc = dalloc(I.allocs, &p, sizeof(double) * 2 * h.nparts))) return rc;
+  if ((rc = dalloc(I.allocs, &p, sizeof(double) * 2 * nparts))) return rc;
   h.part = (double*)p;
   if ((rc = dalloc(I.allocs, &p, sizeof(uint64_t) * d.max_iter))) return rc;
   h.norms = (uint64_t*)p;
   if ((rc = dalloc(I.allocs, &p, 64))) return rc;
   h.iter_base = (int32_t*)p;
   h.flags = (int32_t*)p + 1;
-  if ((rc = dalloc(I.allocs, &p, sizeof(double) * ACC_BLOCKS))) return rc;
-  I.mass_part = (double*)p;
-  if ((rc = dalloc(I.allocs, &p, sizeof(double)))) return rc;
-  I.mass_out = (double*)p;
   c2* tw = nullptr;
   if ((rc = get_twiddles(ctx, I.nx, &tw))) return rc;
   h.tw_x = tw;
@@ -361,17 +385,16 @@ int setup_instance(pfch_ctx* ctx, Instance& I) {
   h.tw_z = nullptr;
   if ((rc = dalloc(I.allocs, &p, sizeof(InstDev)))) return rc;
   I.dev = (InstDev*)p;
+  if ((rc = dalloc(I.allocs, &p, sizeof(InstDev*)))) return rc;
+  I.d_solo = (InstDev**)p;
+  if ((rc = dalloc(I.allocs, &p, sizeof(StepArgs)))) return rc;
+  I.d_solo_args = (StepArgs*)p;
+  HIPCHK(hipMemcpy(I.d_solo, &I.dev, sizeof(InstDev*), hipMemcpyHostToDevice));
   // No instance iterates before its first setup: park the iteration base
   // beyond the cap so every iteration kernel exits at once.
   int32_t init[2] = {d.max_iter + 1, 0};
   HIPCHK(hipMemcpy(h.iter_base, init, sizeof(init), hipMemcpyHostToDevice));
   HIPCHK(hipMemset(h.norms, 0, sizeof(uint64_t) * d.max_iter));
-  return PFCH_OK;
-}
-
-int upload_desc(pfch_ctx* ctx, Instance& I) {
-  HIPCHK(hipMemcpyAsync(I.dev, &I.h, sizeof(InstDev), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
   return PFCH_OK;
 }
 
@@ -381,7 +404,7 @@ int launch(const void* f, dim3 g, dim3 b, size_t lds, void** args, hipStream_t s
 }
 
 // Build (once per chunk length) a graph running `K` iterations of every
-// instance, then the chunk-end bookkeeping.
+// group, then the chunk-end bookkeeping.
 int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
   auto it = ctx->graphs.find(K);
   if (it != ctx->graphs.end()) {
@@ -392,18 +415,20 @@ int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
   HIPCHK(hipGraphCreate(&g, 0));
   std::vector<hipGraphNode_t> tails;
   // Kernel arguments are copied into the node at creation time.
-  for (auto& I : ctx->inst) {
+  for (auto& G : ctx->groups) {
     hipGraphNode_t prev = nullptr;
+    const unsigned nm = (unsigned)G.members.size();
     for (int l = 0; l < K; ++l) {
       for (int half = 0; half < 2; ++half) {
         hipKernelNodeParams p{};
-        InstDev* dev = I.dev;
+        InstDev** grp = G.d_members;
+        int bpi = half == 0 ? G.col_bpi : G.row_bpi;
         int lv = l;
-        void* args[] = {&dev, &lv};
-        p.func = const_cast<void*>(half == 0 ? I.ck.iter : I.rk.iter);
-        p.gridDim = half == 0 ? I.col_grid : I.row_grid;
-        p.blockDim = half == 0 ? I.col_block : I.row_block;
-        p.sharedMemBytes = (unsigned)(half == 0 ? I.col_lds : I.row_lds);
+        void* args[] = {&grp, &bpi, &lv};
+        p.func = const_cast<void*>(half == 0 ? G.ck.iter : G.rk.iter);
+        p.gridDim = dim3(nm * bpi);
+        p.blockDim = half == 0 ? G.col_block : G.row_block;
+        p.sharedMemBytes = (unsigned)(half == 0 ? G.col_lds : G.row_lds);
         p.kernelParams = args;
         p.extra = nullptr;
         hipGraphNode_t node;
@@ -454,6 +479,19 @@ struct StepSetup {
   double a, b, c, theta, rho;
 };
 
+StepArgs to_args(const StepSetup& ss) {
+  StepArgs sa;
+  sa.un = ss.un;
+  sa.unm1 = ss.unm1 ? ss.unm1 : ss.un;
+  sa.xin = ss.xin;
+  sa.rho = ss.rho;
+  sa.a = ss.a;
+  sa.theta = ss.theta;
+  sa.gu = ss.b - ss.a * (1.0 - ss.theta) / ss.theta;
+  sa.gm = ss.c;
+  return sa;
+}
+
 // Coefficients (eq. obj:BDF2 with backward Euler first, eq. obj:MP) and
 // extrapolation factor for the next step of size dt.
 StepSetup step_setup_for(const Instance& I, double dt) {
@@ -482,38 +520,43 @@ StepSetup step_setup_for(const Instance& I, double dt) {
   return ss;
 }
 
-int launch_setup(pfch_ctx* ctx, Instance& I, const StepSetup& ss) {
-  StepArgs sa;
-  sa.un = ss.un;
-  sa.unm1 = ss.unm1 ? ss.unm1 : ss.un;
-  sa.xin = ss.xin;
-  sa.rho = ss.rho;
-  sa.a = ss.a;
-  sa.theta = ss.theta;
-  sa.gu = ss.b - ss.a * (1.0 - ss.theta) / ss.theta;
-  sa.gm = ss.c;
-  InstDev* dev = I.dev;
+// Setup kernels for `nm` instances of group G described by the device arrays
+// (grp, args).
+int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, unsigned nm) {
   int rc;
+  int rbpi = G.row_bpi, cbpi = G.col_bpi;
   {
-    void* args[] = {&dev, &sa};
-    if ((rc = launch(I.rk.setup, I.row_grid, I.row_block, I.row_lds, args, ctx->stream))) return rc;
+    void* a[] = {&grp, &args, &rbpi};
+    if ((rc = launch(G.rk.setup, dim3(nm * rbpi), G.row_block, G.row_lds, a, ctx->stream))) return rc;
   }
   {
-    void* args[] = {&dev};
-    if ((rc = launch(I.ck.setup, I.col_grid, I.col_block, I.col_lds, args, ctx->stream))) return rc;
+    void* a[] = {&grp, &cbpi};
+    if ((rc = launch(G.ck.setup, dim3(nm * cbpi), G.col_block, G.col_lds, a, ctx->stream))) return rc;
   }
-  if (I.d.model == PFCH_FCH) {
-    void* args[] = {&dev};
-    if ((rc = launch(I.rk.start_fch, I.row_grid, I.row_block, I.row_lds, args, ctx->stream))) return rc;
+  if (G.model == PFCH_FCH) {
+    void* a[] = {&grp, &rbpi};
+    if ((rc = launch(G.rk.start_fch, dim3(nm * rbpi), G.row_block, G.row_lds, a, ctx->stream))) return rc;
   }
   return PFCH_OK;
+}
+
+int launch_setup_solo(pfch_ctx* ctx, Instance& I, const StepSetup& ss) {
+  StepArgs* h = ctx->groups[I.group].h_args;  // pinned staging (synchronised below)
+  *h = to_args(ss);
+  HIPCHK(hipMemcpyAsync(I.d_solo_args, h, sizeof(StepArgs), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return launch_setup(ctx, ctx->groups[I.group], I.d_solo, I.d_solo_args, 1);
 }
 
 // Replay iteration chunks until every instance in `active` has stopped.
 int run_iterations(pfch_ctx* ctx, const std::vector<int>& active) {
   int predicted = 1;
-  for (int i : active) predicted = std::max(predicted, ctx->inst[i].last_iters);
-  int K = chunk_len(ctx->inst[active[0]].last_iters > 0 ? predicted : 16);
+  bool known = true;
+  for (int i : active) {
+    predicted = std::max(predicted, ctx->inst[i].last_iters);
+    known = known && ctx->inst[i].last_iters > 0;
+  }
+  int K = chunk_len(known ? predicted : 16);
   const int n = (int)ctx->inst.size();
   for (;;) {
     hipGraphExec_t ex;
@@ -574,10 +617,12 @@ int betas_host(pfch_ctx* ctx, Instance& I, double a, double out[4]) {
 }
 
 int fft_pairs_of(const Instance& I, int iters) {
-  // real-field transform pairs: iterations use (nfwd + ninv)/2, setup adds
-  // the transforms of g, x0 (FCH) and u^n (FCH midpoint).
+  // Transform pairs of real fields (one forward + one inverse 2D transform
+  // of a real field counts as one pair).  Per iteration: PFC 2 forward + 1
+  // inverse, FCH 3 forward + 2 inverse.  Setup: g (+ x0 and its Laplacian,
+  // + u^n for the midpoint rule, FCH), plus the first iteration's forwards.
   const bool fch = I.d.model == PFCH_FCH;
-  const int per_iter = fch ? 5 : 3;  // forward + inverse real fields
+  const int per_iter = fch ? 5 : 3;
   const int setup = fch ? (I.d.scheme == PFCH_MP ? 2 * 3 + 3 : 2 * 2 + 3) : 1 + 2;
   return (per_iter * iters + setup + 1) / 2;
 }
@@ -640,8 +685,7 @@ void pfch_destroy(pfch_ctx* ctx) {
   for (auto& I : ctx->inst)
     for (void* p : I.allocs) (void)hipFree(p);
   for (void* p : ctx->allocs) (void)hipFree(p);
-  if (ctx->h_recs) (void)hipHostFree(ctx->h_recs);
-  if (ctx->h_mass) (void)hipHostFree(ctx->h_mass);
+  for (void* p : ctx->host_allocs) (void)hipHostFree(p);
   delete ctx;
 }
 
@@ -658,32 +702,113 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   ctx->inst.resize(n_inst);
   int rc = PFCH_OK;
   void* p = nullptr;
+  // --- groups by (model, Nx, Ny)
+  std::map<std::tuple<int, int, int>, int> gidx;
+  for (int i = 0; i < n_inst; ++i) {
+    Instance& I = ctx->inst[i];
+    I.d = descs[i];
+    I.nx = I.d.n[0];
+    I.ny = I.d.n[1];
+    I.nh = I.nx / 2;
+    I.rows = I.ny;
+    I.npts = (int64_t)I.nx * I.ny;
+    auto key = std::make_tuple(I.d.model, I.nx, I.ny);
+    auto it = gidx.find(key);
+    if (it == gidx.end()) {
+      Group G;
+      G.model = I.d.model;
+      G.nx = I.nx;
+      G.ny = I.ny;
+      const bool ok = G.model == PFCH_PFC
+                          ? row_kernels<MODEL_PFC>(I.nx, G.rk) && col_kernels<MODEL_PFC>(I.ny, G.ck)
+                          : row_kernels<MODEL_FCH>(I.nx, G.rk) && col_kernels<MODEL_FCH>(I.ny, G.ck);
+      if (!ok) {
+        delete ctx;
+        return PFCH_E_UNSUPPORTED;
+      }
+      it = gidx.emplace(key, (int)ctx->groups.size()).first;
+      ctx->groups.push_back(G);
+    }
+    I.group = it->second;
+    ctx->groups[I.group].members.push_back(i);
+  }
+  for (auto& G : ctx->groups) {
+    const int nm = (int)G.members.size();
+    const int pairs = G.ny / 2, H = G.nx / 2;
+    const int teams = pick_teams(G.rk.T, pairs);
+    G.row_block = dim3(G.rk.T * teams);
+    G.row_bpi = pairs / teams;
+    G.row_lds = (size_t)teams * G.rk.lds_elems * sizeof(c2);
+    const int cb = pick_cols(G.ck.T, H);
+    G.col_block = dim3(G.ck.T * cb);
+    G.col_bpi = H / cb;
+    G.col_lds = (size_t)cb * G.ck.lds_elems * sizeof(c2);
+    if (G.row_lds > 160 * 1024 || G.col_lds > 160 * 1024) {
+      rc = PFCH_E_UNSUPPORTED;
+      goto fail;
+    }
+    if ((rc = dalloc(ctx->allocs, &p, sizeof(InstDev*) * nm))) goto fail;
+    G.d_members = (InstDev**)p;
+    if ((rc = dalloc(ctx->allocs, &p, sizeof(StepArgs) * nm))) goto fail;
+    G.d_args = (StepArgs*)p;
+    if ((rc = halloc(ctx->host_allocs, &p, sizeof(StepArgs) * nm))) goto fail;
+    G.h_args = (StepArgs*)p;
+    const void* fs[] = {G.rk.iter, G.rk.setup, G.rk.start_fch};
+    for (const void* f : fs)
+      if (f && G.row_lds > 65536)
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.row_lds);
+    const void* gs[] = {G.ck.iter, G.ck.setup};
+    for (const void* f : gs)
+      if (f && G.col_lds > 65536)
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.col_lds);
+  }
   if ((rc = dalloc(ctx->allocs, &p, sizeof(StopRec) * n_inst))) goto fail;
   ctx->d_recs = (StopRec*)p;
   if ((rc = dalloc(ctx->allocs, &p, sizeof(InstDev*) * n_inst))) goto fail;
   ctx->d_ptrs = (InstDev**)p;
-  if (hipHostMalloc((void**)&ctx->h_recs, sizeof(StopRec) * n_inst, 0) != hipSuccess) {
-    rc = PFCH_E_NOMEM;
-    goto fail;
-  }
-  if (hipHostMalloc((void**)&ctx->h_mass, sizeof(double) * n_inst, 0) != hipSuccess) {
-    rc = PFCH_E_NOMEM;
-    goto fail;
-  }
+  if ((rc = dalloc(ctx->allocs, &p, sizeof(double*) * n_inst))) goto fail;
+  ctx->d_dsts = (double**)p;
+  if ((rc = dalloc(ctx->allocs, &p, sizeof(double) * n_inst * ACC_BLOCKS))) goto fail;
+  ctx->d_part = (double*)p;
+  if ((rc = dalloc(ctx->allocs, &p, sizeof(double) * n_inst))) goto fail;
+  ctx->d_scale = (double*)p;
+  if ((rc = dalloc(ctx->allocs, &p, sizeof(double) * n_inst))) goto fail;
+  ctx->d_mass = (double*)p;
+  if ((rc = halloc(ctx->host_allocs, &p, sizeof(StopRec) * n_inst))) goto fail;
+  ctx->h_recs = (StopRec*)p;
+  if ((rc = halloc(ctx->host_allocs, &p, sizeof(double*) * n_inst))) goto fail;
+  ctx->h_dsts = (double**)p;
+  if ((rc = halloc(ctx->host_allocs, &p, sizeof(double) * n_inst))) goto fail;
+  ctx->h_mass = (double*)p;
   {
     std::vector<InstDev*> ptrs(n_inst);
+    std::vector<double> scale(n_inst);
     for (int i = 0; i < n_inst; ++i) {
       Instance& I = ctx->inst[i];
-      I.d = descs[i];
-      if ((rc = setup_instance(ctx, I))) goto fail;
+      if ((rc = setup_instance(ctx, I, ctx->groups[I.group].row_bpi))) goto fail;
       I.h.rec = ctx->d_recs + i;
-      if ((rc = upload_desc(ctx, I))) goto fail;
+      if (hipMemcpy(I.dev, &I.h, sizeof(InstDev), hipMemcpyHostToDevice) != hipSuccess) {
+        rc = PFCH_E_HIP;
+        goto fail;
+      }
       ptrs[i] = I.dev;
+      scale[i] = 1.0 / (double)I.npts;
     }
     if (hipMemcpy(ctx->d_ptrs, ptrs.data(), sizeof(InstDev*) * n_inst, hipMemcpyHostToDevice) !=
-        hipSuccess) {
+            hipSuccess ||
+        hipMemcpy(ctx->d_scale, scale.data(), sizeof(double) * n_inst, hipMemcpyHostToDevice) !=
+            hipSuccess) {
       rc = PFCH_E_HIP;
       goto fail;
+    }
+    for (auto& G : ctx->groups) {
+      std::vector<InstDev*> mp;
+      for (int i : G.members) mp.push_back(ctx->inst[i].dev);
+      if (hipMemcpy(G.d_members, mp.data(), sizeof(InstDev*) * mp.size(), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+        rc = PFCH_E_HIP;
+        goto fail;
+      }
     }
     std::vector<StopRec> recs(n_inst);
     for (auto& r : recs) {
@@ -695,17 +820,6 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
         hipSuccess) {
       rc = PFCH_E_HIP;
       goto fail;
-    }
-    // Kernels that need more than the default dynamic LDS.
-    for (auto& I : ctx->inst) {
-      const void* fs[] = {I.rk.iter, I.rk.setup, I.rk.start_fch};
-      for (const void* f : fs)
-        if (f && I.row_lds > 65536)
-          (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)I.row_lds);
-      const void* gs[] = {I.ck.iter, I.ck.setup};
-      for (const void* f : gs)
-        if (f && I.col_lds > 65536)
-          (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)I.col_lds);
     }
   }
   *out = ctx;
@@ -724,19 +838,22 @@ int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail) {
 int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[2]) {
   if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
   Instance& I = ctx->inst[0];
+  const Group& G = ctx->groups[I.group];
   int rc;
-  if ((rc = launch_setup(ctx, I, step_setup_for(I, dt)))) return rc;
+  if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, dt)))) return rc;
   hipEvent_t e[3];
   for (auto& ev : e) HIPCHK(hipEventCreate(&ev));
-  InstDev* dev = I.dev;
+  InstDev** grp = I.d_solo;
   int l0 = 0;  // iteration 0 after setup: every launch does full work
-  void* args[] = {&dev, &l0};
+  int cbpi = G.col_bpi, rbpi = G.row_bpi;
+  void* ca[] = {&grp, &cbpi, &l0};
+  void* ra[] = {&grp, &rbpi, &l0};
   HIPCHK(hipEventRecord(e[0], ctx->stream));
   for (int r = 0; r < reps; ++r)
-    if ((rc = launch(I.ck.iter, I.col_grid, I.col_block, I.col_lds, args, ctx->stream))) return rc;
+    if ((rc = launch(G.ck.iter, dim3(cbpi), G.col_block, G.col_lds, ca, ctx->stream))) return rc;
   HIPCHK(hipEventRecord(e[1], ctx->stream));
   for (int r = 0; r < reps; ++r)
-    if ((rc = launch(I.rk.iter, I.row_grid, I.row_block, I.row_lds, args, ctx->stream))) return rc;
+    if ((rc = launch(G.rk.iter, dim3(rbpi), G.row_block, G.row_lds, ra, ctx->stream))) return rc;
   HIPCHK(hipEventRecord(e[2], ctx->stream));
   HIPCHK(hipEventSynchronize(e[2]));
   float t0 = 0.f, t1 = 0.f;
@@ -746,21 +863,23 @@ int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[2]) {
   out[0] = 1e3 * t0 / reps;
   out[1] = 1e3 * t1 / reps;
   // park the instance so later chunk launches leave it alone
-  int32_t park = I.d.max_iter + 1;
-  HIPCHK(hipMemcpyAsync(I.h.iter_base, &park, sizeof(park), hipMemcpyHostToDevice, ctx->stream));
+  int32_t* park = (int32_t*)ctx->h_recs;  // pinned scratch, free until the next poll
+  *park = I.d.max_iter + 1;
+  HIPCHK(hipMemcpyAsync(I.h.iter_base, park, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return PFCH_OK;
 }
 
 int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]) {
   if (!ctx || !out || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
-  const Instance& I = ctx->inst[inst];
-  out[0] = I.row_grid.x;
-  out[1] = I.row_block.x;
-  out[2] = (int64_t)I.row_lds;
-  out[3] = I.col_grid.x;
-  out[4] = I.col_block.x;
-  out[5] = (int64_t)I.col_lds;
+  const Group& G = ctx->groups[ctx->inst[inst].group];
+  const int64_t nm = (int64_t)G.members.size();
+  out[0] = nm * G.row_bpi;
+  out[1] = G.row_block.x;
+  out[2] = (int64_t)G.row_lds;
+  out[3] = nm * G.col_bpi;
+  out[4] = G.col_block.x;
+  out[5] = (int64_t)G.col_lds;
   return PFCH_OK;
 }
 
@@ -803,12 +922,18 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
   std::vector<int> active(n);
   std::vector<double> as(n);
   int rc;
-  for (int i = 0; i < n; ++i) {
-    Instance& I = ctx->inst[i];
-    active[i] = i;
-    const StepSetup ss = step_setup_for(I, dt[i]);
-    as[i] = ss.a;
-    if ((rc = launch_setup(ctx, I, ss))) return rc;
+  for (int i = 0; i < n; ++i) active[i] = i;
+  for (auto& G : ctx->groups) {
+    for (size_t k = 0; k < G.members.size(); ++k) {
+      const Instance& I = ctx->inst[G.members[k]];
+      const StepSetup ss = step_setup_for(I, dt[G.members[k]]);
+      as[G.members[k]] = ss.a;
+      G.h_args[k] = to_args(ss);
+    }
+    const unsigned nm = (unsigned)G.members.size();
+    HIPCHK(hipMemcpyAsync(G.d_args, G.h_args, sizeof(StepArgs) * nm, hipMemcpyHostToDevice,
+                          ctx->stream));
+    if ((rc = launch_setup(ctx, G, G.d_members, G.d_args, nm))) return rc;
   }
   if ((rc = run_iterations(ctx, active))) return rc;
   int first_err = PFCH_OK;
@@ -818,27 +943,34 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
   for (int i = 0; i < n; ++i) {
     Instance& I = ctx->inst[i];
     status[i] = status_of(I, ctx->h_recs[i], &iters[i], &dn[i]);
+    ctx->h_dsts[i] = nullptr;
     if (status[i] != PFCH_OK) {
       if (first_err == PFCH_OK) first_err = status[i];
       continue;
     }
-    const int slot = (ctx->h_recs[i].stop_iter + 1) % 3;
-    double* dst = I.U[1 - I.ucur];
-    int64_t np = I.npts;
-    double* part = want_mass ? I.mass_part : nullptr;
-    const double* src = I.h.X[slot];
-    void* args[] = {&src, &dst, &np, &part};
-    if ((rc = launch((const void*)&k_copy_sum, dim3(ACC_BLOCKS), dim3(ACC_THREADS), 0, args, ctx->stream)))
+    ctx->h_dsts[i] = I.U[1 - I.ucur];
+  }
+  HIPCHK(hipMemcpyAsync(ctx->d_dsts, ctx->h_dsts, sizeof(double*) * n, hipMemcpyHostToDevice, ctx->stream));
+  {
+    InstDev** ptrs = ctx->d_ptrs;
+    double** dsts = ctx->d_dsts;
+    double* part = want_mass ? ctx->d_part : nullptr;
+    void* a[] = {&ptrs, &dsts, &part};
+    if ((rc = launch((const void*)&k_accept, dim3(ACC_BLOCKS, n), dim3(ACC_THREADS), 0, a, ctx->stream)))
       return rc;
-    if (want_mass) {
-      int nb = ACC_BLOCKS;
-      double scale = 1.0 / (double)I.npts;
-      double* o = I.mass_out;
-      void* a2[] = {&I.mass_part, &nb, &scale, &o};
-      if ((rc = launch((const void*)&k_sum_parts, dim3(1), dim3(1), 0, a2, ctx->stream))) return rc;
-      HIPCHK(hipMemcpyAsync(&ctx->h_mass[i], I.mass_out, sizeof(double), hipMemcpyDeviceToHost,
-                            ctx->stream));
-    }
+  }
+  if (want_mass) {
+    const double* part = ctx->d_part;
+    int nb = ACC_BLOCKS, nn = n;
+    const double* scale = ctx->d_scale;
+    double* o = ctx->d_mass;
+    void* a[] = {&part, &nb, &nn, &scale, &o};
+    if ((rc = launch((const void*)&k_sum_parts, dim3((n + 63) / 64), dim3(64), 0, a, ctx->stream))) return rc;
+    HIPCHK(hipMemcpyAsync(ctx->h_mass, ctx->d_mass, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+  }
+  for (int i = 0; i < n; ++i) {
+    if (status[i] != PFCH_OK) continue;
+    Instance& I = ctx->inst[i];
     I.ucur = 1 - I.ucur;
     I.has_prev = true;
     I.dt_prev = dt[i];
@@ -883,7 +1015,7 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
   ss.theta = I.d.scheme == PFCH_MP ? 0.5 : 1.0;
   ss.rho = 0.0;
   int rc;
-  if ((rc = launch_setup(ctx, I, ss))) return rc;
+  if ((rc = launch_setup_solo(ctx, I, ss))) return rc;
   std::vector<int> active{inst};
   if ((rc = run_iterations(ctx, active))) return rc;
   int iters = 0;
