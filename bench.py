@@ -80,12 +80,15 @@ def measured_traffic(w, kernel):
 
 
 def kernel_source_hash():
+    """Hash of the sources that define the iteration kernels (transform
+    passes, fused k-space and real-space bodies, plan table) and their
+    compile flags: counter totals are reused only while this is unchanged."""
     import hashlib
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2204_07247_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode() + b"\0" + fh.read())
+    pkg = os.path.join(ROOT, "paper_2204_07247_amd")
+    for rel in ("csrc/fft.hpp", "csrc/kernels2d.hpp", "csrc/pfch_dev.hpp", "csrc/plans.hpp", "build.py"):
+        with open(os.path.join(pkg, rel), "rb") as fh:
+            h.update(rel.encode() + b"\0" + fh.read())
     return h.hexdigest()
 
 

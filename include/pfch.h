@@ -55,8 +55,9 @@ enum { PFCH_BDF2 = 0, PFCH_MP = 1 };  /* fully implicit scheme */
  * ||d_i||_inf < tol, at most max_iter iterations.  theta_l weights the
  * beta_0/beta_2/beta_4 part of the averaged-Newton preconditioner
  * (Sec. 3.4.1); 1.0 is the operator as printed.
- * guess: 0 = extrapolated initial guess (the only value accepted so far).
- * reserved must be 0.
+ * guess: 0 = extrapolated initial guess u^n + rho (u^n - u^{n-1}) (Alg. 2
+ * input x_0, extrapolation as in Sec. 3.1); 1 = learned guess when a network
+ * is attached with pfch_set_fno (otherwise extrapolated).  reserved must be 0.
  */
 typedef struct pfch_instance_desc {
   double len[3]; /* periods per axis, x first */
@@ -76,7 +77,9 @@ typedef struct pfch_stats {
   int32_t iters;    /* PAGD iterations */
   int32_t fft_pairs;/* 2D transform pairs of real fields used (setup + iterations) */
   int32_t status;   /* PFCH_OK or the error of this instance */
-  int32_t reserved;
+  int32_t guess;    /* initial guess used: 0 extrapolated, 1 learned,
+                       2 learned guess failed, step solved again from the
+                       extrapolated guess */
 } pfch_stats;
 
 typedef struct pfch_ctx pfch_ctx; /* opaque; owned by the library */
@@ -140,6 +143,76 @@ int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[2]);
 /* Launch geometry of instance `inst` for reporting: {row grid, row block,
  * row LDS bytes, column grid, column block, column LDS bytes}. */
 int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]);
+
+/*
+ * Learned initial guess: a Fourier neural operator (FNO) in float32.
+ *
+ * The network maps (u^n, u^{n-1}) to a correction of the extrapolated guess:
+ *   input  x[0] = (u^n - mu)/su,  x[1] = (u^n - u^{n-1})/sd
+ *   guess  x_0 = u^n + rho (u^n - u^{n-1}) + so * Pi_0 y
+ * where Pi_0 removes the mean (the PAGD solve keeps the mean of its initial
+ * guess, so the mass stays that of the extrapolation) and norm = {mu, su, sd,
+ * so}.  PAGD still iterates to ||d||_inf < tol from this guess, so the
+ * solution differs from the extrapolated-guess solution only within that
+ * tolerance; a guess from which the solve fails is replaced by the
+ * extrapolated one.
+ *
+ * Network: lift 2 -> W channels, L spectral layers
+ *   z = K v + W_l^T v + b_l,  v <- gelu(z) (no gelu after the last layer),
+ * K keeping kx in [0, M) and ky in {0..M-1} U {Ny-M..Ny-1} of the 2D real
+ * transform with complex per-mode channel mixing, then projection W -> 1.
+ * Flat float32 parameter vector, in order: P[2][W], pb[W], per layer
+ * R[W][W][2M][M][re, im] (row kyi >= M holds ky = Ny - 2M + kyi), Wl[W][W],
+ * bl[W]; then Q[W], qb.  All fields are [B][C][Ny][Nx] float32, x fastest.
+ * One network object is used by one stream at a time (its activations live
+ * in the object).
+ */
+typedef struct pfch_fno pfch_fno; /* opaque; owned by the library */
+
+/* Number of parameters, or PFCH_E_INVAL for invalid sizes. */
+int64_t pfch_fno_num_params(int32_t width, int32_t modes, int32_t layers);
+
+/* Create a network of width W <= 64, M modes (2M <= Ny, M <= Nx/2), L
+ * layers, for Ny x Nx fields and batches of at most max_batch samples.
+ * Parameters start at zero (see pfch_fno_init_params). */
+int pfch_fno_create(int32_t width, int32_t modes, int32_t layers, int32_t ny, int32_t nx,
+                    int32_t max_batch, void* hip_stream, pfch_fno** out);
+
+/* Deterministic pseudo-random initial parameters (scaled uniform). */
+int pfch_fno_init_params(pfch_fno* f, uint64_t seed);
+
+/* Copy the n parameters from / to a device float32 array. */
+int pfch_fno_set_params(pfch_fno* f, const float* theta, int64_t n);
+int pfch_fno_get_params(pfch_fno* f, float* theta, int64_t n);
+
+/* y[batch][Ny][Nx] = network(x[batch][2][Ny][Nx]); device arrays. */
+int pfch_fno_forward(pfch_fno* f, const float* x, float* y, int32_t batch);
+
+/* Mean squared error of the network on (x, t[batch][Ny][Nx]) and its
+ * gradient with respect to the parameters, kept for pfch_fno_adam_step and
+ * copied to `grad` (device, n floats) when it is not NULL.  `loss` (host) is
+ * written when not NULL, which synchronises the stream. */
+int pfch_fno_grad(pfch_fno* f, const float* x, const float* t, int32_t batch, float* grad,
+                  double* loss);
+
+/* One Adam update with the last gradient; `step` counts from 1 (moments are
+ * cleared at step 1). */
+int pfch_fno_adam_step(pfch_fno* f, float lr, float beta1, float beta2, float eps, int32_t step);
+
+/* Network input x[2][Ny][Nx] (and, when u_np1 and t are not NULL, the
+ * training target t = (u^{n+1} - u^n - rho (u^n - u^{n-1}))/so) of one
+ * sample from float64 device fields. */
+int pfch_fno_prepare(pfch_fno* f, const double* u_nm1, const double* u_n, const double* u_np1,
+                     double rho, const double norm[4], float* x, float* t);
+
+void pfch_fno_destroy(pfch_fno* f);
+
+/* Attach network `f` (NULL detaches) to instance `inst`: its steps then use
+ * the learned guess when the instance's desc.guess is 1 and it has a
+ * history.  The network's grid must equal the instance's.  norm = {mu, su,
+ * sd, so}, su, sd, so > 0.  The network is not owned; it must outlive its
+ * use and must not be used on another stream while the context steps. */
+int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4]);
 
 void pfch_destroy(pfch_ctx* ctx);
 const char* pfch_strerror(int code);

@@ -1,0 +1,529 @@
+// FP32 Fourier neural operator for the learned warm start of the PAGD solve:
+// forward, backward (mean squared error) and Adam, written as HIP kernels.
+//
+// Network (width W, retained modes M per axis, L spectral layers) on fields
+// [B][C][Ny][Nx]:
+//   v0 = P^T x + pb                          (lift, 2 -> W channels)
+//   z_l = K_l v_l + W_l^T v_l + b_l,  v_{l+1} = gelu(z_l)  (last layer: no gelu)
+//   y = Q^T v_L + qb                         (projection, W -> 1)
+// K_l keeps kx in [0, M) and ky in {0..M-1} U {Ny-M..Ny-1} of the real 2D
+// transform and mixes channels per mode with complex weights R_l[i][o][mode].
+// The truncated transforms are dense products with DFT matrices (M << N), so
+// every step of the layer and of its adjoint is one strided batched complex
+// GEMM (k_gemm).
+//
+// Flat parameter layout (shared with the float64 reference of the tests):
+// P[2][W], pb[W], per layer R[W][W][2M][M][re,im], Wl[W][W], bl[W]; Q[W], qb.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+namespace pfch {
+
+struct GemmP {
+  int M, N, K;
+  const float* A;
+  long long sAz, sAm, sAk;  // strides in elements (a complex element is two floats)
+  const float* B;
+  long long sBz, sBk, sBn;
+  float* C;
+  long long sCz, sCm, sCn;
+  int accumulate;  // 1: C += A B
+};
+
+struct f2 {
+  float x, y;
+};
+
+// Complex multiply-accumulate with operands known real at compile time.
+template <bool AC, bool BC>
+__device__ __forceinline__ void cmac(f2& c, const f2 a, const f2 b) {
+  c.x += a.x * b.x;
+  if (AC && BC) c.x -= a.y * b.y;
+  if (BC) c.y += a.x * b.y;
+  if (AC) c.y += a.y * b.x;
+}
+
+// C[z] (+)= A[z] B[z] for z = blockIdx.z.  AC / BC: operand is complex (else
+// real); CJA / CJB: conjugate it; CC: C is complex (else the real part is
+// stored).  16 x 16 threads, BM x BN output tile (thread (tx, ty) owns rows
+// ty + 16 i and columns tx + 16 j), K staged through LDS in steps of 16.
+template <bool AC, bool BC, bool CJA, bool CJB, bool CC, int BM, int BN>
+__global__ __launch_bounds__(256) void k_gemm(GemmP p) {
+  constexpr int RM = BM / 16, RN = BN / 16;
+  __shared__ f2 As[BM][17];
+  __shared__ f2 Bs[16][BN + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const long long m0 = (long long)blockIdx.y * BM, n0 = (long long)blockIdx.x * BN;
+  const long long z = blockIdx.z;
+  const float* A = p.A + (AC ? 2 : 1) * z * p.sAz;
+  const float* B = p.B + (BC ? 2 : 1) * z * p.sBz;
+  float* C = p.C + (CC ? 2 : 1) * z * p.sCz;
+  f2 acc[RM][RN];
+#pragma unroll
+  for (int i = 0; i < RM; ++i)
+#pragma unroll
+    for (int j = 0; j < RN; ++j) acc[i][j] = f2{0.f, 0.f};
+  for (int k0 = 0; k0 < p.K; k0 += 16) {
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+      const int e = threadIdx.x + 256 * r;
+      const int mm = e >> 4, kk = e & 15;
+      const long long m = m0 + mm;
+      const int k = k0 + kk;
+      f2 a = {0.f, 0.f};
+      if (m < p.M && k < p.K) {
+        const long long o = m * p.sAm + k * p.sAk;
+        if (AC) {
+          a.x = A[2 * o];
+          a.y = CJA ? -A[2 * o + 1] : A[2 * o + 1];
+        } else {
+          a.x = A[o];
+        }
+      }
+      As[mm][kk] = a;
+    }
+#pragma unroll
+    for (int r = 0; r < RN; ++r) {
+      const int e = threadIdx.x + 256 * r;
+      const int kk = e / BN, nn = e % BN;
+      const int k = k0 + kk;
+      const long long n = n0 + nn;
+      f2 b = {0.f, 0.f};
+      if (k < p.K && n < p.N) {
+        const long long o = k * p.sBk + n * p.sBn;
+        if (BC) {
+          b.x = B[2 * o];
+          b.y = CJB ? -B[2 * o + 1] : B[2 * o + 1];
+        } else {
+          b.x = B[o];
+        }
+      }
+      Bs[kk][nn] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      f2 bv[RN];
+#pragma unroll
+      for (int j = 0; j < RN; ++j) bv[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < RM; ++i) {
+        const f2 a = As[ty + 16 * i][kk];
+#pragma unroll
+        for (int j = 0; j < RN; ++j) cmac<AC, BC>(acc[i][j], a, bv[j]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < RM; ++i) {
+    const long long m = m0 + ty + 16 * i;
+    if (m >= p.M) continue;
+#pragma unroll
+    for (int j = 0; j < RN; ++j) {
+      const long long n = n0 + tx + 16 * j;
+      if (n >= p.N) continue;
+      const long long o = m * p.sCm + n * p.sCn;
+      if (CC) {
+        if (p.accumulate) {
+          C[2 * o] += acc[i][j].x;
+          C[2 * o + 1] += acc[i][j].y;
+        } else {
+          C[2 * o] = acc[i][j].x;
+          C[2 * o + 1] = acc[i][j].y;
+        }
+      } else {
+        if (p.accumulate)
+          C[o] += acc[i][j].x;
+        else
+          C[o] = acc[i][j].x;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// z[b][c][p] += bias[c]; v = gelu(z) (or z).  One thread per element.
+__global__ void k_bias_act(float* __restrict__ z, float* __restrict__ v, const float* __restrict__ bias,
+                           int C, long long P, long long n, int gelu) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)((i / P) % C);
+  const float zz = z[i] + bias[c];
+  z[i] = zz;
+  if (v) v[i] = gelu ? gelu_f(zz) : zz;
+}
+
+__global__ void k_gelu_bwd(const float* __restrict__ dv, const float* __restrict__ z, float* __restrict__ dz,
+                           long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dz[i] = dv[i] * gelu_grad_f(z[i]);
+}
+
+// dy = 2 (y - t) / n; part[block] = sum of (y - t)^2 over the block.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const float* __restrict__ t,
+                                             float* __restrict__ dy, long long n, float* __restrict__ part) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float d = y[i] - t[i];
+    dy[i] = 2.0f * d / (float)n;
+    s += d * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// dv[b][i][p] = Q[i] dy[b][p]
+__global__ void k_outer(const float* __restrict__ Q, const float* __restrict__ dy, float* __restrict__ dv,
+                        int W, long long P, long long n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const long long p = e % P;
+  const int i = (int)((e / P) % W);
+  const long long b = e / (P * W);
+  dv[e] = Q[i] * dy[b * P + p];
+}
+
+__global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long long n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// Weight and bias gradients of a 1x1 convolution out = sum_i Wt[i][j] X[i] + b[j]
+// with upstream gradient Y: part[blk][i][j] = sum over the block's points of
+// X[b][i][p] Y[b][j][p] for i < CX, and row CX = sum of Y[b][j][p] (bias).
+// Points are the flat (b, p) index space in tiles of 64; block blk takes tiles
+// blk, blk + gridDim.x, ... (fixed assignment, so the result is reproducible).
+constexpr int WG_TILE = 64, WG_MAXC = 64, WG_MAXACC = 17;
+__global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ X, int CX, const float* __restrict__ Y,
+                                               int CY, long long P, long long total, float* __restrict__ part) {
+  __shared__ float Xs[WG_MAXC][WG_TILE + 1];
+  __shared__ float Ys[WG_MAXC][WG_TILE + 1];
+  const int nout = (CX + 1) * CY;
+  float acc[WG_MAXACC];
+#pragma unroll
+  for (int k = 0; k < WG_MAXACC; ++k) acc[k] = 0.f;
+  const long long ntiles = (total + WG_TILE - 1) / WG_TILE;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long f0 = tile * WG_TILE;
+    for (int e = threadIdx.x; e < CX * WG_TILE; e += blockDim.x) {
+      const int i = e / WG_TILE, t = e % WG_TILE;
+      const long long f = f0 + t;
+      float v = 0.f;
+      if (f < total) {
+        const long long b = f / P, p = f % P;
+        v = X[(b * CX + i) * P + p];
+      }
+      Xs[i][t] = v;
+    }
+    for (int e = threadIdx.x; e < CY * WG_TILE; e += blockDim.x) {
+      const int j = e / WG_TILE, t = e % WG_TILE;
+      const long long f = f0 + t;
+      float v = 0.f;
+      if (f < total) {
+        const long long b = f / P, p = f % P;
+        v = Y[(b * CY + j) * P + p];
+      }
+      Ys[j][t] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < WG_MAXACC; ++k) {
+      const int o = threadIdx.x + 256 * k;
+      if (o < nout) {
+        const int i = o / CY, j = o % CY;
+        float s = 0.f;
+        if (i < CX) {
+          for (int t = 0; t < WG_TILE; ++t) s += Xs[i][t] * Ys[j][t];
+        } else {
+          for (int t = 0; t < WG_TILE; ++t) s += Ys[j][t];
+        }
+        acc[k] += s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < WG_MAXACC; ++k) {
+    const int o = threadIdx.x + 256 * k;
+    if (o < nout) part[(long long)blockIdx.x * nout + o] = acc[k];
+  }
+}
+
+// Sum the per-block partials of k_wgrad in block order: out_w[i][j] for
+// i < CX, out_b[j] for the bias row.
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int nblk, int CX, int CY, float* __restrict__ out_w,
+                               float* __restrict__ out_b) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nout = (CX + 1) * CY;
+  if (o >= nout) return;
+  float s = 0.f;
+  for (int k = 0; k < nblk; ++k) s += part[(long long)k * nout + o];
+  const int i = o / CY, j = o % CY;
+  if (i < CX)
+    out_w[o] = s;
+  else
+    out_b[j] = s;
+}
+
+// y[b][p] = sum_i Q[i] v[b][i][p] + qb
+__global__ void k_project(const float* __restrict__ v, const float* __restrict__ Q, const float* __restrict__ qb,
+                          float* __restrict__ y, int W, long long P, long long n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const long long b = e / P, p = e % P;
+  float s = qb[0];
+  for (int i = 0; i < W; ++i) s += Q[i] * v[(b * W + i) * P + p];
+  y[e] = s;
+}
+
+// out = sum of part[0..n) in order (one thread); float partials, double sum.
+__global__ void k_sum_parts_f(const float* __restrict__ part, int n, double scale, double* __restrict__ out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s += (double)part[k];
+  *out = s * scale;
+}
+
+// Per-block float64 partial sums of a float field (fixed grid).
+__global__ __launch_bounds__(256) void k_partial_sum(const float* __restrict__ y, long long n,
+                                                     double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    s += (double)y[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Learned initial guess: x0 = u^n + rho (u^n - u^{n-1}) + so (y - mean(y)).
+// The correction is projected to zero mean so that x0 keeps the mass of the
+// extrapolation (the solve preserves the mean of its initial guess).
+__global__ void k_learned_guess(const double* __restrict__ un, const double* __restrict__ unm1, double rho,
+                                double so, const float* __restrict__ y, const double* __restrict__ part,
+                                int nparts, long long n, double* __restrict__ x0) {
+  __shared__ double mean;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k) s += part[k];
+    mean = s / (double)n;
+  }
+  __syncthreads();
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const double u = un[p];
+  x0[p] = u + rho * (u - unm1[p]) + so * ((double)y[p] - mean);
+}
+
+// Network inputs and (optional) targets from float64 fields:
+// x[0] = (u^n - mu)/su, x[1] = (u^n - u^{n-1})/sd,
+// t = (u^{n+1} - (u^n + rho (u^n - u^{n-1})))/so.
+__global__ void k_fno_inputs(const double* __restrict__ unm1, const double* __restrict__ un,
+                             const double* __restrict__ unp1, long long P, double rho, double mu, double su,
+                             double sd, double so, float* __restrict__ x, float* __restrict__ t) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const double a = un[p], b = unm1[p];
+  x[p] = (float)((a - mu) / su);
+  x[P + p] = (float)((a - b) / sd);
+  if (t) t[p] = (float)((unp1[p] - (a + rho * (a - b))) / so);
+}
+
+struct Fno {
+  int W = 0, M = 0, L = 0, ny = 0, nx = 0, maxb = 0;
+  long long P = 0, n = 0, MM2 = 0;
+  hipStream_t s = nullptr;
+  float *theta = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
+  float *Fx = nullptr, *Fy = nullptr, *Gy = nullptr, *Gx = nullptr;  // complex DFT matrices
+  std::vector<float*> v, z, vh;  // v[0..L], z[0..L-1], vh[0..L-1]
+  float *S1 = nullptr, *Yb = nullptr, *Yb2 = nullptr;
+  float *xin = nullptr, *y = nullptr, *dy = nullptr, *dvA = nullptr, *dvB = nullptr;
+  float *wpart = nullptr, *lpart = nullptr;
+  double *loss = nullptr, *h_loss = nullptr, *ypart = nullptr;
+  int wg_blocks = 0;
+  std::vector<void*> allocs;
+  std::vector<void*> host_allocs;
+  long long oP = 0, opb = 0, oQ = 0, oqb = 0;
+  std::vector<long long> oR, oW, ob;
+};
+
+inline long long fno_count(long long W, long long M, long long L) {
+  return 2 * W + W + L * (W * W * 2 * M * M * 2 + W * W + W) + W + 1;
+}
+
+constexpr int FNO_LOSS_BLOCKS = 256, FNO_SUM_BLOCKS = 256;
+
+template <bool AC, bool BC, bool CJA, bool CJB, bool CC, int BM, int BN>
+inline hipError_t gemm_launch(const GemmP& p, long long Z, hipStream_t s) {
+  const long long gy = (p.M + BM - 1) / BM, gx = (p.N + BN - 1) / BN;
+  if (gy > 65535 || Z > 65535 || gx > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_gemm<AC, BC, CJA, CJB, CC, BM, BN>), dim3((unsigned)gx, (unsigned)gy, (unsigned)Z),
+                     dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+inline GemmP gp_make(long long M, long long N, long long K, const float* A, long long sAz, long long sAm,
+                     long long sAk, const float* B, long long sBz, long long sBk, long long sBn, float* C,
+                     long long sCz, long long sCm, long long sCn, int acc) {
+  GemmP p;
+  p.M = (int)M;
+  p.N = (int)N;
+  p.K = (int)K;
+  p.A = A;
+  p.sAz = sAz;
+  p.sAm = sAm;
+  p.sAk = sAk;
+  p.B = B;
+  p.sBz = sBz;
+  p.sBk = sBk;
+  p.sBn = sBn;
+  p.C = C;
+  p.sCz = sCz;
+  p.sCm = sCm;
+  p.sCn = sCn;
+  p.accumulate = acc;
+  return p;
+}
+
+#define FNO_CHK(x)                   \
+  do {                               \
+    hipError_t e_ = (x);             \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
+inline unsigned blocks_for(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+// Forward pass for `B` samples x[B][2][ny][nx]; keeps every layer's input,
+// pre-activation and retained spectrum for the backward pass; y[B][ny][nx].
+inline hipError_t fno_forward(Fno& F, const float* x, int B, hipStream_t s) {
+  const long long W = F.W, M = F.M, P = F.P, ny = F.ny, nx = F.nx, MM2 = F.MM2;
+  const float* th = F.theta;
+  // lift
+  FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(
+      gp_make(W, P, 2, th + F.oP, 0, 1, W, x, 2 * P, P, 1, F.v[0], W * P, P, 1, 0), B, s)));
+  hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * W * P)), dim3(256), 0, s, F.v[0], (float*)nullptr,
+                     th + F.opb, (int)W, P, B * W * P, 0);
+  for (int l = 0; l < F.L; ++l) {
+    const float* vin = F.v[l];
+    // A1 = v Fx over x
+    FNO_CHK((gemm_launch<false, true, false, false, true, 64, 16>(
+        gp_make(B * W * ny, M, nx, vin, 0, nx, 1, F.Fx, 0, M, 1, F.S1, 0, M, 1, 0), 1, s)));
+    // vh = Fy A1 over y (retained ky rows)
+    FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
+        gp_make(2 * M, M, ny, F.Fy, 0, ny, 1, F.S1, ny * M, M, 1, F.vh[l], MM2, M, 1, 0), B * W, s)));
+    // per-mode channel mixing Y[b][o] = sum_i vh[b][i] R[i][o]
+    FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
+        gp_make(B, W, W, F.vh[l], 1, W * MM2, MM2, th + F.oR[l], 1, W * MM2, MM2, F.Yb, 1, W * MM2, MM2, 0),
+        MM2, s)));
+    // B1 = Gy Y over y
+    FNO_CHK((gemm_launch<true, true, false, false, true, 64, 16>(
+        gp_make(ny, M, 2 * M, F.Gy, 0, 2 * M, 1, F.Yb, MM2, M, 1, F.S1, ny * M, M, 1, 0), B * W, s)));
+    // z = Re(B1 Gx) over x
+    FNO_CHK((gemm_launch<true, true, false, false, false, 32, 64>(
+        gp_make(B * W * ny, nx, M, F.S1, 0, M, 1, F.Gx, 0, nx, 1, F.z[l], 0, nx, 1, 0), 1, s)));
+    // z += W_l^T v
+    FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(
+        gp_make(W, P, W, th + F.oW[l], 0, 1, W, vin, W * P, P, 1, F.z[l], W * P, P, 1, 1), B, s)));
+    hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * W * P)), dim3(256), 0, s, F.z[l], F.v[l + 1],
+                       th + F.ob[l], (int)W, P, B * W * P, l < F.L - 1 ? 1 : 0);
+  }
+  hipLaunchKernelGGL(k_project, dim3(blocks_for(B * P)), dim3(256), 0, s, (const float*)F.v[F.L], th + F.oQ,
+                     th + F.oqb, F.y, (int)W, P, B * P);
+  return hipGetLastError();
+}
+
+inline hipError_t wgrad(Fno& F, const float* X, int CX, const float* Y, int CY, long long total, float* out_w,
+                        float* out_b, hipStream_t s) {
+  hipLaunchKernelGGL(k_wgrad, dim3(F.wg_blocks), dim3(256), 0, s, X, CX, Y, CY, F.P, total, F.wpart);
+  const int nout = (CX + 1) * CY;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(nout)), dim3(256), 0, s, (const float*)F.wpart,
+                     F.wg_blocks, CX, CY, out_w, out_b);
+  return hipGetLastError();
+}
+
+// Forward, mean squared error against t[B][ny][nx] and the gradient of the
+// loss with respect to every parameter (into F.grad).  F.loss receives the
+// loss (device float64).
+inline hipError_t fno_backward(Fno& F, const float* x, const float* t, int B, hipStream_t s) {
+  FNO_CHK(fno_forward(F, x, B, s));
+  const long long W = F.W, M = F.M, P = F.P, ny = F.ny, nx = F.nx, MM2 = F.MM2;
+  const long long nB = (long long)B * P;
+  const float* th = F.theta;
+  float* g = F.grad;
+  hipLaunchKernelGGL(k_mse, dim3(FNO_LOSS_BLOCKS), dim3(256), 0, s, (const float*)F.y, t, F.dy, nB, F.lpart);
+  hipLaunchKernelGGL(k_sum_parts_f, dim3(1), dim3(1), 0, s, (const float*)F.lpart, FNO_LOSS_BLOCKS,
+                     1.0 / (double)nB, F.loss);
+  FNO_CHK(wgrad(F, F.v[F.L], (int)W, F.dy, 1, nB, g + F.oQ, g + F.oqb, s));
+  float* dv = F.dvA;
+  float* dvin = F.dvB;
+  hipLaunchKernelGGL(k_outer, dim3(blocks_for(B * W * P)), dim3(256), 0, s, th + F.oQ, (const float*)F.dy, dv,
+                     (int)W, P, B * W * P);
+  for (int l = F.L - 1; l >= 0; --l) {
+    if (l < F.L - 1)
+      hipLaunchKernelGGL(k_gelu_bwd, dim3(blocks_for(B * W * P)), dim3(256), 0, s, (const float*)dv,
+                         (const float*)F.z[l], dv, B * W * P);
+    const float* dz = dv;
+    const float* vin = F.v[l];
+    FNO_CHK(wgrad(F, vin, (int)W, dz, (int)W, nB, g + F.oW[l], g + F.ob[l], s));
+    // dvin = W_l dz
+    FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(
+        gp_make(W, P, W, th + F.oW[l], 0, W, 1, dz, W * P, P, 1, dvin, W * P, P, 1, 0), B, s)));
+    // D_B1 = dz Gx^T
+    FNO_CHK((gemm_launch<false, true, false, false, true, 64, 16>(
+        gp_make(B * W * ny, M, nx, dz, 0, nx, 1, F.Gx, 0, 1, nx, F.S1, 0, M, 1, 0), 1, s)));
+    // D_Y = Gy^T D_B1
+    FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
+        gp_make(2 * M, M, ny, F.Gy, 0, 1, 2 * M, F.S1, ny * M, M, 1, F.Yb, MM2, M, 1, 0), B * W, s)));
+    // grad R = conj(sum_b vh[b][i] D_Y[b][o]) per mode, stored (re, im)
+    FNO_CHK((gemm_launch<true, true, true, true, true, 32, 32>(
+        gp_make(W, W, B, F.vh[l], 1, MM2, W * MM2, F.Yb, 1, W * MM2, MM2, g + F.oR[l], 1, W * MM2, MM2, 0),
+        MM2, s)));
+    // D_vh[b][i] = sum_o D_Y[b][o] R[i][o]
+    FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
+        gp_make(B, W, W, F.Yb, 1, W * MM2, MM2, th + F.oR[l], 1, MM2, W * MM2, F.Yb2, 1, W * MM2, MM2, 0),
+        MM2, s)));
+    // D_A1 = Fy^T D_vh
+    FNO_CHK((gemm_launch<true, true, false, false, true, 64, 16>(
+        gp_make(ny, M, 2 * M, F.Fy, 0, 1, ny, F.Yb2, MM2, M, 1, F.S1, ny * M, M, 1, 0), B * W, s)));
+    // dvin += Re(D_A1 Fx^T)
+    FNO_CHK((gemm_launch<true, true, false, false, false, 32, 64>(
+        gp_make(B * W * ny, nx, M, F.S1, 0, M, 1, F.Fx, 0, 1, M, dvin, 0, nx, 1, 1), 1, s)));
+    float* tmp = dv;
+    dv = dvin;
+    dvin = tmp;
+  }
+  FNO_CHK(wgrad(F, x, 2, dv, (int)W, nB, g + F.oP, g + F.opb, s));
+  return hipGetLastError();
+}
+
+}  // namespace pfch

@@ -17,90 +17,12 @@
 
 #include "../../include/pfch.h"
 #include "kernels2d.hpp"
+#include "plans.hpp"
+#include "fno.hpp"
 
 using namespace pfch;
 
 namespace {
-
-// ---------------------------------------------------------------------------
-// Kernel dispatch per transform length.
-// ---------------------------------------------------------------------------
-struct RowK {
-  const void* iter = nullptr;
-  const void* setup = nullptr;
-  const void* start_fch = nullptr;
-  int T = 0;
-  int lds_elems = 0;  // per team
-};
-struct ColK {
-  const void* iter = nullptr;
-  const void* setup = nullptr;
-  int T = 0;
-  int lds_elems = 0;  // per column
-};
-
-template <class P, int MODEL>
-RowK make_row() {
-  RowK k;
-  k.iter = (const void*)&k_row_iter<P, MODEL>;
-  k.setup = (const void*)&k_row_setup<P, MODEL>;
-  if (MODEL == MODEL_FCH) k.start_fch = (const void*)&k_row_start_fch<P>;
-  k.T = P::T;
-  k.lds_elems = lds_len(P::N);
-  return k;
-}
-template <class P, int MODEL>
-ColK make_col() {
-  ColK k;
-  k.iter = (const void*)&k_col_iter<P, MODEL>;
-  k.setup = (const void*)&k_col_setup<P, MODEL>;
-  k.T = P::T;
-  k.lds_elems = lds_len(P::N);
-  return k;
-}
-
-using P8 = Plan<8, 8>;
-using P16 = Plan<16, 8, 2>;
-using P32 = Plan<32, 8, 4>;
-using P64 = Plan<64, 8, 8>;
-using P128 = Plan<128, 8, 8, 2>;
-using P256 = Plan<256, 8, 8, 4>;
-using P512 = Plan<512, 8, 8, 8>;
-using P1024 = Plan<1024, 8, 8, 4, 4>;
-using P2048 = Plan<2048, 8, 8, 8, 4>;
-
-template <int MODEL>
-bool row_kernels(int n, RowK& k) {
-  switch (n) {
-    case 8: k = make_row<P8, MODEL>(); return true;
-    case 16: k = make_row<P16, MODEL>(); return true;
-    case 32: k = make_row<P32, MODEL>(); return true;
-    case 64: k = make_row<P64, MODEL>(); return true;
-    case 128: k = make_row<P128, MODEL>(); return true;
-    case 256: k = make_row<P256, MODEL>(); return true;
-    case 512: k = make_row<P512, MODEL>(); return true;
-    case 1024: k = make_row<P1024, MODEL>(); return true;
-    case 2048: k = make_row<P2048, MODEL>(); return true;
-    default: return false;
-  }
-}
-template <int MODEL>
-bool col_kernels(int n, ColK& k) {
-  switch (n) {
-    case 8: k = make_col<P8, MODEL>(); return true;
-    case 16: k = make_col<P16, MODEL>(); return true;
-    case 32: k = make_col<P32, MODEL>(); return true;
-    case 64: k = make_col<P64, MODEL>(); return true;
-    case 128: k = make_col<P128, MODEL>(); return true;
-    case 256: k = make_col<P256, MODEL>(); return true;
-    case 512: k = make_col<P512, MODEL>(); return true;
-    case 1024: k = make_col<P1024, MODEL>(); return true;
-    case 2048: k = make_col<P2048, MODEL>(); return true;
-    default: return false;
-  }
-}
-
-bool supported_len(int n) { return n >= 8 && n <= 2048 && (n & (n - 1)) == 0; }
 
 // ---------------------------------------------------------------------------
 // Small kernels: end of a chunk of iterations, accept, mass reduction.
@@ -192,6 +114,10 @@ struct Instance {
   double t = 0.0, dt_prev = 0.0;
   int step_index = 0;
   int last_iters = 0;
+  pfch_fno* fno = nullptr;  // learned initial guess (not owned)
+  double fno_norm[4] = {0, 1, 1, 1};
+  double* xguess = nullptr;  // learned guess buffer (allocated on first attach)
+  double* gpart = nullptr;   // FNO_SUM_BLOCKS partial sums of the network output
   std::vector<void*> allocs;
 };
 
@@ -209,6 +135,10 @@ struct Group {
 };
 
 }  // namespace
+
+struct pfch_fno {
+  Fno f;
+};
 
 struct pfch_ctx {
   hipStream_t stream = nullptr;
@@ -616,6 +546,26 @@ int betas_host(pfch_ctx* ctx, Instance& I, double a, double out[4]) {
   return PFCH_OK;
 }
 
+// Learned initial guess of instance I for a step of size dt: network inputs
+// from (u^n, u^{n-1}), one forward pass on the context's stream, then
+// x0 = extrapolation + Pi_0(so * y) into I.xguess.
+int learned_guess(pfch_ctx* ctx, Instance& I, double rho) {
+  Fno& F = I.fno->f;
+  hipStream_t s = ctx->stream;
+  const double* un = I.U[I.ucur];
+  const double* unm1 = I.U[1 - I.ucur];
+  const long long P = I.npts;
+  const double* nrm = I.fno_norm;
+  hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(P)), dim3(256), 0, s, unm1, un, (const double*)nullptr, P,
+                     rho, nrm[0], nrm[1], nrm[2], nrm[3], F.xin, (float*)nullptr);
+  if (fno_forward(F, F.xin, 1, s) != hipSuccess) return PFCH_E_HIP;
+  hipLaunchKernelGGL(k_partial_sum, dim3(FNO_SUM_BLOCKS), dim3(256), 0, s, (const float*)F.y, P, I.gpart);
+  hipLaunchKernelGGL(k_learned_guess, dim3(blocks_for(P)), dim3(256), 0, s, un, unm1, rho, nrm[3],
+                     (const float*)F.y, (const double*)I.gpart, FNO_SUM_BLOCKS, P, I.xguess);
+  HIPCHK(hipGetLastError());
+  return PFCH_OK;
+}
+
 int fft_pairs_of(const Instance& I, int iters) {
   // Transform pairs of real fields (one forward + one inverse 2D transform
   // of a real field counts as one pair).  Per iteration: PFC 2 forward + 1
@@ -671,7 +621,7 @@ int pfch_validate_desc(const pfch_instance_desc* d) {
   for (int i = 0; i < d->n_eta; ++i)
     if (!(d->eta[i] >= 0.0) || !std::isfinite(d->eta[i])) return PFCH_E_INVAL;
   if (d->max_iter < 1 || d->max_iter > 1000000) return PFCH_E_INVAL;
-  if (d->guess != 0) return PFCH_E_UNSUPPORTED;
+  if (d->guess != 0 && d->guess != 1) return PFCH_E_INVAL;
   if (d->ndim != 2) return PFCH_E_UNSUPPORTED;
   if (!supported_len(d->n[0]) || !supported_len(d->n[1])) return PFCH_E_UNSUPPORTED;
   return PFCH_OK;
@@ -923,10 +873,16 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
   std::vector<double> as(n);
   int rc;
   for (int i = 0; i < n; ++i) active[i] = i;
+  std::vector<int> guess_kind(n, 0);  // 0 extrapolated, 1 learned, 2 learned then extrapolated
   for (auto& G : ctx->groups) {
     for (size_t k = 0; k < G.members.size(); ++k) {
-      const Instance& I = ctx->inst[G.members[k]];
-      const StepSetup ss = step_setup_for(I, dt[G.members[k]]);
+      Instance& I = ctx->inst[G.members[k]];
+      StepSetup ss = step_setup_for(I, dt[G.members[k]]);
+      if (I.fno && I.d.guess == 1 && I.has_prev) {
+        if ((rc = learned_guess(ctx, I, ss.rho))) return rc;
+        ss.xin = I.xguess;
+        guess_kind[G.members[k]] = 1;
+      }
       as[G.members[k]] = ss.a;
       G.h_args[k] = to_args(ss);
     }
@@ -936,6 +892,20 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
     if ((rc = launch_setup(ctx, G, G.d_members, G.d_args, nm))) return rc;
   }
   if ((rc = run_iterations(ctx, active))) return rc;
+  // A learned guess that does not lead to convergence falls back to the
+  // extrapolated guess: the step is solved again from it.
+  std::vector<int> retry;
+  for (int i = 0; i < n; ++i) {
+    if (guess_kind[i] != 1) continue;
+    int it = 0;
+    double d = 0.0;
+    if (status_of(ctx->inst[i], ctx->h_recs[i], &it, &d) == PFCH_OK) continue;
+    Instance& I = ctx->inst[i];
+    if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, dt[i])))) return rc;
+    guess_kind[i] = 2;
+    retry.push_back(i);
+  }
+  if (!retry.empty() && (rc = run_iterations(ctx, retry))) return rc;
   int first_err = PFCH_OK;
   std::vector<int> status(n), iters(n);
   std::vector<double> dn(n);
@@ -988,6 +958,7 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
       s.iters = iters[i];
       s.dnorm_inf = dn[i];
       s.fft_pairs = fft_pairs_of(I, iters[i]);
+      s.guess = guess_kind[i];
       s.mass = (want_mass && status[i] == PFCH_OK) ? ctx->h_mass[i] : NAN;
       if (ctx->stats_detail > 0) {
         if ((rc = betas_host(ctx, I, as[i], s.beta))) return rc;
@@ -1039,6 +1010,248 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
     if ((rc = betas_host(ctx, I, a, st->beta))) return rc;
   }
   return status;
+}
+
+
+// ---------------------------------------------------------------------------
+// Learned initial guess (float32 Fourier neural operator).
+// ---------------------------------------------------------------------------
+
+int64_t pfch_fno_num_params(int32_t width, int32_t modes, int32_t layers) {
+  if (width < 1 || width > WG_MAXC || modes < 1 || modes > 64 || layers < 1 || layers > 16) return PFCH_E_INVAL;
+  return fno_count(width, modes, layers);
+}
+
+void pfch_fno_destroy(pfch_fno* f) {
+  if (!f) return;
+  if (f->f.s) (void)hipStreamSynchronize(f->f.s);
+  for (void* p : f->f.allocs) (void)hipFree(p);
+  for (void* p : f->f.host_allocs) (void)hipHostFree(p);
+  delete f;
+}
+
+int pfch_fno_create(int32_t width, int32_t modes, int32_t layers, int32_t ny, int32_t nx, int32_t max_batch,
+                    void* hip_stream, pfch_fno** out) {
+  if (!out) return PFCH_E_INVAL;
+  *out = nullptr;
+  if (pfch_fno_num_params(width, modes, layers) < 0) return PFCH_E_INVAL;
+  if (ny < 2 || nx < 2 || 2 * modes > ny || 2 * modes > nx || max_batch < 1) return PFCH_E_INVAL;
+  const long long W = width, M = modes, P = (long long)ny * nx, B = max_batch;
+  // launch limits of the strided products (grid y and z extents)
+  if ((B * W * ny + 31) / 32 > 65535 || B * W > 65535 || 2 * M * M > 65535) return PFCH_E_UNSUPPORTED;
+  pfch_fno* h = new pfch_fno();
+  Fno& F = h->f;
+  F.W = width;
+  F.M = modes;
+  F.L = layers;
+  F.ny = ny;
+  F.nx = nx;
+  F.maxb = max_batch;
+  F.P = P;
+  F.MM2 = 2 * M * M;
+  F.n = fno_count(W, M, layers);
+  F.s = (hipStream_t)hip_stream;
+  long long o = 0;
+  F.oP = o;
+  o += 2 * W;
+  F.opb = o;
+  o += W;
+  for (int l = 0; l < layers; ++l) {
+    F.oR.push_back(o);
+    o += W * W * F.MM2 * 2;
+    F.oW.push_back(o);
+    o += W * W;
+    F.ob.push_back(o);
+    o += W;
+  }
+  F.oQ = o;
+  o += W;
+  F.oqb = o;
+  o += 1;
+  auto fail = [&](int rc) {
+    pfch_fno_destroy(h);
+    return rc;
+  };
+  auto fal = [&](float** p, long long nfloats) {
+    void* q = nullptr;
+    const int rc = dalloc(F.allocs, &q, sizeof(float) * (size_t)nfloats);
+    *p = (float*)q;
+    return rc;
+  };
+  int rc;
+  const long long field = B * W * P;
+  if ((rc = fal(&F.theta, F.n)) || (rc = fal(&F.grad, F.n)) || (rc = fal(&F.am, F.n)) || (rc = fal(&F.av, F.n)))
+    return fail(rc);
+  if ((rc = fal(&F.Fx, 2 * nx * M)) || (rc = fal(&F.Fy, 2 * 2 * M * ny)) || (rc = fal(&F.Gy, 2 * ny * 2 * M)) ||
+      (rc = fal(&F.Gx, 2 * M * nx)))
+    return fail(rc);
+  F.v.assign(layers + 1, nullptr);
+  F.z.assign(layers, nullptr);
+  F.vh.assign(layers, nullptr);
+  for (int l = 0; l <= layers; ++l)
+    if ((rc = fal(&F.v[l], field))) return fail(rc);
+  for (int l = 0; l < layers; ++l)
+    if ((rc = fal(&F.z[l], field)) || (rc = fal(&F.vh[l], 2 * B * W * F.MM2))) return fail(rc);
+  if ((rc = fal(&F.S1, 2 * B * W * ny * M)) || (rc = fal(&F.Yb, 2 * B * W * F.MM2)) ||
+      (rc = fal(&F.Yb2, 2 * B * W * F.MM2)))
+    return fail(rc);
+  if ((rc = fal(&F.xin, B * 2 * P)) || (rc = fal(&F.y, B * P)) || (rc = fal(&F.dy, B * P)) ||
+      (rc = fal(&F.dvA, field)) || (rc = fal(&F.dvB, field)))
+    return fail(rc);
+  F.wg_blocks = (int)std::min<long long>(1024, (B * P + WG_TILE - 1) / WG_TILE);
+  if ((rc = fal(&F.wpart, (long long)F.wg_blocks * (W + 1) * W))) return fail(rc);
+  if ((rc = fal(&F.lpart, FNO_LOSS_BLOCKS))) return fail(rc);
+  {
+    void* q = nullptr;
+    if ((rc = dalloc(F.allocs, &q, sizeof(double)))) return fail(rc);
+    F.loss = (double*)q;
+    if ((rc = halloc(F.host_allocs, &q, sizeof(double)))) return fail(rc);
+    F.h_loss = (double*)q;
+  }
+  // DFT matrices, angles reduced exactly in integers before the float64 sin/cos
+  {
+    const double tp = 2.0 * M_PI;
+    std::vector<float> fx(2 * nx * M), fy(2 * 2 * M * ny), gy(2 * ny * 2 * M), gx(2 * M * nx);
+    auto kyv = [&](long long kyi) { return kyi < M ? kyi : ny - 2 * M + kyi; };
+    for (long long x = 0; x < nx; ++x)
+      for (long long kx = 0; kx < M; ++kx) {
+        const double ang = tp * (double)((kx * x) % nx) / nx;
+        fx[2 * (x * M + kx)] = (float)std::cos(ang);
+        fx[2 * (x * M + kx) + 1] = (float)-std::sin(ang);
+        const double c = (kx == 0 || 2 * kx == nx ? 1.0 : 2.0) / ((double)nx * ny);
+        gx[2 * (kx * nx + x)] = (float)(c * std::cos(ang));
+        gx[2 * (kx * nx + x) + 1] = (float)(c * std::sin(ang));
+      }
+    for (long long kyi = 0; kyi < 2 * M; ++kyi)
+      for (long long y = 0; y < ny; ++y) {
+        const double ang = tp * (double)((kyv(kyi) * y) % ny) / ny;
+        fy[2 * (kyi * ny + y)] = (float)std::cos(ang);
+        fy[2 * (kyi * ny + y) + 1] = (float)-std::sin(ang);
+        gy[2 * (y * 2 * M + kyi)] = (float)std::cos(ang);
+        gy[2 * (y * 2 * M + kyi) + 1] = (float)std::sin(ang);
+      }
+    if (hipMemcpy(F.Fx, fx.data(), fx.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(F.Fy, fy.data(), fy.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(F.Gy, gy.data(), gy.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(F.Gx, gx.data(), gx.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(F.theta, 0, sizeof(float) * F.n) != hipSuccess ||
+        hipMemset(F.am, 0, sizeof(float) * F.n) != hipSuccess ||
+        hipMemset(F.av, 0, sizeof(float) * F.n) != hipSuccess)
+      return fail(PFCH_E_HIP);
+  }
+  *out = h;
+  return PFCH_OK;
+}
+
+int pfch_fno_init_params(pfch_fno* f, uint64_t seed) {
+  if (!f) return PFCH_E_INVAL;
+  Fno& F = f->f;
+  std::vector<float> th(F.n, 0.0f);
+  uint64_t st = seed;
+  auto uni = [&]() {  // splitmix64 -> uniform [-1, 1)
+    st += 0x9E3779B97F4A7C15ULL;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  };
+  const double W = F.W;
+  for (long long k = 0; k < 2 * F.W; ++k) th[F.oP + k] = (float)(uni() / std::sqrt(2.0));
+  for (int l = 0; l < F.L; ++l) {
+    for (long long k = 0; k < (long long)F.W * F.W * F.MM2 * 2; ++k)
+      th[F.oR[l] + k] = (float)((uni() + 1.0) / (2.0 * W * W));
+    for (long long k = 0; k < (long long)F.W * F.W; ++k) th[F.oW[l] + k] = (float)(uni() / std::sqrt(W));
+  }
+  for (long long k = 0; k < F.W; ++k) th[F.oQ + k] = (float)(uni() / std::sqrt(W));
+  HIPCHK(hipMemcpyAsync(F.theta, th.data(), sizeof(float) * F.n, hipMemcpyHostToDevice, F.s));
+  HIPCHK(hipStreamSynchronize(F.s));
+  return PFCH_OK;
+}
+
+int pfch_fno_set_params(pfch_fno* f, const float* theta, int64_t n) {
+  if (!f || !theta || n != f->f.n) return PFCH_E_INVAL;
+  HIPCHK(hipMemcpyAsync(f->f.theta, theta, sizeof(float) * n, hipMemcpyDeviceToDevice, f->f.s));
+  return PFCH_OK;
+}
+
+int pfch_fno_get_params(pfch_fno* f, float* theta, int64_t n) {
+  if (!f || !theta || n != f->f.n) return PFCH_E_INVAL;
+  HIPCHK(hipMemcpyAsync(theta, f->f.theta, sizeof(float) * n, hipMemcpyDeviceToDevice, f->f.s));
+  HIPCHK(hipStreamSynchronize(f->f.s));
+  return PFCH_OK;
+}
+
+int pfch_fno_forward(pfch_fno* f, const float* x, float* y, int32_t batch) {
+  if (!f || !x || !y || batch < 1 || batch > f->f.maxb) return PFCH_E_INVAL;
+  Fno& F = f->f;
+  if (fno_forward(F, x, batch, F.s) != hipSuccess) return PFCH_E_HIP;
+  HIPCHK(hipMemcpyAsync(y, F.y, sizeof(float) * batch * F.P, hipMemcpyDeviceToDevice, F.s));
+  return PFCH_OK;
+}
+
+int pfch_fno_grad(pfch_fno* f, const float* x, const float* t, int32_t batch, float* grad, double* loss) {
+  if (!f || !x || !t || batch < 1 || batch > f->f.maxb) return PFCH_E_INVAL;
+  Fno& F = f->f;
+  if (fno_backward(F, x, t, batch, F.s) != hipSuccess) return PFCH_E_HIP;
+  if (grad) HIPCHK(hipMemcpyAsync(grad, F.grad, sizeof(float) * F.n, hipMemcpyDeviceToDevice, F.s));
+  if (loss) {
+    HIPCHK(hipMemcpyAsync(F.h_loss, F.loss, sizeof(double), hipMemcpyDeviceToHost, F.s));
+    HIPCHK(hipStreamSynchronize(F.s));
+    *loss = *F.h_loss;
+  }
+  return PFCH_OK;
+}
+
+int pfch_fno_adam_step(pfch_fno* f, float lr, float beta1, float beta2, float eps, int32_t step) {
+  if (!f || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return PFCH_E_INVAL;
+  Fno& F = f->f;
+  if (step == 1) {
+    HIPCHK(hipMemsetAsync(F.am, 0, sizeof(float) * F.n, F.s));
+    HIPCHK(hipMemsetAsync(F.av, 0, sizeof(float) * F.n, F.s));
+  }
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(F.n)), dim3(256), 0, F.s, F.theta, (const float*)F.grad, F.am, F.av,
+                     F.n, lr, beta1, beta2, eps, c1, c2);
+  HIPCHK(hipGetLastError());
+  return PFCH_OK;
+}
+
+int pfch_fno_prepare(pfch_fno* f, const double* u_nm1, const double* u_n, const double* u_np1, double rho,
+                     const double norm[4], float* x, float* t) {
+  if (!f || !u_nm1 || !u_n || !x || !norm || ((u_np1 == nullptr) != (t == nullptr))) return PFCH_E_INVAL;
+  if (!(norm[1] > 0.0) || !(norm[2] > 0.0) || !(norm[3] > 0.0) || !std::isfinite(rho)) return PFCH_E_INVAL;
+  Fno& F = f->f;
+  hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(F.P)), dim3(256), 0, F.s, u_nm1, u_n, u_np1, F.P, rho,
+                     norm[0], norm[1], norm[2], norm[3], x, t);
+  HIPCHK(hipGetLastError());
+  return PFCH_OK;
+}
+
+int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4]) {
+  if (!ctx || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
+  Instance& I = ctx->inst[inst];
+  if (!f) {
+    I.fno = nullptr;
+    return PFCH_OK;
+  }
+  if (!norm || !(norm[1] > 0.0) || !(norm[2] > 0.0) || !(norm[3] > 0.0) || !std::isfinite(norm[0]))
+    return PFCH_E_INVAL;
+  if (f->f.ny != I.ny || f->f.nx != I.nx) return PFCH_E_INVAL;
+  int rc;
+  if (!I.xguess) {
+    void* q = nullptr;
+    if ((rc = dalloc(I.allocs, &q, sizeof(double) * (size_t)I.npts))) return rc;
+    I.xguess = (double*)q;
+    if ((rc = dalloc(I.allocs, &q, sizeof(double) * FNO_SUM_BLOCKS))) return rc;
+    I.gpart = (double*)q;
+  }
+  I.fno = f;
+  for (int k = 0; k < 4; ++k) I.fno_norm[k] = norm[k];
+  return PFCH_OK;
 }
 
 }  // extern "C"

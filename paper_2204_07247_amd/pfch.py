@@ -30,6 +30,9 @@ EXPORTED = (
     "pfch_step", "pfch_solve", "pfch_set_stats_detail", "pfch_time_kernels",
     "pfch_get_launch_config", "pfch_destroy",
     "pfch_strerror", "pfch_version",
+    "pfch_fno_num_params", "pfch_fno_create", "pfch_fno_init_params", "pfch_fno_set_params",
+    "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad", "pfch_fno_adam_step",
+    "pfch_fno_prepare", "pfch_fno_destroy", "pfch_set_fno",
 )
 
 
@@ -55,12 +58,13 @@ class Stats(ctypes.Structure):
         ("iters", ctypes.c_int32),
         ("fft_pairs", ctypes.c_int32),
         ("status", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("guess", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return dict(iters=self.iters, status=self.status, dnorm=self.dnorm_inf,
-                    betas=tuple(self.beta), mass=self.mass, fft_pairs=self.fft_pairs)
+                    betas=tuple(self.beta), mass=self.mass, fft_pairs=self.fft_pairs,
+                    guess=self.guess)
 
 
 class PfchError(RuntimeError):
@@ -96,6 +100,25 @@ def lib():
         L.pfch_strerror.argtypes = [ctypes.c_int]
         L.pfch_strerror.restype = ctypes.c_char_p
         L.pfch_version.argtypes = []
+        fp = ctypes.c_void_p
+        L.pfch_fno_num_params.argtypes = [i32, i32, i32]
+        L.pfch_fno_num_params.restype = ctypes.c_int64
+        L.pfch_fno_create.argtypes = [i32, i32, i32, i32, i32, i32, vp, ctypes.POINTER(vp)]
+        L.pfch_fno_init_params.argtypes = [fp, ctypes.c_uint64]
+        L.pfch_fno_set_params.argtypes = [fp, vp, ctypes.c_int64]
+        L.pfch_fno_get_params.argtypes = [fp, vp, ctypes.c_int64]
+        L.pfch_fno_forward.argtypes = [fp, vp, vp, i32]
+        L.pfch_fno_grad.argtypes = [fp, vp, vp, i32, vp, ctypes.POINTER(dbl)]
+        L.pfch_fno_adam_step.argtypes = [fp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, i32]
+        L.pfch_fno_prepare.argtypes = [fp, vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, vp]
+        L.pfch_fno_destroy.argtypes = [fp]
+        L.pfch_fno_destroy.restype = None
+        L.pfch_set_fno.argtypes = [vp, i32, fp, ctypes.POINTER(dbl)]
+        for name in ("pfch_fno_create", "pfch_fno_init_params", "pfch_fno_set_params",
+                     "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad",
+                     "pfch_fno_adam_step", "pfch_fno_prepare", "pfch_set_fno"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("pfch_validate_desc", "pfch_create", "pfch_set_state", "pfch_get_state",
                      "pfch_step", "pfch_solve", "pfch_set_stats_detail", "pfch_time_kernels",
                      "pfch_get_launch_config", "pfch_version"):
@@ -110,7 +133,7 @@ def strerror(code):
 
 def make_desc(model, scheme, shape, lengths, eps, eta1=0.0, eta2=0.0, tau=0.0,
               mobility=1.0, s=0.9, etas=PAPER_ETAS, tol=1e-10, max_iter=1000,
-              theta_l=1.0):
+              theta_l=1.0, guess=0):
     """Descriptor from plain values.  ``shape``/``lengths`` are in array
     order ((Ny, Nx) in 2D); the C struct stores them x first."""
     d = InstanceDesc()
@@ -128,7 +151,7 @@ def make_desc(model, scheme, shape, lengths, eps, eta1=0.0, eta2=0.0, tau=0.0,
     for i, e in enumerate(etas):
         d.eta[i] = e
     d.max_iter = int(max_iter)
-    d.guess = 0
+    d.guess = int(guess)
     d.reserved = 0
     return d
 
@@ -137,15 +160,19 @@ def validate_desc(desc):
     return lib().pfch_validate_desc(ctypes.byref(desc))
 
 
-def _ptr(t):
+def _ptr(t, dtype="float64"):
     if t is None:
         return None
     if not (t.is_cuda and t.is_contiguous()):
         raise ValueError("expected a contiguous GPU tensor")
     import torch
-    if t.dtype != torch.float64:
-        raise ValueError("expected float64")
+    if t.dtype != getattr(torch, dtype):
+        raise ValueError(f"expected {dtype}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _fptr(t):
+    return _ptr(t, "float32")
 
 
 def _stream_handle():
@@ -232,6 +259,16 @@ class Context:
             raise PfchError(rc, "pfch_step")
         return rc, ([s.as_dict() for s in st] if stats else None)
 
+    def set_fno(self, inst, fno, norm=None):
+        """Attach an Fno (None detaches) to instance `inst` with
+        norm = (mu, su, sd, so)."""
+        nrm = (ctypes.c_double * 4)(*(norm if norm is not None else (0.0, 1.0, 1.0, 1.0)))
+        self._fno_refs = getattr(self, "_fno_refs", {})
+        self._fno_refs[inst] = fno
+        rc = lib().pfch_set_fno(self._h, inst, fno._h if fno is not None else None, nrm)
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_set_fno")
+
     def solve(self, inst, a, b, c, u_n, u_nm1, x):
         st = Stats()
         rc = lib().pfch_solve(self._h, inst, float(a), float(b), float(c), _ptr(u_n),
@@ -239,3 +276,77 @@ class Context:
         if rc in (PFCH_E_INVAL, PFCH_E_NOMEM, PFCH_E_HIP, PFCH_E_UNSUPPORTED):
             raise PfchError(rc, "pfch_solve")
         return rc, st.as_dict()
+
+
+def fno_num_params(width, modes, layers):
+    return int(lib().pfch_fno_num_params(width, modes, layers))
+
+
+class Fno:
+    """Float32 Fourier neural operator on the GPU (pfch_fno_* entry points).
+    Arrays are contiguous float32 GPU tensors: x [B, 2, Ny, Nx], y/t
+    [B, Ny, Nx], parameters [n]."""
+
+    def __init__(self, width, modes, layers, ny, nx, max_batch=1, stream=None):
+        L = lib()
+        h = ctypes.c_void_p()
+        s = _stream_handle() if stream is None else ctypes.c_void_p(stream)
+        rc = L.pfch_fno_create(width, modes, layers, ny, nx, max_batch, s, ctypes.byref(h))
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_fno_create")
+        self._h = h
+        self.width, self.modes, self.layers = width, modes, layers
+        self.shape = (ny, nx)
+        self.max_batch = max_batch
+        self.n_params = fno_num_params(width, modes, layers)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pfch_fno_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _check(self, rc, where):
+        if rc != PFCH_OK:
+            raise PfchError(rc, where)
+
+    def init_params(self, seed=0):
+        self._check(lib().pfch_fno_init_params(self._h, int(seed)), "pfch_fno_init_params")
+
+    def set_params(self, theta):
+        self._check(lib().pfch_fno_set_params(self._h, _fptr(theta), theta.numel()),
+                    "pfch_fno_set_params")
+
+    def get_params(self):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        self._check(lib().pfch_fno_get_params(self._h, _fptr(out), out.numel()), "pfch_fno_get_params")
+        return out
+
+    def forward(self, x):
+        import torch
+        b = x.shape[0]
+        y = torch.empty((b,) + tuple(self.shape), dtype=torch.float32, device=x.device)
+        self._check(lib().pfch_fno_forward(self._h, _fptr(x), _fptr(y), b), "pfch_fno_forward")
+        return y
+
+    def grad(self, x, t, want_grad=True, want_loss=True):
+        """(loss or None, gradient tensor or None)."""
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device) if want_grad else None
+        loss = ctypes.c_double()
+        self._check(lib().pfch_fno_grad(self._h, _fptr(x), _fptr(t), x.shape[0],
+                                        _fptr(g) if g is not None else None,
+                                        ctypes.byref(loss) if want_loss else None), "pfch_fno_grad")
+        return (loss.value if want_loss else None), g
+
+    def adam_step(self, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(lib().pfch_fno_adam_step(self._h, lr, beta1, beta2, eps, int(step)),
+                    "pfch_fno_adam_step")
+
+    def prepare(self, u_nm1, u_n, u_np1, rho, norm, x, t=None):
+        """Fill x [2, Ny, Nx] (and t [Ny, Nx]) of one sample from float64 fields."""
+        nrm = (ctypes.c_double * 4)(*norm)
+        self._check(lib().pfch_fno_prepare(self._h, _ptr(u_nm1), _ptr(u_n), _ptr(u_np1), float(rho),
+                                           nrm, _fptr(x), _fptr(t)), "pfch_fno_prepare")

@@ -77,7 +77,30 @@ def test_invalid_model_and_reserved_fields():
     assert pfch.validate_desc(d) == pfch.PFCH_E_INVAL
     d = _desc()
     d.guess = 1
-    assert pfch.validate_desc(d) == pfch.PFCH_E_UNSUPPORTED
+    assert pfch.validate_desc(d) == pfch.PFCH_OK
+    d.guess = 2
+    assert pfch.validate_desc(d) == pfch.PFCH_E_INVAL
+
+
+def test_fno_sizes_and_argument_checks_on_host():
+    """Parameter count equals the reference network's; invalid network
+    shapes and arguments are rejected before any device work."""
+    from oracle import fno as ofno
+    from paper_2204_07247_amd import pfch
+    for w, m, l in ((32, 16, 4), (4, 3, 2), (8, 5, 3)):
+        assert pfch.fno_num_params(w, m, l) == ofno.n_params(w, m, l)
+    assert pfch.fno_num_params(0, 3, 2) == pfch.PFCH_E_INVAL
+    assert pfch.fno_num_params(65, 3, 2) == pfch.PFCH_E_INVAL
+    L = pfch.lib()
+    h = ctypes.c_void_p()
+    # 2M > Ny, 2M > Nx, zero batch, null output
+    assert L.pfch_fno_create(4, 7, 2, 12, 12, 1, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
+    assert L.pfch_fno_create(4, 3, 2, 12, 4, 1, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
+    assert L.pfch_fno_create(4, 3, 2, 12, 12, 0, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
+    assert L.pfch_fno_create(4, 3, 2, 12, 12, 1, None, None) == pfch.PFCH_E_INVAL
+    assert L.pfch_fno_forward(None, None, None, 1) == pfch.PFCH_E_INVAL
+    assert L.pfch_fno_adam_step(None, 1e-3, 0.9, 0.999, 1e-8, 1) == pfch.PFCH_E_INVAL
+    assert L.pfch_set_fno(None, 0, None, None) == pfch.PFCH_E_INVAL
 
 
 def test_create_rejects_bad_arguments_before_device_work():
