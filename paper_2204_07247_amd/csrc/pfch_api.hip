@@ -1099,7 +1099,8 @@ int pfch_fno_create(int32_t width, int32_t modes, int32_t layers, int32_t ny, in
       (rc = fal(&F.dvA, field)) || (rc = fal(&F.dvB, field)))
     return fail(rc);
   F.wg_blocks = (int)std::min<long long>(1024, (B * P + WG_TILE - 1) / WG_TILE);
-  if ((rc = fal(&F.wpart, (long long)F.wg_blocks * (W + 1) * W))) return fail(rc);
+  // largest (CX + 1) * CY of the three weight-gradient shapes: (W+1)W, 3W, W+1
+  if ((rc = fal(&F.wpart, (long long)F.wg_blocks * (W + 2) * W))) return fail(rc);
   if ((rc = fal(&F.lpart, FNO_LOSS_BLOCKS))) return fail(rc);
   {
     void* q = nullptr;

@@ -1,0 +1,202 @@
+"""Float32 FNO kernels against the float64 reference network, and the learned
+initial guess inside pfch_step.
+
+Forward and gradient are compared on tiny networks at float32-scaled
+tolerances; the learned guess must leave the converged step within the PAGD
+tolerance of the extrapolated-guess step, with the same mass, and fall back
+to the extrapolated guess when its own solve fails."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fno as ofno
+from tests._common import desc_for
+
+pytestmark = pytest.mark.gpu
+
+NETS = [  # (width, modes, layers, ny, nx, batch)
+    (4, 3, 2, 12, 12, 2),
+    (5, 3, 3, 8, 12, 3),   # rectangular
+    (4, 3, 2, 6, 10, 2),   # 2M == Ny: every ky kept
+]
+
+
+def _inputs(w, m, l, ny, nx, b, seed):
+    rng = np.random.default_rng(seed)
+    theta = ofno.init_params(w, m, l, seed=seed)
+    x = rng.normal(size=(b, 2, ny, nx))
+    t = rng.normal(size=(b, ny, nx)) * 0.5
+    # round to float32 first so both sides see the same numbers
+    return theta.astype(np.float32), x.astype(np.float32), t.astype(np.float32)
+
+
+def _groups(w, m, l):
+    """(name, slice) of each parameter block in the flat layout."""
+    out, o = [], 0
+    for name, n in [("P", 2 * w), ("pb", w)]:
+        out.append((name, slice(o, o + n)))
+        o += n
+    for k in range(l):
+        for name, n in [(f"R{k}", w * w * 2 * m * m * 2), (f"W{k}", w * w), (f"b{k}", w)]:
+            out.append((name, slice(o, o + n)))
+            o += n
+    for name, n in [("Q", w), ("qb", 1)]:
+        out.append((name, slice(o, o + n)))
+        o += n
+    return out
+
+
+def _net(w, m, l, ny, nx, b, theta):
+    import torch
+    from paper_2204_07247_amd import pfch
+    f = pfch.Fno(w, m, l, ny, nx, max_batch=b)
+    f.set_params(torch.from_numpy(theta).cuda())
+    return f
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
+
+
+@pytest.mark.parametrize("net", NETS, ids=lambda n: "x".join(map(str, n)))
+def test_forward_matches_reference(net):
+    import torch
+    w, m, l, ny, nx, b = net
+    theta, x, _ = _inputs(*net, seed=11)
+    print(f"fno forward {net}", flush=True)
+    f = _net(*net, theta)
+    y = f.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref, _ = ofno.forward(theta.astype(np.float64), x.astype(np.float64), w, m, l)
+    assert _rel(y, ref) <= 1e-5, _rel(y, ref)
+    f.close()
+
+
+@pytest.mark.parametrize("net", NETS, ids=lambda n: "x".join(map(str, n)))
+def test_gradient_matches_reference(net):
+    import torch
+    w, m, l, ny, nx, b = net
+    theta, x, t = _inputs(*net, seed=12)
+    print(f"fno grad {net}", flush=True)
+    f = _net(*net, theta)
+    loss, g = f.grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    gref, lref = ofno.backward(theta.astype(np.float64), x.astype(np.float64), t.astype(np.float64),
+                               w, m, l)
+    assert abs(loss - lref) <= 1e-5 * abs(lref)
+    assert _rel(g, gref) <= 1e-4, _rel(g, gref)
+    for name, sl in _groups(w, m, l):
+        assert _rel(g[sl], gref[sl]) <= 1e-3, (name, _rel(g[sl], gref[sl]))
+    f.close()
+
+
+def test_adam_update_and_training_reduce_loss():
+    """One Adam update equals the textbook formula on the returned gradient;
+    a few dozen updates on a fixed batch cut the loss."""
+    import torch
+    net = (4, 3, 2, 12, 12, 4)
+    w, m, l, ny, nx, b = net
+    theta, x, _ = _inputs(*net, seed=13)
+    t = (0.5 * x[:, 0] - 0.3 * x[:, 1]).astype(np.float32)  # a target the network can fit
+    f = _net(*net, theta)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    loss0, g = f.grad(xd, td)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    f.adam_step(lr, 1, b1, b2, eps)
+    th1 = f.get_params().cpu().numpy().astype(np.float64)
+    g = g.cpu().numpy().astype(np.float64)
+    mh = (1 - b1) * g / (1 - b1)
+    vh = (1 - b2) * g * g / (1 - b2)
+    expect = theta.astype(np.float64) - lr * mh / (np.sqrt(vh) + eps)
+    assert np.max(np.abs(th1 - expect)) <= 1e-6
+    for k in range(2, 41):
+        f.grad(xd, td, want_grad=False, want_loss=False)
+        f.adam_step(lr, k, b1, b2, eps)
+    loss1, _ = f.grad(xd, td, want_grad=False)
+    assert loss1 < 0.6 * loss0, (loss0, loss1)
+    f.close()
+
+
+def _history(w, nsteps):
+    """State after `nsteps` plain steps (u^n, u^{n-1}, dt_prev) on the GPU."""
+    import torch
+    from paper_2204_07247_amd import pfch
+    ctx = pfch.Context([desc_for(w)])
+    u0 = torch.from_numpy(W.initial_condition(w)).cuda()
+    ctx.set_state(0, u0)
+    for _ in range(nsteps):
+        rc, _ = ctx.step(w.dt)
+        assert rc == pfch.PFCH_OK
+    un, unm1 = torch.empty_like(u0), torch.empty_like(u0)
+    _, dtp, k = ctx.get_state(0, un, unm1)
+    ctx.close()
+    return un, unm1, dtp, k
+
+
+def _one_step(w, un, unm1, dtp, k, fno=None, norm=None, guess=0, max_iter=None):
+    import torch
+    from paper_2204_07247_amd import pfch
+    d = desc_for(w)
+    d.guess = guess
+    if max_iter is not None:
+        d.max_iter = max_iter
+    ctx = pfch.Context([d])
+    ctx.set_state(0, un, unm1, t=0.0, dt_prev=dtp, step_index=k)
+    if fno is not None:
+        ctx.set_fno(0, fno, norm)
+    rc, st = ctx.step(w.dt)
+    out = torch.empty_like(un)
+    ctx.get_state(0, out)
+    ctx.close()
+    return rc, st[0], out.cpu().numpy()
+
+
+@pytest.mark.parametrize("w", [
+    dataclasses.replace(W.PFC64_MP, seeds=(0,)),
+    dataclasses.replace(W.FCH256_BDF2, shape=(64, 64), seeds=(1,)),
+], ids=lambda w: f"{w.model}-{w.scheme}")
+def test_learned_guess_step_within_tolerance(w):
+    """From the same state, the learned-guess step and the extrapolated-guess
+    step both converge; the solutions differ within the PAGD tolerance and
+    have the same mass."""
+    from paper_2204_07247_amd import pfch
+    print(f"learned guess {w.model} {w.scheme} {w.shape}", flush=True)
+    un, unm1, dtp, k = _history(w, 3)
+    ny, nx = w.shape
+    fno = pfch.Fno(8, 4, 2, ny, nx)
+    fno.init_params(seed=5)
+    u = un.cpu().numpy()
+    du = (un - unm1).cpu().numpy()
+    norm = (float(u.mean()), float(u.std()), float(du.std()), 0.1 * float(du.std()))
+    rc_p, st_p, plain = _one_step(w, un, unm1, dtp, k)
+    rc_l, st_l, learned = _one_step(w, un, unm1, dtp, k, fno=fno, norm=norm, guess=1)
+    assert rc_p == pfch.PFCH_OK and rc_l == pfch.PFCH_OK
+    assert st_p["guess"] == 0 and st_l["guess"] == 1
+    assert st_l["dnorm"] < w.tol and st_p["dnorm"] < w.tol
+    assert np.max(np.abs(learned - plain)) <= 1e-9
+    assert abs(learned.mean() - plain.mean()) <= 1e-14
+    # without desc.guess = 1 the attached network is not used
+    rc_n, st_n, same = _one_step(w, un, unm1, dtp, k, fno=fno, norm=norm, guess=0)
+    assert rc_n == pfch.PFCH_OK and st_n["guess"] == 0 and np.array_equal(same, plain)
+    fno.close()
+
+
+def test_failed_learned_guess_falls_back_to_extrapolation():
+    """A guess from which the solve fails (here: non-finite residual) is
+    replaced by the extrapolated guess; the step then equals the plain step
+    bitwise."""
+    from paper_2204_07247_amd import pfch
+    w = dataclasses.replace(W.PFC64_MP, seeds=(2,))
+    un, unm1, dtp, k = _history(w, 2)
+    ny, nx = w.shape
+    fno = pfch.Fno(4, 3, 1, ny, nx)
+    fno.init_params(seed=9)
+    norm = (0.0, 1.0, 1.0, 1e150)  # correction of order 1e150: the cubic term overflows
+    rc_p, st_p, plain = _one_step(w, un, unm1, dtp, k, max_iter=60)
+    rc_l, st_l, learned = _one_step(w, un, unm1, dtp, k, fno=fno, norm=norm, guess=1, max_iter=60)
+    assert rc_p == pfch.PFCH_OK and rc_l == pfch.PFCH_OK
+    assert st_l["guess"] == 2
+    assert st_l["iters"] == st_p["iters"]
+    assert np.array_equal(learned, plain)
+    fno.close()
