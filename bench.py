@@ -198,6 +198,89 @@ def batched_comparison(count, steps, solo_steps):
                 iters_per_step_mean=round(float(np.mean(its)), 3))
 
 
+def _learned_vs_plain(w, fno, norm_fn, steps):
+    """Plain and learned-guess runs of `steps` steps of w from the same
+    initial condition (after 2 untimed steps that build the history)."""
+    import torch
+    from paper_2204_07247_amd import learned, pfch
+    u0 = torch.from_numpy(W.initial_condition(w)).cuda()
+    res, finals = {}, {}
+    for mode in ("plain", "learned"):
+        ctx = pfch.Context([learned.desc_of(w, guess=1 if mode == "learned" else 0)])
+        ctx.set_stats_detail(0)
+        ctx.set_state(0, u0)
+        for _ in range(2):
+            ctx.step(w.dt)
+        if mode == "learned":
+            un, unm1 = torch.empty_like(u0), torch.empty_like(u0)
+            ctx.get_state(0, un, unm1)
+            ctx.set_fno(0, fno, norm_fn(un, unm1))
+        its, kinds = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rc, st = ctx.step(w.dt)
+            if rc != pfch.PFCH_OK:
+                raise RuntimeError(f"{mode} step failed: {pfch.strerror(rc)}")
+            its.append(st[0]["iters"])
+            kinds.append(st[0]["guess"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out = torch.empty_like(u0)
+        ctx.get_state(0, out)
+        finals[mode] = out
+        ctx.close()
+        res[mode] = dict(steps_per_s=round(steps / el, 2), iters_per_step=round(float(np.mean(its)), 3))
+        if mode == "learned":
+            res[mode]["fallbacks"] = int(sum(k == 2 for k in kinds))
+    res["steps"] = steps
+    res["learned_over_plain_steps_per_s"] = round(res["learned"]["steps_per_s"] / res["plain"]["steps_per_s"], 3)
+    res["final_max_abs_diff"] = float((finals["learned"] - finals["plain"]).abs().max().item())
+    return res
+
+
+def learned_comparison(epochs, eval_steps, deploy_steps):
+    """FNO warm start trained on solver trajectories of the FCH 256^2
+    generator (seeds 100-119, 100 steps each, 10% of the triples held out),
+    then plain vs learned guess on FCH 256^2 (seed 0) and, with the same
+    weights, on PFC 1024^2."""
+    import dataclasses
+
+    import torch
+    from paper_2204_07247_amd import learned
+    base = W.FCH256_BDF2
+    ws = [dataclasses.replace(base, seeds=(s,)) for s in range(100, 120)]
+    u0s = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    cfg = learned.TrainConfig(epochs=epochs)
+    log(f"[bench] learned guess: trajectories and training ({epochs} epochs)")
+    t0 = time.perf_counter()
+    tr = learned.train(ws, u0s, base.steps, cfg, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res = dict(network=dict(width=cfg.width, modes=cfg.modes, layers=cfg.layers, dtype="f32"),
+               training=dict(data=f"{len(ws)} x {base.steps} steps of {base.name} (seeds 100-119)",
+                             triples=tr.n_train + tr.n_val, held_out=tr.n_val, epochs=epochs,
+                             batch=cfg.batch, lr=cfg.lr, seconds=round(t_train, 1),
+                             train_loss=[round(v, 5) for v in tr.train_loss],
+                             held_out_loss=[round(v, 5) for v in tr.val_loss]))
+    log("[bench] learned guess: FCH 256^2 plain vs learned")
+    res[base.name] = _learned_vs_plain(base, tr.fno, lambda un, unm1: tr.norm, eval_steps)
+    pfc = WORKLOADS["pfc1024"]
+    f = learned.deploy(tr, *pfc.shape, cfg)
+    ratio = tr.norm[3] / tr.norm[2]
+
+    def pfc_norm(un, unm1):
+        d = (un - unm1)
+        sd = float(d.std().item()) or 1.0
+        return (float(un.mean().item()), float(un.std().item()) or 1.0, sd, ratio * sd)
+
+    log("[bench] learned guess: PFC 1024^2 with the FCH-trained weights")
+    res[pfc.name + "_fch_trained"] = _learned_vs_plain(pfc, f, pfc_norm, deploy_steps)
+    f.close()
+    tr.fno.close()
+    return res
+
+
 def cpu_baseline(w, max_steps, budget_s):
     """The CPU oracle on the same workload, first steps of the same trajectory."""
     from oracle import driver, models, spectral
@@ -229,6 +312,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the batched-ensemble comparison")
     ap.add_argument("--ensemble", type=int, default=64, help="instances in the batched comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
+    ap.add_argument("--learned-epochs", type=int, default=8)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the run, copy a MIB-sized float64 buffer three times "
                          "(a plain copy kernel of known traffic for counter calibration)")
@@ -268,6 +353,9 @@ def main():
     batched = None
     if not args.no_compare:
         batched = batched_comparison(args.ensemble, steps=10, solo_steps=4)
+    learned_res = None
+    if not args.no_learned and not args.no_compare:
+        learned_res = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=20)
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
@@ -283,6 +371,7 @@ def main():
         iters_per_step=dict(mean=round(float(it.mean()), 3), min=int(it.min()), max=int(it.max())),
         fft_pairs_per_iter=fft_pairs,
         roofline=roof, kernels=kernels, launch=cfg, cpu_baseline=cpu, batched=batched,
+        learned=learned_res,
     )
     if cpu:
         out["gpu_over_cpu"] = round(value / cpu["value"], 2)
