@@ -129,6 +129,7 @@ def gpu_run(w, steps, warmup, kernel_timing):
         timing = ctx.time_kernels(w.dt, reps)
         timing["reps"] = reps
     cfg = ctx.launch_config()
+    cfg["plan"] = ctx.plan(0)
     ctx.close()
     return elapsed, iters, timing, cfg
 

@@ -214,6 +214,21 @@ void pfch_fno_destroy(pfch_fno* f);
  * use and must not be used on another stream while the context steps. */
 int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4]);
 
+/* Transform plan of the iteration kernels of instance `inst`'s group (all
+ * instances of one model, scheme and grid share it), as chosen by the
+ * autotuner at pfch_create (which times the candidates on the device; set
+ * PFCH_AUTOTUNE=0 in the environment to keep the defaults):
+ * out = {row alternative (-1 = default plan), row pairs per block, column
+ * alternative (-1 = default), columns per block, number of row alternatives,
+ * number of column alternatives, row radices[5], column radices[5]}. */
+int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[16]);
+
+/* Override that choice: choice = {row alternative, row pairs per block,
+ * column alternative, columns per block}, each validated against the
+ * kernel's limits (PFCH_E_INVAL otherwise).  Results of different plans
+ * agree to rounding. */
+int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[4]);
+
 void pfch_destroy(pfch_ctx* ctx);
 const char* pfch_strerror(int code);
 int pfch_version(void);

@@ -442,7 +442,9 @@ __device__ __forceinline__ void pair_forward(const double (&a)[PX::RMAX], const 
   unpack_store<PX>(z, lds, FA, ra, FB, rb, rows, t);
 }
 
-template <class PX, int MODEL>
+// MPS: implicit midpoint (the nonlinear terms are taken at
+// theta y + (1 - theta) u^n); otherwise theta = 1 and u^n is not read.
+template <class PX, int MODEL, bool MPS>
 __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restrict__ grp, int bpi,
                                                   int l) {
   extern __shared__ c2 smem[];
@@ -461,7 +463,7 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
   const int ne = I->n_eta;
   const double lam = I->lam[j % ne], lamn = I->lam[(j + 1) % ne];
   const double s = I->s, th = I->theta;
-  const bool mp = th != 1.0;
+  constexpr bool mp = MPS;
   const auto xj = gp(I->X[j % 3]);
   const auto xm = gp(I->X[(j + 2) % 3]);
   auto xn = gp(I->X[(j + 1) % 3]);

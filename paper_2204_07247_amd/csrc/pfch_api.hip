@@ -11,7 +11,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -122,12 +124,22 @@ struct Instance {
 };
 
 struct Group {
-  int model = 0, nx = 0, ny = 0;
+  int model = 0, scheme = 0, nx = 0, ny = 0;
+  // iteration kernels and their launch geometry (autotuned)
   RowK rk;
   ColK ck;
   dim3 row_block, col_block;
   int row_bpi = 0, col_bpi = 0;  // blocks per instance
   size_t row_lds = 0, col_lds = 0;
+  // step-setup kernels: always the default plan and geometry, so that the
+  // partial sums of the averaged-Newton constants do not depend on tuning
+  RowK rs;
+  ColK cs;
+  dim3 srow_block, scol_block;
+  int srow_bpi = 0, scol_bpi = 0;
+  size_t srow_lds = 0, scol_lds = 0;
+  std::vector<RowK> ralts;  // alternative iteration plans
+  std::vector<ColK> calts;
   std::vector<int> members;
   InstDev** d_members = nullptr;
   StepArgs* d_args = nullptr;
@@ -454,18 +466,18 @@ StepSetup step_setup_for(const Instance& I, double dt) {
 // (grp, args).
 int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, unsigned nm) {
   int rc;
-  int rbpi = G.row_bpi, cbpi = G.col_bpi;
+  int rbpi = G.srow_bpi, cbpi = G.scol_bpi;
   {
     void* a[] = {&grp, &args, &rbpi};
-    if ((rc = launch(G.rk.setup, dim3(nm * rbpi), G.row_block, G.row_lds, a, ctx->stream))) return rc;
+    if ((rc = launch(G.rs.setup, dim3(nm * rbpi), G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
   }
   {
     void* a[] = {&grp, &cbpi};
-    if ((rc = launch(G.ck.setup, dim3(nm * cbpi), G.col_block, G.col_lds, a, ctx->stream))) return rc;
+    if ((rc = launch(G.cs.setup, dim3(nm * cbpi), G.scol_block, G.scol_lds, a, ctx->stream))) return rc;
   }
   if (G.model == PFCH_FCH) {
     void* a[] = {&grp, &rbpi};
-    if ((rc = launch(G.rk.start_fch, dim3(nm * rbpi), G.row_block, G.row_lds, a, ctx->stream))) return rc;
+    if ((rc = launch(G.rs.start_fch, dim3(nm * rbpi), G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
   }
   return PFCH_OK;
 }
@@ -566,6 +578,168 @@ int learned_guess(pfch_ctx* ctx, Instance& I, double rho) {
   return PFCH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner: per (model, scheme, Nx, Ny), the radix schedule and launch
+// geometry of the two iteration kernels are picked by timing every candidate
+// on the group's first instance (from a zero state; the iteration kernels'
+// cost does not depend on the values).  Choices are kept for the process.
+// PFCH_AUTOTUNE=0 in the environment keeps the defaults.
+// ---------------------------------------------------------------------------
+struct TuneChoice {
+  int row_alt = -1, teams = 0;  // alt -1: default plan
+  int col_alt = -1, cb = 0;
+};
+
+std::mutex& tune_mutex() {
+  static std::mutex m;
+  return m;
+}
+std::map<std::tuple<int, int, int, int>, TuneChoice>& tune_cache() {
+  static std::map<std::tuple<int, int, int, int>, TuneChoice> c;
+  return c;
+}
+
+bool autotune_enabled() {
+  const char* e = std::getenv("PFCH_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
+
+constexpr size_t LDS_MAX = 160 * 1024;
+
+bool row_geometry_ok(const Group& G, const RowK& k, int teams) {
+  const int pairs = G.ny / 2;
+  return k.T * teams <= 256 && pairs % teams == 0 && (size_t)teams * k.lds_elems * sizeof(c2) <= LDS_MAX;
+}
+bool col_geometry_ok(const Group& G, const ColK& k, int cb) {
+  const int H = G.nx / 2;
+  return k.T * cb <= 512 && H % cb == 0 && (size_t)cb * k.lds_elems * sizeof(c2) <= LDS_MAX;
+}
+
+void apply_row(Group& G, const RowK& k, int teams) {
+  G.rk = k;
+  G.row_block = dim3(k.T * teams);
+  G.row_bpi = (G.ny / 2) / teams;
+  G.row_lds = (size_t)teams * k.lds_elems * sizeof(c2);
+  if (G.row_lds > 65536)
+    (void)hipFuncSetAttribute(k.iter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.row_lds);
+}
+void apply_col(Group& G, const ColK& k, int cb) {
+  G.ck = k;
+  G.col_block = dim3(k.T * cb);
+  G.col_bpi = (G.nx / 2) / cb;
+  G.col_lds = (size_t)cb * k.lds_elems * sizeof(c2);
+  if (G.col_lds > 65536)
+    (void)hipFuncSetAttribute(k.iter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.col_lds);
+}
+
+// Milliseconds per launch of the group's current row (which = 1) or column
+// (which = 0) iteration kernel on instance I alone.
+int time_iter_kernel(pfch_ctx* ctx, const Group& G, Instance& I, int which, hipEvent_t e0, hipEvent_t e1,
+                     float* ms) {
+  InstDev** grp = I.d_solo;
+  int bpi = which ? G.row_bpi : G.col_bpi;
+  int l0 = 0;
+  void* a[] = {&grp, &bpi, &l0};
+  const void* f = which ? G.rk.iter : G.ck.iter;
+  const dim3 blk = which ? G.row_block : G.col_block;
+  const size_t lds = which ? G.row_lds : G.col_lds;
+  constexpr int WARM = 2, REPS = 8;
+  int rc;
+  for (int r = 0; r < WARM; ++r)
+    if ((rc = launch(f, dim3(bpi), blk, lds, a, ctx->stream))) return rc;
+  HIPCHK(hipEventRecord(e0, ctx->stream));
+  for (int r = 0; r < REPS; ++r)
+    if ((rc = launch(f, dim3(bpi), blk, lds, a, ctx->stream))) return rc;
+  HIPCHK(hipEventRecord(e1, ctx->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, e0, e1));
+  *ms = t / REPS;
+  return PFCH_OK;
+}
+
+void apply_choice(Group& G, const TuneChoice& c) {
+  apply_row(G, c.row_alt < 0 ? G.rs : G.ralts[c.row_alt], c.teams);
+  apply_col(G, c.col_alt < 0 ? G.cs : G.calts[c.col_alt], c.cb);
+}
+
+int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
+  *used_instance = false;
+  const auto key = std::make_tuple(G.model, G.scheme, G.nx, G.ny);
+  std::lock_guard<std::mutex> lock(tune_mutex());
+  auto& cache = tune_cache();
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    apply_choice(G, it->second);
+    return PFCH_OK;
+  }
+  TuneChoice def;
+  def.teams = (int)(G.row_block.x / G.rk.T);
+  def.cb = (int)(G.col_block.x / G.ck.T);
+  if (!autotune_enabled() || (G.ralts.empty() && G.calts.empty())) {
+    cache[key] = def;
+    return PFCH_OK;
+  }
+  Instance& I = ctx->inst[G.members[0]];
+  *used_instance = true;
+  const size_t bytes = sizeof(double) * (size_t)I.npts;
+  HIPCHK(hipMemsetAsync(I.U[0], 0, bytes, ctx->stream));
+  HIPCHK(hipMemsetAsync(I.U[1], 0, bytes, ctx->stream));
+  I.has_prev = false;
+  int rc;
+  if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, 1e-3)))) return rc;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  TuneChoice best = def;
+  float t_def_row = 0.f, t_def_col = 0.f;
+  // rows
+  {
+    apply_row(G, G.rs, def.teams);
+    if ((rc = time_iter_kernel(ctx, G, I, 1, e0, e1, &t_def_row))) return rc;
+    float t_best = t_def_row;
+    for (int alt = -1; alt < (int)G.ralts.size(); ++alt) {
+      const RowK& k = alt < 0 ? G.rs : G.ralts[alt];
+      for (int teams = 1; teams <= 64; teams *= 2) {
+        if (!row_geometry_ok(G, k, teams) || (alt < 0 && teams == def.teams)) continue;
+        apply_row(G, k, teams);
+        float t = 0.f;
+        if ((rc = time_iter_kernel(ctx, G, I, 1, e0, e1, &t))) return rc;
+        if (t < 0.97f * t_def_row && t < t_best) {
+          t_best = t;
+          best.row_alt = alt;
+          best.teams = teams;
+        }
+      }
+    }
+  }
+  // columns
+  {
+    apply_col(G, G.cs, def.cb);
+    if ((rc = time_iter_kernel(ctx, G, I, 0, e0, e1, &t_def_col))) return rc;
+    float t_best = t_def_col;
+    for (int alt = -1; alt < (int)G.calts.size(); ++alt) {
+      const ColK& k = alt < 0 ? G.cs : G.calts[alt];
+      for (int cb = 1; cb <= 4; cb *= 2) {
+        if (!col_geometry_ok(G, k, cb) || (alt < 0 && cb == def.cb)) continue;
+        apply_col(G, k, cb);
+        float t = 0.f;
+        if ((rc = time_iter_kernel(ctx, G, I, 0, e0, e1, &t))) return rc;
+        if (t < 0.97f * t_def_col && t < t_best) {
+          t_best = t;
+          best.col_alt = alt;
+          best.cb = cb;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  apply_choice(G, best);
+  cache[key] = best;
+  return PFCH_OK;
+}
+
 int fft_pairs_of(const Instance& I, int iters) {
   // Transform pairs of real fields (one forward + one inverse 2D transform
   // of a real field counts as one pair).  Per iteration: PFC 2 forward + 1
@@ -653,7 +827,7 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   int rc = PFCH_OK;
   void* p = nullptr;
   // --- groups by (model, Nx, Ny)
-  std::map<std::tuple<int, int, int>, int> gidx;
+  std::map<std::tuple<int, int, int, int>, int> gidx;
   for (int i = 0; i < n_inst; ++i) {
     Instance& I = ctx->inst[i];
     I.d = descs[i];
@@ -662,16 +836,35 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
     I.nh = I.nx / 2;
     I.rows = I.ny;
     I.npts = (int64_t)I.nx * I.ny;
-    auto key = std::make_tuple(I.d.model, I.nx, I.ny);
+    auto key = std::make_tuple(I.d.model, I.d.scheme, I.nx, I.ny);
     auto it = gidx.find(key);
     if (it == gidx.end()) {
       Group G;
       G.model = I.d.model;
+      G.scheme = I.d.scheme;
       G.nx = I.nx;
       G.ny = I.ny;
-      const bool ok = G.model == PFCH_PFC
-                          ? row_kernels<MODEL_PFC>(I.nx, G.rk) && col_kernels<MODEL_PFC>(I.ny, G.ck)
-                          : row_kernels<MODEL_FCH>(I.nx, G.rk) && col_kernels<MODEL_FCH>(I.ny, G.ck);
+      const bool mps = I.d.scheme == PFCH_MP;
+      bool ok;
+      if (G.model == PFCH_PFC) {
+        ok = (mps ? row_kernels<MODEL_PFC, true>(I.nx, G.rs) : row_kernels<MODEL_PFC, false>(I.nx, G.rs)) &&
+             col_kernels<MODEL_PFC>(I.ny, G.cs);
+        if (mps)
+          row_alternatives<MODEL_PFC, true>(I.nx, G.ralts);
+        else
+          row_alternatives<MODEL_PFC, false>(I.nx, G.ralts);
+        col_alternatives<MODEL_PFC>(I.ny, G.calts);
+      } else {
+        ok = (mps ? row_kernels<MODEL_FCH, true>(I.nx, G.rs) : row_kernels<MODEL_FCH, false>(I.nx, G.rs)) &&
+             col_kernels<MODEL_FCH>(I.ny, G.cs);
+        if (mps)
+          row_alternatives<MODEL_FCH, true>(I.nx, G.ralts);
+        else
+          row_alternatives<MODEL_FCH, false>(I.nx, G.ralts);
+        col_alternatives<MODEL_FCH>(I.ny, G.calts);
+      }
+      G.rk = G.rs;
+      G.ck = G.cs;
       if (!ok) {
         delete ctx;
         return PFCH_E_UNSUPPORTED;
@@ -685,14 +878,14 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   for (auto& G : ctx->groups) {
     const int nm = (int)G.members.size();
     const int pairs = G.ny / 2, H = G.nx / 2;
-    const int teams = pick_teams(G.rk.T, pairs);
-    G.row_block = dim3(G.rk.T * teams);
-    G.row_bpi = pairs / teams;
-    G.row_lds = (size_t)teams * G.rk.lds_elems * sizeof(c2);
-    const int cb = pick_cols(G.ck.T, H);
-    G.col_block = dim3(G.ck.T * cb);
-    G.col_bpi = H / cb;
-    G.col_lds = (size_t)cb * G.ck.lds_elems * sizeof(c2);
+    const int teams = pick_teams(G.rs.T, pairs);
+    G.srow_block = G.row_block = dim3(G.rs.T * teams);
+    G.srow_bpi = G.row_bpi = pairs / teams;
+    G.srow_lds = G.row_lds = (size_t)teams * G.rs.lds_elems * sizeof(c2);
+    const int cb = pick_cols(G.cs.T, H);
+    G.scol_block = G.col_block = dim3(G.cs.T * cb);
+    G.scol_bpi = G.col_bpi = H / cb;
+    G.scol_lds = G.col_lds = (size_t)cb * G.cs.lds_elems * sizeof(c2);
     if (G.row_lds > 160 * 1024 || G.col_lds > 160 * 1024) {
       rc = PFCH_E_UNSUPPORTED;
       goto fail;
@@ -703,11 +896,11 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
     G.d_args = (StepArgs*)p;
     if ((rc = halloc(ctx->host_allocs, &p, sizeof(StepArgs) * nm))) goto fail;
     G.h_args = (StepArgs*)p;
-    const void* fs[] = {G.rk.iter, G.rk.setup, G.rk.start_fch};
+    const void* fs[] = {G.rs.iter, G.rs.setup, G.rs.start_fch};
     for (const void* f : fs)
       if (f && G.row_lds > 65536)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.row_lds);
-    const void* gs[] = {G.ck.iter, G.ck.setup};
+    const void* gs[] = {G.cs.iter, G.cs.setup};
     for (const void* f : gs)
       if (f && G.col_lds > 65536)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.col_lds);
@@ -735,7 +928,7 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
     std::vector<double> scale(n_inst);
     for (int i = 0; i < n_inst; ++i) {
       Instance& I = ctx->inst[i];
-      if ((rc = setup_instance(ctx, I, ctx->groups[I.group].row_bpi))) goto fail;
+      if ((rc = setup_instance(ctx, I, ctx->groups[I.group].srow_bpi))) goto fail;
       I.h.rec = ctx->d_recs + i;
       if (hipMemcpy(I.dev, &I.h, sizeof(InstDev), hipMemcpyHostToDevice) != hipSuccess) {
         rc = PFCH_E_HIP;
@@ -768,6 +961,27 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
     }
     if (hipMemcpy(ctx->d_recs, recs.data(), sizeof(StopRec) * n_inst, hipMemcpyHostToDevice) !=
         hipSuccess) {
+      rc = PFCH_E_HIP;
+      goto fail;
+    }
+    // autotune the iteration kernels, then return the instances it used to
+    // the state of a fresh context (no iteration pending)
+    bool any = false;
+    for (auto& G : ctx->groups) {
+      bool used = false;
+      if ((rc = tune_group(ctx, G, &used))) goto fail;
+      if (used) {
+        Instance& I = ctx->inst[G.members[0]];
+        int32_t park = I.d.max_iter + 1;
+        if (hipMemcpy(I.h.iter_base, &park, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+          rc = PFCH_E_HIP;
+          goto fail;
+        }
+        any = true;
+      }
+    }
+    if (any && hipMemcpy(ctx->d_recs, recs.data(), sizeof(StopRec) * n_inst, hipMemcpyHostToDevice) !=
+                   hipSuccess) {
       rc = PFCH_E_HIP;
       goto fail;
     }
@@ -830,6 +1044,51 @@ int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]) {
   out[3] = nm * G.col_bpi;
   out[4] = G.col_block.x;
   out[5] = (int64_t)G.col_lds;
+  return PFCH_OK;
+}
+
+int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[16]) {
+  if (!ctx || !out || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
+  const Group& G = ctx->groups[ctx->inst[inst].group];
+  int row_alt = -1, col_alt = -1;
+  for (int k = 0; k < (int)G.ralts.size(); ++k)
+    if (G.ralts[k].iter == G.rk.iter) row_alt = k;
+  for (int k = 0; k < (int)G.calts.size(); ++k)
+    if (G.calts[k].iter == G.ck.iter) col_alt = k;
+  out[0] = row_alt;
+  out[1] = (int32_t)(G.row_block.x / G.rk.T);
+  out[2] = col_alt;
+  out[3] = (int32_t)(G.col_block.x / G.ck.T);
+  out[4] = (int32_t)G.ralts.size();
+  out[5] = (int32_t)G.calts.size();
+  for (int p = 0; p < 5; ++p) {
+    out[6 + p] = G.rk.radix[p];
+    out[11 + p] = G.ck.radix[p];
+  }
+  return PFCH_OK;
+}
+
+int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[4]) {
+  if (!ctx || !choice || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
+  Group& G = ctx->groups[ctx->inst[inst].group];
+  TuneChoice c;
+  c.row_alt = choice[0];
+  c.teams = choice[1];
+  c.col_alt = choice[2];
+  c.cb = choice[3];
+  if (c.row_alt < -1 || c.row_alt >= (int)G.ralts.size() || c.col_alt < -1 || c.col_alt >= (int)G.calts.size())
+    return PFCH_E_INVAL;
+  const RowK& rk = c.row_alt < 0 ? G.rs : G.ralts[c.row_alt];
+  const ColK& ck = c.col_alt < 0 ? G.cs : G.calts[c.col_alt];
+  if (c.teams < 1 || (c.teams & (c.teams - 1)) || !row_geometry_ok(G, rk, c.teams)) return PFCH_E_INVAL;
+  if (c.cb != 1 && c.cb != 2 && c.cb != 4) return PFCH_E_INVAL;
+  if (!col_geometry_ok(G, ck, c.cb)) return PFCH_E_INVAL;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto g : ctx->graph_defs) (void)hipGraphDestroy(g);
+  ctx->graphs.clear();
+  ctx->graph_defs.clear();
+  apply_choice(G, c);
   return PFCH_OK;
 }
 

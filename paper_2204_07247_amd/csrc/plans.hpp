@@ -1,6 +1,8 @@
 // Transform plans (radix schedule per length) and the kernel instantiations
 // the host dispatches to, per model and length.
 #pragma once
+#include <vector>
+
 #include "kernels2d.hpp"
 
 namespace pfch {
@@ -14,22 +16,40 @@ struct RowK {
   const void* start_fch = nullptr;
   int T = 0;
   int lds_elems = 0;  // per team
+  int radix[5] = {1, 1, 1, 1, 1};
 };
 struct ColK {
   const void* iter = nullptr;
   const void* setup = nullptr;
   int T = 0;
   int lds_elems = 0;  // per column
+  int radix[5] = {1, 1, 1, 1, 1};
 };
 
-template <class P, int MODEL>
+template <class P>
+void plan_radices(int* r) {
+  for (int p = 0; p < 5; ++p) r[p] = p < P::NPASS ? P::radix(p) : 1;
+}
+
+template <class P, int MODEL, bool MPS>
 RowK make_row() {
   RowK k;
-  k.iter = (const void*)&k_row_iter<P, MODEL>;
+  k.iter = (const void*)&k_row_iter<P, MODEL, MPS>;
   k.setup = (const void*)&k_row_setup<P, MODEL>;
   if (MODEL == MODEL_FCH) k.start_fch = (const void*)&k_row_start_fch<P>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
+  plan_radices<P>(k.radix);
+  return k;
+}
+// Iteration kernel only (setup kernels come from the default plan).
+template <class P, int MODEL, bool MPS>
+RowK make_row_iter() {
+  RowK k;
+  k.iter = (const void*)&k_row_iter<P, MODEL, MPS>;
+  k.T = P::T;
+  k.lds_elems = lds_len(P::N);
+  plan_radices<P>(k.radix);
   return k;
 }
 template <class P, int MODEL>
@@ -39,9 +59,22 @@ ColK make_col() {
   k.setup = (const void*)&k_col_setup<P, MODEL>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
+  plan_radices<P>(k.radix);
+  return k;
+}
+template <class P, int MODEL>
+ColK make_col_iter() {
+  ColK k;
+  k.iter = (const void*)&k_col_iter<P, MODEL>;
+  k.T = P::T;
+  k.lds_elems = lds_len(P::N);
+  plan_radices<P>(k.radix);
   return k;
 }
 
+// Default radix schedule per length (radix 8 first, one smaller radix last):
+// used by the step-setup kernels always and by the iteration kernels unless
+// the autotuner picks an alternative.
 using P8 = Plan<8, 8>;
 using P16 = Plan<16, 8, 2>;
 using P32 = Plan<32, 8, 4>;
@@ -52,18 +85,18 @@ using P512 = Plan<512, 8, 8, 8>;
 using P1024 = Plan<1024, 8, 8, 4, 4>;
 using P2048 = Plan<2048, 8, 8, 8, 4>;
 
-template <int MODEL>
+template <int MODEL, bool MPS>
 bool row_kernels(int n, RowK& k) {
   switch (n) {
-    case 8: k = make_row<P8, MODEL>(); return true;
-    case 16: k = make_row<P16, MODEL>(); return true;
-    case 32: k = make_row<P32, MODEL>(); return true;
-    case 64: k = make_row<P64, MODEL>(); return true;
-    case 128: k = make_row<P128, MODEL>(); return true;
-    case 256: k = make_row<P256, MODEL>(); return true;
-    case 512: k = make_row<P512, MODEL>(); return true;
-    case 1024: k = make_row<P1024, MODEL>(); return true;
-    case 2048: k = make_row<P2048, MODEL>(); return true;
+    case 8: k = make_row<P8, MODEL, MPS>(); return true;
+    case 16: k = make_row<P16, MODEL, MPS>(); return true;
+    case 32: k = make_row<P32, MODEL, MPS>(); return true;
+    case 64: k = make_row<P64, MODEL, MPS>(); return true;
+    case 128: k = make_row<P128, MODEL, MPS>(); return true;
+    case 256: k = make_row<P256, MODEL, MPS>(); return true;
+    case 512: k = make_row<P512, MODEL, MPS>(); return true;
+    case 1024: k = make_row<P1024, MODEL, MPS>(); return true;
+    case 2048: k = make_row<P2048, MODEL, MPS>(); return true;
     default: return false;
   }
 }
@@ -81,6 +114,38 @@ bool col_kernels(int n, ColK& k) {
     case 2048: k = make_col<P2048, MODEL>(); return true;
     default: return false;
   }
+}
+
+// Alternative radix schedules the autotuner may pick for the iteration
+// kernels: radix 4 (fewer registers per thread, more threads and passes) and
+// radix 16 (fewer passes through LDS, more registers).
+using A64a = Plan<64, 4, 4, 4>;
+using A64b = Plan<64, 16, 4>;
+using A128a = Plan<128, 4, 4, 4, 2>;
+using A128b = Plan<128, 16, 8>;
+using A256a = Plan<256, 4, 4, 4, 4>;
+using A256b = Plan<256, 16, 16>;
+using A512a = Plan<512, 16, 16, 2>;
+using A1024a = Plan<1024, 16, 16, 4>;
+using A1024b = Plan<1024, 4, 4, 4, 4, 4>;
+using A2048a = Plan<2048, 16, 16, 8>;
+#define PFCH_ALT_PLANS(X)                                                                          \
+  X(64, A64a) X(64, A64b) X(128, A128a) X(128, A128b) X(256, A256a) X(256, A256b) X(512, A512a)   \
+  X(1024, A1024a) X(1024, A1024b) X(2048, A2048a)
+
+template <int MODEL, bool MPS>
+void row_alternatives(int n, std::vector<RowK>& out) {
+#define PFCH_ROW_ALT(LEN, PLAN) \
+  if (n == LEN) out.push_back(make_row_iter<PLAN, MODEL, MPS>());
+  PFCH_ALT_PLANS(PFCH_ROW_ALT)
+#undef PFCH_ROW_ALT
+}
+template <int MODEL>
+void col_alternatives(int n, std::vector<ColK>& out) {
+#define PFCH_COL_ALT(LEN, PLAN) \
+  if (n == LEN) out.push_back(make_col_iter<PLAN, MODEL>());
+  PFCH_ALT_PLANS(PFCH_COL_ALT)
+#undef PFCH_COL_ALT
 }
 
 inline bool supported_len(int n) { return n >= 8 && n <= 2048 && (n & (n - 1)) == 0; }

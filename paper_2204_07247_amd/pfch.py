@@ -32,7 +32,7 @@ EXPORTED = (
     "pfch_strerror", "pfch_version",
     "pfch_fno_num_params", "pfch_fno_create", "pfch_fno_init_params", "pfch_fno_set_params",
     "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad", "pfch_fno_adam_step",
-    "pfch_fno_prepare", "pfch_fno_destroy", "pfch_set_fno",
+    "pfch_fno_prepare", "pfch_fno_destroy", "pfch_set_fno", "pfch_get_plan", "pfch_set_plan",
 )
 
 
@@ -115,6 +115,10 @@ def lib():
         L.pfch_fno_destroy.argtypes = [fp]
         L.pfch_fno_destroy.restype = None
         L.pfch_set_fno.argtypes = [vp, i32, fp, ctypes.POINTER(dbl)]
+        L.pfch_get_plan.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.pfch_set_plan.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.pfch_get_plan.restype = ctypes.c_int
+        L.pfch_set_plan.restype = ctypes.c_int
         for name in ("pfch_fno_create", "pfch_fno_init_params", "pfch_fno_set_params",
                      "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad",
                      "pfch_fno_adam_step", "pfch_fno_prepare", "pfch_set_fno"):
@@ -258,6 +262,23 @@ class Context:
         if rc in (PFCH_E_INVAL, PFCH_E_NOMEM, PFCH_E_HIP, PFCH_E_UNSUPPORTED):
             raise PfchError(rc, "pfch_step")
         return rc, ([s.as_dict() for s in st] if stats else None)
+
+    def plan(self, inst=0):
+        """Iteration-kernel plan of the instance's group (see pfch_get_plan)."""
+        out = (ctypes.c_int32 * 16)()
+        rc = lib().pfch_get_plan(self._h, inst, out)
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_get_plan")
+        rad = lambda v: [r for r in v if r > 1]
+        return dict(row_alt=out[0], row_teams=out[1], col_alt=out[2], col_cb=out[3],
+                    n_row_alts=out[4], n_col_alts=out[5], row_radices=rad(out[6:11]),
+                    col_radices=rad(out[11:16]))
+
+    def set_plan(self, inst, row_alt, teams, col_alt, cb):
+        ch = (ctypes.c_int32 * 4)(row_alt, teams, col_alt, cb)
+        rc = lib().pfch_set_plan(self._h, inst, ch)
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_set_plan")
 
     def set_fno(self, inst, fno, norm=None):
         """Attach an Fno (None detaches) to instance `inst` with
