@@ -34,6 +34,7 @@ WORKLOADS = {
         lengths=(1024.0, 1024.0), dt=0.2, steps=500, mean=-0.25, amp=0.05, eps=0.25),
     "fch2048": W.scaled(W.FCH256_BDF2, name="fch2d_2048_bdf2", shape=(2048, 2048), steps=300),
     "fch1024": W.scaled(W.FCH256_BDF2, name="fch2d_1024_bdf2", shape=(1024, 1024), steps=300),
+    "pfc192_3d": W.PFC192_3D,
 }
 
 
@@ -41,23 +42,31 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(w):
-    """Compulsory HBM bytes per launch of the two iteration kernels.
+KERNEL_NAMES = {"row": "k_row_iter", "col": "k_col_iter", "yfwd": "k_y3_iter<fwd>",
+                "z": "k_z3_iter", "yinv": "k_y3_iter<inv>"}
 
-    Real field: Ny*Nx doubles.  Spectral field: Ny*Nx/2 complex doubles (the
-    half spectrum's two real columns kx = 0 and kx = Nx/2 share one).
-    PFC row kernel: read 1 spectral + x_j, x_{j-1} (+ u^n for MP), write
-    x_{j+1} + 2 spectral.  PFC column kernel: read 2 spectral + g^, write 1.
-    FCH row kernel: read 2 spectral + x_j, x_{j-1}, Lx_j, Lx_{j-1} (+ u^n,
-    Lu^n for MP), write x_{j+1}, Lx_{j+1} + 3 spectral.  FCH column kernel:
-    read 3 spectral + g^, write 2 spectral.
+
+def algorithmic_bytes(w):
+    """Compulsory HBM bytes per launch of each iteration kernel.
+
+    Real field: Ny*Nx (*Nz) doubles.  Spectral field: half as many complex
+    doubles (the half spectrum's two real columns kx = 0 and kx = Nx/2 share
+    one).  PFC row kernel: read 1 spectral + x_j, x_{j-1} (+ u^n for MP),
+    write x_{j+1} + 2 spectral.  PFC column kernel: read 2 spectral + g^,
+    write 1.  FCH row kernel: read 2 spectral + x_j, x_{j-1}, Lx_j, Lx_{j-1}
+    (+ u^n, Lu^n for MP), write x_{j+1}, Lx_{j+1} + 3 spectral.  FCH column
+    kernel: read 3 spectral + g^, write 2 spectral.  3D PFC: the row kernel
+    as in 2D; y forward: read and write 2 spectral; z: read 2 spectral + g^,
+    write 1; y inverse: read and write 1 spectral.
     """
-    ny, nx = w.shape
-    real = 8 * nx * ny
-    spec = 16 * ny * (nx // 2)
+    npts = int(np.prod(w.shape))
+    real = 8 * npts
+    spec = 16 * (npts // 2)
     mp = w.scheme == "mp"
     if w.model == "pfc":
         row = spec + 2 * real + (real if mp else 0) + real + 2 * spec
+        if len(w.shape) == 3:
+            return dict(yfwd=4 * spec, z=4 * spec, yinv=2 * spec, row=row)
         col = 2 * spec + spec + spec
     else:
         row = 2 * spec + 4 * real + (2 * real if mp else 0) + 2 * real + 3 * spec
@@ -73,7 +82,7 @@ def measured_traffic(w, kernel):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    ent = rec.get(w.name, {}).get(f"k_{kernel}_iter")
+    ent = rec.get(w.name, {}).get(KERNEL_NAMES[kernel])
     if not ent or ent.get("source_sha256") != kernel_source_hash():
         return None
     return ent["traffic_bytes"]
@@ -341,13 +350,13 @@ def main():
     roof = None
     kernels = {}
     if timing:
-        for k in ("row", "col"):
+        for k in ab:
             avg = timing[f"{k}_us"] * 1e-6
             kernels[k] = dict(avg_us=round(avg * 1e6, 3), launches=timing["reps"], alg_bytes=ab[k],
                               achieved_gbs=round(ab[k] / avg / 1e9, 2))
         dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
         kd = kernels[dom]
-        roof = dict(bound="hbm", kernel=f"k_{dom}_iter", achieved=kd["achieved_gbs"],
+        roof = dict(bound="hbm", kernel=KERNEL_NAMES[dom], achieved=kd["achieved_gbs"],
                     peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4),
                     traffic=measured_traffic(w, dom))

@@ -7,7 +7,8 @@
  *
  * Conventions
  *  - All floating point is IEEE float64.  Fields are C-order real arrays
- *    [Ny][Nx] (2D) with x fastest; n[0] = Nx, n[1] = Ny.
+ *    [Ny][Nx] (2D) or [Nz][Ny][Nx] (3D) with x fastest; n[0] = Nx,
+ *    n[1] = Ny, n[2] = Nz.
  *  - Field pointers passed to pfch_set_state, pfch_get_state and pfch_solve
  *    are DEVICE pointers to contiguous arrays of Nx*Ny doubles owned by the
  *    caller.  The library never keeps a caller pointer after a call returns.
@@ -58,6 +59,10 @@ enum { PFCH_BDF2 = 0, PFCH_MP = 1 };  /* fully implicit scheme */
  * guess: 0 = extrapolated initial guess u^n + rho (u^n - u^{n-1}) (Alg. 2
  * input x_0, extrapolation as in Sec. 3.1); 1 = learned guess when a network
  * is attached with pfch_set_fno (otherwise extrapolated).  reserved must be 0.
+ * Grids: ndim = 2 with Nx, Ny powers of two in [8, 2048] or 192; ndim = 3
+ * (PFC only, extrapolated guess) with Nx as in 2D and Ny, Nz in
+ * {8, 16, 32, 64, 128, 192, 256}.  Other valid descriptors give
+ * PFCH_E_UNSUPPORTED.
  */
 typedef struct pfch_instance_desc {
   double len[3]; /* periods per axis, x first */
@@ -132,13 +137,14 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
 int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail);
 
 /* Kernel timing for measurement.  Sets up one step of instance 0 from its
- * current state (as pfch_step would, with step size dt), then launches its
- * column and row iteration kernels `reps` times each, back to back on the
- * context's stream, every launch doing the full work of an iteration, with
- * one HIP event pair around each batch.  out = {column us per launch, row us
- * per launch}.  The instance's state (u^n, u^{n-1}, t, step index) is not
- * changed; its iteration workspaces are. */
-int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[2]);
+ * current state (as pfch_step would, with step size dt), then launches each
+ * of its iteration kernels `reps` times back to back on the context's
+ * stream, every launch doing the full work of an iteration, with HIP events
+ * between the batches.  out[k] = microseconds per launch of the k-th
+ * iteration kernel in launch order: 2D {column, row, 0, 0}; 3D {y forward,
+ * z, y inverse, row}.  The instance's state (u^n, u^{n-1}, t, step index)
+ * is not changed; its iteration workspaces are. */
+int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]);
 
 /* Launch geometry of instance `inst` for reporting: {row grid, row block,
  * row LDS bytes, column grid, column block, column LDS bytes}. */

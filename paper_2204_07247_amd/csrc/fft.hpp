@@ -180,14 +180,16 @@ __device__ __forceinline__ void dft(c2* x) {
 __device__ __forceinline__ int lds_idx(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_len(int n) { return n + (n >> 4) + 1; }
 
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+constexpr int clcm(int a, int b) { return a / cgcd(a, b) * b; }
 
-// Plan: up to five passes; unused trailing radices are 1.  Every radix
-// must divide RMAX so that each thread handles whole butterflies.
+// Plan: up to five passes; unused trailing radices are 1.  Each thread holds
+// RMAX = lcm of the radices elements, so that it handles whole butterflies in
+// every pass (RMAX = 12 for mixed radix 3 and 4).
 template <int N_, int R1, int R2 = 1, int R3 = 1, int R4 = 1, int R5 = 1>
 struct Plan {
   static constexpr int N = N_;
-  static constexpr int RMAX = cmax(cmax(cmax(R1, R2), cmax(R3, R4)), R5);
+  static constexpr int RMAX = clcm(clcm(clcm(R1, R2), clcm(R3, R4)), R5);
   static constexpr int T = N / RMAX;
   static constexpr int NPASS = (R2 == 1) ? 1 : (R3 == 1) ? 2 : (R4 == 1) ? 3 : (R5 == 1) ? 4 : 5;
   static_assert(R1 * R2 * R3 * R4 * R5 == N, "radices must multiply to N");

@@ -103,7 +103,7 @@ __global__ void k_sum_parts(const double* __restrict__ part, int nb, int n, cons
 
 struct Instance {
   pfch_instance_desc d{};
-  int nx = 0, ny = 0, nh = 0, rows = 0;
+  int nx = 0, ny = 0, nz = 1, nh = 0, rows = 0;
   int64_t npts = 0;
   int group = -1;
   InstDev h{};             // host mirror of the device descriptor
@@ -140,6 +140,13 @@ struct Group {
   size_t srow_lds = 0, scol_lds = 0;
   std::vector<RowK> ralts;  // alternative iteration plans
   std::vector<ColK> calts;
+  // 3D (PFC): y- and z-pass kernels and geometry
+  int ndim = 2, nz = 1, rows = 0;
+  Y3K y3;
+  Z3K z3;
+  dim3 y3_block, z3_block;
+  int y3_bpi = 0, z3_bpi = 0;
+  size_t y3_lds = 0, z3_lds = 0;
   std::vector<int> members;
   InstDev** d_members = nullptr;
   StepArgs* d_args = nullptr;
@@ -256,7 +263,7 @@ int setup_instance(pfch_ctx* ctx, Instance& I, int nparts) {
   std::memset(&h, 0, sizeof(h));
   h.nx = I.nx;
   h.ny = I.ny;
-  h.nz = 1;
+  h.nz = I.nz;
   h.nh = I.nh;
   h.model = fch ? MODEL_FCH : MODEL_PFC;
   h.scheme = d.scheme == PFCH_MP ? SCHEME_MP : SCHEME_BDF2;
@@ -265,7 +272,7 @@ int setup_instance(pfch_ctx* ctx, Instance& I, int nparts) {
   const double two_pi = 6.283185307179586476925286766559;
   h.kx_scale = two_pi / d.len[0];
   h.ky_scale = two_pi / d.len[1];
-  h.kz_scale = 0.0;
+  h.kz_scale = I.nz > 1 ? two_pi / d.len[2] : 0.0;
   h.inv_p = 1.0 / (double)I.npts;
   h.eps = d.eps;
   h.eta1 = d.eta1;
@@ -325,6 +332,10 @@ int setup_instance(pfch_ctx* ctx, Instance& I, int nparts) {
   if ((rc = get_twiddles(ctx, I.ny, &tw))) return rc;
   h.tw_y = tw;
   h.tw_z = nullptr;
+  if (I.nz > 1) {
+    if ((rc = get_twiddles(ctx, I.nz, &tw))) return rc;
+    h.tw_z = tw;
+  }
   if ((rc = dalloc(I.allocs, &p, sizeof(InstDev)))) return rc;
   I.dev = (InstDev*)p;
   if ((rc = dalloc(I.allocs, &p, sizeof(InstDev*)))) return rc;
@@ -345,6 +356,27 @@ int launch(const void* f, dim3 g, dim3 b, size_t lds, void** args, hipStream_t s
   return PFCH_OK;
 }
 
+// The iteration kernels of a group in launch order: 2D {column, row}; 3D
+// {y forward, z, y inverse, row}.
+struct Stage {
+  const void* f;
+  int bpi;
+  dim3 block;
+  size_t lds;
+};
+int iter_stages(const Group& G, Stage* st) {
+  if (G.ndim == 3) {
+    st[0] = Stage{G.y3.fwd, G.y3_bpi, G.y3_block, G.y3_lds};
+    st[1] = Stage{G.z3.iter, G.z3_bpi, G.z3_block, G.z3_lds};
+    st[2] = Stage{G.y3.inv, G.y3_bpi, G.y3_block, G.y3_lds};
+    st[3] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds};
+    return 4;
+  }
+  st[0] = Stage{G.ck.iter, G.col_bpi, G.col_block, G.col_lds};
+  st[1] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds};
+  return 2;
+}
+
 // Build (once per chunk length) a graph running `K` iterations of every
 // group, then the chunk-end bookkeeping.
 int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
@@ -360,17 +392,19 @@ int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
   for (auto& G : ctx->groups) {
     hipGraphNode_t prev = nullptr;
     const unsigned nm = (unsigned)G.members.size();
+    Stage st[4];
+    const int ns = iter_stages(G, st);
     for (int l = 0; l < K; ++l) {
-      for (int half = 0; half < 2; ++half) {
+      for (int k = 0; k < ns; ++k) {
         hipKernelNodeParams p{};
         InstDev** grp = G.d_members;
-        int bpi = half == 0 ? G.col_bpi : G.row_bpi;
+        int bpi = st[k].bpi;
         int lv = l;
         void* args[] = {&grp, &bpi, &lv};
-        p.func = const_cast<void*>(half == 0 ? G.ck.iter : G.rk.iter);
+        p.func = const_cast<void*>(st[k].f);
         p.gridDim = dim3(nm * bpi);
-        p.blockDim = half == 0 ? G.col_block : G.row_block;
-        p.sharedMemBytes = (unsigned)(half == 0 ? G.col_lds : G.row_lds);
+        p.blockDim = st[k].block;
+        p.sharedMemBytes = (unsigned)st[k].lds;
         p.kernelParams = args;
         p.extra = nullptr;
         hipGraphNode_t node;
@@ -470,6 +504,14 @@ int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, u
   {
     void* a[] = {&grp, &args, &rbpi};
     if ((rc = launch(G.rs.setup, dim3(nm * rbpi), G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
+  }
+  if (G.ndim == 3) {
+    int ybpi = G.y3_bpi, zbpi = G.z3_bpi;
+    void* a[] = {&grp, &ybpi};
+    if ((rc = launch(G.y3.setup, dim3(nm * ybpi), G.y3_block, G.y3_lds, a, ctx->stream))) return rc;
+    void* b[] = {&grp, &zbpi};
+    if ((rc = launch(G.z3.setup, dim3(nm * zbpi), G.z3_block, G.z3_lds, b, ctx->stream))) return rc;
+    return PFCH_OK;
   }
   {
     void* a[] = {&grp, &cbpi};
@@ -594,8 +636,8 @@ std::mutex& tune_mutex() {
   static std::mutex m;
   return m;
 }
-std::map<std::tuple<int, int, int, int>, TuneChoice>& tune_cache() {
-  static std::map<std::tuple<int, int, int, int>, TuneChoice> c;
+std::map<std::tuple<int, int, int, int, int>, TuneChoice>& tune_cache() {
+  static std::map<std::tuple<int, int, int, int, int>, TuneChoice> c;
   return c;
 }
 
@@ -607,7 +649,7 @@ bool autotune_enabled() {
 constexpr size_t LDS_MAX = 160 * 1024;
 
 bool row_geometry_ok(const Group& G, const RowK& k, int teams) {
-  const int pairs = G.ny / 2;
+  const int pairs = G.rows / 2;
   return k.T * teams <= 256 && pairs % teams == 0 && (size_t)teams * k.lds_elems * sizeof(c2) <= LDS_MAX;
 }
 bool col_geometry_ok(const Group& G, const ColK& k, int cb) {
@@ -618,7 +660,7 @@ bool col_geometry_ok(const Group& G, const ColK& k, int cb) {
 void apply_row(Group& G, const RowK& k, int teams) {
   G.rk = k;
   G.row_block = dim3(k.T * teams);
-  G.row_bpi = (G.ny / 2) / teams;
+  G.row_bpi = (G.rows / 2) / teams;
   G.row_lds = (size_t)teams * k.lds_elems * sizeof(c2);
   if (G.row_lds > 65536)
     (void)hipFuncSetAttribute(k.iter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.row_lds);
@@ -665,7 +707,7 @@ void apply_choice(Group& G, const TuneChoice& c) {
 
 int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
   *used_instance = false;
-  const auto key = std::make_tuple(G.model, G.scheme, G.nx, G.ny);
+  const auto key = std::make_tuple(G.model, G.scheme, G.nx, G.ny, G.nz);
   std::lock_guard<std::mutex> lock(tune_mutex());
   auto& cache = tune_cache();
   auto it = cache.find(key);
@@ -673,6 +715,7 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
     apply_choice(G, it->second);
     return PFCH_OK;
   }
+  if (G.ndim == 3) return PFCH_OK;  // 3D: default plans, nothing to choose
   TuneChoice def;
   def.teams = (int)(G.row_block.x / G.rk.T);
   def.cb = (int)(G.col_block.x / G.ck.T);
@@ -796,7 +839,13 @@ int pfch_validate_desc(const pfch_instance_desc* d) {
     if (!(d->eta[i] >= 0.0) || !std::isfinite(d->eta[i])) return PFCH_E_INVAL;
   if (d->max_iter < 1 || d->max_iter > 1000000) return PFCH_E_INVAL;
   if (d->guess != 0 && d->guess != 1) return PFCH_E_INVAL;
-  if (d->ndim != 2) return PFCH_E_UNSUPPORTED;
+  if (d->ndim == 3) {
+    // 3D: PFC, x length as in 2D, y and z lengths of the 3D passes, rows even
+    if (d->model != PFCH_PFC || d->guess != 0) return PFCH_E_UNSUPPORTED;
+    if (!supported_len(d->n[0]) || !supported_len3(d->n[1]) || !supported_len3(d->n[2]))
+      return PFCH_E_UNSUPPORTED;
+    return PFCH_OK;
+  }
   if (!supported_len(d->n[0]) || !supported_len(d->n[1])) return PFCH_E_UNSUPPORTED;
   return PFCH_OK;
 }
@@ -826,17 +875,18 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   ctx->inst.resize(n_inst);
   int rc = PFCH_OK;
   void* p = nullptr;
-  // --- groups by (model, Nx, Ny)
-  std::map<std::tuple<int, int, int, int>, int> gidx;
+  // --- groups by (model, scheme, Nx, Ny, Nz)
+  std::map<std::tuple<int, int, int, int, int>, int> gidx;
   for (int i = 0; i < n_inst; ++i) {
     Instance& I = ctx->inst[i];
     I.d = descs[i];
     I.nx = I.d.n[0];
     I.ny = I.d.n[1];
+    I.nz = I.d.ndim == 3 ? I.d.n[2] : 1;
     I.nh = I.nx / 2;
-    I.rows = I.ny;
-    I.npts = (int64_t)I.nx * I.ny;
-    auto key = std::make_tuple(I.d.model, I.d.scheme, I.nx, I.ny);
+    I.rows = I.ny * I.nz;
+    I.npts = (int64_t)I.nx * I.ny * I.nz;
+    auto key = std::make_tuple(I.d.model, I.d.scheme, I.nx, I.ny, I.nz);
     auto it = gidx.find(key);
     if (it == gidx.end()) {
       Group G;
@@ -844,9 +894,15 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
       G.scheme = I.d.scheme;
       G.nx = I.nx;
       G.ny = I.ny;
+      G.nz = I.nz;
+      G.rows = I.rows;
+      G.ndim = I.d.ndim;
       const bool mps = I.d.scheme == PFCH_MP;
       bool ok;
-      if (G.model == PFCH_PFC) {
+      if (G.ndim == 3) {
+        ok = (mps ? row_kernels<MODEL_PFC, true>(I.nx, G.rs) : row_kernels<MODEL_PFC, false>(I.nx, G.rs)) &&
+             y3_kernels(I.ny, G.y3) && z3_kernels(I.nz, G.z3);
+      } else if (G.model == PFCH_PFC) {
         ok = (mps ? row_kernels<MODEL_PFC, true>(I.nx, G.rs) : row_kernels<MODEL_PFC, false>(I.nx, G.rs)) &&
              col_kernels<MODEL_PFC>(I.ny, G.cs);
         if (mps)
@@ -877,15 +933,42 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   }
   for (auto& G : ctx->groups) {
     const int nm = (int)G.members.size();
-    const int pairs = G.ny / 2, H = G.nx / 2;
+    const int pairs = G.rows / 2, H = G.nx / 2;
     const int teams = pick_teams(G.rs.T, pairs);
     G.srow_block = G.row_block = dim3(G.rs.T * teams);
     G.srow_bpi = G.row_bpi = pairs / teams;
     G.srow_lds = G.row_lds = (size_t)teams * G.rs.lds_elems * sizeof(c2);
-    const int cb = pick_cols(G.cs.T, H);
-    G.scol_block = G.col_block = dim3(G.cs.T * cb);
-    G.scol_bpi = G.col_bpi = H / cb;
-    G.scol_lds = G.col_lds = (size_t)cb * G.cs.lds_elems * sizeof(c2);
+    if (G.ndim == 3) {
+      // y-pass: the widest tile part (<= 512 threads); z-pass: 4 columns of
+      // a tile times kyb consecutive ky (<= 512 threads, kyb <= Ny/2)
+      int cy = 4;
+      while (cy > 1 && cy * G.y3.T > 512) cy >>= 1;
+      G.y3_block = dim3(G.y3.T * cy);
+      G.y3_bpi = G.nz * H / cy;
+      G.y3_lds = (size_t)cy * G.y3.lds_elems * sizeof(c2);
+      int kyb = 4;
+      while (kyb > 1 && (TW * kyb * G.z3.T > 512 || G.ny % kyb != 0 || 2 * kyb > G.ny)) kyb >>= 1;
+      G.z3_block = dim3(G.z3.T * TW * kyb);
+      G.z3_bpi = (H / TW) * (G.ny / kyb);
+      G.z3_lds = (size_t)TW * kyb * G.z3.lds_elems * sizeof(c2);
+      if (G.y3_lds > 160 * 1024 || G.z3_lds > 160 * 1024) {
+        rc = PFCH_E_UNSUPPORTED;
+        goto fail;
+      }
+      const void* ys[] = {G.y3.fwd, G.y3.inv, G.y3.setup};
+      for (const void* f : ys)
+        if (G.y3_lds > 65536)
+          (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.y3_lds);
+      const void* zs[] = {G.z3.iter, G.z3.setup};
+      for (const void* f : zs)
+        if (G.z3_lds > 65536)
+          (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.z3_lds);
+    } else {
+      const int cb = pick_cols(G.cs.T, H);
+      G.scol_block = G.col_block = dim3(G.cs.T * cb);
+      G.scol_bpi = G.col_bpi = H / cb;
+      G.scol_lds = G.col_lds = (size_t)cb * G.cs.lds_elems * sizeof(c2);
+    }
     if (G.row_lds > 160 * 1024 || G.col_lds > 160 * 1024) {
       rc = PFCH_E_UNSUPPORTED;
       goto fail;
@@ -999,33 +1082,34 @@ int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail) {
   return PFCH_OK;
 }
 
-int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[2]) {
+int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
   if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
   Instance& I = ctx->inst[0];
   const Group& G = ctx->groups[I.group];
   int rc;
   if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, dt)))) return rc;
-  hipEvent_t e[3];
+  Stage st[4];
+  const int ns = iter_stages(G, st);
+  hipEvent_t e[5];
   for (auto& ev : e) HIPCHK(hipEventCreate(&ev));
   InstDev** grp = I.d_solo;
   int l0 = 0;  // iteration 0 after setup: every launch does full work
-  int cbpi = G.col_bpi, rbpi = G.row_bpi;
-  void* ca[] = {&grp, &cbpi, &l0};
-  void* ra[] = {&grp, &rbpi, &l0};
   HIPCHK(hipEventRecord(e[0], ctx->stream));
-  for (int r = 0; r < reps; ++r)
-    if ((rc = launch(G.ck.iter, dim3(cbpi), G.col_block, G.col_lds, ca, ctx->stream))) return rc;
-  HIPCHK(hipEventRecord(e[1], ctx->stream));
-  for (int r = 0; r < reps; ++r)
-    if ((rc = launch(G.rk.iter, dim3(rbpi), G.row_block, G.row_lds, ra, ctx->stream))) return rc;
-  HIPCHK(hipEventRecord(e[2], ctx->stream));
-  HIPCHK(hipEventSynchronize(e[2]));
-  float t0 = 0.f, t1 = 0.f;
-  HIPCHK(hipEventElapsedTime(&t0, e[0], e[1]));
-  HIPCHK(hipEventElapsedTime(&t1, e[1], e[2]));
+  for (int k = 0; k < ns; ++k) {
+    int bpi = st[k].bpi;
+    void* a[] = {&grp, &bpi, &l0};
+    for (int r = 0; r < reps; ++r)
+      if ((rc = launch(st[k].f, dim3(bpi), st[k].block, st[k].lds, a, ctx->stream))) return rc;
+    HIPCHK(hipEventRecord(e[k + 1], ctx->stream));
+  }
+  HIPCHK(hipEventSynchronize(e[ns]));
+  for (int k = 0; k < 4; ++k) out[k] = 0.0;
+  for (int k = 0; k < ns; ++k) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e[k], e[k + 1]));
+    out[k] = 1e3 * t / reps;
+  }
   for (auto& ev : e) (void)hipEventDestroy(ev);
-  out[0] = 1e3 * t0 / reps;
-  out[1] = 1e3 * t1 / reps;
   // park the instance so later chunk launches leave it alone
   int32_t* park = (int32_t*)ctx->h_recs;  // pinned scratch, free until the next poll
   *park = I.d.max_iter + 1;
@@ -1056,9 +1140,9 @@ int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[16]) {
   for (int k = 0; k < (int)G.calts.size(); ++k)
     if (G.calts[k].iter == G.ck.iter) col_alt = k;
   out[0] = row_alt;
-  out[1] = (int32_t)(G.row_block.x / G.rk.T);
+  out[1] = G.rk.T > 0 ? (int32_t)(G.row_block.x / G.rk.T) : 0;
   out[2] = col_alt;
-  out[3] = (int32_t)(G.col_block.x / G.ck.T);
+  out[3] = G.ck.T > 0 ? (int32_t)(G.col_block.x / G.ck.T) : 0;
   out[4] = (int32_t)G.ralts.size();
   out[5] = (int32_t)G.calts.size();
   for (int p = 0; p < 5; ++p) {
@@ -1071,6 +1155,7 @@ int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[16]) {
 int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[4]) {
   if (!ctx || !choice || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
   Group& G = ctx->groups[ctx->inst[inst].group];
+  if (G.ndim == 3) return PFCH_E_UNSUPPORTED;
   TuneChoice c;
   c.row_alt = choice[0];
   c.teams = choice[1];
@@ -1500,7 +1585,7 @@ int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4])
   }
   if (!norm || !(norm[1] > 0.0) || !(norm[2] > 0.0) || !(norm[3] > 0.0) || !std::isfinite(norm[0]))
     return PFCH_E_INVAL;
-  if (f->f.ny != I.ny || f->f.nx != I.nx) return PFCH_E_INVAL;
+  if (f->f.ny != I.ny || f->f.nx != I.nx || I.nz != 1) return PFCH_E_INVAL;
   int rc;
   if (!I.xguess) {
     void* q = nullptr;

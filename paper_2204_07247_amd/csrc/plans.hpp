@@ -4,6 +4,7 @@
 #include <vector>
 
 #include "kernels2d.hpp"
+#include "kernels3d.hpp"
 
 namespace pfch {
 
@@ -84,6 +85,7 @@ using P256 = Plan<256, 8, 8, 4>;
 using P512 = Plan<512, 8, 8, 8>;
 using P1024 = Plan<1024, 8, 8, 4, 4>;
 using P2048 = Plan<2048, 8, 8, 8, 4>;
+using P192 = Plan<192, 3, 4, 4, 4>;  // 12 elements per thread
 
 template <int MODEL, bool MPS>
 bool row_kernels(int n, RowK& k) {
@@ -97,6 +99,7 @@ bool row_kernels(int n, RowK& k) {
     case 512: k = make_row<P512, MODEL, MPS>(); return true;
     case 1024: k = make_row<P1024, MODEL, MPS>(); return true;
     case 2048: k = make_row<P2048, MODEL, MPS>(); return true;
+    case 192: k = make_row<P192, MODEL, MPS>(); return true;
     default: return false;
   }
 }
@@ -112,6 +115,7 @@ bool col_kernels(int n, ColK& k) {
     case 512: k = make_col<P512, MODEL>(); return true;
     case 1024: k = make_col<P1024, MODEL>(); return true;
     case 2048: k = make_col<P2048, MODEL>(); return true;
+    case 192: k = make_col<P192, MODEL>(); return true;
     default: return false;
   }
 }
@@ -148,6 +152,66 @@ void col_alternatives(int n, std::vector<ColK>& out) {
 #undef PFCH_COL_ALT
 }
 
-inline bool supported_len(int n) { return n >= 8 && n <= 2048 && (n & (n - 1)) == 0; }
+// Three-dimensional PFC: kernels of the y- and z-passes per length.
+struct Y3K {
+  const void* fwd = nullptr;
+  const void* inv = nullptr;
+  const void* setup = nullptr;
+  int T = 0;
+  int lds_elems = 0;
+};
+struct Z3K {
+  const void* iter = nullptr;
+  const void* setup = nullptr;
+  int T = 0;
+  int lds_elems = 0;
+};
+template <class P>
+Y3K make_y3() {
+  Y3K k;
+  k.fwd = (const void*)&k_y3_iter<P, false>;
+  k.inv = (const void*)&k_y3_iter<P, true>;
+  k.setup = (const void*)&k_y3_setup<P>;
+  k.T = P::T;
+  k.lds_elems = lds_len(P::N);
+  return k;
+}
+template <class P>
+Z3K make_z3() {
+  Z3K k;
+  k.iter = (const void*)&k_z3_iter<P>;
+  k.setup = (const void*)&k_z3_setup<P>;
+  k.T = P::T;
+  k.lds_elems = lds_len(P::N);
+  return k;
+}
+// y and z lengths of the 3D path
+inline bool supported_len3(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 192 || n == 256; }
+inline bool y3_kernels(int n, Y3K& k) {
+  switch (n) {
+    case 8: k = make_y3<P8>(); return true;
+    case 16: k = make_y3<P16>(); return true;
+    case 32: k = make_y3<P32>(); return true;
+    case 64: k = make_y3<P64>(); return true;
+    case 128: k = make_y3<P128>(); return true;
+    case 192: k = make_y3<P192>(); return true;
+    case 256: k = make_y3<P256>(); return true;
+    default: return false;
+  }
+}
+inline bool z3_kernels(int n, Z3K& k) {
+  switch (n) {
+    case 8: k = make_z3<P8>(); return true;
+    case 16: k = make_z3<P16>(); return true;
+    case 32: k = make_z3<P32>(); return true;
+    case 64: k = make_z3<P64>(); return true;
+    case 128: k = make_z3<P128>(); return true;
+    case 192: k = make_z3<P192>(); return true;
+    case 256: k = make_z3<P256>(); return true;
+    default: return false;
+  }
+}
+
+inline bool supported_len(int n) { return (n >= 8 && n <= 2048 && (n & (n - 1)) == 0) || n == 192; }
 
 }  // namespace pfch

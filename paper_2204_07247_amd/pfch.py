@@ -220,13 +220,16 @@ class Context:
             raise PfchError(rc, "pfch_set_stats_detail")
 
     def time_kernels(self, dt, reps):
-        """Average microseconds per launch of instance 0's column and row
-        iteration kernels (HIP events around `reps` back-to-back launches)."""
-        out = (ctypes.c_double * 2)()
+        """Average microseconds per launch of instance 0's iteration kernels
+        (HIP events around `reps` back-to-back launches of each): 2D
+        {col_us, row_us}; 3D {yfwd_us, z_us, yinv_us, row_us}."""
+        out = (ctypes.c_double * 4)()
         rc = lib().pfch_time_kernels(self._h, float(dt), int(reps), out)
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_time_kernels")
-        return dict(col_us=out[0], row_us=out[1])
+        if out[2] == 0.0 and out[3] == 0.0:
+            return dict(col_us=out[0], row_us=out[1])
+        return dict(yfwd_us=out[0], z_us=out[1], yinv_us=out[2], row_us=out[3])
 
     def launch_config(self, inst=0):
         out = (ctypes.c_int64 * 6)()

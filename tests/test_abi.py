@@ -53,7 +53,11 @@ def _desc(**kw):
     (dict(shape=(2048, 8), lengths=(1.0, 1.0)), 0),
     (dict(shape=(64, 100)), -7),
     (dict(shape=(4096, 64)), -7),
-    (dict(shape=(8, 8, 8), lengths=(1.0, 1.0, 1.0)), -7),
+    (dict(shape=(8, 8, 8), lengths=(1.0, 1.0, 1.0)), 0),            # 3D PFC
+    (dict(shape=(8, 24, 8), lengths=(1.0, 1.0, 1.0)), -7),          # y length not supported
+    (dict(model="fch", shape=(8, 8, 8), lengths=(1.0, 1.0, 1.0), eps=0.1), -7),  # 3D FCH
+    (dict(shape=(64, 192), lengths=(64.0, 192.0)), 0),              # mixed radix 2D
+    (dict(shape=(64, 96), lengths=(64.0, 96.0)), -7),
     (dict(s=0.0), -1),
     (dict(tol=-1.0), -1),
     (dict(max_iter=0), -1),

@@ -1,0 +1,88 @@
+"""Three-dimensional PFC on the GPU against the oracle.
+
+Small grids put each transform length (including the mixed-radix 192) on
+each axis; every case runs a short trajectory and must match the oracle's
+iteration counts and, to the parity bar, its fields.  The full 192^3 grid
+is checked through properties that hold at any size (convergence, mass)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests._common import desc_for, oracle_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # (Nz, Ny, Nx)
+    (8, 8, 8),
+    (16, 8, 32),
+    (8, 32, 16),
+    (32, 16, 8),
+    (192, 8, 16),
+    (8, 192, 16),
+    (8, 8, 192),
+]
+
+
+def _w(shape, scheme):
+    return dataclasses.replace(W.PFC64_MP, name="pfc3d", shape=shape,
+                               lengths=tuple(float(n) for n in shape), scheme=scheme, seeds=(7,))
+
+
+def _run(w, nsteps):
+    import torch
+    from paper_2204_07247_amd import pfch
+    ctx = pfch.Context([desc_for(w)])
+    u = torch.from_numpy(W.initial_condition(w)).cuda()
+    ctx.set_state(0, u)
+    iters = []
+    for _ in range(nsteps):
+        rc, st = ctx.step(w.dt)
+        assert rc == pfch.PFCH_OK, (rc, st)
+        iters.append(st[0]["iters"])
+    out = torch.empty_like(u)
+    ctx.get_state(0, out)
+    ctx.close()
+    return out.cpu().numpy(), iters, st[0]
+
+
+@pytest.mark.parametrize("scheme", ["bdf2", "mp"])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_3d_trajectory_matches_oracle(shape, scheme):
+    w = _w(shape, scheme)
+    print(f"3d {shape} {scheme}", flush=True)
+    got, iters, _ = _run(w, 3)
+    ref, ref_iters = oracle_run(w, W.initial_condition(w), 3)
+    assert iters == ref_iters
+    assert rel_l2(got, ref) <= 1e-9
+
+
+def test_2d_mixed_radix_192_matches_oracle():
+    w = dataclasses.replace(W.PFC64_MP, shape=(192, 192), lengths=(192.0, 192.0), seeds=(8,))
+    got, iters, _ = _run(w, 3)
+    ref, ref_iters = oracle_run(w, W.initial_condition(w), 3)
+    assert iters == ref_iters
+    assert rel_l2(got, ref) <= 1e-9
+
+
+def test_3d_full_size_step_converges_and_keeps_mass():
+    """192^3, the bench configuration: two steps (backward Euler, then
+    BDF2) converge to the tolerance and keep the mean exactly."""
+    w = W.PFC192_3D
+    print("3d full size 192^3", flush=True)
+    u0 = W.initial_condition(w)
+    got, iters, st = _run(w, 2)
+    assert st["dnorm"] < w.tol
+    assert abs(got.mean() - u0.mean()) <= 1e-14
+    assert np.all(np.isfinite(got))
+
+
+def test_3d_unsupported_shapes_are_rejected_on_host():
+    from paper_2204_07247_amd import pfch
+    d = desc_for(_w((8, 8, 8), "bdf2"))
+    assert pfch.validate_desc(d) == pfch.PFCH_OK
+    d2 = desc_for(_w((24, 8, 8), "bdf2"))
+    assert pfch.validate_desc(d2) == pfch.PFCH_E_UNSUPPORTED
+    fw = dataclasses.replace(W.FCH256_BDF2, shape=(8, 8, 8), lengths=(1.0, 1.0, 1.0))
+    assert pfch.validate_desc(desc_for(fw)) == pfch.PFCH_E_UNSUPPORTED

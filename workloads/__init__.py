@@ -99,3 +99,11 @@ def pfc_ensemble(count=64, steps=200, base_seed=1000, sizes=(128, 256, 512)):
 
 def scaled(w: Workload, **changes):
     return replace(w, **changes)
+
+
+# PFC 3D, 192^3 on [0, 192)^3, eps = 0.25, phi0 = -0.2 + 0.05 U(-1, 1),
+# BDF2 (backward Euler first), dt = 0.1, 300 steps.
+PFC192_3D = Workload(
+    name="pfc3d_192_bdf2", model="pfc", scheme="bdf2", shape=(192, 192, 192),
+    lengths=(192.0, 192.0, 192.0), dt=0.1, steps=300, mean=-0.2, amp=0.05, eps=0.25,
+    seeds=(0,))
