@@ -220,20 +220,25 @@ void pfch_fno_destroy(pfch_fno* f);
  * use and must not be used on another stream while the context steps. */
 int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4]);
 
-/* Transform plan of the iteration kernels of instance `inst`'s group (all
- * instances of one model, scheme and grid share it), as chosen by the
- * autotuner at pfch_create (which times the candidates on the device; set
- * PFCH_AUTOTUNE=0 in the environment to keep the defaults):
- * out = {row alternative (-1 = default plan), row pairs per block, column
- * alternative (-1 = default), columns per block, number of row alternatives,
- * number of column alternatives, row radices[5], column radices[5]}. */
-int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[16]);
+/* Transform plans and launch geometry of the iteration kernels of instance
+ * `inst`'s group (all instances of one model, scheme and grid share them),
+ * as chosen by the autotuner at pfch_create, which times the candidates on
+ * the device and keeps the choice for the process (set PFCH_AUTOTUNE=0 in
+ * the environment to keep the defaults).  out[36]:
+ *   0 row plan alternative (-1 = default), 1 row pairs per block,
+ *   2 column plan alternative (2D), 3 columns per block (2D),
+ *   4 y-pass plan alternative (3D), 5 y-pass columns per block (3D),
+ *   6 z-pass plan alternative (3D), 7 z-pass ky per block (3D),
+ *   8..11 numbers of row, column, y and z alternatives,
+ *   12..19 row radices, 20..27 column (2D) or y-pass (3D) radices,
+ *   28..35 z-pass radices (unused passes have radix 1). */
+int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[36]);
 
-/* Override that choice: choice = {row alternative, row pairs per block,
- * column alternative, columns per block}, each validated against the
- * kernel's limits (PFCH_E_INVAL otherwise).  Results of different plans
+/* Override that choice: choice = out[0..7] of pfch_get_plan (entries that do
+ * not apply to the grid's dimension are ignored), each validated against the
+ * kernels' limits (PFCH_E_INVAL otherwise).  Results of different plans
  * agree to rounding. */
-int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[4]);
+int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[8]);
 
 void pfch_destroy(pfch_ctx* ctx);
 const char* pfch_strerror(int code);

@@ -21,6 +21,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 namespace pfch {
 
 // Device pointers kept in memory are generic; kernels cast them to the
@@ -183,25 +185,28 @@ __host__ __device__ constexpr int lds_len(int n) { return n + (n >> 4) + 1; }
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 constexpr int clcm(int a, int b) { return a / cgcd(a, b) * b; }
 
-// Plan: up to five passes; unused trailing radices are 1.  Each thread holds
-// RMAX = lcm of the radices elements, so that it handles whole butterflies in
-// every pass (RMAX = 12 for mixed radix 3 and 4).
-template <int N_, int R1, int R2 = 1, int R3 = 1, int R4 = 1, int R5 = 1>
+// Plan: the radices of the passes, first to last.  Each thread holds
+// RMAX = lcm of the radices elements, so that it handles whole butterflies
+// in every pass (RMAX = 12 for mixed radix 3 and 4).
+template <int N_, int... Rs>
 struct Plan {
   static constexpr int N = N_;
-  static constexpr int RMAX = clcm(clcm(clcm(R1, R2), clcm(R3, R4)), R5);
+  static constexpr int NPASS = sizeof...(Rs);
+  static constexpr int RS[NPASS] = {Rs...};
+  static constexpr int RMAX = [] {
+    int l = 1;
+    for (int r : RS) l = clcm(l, r);
+    return l;
+  }();
   static constexpr int T = N / RMAX;
-  static constexpr int NPASS = (R2 == 1) ? 1 : (R3 == 1) ? 2 : (R4 == 1) ? 3 : (R5 == 1) ? 4 : 5;
-  static_assert(R1 * R2 * R3 * R4 * R5 == N, "radices must multiply to N");
-  static_assert(RMAX % R1 == 0 && RMAX % R2 == 0 && RMAX % R3 == 0 && RMAX % R4 == 0 &&
-                    RMAX % R5 == 0,
-                "every radix must divide RMAX");
-  static constexpr int radix(int p) {
-    return p == 0 ? R1 : p == 1 ? R2 : p == 2 ? R3 : p == 3 ? R4 : R5;
-  }
+  static constexpr int radix(int p) { return RS[p]; }
   static constexpr int ns(int p) {
-    return p == 0 ? 1 : p == 1 ? R1 : p == 2 ? R1 * R2 : p == 3 ? R1 * R2 * R3 : R1 * R2 * R3 * R4;
+    int s = 1;
+    for (int i = 0; i < p; ++i) s *= RS[i];
+    return s;
   }
+  static_assert(NPASS >= 1 && NPASS <= 8, "one to eight passes");
+  static_assert(ns(NPASS) == N, "radices must multiply to N");
 };
 
 // Per-thread twiddles w1 = w_N^{(j mod Ns) * N/(Ns*R)} of every butterfly
@@ -291,6 +296,13 @@ __device__ __forceinline__ double opaque_d(double v) {
   return v;
 }
 
+// Passes 1 .. NPASS-2, LDS to LDS.
+template <class P, bool INV, int... I>
+__device__ __forceinline__ void mid_passes(c2 (&v)[P::RMAX], c2* lds, const Twiddles<P>& tw, int t,
+                                           std::integer_sequence<int, I...>) {
+  ((stockham_pass<P, I + 1, INV, false, false>(v, lds, tw, t), __syncthreads()), ...);
+}
+
 // Full transform: registers in, registers out.  Every thread of the block
 // must call this (it contains block-wide barriers when NPASS > 1).
 template <class P, bool INV>
@@ -310,18 +322,7 @@ __device__ __forceinline__ void fft(c2 (&v)[P::RMAX], c2* lds, const Twiddles<P>
   } else {
     stockham_pass<P, 0, INV, true, false>(v, lds, tw, t);
     __syncthreads();
-    if constexpr (P::NPASS >= 3) {
-      stockham_pass<P, 1, INV, false, false>(v, lds, tw, t);
-      __syncthreads();
-    }
-    if constexpr (P::NPASS >= 4) {
-      stockham_pass<P, 2, INV, false, false>(v, lds, tw, t);
-      __syncthreads();
-    }
-    if constexpr (P::NPASS >= 5) {
-      stockham_pass<P, 3, INV, false, false>(v, lds, tw, t);
-      __syncthreads();
-    }
+    mid_passes<P, INV>(v, lds, tw, t, std::make_integer_sequence<int, P::NPASS - 2>{});
     stockham_pass<P, P::NPASS - 1, INV, false, true>(v, lds, tw, t);
     __syncthreads();  // LDS free for reuse on return
   }

@@ -227,7 +227,10 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
     return f == 1 ? inv_m * aot + q * (e1 - 2.0 * q + q * q) : q;
   };
 
-  c2 v[RM], nxt[RM], acc[RM];
+  // With up to 8 elements per thread the next field is loaded before the
+  // transform of the current one; with more, after it (registers).
+  constexpr bool PREFETCH = RM <= 8;
+  c2 v[RM], nxt[PREFETCH ? RM : 1], acc[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
     v[m] = gload(S + at(m));
@@ -235,8 +238,10 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
   }
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
+    if constexpr (PREFETCH) {
 #pragma unroll
-    for (int m = 0; m < RM; ++m) nxt[m] = f == 0 ? gload(S + fs + at(m)) : gload(gp(I->ghat) + at(m));
+      for (int m = 0; m < RM; ++m) nxt[m] = f == 0 ? gload(S + fs + at(m)) : gload(gp(I->ghat) + at(m));
+    }
     fft<PZ, false>(v, lds, tw, t);
 #pragma unroll
     for (int m = 0; m < RM; ++m) {
@@ -250,7 +255,12 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
         acc[m] = cadd(acc[m], cscale(w, 0.5 * (coef(f, q) - coef(f, q + kxn2))));
       });
 #pragma unroll
-    for (int m = 0; m < RM; ++m) v[m] = nxt[m];
+    for (int m = 0; m < RM; ++m) {
+      if constexpr (PREFETCH)
+        v[m] = nxt[m];
+      else
+        v[m] = f == 0 ? gload(S + fs + at(m)) : gload(gp(I->ghat) + at(m));
+    }
   }
 #pragma unroll
   for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(v[m], inv_m));

@@ -142,8 +142,10 @@ struct Group {
   std::vector<ColK> calts;
   // 3D (PFC): y- and z-pass kernels and geometry
   int ndim = 2, nz = 1, rows = 0;
-  Y3K y3;
-  Z3K z3;
+  Y3K y3, y3d;  // current and default plan
+  Z3K z3, z3d;
+  std::vector<Y3K> y3alts;
+  std::vector<Z3K> z3alts;
   dim3 y3_block, z3_block;
   int y3_bpi = 0, z3_bpi = 0;
   size_t y3_lds = 0, z3_lds = 0;
@@ -630,6 +632,8 @@ int learned_guess(pfch_ctx* ctx, Instance& I, double rho) {
 struct TuneChoice {
   int row_alt = -1, teams = 0;  // alt -1: default plan
   int col_alt = -1, cb = 0;
+  int cy = 0, kyb = 0;          // 3D: y-pass columns per block, z-pass ky per block
+  int y3_alt = -1, z3_alt = -1;  // 3D: y- and z-pass plans
 };
 
 std::mutex& tune_mutex() {
@@ -700,13 +704,143 @@ int time_iter_kernel(pfch_ctx* ctx, const Group& G, Instance& I, int which, hipE
   return PFCH_OK;
 }
 
+bool y3_geometry_ok(const Group& G, const Y3K& k, int cy) {
+  return (cy == 1 || cy == 2 || cy == 4) && cy * k.T <= 512 && (size_t)cy * k.lds_elems * sizeof(c2) <= LDS_MAX;
+}
+bool z3_geometry_ok(const Group& G, const Z3K& k, int kyb) {
+  return kyb >= 1 && (kyb & (kyb - 1)) == 0 && TW * kyb * k.T <= 512 && G.ny % kyb == 0 &&
+         2 * kyb <= G.ny && (size_t)TW * kyb * k.lds_elems * sizeof(c2) <= LDS_MAX;
+}
+void apply_y3(Group& G, const Y3K& k, int cy) {
+  G.y3 = k;
+  G.y3_block = dim3(G.y3.T * cy);
+  G.y3_bpi = G.nz * (G.nx / 2) / cy;
+  G.y3_lds = (size_t)cy * G.y3.lds_elems * sizeof(c2);
+  const void* fs[] = {G.y3.fwd, G.y3.inv, G.y3.setup};
+  for (const void* f : fs)
+    if (G.y3_lds > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.y3_lds);
+}
+void apply_z3(Group& G, const Z3K& k, int kyb) {
+  G.z3 = k;
+  G.z3_block = dim3(G.z3.T * TW * kyb);
+  G.z3_bpi = (G.nx / 2 / TW) * (G.ny / kyb);
+  G.z3_lds = (size_t)TW * kyb * G.z3.lds_elems * sizeof(c2);
+  const void* fs[] = {G.z3.iter, G.z3.setup};
+  for (const void* f : fs)
+    if (G.z3_lds > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.z3_lds);
+}
+
 void apply_choice(Group& G, const TuneChoice& c) {
   apply_row(G, c.row_alt < 0 ? G.rs : G.ralts[c.row_alt], c.teams);
-  apply_col(G, c.col_alt < 0 ? G.cs : G.calts[c.col_alt], c.cb);
+  if (G.ndim == 3) {
+    apply_y3(G, c.y3_alt < 0 ? G.y3d : G.y3alts[c.y3_alt], c.cy);
+    apply_z3(G, c.z3_alt < 0 ? G.z3d : G.z3alts[c.z3_alt], c.kyb);
+  } else {
+    apply_col(G, c.col_alt < 0 ? G.cs : G.calts[c.col_alt], c.cb);
+  }
+}
+
+// Milliseconds per launch of one iteration stage on instance I alone.
+int time_stage(pfch_ctx* ctx, Instance& I, const Stage& st, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  InstDev** grp = I.d_solo;
+  int bpi = st.bpi;
+  int l0 = 0;
+  void* a[] = {&grp, &bpi, &l0};
+  constexpr int WARM = 2, REPS = 8;
+  int rc;
+  for (int r = 0; r < WARM; ++r)
+    if ((rc = launch(st.f, dim3(bpi), st.block, st.lds, a, ctx->stream))) return rc;
+  HIPCHK(hipEventRecord(e0, ctx->stream));
+  for (int r = 0; r < REPS; ++r)
+    if ((rc = launch(st.f, dim3(bpi), st.block, st.lds, a, ctx->stream))) return rc;
+  HIPCHK(hipEventRecord(e1, ctx->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, e0, e1));
+  *ms = t / REPS;
+  return PFCH_OK;
+}
+
+// 3D groups: rows per block of the x-pass, columns per block of the
+// y-passes (both timed on the forward pass) and ky per block of the z-pass.
+int tune_group3(pfch_ctx* ctx, Group& G, TuneChoice& best) {
+  Instance& I = ctx->inst[G.members[0]];
+  const size_t bytes = sizeof(double) * (size_t)I.npts;
+  HIPCHK(hipMemsetAsync(I.U[0], 0, bytes, ctx->stream));
+  HIPCHK(hipMemsetAsync(I.U[1], 0, bytes, ctx->stream));
+  I.has_prev = false;
+  int rc;
+  if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, 1e-3)))) return rc;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  Stage st[4];
+  float t_def = 0.f, t = 0.f;
+  // x-pass
+  iter_stages(G, st);
+  if ((rc = time_stage(ctx, I, st[3], e0, e1, &t_def))) return rc;
+  float t_best = t_def;
+  for (int alt = -1; alt < (int)G.ralts.size(); ++alt) {
+    const RowK& k = alt < 0 ? G.rs : G.ralts[alt];
+    for (int teams = 1; teams <= 64; teams *= 2) {
+      if (!row_geometry_ok(G, k, teams) || (alt < 0 && teams == best.teams)) continue;
+      apply_row(G, k, teams);
+      iter_stages(G, st);
+      if ((rc = time_stage(ctx, I, st[3], e0, e1, &t))) return rc;
+      if (t < 0.97f * t_def && t < t_best) {
+        t_best = t;
+        best.row_alt = alt;
+        best.teams = teams;
+      }
+    }
+  }
+  apply_row(G, best.row_alt < 0 ? G.rs : G.ralts[best.row_alt], best.teams);
+  // y-passes (timed on the forward pass)
+  iter_stages(G, st);
+  if ((rc = time_stage(ctx, I, st[0], e0, e1, &t_def))) return rc;
+  t_best = t_def;
+  for (int alt = -1; alt < (int)G.y3alts.size(); ++alt) {
+    const Y3K& k = alt < 0 ? G.y3d : G.y3alts[alt];
+    for (int cy = 1; cy <= 4; cy *= 2) {
+      if (!y3_geometry_ok(G, k, cy) || (alt < 0 && cy == best.cy)) continue;
+      apply_y3(G, k, cy);
+      iter_stages(G, st);
+      if ((rc = time_stage(ctx, I, st[0], e0, e1, &t))) return rc;
+      if (t < 0.97f * t_def && t < t_best) {
+        t_best = t;
+        best.y3_alt = alt;
+        best.cy = cy;
+      }
+    }
+  }
+  apply_y3(G, best.y3_alt < 0 ? G.y3d : G.y3alts[best.y3_alt], best.cy);
+  // z-pass
+  iter_stages(G, st);
+  if ((rc = time_stage(ctx, I, st[1], e0, e1, &t_def))) return rc;
+  t_best = t_def;
+  for (int alt = -1; alt < (int)G.z3alts.size(); ++alt) {
+    const Z3K& k = alt < 0 ? G.z3d : G.z3alts[alt];
+    for (int kyb = 1; kyb <= 32; kyb *= 2) {
+      if (!z3_geometry_ok(G, k, kyb) || (alt < 0 && kyb == best.kyb)) continue;
+      apply_z3(G, k, kyb);
+      iter_stages(G, st);
+      if ((rc = time_stage(ctx, I, st[1], e0, e1, &t))) return rc;
+      if (t < 0.97f * t_def && t < t_best) {
+        t_best = t;
+        best.z3_alt = alt;
+        best.kyb = kyb;
+      }
+    }
+  }
+  apply_z3(G, best.z3_alt < 0 ? G.z3d : G.z3alts[best.z3_alt], best.kyb);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return PFCH_OK;
 }
 
 int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
   *used_instance = false;
+  if (!autotune_enabled()) return PFCH_OK;  // defaults as set up
   const auto key = std::make_tuple(G.model, G.scheme, G.nx, G.ny, G.nz);
   std::lock_guard<std::mutex> lock(tune_mutex());
   auto& cache = tune_cache();
@@ -715,11 +849,21 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
     apply_choice(G, it->second);
     return PFCH_OK;
   }
-  if (G.ndim == 3) return PFCH_OK;  // 3D: default plans, nothing to choose
+  if (G.ndim == 3) {
+    TuneChoice c;
+    c.teams = (int)(G.row_block.x / G.rk.T);
+    c.cy = (int)(G.y3_block.x / G.y3.T);
+    c.kyb = (int)(G.z3_block.x / (G.z3.T * TW));
+    *used_instance = true;
+    int rc;
+    if ((rc = tune_group3(ctx, G, c))) return rc;
+    cache[key] = c;
+    return PFCH_OK;
+  }
   TuneChoice def;
   def.teams = (int)(G.row_block.x / G.rk.T);
   def.cb = (int)(G.col_block.x / G.ck.T);
-  if (!autotune_enabled() || (G.ralts.empty() && G.calts.empty())) {
+  if (G.ralts.empty() && G.calts.empty()) {
     cache[key] = def;
     return PFCH_OK;
   }
@@ -901,7 +1045,15 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
       bool ok;
       if (G.ndim == 3) {
         ok = (mps ? row_kernels<MODEL_PFC, true>(I.nx, G.rs) : row_kernels<MODEL_PFC, false>(I.nx, G.rs)) &&
-             y3_kernels(I.ny, G.y3) && z3_kernels(I.nz, G.z3);
+             y3_kernels(I.ny, G.y3d) && z3_kernels(I.nz, G.z3d);
+        G.y3 = G.y3d;
+        G.z3 = G.z3d;
+        if (mps)
+          row_alternatives<MODEL_PFC, true>(I.nx, G.ralts);
+        else
+          row_alternatives<MODEL_PFC, false>(I.nx, G.ralts);
+        y3_alternatives(I.ny, G.y3alts);
+        z3_alternatives(I.nz, G.z3alts);
       } else if (G.model == PFCH_PFC) {
         ok = (mps ? row_kernels<MODEL_PFC, true>(I.nx, G.rs) : row_kernels<MODEL_PFC, false>(I.nx, G.rs)) &&
              col_kernels<MODEL_PFC>(I.ny, G.cs);
@@ -1131,43 +1283,67 @@ int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]) {
   return PFCH_OK;
 }
 
-int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[16]) {
+int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[36]) {
   if (!ctx || !out || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
   const Group& G = ctx->groups[ctx->inst[inst].group];
-  int row_alt = -1, col_alt = -1;
-  for (int k = 0; k < (int)G.ralts.size(); ++k)
-    if (G.ralts[k].iter == G.rk.iter) row_alt = k;
-  for (int k = 0; k < (int)G.calts.size(); ++k)
-    if (G.calts[k].iter == G.ck.iter) col_alt = k;
-  out[0] = row_alt;
+  auto find = [](const auto& alts, const void* f, auto get) {
+    for (int k = 0; k < (int)alts.size(); ++k)
+      if (get(alts[k]) == f) return k;
+    return -1;
+  };
+  for (int k = 0; k < 36; ++k) out[k] = 0;
+  out[0] = find(G.ralts, G.rk.iter, [](const RowK& k) { return k.iter; });
   out[1] = G.rk.T > 0 ? (int32_t)(G.row_block.x / G.rk.T) : 0;
-  out[2] = col_alt;
-  out[3] = G.ck.T > 0 ? (int32_t)(G.col_block.x / G.ck.T) : 0;
-  out[4] = (int32_t)G.ralts.size();
-  out[5] = (int32_t)G.calts.size();
-  for (int p = 0; p < 5; ++p) {
-    out[6 + p] = G.rk.radix[p];
-    out[11 + p] = G.ck.radix[p];
+  out[8] = (int32_t)G.ralts.size();
+  for (int p = 0; p < 8; ++p) out[12 + p] = G.rk.radix[p];
+  if (G.ndim == 3) {
+    out[2] = -1;
+    out[4] = find(G.y3alts, G.y3.fwd, [](const Y3K& k) { return k.fwd; });
+    out[5] = (int32_t)(G.y3_block.x / G.y3.T);
+    out[6] = find(G.z3alts, G.z3.iter, [](const Z3K& k) { return k.iter; });
+    out[7] = (int32_t)(G.z3_block.x / (G.z3.T * TW));
+    out[10] = (int32_t)G.y3alts.size();
+    out[11] = (int32_t)G.z3alts.size();
+    for (int p = 0; p < 8; ++p) {
+      out[20 + p] = G.y3.radix[p];
+      out[28 + p] = G.z3.radix[p];
+    }
+  } else {
+    out[2] = find(G.calts, G.ck.iter, [](const ColK& k) { return k.iter; });
+    out[3] = (int32_t)(G.col_block.x / G.ck.T);
+    out[4] = out[6] = -1;
+    out[9] = (int32_t)G.calts.size();
+    for (int p = 0; p < 8; ++p) out[20 + p] = G.ck.radix[p];
   }
   return PFCH_OK;
 }
 
-int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[4]) {
+int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[8]) {
   if (!ctx || !choice || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
   Group& G = ctx->groups[ctx->inst[inst].group];
-  if (G.ndim == 3) return PFCH_E_UNSUPPORTED;
   TuneChoice c;
   c.row_alt = choice[0];
   c.teams = choice[1];
   c.col_alt = choice[2];
   c.cb = choice[3];
-  if (c.row_alt < -1 || c.row_alt >= (int)G.ralts.size() || c.col_alt < -1 || c.col_alt >= (int)G.calts.size())
-    return PFCH_E_INVAL;
+  c.y3_alt = choice[4];
+  c.cy = choice[5];
+  c.z3_alt = choice[6];
+  c.kyb = choice[7];
+  if (c.row_alt < -1 || c.row_alt >= (int)G.ralts.size()) return PFCH_E_INVAL;
   const RowK& rk = c.row_alt < 0 ? G.rs : G.ralts[c.row_alt];
-  const ColK& ck = c.col_alt < 0 ? G.cs : G.calts[c.col_alt];
   if (c.teams < 1 || (c.teams & (c.teams - 1)) || !row_geometry_ok(G, rk, c.teams)) return PFCH_E_INVAL;
-  if (c.cb != 1 && c.cb != 2 && c.cb != 4) return PFCH_E_INVAL;
-  if (!col_geometry_ok(G, ck, c.cb)) return PFCH_E_INVAL;
+  if (G.ndim == 3) {
+    if (c.y3_alt < -1 || c.y3_alt >= (int)G.y3alts.size() || c.z3_alt < -1 || c.z3_alt >= (int)G.z3alts.size())
+      return PFCH_E_INVAL;
+    if (!y3_geometry_ok(G, c.y3_alt < 0 ? G.y3d : G.y3alts[c.y3_alt], c.cy)) return PFCH_E_INVAL;
+    if (!z3_geometry_ok(G, c.z3_alt < 0 ? G.z3d : G.z3alts[c.z3_alt], c.kyb)) return PFCH_E_INVAL;
+  } else {
+    if (c.col_alt < -1 || c.col_alt >= (int)G.calts.size()) return PFCH_E_INVAL;
+    const ColK& ck = c.col_alt < 0 ? G.cs : G.calts[c.col_alt];
+    if (c.cb != 1 && c.cb != 2 && c.cb != 4) return PFCH_E_INVAL;
+    if (!col_geometry_ok(G, ck, c.cb)) return PFCH_E_INVAL;
+  }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
   for (auto g : ctx->graph_defs) (void)hipGraphDestroy(g);

@@ -17,19 +17,19 @@ struct RowK {
   const void* start_fch = nullptr;
   int T = 0;
   int lds_elems = 0;  // per team
-  int radix[5] = {1, 1, 1, 1, 1};
+  int radix[8] = {1, 1, 1, 1, 1, 1, 1, 1};
 };
 struct ColK {
   const void* iter = nullptr;
   const void* setup = nullptr;
   int T = 0;
   int lds_elems = 0;  // per column
-  int radix[5] = {1, 1, 1, 1, 1};
+  int radix[8] = {1, 1, 1, 1, 1, 1, 1, 1};
 };
 
 template <class P>
 void plan_radices(int* r) {
-  for (int p = 0; p < 5; ++p) r[p] = p < P::NPASS ? P::radix(p) : 1;
+  for (int p = 0; p < 8; ++p) r[p] = p < P::NPASS ? P::radix(p) : 1;
 }
 
 template <class P, int MODEL, bool MPS>
@@ -133,9 +133,10 @@ using A512a = Plan<512, 16, 16, 2>;
 using A1024a = Plan<1024, 16, 16, 4>;
 using A1024b = Plan<1024, 4, 4, 4, 4, 4>;
 using A2048a = Plan<2048, 16, 16, 8>;
+using A192a = Plan<192, 3, 2, 2, 2, 2, 2, 2>;  // 6 elements per thread
 #define PFCH_ALT_PLANS(X)                                                                          \
   X(64, A64a) X(64, A64b) X(128, A128a) X(128, A128b) X(256, A256a) X(256, A256b) X(512, A512a)   \
-  X(1024, A1024a) X(1024, A1024b) X(2048, A2048a)
+  X(1024, A1024a) X(1024, A1024b) X(2048, A2048a) X(192, A192a)
 
 template <int MODEL, bool MPS>
 void row_alternatives(int n, std::vector<RowK>& out) {
@@ -159,12 +160,14 @@ struct Y3K {
   const void* setup = nullptr;
   int T = 0;
   int lds_elems = 0;
+  int radix[8] = {1, 1, 1, 1, 1, 1, 1, 1};
 };
 struct Z3K {
   const void* iter = nullptr;
   const void* setup = nullptr;
   int T = 0;
   int lds_elems = 0;
+  int radix[8] = {1, 1, 1, 1, 1, 1, 1, 1};
 };
 template <class P>
 Y3K make_y3() {
@@ -174,6 +177,7 @@ Y3K make_y3() {
   k.setup = (const void*)&k_y3_setup<P>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
+  plan_radices<P>(k.radix);
   return k;
 }
 template <class P>
@@ -183,10 +187,17 @@ Z3K make_z3() {
   k.setup = (const void*)&k_z3_setup<P>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
+  plan_radices<P>(k.radix);
   return k;
 }
 // y and z lengths of the 3D path
 inline bool supported_len3(int n) { return n == 8 || n == 16 || n == 32 || n == 64 || n == 128 || n == 192 || n == 256; }
+inline void y3_alternatives(int n, std::vector<Y3K>& out) {
+  if (n == 192) out.push_back(make_y3<A192a>());
+}
+inline void z3_alternatives(int n, std::vector<Z3K>& out) {
+  if (n == 192) out.push_back(make_z3<A192a>());
+}
 inline bool y3_kernels(int n, Y3K& k) {
   switch (n) {
     case 8: k = make_y3<P8>(); return true;

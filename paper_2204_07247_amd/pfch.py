@@ -267,18 +267,21 @@ class Context:
         return rc, ([s.as_dict() for s in st] if stats else None)
 
     def plan(self, inst=0):
-        """Iteration-kernel plan of the instance's group (see pfch_get_plan)."""
-        out = (ctypes.c_int32 * 16)()
+        """Iteration-kernel plans of the instance's group (see pfch_get_plan)."""
+        out = (ctypes.c_int32 * 36)()
         rc = lib().pfch_get_plan(self._h, inst, out)
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_get_plan")
         rad = lambda v: [r for r in v if r > 1]
         return dict(row_alt=out[0], row_teams=out[1], col_alt=out[2], col_cb=out[3],
-                    n_row_alts=out[4], n_col_alts=out[5], row_radices=rad(out[6:11]),
-                    col_radices=rad(out[11:16]))
+                    y_alt=out[4], y_cb=out[5], z_alt=out[6], z_kyb=out[7],
+                    n_row_alts=out[8], n_col_alts=out[9], n_y_alts=out[10], n_z_alts=out[11],
+                    row_radices=rad(out[12:20]), col_radices=rad(out[20:28]),
+                    z_radices=rad(out[28:36]))
 
-    def set_plan(self, inst, row_alt, teams, col_alt, cb):
-        ch = (ctypes.c_int32 * 4)(row_alt, teams, col_alt, cb)
+    def set_plan(self, inst, row_alt, teams, col_alt=-1, cb=1, y_alt=-1, y_cb=1, z_alt=-1,
+                 z_kyb=1):
+        ch = (ctypes.c_int32 * 8)(row_alt, teams, col_alt, cb, y_alt, y_cb, z_alt, z_kyb)
         rc = lib().pfch_set_plan(self._h, inst, ch)
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_set_plan")
