@@ -41,7 +41,7 @@ enum {
 };
 
 enum { PFCH_PFC = 0, PFCH_FCH = 1 };  /* model */
-enum { PFCH_BDF2 = 0, PFCH_MP = 1 };  /* fully implicit scheme */
+enum { PFCH_BDF2 = 0, PFCH_MP = 1, PFCH_LBDF2 = 2, PFCH_LMP = 3 };  /* time scheme */
 
 /*
  * One simulation instance.  Model (Sec. 2 of the paper):
@@ -51,9 +51,17 @@ enum { PFCH_BDF2 = 0, PFCH_MP = 1 };  /* fully implicit scheme */
  * with d_t u = M Delta mu, M = mobility.  eta1 and eta2 are the
  * coefficients as they stand in the energy (e.g. 1.45 eps and 2 eps).
  * Scheme (Sec. 3.1): PFCH_BDF2 (variable-step BDF2, backward Euler on the
- * first step) or PFCH_MP (implicit midpoint).
- * Solver (Alg. 2): step size s, friction sweep eta[0..n_eta-1], stop when
- * ||d_i||_inf < tol, at most max_iter iterations.  theta_l weights the
+ * first step) or PFCH_MP (implicit midpoint), each solved by PAGD; or the
+ * linear IMEX schemes PFCH_LBDF2 / PFCH_LMP (eq. eqn:FCH-semidis-simplicit
+ * with the paper's splitting of the chemical potential: PFC
+ * L = (1 + Delta)^2; FCH L = eps^4 Delta^2 - kappa2 Delta + kappa0,
+ * kappa0 = 1 - 2 tau^2 + eta2, kappa2 = 1), one linear k-space solve per
+ * step; for these s, eta, tol, theta_l and max_iter are not used, guess
+ * must be 0 and the statistics report one iteration.
+ * Solver (Alg. 2): step size s, friction sweep eta[0..n_eta-1] (one entry:
+ * constant friction; n_eta = 0: no momentum, the preconditioned gradient
+ * descent of Alg. 1), stop when ||d_i||_inf < tol, at most max_iter
+ * iterations.  theta_l weights the
  * beta_0/beta_2/beta_4 part of the averaged-Newton preconditioner
  * (Sec. 3.4.1); 1.0 is the operator as printed.
  * guess: 0 = extrapolated initial guess u^n + rho (u^n - u^{n-1}) (Alg. 2

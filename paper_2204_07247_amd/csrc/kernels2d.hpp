@@ -204,6 +204,11 @@ __device__ __forceinline__ void betas(const InstDev* I, double& bm2, double& b0,
 }
 
 __device__ __forceinline__ void finish_betas(InstDev* I) {
+  if (I->imex) {
+    I->beta0 = I->imex_b0;
+    I->beta2 = I->imex_b2;
+    return;
+  }
   double s0 = 0.0, s1 = 0.0;
   for (int i = 0; i < I->nparts; ++i) {
     s0 += I->part[2 * i];

@@ -26,6 +26,10 @@ using namespace pfch;
 
 namespace {
 
+// Implicit-midpoint family (u_breve blends u^n) and the linear IMEX schemes.
+inline bool scheme_mp(int s) { return s == PFCH_MP || s == PFCH_LMP; }
+inline bool scheme_imex(int s) { return s == PFCH_LBDF2 || s == PFCH_LMP; }
+
 // ---------------------------------------------------------------------------
 // Small kernels: end of a chunk of iterations, accept, mass reduction.
 // ---------------------------------------------------------------------------
@@ -268,7 +272,7 @@ int setup_instance(pfch_ctx* ctx, Instance& I, int nparts) {
   h.nz = I.nz;
   h.nh = I.nh;
   h.model = fch ? MODEL_FCH : MODEL_PFC;
-  h.scheme = d.scheme == PFCH_MP ? SCHEME_MP : SCHEME_BDF2;
+  h.scheme = scheme_mp(d.scheme) ? SCHEME_MP : SCHEME_BDF2;
   h.rows = I.rows;
   h.nparts = nparts;
   const double two_pi = 6.283185307179586476925286766559;
@@ -287,10 +291,32 @@ int setup_instance(pfch_ctx* ctx, Instance& I, int nparts) {
   const double rs = std::sqrt(d.s);
   for (int i = 0; i < 8; ++i) h.lam[i] = 0.0;
   for (int i = 0; i < d.n_eta; ++i) h.lam[i] = (1.0 - d.eta[i] * rs) / (1.0 + d.eta[i] * rs);
-  h.n_eta = d.n_eta;
+  h.n_eta = d.n_eta > 0 ? d.n_eta : 1;  // n_eta = 0: lambda = 0, plain PGD (Alg. 1)
   h.max_iter = d.max_iter;
   h.tol_bits = bits_of(d.tol);
-  h.theta = d.scheme == PFCH_MP ? 0.5 : 1.0;
+  h.theta = scheme_mp(d.scheme) ? 0.5 : 1.0;
+  if (scheme_imex(d.scheme)) {
+    // A linear IMEX step (eq. eqn:FCH-semidis-simplicit) is one iteration
+    // of the same kernels from y = u^n + rho (u^n - u^{n-1}) (LMP: the
+    // unknown's midpoint with u^n is then ((2 + rho) u^n - rho u^{n-1})/2,
+    // LBDF2: y itself), with unit step, the preconditioner replaced by the
+    // symbol of the implicit part, l(k) = beta0 + beta2 q + beta4 q^2 with
+    // weight theta, and no tolerance: d = (a/M + theta q l)^{-1} (-residual)
+    // solves the linear step exactly and u^{n+1} = y + d.
+    h.imex = 1;
+    h.s = 1.0;
+    for (int i = 0; i < 8; ++i) h.lam[i] = 0.0;
+    h.n_eta = 1;
+    h.tol_bits = INF_BITS;
+    h.theta_l = h.theta;
+    if (fch) {
+      h.imex_b0 = 1.0 - 2.0 * d.tau * d.tau + d.eta2;  // kappa0
+      h.imex_b2 = 1.0;                                  // kappa2
+    } else {
+      h.imex_b0 = 1.0;  // (1 - q)^2 = 1 - 2 q + q^2
+      h.imex_b2 = -2.0;
+    }
+  }
   h.a = 1.0;
   h.a_over_theta = 1.0;
   h.field_stride = fstride;
@@ -307,7 +333,7 @@ int setup_instance(pfch_ctx* ctx, Instance& I, int nparts) {
       h.DX[i] = (double*)p;
     }
   }
-  if (fch && d.scheme == PFCH_MP) {
+  if (fch && scheme_mp(d.scheme)) {
     if ((rc = dalloc(I.allocs, &p, rbytes))) return rc;
     h.dun = (double*)p;
   }
@@ -477,7 +503,7 @@ StepSetup step_setup_for(const Instance& I, double dt) {
   ss.un = I.U[I.ucur];
   ss.unm1 = I.has_prev ? I.U[1 - I.ucur] : I.U[I.ucur];
   ss.xin = nullptr;
-  if (I.d.scheme == PFCH_MP) {
+  if (scheme_mp(I.d.scheme)) {
     ss.a = 1.0 / dt;
     ss.b = -1.0 / dt;
     ss.c = 0.0;
@@ -589,6 +615,13 @@ int betas_host(pfch_ctx* ctx, Instance& I, double a, double out[4]) {
     s1 += part[2 * i + 1];
   }
   out[0] = a / I.d.mobility;
+  if (I.h.imex) {
+    const double e2 = I.d.eps * I.d.eps;
+    out[1] = I.h.imex_b0;
+    out[2] = I.h.imex_b2;
+    out[3] = I.d.model == PFCH_PFC ? 1.0 : e2 * e2;
+    return PFCH_OK;
+  }
   if (I.d.model == PFCH_PFC) {
     out[1] = std::fabs(s0 * I.h.inv_p);
     out[2] = -2.0;
@@ -934,7 +967,7 @@ int fft_pairs_of(const Instance& I, int iters) {
   // + u^n for the midpoint rule, FCH), plus the first iteration's forwards.
   const bool fch = I.d.model == PFCH_FCH;
   const int per_iter = fch ? 5 : 3;
-  const int setup = fch ? (I.d.scheme == PFCH_MP ? 2 * 3 + 3 : 2 * 2 + 3) : 1 + 2;
+  const int setup = fch ? (scheme_mp(I.d.scheme) ? 2 * 3 + 3 : 2 * 2 + 3) : 1 + 2;
   return (per_iter * iters + setup + 1) / 2;
 }
 
@@ -964,7 +997,7 @@ const char* pfch_strerror(int code) {
 int pfch_validate_desc(const pfch_instance_desc* d) {
   if (!d) return PFCH_E_INVAL;
   if (d->model != PFCH_PFC && d->model != PFCH_FCH) return PFCH_E_INVAL;
-  if (d->scheme != PFCH_BDF2 && d->scheme != PFCH_MP) return PFCH_E_INVAL;
+  if (d->scheme < PFCH_BDF2 || d->scheme > PFCH_LMP) return PFCH_E_INVAL;
   if (d->reserved != 0) return PFCH_E_INVAL;
   if (d->ndim != 2 && d->ndim != 3) return PFCH_E_INVAL;
   for (int a = 0; a < d->ndim; ++a) {
@@ -978,11 +1011,12 @@ int pfch_validate_desc(const pfch_instance_desc* d) {
   if (!(d->s > 0.0) || !std::isfinite(d->s)) return PFCH_E_INVAL;
   if (!(d->tol > 0.0) || !std::isfinite(d->tol)) return PFCH_E_INVAL;
   if (!(d->theta_l > 0.0) || !std::isfinite(d->theta_l)) return PFCH_E_INVAL;
-  if (d->n_eta < 1 || d->n_eta > 8) return PFCH_E_INVAL;
+  if (d->n_eta < 0 || d->n_eta > 8) return PFCH_E_INVAL;
   for (int i = 0; i < d->n_eta; ++i)
     if (!(d->eta[i] >= 0.0) || !std::isfinite(d->eta[i])) return PFCH_E_INVAL;
   if (d->max_iter < 1 || d->max_iter > 1000000) return PFCH_E_INVAL;
   if (d->guess != 0 && d->guess != 1) return PFCH_E_INVAL;
+  if (scheme_imex(d->scheme) && d->guess != 0) return PFCH_E_INVAL;  // no solve to warm-start
   if (d->ndim == 3) {
     // 3D: PFC, x length as in 2D, y and z lengths of the 3D passes, rows even
     if (d->model != PFCH_PFC || d->guess != 0) return PFCH_E_UNSUPPORTED;
@@ -1030,18 +1064,19 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
     I.nh = I.nx / 2;
     I.rows = I.ny * I.nz;
     I.npts = (int64_t)I.nx * I.ny * I.nz;
-    auto key = std::make_tuple(I.d.model, I.d.scheme, I.nx, I.ny, I.nz);
+    const int eff_scheme = scheme_mp(I.d.scheme) ? PFCH_MP : PFCH_BDF2;  // kernel variant
+    auto key = std::make_tuple(I.d.model, eff_scheme, I.nx, I.ny, I.nz);
     auto it = gidx.find(key);
     if (it == gidx.end()) {
       Group G;
       G.model = I.d.model;
-      G.scheme = I.d.scheme;
+      G.scheme = eff_scheme;
       G.nx = I.nx;
       G.ny = I.ny;
       G.nz = I.nz;
       G.rows = I.rows;
       G.ndim = I.d.ndim;
-      const bool mps = I.d.scheme == PFCH_MP;
+      const bool mps = scheme_mp(I.d.scheme);
       bool ok;
       if (G.ndim == 3) {
         ok = (mps ? row_kernels<MODEL_PFC, true>(I.nx, G.rs) : row_kernels<MODEL_PFC, false>(I.nx, G.rs)) &&
@@ -1503,7 +1538,7 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
   ss.a = a;
   ss.b = b;
   ss.c = c;
-  ss.theta = I.d.scheme == PFCH_MP ? 0.5 : 1.0;
+  ss.theta = scheme_mp(I.d.scheme) ? 0.5 : 1.0;
   ss.rho = 0.0;
   int rc;
   if ((rc = launch_setup_solo(ctx, I, ss))) return rc;

@@ -55,6 +55,10 @@ struct InstDev {
   const c2* tw_y;          // twiddles for the y length
   const c2* tw_z;          // twiddles for the z length (3D)
   int64_t field_stride;    // rows * nh
+  // linear IMEX step: the preconditioner constants are those of the
+  // implicit part of the splitting instead of the averaged-Newton means
+  int32_t imex;
+  double imex_b0, imex_b2;
 };
 
 }  // namespace pfch

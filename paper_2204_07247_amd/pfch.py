@@ -21,7 +21,7 @@ PFCH_E_PRECOND = -6
 PFCH_E_UNSUPPORTED = -7
 
 PFC, FCH = 0, 1
-BDF2, MP = 0, 1
+BDF2, MP, LBDF2, LMP = 0, 1, 2, 3
 
 PAPER_ETAS = tuple(math.sqrt(v) for v in (0.1, 0.575, 1.05, 1.525, 2.0))
 
@@ -147,10 +147,10 @@ def make_desc(model, scheme, shape, lengths, eps, eta1=0.0, eta2=0.0, tau=0.0,
         d.len[a] = float(lengths[nd - 1 - a])
     d.ndim = nd
     d.model = {"pfc": PFC, "fch": FCH}.get(model, model)
-    d.scheme = {"bdf2": BDF2, "mp": MP}.get(scheme, scheme)
+    d.scheme = {"bdf2": BDF2, "mp": MP, "lbdf2": LBDF2, "lmp": LMP}.get(scheme, scheme)
     d.eps, d.eta1, d.eta2, d.tau, d.mobility = eps, eta1, eta2, tau, mobility
     d.s, d.tol, d.theta_l = s, tol, theta_l
-    etas = tuple(etas)
+    etas = tuple(etas)  # () selects plain preconditioned gradient descent (no momentum)
     d.n_eta = len(etas)
     for i, e in enumerate(etas):
         d.eta[i] = e

@@ -61,7 +61,9 @@ def _desc(**kw):
     (dict(s=0.0), -1),
     (dict(tol=-1.0), -1),
     (dict(max_iter=0), -1),
-    (dict(etas=()), -1),
+    (dict(etas=()), 0),                       # no momentum: Alg. 1
+    (dict(scheme="lbdf2"), 0),
+    (dict(scheme=4), -1),
     (dict(lengths=(0.0, 1.0)), -1),
     (dict(model="fch", eps=0.0), -1),
     (dict(mobility=float("nan")), -1),
