@@ -208,6 +208,45 @@ def batched_comparison(count, steps, solo_steps):
                 iters_per_step_mean=round(float(np.mean(its)), 3))
 
 
+def ensemble_bandwidth(ws, steps, warmup, label):
+    """All instances in one context (grouped launches): time-steps/s of the
+    whole set and the effective bandwidth algorithmic bytes x iterations /
+    wall time (setup, accept and host polls included)."""
+    import torch
+    from paper_2204_07247_amd import pfch
+    ctx = pfch.Context([_desc(w) for w in ws])
+    ctx.set_stats_detail(0)
+    u0 = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    per_iter = [sum(algorithmic_bytes(w).values()) for w in ws]
+
+    def run(n):
+        for i, u in enumerate(u0):
+            ctx.set_state(i, u)
+        its = np.zeros(len(ws))
+        for _ in range(n):
+            rc, st = ctx.step([w.dt for w in ws])
+            if rc != pfch.PFCH_OK:
+                raise RuntimeError(f"{label} step failed: {pfch.strerror(rc)}")
+            its += [x["iters"] for x in st]
+        return its
+
+    log(f"[bench] {label}: {len(ws)} instances, {steps} steps")
+    run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.close()
+    moved = float(np.dot(per_iter, its))
+    return dict(workload=label, instances=len(ws), points=int(sum(w.npoints for w in ws)),
+                steps=steps, instance_steps_per_s=round(len(ws) * steps / el, 2),
+                ms_per_step=round(1e3 * el / steps, 3),
+                iters_per_step_mean=round(float(its.sum() / (len(ws) * steps)), 3),
+                effective_gbs=round(moved / el / 1e9, 1),
+                effective_frac=round(moved / el / 1e9 / HBM_PEAK_GBS, 4))
+
+
 def _learned_vs_plain(w, fno, norm_fn, steps):
     """Plain and learned-guess runs of `steps` steps of w from the same
     initial condition (after 2 untimed steps that build the history)."""
@@ -363,6 +402,14 @@ def main():
     batched = None
     if not args.no_compare:
         batched = batched_comparison(args.ensemble, steps=10, solo_steps=4)
+    ensembles = None
+    if not args.no_compare:
+        ensembles = [
+            ensemble_bandwidth(W.pfc_ensemble(count=64), steps=10, warmup=2,
+                               label="pfc2d_ensemble64 (128..512, MP)"),
+            ensemble_bandwidth(W.fch_ensemble() + [W.PFC192_3D], steps=5, warmup=2,
+                               label="fch2d_8x1024_8x2048_bdf2 + pfc3d_192_bdf2"),
+        ]
     learned_res = None
     if not args.no_learned and not args.no_compare:
         learned_res = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=20)
@@ -381,7 +428,7 @@ def main():
         iters_per_step=dict(mean=round(float(it.mean()), 3), min=int(it.min()), max=int(it.max())),
         fft_pairs_per_iter=fft_pairs,
         roofline=roof, kernels=kernels, launch=cfg, cpu_baseline=cpu, batched=batched,
-        learned=learned_res,
+        learned=learned_res, ensembles=ensembles,
     )
     if cpu:
         out["gpu_over_cpu"] = round(value / cpu["value"], 2)

@@ -107,3 +107,24 @@ PFC192_3D = Workload(
     name="pfc3d_192_bdf2", model="pfc", scheme="bdf2", shape=(192, 192, 192),
     lengths=(192.0, 192.0, 192.0), dt=0.1, steps=300, mean=-0.2, amp=0.05, eps=0.25,
     seeds=(0,))
+
+
+def fch_ensemble(count_per_size=8, sizes=(1024, 2048), steps=300, base_seed=2000):
+    """Large FCH ensemble: ``count_per_size`` instances per grid size (square
+    grids on [0, 4 pi)^2), e ~ U[0.08, 0.12] with eps = e, eta1 = 1.45 e,
+    eta2 = 2 e, tau = 0, mean ~ U[-0.7, -0.5], noise amplitude 0.01, BDF2
+    (backward Euler first), dt = 1e-3.  Instance i draws its parameters from
+    seed ``base_seed + i``."""
+    out = []
+    i = 0
+    for n in sizes:
+        for _ in range(count_per_size):
+            rng = np.random.default_rng(base_seed + i)
+            e = float(rng.uniform(0.08, 0.12))
+            mean = float(rng.uniform(-0.7, -0.5))
+            out.append(Workload(
+                name=f"fch2d_ens{i}_{n}", model="fch", scheme="bdf2", shape=(n, n),
+                lengths=(4 * math.pi, 4 * math.pi), dt=1e-3, steps=steps, mean=mean, amp=0.01,
+                eps=e, eta1=1.45 * e, eta2=2.0 * e, tau=0.0, seeds=(base_seed + i,)))
+            i += 1
+    return out
