@@ -232,21 +232,24 @@ int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4])
  * `inst`'s group (all instances of one model, scheme and grid share them),
  * as chosen by the autotuner at pfch_create, which times the candidates on
  * the device and keeps the choice for the process (set PFCH_AUTOTUNE=0 in
- * the environment to keep the defaults).  out[36]:
+ * the environment to keep the defaults).  out[37]:
  *   0 row plan alternative (-1 = default), 1 row pairs per block,
  *   2 column plan alternative (2D), 3 columns per block (2D),
  *   4 y-pass plan alternative (3D), 5 y-pass columns per block (3D),
  *   6 z-pass plan alternative (3D), 7 z-pass ky per block (3D),
  *   8..11 numbers of row, column, y and z alternatives,
  *   12..19 row radices, 20..27 column (2D) or y-pass (3D) radices,
- *   28..35 z-pass radices (unused passes have radix 1). */
-int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[36]);
+ *   28..35 z-pass radices (unused passes have radix 1),
+ *   36 column-kernel grid when its blocks loop over several column blocks
+ *      (0: one block per column block). */
+int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[37]);
 
-/* Override that choice: choice = out[0..7] of pfch_get_plan (entries that do
- * not apply to the grid's dimension are ignored), each validated against the
- * kernels' limits (PFCH_E_INVAL otherwise).  Results of different plans
- * agree to rounding. */
-int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[8]);
+/* Override that choice: choice = out[0..7] of pfch_get_plan plus choice[8]
+ * = 1 for looping column blocks (2D); entries that do not apply to the
+ * grid's dimension are ignored.  Each is validated against the kernels'
+ * limits (PFCH_E_INVAL otherwise).  Results of different plans agree to
+ * rounding. */
+int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]);
 
 void pfch_destroy(pfch_ctx* ctx);
 const char* pfch_strerror(int code);

@@ -282,121 +282,158 @@ __device__ __forceinline__ void col0_mirror(const c2 (&v)[P::RMAX], c2* lds0, bo
 // and d^ = 0 at k = 0.  The bracket is accumulated field by field as it
 // comes out of its y-transform.
 // ---------------------------------------------------------------------------
+//
+// Blocks loop over the items (instance, column block) b, b + gridDim.x, ...
+// of the group: launched with one block per item this is the plain kernel;
+// launched with fewer blocks, each block loads the first field of its next
+// item while it finishes the current one (inverse transforms and stores).
 template <class PY, int MODEL>
-__global__ __launch_bounds__(512) void k_col_iter(const InstDev* const* __restrict__ grp, int bpi,
-                                                  int l) {
+__global__ __launch_bounds__(512) void k_col_iter(const InstDev* const* __restrict__ grp, int bpi, int l,
+                                                  int total) {
   extern __shared__ c2 smem[];
-  const GroupPos gpos = group_pos(grp, bpi);
-  const InstDev* __restrict__ I = gpos.I;
-  const int j = *I->iter_base + l;
-  if (stopped_before(I, j)) return;
   constexpr int N = PY::N, T = PY::T, RM = PY::RMAX;
-  const int rows = N;
-  const ColPos pos = col_pos(T, I->nh / TW, gpos.lb);
-  const int t = pos.t, kp = pos.kp;
-  c2* lds = smem + pos.c * lds_len(N);
-  const bool special = kp == 0;  // this thread's column holds kx = 0 and kx = nx/2
-  const bool blk0 = gpos.lb == 0;  // the block holding physical column 0
-  const uint32_t fs = (uint32_t)I->field_stride;
-  GLB c2* S = gp(I->S);
-  Twiddles<PY> tw;
-  load_twiddles<PY>(tw, I->tw_y, t);
-
-  double bm2, b0, b2, b4;
-  betas(I, bm2, b0, b2, b4);
-  const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
-  const double inv_p = I->inv_p;
-  const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
-  const double kx2 = (kp * I->kx_scale) * (kp * I->kx_scale);
-  auto q_of = [&](int m) {  // |k|^2 of this thread's logical column (kx = 0 for column 0)
-    const int ky = t + m * T;
-    const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
-    return kx2 + a * a;
-  };
-  auto q_col0 = [&](int ky) {  // |k|^2 at kx = 0
-    const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
-    return a * a;
-  };
   constexpr int NF = MODEL == MODEL_PFC ? 2 : 3;  // transformed fields; the last is v_breve
-  const double e2 = I->eps * I->eps, e4 = e2 * e2, e2h1 = e2 * I->eta1, e1 = 1.0 - I->eps;
-  auto coef = [&](int f, double q) -> double {
-    if (f == NF - 1) {
-      const double lin = MODEL == MODEL_PFC ? e1 - 2.0 * q + q * q : e4 * q * q - e2h1 * q;
-      return inv_m * aot + q * lin;
+  const int rows = N;
+  // the next active item at or after `item` (total if none)
+  auto next_active = [&](int item) {
+    for (; item < total; item += gridDim.x) {
+      const InstDev* J = grp[item / bpi];
+      if (!stopped_before(J, *J->iter_base + l)) break;
     }
-    if (MODEL == MODEL_FCH && f == 0) return e2 * q * q;
-    return q;
+    return item;
   };
-
+  int item = next_active(blockIdx.x);
+  if (item >= total) return;
+  Twiddles<PY> tw;
+  bool have_tw = false;
   c2 v[RM], nxt[RM], acc[RM];
-#pragma unroll
-  for (int m = 0; m < RM; ++m) {
-    v[m] = gload(S + sidx(rows, t + m * T, kp));
-    acc[m] = c2{0.0, 0.0};
-  }
-#pragma unroll
-  for (int f = 0; f < NF; ++f) {
-#pragma unroll
-    for (int m = 0; m < RM; ++m)  // prefetch the next field, then g^
-      nxt[m] = f + 1 < NF ? gload(S + (f + 1) * fs + sidx(rows, t + m * T, kp))
-                          : gload(gp(I->ghat) + sidx(rows, t + m * T, kp));
-    fft<PY, false>(v, lds, tw, t);
+  bool pre = false;  // v holds the current item's field 0
+  for (; item < total;) {
+    const int gi = item / bpi, lbi = item - gi * bpi;
+    const InstDev* __restrict__ I = grp[gi];
+    const ColPos pos = col_pos(T, I->nh / TW, lbi);
+    const int t = pos.t, kp = pos.kp;
+    c2* lds = smem + pos.c * lds_len(N);
+    const bool special = kp == 0;  // this thread's column holds kx = 0 and kx = nx/2
+    const bool blk0 = lbi == 0;    // the block holding physical column 0
+    const uint32_t fs = (uint32_t)I->field_stride;
+    GLB c2* S = gp(I->S);
+    if (!have_tw) {
+      load_twiddles<PY>(tw, I->tw_y, t);
+      have_tw = true;
+    }
+
+    double bm2, b0, b2, b4;
+    betas(I, bm2, b0, b2, b4);
+    const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
+    const double inv_p = I->inv_p;
+    const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
+    const double kx2 = (kp * I->kx_scale) * (kp * I->kx_scale);
+    auto q_of = [&](int m) {  // |k|^2 of this thread's logical column (kx = 0 for column 0)
+      const int ky = t + m * T;
+      const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
+      return kx2 + a * a;
+    };
+    auto q_col0 = [&](int ky) {  // |k|^2 at kx = 0
+      const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
+      return a * a;
+    };
+    const double e2 = I->eps * I->eps, e4 = e2 * e2, e2h1 = e2 * I->eta1, e1 = 1.0 - I->eps;
+    auto coef = [&](int f, double q) -> double {
+      if (f == NF - 1) {
+        const double lin = MODEL == MODEL_PFC ? e1 - 2.0 * q + q * q : e4 * q * q - e2h1 * q;
+        return inv_m * aot + q * lin;
+      }
+      if (MODEL == MODEL_FCH && f == 0) return e2 * q * q;
+      return q;
+    };
+
 #pragma unroll
     for (int m = 0; m < RM; ++m) {
-      const double q = q_of(m);
-      const double c = special ? 0.5 * (coef(f, q) + coef(f, q + kxn2)) : coef(f, q);
-      acc[m] = cadd(acc[m], cscale(v[m], c));
+      if (!pre) v[m] = gload(S + sidx(rows, t + m * T, kp));
+      acc[m] = c2{0.0, 0.0};
     }
-    if (blk0)
-      col0_mirror<PY>(v, smem, special, t, [&](int m, c2 w) {
-        const double q = q_col0(opaque(t + m * T));
-        acc[m] = cadd(acc[m], cscale(w, 0.5 * (coef(f, q) - coef(f, q + kxn2))));
-      });
 #pragma unroll
-    for (int m = 0; m < RM; ++m) v[m] = nxt[m];
-  }
-  // g^ enters with the same coefficient 1/M on both logical columns.
+    for (int f = 0; f < NF; ++f) {
 #pragma unroll
-  for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(v[m], inv_m));
+      for (int m = 0; m < RM; ++m)  // prefetch the next field, then g^
+        nxt[m] = f + 1 < NF ? gload(S + (f + 1) * fs + sidx(rows, t + m * T, kp))
+                            : gload(gp(I->ghat) + sidx(rows, t + m * T, kp));
+      fft<PY, false>(v, lds, tw, t);
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const double q = q_of(m);
+        const double c = special ? 0.5 * (coef(f, q) + coef(f, q + kxn2)) : coef(f, q);
+        acc[m] = cadd(acc[m], cscale(v[m], c));
+      }
+      if (blk0)
+        col0_mirror<PY>(v, smem, special, t, [&](int m, c2 w) {
+          const double q = q_col0(opaque(t + m * T));
+          acc[m] = cadd(acc[m], cscale(w, 0.5 * (coef(f, q) - coef(f, q + kxn2))));
+        });
+#pragma unroll
+      for (int m = 0; m < RM; ++m) v[m] = nxt[m];
+    }
+    // g^ enters with the same coefficient 1/M on both logical columns.
+#pragma unroll
+    for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(v[m], inv_m));
 
-  // scale by -1/(P Lq), zero at k = 0
-  int bad = 0;
-  auto scale = [&](double q) -> double {
-    if (!(q > 0.0)) return 0.0;
-    const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
-    bad |= !(Lq > 0.0);
-    return -inv_p * rcp_pos(Lq);
-  };
+    // next item: its first field streams in during the inverse transforms
+    const int nitem = next_active(item + gridDim.x);
+    pre = nitem < total;
+    if (pre) {
+      const int ngi = nitem / bpi;
+      const InstDev* In = grp[ngi];
+      const ColPos np = col_pos(T, In->nh / TW, nitem - ngi * bpi);
+      const GLB c2* Sn = gp(In->S);
 #pragma unroll
-  for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], scale(q_of(m)));
-  if (blk0)
-    col0_mirror<PY>(acc, smem, special, t, [&](int m, c2 w) {
-      const double q = q_col0(opaque(t + m * T));
-      const double s0 = scale(q), sn = scale(q + kxn2);
-      v[m] = cadd(cscale(acc[m], 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn)));
-    });
-  if constexpr (MODEL == MODEL_FCH) {
-    // keep d^ for the Laplacian field: acc <- d^ (packed for column 0)
+      for (int m = 0; m < RM; ++m) nxt[m] = gload(Sn + sidx(rows, np.t + m * T, np.kp));
+    }
+
+    // scale by -1/(P Lq), zero at k = 0
+    int bad = 0;
+    auto scale = [&](double q) -> double {
+      if (!(q > 0.0)) return 0.0;
+      const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
+      bad |= !(Lq > 0.0);
+      return -inv_p * rcp_pos(Lq);
+    };
 #pragma unroll
-    for (int m = 0; m < RM; ++m) acc[m] = v[m];
-  }
-  fft<PY, true>(v, lds, tw, t);
-#pragma unroll
-  for (int m = 0; m < RM; ++m) gstore(S + sidx(rows, t + m * T, kp), v[m]);
-  if constexpr (MODEL == MODEL_FCH) {
-    // Delta d: symbol -q on each logical column
-#pragma unroll
-    for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], -q_of(m));
+    for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], scale(q_of(m)));
     if (blk0)
       col0_mirror<PY>(acc, smem, special, t, [&](int m, c2 w) {
         const double q = q_col0(opaque(t + m * T));
-        v[m] = cadd(cscale(acc[m], -(q + 0.5 * kxn2)), cscale(w, 0.5 * kxn2));
+        const double s0 = scale(q), sn = scale(q + kxn2);
+        v[m] = cadd(cscale(acc[m], 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn)));
       });
+    if constexpr (MODEL == MODEL_FCH) {
+      // keep d^ for the Laplacian field: acc <- d^ (packed for column 0)
+#pragma unroll
+      for (int m = 0; m < RM; ++m) acc[m] = v[m];
+    }
     fft<PY, true>(v, lds, tw, t);
 #pragma unroll
-    for (int m = 0; m < RM; ++m) gstore(S + fs + sidx(rows, t + m * T, kp), v[m]);
+    for (int m = 0; m < RM; ++m) gstore(S + sidx(rows, t + m * T, kp), v[m]);
+    if constexpr (MODEL == MODEL_FCH) {
+      // Delta d: symbol -q on each logical column
+#pragma unroll
+      for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], -q_of(m));
+      if (blk0)
+        col0_mirror<PY>(acc, smem, special, t, [&](int m, c2 w) {
+          const double q = q_col0(opaque(t + m * T));
+          v[m] = cadd(cscale(acc[m], -(q + 0.5 * kxn2)), cscale(w, 0.5 * kxn2));
+        });
+      fft<PY, true>(v, lds, tw, t);
+#pragma unroll
+      for (int m = 0; m < RM; ++m) gstore(S + fs + sidx(rows, t + m * T, kp), v[m]);
+    }
+    if (bad) atomicOr(I->flags, FLAG_PRECOND);
+    if (pre) {
+#pragma unroll
+      for (int m = 0; m < RM; ++m) v[m] = nxt[m];
+    }
+    item = nitem;
   }
-  if (bad) atomicOr(I->flags, FLAG_PRECOND);
 }
 
 // ---------------------------------------------------------------------------
@@ -451,7 +488,7 @@ __device__ __forceinline__ void pair_forward(const double (&a)[PX::RMAX], const 
 // theta y + (1 - theta) u^n); otherwise theta = 1 and u^n is not read.
 template <class PX, int MODEL, bool MPS>
 __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restrict__ grp, int bpi,
-                                                  int l) {
+                                                  int l, int /*total*/) {
   extern __shared__ c2 smem[];
   __shared__ uint64_t red[4];
   const GroupPos gpos = group_pos(grp, bpi);

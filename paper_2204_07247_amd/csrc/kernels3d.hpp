@@ -100,7 +100,8 @@ __device__ __forceinline__ void col0_merge(c2 (&v)[P::RMAX], c2* lds0, bool mine
 // the x-transform), then column 0 split.  Inverse: column 0 merged, then the
 // inverse y-transform of d^ (field 0).  In place.
 template <class PY, bool INV>
-__global__ __launch_bounds__(512) void k_y3_iter(const InstDev* const* __restrict__ grp, int bpi, int l) {
+__global__ __launch_bounds__(512) void k_y3_iter(const InstDev* const* __restrict__ grp, int bpi, int l,
+                                                 int /*total*/) {
   extern __shared__ c2 smem[];
   const GroupPos gpos = group_pos(grp, bpi);
   const InstDev* __restrict__ I = gpos.I;
@@ -201,7 +202,8 @@ __device__ __forceinline__ double q3(const InstDev* I, int kp, int ky, int kz) {
 //   d^ = -(1/(P Lq)) [ (a/theta v^ + g^)/M + q N^ + q (1 - eps - 2q + q^2) v^ ],
 // zero at k = 0, and the inverse z-transform of d^ into field 0.
 template <class PZ>
-__global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restrict__ grp, int bpi, int l) {
+__global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restrict__ grp, int bpi, int l,
+                                                 int /*total*/) {
   extern __shared__ c2 smem[];
   const GroupPos gpos = group_pos(grp, bpi);
   const InstDev* __restrict__ I = gpos.I;

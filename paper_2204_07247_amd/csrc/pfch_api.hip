@@ -135,6 +135,8 @@ struct Group {
   dim3 row_block, col_block;
   int row_bpi = 0, col_bpi = 0;  // blocks per instance
   size_t row_lds = 0, col_lds = 0;
+  int col_cap = 0;               // column kernel: > 0 = persistent grid size
+  int num_cus = 0;
   // step-setup kernels: always the default plan and geometry, so that the
   // partial sums of the averaged-Newton constants do not depend on tuning
   RowK rs;
@@ -391,17 +393,23 @@ struct Stage {
   int bpi;
   dim3 block;
   size_t lds;
+  int cap;  // > 0: at most this many blocks, each looping over items
 };
+// Grid of a stage launched for `nm` instances.
+unsigned stage_grid(const Stage& st, unsigned nm) {
+  const unsigned tot = nm * (unsigned)st.bpi;
+  return st.cap > 0 && (unsigned)st.cap < tot ? (unsigned)st.cap : tot;
+}
 int iter_stages(const Group& G, Stage* st) {
   if (G.ndim == 3) {
-    st[0] = Stage{G.y3.fwd, G.y3_bpi, G.y3_block, G.y3_lds};
-    st[1] = Stage{G.z3.iter, G.z3_bpi, G.z3_block, G.z3_lds};
-    st[2] = Stage{G.y3.inv, G.y3_bpi, G.y3_block, G.y3_lds};
-    st[3] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds};
+    st[0] = Stage{G.y3.fwd, G.y3_bpi, G.y3_block, G.y3_lds, 0};
+    st[1] = Stage{G.z3.iter, G.z3_bpi, G.z3_block, G.z3_lds, 0};
+    st[2] = Stage{G.y3.inv, G.y3_bpi, G.y3_block, G.y3_lds, 0};
+    st[3] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds, 0};
     return 4;
   }
-  st[0] = Stage{G.ck.iter, G.col_bpi, G.col_block, G.col_lds};
-  st[1] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds};
+  st[0] = Stage{G.ck.iter, G.col_bpi, G.col_block, G.col_lds, G.col_cap};
+  st[1] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds, 0};
   return 2;
 }
 
@@ -428,9 +436,10 @@ int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
         InstDev** grp = G.d_members;
         int bpi = st[k].bpi;
         int lv = l;
-        void* args[] = {&grp, &bpi, &lv};
+        int total = (int)nm * bpi;
+        void* args[] = {&grp, &bpi, &lv, &total};
         p.func = const_cast<void*>(st[k].f);
-        p.gridDim = dim3(nm * bpi);
+        p.gridDim = dim3(stage_grid(st[k], nm));
         p.blockDim = st[k].block;
         p.sharedMemBytes = (unsigned)st[k].lds;
         p.kernelParams = args;
@@ -664,7 +673,7 @@ int learned_guess(pfch_ctx* ctx, Instance& I, double rho) {
 // ---------------------------------------------------------------------------
 struct TuneChoice {
   int row_alt = -1, teams = 0;  // alt -1: default plan
-  int col_alt = -1, cb = 0;
+  int col_alt = -1, cb = 0, persist = 0;
   int cy = 0, kyb = 0;          // 3D: y-pass columns per block, z-pass ky per block
   int y3_alt = -1, z3_alt = -1;  // 3D: y- and z-pass plans
 };
@@ -702,39 +711,53 @@ void apply_row(Group& G, const RowK& k, int teams) {
   if (G.row_lds > 65536)
     (void)hipFuncSetAttribute(k.iter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.row_lds);
 }
-void apply_col(Group& G, const ColK& k, int cb) {
+// persist: launch only as many column blocks as fit on the device at once,
+// each looping over items (next item's first field prefetched).
+void apply_col(Group& G, const ColK& k, int cb, int persist = 0) {
   G.ck = k;
   G.col_block = dim3(k.T * cb);
   G.col_bpi = (G.nx / 2) / cb;
   G.col_lds = (size_t)cb * k.lds_elems * sizeof(c2);
   if (G.col_lds > 65536)
     (void)hipFuncSetAttribute(k.iter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.col_lds);
+  G.col_cap = 0;
+  if (persist) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.iter, (int)G.col_block.x, G.col_lds) == hipSuccess &&
+        nb > 0 && G.num_cus > 0)
+      G.col_cap = nb * G.num_cus;
+  }
 }
 
-// Milliseconds per launch of the group's current row (which = 1) or column
-// (which = 0) iteration kernel on instance I alone.
-int time_iter_kernel(pfch_ctx* ctx, const Group& G, Instance& I, int which, hipEvent_t e0, hipEvent_t e1,
-                     float* ms) {
+// Milliseconds per launch of one iteration stage on instance I alone.
+int time_stage(pfch_ctx* ctx, Instance& I, const Stage& st, hipEvent_t e0, hipEvent_t e1, float* ms) {
   InstDev** grp = I.d_solo;
-  int bpi = which ? G.row_bpi : G.col_bpi;
+  int bpi = st.bpi;
   int l0 = 0;
-  void* a[] = {&grp, &bpi, &l0};
-  const void* f = which ? G.rk.iter : G.ck.iter;
-  const dim3 blk = which ? G.row_block : G.col_block;
-  const size_t lds = which ? G.row_lds : G.col_lds;
+  int total = bpi;
+  void* a[] = {&grp, &bpi, &l0, &total};
+  const dim3 grid(stage_grid(st, 1));
   constexpr int WARM = 2, REPS = 8;
   int rc;
   for (int r = 0; r < WARM; ++r)
-    if ((rc = launch(f, dim3(bpi), blk, lds, a, ctx->stream))) return rc;
+    if ((rc = launch(st.f, grid, st.block, st.lds, a, ctx->stream))) return rc;
   HIPCHK(hipEventRecord(e0, ctx->stream));
   for (int r = 0; r < REPS; ++r)
-    if ((rc = launch(f, dim3(bpi), blk, lds, a, ctx->stream))) return rc;
+    if ((rc = launch(st.f, grid, st.block, st.lds, a, ctx->stream))) return rc;
   HIPCHK(hipEventRecord(e1, ctx->stream));
   HIPCHK(hipEventSynchronize(e1));
   float t = 0.f;
   HIPCHK(hipEventElapsedTime(&t, e0, e1));
   *ms = t / REPS;
   return PFCH_OK;
+}
+
+// The group's current row (which = 1) or column (which = 0) kernel.
+int time_iter_kernel(pfch_ctx* ctx, const Group& G, Instance& I, int which, hipEvent_t e0, hipEvent_t e1,
+                     float* ms) {
+  Stage st[4];
+  iter_stages(G, st);
+  return time_stage(ctx, I, st[which], e0, e1, ms);
 }
 
 bool y3_geometry_ok(const Group& G, const Y3K& k, int cy) {
@@ -769,29 +792,8 @@ void apply_choice(Group& G, const TuneChoice& c) {
     apply_y3(G, c.y3_alt < 0 ? G.y3d : G.y3alts[c.y3_alt], c.cy);
     apply_z3(G, c.z3_alt < 0 ? G.z3d : G.z3alts[c.z3_alt], c.kyb);
   } else {
-    apply_col(G, c.col_alt < 0 ? G.cs : G.calts[c.col_alt], c.cb);
+    apply_col(G, c.col_alt < 0 ? G.cs : G.calts[c.col_alt], c.cb, c.persist);
   }
-}
-
-// Milliseconds per launch of one iteration stage on instance I alone.
-int time_stage(pfch_ctx* ctx, Instance& I, const Stage& st, hipEvent_t e0, hipEvent_t e1, float* ms) {
-  InstDev** grp = I.d_solo;
-  int bpi = st.bpi;
-  int l0 = 0;
-  void* a[] = {&grp, &bpi, &l0};
-  constexpr int WARM = 2, REPS = 8;
-  int rc;
-  for (int r = 0; r < WARM; ++r)
-    if ((rc = launch(st.f, dim3(bpi), st.block, st.lds, a, ctx->stream))) return rc;
-  HIPCHK(hipEventRecord(e0, ctx->stream));
-  for (int r = 0; r < REPS; ++r)
-    if ((rc = launch(st.f, dim3(bpi), st.block, st.lds, a, ctx->stream))) return rc;
-  HIPCHK(hipEventRecord(e1, ctx->stream));
-  HIPCHK(hipEventSynchronize(e1));
-  float t = 0.f;
-  HIPCHK(hipEventElapsedTime(&t, e0, e1));
-  *ms = t / REPS;
-  return PFCH_OK;
 }
 
 // 3D groups: rows per block of the x-pass, columns per block of the
@@ -941,14 +943,18 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
     for (int alt = -1; alt < (int)G.calts.size(); ++alt) {
       const ColK& k = alt < 0 ? G.cs : G.calts[alt];
       for (int cb = 1; cb <= 4; cb *= 2) {
-        if (!col_geometry_ok(G, k, cb) || (alt < 0 && cb == def.cb)) continue;
-        apply_col(G, k, cb);
-        float t = 0.f;
-        if ((rc = time_iter_kernel(ctx, G, I, 0, e0, e1, &t))) return rc;
-        if (t < 0.97f * t_def_col && t < t_best) {
-          t_best = t;
-          best.col_alt = alt;
-          best.cb = cb;
+        for (int persist = 0; persist <= 1; ++persist) {
+          if (!col_geometry_ok(G, k, cb) || (alt < 0 && cb == def.cb && !persist)) continue;
+          apply_col(G, k, cb, persist);
+          if (persist && G.col_cap == 0) continue;
+          float t = 0.f;
+          if ((rc = time_iter_kernel(ctx, G, I, 0, e0, e1, &t))) return rc;
+          if (t < 0.97f * t_def_col && t < t_best) {
+            t_best = t;
+            best.col_alt = alt;
+            best.cb = cb;
+            best.persist = persist;
+          }
         }
       }
     }
@@ -1075,6 +1081,12 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
       G.ny = I.ny;
       G.nz = I.nz;
       G.rows = I.rows;
+      {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&G.num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+          G.num_cus = 0;
+      }
       G.ndim = I.d.ndim;
       const bool mps = scheme_mp(I.d.scheme);
       bool ok;
@@ -1284,9 +1296,10 @@ int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
   HIPCHK(hipEventRecord(e[0], ctx->stream));
   for (int k = 0; k < ns; ++k) {
     int bpi = st[k].bpi;
-    void* a[] = {&grp, &bpi, &l0};
+    int total = bpi;
+    void* a[] = {&grp, &bpi, &l0, &total};
     for (int r = 0; r < reps; ++r)
-      if ((rc = launch(st[k].f, dim3(bpi), st[k].block, st[k].lds, a, ctx->stream))) return rc;
+      if ((rc = launch(st[k].f, dim3(stage_grid(st[k], 1)), st[k].block, st[k].lds, a, ctx->stream))) return rc;
     HIPCHK(hipEventRecord(e[k + 1], ctx->stream));
   }
   HIPCHK(hipEventSynchronize(e[ns]));
@@ -1312,13 +1325,13 @@ int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]) {
   out[0] = nm * G.row_bpi;
   out[1] = G.row_block.x;
   out[2] = (int64_t)G.row_lds;
-  out[3] = nm * G.col_bpi;
+  out[3] = G.col_cap > 0 && G.col_cap < nm * G.col_bpi ? G.col_cap : nm * G.col_bpi;
   out[4] = G.col_block.x;
   out[5] = (int64_t)G.col_lds;
   return PFCH_OK;
 }
 
-int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[36]) {
+int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[37]) {
   if (!ctx || !out || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
   const Group& G = ctx->groups[ctx->inst[inst].group];
   auto find = [](const auto& alts, const void* f, auto get) {
@@ -1326,7 +1339,8 @@ int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[36]) {
       if (get(alts[k]) == f) return k;
     return -1;
   };
-  for (int k = 0; k < 36; ++k) out[k] = 0;
+  for (int k = 0; k < 37; ++k) out[k] = 0;
+  out[36] = G.col_cap;
   out[0] = find(G.ralts, G.rk.iter, [](const RowK& k) { return k.iter; });
   out[1] = G.rk.T > 0 ? (int32_t)(G.row_block.x / G.rk.T) : 0;
   out[8] = (int32_t)G.ralts.size();
@@ -1353,7 +1367,7 @@ int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[36]) {
   return PFCH_OK;
 }
 
-int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[8]) {
+int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]) {
   if (!ctx || !choice || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
   Group& G = ctx->groups[ctx->inst[inst].group];
   TuneChoice c;
@@ -1365,6 +1379,7 @@ int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[8]) {
   c.cy = choice[5];
   c.z3_alt = choice[6];
   c.kyb = choice[7];
+  c.persist = choice[8] != 0;
   if (c.row_alt < -1 || c.row_alt >= (int)G.ralts.size()) return PFCH_E_INVAL;
   const RowK& rk = c.row_alt < 0 ? G.rs : G.ralts[c.row_alt];
   if (c.teams < 1 || (c.teams & (c.teams - 1)) || !row_geometry_ok(G, rk, c.teams)) return PFCH_E_INVAL;

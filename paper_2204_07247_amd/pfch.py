@@ -202,9 +202,9 @@ class Context:
         self._h = h
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().pfch_destroy(self._h)
-            self._h = None
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pfch_destroy(self._h)
+        self._h = None
 
     __del__ = close
 
@@ -268,7 +268,7 @@ class Context:
 
     def plan(self, inst=0):
         """Iteration-kernel plans of the instance's group (see pfch_get_plan)."""
-        out = (ctypes.c_int32 * 36)()
+        out = (ctypes.c_int32 * 37)()
         rc = lib().pfch_get_plan(self._h, inst, out)
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_get_plan")
@@ -277,11 +277,11 @@ class Context:
                     y_alt=out[4], y_cb=out[5], z_alt=out[6], z_kyb=out[7],
                     n_row_alts=out[8], n_col_alts=out[9], n_y_alts=out[10], n_z_alts=out[11],
                     row_radices=rad(out[12:20]), col_radices=rad(out[20:28]),
-                    z_radices=rad(out[28:36]))
+                    z_radices=rad(out[28:36]), col_persistent_grid=out[36])
 
     def set_plan(self, inst, row_alt, teams, col_alt=-1, cb=1, y_alt=-1, y_cb=1, z_alt=-1,
-                 z_kyb=1):
-        ch = (ctypes.c_int32 * 8)(row_alt, teams, col_alt, cb, y_alt, y_cb, z_alt, z_kyb)
+                 z_kyb=1, col_persist=0):
+        ch = (ctypes.c_int32 * 9)(row_alt, teams, col_alt, cb, y_alt, y_cb, z_alt, z_kyb, col_persist)
         rc = lib().pfch_set_plan(self._h, inst, ch)
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_set_plan")
@@ -328,9 +328,9 @@ class Fno:
         self.n_params = fno_num_params(width, modes, layers)
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().pfch_fno_destroy(self._h)
-            self._h = None
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pfch_fno_destroy(self._h)
+        self._h = None
 
     __del__ = close
 

@@ -36,11 +36,13 @@ def _candidates(ctx, axis):
     if axis == "row":
         for alt in range(-1, p["n_row_alts"]):
             for teams in (1, 2, 4, 8, 16, 32, 64):
-                out.append((alt, teams, -1, p["col_cb"]))
+                out.append(dict(row_alt=alt, teams=teams, col_alt=-1, cb=p["col_cb"]))
     else:
         for alt in range(-1, p["n_col_alts"]):
             for cb in (1, 2, 4):
-                out.append((-1, p["row_teams"], alt, cb))
+                for persist in (0, 1):
+                    out.append(dict(row_alt=-1, teams=p["row_teams"], col_alt=alt, cb=cb,
+                                    col_persist=persist))
     return out
 
 
@@ -63,7 +65,7 @@ def test_every_plan_matches_oracle(case):
     tried = 0
     for ch in _candidates(ctx, axis):
         try:
-            ctx.set_plan(0, *ch)
+            ctx.set_plan(0, **ch)
         except pfch.PfchError as e:
             assert e.code == pfch.PFCH_E_INVAL
             continue
