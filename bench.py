@@ -134,9 +134,11 @@ def gpu_run(w, steps, warmup, kernel_timing):
     timing = None
     if kernel_timing:
         reps = 50
-        log(f"[bench] kernel timing: HIP events around {reps} back-to-back launches per kernel")
-        timing = ctx.time_kernels(w.dt, reps)
+        log(f"[bench] kernel timing: HIP events around {reps} back-to-back launches per kernel; "
+            "HIP start/stop events on every iteration-kernel launch of 10 solves")
+        timing = ctx.time_kernels(w.dt, reps, events=True)
         timing["reps"] = reps
+        timing["in_solve"] = ctx.time_kernels(w.dt, 10)
     cfg = ctx.launch_config()
     cfg["plan"] = ctx.plan(0)
     ctx.close()
@@ -206,6 +208,49 @@ def batched_comparison(count, steps, solo_steps):
                 batched_over_plain=round(batched / plain, 3),
                 batched_steps=steps, plain_steps_per_instance=solo_steps,
                 iters_per_step_mean=round(float(np.mean(its)), 3))
+
+
+def solver_variants(w, steps):
+    """The same steps of w solved by PAGD with the paper's friction sweep,
+    PAGD with each constant friction of the sweep, plain preconditioned
+    gradient descent (Alg. 1), and the linear IMEX scheme of the same
+    family (one linear solve per step): iterations and FFT pairs per step,
+    time-steps/s."""
+    import dataclasses
+
+    import torch
+    from paper_2204_07247_amd import pfch
+    u0 = torch.from_numpy(W.initial_condition(w)).cuda()
+    fft_pairs = {"pfc": 1.5, "fch": 2.5}[w.model]
+    variants = [("pagd_sweep", {}), ("pgd", dict(etas=()))]
+    variants += [(f"pagd_eta{e * e:g}", dict(etas=(e,))) for e in w.etas]
+    imex = "lbdf2" if w.scheme == "bdf2" else "lmp"
+    variants.append((imex, dict(scheme=imex)))
+    out = {}
+    for name, kw in variants:
+        wv = dataclasses.replace(w, **{k: v for k, v in kw.items() if k in ("etas", "scheme")})
+        ctx = pfch.Context([_desc(wv)])
+        ctx.set_stats_detail(0)
+        ctx.set_state(0, u0)
+        its = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rc, st = ctx.step(w.dt)
+            if rc != pfch.PFCH_OK:
+                its = None
+                break
+            its.append(st[0]["iters"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx.close()
+        if its is None:
+            out[name] = dict(status=pfch.strerror(rc))
+            continue
+        out[name] = dict(iters_per_step=round(float(np.mean(its)), 3),
+                         fft_pairs_per_step=round(float(np.mean(its)) * fft_pairs, 2),
+                         steps_per_s=round(steps / el, 1))
+    return dict(workload=w.name, steps=steps, variants=out)
 
 
 def ensemble_bandwidth(ws, steps, warmup, label):
@@ -392,7 +437,8 @@ def main():
         for k in ab:
             avg = timing[f"{k}_us"] * 1e-6
             kernels[k] = dict(avg_us=round(avg * 1e6, 3), launches=timing["reps"], alg_bytes=ab[k],
-                              achieved_gbs=round(ab[k] / avg / 1e9, 2))
+                              achieved_gbs=round(ab[k] / avg / 1e9, 2),
+                              in_solve_us=round(timing["in_solve"][f"{k}_us"], 3))
         dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
         kd = kernels[dom]
         roof = dict(bound="hbm", kernel=KERNEL_NAMES[dom], achieved=kd["achieved_gbs"],
@@ -410,6 +456,10 @@ def main():
             ensemble_bandwidth(W.fch_ensemble() + [W.PFC192_3D], steps=5, warmup=2,
                                label="fch2d_8x1024_8x2048_bdf2 + pfc3d_192_bdf2"),
         ]
+    variants = None
+    if not args.no_compare:
+        variants = [solver_variants(w, steps=min(w.steps, 50)),
+                    solver_variants(W.PFC64_MP, steps=W.PFC64_MP.steps)]
     learned_res = None
     if not args.no_learned and not args.no_compare:
         learned_res = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=20)
@@ -428,7 +478,7 @@ def main():
         iters_per_step=dict(mean=round(float(it.mean()), 3), min=int(it.min()), max=int(it.max())),
         fft_pairs_per_iter=fft_pairs,
         roofline=roof, kernels=kernels, launch=cfg, cpu_baseline=cpu, batched=batched,
-        learned=learned_res, ensembles=ensembles,
+        learned=learned_res, ensembles=ensembles, solver_variants=variants,
     )
     if cpu:
         out["gpu_over_cpu"] = round(value / cpu["value"], 2)

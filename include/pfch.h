@@ -144,15 +144,24 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
  * solution (one extra reduction and synchronisation per step). */
 int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail);
 
-/* Kernel timing for measurement.  Sets up one step of instance 0 from its
- * current state (as pfch_step would, with step size dt), then launches each
- * of its iteration kernels `reps` times back to back on the context's
- * stream, every launch doing the full work of an iteration, with HIP events
- * between the batches.  out[k] = microseconds per launch of the k-th
- * iteration kernel in launch order: 2D {column, row, 0, 0}; 3D {y forward,
- * z, y inverse, row}.  The instance's state (u^n, u^{n-1}, t, step index)
- * is not changed; its iteration workspaces are. */
+/* Kernel timing for measurement.  Solves `reps` times the step of size dt
+ * from instance 0's current state (as pfch_step would, launching the same
+ * iteration kernels in the same order, without accepting the result), with a
+ * HIP start/stop event pair attached to every iteration-kernel launch
+ * (hipExtLaunchKernel).  out[k] = average microseconds of the k-th iteration
+ * kernel over the launches that did an iteration's work: 2D {column, row,
+ * 0, 0}; 3D {y forward, z, y inverse, row}.  The instance's state (u^n,
+ * u^{n-1}, t, step index) is not changed; its iteration workspaces are. */
 int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]);
+
+/* Kernel timing with HIP events: sets up one step of instance 0 (as
+ * pfch_step would), then launches each iteration kernel `reps` times back
+ * to back on the context's stream (every launch doing an iteration's full
+ * work) with one event pair around each batch.  out as for
+ * pfch_time_kernels.  Back-to-back launches of one kernel find the caches
+ * warm from its previous launch, unlike the solve.  The instance's state is
+ * not changed; its iteration workspaces are. */
+int pfch_time_kernels_events(pfch_ctx* ctx, double dt, int32_t reps, double out[4]);
 
 /* Launch geometry of instance `inst` for reporting: {row grid, row block,
  * row LDS bytes, column grid, column block, column LDS bytes}. */

@@ -5,6 +5,7 @@
 // covers a whole group (block b works on member b / bpi).  One iteration
 // graph holds, per group, a chain of column/row kernels for K iterations;
 // the chains of different groups are independent and may run concurrently.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -693,6 +694,9 @@ bool autotune_enabled() {
 }
 
 constexpr size_t LDS_MAX = 160 * 1024;
+// An alternative replaces the default only when it is clearly faster, so
+// that timing noise does not flip the choice between processes.
+constexpr float TUNE_MARGIN = 0.94f;
 
 bool row_geometry_ok(const Group& G, const RowK& k, int teams) {
   const int pairs = G.rows / 2;
@@ -737,18 +741,22 @@ int time_stage(pfch_ctx* ctx, Instance& I, const Stage& st, hipEvent_t e0, hipEv
   int total = bpi;
   void* a[] = {&grp, &bpi, &l0, &total};
   const dim3 grid(stage_grid(st, 1));
-  constexpr int WARM = 2, REPS = 8;
+  constexpr int WARM = 2, REPS = 8, ROUNDS = 3;
   int rc;
   for (int r = 0; r < WARM; ++r)
     if ((rc = launch(st.f, grid, st.block, st.lds, a, ctx->stream))) return rc;
-  HIPCHK(hipEventRecord(e0, ctx->stream));
-  for (int r = 0; r < REPS; ++r)
-    if ((rc = launch(st.f, grid, st.block, st.lds, a, ctx->stream))) return rc;
-  HIPCHK(hipEventRecord(e1, ctx->stream));
-  HIPCHK(hipEventSynchronize(e1));
-  float t = 0.f;
-  HIPCHK(hipEventElapsedTime(&t, e0, e1));
-  *ms = t / REPS;
+  float best = 0.f;
+  for (int round = 0; round < ROUNDS; ++round) {  // best of three batches
+    HIPCHK(hipEventRecord(e0, ctx->stream));
+    for (int r = 0; r < REPS; ++r)
+      if ((rc = launch(st.f, grid, st.block, st.lds, a, ctx->stream))) return rc;
+    HIPCHK(hipEventRecord(e1, ctx->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    if (round == 0 || t < best) best = t;
+  }
+  *ms = best / REPS;
   return PFCH_OK;
 }
 
@@ -822,7 +830,7 @@ int tune_group3(pfch_ctx* ctx, Group& G, TuneChoice& best) {
       apply_row(G, k, teams);
       iter_stages(G, st);
       if ((rc = time_stage(ctx, I, st[3], e0, e1, &t))) return rc;
-      if (t < 0.97f * t_def && t < t_best) {
+      if (t < TUNE_MARGIN * t_def && t < t_best) {
         t_best = t;
         best.row_alt = alt;
         best.teams = teams;
@@ -841,7 +849,7 @@ int tune_group3(pfch_ctx* ctx, Group& G, TuneChoice& best) {
       apply_y3(G, k, cy);
       iter_stages(G, st);
       if ((rc = time_stage(ctx, I, st[0], e0, e1, &t))) return rc;
-      if (t < 0.97f * t_def && t < t_best) {
+      if (t < TUNE_MARGIN * t_def && t < t_best) {
         t_best = t;
         best.y3_alt = alt;
         best.cy = cy;
@@ -860,7 +868,7 @@ int tune_group3(pfch_ctx* ctx, Group& G, TuneChoice& best) {
       apply_z3(G, k, kyb);
       iter_stages(G, st);
       if ((rc = time_stage(ctx, I, st[1], e0, e1, &t))) return rc;
-      if (t < 0.97f * t_def && t < t_best) {
+      if (t < TUNE_MARGIN * t_def && t < t_best) {
         t_best = t;
         best.z3_alt = alt;
         best.kyb = kyb;
@@ -927,7 +935,7 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
         apply_row(G, k, teams);
         float t = 0.f;
         if ((rc = time_iter_kernel(ctx, G, I, 1, e0, e1, &t))) return rc;
-        if (t < 0.97f * t_def_row && t < t_best) {
+        if (t < TUNE_MARGIN * t_def_row && t < t_best) {
           t_best = t;
           best.row_alt = alt;
           best.teams = teams;
@@ -949,7 +957,7 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
           if (persist && G.col_cap == 0) continue;
           float t = 0.f;
           if ((rc = time_iter_kernel(ctx, G, I, 0, e0, e1, &t))) return rc;
-          if (t < 0.97f * t_def_col && t < t_best) {
+          if (t < TUNE_MARGIN * t_def_col && t < t_best) {
             t_best = t;
             best.col_alt = alt;
             best.cb = cb;
@@ -1282,6 +1290,64 @@ int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail) {
 }
 
 int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
+  if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
+  Instance& I = ctx->inst[0];
+  const Group& G = ctx->groups[I.group];
+  Stage st[4];
+  const int ns = iter_stages(G, st);
+  // iterations launched per solve: the last step's count plus two
+  const int nit = std::min(I.d.max_iter, std::max(I.last_iters, 1) + 2);
+  std::vector<hipEvent_t> ev((size_t)2 * ns * nit);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  std::vector<uint64_t> norms(nit);
+  double sum[4] = {0, 0, 0, 0};
+  int cnt[4] = {0, 0, 0, 0};
+  int rc = PFCH_OK;
+  InstDev** grp = I.d_solo;
+  for (int r = 0; r < reps && rc == PFCH_OK; ++r) {
+    if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, dt)))) break;
+    for (int j = 0; j < nit && rc == PFCH_OK; ++j)
+      for (int k = 0; k < ns; ++k) {
+        int bpi = st[k].bpi, lv = j, total = bpi;
+        void* a[] = {&grp, &bpi, &lv, &total};
+        hipEvent_t* e = &ev[2 * ((size_t)j * ns + k)];
+        if (hipExtLaunchKernel(st[k].f, dim3(stage_grid(st[k], 1)), st[k].block, a, st[k].lds, ctx->stream,
+                               e[0], e[1], 0) != hipSuccess) {
+          rc = PFCH_E_HIP;
+          break;
+        }
+      }
+    if (rc) break;
+    if (hipMemcpyAsync(norms.data(), I.h.norms, sizeof(uint64_t) * nit, hipMemcpyDeviceToHost, ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      rc = PFCH_E_HIP;
+      break;
+    }
+    // iteration j did work if j = 0 or iteration j-1 did not stop
+    for (int j = 0; j < nit; ++j) {
+      if (j > 0 && (norms[j - 1] < I.h.tol_bits || norms[j - 1] >= INF_BITS)) break;
+      for (int k = 0; k < ns; ++k) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[2 * ((size_t)j * ns + k)], ev[2 * ((size_t)j * ns + k) + 1]) != hipSuccess)
+          continue;
+        sum[k] += 1e3 * t;
+        cnt[k] += 1;
+      }
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  for (int k = 0; k < 4; ++k) out[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+  // park the instance so later chunk launches leave it alone
+  int32_t* park = (int32_t*)ctx->h_recs;  // pinned scratch, free until the next poll
+  *park = I.d.max_iter + 1;
+  HIPCHK(hipMemcpyAsync(I.h.iter_base, park, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return PFCH_OK;
+}
+
+int pfch_time_kernels_events(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
   if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
   Instance& I = ctx->inst[0];
   const Group& G = ctx->groups[I.group];

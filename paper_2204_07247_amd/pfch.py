@@ -28,7 +28,7 @@ PAPER_ETAS = tuple(math.sqrt(v) for v in (0.1, 0.575, 1.05, 1.525, 2.0))
 EXPORTED = (
     "pfch_validate_desc", "pfch_create", "pfch_set_state", "pfch_get_state",
     "pfch_step", "pfch_solve", "pfch_set_stats_detail", "pfch_time_kernels",
-    "pfch_get_launch_config", "pfch_destroy",
+    "pfch_get_launch_config", "pfch_destroy", "pfch_time_kernels_events",
     "pfch_strerror", "pfch_version",
     "pfch_fno_num_params", "pfch_fno_create", "pfch_fno_init_params", "pfch_fno_set_params",
     "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad", "pfch_fno_adam_step",
@@ -94,6 +94,8 @@ def lib():
         L.pfch_solve.argtypes = [vp, i32, dbl, dbl, dbl, vp, vp, vp, ctypes.POINTER(Stats)]
         L.pfch_set_stats_detail.argtypes = [vp, i32]
         L.pfch_time_kernels.argtypes = [vp, dbl, i32, ctypes.POINTER(dbl)]
+        L.pfch_time_kernels_events.argtypes = [vp, dbl, i32, ctypes.POINTER(dbl)]
+        L.pfch_time_kernels_events.restype = ctypes.c_int
         L.pfch_get_launch_config.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
         L.pfch_destroy.argtypes = [vp]
         L.pfch_destroy.restype = None
@@ -219,12 +221,14 @@ class Context:
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_set_stats_detail")
 
-    def time_kernels(self, dt, reps):
-        """Average microseconds per launch of instance 0's iteration kernels
-        (HIP events around `reps` back-to-back launches of each): 2D
-        {col_us, row_us}; 3D {yfwd_us, z_us, yinv_us, row_us}."""
+    def time_kernels(self, dt, reps, events=False):
+        """Average microseconds per launch of instance 0's iteration kernels:
+        HIP events on every launch of `reps` solves (default), or HIP events
+        around `reps` back-to-back launches of each kernel (events=True).
+        2D {col_us, row_us}; 3D {yfwd_us, z_us, yinv_us, row_us}."""
         out = (ctypes.c_double * 4)()
-        rc = lib().pfch_time_kernels(self._h, float(dt), int(reps), out)
+        fn = lib().pfch_time_kernels_events if events else lib().pfch_time_kernels
+        rc = fn(self._h, float(dt), int(reps), out)
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_time_kernels")
         if out[2] == 0.0 and out[3] == 0.0:
