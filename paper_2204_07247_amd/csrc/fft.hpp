@@ -15,9 +15,9 @@
 // Thread t processes the butterflies j = t + q*T, q = 0..RMAX/R-1.
 //
 // Twiddles come from a per-length table tw[k] = exp(-2 pi i k / N) computed
-// on the host in long double; each thread reads the ones its butterflies
-// need once per kernel (Twiddles).  Inverse transforms use conjugates.
-// Neither direction is normalised.
+// on the host in long double, read once per kernel into registers or, for
+// plans that would need many per thread, into an LDS table (Twiddles).
+// Inverse transforms use conjugates.  Neither direction is normalised.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -209,29 +209,122 @@ struct Plan {
   static_assert(ns(NPASS) == N, "radices must multiply to N");
 };
 
-// Per-thread twiddles w1 = w_N^{(j mod Ns) * N/(Ns*R)} of every butterfly
-// j = t + q*T of passes 1..NPASS-1 (pass 0 needs none).  They are read once
-// per kernel; the powers w1^r of a butterfly are formed by repeated complex
-// multiplication (at most 15 products, error a few ulps).
+// Twiddles live in LDS, after the block's transform buffers: for every pass
+// p >= 1 the Ns(p) values w_N^{i N/(Ns R)}, i < Ns(p), which are all the
+// first-power twiddles w1 = w_N^{(j mod Ns) N/(Ns R)} its butterflies need
+// (pass 0 needs none); the powers w1^r are formed by repeated complex
+// multiplication (at most 15 products, error a few ulps).  The block fills the
+// table once per kernel from the host-computed table of N entries.
 template <class P>
-struct Twiddles {
-  c2 w[P::NPASS > 1 ? P::NPASS - 1 : 1][P::RMAX];
-};
+constexpr int tw_offset(int p) {  // start of pass p's entries
+  int o = 0;
+  for (int q = 1; q < p; ++q) o += P::ns(q);
+  return o;
+}
+template <class P>
+constexpr int tw_count() {
+  return tw_offset<P>(P::NPASS);
+}
+
+// Where a plan keeps its twiddles: in registers (each thread holds the
+// first powers of its own butterflies, read once per kernel) when that is at
+// most four complex values per thread, else in the LDS table (radix-3/2 and
+// many-pass plans, whose register copies would cost occupancy).
+template <class P>
+constexpr int tw_per_thread() {
+  int n = 0;
+  for (int p = 1; p < P::NPASS; ++p) n += P::RMAX / P::radix(p);
+  return n;
+}
+template <class P>
+constexpr bool tw_in_lds() {
+  return tw_per_thread<P>() > 4;
+}
+// LDS entries the plan's twiddle table needs (0 in register mode).
+template <class P>
+constexpr int tw_lds_count() {
+  return tw_in_lds<P>() ? tw_count<P>() : 0;
+}
 
 template <class P>
-__device__ __forceinline__ void load_twiddles(Twiddles<P>& tw, const c2* __restrict__ table_, int t) {
+struct Twiddles {
+  const c2* lds;                                   // LDS mode
+  c2 w[P::NPASS > 1 ? P::NPASS - 1 : 1][P::RMAX];  // register mode
+};
+
+// Index into the host table of compact entry i.
+template <class P>
+__device__ __forceinline__ int tw_source(int i) {
+  int p = 1, o = 0;
+  while (p + 1 < P::NPASS && i >= o + P::ns(p)) {
+    o += P::ns(p);
+    ++p;
+  }
+  return (i - o) * (P::N / (P::ns(p) * P::radix(p)));
+}
+
+// Two-phase set-up, so that a kernel can issue its data loads between the
+// two.  LDS mode: tw_fetch reads this thread's share of the table into
+// registers (blocks have at least T threads, hence the bound) and tw_commit
+// stores it into LDS and synchronises the block.  Register mode: tw_fetch
+// reads the thread's own twiddles and tw_commit only hands them over.
+// Every thread of the block calls tw_commit.
+template <class P>
+struct TwFetch {
+  static constexpr int NT = tw_count<P>();
+  static constexpr int PER = tw_in_lds<P>() && NT > 0 ? (NT + P::T - 1) / P::T : 1;
+  c2 v[PER];
+  c2 w[P::NPASS > 1 ? P::NPASS - 1 : 1][P::RMAX];
+};
+template <class P>
+__device__ __forceinline__ void tw_fetch(TwFetch<P>& f, const c2* __restrict__ table_, int t) {
   const GLB c2* table = gp(table_);
+  if constexpr (tw_in_lds<P>()) {
 #pragma unroll
-  for (int p = 1; p < P::NPASS; ++p) {
-    const int R = P::radix(p), NS = P::ns(p), QN = P::RMAX / R;
+    for (int q = 0; q < TwFetch<P>::PER; ++q) {
+      const int i = threadIdx.x + q * blockDim.x;
+      if (i < TwFetch<P>::NT) f.v[q] = gload(table + tw_source<P>(i));
+    }
+  } else {
 #pragma unroll
-    for (int q = 0; q < P::RMAX; ++q) {
-      if (q < QN) {
-        const int j = t + q * P::T;
-        tw.w[p - 1][q] = gload(table + (j % NS) * (P::N / (NS * R)));
+    for (int p = 1; p < P::NPASS; ++p) {
+      const int R = P::radix(p), NS = P::ns(p), QN = P::RMAX / R;
+#pragma unroll
+      for (int q = 0; q < P::RMAX; ++q) {
+        if (q < QN) {
+          const int j = t + q * P::T;
+          f.w[p - 1][q] = gload(table + (j % NS) * (P::N / (NS * R)));
+        }
       }
     }
   }
+}
+template <class P>
+__device__ __forceinline__ void tw_commit(Twiddles<P>& tw, const TwFetch<P>& f) {
+  if constexpr (tw_in_lds<P>()) {
+    extern __shared__ c2 smem_tw[];
+    c2* dst = smem_tw + (blockDim.x / P::T) * lds_len(P::N);
+#pragma unroll
+    for (int q = 0; q < TwFetch<P>::PER; ++q) {
+      const int i = threadIdx.x + q * blockDim.x;
+      if (i < TwFetch<P>::NT) dst[i] = f.v[q];
+    }
+    __syncthreads();
+    tw.lds = dst;
+  } else {
+#pragma unroll
+    for (int p = 1; p < P::NPASS; ++p)
+#pragma unroll
+      for (int q = 0; q < P::RMAX / P::radix(p); ++q) tw.w[p - 1][q] = f.w[p - 1][q];
+  }
+}
+
+// Both phases at once.  Every thread of the block calls this.
+template <class P>
+__device__ __forceinline__ void load_twiddles(Twiddles<P>& tw, const c2* __restrict__ table, int t) {
+  TwFetch<P> f;
+  tw_fetch<P>(f, table, t);
+  tw_commit<P>(tw, f);
 }
 
 // One Stockham pass.  FROM_REG / TO_REG select registers or LDS as source
@@ -261,7 +354,11 @@ __device__ __forceinline__ void stockham_pass(c2 (&v)[P::RMAX], c2* lds, const T
   for (int q = 0; q < QN; ++q) {
     const int j = t + q * T;
     if constexpr (NS > 1) {
-      c2 w1 = tw.w[PASS - 1][q];
+      c2 w1;
+      if constexpr (tw_in_lds<P>())
+        w1 = tw.lds[tw_offset<P>(PASS) + j % NS];
+      else
+        w1 = tw.w[PASS - 1][q];
       if (INV) w1.y = -w1.y;
       c2 w = w1;
 #pragma unroll
@@ -309,12 +406,16 @@ template <class P, bool INV>
 __device__ __forceinline__ void fft(c2 (&v)[P::RMAX], c2* lds, const Twiddles<P>& tw_in, int t_in) {
   const int t = opaque_i(t_in);
   Twiddles<P> tw;
+  if constexpr (tw_in_lds<P>()) {
+    tw.lds = tw_in.lds;
+  } else {
 #pragma unroll
-  for (int p = 1; p < P::NPASS; ++p) {
+    for (int p = 1; p < P::NPASS; ++p) {
 #pragma unroll
-    for (int q = 0; q < P::RMAX / P::radix(p); ++q) {
-      tw.w[p - 1][q].x = opaque_d(tw_in.w[p - 1][q].x);
-      tw.w[p - 1][q].y = opaque_d(tw_in.w[p - 1][q].y);
+      for (int q = 0; q < P::RMAX / P::radix(p); ++q) {
+        tw.w[p - 1][q].x = opaque_d(tw_in.w[p - 1][q].x);
+        tw.w[p - 1][q].y = opaque_d(tw_in.w[p - 1][q].y);
+      }
     }
   }
   if constexpr (P::NPASS == 1) {

@@ -700,18 +700,18 @@ constexpr float TUNE_MARGIN = 0.94f;
 
 bool row_geometry_ok(const Group& G, const RowK& k, int teams) {
   const int pairs = G.rows / 2;
-  return k.T * teams <= 256 && pairs % teams == 0 && (size_t)teams * k.lds_elems * sizeof(c2) <= LDS_MAX;
+  return k.T * teams <= 256 && pairs % teams == 0 && ((size_t)teams * k.lds_elems + k.tw_elems) * sizeof(c2) <= LDS_MAX;
 }
 bool col_geometry_ok(const Group& G, const ColK& k, int cb) {
   const int H = G.nx / 2;
-  return k.T * cb <= 512 && H % cb == 0 && (size_t)cb * k.lds_elems * sizeof(c2) <= LDS_MAX;
+  return k.T * cb <= 512 && H % cb == 0 && ((size_t)cb * k.lds_elems + k.tw_elems) * sizeof(c2) <= LDS_MAX;
 }
 
 void apply_row(Group& G, const RowK& k, int teams) {
   G.rk = k;
   G.row_block = dim3(k.T * teams);
   G.row_bpi = (G.rows / 2) / teams;
-  G.row_lds = (size_t)teams * k.lds_elems * sizeof(c2);
+  G.row_lds = ((size_t)teams * k.lds_elems + k.tw_elems) * sizeof(c2);
   if (G.row_lds > 65536)
     (void)hipFuncSetAttribute(k.iter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.row_lds);
 }
@@ -721,7 +721,7 @@ void apply_col(Group& G, const ColK& k, int cb, int persist = 0) {
   G.ck = k;
   G.col_block = dim3(k.T * cb);
   G.col_bpi = (G.nx / 2) / cb;
-  G.col_lds = (size_t)cb * k.lds_elems * sizeof(c2);
+  G.col_lds = ((size_t)cb * k.lds_elems + k.tw_elems) * sizeof(c2);
   if (G.col_lds > 65536)
     (void)hipFuncSetAttribute(k.iter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.col_lds);
   G.col_cap = 0;
@@ -769,17 +769,17 @@ int time_iter_kernel(pfch_ctx* ctx, const Group& G, Instance& I, int which, hipE
 }
 
 bool y3_geometry_ok(const Group& G, const Y3K& k, int cy) {
-  return (cy == 1 || cy == 2 || cy == 4) && cy * k.T <= 512 && (size_t)cy * k.lds_elems * sizeof(c2) <= LDS_MAX;
+  return (cy == 1 || cy == 2 || cy == 4) && cy * k.T <= 512 && ((size_t)cy * k.lds_elems + k.tw_elems) * sizeof(c2) <= LDS_MAX;
 }
 bool z3_geometry_ok(const Group& G, const Z3K& k, int kyb) {
   return kyb >= 1 && (kyb & (kyb - 1)) == 0 && TW * kyb * k.T <= 512 && G.ny % kyb == 0 &&
-         2 * kyb <= G.ny && (size_t)TW * kyb * k.lds_elems * sizeof(c2) <= LDS_MAX;
+         2 * kyb <= G.ny && ((size_t)TW * kyb * k.lds_elems + k.tw_elems) * sizeof(c2) <= LDS_MAX;
 }
 void apply_y3(Group& G, const Y3K& k, int cy) {
   G.y3 = k;
   G.y3_block = dim3(G.y3.T * cy);
   G.y3_bpi = G.nz * (G.nx / 2) / cy;
-  G.y3_lds = (size_t)cy * G.y3.lds_elems * sizeof(c2);
+  G.y3_lds = ((size_t)cy * G.y3.lds_elems + G.y3.tw_elems) * sizeof(c2);
   const void* fs[] = {G.y3.fwd, G.y3.inv, G.y3.setup};
   for (const void* f : fs)
     if (G.y3_lds > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.y3_lds);
@@ -788,7 +788,7 @@ void apply_z3(Group& G, const Z3K& k, int kyb) {
   G.z3 = k;
   G.z3_block = dim3(G.z3.T * TW * kyb);
   G.z3_bpi = (G.nx / 2 / TW) * (G.ny / kyb);
-  G.z3_lds = (size_t)TW * kyb * G.z3.lds_elems * sizeof(c2);
+  G.z3_lds = ((size_t)TW * kyb * G.z3.lds_elems + G.z3.tw_elems) * sizeof(c2);
   const void* fs[] = {G.z3.iter, G.z3.setup};
   for (const void* f : fs)
     if (G.z3_lds > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.z3_lds);
@@ -1144,7 +1144,7 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
     const int teams = pick_teams(G.rs.T, pairs);
     G.srow_block = G.row_block = dim3(G.rs.T * teams);
     G.srow_bpi = G.row_bpi = pairs / teams;
-    G.srow_lds = G.row_lds = (size_t)teams * G.rs.lds_elems * sizeof(c2);
+    G.srow_lds = G.row_lds = ((size_t)teams * G.rs.lds_elems + G.rs.tw_elems) * sizeof(c2);
     if (G.ndim == 3) {
       // y-pass: the widest tile part (<= 512 threads); z-pass: 4 columns of
       // a tile times kyb consecutive ky (<= 512 threads, kyb <= Ny/2)
@@ -1152,12 +1152,12 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
       while (cy > 1 && cy * G.y3.T > 512) cy >>= 1;
       G.y3_block = dim3(G.y3.T * cy);
       G.y3_bpi = G.nz * H / cy;
-      G.y3_lds = (size_t)cy * G.y3.lds_elems * sizeof(c2);
+      G.y3_lds = ((size_t)cy * G.y3.lds_elems + G.y3.tw_elems) * sizeof(c2);
       int kyb = 4;
       while (kyb > 1 && (TW * kyb * G.z3.T > 512 || G.ny % kyb != 0 || 2 * kyb > G.ny)) kyb >>= 1;
       G.z3_block = dim3(G.z3.T * TW * kyb);
       G.z3_bpi = (H / TW) * (G.ny / kyb);
-      G.z3_lds = (size_t)TW * kyb * G.z3.lds_elems * sizeof(c2);
+      G.z3_lds = ((size_t)TW * kyb * G.z3.lds_elems + G.z3.tw_elems) * sizeof(c2);
       if (G.y3_lds > 160 * 1024 || G.z3_lds > 160 * 1024) {
         rc = PFCH_E_UNSUPPORTED;
         goto fail;
@@ -1174,7 +1174,7 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
       const int cb = pick_cols(G.cs.T, H);
       G.scol_block = G.col_block = dim3(G.cs.T * cb);
       G.scol_bpi = G.col_bpi = H / cb;
-      G.scol_lds = G.col_lds = (size_t)cb * G.cs.lds_elems * sizeof(c2);
+      G.scol_lds = G.col_lds = ((size_t)cb * G.cs.lds_elems + G.cs.tw_elems) * sizeof(c2);
     }
     if (G.row_lds > 160 * 1024 || G.col_lds > 160 * 1024) {
       rc = PFCH_E_UNSUPPORTED;

@@ -17,6 +17,7 @@ struct RowK {
   const void* start_fch = nullptr;
   int T = 0;
   int lds_elems = 0;  // per team
+  int tw_elems = 0;   // twiddle table after the teams' buffers
   int radix[8] = {1, 1, 1, 1, 1, 1, 1, 1};
 };
 struct ColK {
@@ -24,6 +25,7 @@ struct ColK {
   const void* setup = nullptr;
   int T = 0;
   int lds_elems = 0;  // per column
+  int tw_elems = 0;   // twiddle table after the columns' buffers
   int radix[8] = {1, 1, 1, 1, 1, 1, 1, 1};
 };
 
@@ -40,6 +42,7 @@ RowK make_row() {
   if (MODEL == MODEL_FCH) k.start_fch = (const void*)&k_row_start_fch<P>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
+  k.tw_elems = tw_lds_count<P>();
   plan_radices<P>(k.radix);
   return k;
 }
@@ -50,6 +53,7 @@ RowK make_row_iter() {
   k.iter = (const void*)&k_row_iter<P, MODEL, MPS>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
+  k.tw_elems = tw_lds_count<P>();
   plan_radices<P>(k.radix);
   return k;
 }
@@ -60,6 +64,7 @@ ColK make_col() {
   k.setup = (const void*)&k_col_setup<P, MODEL>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
+  k.tw_elems = tw_lds_count<P>();
   plan_radices<P>(k.radix);
   return k;
 }
@@ -69,6 +74,7 @@ ColK make_col_iter() {
   k.iter = (const void*)&k_col_iter<P, MODEL>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
+  k.tw_elems = tw_lds_count<P>();
   plan_radices<P>(k.radix);
   return k;
 }
@@ -160,6 +166,7 @@ struct Y3K {
   const void* setup = nullptr;
   int T = 0;
   int lds_elems = 0;
+  int tw_elems = 0;
   int radix[8] = {1, 1, 1, 1, 1, 1, 1, 1};
 };
 struct Z3K {
@@ -167,6 +174,7 @@ struct Z3K {
   const void* setup = nullptr;
   int T = 0;
   int lds_elems = 0;
+  int tw_elems = 0;
   int radix[8] = {1, 1, 1, 1, 1, 1, 1, 1};
 };
 template <class P>
@@ -177,6 +185,7 @@ Y3K make_y3() {
   k.setup = (const void*)&k_y3_setup<P>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
+  k.tw_elems = tw_lds_count<P>();
   plan_radices<P>(k.radix);
   return k;
 }
@@ -187,6 +196,7 @@ Z3K make_z3() {
   k.setup = (const void*)&k_z3_setup<P>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
+  k.tw_elems = tw_lds_count<P>();
   plan_radices<P>(k.radix);
   return k;
 }
