@@ -133,12 +133,13 @@ def gpu_run(w, steps, warmup, kernel_timing):
     log(f"[bench] timed region done: {elapsed:.4f} s")
     timing = None
     if kernel_timing:
-        reps = 50
-        log(f"[bench] kernel timing: HIP events around {reps} back-to-back launches per kernel; "
-            "HIP start/stop events on every iteration-kernel launch of 10 solves")
-        timing = ctx.time_kernels(w.dt, reps, events=True)
-        timing["reps"] = reps
-        timing["in_solve"] = ctx.time_kernels(w.dt, 10)
+        solves, reps = 20, 50
+        log(f"[bench] kernel timing: HIP start/stop events on every iteration-kernel launch of "
+            f"{solves} solves; HIP events around {reps} back-to-back launches per kernel")
+        timing = ctx.time_kernels(w.dt, solves)
+        timing["solves"] = solves
+        timing["back_to_back"] = ctx.time_kernels(w.dt, reps, events=True)
+        timing["back_to_back_reps"] = reps
     cfg = ctx.launch_config()
     cfg["plan"] = ctx.plan(0)
     ctx.close()
@@ -436,9 +437,9 @@ def main():
     if timing:
         for k in ab:
             avg = timing[f"{k}_us"] * 1e-6
-            kernels[k] = dict(avg_us=round(avg * 1e6, 3), launches=timing["reps"], alg_bytes=ab[k],
+            kernels[k] = dict(avg_us=round(avg * 1e6, 3), solves=timing["solves"], alg_bytes=ab[k],
                               achieved_gbs=round(ab[k] / avg / 1e9, 2),
-                              in_solve_us=round(timing["in_solve"][f"{k}_us"], 3))
+                              back_to_back_us=round(timing["back_to_back"][f"{k}_us"], 3))
         dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
         kd = kernels[dom]
         roof = dict(bound="hbm", kernel=KERNEL_NAMES[dom], achieved=kd["achieved_gbs"],

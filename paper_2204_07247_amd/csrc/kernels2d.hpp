@@ -440,39 +440,6 @@ __global__ __launch_bounds__(512) void k_col_iter(const InstDev* const* __restri
 // Row kernel of one PAGD iteration (end of j, start of j+1).
 // ---------------------------------------------------------------------------
 template <class PX>
-__device__ __forceinline__ void pfc_forward_row(const InstDev* I, const double (&vb)[PX::RMAX],
-                                                const Twiddles<PX>& tw, c2* lds, int row, int t) {
-  constexpr int RM = PX::RMAX;
-  c2 z[RM];
-#pragma unroll
-  for (int m = 0; m < RM; ++m) z[m] = c2{vb[m] * vb[m] * vb[m], vb[m]};
-  fft<PX, false>(z, lds, tw, t);
-  unpack_store<PX>(z, lds, gp(I->S), row, gp(I->S) + I->field_stride, row, I->rows, t);
-}
-
-// FCH pointwise terms at v_breve with Laplacian lv:
-//   F' = (v^2-1)(v+tau), F'' = 3v^2 - 1 + 2 tau v, omega = eps^2 lv - F',
-//   p = -F'' omega - eta2 F'.
-template <class PX>
-__device__ __forceinline__ void fch_forward_row(const InstDev* I, const double (&vb)[PX::RMAX],
-                                                const double (&lv)[PX::RMAX], const Twiddles<PX>& tw,
-                                                c2* lds, int row, int t) {
-  constexpr int RM = PX::RMAX;
-  const double e2 = I->eps * I->eps, tau = I->tau, eta2 = I->eta2;
-  c2 z[RM];
-#pragma unroll
-  for (int m = 0; m < RM; ++m) {
-    const double u = vb[m];
-    const double f1 = (u * u - 1.0) * (u + tau);
-    const double f2 = 3.0 * u * u - 1.0 + 2.0 * tau * u;
-    const double om = e2 * lv[m] - f1;
-    z[m] = c2{f1, -f2 * om - eta2 * f1};
-  }
-  fft<PX, false>(z, lds, tw, t);
-  unpack_store<PX>(z, lds, gp(I->S), row, gp(I->S) + I->field_stride, row, I->rows, t);
-}
-
-template <class PX>
 __device__ __forceinline__ void pair_forward(const double (&a)[PX::RMAX], const double (&b)[PX::RMAX],
                                              const Twiddles<PX>& tw, c2* lds, GLB c2* FA, int ra,
                                              GLB c2* FB, int rb, int rows, int t) {
@@ -482,6 +449,65 @@ __device__ __forceinline__ void pair_forward(const double (&a)[PX::RMAX], const 
   for (int m = 0; m < RM; ++m) z[m] = c2{a[m], b[m]};
   fft<PX, false>(z, lds, tw, t);
   unpack_store<PX>(z, lds, FA, ra, FB, rb, rows, t);
+}
+
+// The forward transforms that start a PFC iteration, for the two real rows
+// r0, r0 + 1 of v_breve: field 0 <- (v^3)^, field 1 <- v^.  Rows are paired
+// within a field so that each transform writes whole 128-byte lines of the
+// tiled spectral layout (two adjacent rows of one tile).
+template <class PX>
+__device__ __forceinline__ void pfc_forward_pair(const InstDev* I, const double (&vb)[2][PX::RMAX],
+                                                 const Twiddles<PX>& tw, c2* lds, int r0, int t) {
+  constexpr int RM = PX::RMAX;
+  GLB c2* S = gp(I->S);
+  const uint32_t fs = (uint32_t)I->field_stride;
+  c2 z[RM];
+#pragma unroll
+  for (int m = 0; m < RM; ++m) z[m] = c2{vb[0][m] * vb[0][m] * vb[0][m], vb[1][m] * vb[1][m] * vb[1][m]};
+  fft<PX, false>(z, lds, tw, t);
+  unpack_store<PX>(z, lds, S, r0, S, r0 + 1, I->rows, t);
+  pair_forward<PX>(vb[0], vb[1], tw, lds, S + fs, r0, S + fs, r0 + 1, I->rows, t);
+}
+
+// FCH pointwise terms at v_breve with Laplacian lv:
+//   F' = (v^2-1)(v+tau), F'' = 3v^2 - 1 + 2 tau v, omega = eps^2 lv - F',
+//   p = -F'' omega - eta2 F'.
+// Forward transforms for the rows r0, r0 + 1, paired within each field:
+// field 0 <- (F')^, field 1 <- p^, field 2 <- v^.
+template <class PX>
+__device__ __forceinline__ void fch_forward_pair(const InstDev* I, const double (&vb)[2][PX::RMAX],
+                                                 const double (&lv)[2][PX::RMAX], const Twiddles<PX>& tw,
+                                                 c2* lds, int r0, int t) {
+  constexpr int RM = PX::RMAX;
+  const double e2 = I->eps * I->eps, tau = I->tau, eta2 = I->eta2;
+  GLB c2* S = gp(I->S);
+  const uint32_t fs = (uint32_t)I->field_stride;
+  const int rows = I->rows;
+  c2 z[RM];
+  // p first: lv is no longer needed once it is formed.
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+    double pr[2];
+#pragma unroll
+    for (int row = 0; row < 2; ++row) {
+      const double u = vb[row][m];
+      const double f1 = (u * u - 1.0) * (u + tau);
+      const double f2 = 3.0 * u * u - 1.0 + 2.0 * tau * u;
+      const double om = e2 * lv[row][m] - f1;
+      pr[row] = -f2 * om - eta2 * f1;
+    }
+    z[m] = c2{pr[0], pr[1]};
+  }
+  fft<PX, false>(z, lds, tw, t);
+  unpack_store<PX>(z, lds, S + fs, r0, S + fs, r0 + 1, rows, t);
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+    const double u0 = vb[0][m], u1 = vb[1][m];
+    z[m] = c2{(u0 * u0 - 1.0) * (u0 + tau), (u1 * u1 - 1.0) * (u1 + tau)};
+  }
+  fft<PX, false>(z, lds, tw, t);
+  unpack_store<PX>(z, lds, S, r0, S, r0 + 1, rows, t);
+  pair_forward<PX>(vb[0], vb[1], tw, lds, S + 2 * fs, r0, S + 2 * fs, r0 + 1, rows, t);
 }
 
 // MPS: implicit midpoint (the nonlinear terms are taken at
@@ -529,9 +555,9 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
     c2 v[RM];
     load_pack<PX>(v, gp(I->S), r0, gp(I->S), r0 + 1, rows, t);
     fft<PX, true>(v, lds, tw, t);
+    double vb[2][RM];
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
-      double vb[RM];
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
         const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
@@ -542,54 +568,82 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
         const uint64_t db = dbits(fabs(d));
         dmax = db > dmax ? db : dmax;
         const double yn = x1 + lamn * (x1 - a[row][m]);
-        vb[m] = mp ? th * yn + (1.0 - th) * uu[row][m] : yn;
+        vb[row][m] = mp ? th * yn + (1.0 - th) * uu[row][m] : yn;
       }
-      pfc_forward_row<PX>(I, vb, tw, lds, r0 + row, t);
     }
+    pfc_forward_pair<PX>(I, vb, tw, lds, r0, t);
   } else {
     const auto dxj = gp(I->DX[j % 3]);
     const auto dxm = gp(I->DX[(j + 2) % 3]);
     auto dxn = gp(I->DX[(j + 1) % 3]);
     const auto dun = gp(I->dun);
-    double vbs[2][RM];
-#pragma unroll
-    for (int row = 0; row < 2; ++row) {
-      const int r = r0 + row;
-      double a[RM], b[RM], la[RM], lb[RM], uu[RM], lu[RM];
-#pragma unroll
-      for (int m = 0; m < RM; ++m) {
-        const uint32_t idx = (uint32_t)r * N + t + m * T;
-        a[m] = xj[idx];
-        b[m] = xm[idx];
-        la[m] = dxj[idx];
-        lb[m] = dxm[idx];
-        uu[m] = mp ? un[idx] : 0.0;
-        lu[m] = mp ? dun[idx] : 0.0;
-      }
+    // Both real rows of the pair at once, one transform per spectral field:
+    // the direction d (field 0) first, then its Laplacian (field 1), so
+    // every spectral read covers whole 128-byte lines of the tiled layout.
+    // The real-space loads of each half follow its transform, which keeps
+    // the kernel within the registers of two waves per SIMD.
+    double vbs[2][RM], lv[2][RM];
+    {
       c2 v[RM];
-      load_pack<PX>(v, gp(I->S), r, gp(I->S) + fs, r, rows, t);
+      load_pack<PX>(v, gp(I->S), r0, gp(I->S), r0 + 1, rows, t);
       fft<PX, true>(v, lds, tw, t);
-      double lv[RM];
+      double a[2][RM], b[2][RM], uu[2][RM];
 #pragma unroll
-      for (int m = 0; m < RM; ++m) {
-        const uint32_t idx = (uint32_t)r * N + t + m * T;
-        const double d = v[m].x, ld = v[m].y;
-        const double y = a[m] + lam * (a[m] - b[m]);
-        const double ly = la[m] + lam * (la[m] - lb[m]);
-        const double x1 = y + s * d;
-        const double lx1 = ly + s * ld;
-        xn[idx] = x1;
-        dxn[idx] = lx1;
-        const uint64_t db = dbits(fabs(d));
-        dmax = db > dmax ? db : dmax;
-        const double yn = x1 + lamn * (x1 - a[m]);
-        const double lyn = lx1 + lamn * (lx1 - la[m]);
-        vbs[row][m] = mp ? th * yn + (1.0 - th) * uu[m] : yn;
-        lv[m] = mp ? th * lyn + (1.0 - th) * lu[m] : lyn;
+      for (int row = 0; row < 2; ++row) {
+#pragma unroll
+        for (int m = 0; m < RM; ++m) {
+          const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+          a[row][m] = xj[idx];
+          b[row][m] = xm[idx];
+          uu[row][m] = mp ? un[idx] : 0.0;
+        }
       }
-      fch_forward_row<PX>(I, vbs[row], lv, tw, lds, r, t);
+#pragma unroll
+      for (int row = 0; row < 2; ++row) {
+#pragma unroll
+        for (int m = 0; m < RM; ++m) {
+          const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+          const double d = row ? v[m].y : v[m].x;
+          const double y = a[row][m] + lam * (a[row][m] - b[row][m]);
+          const double x1 = y + s * d;
+          xn[idx] = x1;
+          const uint64_t db = dbits(fabs(d));
+          dmax = db > dmax ? db : dmax;
+          const double yn = x1 + lamn * (x1 - a[row][m]);
+          vbs[row][m] = mp ? th * yn + (1.0 - th) * uu[row][m] : yn;
+        }
+      }
     }
-    pair_forward<PX>(vbs[0], vbs[1], tw, lds, gp(I->S) + 2 * fs, r0, gp(I->S) + 2 * fs, r0 + 1, rows, t);
+    {
+      c2 v[RM];
+      load_pack<PX>(v, gp(I->S) + fs, r0, gp(I->S) + fs, r0 + 1, rows, t);
+      fft<PX, true>(v, lds, tw, t);
+      double la[2][RM], lb[2][RM], lu[2][RM];
+#pragma unroll
+      for (int row = 0; row < 2; ++row) {
+#pragma unroll
+        for (int m = 0; m < RM; ++m) {
+          const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+          la[row][m] = dxj[idx];
+          lb[row][m] = dxm[idx];
+          lu[row][m] = mp ? dun[idx] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int row = 0; row < 2; ++row) {
+#pragma unroll
+        for (int m = 0; m < RM; ++m) {
+          const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+          const double ld = row ? v[m].y : v[m].x;
+          const double ly = la[row][m] + lam * (la[row][m] - lb[row][m]);
+          const double lx1 = ly + s * ld;
+          dxn[idx] = lx1;
+          const double lyn = lx1 + lamn * (lx1 - la[row][m]);
+          lv[row][m] = mp ? th * lyn + (1.0 - th) * lu[row][m] : lyn;
+        }
+      }
+    }
+    fch_forward_pair<PX>(I, vbs, lv, tw, lds, r0, t);
   }
   const uint64_t bm = block_max_bits(dmax, red);
   if (threadIdx.x == 0) atomicMax((unsigned long long*)&I->norms[j], (unsigned long long)bm);
@@ -675,19 +729,16 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* const* __restrict__ 
   }
   if constexpr (MODEL == MODEL_PFC) {
     pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, gp(I->G), r0 + 1, rows, t);
+    double vb[2][RM];
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
-      double vb[RM];
 #pragma unroll
-      for (int m = 0; m < RM; ++m) vb[m] = th * x0v[row][m] + (1.0 - th) * uv[row][m];
-      pfc_forward_row<PX>(I, vb, tw, lds, r0 + row, t);
+      for (int m = 0; m < RM; ++m) vb[row][m] = th * x0v[row][m] + (1.0 - th) * uv[row][m];
     }
+    pfc_forward_pair<PX>(I, vb, tw, lds, r0, t);
   } else {
-#pragma unroll
-    for (int row = 0; row < 2; ++row) {
-      const int r = r0 + row;
-      pair_forward<PX>(gv[row], x0v[row], tw, lds, gp(I->G), r, gp(I->G) + fs, r, rows, t);
-    }
+    pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, gp(I->G), r0 + 1, rows, t);
+    pair_forward<PX>(x0v[0], x0v[1], tw, lds, gp(I->G) + fs, r0, gp(I->G) + fs, r0 + 1, rows, t);
     if (th != 1.0) pair_forward<PX>(uv[0], uv[1], tw, lds, gp(I->G) + 2 * fs, r0, gp(I->G) + 2 * fs, r0 + 1, rows, t);
   }
   const double bs0 = block_sum(s0, red);
@@ -766,35 +817,28 @@ __global__ __launch_bounds__(256) void k_row_start_fch(const InstDev* const* __r
   Twiddles<PX> tw;
   load_twiddles<PX>(tw, I->tw_x, t);
   double lx[2][RM], lu[2][RM];
-  if (!mp) {
-    c2 v[RM];
-    load_pack<PX>(v, gp(I->G) + fs, r0, gp(I->G) + fs, r0 + 1, rows, t);
+  c2 v[RM];
+  load_pack<PX>(v, gp(I->G) + fs, r0, gp(I->G) + fs, r0 + 1, rows, t);
+  fft<PX, true>(v, lds, tw, t);
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+    lx[0][m] = v[m].x;
+    lx[1][m] = v[m].y;
+    lu[0][m] = 0.0;
+    lu[1][m] = 0.0;
+  }
+  if (mp) {
+    load_pack<PX>(v, gp(I->G) + 2 * fs, r0, gp(I->G) + 2 * fs, r0 + 1, rows, t);
     fft<PX, true>(v, lds, tw, t);
 #pragma unroll
     for (int m = 0; m < RM; ++m) {
-      lx[0][m] = v[m].x;
-      lx[1][m] = v[m].y;
-      lu[0][m] = 0.0;
-      lu[1][m] = 0.0;
-    }
-  } else {
-#pragma unroll
-    for (int row = 0; row < 2; ++row) {
-      c2 v[RM];
-      const int r = r0 + row;
-      load_pack<PX>(v, gp(I->G) + fs, r, gp(I->G) + 2 * fs, r, rows, t);
-      fft<PX, true>(v, lds, tw, t);
-#pragma unroll
-      for (int m = 0; m < RM; ++m) {
-        lx[row][m] = v[m].x;
-        lu[row][m] = v[m].y;
-      }
+      lu[0][m] = v[m].x;
+      lu[1][m] = v[m].y;
     }
   }
-  double vbs[2][RM];
+  double vbs[2][RM], lv[2][RM];
 #pragma unroll
   for (int row = 0; row < 2; ++row) {
-    double lv[RM];
 #pragma unroll
     for (int m = 0; m < RM; ++m) {
       const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
@@ -803,11 +847,10 @@ __global__ __launch_bounds__(256) void k_row_start_fch(const InstDev* const* __r
       if (mp) gp(I->dun)[idx] = lu[row][m];
       const double x0 = gp(I->X[0])[idx];
       vbs[row][m] = mp ? th * x0 + (1.0 - th) * gp(I->un)[idx] : x0;
-      lv[m] = mp ? th * lx[row][m] + (1.0 - th) * lu[row][m] : lx[row][m];
+      lv[row][m] = mp ? th * lx[row][m] + (1.0 - th) * lu[row][m] : lx[row][m];
     }
-    fch_forward_row<PX>(I, vbs[row], lv, tw, lds, r0 + row, t);
   }
-  pair_forward<PX>(vbs[0], vbs[1], tw, lds, gp(I->S) + 2 * fs, r0, gp(I->S) + 2 * fs, r0 + 1, rows, t);
+  fch_forward_pair<PX>(I, vbs, lv, tw, lds, r0, t);
 }
 
 }  // namespace pfch
