@@ -254,15 +254,19 @@ __device__ __forceinline__ ColPos col_pos(int T, int ntiles, int lb) {
 template <class P, class F>
 __device__ __forceinline__ void col0_mirror(const c2 (&v)[P::RMAX], c2* lds0, bool mine, int t, F use) {
   constexpr int N = P::N, T = P::T;
+  // Indices from opaque copies of t: computed inside the (rare) branches
+  // rather than ahead of them and held live across the transforms.
   if (mine) {
+    const int ts = opaque_i(t);
 #pragma unroll
-    for (int m = 0; m < P::RMAX; ++m) lds0[lds_idx(t + m * T)] = v[m];
+    for (int m = 0; m < P::RMAX; ++m) lds0[lds_idx(ts + m * T)] = v[m];
   }
   __syncthreads();
   if (mine) {
+    const int tl = opaque_i(t);
 #pragma unroll
     for (int m = 0; m < P::RMAX; ++m) {
-      const int ky = t + m * T;
+      const int ky = tl + m * T;
       const c2 w = lds0[lds_idx(ky == 0 ? 0 : N - ky)];
       use(m, c2{w.x, -w.y});
     }

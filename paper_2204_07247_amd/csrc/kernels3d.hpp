@@ -224,7 +224,10 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
   const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
   const double inv_p = I->inv_p, e1 = 1.0 - I->eps;
   const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
-  auto at = [&](int m) { return sidx(rows, ky + (t + m * T) * ny, kp); };
+  // Element m of this thread: z index tt + m T for a thread index tt.  Each
+  // phase takes its own opaque copy of t so that addresses and wavenumbers
+  // are recomputed there instead of being held live across the transforms.
+  auto at = [&](int tt, int m) { return sidx(rows, ky + (tt + m * T) * ny, kp); };
   auto coef = [&](int f, double q) -> double {
     return f == 1 ? inv_m * aot + q * (e1 - 2.0 * q + q * q) : q;
   };
@@ -235,19 +238,20 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
   c2 v[RM], nxt[PREFETCH ? RM : 1], acc[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
-    v[m] = gload(S + at(m));
+    v[m] = gload(S + at(t, m));
     acc[m] = c2{0.0, 0.0};
   }
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
     if constexpr (PREFETCH) {
 #pragma unroll
-      for (int m = 0; m < RM; ++m) nxt[m] = f == 0 ? gload(S + fs + at(m)) : gload(gp(I->ghat) + at(m));
+      for (int m = 0; m < RM; ++m) nxt[m] = f == 0 ? gload(S + fs + at(t, m)) : gload(gp(I->ghat) + at(t, m));
     }
     fft<PZ, false>(v, lds, tw, t);
+    const int tf = opaque(t);
 #pragma unroll
     for (int m = 0; m < RM; ++m) {
-      const double q = q3(I, kp, ky, t + m * T);
+      const double q = q3(I, kp, ky, tf + m * T);
       const double c = pair ? 0.5 * (coef(f, q) + coef(f, q + kxn2)) : coef(f, q);
       acc[m] = cadd(acc[m], cscale(v[m], c));
     }
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
       if constexpr (PREFETCH)
         v[m] = nxt[m];
       else
-        v[m] = f == 0 ? gload(S + fs + at(m)) : gload(gp(I->ghat) + at(m));
+        v[m] = f == 0 ? gload(S + fs + at(tf, m)) : gload(gp(I->ghat) + at(tf, m));
     }
   }
 #pragma unroll
@@ -274,8 +278,9 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
     bad |= !(Lq > 0.0);
     return -inv_p * rcp_pos(Lq);
   };
+  const int te = opaque(t);
 #pragma unroll
-  for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], scale(q3(I, kp, ky, t + m * T)));
+  for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], scale(q3(I, kp, ky, te + m * T)));
   if (pos.has_pair)
     col0_mirror<PZ>(acc, lds, pair, t, [&](int m, c2 w) {
       const double q = q3(I, 0, ky, opaque(t + m * T));
@@ -283,8 +288,9 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
       v[m] = cadd(cscale(acc[m], 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn)));
     });
   fft<PZ, true>(v, lds, tw, t);
+  const int ts = opaque(t);
 #pragma unroll
-  for (int m = 0; m < RM; ++m) gstore(S + at(m), v[m]);
+  for (int m = 0; m < RM; ++m) gstore(S + at(ts, m), v[m]);
   if (bad) atomicOr(I->flags, FLAG_PRECOND);
 }
 
