@@ -18,6 +18,10 @@ accelerated schemes" (arXiv 2204.07247):
 * ``pagd``      objective G_N, projected gradient (eq. obj:G'), averaged-Newton
                 preconditioner (Sec. 3.4.1) and PGD / PAGD (Alg. 1, Alg. 2).
 * ``driver``    fixed-step time marching (Alg. 3 without step adaptation).
+* ``imex``      linear IMEX steps LBDF2 / LMP (Sec. 3.1.1,
+                eq. eqn:FCH-semidis-simplicit).
+* ``adaptive``  AM3 / midAB2 error estimators and the step-size controller
+                of Alg. 3 (Sec. 3.1.2).
 * ``dft``       brute-force O(P^2) DFT sums, used only to pin ``spectral``.
 * ``newton``    dense Newton solve of the step equation, used only to pin the
                 PAGD fixed point on tiny grids.
