@@ -138,6 +138,64 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st);
 int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const double* u_n,
                const double* u_nm1, double* x, pfch_stats* st);
 
+/*
+ * Adaptive time stepping (Sec. 3.1.2, Alg. 3), 2D grids.
+ *
+ * One call is one pass of the loop body of Alg. 3 for every instance: a
+ * tentative solve with step size res[i].dt_try, an error estimate ERR, the
+ * decision, and the next tentative size.
+ *   AM3 (eq. fml:AM3-high-sol, fml:AM3-err), rho = dt~/dt_n (0 on the first
+ *   step, where the R(u^{n-1}) term drops):
+ *     u^ = u^n + dt~/6 [(3+2rho)/(1+rho) R(u~) + (3+rho) R(u^n)
+ *                       - rho^2/(1+rho) R(u^{n-1})],
+ *     ERR = ||u~ - u^||_2 / ||u^||_2,  R(v) = M Delta mu(v).
+ *   midAB2 (eq. fml:midAB2-high-sol, fml:midAB2-err): u^ is the quadratic
+ *     through u^n, u^{n-1}, u^{n-2} at t_n + dt~ and
+ *     ERR = ||u~ - u^|| / ||u^|| / (1 - 1/(24 R_n)),
+ *     R_n = 1/24 + (1 + dt_n/dt~)(1 + 2 dt_n/dt~ + dt_{n-1}/dt~)/8;
+ *     used once three solutions exist, AM3 before that.
+ *   Accept when ERR <= tol or dt~ <= dt_min: u^{n+1} = u~, t += dt~.
+ *   Next size (eqs. fml:time-step, fml:time-step-med):
+ *     dt_try = max(dt_min, min(0.9 (tol/ERR)^(1/3) dt~, dt_max)),
+ *   also after a rejection.  A tentative solve that fails counts as
+ *   ERR = +inf (rejected, next size dt_min).
+ * estimator: PFCH_EST_AUTO = midAB2 for PFCH_MP, AM3 otherwise.
+ * The history the estimators need (u^{n-2}, R(u^n), R(u^{n-1}), dt_{n-1})
+ * is kept by the context across pfch_step_adaptive calls; pfch_set_state
+ * and pfch_step restart it from u^n, u^{n-1}.  Norm sums are taken in a
+ * fixed order, so results do not depend on batching.
+ * res: host array of n_inst; dt_try is read (> 0) and written.  Returns
+ * PFCH_OK, or the solve's error code when an instance's solve failed at
+ * dt~ <= dt_min (that instance cannot advance).  3D instances:
+ * PFCH_E_UNSUPPORTED.
+ */
+enum { PFCH_EST_AUTO = 0, PFCH_EST_AM3 = 1, PFCH_EST_MIDAB2 = 2 };
+
+typedef struct pfch_adapt_desc {
+  double tol;     /* stepping tolerance TOL > 0 */
+  double dt_min;  /* 0 < dt_min <= dt_max */
+  double dt_max;
+  int32_t estimator;
+  int32_t reserved; /* must be 0 */
+} pfch_adapt_desc;
+
+typedef struct pfch_adapt_result {
+  double dt_try;    /* in: tentative step size; out: the next one */
+  double dt;        /* out: size of this attempt */
+  double err;       /* out: ERR (+inf if the solve failed) */
+  int32_t accepted; /* out: 1 = history advanced */
+  int32_t estimator;/* out: PFCH_EST_AM3 or PFCH_EST_MIDAB2, as used */
+  pfch_stats solve; /* out: the tentative solve */
+} pfch_adapt_result;
+
+int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* a, pfch_adapt_result* res);
+
+/* R(v) = M Delta mu(v) (the right-hand side of the PDE, Sec. 2) of instance
+ * `inst`'s model on its grid, v and out device arrays of Nx*Ny doubles (may
+ * not alias); 2D only.  Uses the instance's transform workspace; its state is
+ * not changed. */
+int pfch_rhs(pfch_ctx* ctx, int32_t inst, const double* v, double* out);
+
 /* Statistics detail of pfch_step when st != NULL: 0 = iterations, status and
  * ||d||_inf only (read from the convergence records, no extra
  * synchronisation); 1 (default) = also beta and the mass of the accepted

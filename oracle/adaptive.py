@@ -112,13 +112,15 @@ class AdaptiveRun:
     """
 
     def __init__(self, grid, model, scheme, u0, tol, dt_min, dt_max, estimator=AUTO,
-                 mobility=1.0, **solver):
+                 mobility=1.0, solver=None):
+        """``solver``: keyword arguments of the PAGD driver (s, etas, tol,
+        max_iter, ...); ``tol`` here is the stepping tolerance TOL."""
         self.grid, self.model, self.scheme = grid, model, scheme
         self.tol, self.dt_min, self.dt_max = float(tol), float(dt_min), float(dt_max)
         self.estimator = estimator
         self.M = float(mobility)
         if scheme in ("bdf2", "mp"):
-            self.sim = _driver.Simulation(grid, model, scheme, mobility=mobility, **solver)
+            self.sim = _driver.Simulation(grid, model, scheme, mobility=mobility, **(solver or {}))
         else:
             self.sim = None
         u0 = np.array(u0, dtype=np.float64)

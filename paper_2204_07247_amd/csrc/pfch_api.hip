@@ -125,6 +125,12 @@ struct Instance {
   double fno_norm[4] = {0, 1, 1, 1};
   double* xguess = nullptr;  // learned guess buffer (allocated on first attach)
   double* gpart = nullptr;   // FNO_SUM_BLOCKS partial sums of the network output
+  // adaptive stepping (buffers allocated on first use)
+  double* Um2 = nullptr;     // u^{n-2}
+  double* R[3] = {nullptr, nullptr, nullptr};  // R(u^n), R(u^{n-1}), R(u~)
+  int hist = 1;              // solutions held: u^n, u^{n-1}, u^{n-2}
+  bool r_valid = false;      // R[0] (and R[1] when hist >= 2) match the history
+  double dt_nm1 = 0.0;       // dt_{n-1}, valid when hist == 3
   std::vector<void*> allocs;
 };
 
@@ -160,6 +166,8 @@ struct Group {
   InstDev** d_members = nullptr;
   StepArgs* d_args = nullptr;
   StepArgs* h_args = nullptr;  // pinned
+  const double** d_rptr = nullptr;  // R(v) launches: [member] sources, then destinations
+  const double** h_rptr = nullptr;  // pinned staging
 };
 
 }  // namespace
@@ -181,6 +189,10 @@ struct pfch_ctx {
   double* d_scale = nullptr;   // 1/P per instance
   double* d_mass = nullptr;
   double* h_mass = nullptr;    // pinned
+  EstArgs* d_est = nullptr;    // adaptive error estimate, per instance
+  EstArgs* h_est = nullptr;    // pinned
+  double* d_est_part = nullptr;  // [n][2][EST_BLOCKS]
+  double* h_est_part = nullptr;  // pinned
   std::map<int, c2*> twiddles;
   std::map<int, hipGraphExec_t> graphs;  // key: chunk length K
   std::vector<hipGraph_t> graph_defs;
@@ -1186,6 +1198,20 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
     G.d_args = (StepArgs*)p;
     if ((rc = halloc(ctx->host_allocs, &p, sizeof(StepArgs) * nm))) goto fail;
     G.h_args = (StepArgs*)p;
+    if ((rc = dalloc(ctx->allocs, &p, sizeof(double*) * 2 * nm))) goto fail;
+    G.d_rptr = (const double**)p;
+    if ((rc = halloc(ctx->host_allocs, &p, sizeof(double*) * 2 * nm))) goto fail;
+    G.h_rptr = (const double**)p;
+    if (G.ndim == 2) {
+      const void* rr[] = {G.rs.rhs_fwd, G.rs.rhs_mid, G.rs.rhs_inv};
+      for (const void* f : rr)
+        if (f && G.srow_lds > 65536)
+          (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.srow_lds);
+      const void* rc2[] = {G.cs.rhs_lap, G.cs.rhs};
+      for (const void* f : rc2)
+        if (f && G.scol_lds > 65536)
+          (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.scol_lds);
+    }
     const void* fs[] = {G.rs.iter, G.rs.setup, G.rs.start_fch};
     for (const void* f : fs)
       if (f && G.row_lds > 65536)
@@ -1213,6 +1239,14 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   ctx->h_dsts = (double**)p;
   if ((rc = halloc(ctx->host_allocs, &p, sizeof(double) * n_inst))) goto fail;
   ctx->h_mass = (double*)p;
+  if ((rc = dalloc(ctx->allocs, &p, sizeof(EstArgs) * n_inst))) goto fail;
+  ctx->d_est = (EstArgs*)p;
+  if ((rc = halloc(ctx->host_allocs, &p, sizeof(EstArgs) * n_inst))) goto fail;
+  ctx->h_est = (EstArgs*)p;
+  if ((rc = dalloc(ctx->allocs, &p, sizeof(double) * 2 * EST_BLOCKS * n_inst))) goto fail;
+  ctx->d_est_part = (double*)p;
+  if ((rc = halloc(ctx->host_allocs, &p, sizeof(double) * 2 * EST_BLOCKS * n_inst))) goto fail;
+  ctx->h_est_part = (double*)p;
   {
     std::vector<InstDev*> ptrs(n_inst);
     std::vector<double> scale(n_inst);
@@ -1482,6 +1516,8 @@ int pfch_set_state(pfch_ctx* ctx, int32_t inst, const double* u_n, const double*
   I.t = t;
   I.dt_prev = u_nm1 ? dt_prev : 0.0;
   I.step_index = step_index;
+  I.hist = I.has_prev ? 2 : 1;
+  I.r_valid = false;
   return PFCH_OK;
 }
 
@@ -1500,16 +1536,26 @@ int pfch_get_state(pfch_ctx* ctx, int32_t inst, double* u_n, double* u_nm1, doub
   return PFCH_OK;
 }
 
-int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
-  if (!ctx || !dt) return PFCH_E_INVAL;
+namespace {
+
+// Outcome of the tentative solves of one step of every instance.
+struct SolveOut {
+  std::vector<int> status, iters, guess;
+  std::vector<double> dn, a;
+};
+
+// Tentative solve of every instance at step size dt[i]: set-up, PAGD
+// iterations, and the learned-guess fallback.  Nothing is accepted.
+int solve_all(pfch_ctx* ctx, const double* dt, SolveOut& o) {
   const int n = (int)ctx->inst.size();
-  for (int i = 0; i < n; ++i)
-    if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return PFCH_E_INVAL;
+  o.status.assign(n, PFCH_OK);
+  o.iters.assign(n, 0);
+  o.guess.assign(n, 0);  // 0 extrapolated, 1 learned, 2 learned then extrapolated
+  o.dn.assign(n, 0.0);
+  o.a.assign(n, 0.0);
   std::vector<int> active(n);
-  std::vector<double> as(n);
   int rc;
   for (int i = 0; i < n; ++i) active[i] = i;
-  std::vector<int> guess_kind(n, 0);  // 0 extrapolated, 1 learned, 2 learned then extrapolated
   for (auto& G : ctx->groups) {
     for (size_t k = 0; k < G.members.size(); ++k) {
       Instance& I = ctx->inst[G.members[k]];
@@ -1517,9 +1563,9 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
       if (I.fno && I.d.guess == 1 && I.has_prev) {
         if ((rc = learned_guess(ctx, I, ss.rho))) return rc;
         ss.xin = I.xguess;
-        guess_kind[G.members[k]] = 1;
+        o.guess[G.members[k]] = 1;
       }
-      as[G.members[k]] = ss.a;
+      o.a[G.members[k]] = ss.a;
       G.h_args[k] = to_args(ss);
     }
     const unsigned nm = (unsigned)G.members.size();
@@ -1532,28 +1578,36 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
   // extrapolated guess: the step is solved again from it.
   std::vector<int> retry;
   for (int i = 0; i < n; ++i) {
-    if (guess_kind[i] != 1) continue;
+    if (o.guess[i] != 1) continue;
     int it = 0;
     double d = 0.0;
     if (status_of(ctx->inst[i], ctx->h_recs[i], &it, &d) == PFCH_OK) continue;
     Instance& I = ctx->inst[i];
     if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, dt[i])))) return rc;
-    guess_kind[i] = 2;
+    o.guess[i] = 2;
     retry.push_back(i);
   }
   if (!retry.empty() && (rc = run_iterations(ctx, retry))) return rc;
-  int first_err = PFCH_OK;
-  std::vector<int> status(n), iters(n);
-  std::vector<double> dn(n);
-  const bool want_mass = st && ctx->stats_detail > 0;
+  for (int i = 0; i < n; ++i) o.status[i] = status_of(ctx->inst[i], ctx->h_recs[i], &o.iters[i], &o.dn[i]);
+  return PFCH_OK;
+}
+
+// The converged iterate of instance I after solve_all.
+const double* solution_of(const Instance& I, const StopRec& r) { return I.h.X[(r.stop_iter + 1) % 3]; }
+
+// Accept the tentative solutions of the instances with take[i]: u^{n+1}
+// into the history (with u^{n-2} kept for the adaptive estimators), time
+// and step counters advanced; with want_mass, the mean of each accepted
+// solution lands in ctx->h_mass after the stream is synchronised.
+int accept_solutions(pfch_ctx* ctx, const std::vector<char>& take, const double* dt, const SolveOut& o,
+                     bool want_mass, bool adaptive) {
+  const int n = (int)ctx->inst.size();
+  int rc;
   for (int i = 0; i < n; ++i) {
     Instance& I = ctx->inst[i];
-    status[i] = status_of(I, ctx->h_recs[i], &iters[i], &dn[i]);
     ctx->h_dsts[i] = nullptr;
-    if (status[i] != PFCH_OK) {
-      if (first_err == PFCH_OK) first_err = status[i];
-      continue;
-    }
+    if (!take[i]) continue;
+    if (adaptive) std::swap(I.Um2, I.U[1 - I.ucur]);  // u^{n-1} becomes u^{n-2}
     ctx->h_dsts[i] = I.U[1 - I.ucur];
   }
   HIPCHK(hipMemcpyAsync(ctx->d_dsts, ctx->h_dsts, sizeof(double*) * n, hipMemcpyHostToDevice, ctx->stream));
@@ -1569,41 +1623,289 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
     const double* part = ctx->d_part;
     int nb = ACC_BLOCKS, nn = n;
     const double* scale = ctx->d_scale;
-    double* o = ctx->d_mass;
-    void* a[] = {&part, &nb, &nn, &scale, &o};
+    double* o2 = ctx->d_mass;
+    void* a[] = {&part, &nb, &nn, &scale, &o2};
     if ((rc = launch((const void*)&k_sum_parts, dim3((n + 63) / 64), dim3(64), 0, a, ctx->stream))) return rc;
     HIPCHK(hipMemcpyAsync(ctx->h_mass, ctx->d_mass, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
   }
   for (int i = 0; i < n; ++i) {
-    if (status[i] != PFCH_OK) continue;
+    if (!take[i]) continue;
     Instance& I = ctx->inst[i];
     I.ucur = 1 - I.ucur;
+    if (adaptive) {
+      I.dt_nm1 = I.dt_prev;
+      I.hist = std::min(I.hist + 1, 3);
+    } else {
+      I.hist = 2;  // u^{n-2} is not kept by plain steps
+      I.r_valid = false;
+    }
     I.has_prev = true;
     I.dt_prev = dt[i];
     I.t += dt[i];
     I.step_index += 1;
-    I.last_iters = iters[i];
+    I.last_iters = o.iters[i];
   }
+  return PFCH_OK;
+}
+
+int fill_stats(pfch_ctx* ctx, const SolveOut& o, int i, bool want_mass, bool accepted, pfch_stats& s) {
+  Instance& I = ctx->inst[i];
+  std::memset(&s, 0, sizeof(s));
+  s.status = o.status[i];
+  s.iters = o.iters[i];
+  s.dnorm_inf = o.dn[i];
+  s.fft_pairs = fft_pairs_of(I, o.iters[i]);
+  s.guess = o.guess[i];
+  s.mass = (want_mass && accepted) ? ctx->h_mass[i] : NAN;
+  if (ctx->stats_detail > 0) {
+    int rc = betas_host(ctx, I, o.a[i], s.beta);
+    if (rc) return rc;
+  } else {
+    for (double& b : s.beta) b = NAN;
+  }
+  return PFCH_OK;
+}
+
+// R(v) = M Delta mu(v) for the members of group G with a non-null src[k]
+// (device field of member k) into dst[k].  Uses the members' spectral
+// workspaces.
+int rhs_launch(pfch_ctx* ctx, Group& G, InstDev** grp, unsigned nm, const std::vector<const double*>& src,
+               const std::vector<double*>& dst) {
+  for (unsigned k = 0; k < nm; ++k) {
+    G.h_rptr[k] = src[k];
+    G.h_rptr[nm + k] = dst[k];
+  }
+  HIPCHK(hipMemcpyAsync(G.d_rptr, G.h_rptr, sizeof(double*) * 2 * nm, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));  // the pinned staging is reused
+  const double** ps = G.d_rptr;
+  double** pd = (double**)(G.d_rptr + nm);
+  int rbpi = G.srow_bpi, cbpi = G.scol_bpi, rc;
+  const dim3 rg(nm * rbpi), cg(nm * cbpi);
+  {
+    void* a[] = {&grp, &ps, &rbpi};
+    if ((rc = launch(G.rs.rhs_fwd, rg, G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
+  }
+  if (G.model == PFCH_FCH) {
+    void* a[] = {&grp, &ps, &cbpi};
+    if ((rc = launch(G.cs.rhs_lap, cg, G.scol_block, G.scol_lds, a, ctx->stream))) return rc;
+    void* b[] = {&grp, &ps, &rbpi};
+    if ((rc = launch(G.rs.rhs_mid, rg, G.srow_block, G.srow_lds, b, ctx->stream))) return rc;
+  }
+  {
+    void* a[] = {&grp, &ps, &cbpi};
+    if ((rc = launch(G.cs.rhs, cg, G.scol_block, G.scol_lds, a, ctx->stream))) return rc;
+  }
+  {
+    void* a[] = {&grp, &pd, &rbpi};
+    if ((rc = launch(G.rs.rhs_inv, rg, G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
+  }
+  return PFCH_OK;
+}
+
+// Buffers of the adaptive estimators, and R(u^n), R(u^{n-1}) of every
+// instance whose history changed outside pfch_step_adaptive.
+int prepare_adaptive(pfch_ctx* ctx) {
+  int rc;
+  void* p = nullptr;
+  for (auto& I : ctx->inst) {
+    if (I.Um2) continue;
+    const size_t rbytes = sizeof(double) * (size_t)I.npts;
+    if ((rc = dalloc(I.allocs, &p, rbytes))) return rc;
+    I.Um2 = (double*)p;
+    for (auto& r : I.R) {
+      if ((rc = dalloc(I.allocs, &p, rbytes))) return rc;
+      r = (double*)p;
+    }
+  }
+  for (auto& G : ctx->groups) {
+    const unsigned nm = (unsigned)G.members.size();
+    for (int lev = 0; lev < 2; ++lev) {
+      std::vector<const double*> src(nm, nullptr);
+      std::vector<double*> dst(nm, nullptr);
+      bool any = false;
+      for (unsigned k = 0; k < nm; ++k) {
+        Instance& I = ctx->inst[G.members[k]];
+        if (I.r_valid || (lev == 1 && !I.has_prev)) continue;
+        src[k] = lev == 0 ? I.U[I.ucur] : I.U[1 - I.ucur];
+        dst[k] = I.R[lev];
+        any = true;
+      }
+      if (any && (rc = rhs_launch(ctx, G, G.d_members, nm, src, dst))) return rc;
+    }
+  }
+  for (auto& I : ctx->inst) {
+    if (!I.r_valid) I.hist = I.has_prev ? 2 : 1;
+    I.r_valid = true;
+  }
+  return PFCH_OK;
+}
+
+double next_dt(double err, double tol, double dt, double dt_min, double dt_max) {
+  double bar;
+  if (err == 0.0)
+    bar = INFINITY;
+  else if (std::isinf(err))
+    bar = 0.0;
+  else
+    bar = 0.9 * std::cbrt(tol / err) * dt;
+  return std::max(dt_min, std::min(bar, dt_max));
+}
+
+}  // namespace
+
+int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
+  if (!ctx || !dt) return PFCH_E_INVAL;
+  const int n = (int)ctx->inst.size();
+  for (int i = 0; i < n; ++i)
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return PFCH_E_INVAL;
+  SolveOut o;
+  int rc;
+  if ((rc = solve_all(ctx, dt, o))) return rc;
+  int first_err = PFCH_OK;
+  std::vector<char> take(n);
+  for (int i = 0; i < n; ++i) {
+    take[i] = o.status[i] == PFCH_OK;
+    if (!take[i] && first_err == PFCH_OK) first_err = o.status[i];
+  }
+  const bool want_mass = st && ctx->stats_detail > 0;
+  if ((rc = accept_solutions(ctx, take, dt, o, want_mass, false))) return rc;
   if (st) {
     if (want_mass) HIPCHK(hipStreamSynchronize(ctx->stream));
-    for (int i = 0; i < n; ++i) {
-      Instance& I = ctx->inst[i];
-      pfch_stats& s = st[i];
-      std::memset(&s, 0, sizeof(s));
-      s.status = status[i];
-      s.iters = iters[i];
-      s.dnorm_inf = dn[i];
-      s.fft_pairs = fft_pairs_of(I, iters[i]);
-      s.guess = guess_kind[i];
-      s.mass = (want_mass && status[i] == PFCH_OK) ? ctx->h_mass[i] : NAN;
-      if (ctx->stats_detail > 0) {
-        if ((rc = betas_host(ctx, I, as[i], s.beta))) return rc;
-      } else {
-        for (double& b : s.beta) b = NAN;
+    for (int i = 0; i < n; ++i)
+      if ((rc = fill_stats(ctx, o, i, want_mass, take[i], st[i]))) return rc;
+  }
+  return first_err;
+}
+
+int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_result* res) {
+  if (!ctx || !ad || !res) return PFCH_E_INVAL;
+  if (!(ad->tol > 0.0) || !std::isfinite(ad->tol) || !(ad->dt_min > 0.0) || !std::isfinite(ad->dt_max) ||
+      !(ad->dt_max >= ad->dt_min) || ad->estimator < PFCH_EST_AUTO || ad->estimator > PFCH_EST_MIDAB2 ||
+      ad->reserved != 0)
+    return PFCH_E_INVAL;
+  const int n = (int)ctx->inst.size();
+  std::vector<double> dt(n);
+  for (int i = 0; i < n; ++i) {
+    dt[i] = res[i].dt_try;
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return PFCH_E_INVAL;
+    if (ctx->inst[i].nz > 1) return PFCH_E_UNSUPPORTED;
+  }
+  int rc;
+  if ((rc = prepare_adaptive(ctx))) return rc;
+  SolveOut o;
+  if ((rc = solve_all(ctx, dt.data(), o))) return rc;
+  // R(u~) of every converged instance
+  for (auto& G : ctx->groups) {
+    const unsigned nm = (unsigned)G.members.size();
+    std::vector<const double*> src(nm, nullptr);
+    std::vector<double*> dst(nm, nullptr);
+    bool any = false;
+    for (unsigned k = 0; k < nm; ++k) {
+      const int i = G.members[k];
+      if (o.status[i] != PFCH_OK) continue;
+      src[k] = solution_of(ctx->inst[i], ctx->h_recs[i]);
+      dst[k] = ctx->inst[i].R[2];
+      any = true;
+    }
+    if (any && (rc = rhs_launch(ctx, G, G.d_members, nm, src, dst))) return rc;
+  }
+  // error estimates
+  std::vector<int> est(n, PFCH_EST_AM3);
+  std::vector<double> fac(n, 1.0);
+  for (int i = 0; i < n; ++i) {
+    Instance& I = ctx->inst[i];
+    EstArgs& A = ctx->h_est[i];
+    std::memset(&A, 0, sizeof(A));
+    A.n = I.npts;
+    if (o.status[i] != PFCH_OK) continue;
+    A.ut = solution_of(I, ctx->h_recs[i]);
+    const bool mid = (ad->estimator == PFCH_EST_MIDAB2 ||
+                      (ad->estimator == PFCH_EST_AUTO && I.d.scheme == PFCH_MP)) &&
+                     I.hist >= 3;
+    const double h = dt[i];
+    A.f[0] = I.U[I.ucur];
+    if (mid) {
+      // quadratic through u^n, u^{n-1}, u^{n-2} at t_n + dt~ (eq. fml:midAB2-high-sol)
+      const double dn = I.dt_prev, dm = I.dt_nm1;
+      est[i] = PFCH_EST_MIDAB2;
+      A.f[1] = I.U[1 - I.ucur];
+      A.f[2] = I.Um2;
+      A.w[0] = (h + dn) * (h + dn + dm) / (dn * (dn + dm));
+      A.w[1] = -h * (h + dn + dm) / (dn * dm);
+      A.w[2] = h * (h + dn) / (dm * (dn + dm));
+      const double rn = 1.0 / 24.0 + 0.125 * (1.0 + dn / h) * (1.0 + 2.0 * dn / h + dm / h);
+      fac[i] = 1.0 / (1.0 - 1.0 / (24.0 * rn));
+    } else {
+      // explicit AM3 value (eq. fml:AM3-high-sol); rho = 0 without history
+      const double rho = I.has_prev ? h / I.dt_prev : 0.0;
+      A.w[0] = 1.0;
+      A.f[3] = I.R[2];
+      A.w[3] = h / 6.0 * (3.0 + 2.0 * rho) / (1.0 + rho);
+      A.f[4] = I.R[0];
+      A.w[4] = h / 6.0 * (3.0 + rho);
+      if (I.has_prev) {
+        A.f[5] = I.R[1];
+        A.w[5] = -h / 6.0 * rho * rho / (1.0 + rho);
       }
     }
   }
-  return first_err;
+  HIPCHK(hipMemcpyAsync(ctx->d_est, ctx->h_est, sizeof(EstArgs) * n, hipMemcpyHostToDevice, ctx->stream));
+  {
+    const EstArgs* args = ctx->d_est;
+    double* part = ctx->d_est_part;
+    void* a[] = {&args, &part};
+    if ((rc = launch((const void*)&k_adapt_est, dim3(EST_BLOCKS, n), dim3(EST_THREADS), 0, a, ctx->stream)))
+      return rc;
+  }
+  HIPCHK(hipMemcpyAsync(ctx->h_est_part, ctx->d_est_part, sizeof(double) * 2 * EST_BLOCKS * n,
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::vector<double> err(n, INFINITY);
+  std::vector<char> take(n, 0);
+  int ret = PFCH_OK;
+  for (int i = 0; i < n; ++i) {
+    if (o.status[i] == PFCH_OK) {
+      const double* pp = ctx->h_est_part + (size_t)i * 2 * EST_BLOCKS;
+      double se = 0.0, sh = 0.0;
+      for (int b = 0; b < EST_BLOCKS; ++b) se += pp[b];
+      for (int b = 0; b < EST_BLOCKS; ++b) sh += pp[EST_BLOCKS + b];
+      err[i] = sh > 0.0 ? std::sqrt(se / sh) * fac[i] : (se > 0.0 ? INFINITY : 0.0);
+    }
+    take[i] = o.status[i] == PFCH_OK && (err[i] <= ad->tol || dt[i] <= ad->dt_min);
+    if (o.status[i] != PFCH_OK && dt[i] <= ad->dt_min && ret == PFCH_OK) ret = o.status[i];
+  }
+  const bool want_mass = ctx->stats_detail > 0;
+  if ((rc = accept_solutions(ctx, take, dt.data(), o, want_mass, true))) return rc;
+  if (want_mass) HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < n; ++i) {
+    Instance& I = ctx->inst[i];
+    if (take[i]) {  // R(u~) becomes R(u^n)
+      double* r1 = I.R[1];
+      I.R[1] = I.R[0];
+      I.R[0] = I.R[2];
+      I.R[2] = r1;
+    }
+    pfch_adapt_result& r = res[i];
+    r.dt = dt[i];
+    r.err = err[i];
+    r.accepted = take[i] ? 1 : 0;
+    r.estimator = est[i];
+    r.dt_try = next_dt(err[i], ad->tol, dt[i], ad->dt_min, ad->dt_max);
+    if ((rc = fill_stats(ctx, o, i, want_mass, take[i], r.solve))) return rc;
+  }
+  return ret;
+}
+
+int pfch_rhs(pfch_ctx* ctx, int32_t inst, const double* v, double* out) {
+  if (!ctx || inst < 0 || inst >= (int)ctx->inst.size() || !v || !out || v == out) return PFCH_E_INVAL;
+  Instance& I = ctx->inst[inst];
+  if (I.nz > 1) return PFCH_E_UNSUPPORTED;
+  std::vector<const double*> src{v};
+  std::vector<double*> dst{out};
+  int rc = rhs_launch(ctx, ctx->groups[I.group], I.d_solo, 1, src, dst);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return PFCH_OK;
 }
 
 int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const double* u_n,

@@ -5,6 +5,7 @@
 
 #include "kernels2d.hpp"
 #include "kernels3d.hpp"
+#include "kernels_rhs.hpp"
 
 namespace pfch {
 
@@ -15,6 +16,9 @@ struct RowK {
   const void* iter = nullptr;
   const void* setup = nullptr;
   const void* start_fch = nullptr;
+  const void* rhs_fwd = nullptr;  // R(v) row passes (default plans only)
+  const void* rhs_mid = nullptr;  // FCH
+  const void* rhs_inv = nullptr;
   int T = 0;
   int lds_elems = 0;  // per team
   int tw_elems = 0;   // twiddle table after the teams' buffers
@@ -23,6 +27,8 @@ struct RowK {
 struct ColK {
   const void* iter = nullptr;
   const void* setup = nullptr;
+  const void* rhs_lap = nullptr;  // R(v) column passes (default plans only): FCH Delta v
+  const void* rhs = nullptr;      // R^
   int T = 0;
   int lds_elems = 0;  // per column
   int tw_elems = 0;   // twiddle table after the columns' buffers
@@ -40,6 +46,9 @@ RowK make_row() {
   k.iter = (const void*)&k_row_iter<P, MODEL, MPS>;
   k.setup = (const void*)&k_row_setup<P, MODEL>;
   if (MODEL == MODEL_FCH) k.start_fch = (const void*)&k_row_start_fch<P>;
+  k.rhs_fwd = (const void*)&k_rhs_row_fwd<P, MODEL>;
+  if (MODEL == MODEL_FCH) k.rhs_mid = (const void*)&k_rhs_row_mid<P>;
+  k.rhs_inv = (const void*)&k_rhs_row_inv<P>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
   k.tw_elems = tw_lds_count<P>();
@@ -62,6 +71,12 @@ ColK make_col() {
   ColK k;
   k.iter = (const void*)&k_col_iter<P, MODEL>;
   k.setup = (const void*)&k_col_setup<P, MODEL>;
+  if (MODEL == MODEL_FCH) {
+    k.rhs_lap = (const void*)&k_rhs_col<P, MODEL, 1>;
+    k.rhs = (const void*)&k_rhs_col<P, MODEL, 2>;
+  } else {
+    k.rhs = (const void*)&k_rhs_col<P, MODEL, 0>;
+  }
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
   k.tw_elems = tw_lds_count<P>();

@@ -25,6 +25,8 @@ BDF2, MP, LBDF2, LMP = 0, 1, 2, 3
 
 PAPER_ETAS = tuple(math.sqrt(v) for v in (0.1, 0.575, 1.05, 1.525, 2.0))
 
+EST_AUTO, EST_AM3, EST_MIDAB2 = 0, 1, 2
+
 EXPORTED = (
     "pfch_validate_desc", "pfch_create", "pfch_set_state", "pfch_get_state",
     "pfch_step", "pfch_solve", "pfch_set_stats_detail", "pfch_time_kernels",
@@ -33,6 +35,7 @@ EXPORTED = (
     "pfch_fno_num_params", "pfch_fno_create", "pfch_fno_init_params", "pfch_fno_set_params",
     "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad", "pfch_fno_adam_step",
     "pfch_fno_prepare", "pfch_fno_destroy", "pfch_set_fno", "pfch_get_plan", "pfch_set_plan",
+    "pfch_step_adaptive", "pfch_rhs",
 )
 
 
@@ -65,6 +68,26 @@ class Stats(ctypes.Structure):
         return dict(iters=self.iters, status=self.status, dnorm=self.dnorm_inf,
                     betas=tuple(self.beta), mass=self.mass, fft_pairs=self.fft_pairs,
                     guess=self.guess)
+
+
+class AdaptDesc(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double), ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double),
+        ("estimator", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class AdaptResult(ctypes.Structure):
+    _fields_ = [
+        ("dt_try", ctypes.c_double), ("dt", ctypes.c_double), ("err", ctypes.c_double),
+        ("accepted", ctypes.c_int32), ("estimator", ctypes.c_int32),
+        ("solve", Stats),
+    ]
+
+    def as_dict(self):
+        return dict(dt=self.dt, err=self.err, accepted=bool(self.accepted),
+                    estimator={EST_AM3: "am3", EST_MIDAB2: "midab2"}.get(self.estimator),
+                    dt_next=self.dt_try, solve=self.solve.as_dict())
 
 
 class PfchError(RuntimeError):
@@ -120,6 +143,10 @@ def lib():
         L.pfch_get_plan.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.pfch_set_plan.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.pfch_get_plan.restype = ctypes.c_int
+        L.pfch_step_adaptive.argtypes = [vp, ctypes.POINTER(AdaptDesc), ctypes.POINTER(AdaptResult)]
+        L.pfch_step_adaptive.restype = ctypes.c_int
+        L.pfch_rhs.argtypes = [vp, i32, vp, vp]
+        L.pfch_rhs.restype = ctypes.c_int
         L.pfch_set_plan.restype = ctypes.c_int
         for name in ("pfch_fno_create", "pfch_fno_init_params", "pfch_fno_set_params",
                      "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad",
@@ -269,6 +296,28 @@ class Context:
         if rc in (PFCH_E_INVAL, PFCH_E_NOMEM, PFCH_E_HIP, PFCH_E_UNSUPPORTED):
             raise PfchError(rc, "pfch_step")
         return rc, ([s.as_dict() for s in st] if stats else None)
+
+    def step_adaptive(self, dt_try, tol, dt_min, dt_max, estimator=EST_AUTO):
+        """One attempt of adaptive stepping for every instance (pfch_step_adaptive).
+        ``dt_try``: tentative size(s).  Returns (code, [result dict per
+        instance]); each result's ``dt_next`` is the next tentative size."""
+        if isinstance(dt_try, (int, float)):
+            dt_try = [float(dt_try)] * self.n
+        ad = AdaptDesc(float(tol), float(dt_min), float(dt_max),
+                       {"auto": EST_AUTO, "am3": EST_AM3, "midab2": EST_MIDAB2}.get(estimator, estimator), 0)
+        res = (AdaptResult * self.n)()
+        for i, d in enumerate(dt_try):
+            res[i].dt_try = float(d)
+        rc = lib().pfch_step_adaptive(self._h, ctypes.byref(ad), res)
+        if rc in (PFCH_E_INVAL, PFCH_E_NOMEM, PFCH_E_HIP, PFCH_E_UNSUPPORTED):
+            raise PfchError(rc, "pfch_step_adaptive")
+        return rc, [r.as_dict() for r in res]
+
+    def rhs(self, inst, v, out):
+        """out = M Delta mu(v) for instance ``inst``'s model and grid."""
+        rc = lib().pfch_rhs(self._h, int(inst), _ptr(v), _ptr(out))
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_rhs")
 
     def plan(self, inst=0):
         """Iteration-kernel plans of the instance's group (see pfch_get_plan)."""

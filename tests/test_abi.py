@@ -119,3 +119,7 @@ def test_create_rejects_bad_arguments_before_device_work():
     assert L.pfch_step(None, None, None) == pfch.PFCH_E_INVAL
     assert L.pfch_set_stats_detail(None, 1) == pfch.PFCH_E_INVAL
     assert L.pfch_time_kernels(None, 0.1, 1, None) == pfch.PFCH_E_INVAL
+    ad = pfch.AdaptDesc(1e-4, 1e-3, 1.0, pfch.EST_AUTO, 0)
+    res = (pfch.AdaptResult * 1)()
+    assert L.pfch_step_adaptive(None, ctypes.byref(ad), res) == pfch.PFCH_E_INVAL
+    assert L.pfch_rhs(None, 0, None, None) == pfch.PFCH_E_INVAL
