@@ -95,7 +95,8 @@ def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2204_07247_amd")
-    for rel in ("csrc/fft.hpp", "csrc/kernels2d.hpp", "csrc/pfch_dev.hpp", "csrc/plans.hpp", "build.py"):
+    for rel in ("csrc/fft.hpp", "csrc/kernels2d.hpp", "csrc/kernels3d.hpp", "csrc/pfch_dev.hpp",
+                "csrc/plans.hpp", "build.py"):
         with open(os.path.join(pkg, rel), "rb") as fh:
             h.update(rel.encode() + b"\0" + fh.read())
     return h.hexdigest()
@@ -252,6 +253,46 @@ def solver_variants(w, steps):
                          fft_pairs_per_step=round(float(np.mean(its)) * fft_pairs, 2),
                          steps_per_s=round(steps / el, 1))
     return dict(workload=w.name, steps=steps, variants=out)
+
+
+def adaptive_run(w, tol, dt_min, dt_max, attempts):
+    """Adaptive stepping (Alg. 3) of w from its initial condition:
+    ``attempts`` passes of the loop body (tentative PAGD solve, R(u~), AM3 or
+    midAB2 estimate, accept / reject, next size) with the paper's stepping
+    tolerance and size bounds; counts, reached time and rates."""
+    import torch
+    from paper_2204_07247_amd import pfch
+    ctx = pfch.Context([_desc(w)])
+    ctx.set_stats_detail(0)
+    ctx.set_state(0, torch.from_numpy(W.initial_condition(w)).cuda())
+    dt = dt_min
+    acc = rej = 0
+    its, dts, ests = [], [], set()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(attempts):
+        rc, res = ctx.step_adaptive(dt, tol, dt_min, dt_max)
+        if rc != pfch.PFCH_OK:
+            break
+        r = res[0]
+        its.append(r["solve"]["iters"])
+        ests.add(r["estimator"])
+        if r["accepted"]:
+            acc += 1
+            dts.append(r["dt"])
+        else:
+            rej += 1
+        dt = r["dt_next"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    t, _, _ = ctx.get_state(0)
+    ctx.close()
+    return dict(workload=w.name, scheme=w.scheme, estimators=sorted(e for e in ests if e),
+                tol=tol, dt_min=dt_min, dt_max=dt_max, attempts=acc + rej, accepted=acc,
+                rejected=rej, t_reached=round(t, 6),
+                dt_accepted=[round(min(dts), 8), round(max(dts), 8)] if dts else None,
+                iters_per_attempt=round(float(np.mean(its)), 2) if its else None,
+                attempts_per_s=round((acc + rej) / el, 1), wall_s=round(el, 3))
 
 
 def ensemble_bandwidth(ws, steps, warmup, label):
@@ -461,6 +502,11 @@ def main():
     if not args.no_compare:
         variants = [solver_variants(w, steps=min(w.steps, 50)),
                     solver_variants(W.PFC64_MP, steps=W.PFC64_MP.steps)]
+    adaptive = None
+    if not args.no_compare:
+        log("[bench] adaptive stepping (AM3 / midAB2)")
+        adaptive = [adaptive_run(W.FCH256_BDF2, 1e-4, 1e-5, 0.5, attempts=200),
+                    adaptive_run(W.PFC64_MP, 1e-4, 1e-4, 0.5, attempts=200)]
     learned_res = None
     if not args.no_learned and not args.no_compare:
         learned_res = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=20)
@@ -479,7 +525,7 @@ def main():
         iters_per_step=dict(mean=round(float(it.mean()), 3), min=int(it.min()), max=int(it.max())),
         fft_pairs_per_iter=fft_pairs,
         roofline=roof, kernels=kernels, launch=cfg, cpu_baseline=cpu, batched=batched,
-        learned=learned_res, ensembles=ensembles, solver_variants=variants,
+        learned=learned_res, ensembles=ensembles, solver_variants=variants, adaptive=adaptive,
     )
     if cpu:
         out["gpu_over_cpu"] = round(value / cpu["value"], 2)

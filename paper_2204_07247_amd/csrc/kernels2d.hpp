@@ -584,14 +584,13 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
     // Both real rows of the pair at once, one transform per spectral field:
     // the direction d (field 0) first, then its Laplacian (field 1), so
     // every spectral read covers whole 128-byte lines of the tiled layout.
-    // The real-space loads of each half follow its transform, which keeps
-    // the kernel within the registers of two waves per SIMD.
+    // Large plans load the real-space operands of each half after its
+    // transform, which keeps them within the registers of two waves per
+    // SIMD; small plans (latency-bound grids) issue every load up front.
+    constexpr bool EARLY = RM <= 4;
     double vbs[2][RM], lv[2][RM];
-    {
-      c2 v[RM];
-      load_pack<PX>(v, gp(I->S), r0, gp(I->S), r0 + 1, rows, t);
-      fft<PX, true>(v, lds, tw, t);
-      double a[2][RM], b[2][RM], uu[2][RM];
+    double a[2][RM], b[2][RM], uu[2][RM], la[2][RM], lb[2][RM], lu[2][RM];
+    auto load_x = [&]() {
 #pragma unroll
       for (int row = 0; row < 2; ++row) {
 #pragma unroll
@@ -602,27 +601,8 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
           uu[row][m] = mp ? un[idx] : 0.0;
         }
       }
-#pragma unroll
-      for (int row = 0; row < 2; ++row) {
-#pragma unroll
-        for (int m = 0; m < RM; ++m) {
-          const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
-          const double d = row ? v[m].y : v[m].x;
-          const double y = a[row][m] + lam * (a[row][m] - b[row][m]);
-          const double x1 = y + s * d;
-          xn[idx] = x1;
-          const uint64_t db = dbits(fabs(d));
-          dmax = db > dmax ? db : dmax;
-          const double yn = x1 + lamn * (x1 - a[row][m]);
-          vbs[row][m] = mp ? th * yn + (1.0 - th) * uu[row][m] : yn;
-        }
-      }
-    }
-    {
-      c2 v[RM];
-      load_pack<PX>(v, gp(I->S) + fs, r0, gp(I->S) + fs, r0 + 1, rows, t);
-      fft<PX, true>(v, lds, tw, t);
-      double la[2][RM], lb[2][RM], lu[2][RM];
+    };
+    auto load_l = [&]() {
 #pragma unroll
       for (int row = 0; row < 2; ++row) {
 #pragma unroll
@@ -633,24 +613,312 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
           lu[row][m] = mp ? dun[idx] : 0.0;
         }
       }
+    };
+    c2 v[RM], w[RM];
+    load_pack<PX>(v, gp(I->S), r0, gp(I->S), r0 + 1, rows, t);
+    if constexpr (EARLY) {
+      load_pack<PX>(w, gp(I->S) + fs, r0, gp(I->S) + fs, r0 + 1, rows, t);
+      load_x();
+      load_l();
+    }
+    fft<PX, true>(v, lds, tw, t);
+    if constexpr (!EARLY) load_x();
 #pragma unroll
-      for (int row = 0; row < 2; ++row) {
+    for (int row = 0; row < 2; ++row) {
 #pragma unroll
-        for (int m = 0; m < RM; ++m) {
-          const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
-          const double ld = row ? v[m].y : v[m].x;
-          const double ly = la[row][m] + lam * (la[row][m] - lb[row][m]);
-          const double lx1 = ly + s * ld;
-          dxn[idx] = lx1;
-          const double lyn = lx1 + lamn * (lx1 - la[row][m]);
-          lv[row][m] = mp ? th * lyn + (1.0 - th) * lu[row][m] : lyn;
-        }
+      for (int m = 0; m < RM; ++m) {
+        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+        const double d = row ? v[m].y : v[m].x;
+        const double y = a[row][m] + lam * (a[row][m] - b[row][m]);
+        const double x1 = y + s * d;
+        xn[idx] = x1;
+        const uint64_t db = dbits(fabs(d));
+        dmax = db > dmax ? db : dmax;
+        const double yn = x1 + lamn * (x1 - a[row][m]);
+        vbs[row][m] = mp ? th * yn + (1.0 - th) * uu[row][m] : yn;
+      }
+    }
+    if constexpr (!EARLY) load_pack<PX>(w, gp(I->S) + fs, r0, gp(I->S) + fs, r0 + 1, rows, t);
+    fft<PX, true>(w, lds, tw, t);
+    if constexpr (!EARLY) load_l();
+#pragma unroll
+    for (int row = 0; row < 2; ++row) {
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+        const double ld = row ? w[m].y : w[m].x;
+        const double ly = la[row][m] + lam * (la[row][m] - lb[row][m]);
+        const double lx1 = ly + s * ld;
+        dxn[idx] = lx1;
+        const double lyn = lx1 + lamn * (lx1 - la[row][m]);
+        lv[row][m] = mp ? th * lyn + (1.0 - th) * lu[row][m] : lyn;
       }
     }
     fch_forward_pair<PX>(I, vbs, lv, tw, lds, r0, t);
   }
   const uint64_t bm = block_max_bits(dmax, red);
   if (threadIdx.x == 0) atomicMax((unsigned long long*)&I->norms[j], (unsigned long long)bm);
+}
+
+// ---------------------------------------------------------------------------
+// Field-parallel iteration kernels for short transforms, where a kernel's
+// time is the latency of its chain of transforms rather than HBM traffic:
+// each row pair (column) gets one team of T threads per spectral field (FCH
+// three, PFC two), so the transforms of an iteration run side by side
+// instead of one after another (FCH rows: d and Delta d inverse, then F', p
+// and v forward; PFC rows: d inverse, then v^3 and v forward).  Values cross
+// between the teams through LDS.  Same arithmetic as k_row_iter /
+// k_col_iter.
+// ---------------------------------------------------------------------------
+template <int MODEL>
+constexpr int fp_teams() { return MODEL == MODEL_FCH ? 3 : 2; }
+
+template <class PX, int MODEL, bool MPS>
+__global__ __launch_bounds__(256) void k_row_iter_fp(const InstDev* const* __restrict__ grp, int bpi,
+                                                     int l, int /*total*/) {
+  extern __shared__ c2 smem[];
+  __shared__ uint64_t red[4];
+  const GroupPos gpos = group_pos(grp, bpi);
+  const InstDev* __restrict__ I = gpos.I;
+  const int j = *I->iter_base + l;
+  if (stopped_before(I, j)) return;
+  constexpr int N = PX::N, T = PX::T, RM = PX::RMAX, NT = fp_teams<MODEL>();
+  constexpr bool fch = MODEL == MODEL_FCH;
+  constexpr int NINV = fch ? 2 : 1;              // teams with an inverse transform
+  const int npair = blockDim.x / (NT * T);       // row pairs per block
+  const int pr = threadIdx.x / (NT * T);         // this thread's pair
+  const int role = (threadIdx.x / T) % NT;       // FCH 0: d, F'  1: Delta d, p  2: v;  PFC 0: d, v^3  1: v
+  const int t = threadIdx.x % T;
+  c2* lds = smem + (pr * NT + role) * lds_len(N);
+  // per pair: v_breve of both rows (FCH: then its Laplacian of both rows)
+  double* ex = (double*)(smem + npair * NT * lds_len(N) + tw_lds_count<PX>()) + pr * 2 * NINV * N;
+  const int r0 = 2 * (gpos.lb * npair + pr);
+  const int rows = I->rows;
+  const uint32_t fs = (uint32_t)I->field_stride;
+  const int ne = I->n_eta;
+  const double lam = I->lam[j % ne], lamn = I->lam[(j + 1) % ne];
+  const double s = I->s, th = I->theta;
+  constexpr bool mp = MPS;
+  GLB c2* S = gp(I->S);
+  Twiddles<PX> tw;
+  load_twiddles<PX>(tw, I->tw_x, t);
+  uint64_t dmax = 0;
+
+  // inverse transform of this team's field (the other teams transform zeros)
+  c2 v[RM];
+  double a[2][RM], b[2][RM], uu[2][RM];
+  const GLB double* xa = gp(role == 0 ? I->X[j % 3] : I->DX[j % 3]);
+  const GLB double* xb = gp(role == 0 ? I->X[(j + 2) % 3] : I->DX[(j + 2) % 3]);
+  const GLB double* xu = gp(role == 0 ? I->un : I->dun);
+  if (role < NINV) {
+    load_pack<PX>(v, S + role * fs, r0, S + role * fs, r0 + 1, rows, t);
+#pragma unroll
+    for (int row = 0; row < 2; ++row) {
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+        a[row][m] = xa[idx];
+        b[row][m] = xb[idx];
+        uu[row][m] = mp ? xu[idx] : 0.0;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < RM; ++m) v[m] = c2{0.0, 0.0};
+  }
+  fft<PX, true>(v, lds, tw, t);
+  if (role < NINV) {
+    GLB double* xo = gp(role == 0 ? I->X[(j + 1) % 3] : I->DX[(j + 1) % 3]);
+#pragma unroll
+    for (int row = 0; row < 2; ++row) {
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+        const double d = row ? v[m].y : v[m].x;
+        const double y = a[row][m] + lam * (a[row][m] - b[row][m]);
+        const double x1 = y + s * d;
+        xo[idx] = x1;
+        if (role == 0) {
+          const uint64_t db = dbits(fabs(d));
+          dmax = db > dmax ? db : dmax;
+        }
+        const double yn = x1 + lamn * (x1 - a[row][m]);
+        ex[(2 * role + row) * N + t + m * T] = mp ? th * yn + (1.0 - th) * uu[row][m] : yn;
+      }
+    }
+  }
+  __syncthreads();
+
+  // forward transform of this team's pointwise field
+  const double e2 = I->eps * I->eps, tau = I->tau, eta2 = I->eta2;
+  c2 z[RM];
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+    const int k = t + m * T;
+    double f[2];
+#pragma unroll
+    for (int row = 0; row < 2; ++row) {
+      const double u = ex[row * N + k];
+      if constexpr (fch) {
+        const double f1 = (u * u - 1.0) * (u + tau);
+        if (role == 0) {
+          f[row] = f1;
+        } else if (role == 1) {
+          const double f2 = 3.0 * u * u - 1.0 + 2.0 * tau * u;
+          const double om = e2 * ex[(2 + row) * N + k] - f1;
+          f[row] = -f2 * om - eta2 * f1;
+        } else {
+          f[row] = u;
+        }
+      } else {
+        f[row] = role == 0 ? u * u * u : u;
+      }
+    }
+    z[m] = c2{f[0], f[1]};
+  }
+  fft<PX, false>(z, lds, tw, t);
+  unpack_store<PX>(z, lds, S + role * fs, r0, S + role * fs, r0 + 1, rows, t);
+  const uint64_t bm = block_max_bits(dmax, red);
+  if (threadIdx.x == 0) atomicMax((unsigned long long*)&I->norms[j], (unsigned long long)bm);
+}
+
+// One column per block, one team per transformed field: forward
+// y-transforms side by side, the k-space bracket summed through LDS, then
+// the inverse transforms (FCH: d^ and -q d^ side by side).
+template <class PY, int MODEL>
+__global__ __launch_bounds__(512) void k_col_iter_fp(const InstDev* const* __restrict__ grp, int bpi, int l,
+                                                     int /*total*/) {
+  extern __shared__ c2 smem[];
+  const GroupPos gpos = group_pos(grp, bpi);
+  const InstDev* __restrict__ I = gpos.I;
+  const int j = *I->iter_base + l;
+  if (stopped_before(I, j)) return;
+  constexpr int N = PY::N, T = PY::T, RM = PY::RMAX, NT = fp_teams<MODEL>();
+  constexpr bool fch = MODEL == MODEL_FCH;
+  const int rows = N;
+  const int role = threadIdx.x / T, t = threadIdx.x % T;
+  // physical column: the tiles' four columns go to blocks lb, lb + 8, ...
+  // (same L2 for the partial-line accesses of one tile)
+  const int lb = gpos.lb, ntiles = I->nh / TW;
+  int tile, sub;
+  if ((ntiles & 7) == 0) {
+    const int g = lb / (8 * TW), r = lb % (8 * TW);
+    tile = g * 8 + (r & 7);
+    sub = r >> 3;
+  } else {
+    tile = lb / TW;
+    sub = lb % TW;
+  }
+  const int kp = tile * TW + sub;
+  c2* lds = smem + role * lds_len(N);
+  c2* ex = smem + NT * lds_len(N) + tw_lds_count<PY>();  // [NT][N] bracket parts
+  const bool special = kp == 0;
+  const bool blk0 = lb == 0;
+  const uint32_t fs = (uint32_t)I->field_stride;
+  GLB c2* S = gp(I->S);
+  Twiddles<PY> tw;
+  load_twiddles<PY>(tw, I->tw_y, t);
+  double bm2, b0, b2, b4;
+  betas(I, bm2, b0, b2, b4);
+  const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
+  const double inv_p = I->inv_p;
+  const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
+  const double kx2 = (kp * I->kx_scale) * (kp * I->kx_scale);
+  auto q_of = [&](int ky) {
+    const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
+    return kx2 + a * a;
+  };
+  auto q_col0 = [&](int ky) {
+    const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
+    return a * a;
+  };
+  const double e2 = I->eps * I->eps, e4 = e2 * e2, e2h1 = e2 * I->eta1, e1 = 1.0 - I->eps;
+  auto coef = [&](double q) -> double {
+    if (role == NT - 1) {  // v_breve
+      const double lin = fch ? e4 * q * q - e2h1 * q : e1 - 2.0 * q + q * q;
+      return inv_m * aot + q * lin;
+    }
+    if (fch && role == 0) return e2 * q * q;
+    return q;
+  };
+
+  c2 v[RM], acc[RM], gh[RM];
+#pragma unroll
+  for (int m = 0; m < RM; ++m) v[m] = gload(S + role * fs + sidx(rows, t + m * T, kp));
+  if (role == NT - 1) {
+#pragma unroll
+    for (int m = 0; m < RM; ++m) gh[m] = gload(gp(I->ghat) + sidx(rows, t + m * T, kp));
+  }
+  fft<PY, false>(v, lds, tw, t);
+  {
+    const int tf = opaque(t);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      const double q = q_of(tf + m * T);
+      const double c = special ? 0.5 * (coef(q) + coef(q + kxn2)) : coef(q);
+      acc[m] = cscale(v[m], c);
+    }
+  }
+  if (blk0)
+    col0_mirror<PY>(v, lds, special, t, [&](int m, c2 w) {
+      const double q = q_col0(opaque(t + m * T));
+      acc[m] = cadd(acc[m], cscale(w, 0.5 * (coef(q) - coef(q + kxn2))));
+    });
+  if (role == NT - 1) {
+    // g^ enters with the same coefficient 1/M on both logical columns
+#pragma unroll
+    for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(gh[m], inv_m));
+  }
+#pragma unroll
+  for (int m = 0; m < RM; ++m) ex[role * N + t + m * T] = acc[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+    const int k = t + m * T;
+    acc[m] = fch ? cadd(cadd(ex[k], ex[N + k]), ex[2 * N + k]) : cadd(ex[k], ex[N + k]);
+  }
+
+  // scale by -1/(P Lq), zero at k = 0
+  int bad = 0;
+  auto scale = [&](double q) -> double {
+    if (!(q > 0.0)) return 0.0;
+    const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
+    bad |= !(Lq > 0.0);
+    return -inv_p * rcp_pos(Lq);
+  };
+  {
+    const int tf = opaque(t);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], scale(q_of(tf + m * T)));
+  }
+  if (blk0)
+    col0_mirror<PY>(acc, lds, special, t, [&](int m, c2 w) {
+      const double q = q_col0(opaque(t + m * T));
+      const double s0 = scale(q), sn = scale(q + kxn2);
+      v[m] = cadd(cscale(acc[m], 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn)));
+    });
+  if constexpr (fch) {
+    // team 0 keeps d^, the others take -q d^ (team 2's copy is unused)
+    if (role > 0) {
+#pragma unroll
+      for (int m = 0; m < RM; ++m) acc[m] = v[m];
+      const int tf = opaque(t);
+#pragma unroll
+      for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], -q_of(tf + m * T));
+    }
+    if (blk0)
+      col0_mirror<PY>(acc, lds, special && role > 0, t, [&](int m, c2 w) {
+        const double q = q_col0(opaque(t + m * T));
+        v[m] = cadd(cscale(acc[m], -(q + 0.5 * kxn2)), cscale(w, 0.5 * kxn2));
+      });
+  }
+  fft<PY, true>(v, lds, tw, t);
+  if (role < (fch ? 2 : 1)) {
+    const int ts = opaque(t);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) gstore(S + role * fs + sidx(rows, ts + m * T, kp), v[m]);
+  }
+  if (bad) atomicOr(I->flags, FLAG_PRECOND);
 }
 
 // ---------------------------------------------------------------------------
@@ -667,14 +935,23 @@ struct StepArgs {
   double gu, gm;       // g = gu u^n + gm u^{n-1}
 };
 
+// Up to STEP_ARGS_INLINE instances' arguments travel by value with the
+// launch (no host-to-device copy before the set-up); larger groups pass a
+// device array.
+constexpr int STEP_ARGS_INLINE = 4;
+struct StepArgsInline {
+  StepArgs a[STEP_ARGS_INLINE];
+};
+
 template <class PX, int MODEL>
 __global__ __launch_bounds__(256) void k_row_setup(InstDev* const* __restrict__ grp,
-                                                   const StepArgs* __restrict__ args, int bpi) {
+                                                   const StepArgs* __restrict__ args, int bpi,
+                                                   StepArgsInline inl) {
   extern __shared__ c2 smem[];
   __shared__ double red[4];
   const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
   InstDev* __restrict__ I = grp[gi];
-  const StepArgs sa = args[gi];
+  const StepArgs sa = args ? args[gi] : inl.a[gi];
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
   const int teams = blockDim.x / T;
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;

@@ -65,12 +65,17 @@ constexpr int ACC_BLOCKS = 64, ACC_THREADS = 256;
 // Accept: copy every converged instance's solution x_{stop+1} to its new
 // u^n slot (dsts[i]; null = not accepted) and, if part is given, write
 // ACC_BLOCKS partial sums of it per instance (fixed order).
+// Up to ACC_INLINE destinations travel by value with the launch.
+constexpr int ACC_INLINE = 16;
+struct AccDsts {
+  double* p[ACC_INLINE];
+};
 __global__ __launch_bounds__(ACC_THREADS) void k_accept(InstDev* const* __restrict__ insts,
                                                         double* const* __restrict__ dsts,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, AccDsts inl) {
   __shared__ double red[ACC_THREADS / 64];
   const int i = blockIdx.y;
-  double* dst = dsts[i];
+  double* dst = dsts ? dsts[i] : inl.p[i];
   if (!dst) return;
   const InstDev* I = insts[i];
   const int slot = (I->rec->stop_iter + 1) % 3;
@@ -114,7 +119,6 @@ struct Instance {
   InstDev h{};             // host mirror of the device descriptor
   InstDev* dev = nullptr;  // device descriptor
   InstDev** d_solo = nullptr;  // device array {dev}: single-instance launches
-  StepArgs* d_solo_args = nullptr;
   double* U[2] = {nullptr, nullptr};
   int ucur = 0;
   bool has_prev = false;
@@ -383,8 +387,6 @@ int setup_instance(pfch_ctx* ctx, Instance& I, int nparts) {
   I.dev = (InstDev*)p;
   if ((rc = dalloc(I.allocs, &p, sizeof(InstDev*)))) return rc;
   I.d_solo = (InstDev**)p;
-  if ((rc = dalloc(I.allocs, &p, sizeof(StepArgs)))) return rc;
-  I.d_solo_args = (StepArgs*)p;
   HIPCHK(hipMemcpy(I.d_solo, &I.dev, sizeof(InstDev*), hipMemcpyHostToDevice));
   // No instance iterates before its first setup: park the iteration base
   // beyond the cap so every iteration kernel exits at once.
@@ -548,11 +550,17 @@ StepSetup step_setup_for(const Instance& I, double dt) {
 
 // Setup kernels for `nm` instances of group G described by the device arrays
 // (grp, args).
-int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, unsigned nm) {
+int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, unsigned nm,
+                 const StepArgsInline* inl = nullptr) {
   int rc;
   int rbpi = G.srow_bpi, cbpi = G.scol_bpi;
+  StepArgsInline il{};
+  if (inl) {
+    il = *inl;
+    args = nullptr;
+  }
   {
-    void* a[] = {&grp, &args, &rbpi};
+    void* a[] = {&grp, &args, &rbpi, &il};
     if ((rc = launch(G.rs.setup, dim3(nm * rbpi), G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
   }
   if (G.ndim == 3) {
@@ -575,11 +583,9 @@ int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, u
 }
 
 int launch_setup_solo(pfch_ctx* ctx, Instance& I, const StepSetup& ss) {
-  StepArgs* h = ctx->groups[I.group].h_args;  // pinned staging (synchronised below)
-  *h = to_args(ss);
-  HIPCHK(hipMemcpyAsync(I.d_solo_args, h, sizeof(StepArgs), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  return launch_setup(ctx, ctx->groups[I.group], I.d_solo, I.d_solo_args, 1);
+  StepArgsInline inl{};
+  inl.a[0] = to_args(ss);
+  return launch_setup(ctx, ctx->groups[I.group], I.d_solo, nullptr, 1, &inl);
 }
 
 // Replay iteration chunks until every instance in `active` has stopped.
@@ -716,6 +722,7 @@ bool row_geometry_ok(const Group& G, const RowK& k, int teams) {
 }
 bool col_geometry_ok(const Group& G, const ColK& k, int cb) {
   const int H = G.nx / 2;
+  if (k.fp && cb != 1) return false;  // field-parallel: one column per block
   return k.T * cb <= 512 && H % cb == 0 && ((size_t)cb * k.lds_elems + k.tw_elems) * sizeof(c2) <= LDS_MAX;
 }
 
@@ -964,7 +971,7 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
       const ColK& k = alt < 0 ? G.cs : G.calts[alt];
       for (int cb = 1; cb <= 4; cb *= 2) {
         for (int persist = 0; persist <= 1; ++persist) {
-          if (!col_geometry_ok(G, k, cb) || (alt < 0 && cb == def.cb && !persist)) continue;
+          if (!col_geometry_ok(G, k, cb) || (alt < 0 && cb == def.cb && !persist) || (k.fp && persist)) continue;
           apply_col(G, k, cb, persist);
           if (persist && G.col_cap == 0) continue;
           float t = 0.f;
@@ -1129,6 +1136,11 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
         else
           row_alternatives<MODEL_PFC, false>(I.nx, G.ralts);
         col_alternatives<MODEL_PFC>(I.ny, G.calts);
+        if (mps)
+          row_fp_alternatives<MODEL_PFC, true>(I.nx, G.ralts);
+        else
+          row_fp_alternatives<MODEL_PFC, false>(I.nx, G.ralts);
+        col_fp_alternatives<MODEL_PFC>(I.ny, G.calts);
       } else {
         ok = (mps ? row_kernels<MODEL_FCH, true>(I.nx, G.rs) : row_kernels<MODEL_FCH, false>(I.nx, G.rs)) &&
              col_kernels<MODEL_FCH>(I.ny, G.cs);
@@ -1137,6 +1149,11 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
         else
           row_alternatives<MODEL_FCH, false>(I.nx, G.ralts);
         col_alternatives<MODEL_FCH>(I.ny, G.calts);
+        if (mps)
+          row_fp_alternatives<MODEL_FCH, true>(I.nx, G.ralts);
+        else
+          row_fp_alternatives<MODEL_FCH, false>(I.nx, G.ralts);
+        col_fp_alternatives<MODEL_FCH>(I.ny, G.calts);
       }
       G.rk = G.rs;
       G.ck = G.cs;
@@ -1492,7 +1509,7 @@ int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]) {
     if (c.col_alt < -1 || c.col_alt >= (int)G.calts.size()) return PFCH_E_INVAL;
     const ColK& ck = c.col_alt < 0 ? G.cs : G.calts[c.col_alt];
     if (c.cb != 1 && c.cb != 2 && c.cb != 4) return PFCH_E_INVAL;
-    if (!col_geometry_ok(G, ck, c.cb)) return PFCH_E_INVAL;
+    if (!col_geometry_ok(G, ck, c.cb) || (ck.fp && c.persist)) return PFCH_E_INVAL;
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -1569,9 +1586,15 @@ int solve_all(pfch_ctx* ctx, const double* dt, SolveOut& o) {
       G.h_args[k] = to_args(ss);
     }
     const unsigned nm = (unsigned)G.members.size();
-    HIPCHK(hipMemcpyAsync(G.d_args, G.h_args, sizeof(StepArgs) * nm, hipMemcpyHostToDevice,
-                          ctx->stream));
-    if ((rc = launch_setup(ctx, G, G.d_members, G.d_args, nm))) return rc;
+    if (nm <= (unsigned)STEP_ARGS_INLINE) {
+      StepArgsInline inl{};
+      for (unsigned k = 0; k < nm; ++k) inl.a[k] = G.h_args[k];
+      if ((rc = launch_setup(ctx, G, G.d_members, nullptr, nm, &inl))) return rc;
+    } else {
+      HIPCHK(hipMemcpyAsync(G.d_args, G.h_args, sizeof(StepArgs) * nm, hipMemcpyHostToDevice,
+                            ctx->stream));
+      if ((rc = launch_setup(ctx, G, G.d_members, G.d_args, nm))) return rc;
+    }
   }
   if ((rc = run_iterations(ctx, active))) return rc;
   // A learned guess that does not lead to convergence falls back to the
@@ -1610,12 +1633,18 @@ int accept_solutions(pfch_ctx* ctx, const std::vector<char>& take, const double*
     if (adaptive) std::swap(I.Um2, I.U[1 - I.ucur]);  // u^{n-1} becomes u^{n-2}
     ctx->h_dsts[i] = I.U[1 - I.ucur];
   }
-  HIPCHK(hipMemcpyAsync(ctx->d_dsts, ctx->h_dsts, sizeof(double*) * n, hipMemcpyHostToDevice, ctx->stream));
+  AccDsts inl{};
+  double** dsts = nullptr;
+  if (n <= ACC_INLINE) {
+    for (int i = 0; i < n; ++i) inl.p[i] = ctx->h_dsts[i];
+  } else {
+    HIPCHK(hipMemcpyAsync(ctx->d_dsts, ctx->h_dsts, sizeof(double*) * n, hipMemcpyHostToDevice, ctx->stream));
+    dsts = ctx->d_dsts;
+  }
   {
     InstDev** ptrs = ctx->d_ptrs;
-    double** dsts = ctx->d_dsts;
     double* part = want_mass ? ctx->d_part : nullptr;
-    void* a[] = {&ptrs, &dsts, &part};
+    void* a[] = {&ptrs, &dsts, &part, &inl};
     if ((rc = launch((const void*)&k_accept, dim3(ACC_BLOCKS, n), dim3(ACC_THREADS), 0, a, ctx->stream)))
       return rc;
   }

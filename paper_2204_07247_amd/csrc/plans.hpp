@@ -19,7 +19,8 @@ struct RowK {
   const void* rhs_fwd = nullptr;  // R(v) row passes (default plans only)
   const void* rhs_mid = nullptr;  // FCH
   const void* rhs_inv = nullptr;
-  int T = 0;
+  int T = 0;           // threads per row pair (three teams for field-parallel kernels)
+  int fp = 0;          // field-parallel kernel
   int lds_elems = 0;  // per team
   int tw_elems = 0;   // twiddle table after the teams' buffers
   int radix[8] = {1, 1, 1, 1, 1, 1, 1, 1};
@@ -29,7 +30,8 @@ struct ColK {
   const void* setup = nullptr;
   const void* rhs_lap = nullptr;  // R(v) column passes (default plans only): FCH Delta v
   const void* rhs = nullptr;      // R^
-  int T = 0;
+  int T = 0;           // threads per column (three teams for field-parallel kernels)
+  int fp = 0;          // field-parallel kernel: one column per block
   int lds_elems = 0;  // per column
   int tw_elems = 0;   // twiddle table after the columns' buffers
   int radix[8] = {1, 1, 1, 1, 1, 1, 1, 1};
@@ -166,12 +168,60 @@ void row_alternatives(int n, std::vector<RowK>& out) {
   PFCH_ALT_PLANS(PFCH_ROW_ALT)
 #undef PFCH_ROW_ALT
 }
+// Column kernels keep three fields' transforms and the k-space bracket live
+// at once; with radix 16 they spill hundreds of bytes per lane, so only the
+// radix-4 (and 192's radix-3/2) schedules are column candidates.
+#define PFCH_COL_ALT_PLANS(X) X(64, A64a) X(128, A128a) X(256, A256a) X(1024, A1024b) X(192, A192a)
 template <int MODEL>
 void col_alternatives(int n, std::vector<ColK>& out) {
 #define PFCH_COL_ALT(LEN, PLAN) \
   if (n == LEN) out.push_back(make_col_iter<PLAN, MODEL>());
-  PFCH_ALT_PLANS(PFCH_COL_ALT)
+  PFCH_COL_ALT_PLANS(PFCH_COL_ALT)
 #undef PFCH_COL_ALT
+}
+
+// Field-parallel iteration kernels (one team per spectral field and row pair
+// or column) for the lengths where a plan's team is small enough.
+template <class P, int MODEL, bool MPS>
+RowK make_row_fp() {
+  constexpr int NT = fp_teams<MODEL>(), NINV = MODEL == MODEL_FCH ? 2 : 1;
+  RowK k;
+  k.iter = (const void*)&k_row_iter_fp<P, MODEL, MPS>;
+  k.T = NT * P::T;
+  k.lds_elems = NT * lds_len(P::N) + NINV * P::N;  // transforms + v_breve (, Delta v_breve) of two rows
+  k.tw_elems = tw_lds_count<P>();
+  k.fp = 1;
+  plan_radices<P>(k.radix);
+  return k;
+}
+template <class P, int MODEL>
+ColK make_col_fp() {
+  constexpr int NT = fp_teams<MODEL>();
+  ColK k;
+  k.iter = (const void*)&k_col_iter_fp<P, MODEL>;
+  k.T = NT * P::T;
+  k.lds_elems = NT * lds_len(P::N) + NT * P::N;  // transforms + the bracket's parts
+  k.tw_elems = tw_lds_count<P>();
+  k.fp = 1;
+  plan_radices<P>(k.radix);
+  return k;
+}
+#define PFCH_FP_PLANS(X) \
+  X(64, P64) X(64, A64a) X(128, P128) X(128, A128a) X(256, P256) X(256, A256a) X(512, P512) X(1024, P1024)
+
+template <int MODEL, bool MPS>
+void row_fp_alternatives(int n, std::vector<RowK>& out) {
+#define PFCH_ROW_FP(LEN, PLAN) \
+  if constexpr (fp_teams<MODEL>() * PLAN::T <= 256) if (n == LEN) out.push_back(make_row_fp<PLAN, MODEL, MPS>());
+  PFCH_FP_PLANS(PFCH_ROW_FP)
+#undef PFCH_ROW_FP
+}
+template <int MODEL>
+void col_fp_alternatives(int n, std::vector<ColK>& out) {
+#define PFCH_COL_FP(LEN, PLAN) \
+  if constexpr (fp_teams<MODEL>() * PLAN::T <= 512) if (n == LEN) out.push_back(make_col_fp<PLAN, MODEL>());
+  PFCH_FP_PLANS(PFCH_COL_FP)
+#undef PFCH_COL_FP
 }
 
 // Three-dimensional PFC: kernels of the y- and z-passes per length.
