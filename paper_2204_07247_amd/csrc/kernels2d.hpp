@@ -203,19 +203,37 @@ __device__ __forceinline__ void betas(const InstDev* I, double& bm2, double& b0,
   }
 }
 
+// Called by every thread of one block.  The partial sums are added in index
+// order by one thread (the order the host's report uses), staged through LDS
+// in chunks so that the loads are issued by the whole block.
 __device__ __forceinline__ void finish_betas(InstDev* I) {
   if (I->imex) {
-    I->beta0 = I->imex_b0;
-    I->beta2 = I->imex_b2;
+    if (threadIdx.x == 0) {
+      I->beta0 = I->imex_b0;
+      I->beta2 = I->imex_b2;
+    }
     return;
   }
+  constexpr int CH = 256;  // partial-sum pairs per chunk
+  __shared__ double buf[2 * CH];
   double s0 = 0.0, s1 = 0.0;
-  for (int i = 0; i < I->nparts; ++i) {
-    s0 += I->part[2 * i];
-    s1 += I->part[2 * i + 1];
+  const int np = I->nparts;
+  for (int base = 0; base < np; base += CH) {
+    const int cnt = np - base < CH ? np - base : CH;
+    for (int k = threadIdx.x; k < 2 * cnt; k += blockDim.x) buf[k] = I->part[2 * base + k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int i = 0; i < cnt; ++i) {
+        s0 += buf[2 * i];
+        s1 += buf[2 * i + 1];
+      }
+    }
+    __syncthreads();
   }
-  I->beta0 = fabs(s0 * I->inv_p);
-  I->beta2 = fabs(s1 * I->inv_p);
+  if (threadIdx.x == 0) {
+    I->beta0 = fabs(s0 * I->inv_p);
+    I->beta2 = fabs(s1 * I->inv_p);
+  }
 }
 
 // Column block geometry: `cb` physical columns per block (1, 2 or 4 of a
@@ -933,6 +951,12 @@ struct StepArgs {
   double rho;          // extrapolation factor dt_{n+1}/dt_n (0 on the first step)
   double a, theta;
   double gu, gm;       // g = gu u^n + gm u^{n-1}
+  double* acc_dst;     // where the chunk graph accepts the solution; null = not accepted there
+  // FCH: Laplacians of u^n and u^{n-1} kept from the previous steps (null:
+  // Delta x0 comes from transforms), and where the accept keeps Delta u^{n+1}
+  const double* lun;
+  const double* lunm1;
+  double* acc_ldst;
 };
 
 // Up to STEP_ARGS_INLINE instances' arguments travel by value with the
@@ -952,6 +976,7 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* const* __restrict__ 
   const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
   InstDev* __restrict__ I = grp[gi];
   const StepArgs sa = args ? args[gi] : inl.a[gi];
+  if (sa.lun) return;  // k_row_setup_lap's instance
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
   const int teams = blockDim.x / T;
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;
@@ -970,6 +995,9 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* const* __restrict__ 
     I->theta = sa.theta;
     I->a_over_theta = sa.a / sa.theta;
     I->un = sa.un;
+    I->acc_dst = sa.acc_dst;
+    I->acc_ldst = sa.acc_ldst;
+    I->lap_hist = sa.lun != nullptr;
     *I->iter_base = 0;
     *I->flags = 0;
     I->rec->stop_iter = -1;
@@ -1030,6 +1058,98 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* const* __restrict__ 
   }
 }
 
+// FCH step set-up when the Laplacians of u^n and u^{n-1} were kept by the
+// previous accepts (extrapolated guess): Delta is linear, so
+// Delta x0 = Delta u^n + rho (Delta u^n - Delta u^{n-1}) needs no transform,
+// and the transforms that start iteration 0 are done here; the column set-up
+// then transforms g only and the start kernel is not needed.  The guess,
+// g, the averaged-Newton partial sums and the published scalars are those of
+// k_row_setup (same geometry, same order).
+template <class PX>
+__global__ __launch_bounds__(256) void k_row_setup_lap(InstDev* const* __restrict__ grp,
+                                                       const StepArgs* __restrict__ args, int bpi,
+                                                       StepArgsInline inl) {
+  extern __shared__ c2 smem[];
+  __shared__ double red[4];
+  const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
+  InstDev* __restrict__ I = grp[gi];
+  const StepArgs sa = args ? args[gi] : inl.a[gi];
+  if (!sa.lun) return;  // k_row_setup's instance
+  constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
+  const int teams = blockDim.x / T;
+  const int team = threadIdx.x / T, t = threadIdx.x - team * T;
+  c2* lds = smem + team * lds_len(N);
+  const int r0 = 2 * (lb * teams + team);
+  const int rows = I->rows;
+  const double th = sa.theta;
+  Twiddles<PX> tw;
+  load_twiddles<PX>(tw, I->tw_x, t);
+
+  if (lb == 0 && threadIdx.x == 0) {
+    I->a = sa.a;
+    I->theta = sa.theta;
+    I->a_over_theta = sa.a / sa.theta;
+    I->un = sa.un;
+    I->acc_dst = sa.acc_dst;
+    I->acc_ldst = sa.acc_ldst;
+    I->lap_hist = 1;
+    *I->iter_base = 0;
+    *I->flags = 0;
+    I->rec->stop_iter = -1;
+    I->rec->flags = 0;
+    I->rec->norm_bits = 0;
+  }
+  {  // clear the per-iteration norm slots
+    const int nthreads = bpi * blockDim.x;
+    for (int i = lb * blockDim.x + threadIdx.x; i < I->max_iter; i += nthreads) I->norms[i] = 0;
+  }
+
+  double s0 = 0.0, s1 = 0.0;
+  double gv[2][RM], vb[2][RM];
+  const double tau = I->tau, e2 = I->eps * I->eps;
+#pragma unroll
+  for (int row = 0; row < 2; ++row) {
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+      const double u = gp(sa.un)[idx], um = gp(sa.unm1)[idx];
+      const double x0 = u + sa.rho * (u - um);
+      gp(I->X[0])[idx] = x0;
+      gp(I->X[2])[idx] = x0;
+      gv[row][m] = sa.gu * u + sa.gm * um;
+      const double v = th * x0 + (1.0 - th) * u;
+      vb[row][m] = v;
+      const double f1 = (v * v - 1.0) * (v + tau);
+      const double f2 = 3.0 * v * v - 1.0 + 2.0 * tau * v;
+      const double f3 = 6.0 * v + 2.0 * tau;
+      s0 += f2 * f2 - I->eta2 * f2 + f3 * f1;
+      s1 += e2 * f2 - I->eta1 * e2;
+    }
+  }
+  pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, gp(I->G), r0 + 1, rows, t);
+  double lv[2][RM];
+#pragma unroll
+  for (int row = 0; row < 2; ++row) {
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+      const double lu = gp(sa.lun)[idx], lum = gp(sa.lunm1)[idx];
+      const double lx0 = lu + sa.rho * (lu - lum);
+      gp(I->DX[0])[idx] = lx0;
+      gp(I->DX[2])[idx] = lx0;
+      if (th != 1.0) gp(I->dun)[idx] = lu;
+      lv[row][m] = th * lx0 + (1.0 - th) * lu;
+    }
+  }
+  fch_forward_pair<PX>(I, vb, lv, tw, lds, r0, t);
+  const double bs0 = block_sum(s0, red);
+  const double bs1 = block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    gp(I->part)[2 * lb] = bs0;
+    gp(I->part)[2 * lb + 1] = bs1;
+  }
+}
+
 // Step setup, column part: g^ (stored for the whole step, column 0 packed
 // like every spectral field); FCH also the Laplacians of x0 (and of u^n for
 // the midpoint rule) back as spectral rows.  Block 0 sums the averaged-Newton
@@ -1051,7 +1171,7 @@ __global__ __launch_bounds__(512) void k_col_setup(InstDev* const* __restrict__ 
   Twiddles<PY> tw;
   load_twiddles<PY>(tw, I->tw_y, t);
   const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
-  if (blk0 && threadIdx.x == 0) finish_betas(I);
+  if (blk0) finish_betas(I);
   c2 v[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) v[m] = gload(G + sidx(rows, t + m * T, kp));
@@ -1059,7 +1179,7 @@ __global__ __launch_bounds__(512) void k_col_setup(InstDev* const* __restrict__ 
 #pragma unroll
   for (int m = 0; m < RM; ++m) gstore(gp(I->ghat) + sidx(rows, t + m * T, kp), v[m]);
   if constexpr (MODEL == MODEL_FCH) {
-    const int nlap = I->theta != 1.0 ? 2 : 1;
+    const int nlap = I->lap_hist ? 0 : I->theta != 1.0 ? 2 : 1;
     for (int f = 1; f <= nlap; ++f) {
 #pragma unroll
       for (int m = 0; m < RM; ++m) v[m] = gload(G + f * fs + sidx(rows, t + m * T, kp));
@@ -1086,6 +1206,7 @@ __global__ __launch_bounds__(256) void k_row_start_fch(const InstDev* const* __r
   extern __shared__ c2 smem[];
   const GroupPos gpos = group_pos(grp, bpi);
   const InstDev* __restrict__ I = gpos.I;
+  if (I->lap_hist) return;  // the row set-up has done this step's part
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
   const int teams = blockDim.x / T;
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;

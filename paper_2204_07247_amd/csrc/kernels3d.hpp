@@ -147,7 +147,7 @@ __global__ __launch_bounds__(512) void k_y3_setup(InstDev* const* __restrict__ g
   c2* lds = smem + pos.c * lds_len(N);
   Twiddles<PY> tw;
   load_twiddles<PY>(tw, I->tw_y, t);
-  if (lb == 0 && threadIdx.x == 0) finish_betas(I);
+  if (lb == 0) finish_betas(I);
   c2 v[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) v[m] = gload(gp(I->G) + sidx(rows, r0 + t + m * T, kp));

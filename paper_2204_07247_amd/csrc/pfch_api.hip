@@ -34,50 +34,81 @@ inline bool scheme_imex(int s) { return s == PFCH_LBDF2 || s == PFCH_LMP; }
 // ---------------------------------------------------------------------------
 // Small kernels: end of a chunk of iterations, accept, mass reduction.
 // ---------------------------------------------------------------------------
-__global__ void k_chunk_end(InstDev* const* insts, int n, int K) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  InstDev* I = insts[i];
-  StopRec* rec = I->rec;
-  const int base = *I->iter_base;
-  if (rec->stop_iter < 0 && base < I->max_iter + 1) {
-    for (int jj = base; jj < base + K; ++jj) {
-      if (jj >= I->max_iter) {
-        rec->stop_iter = I->max_iter;
-        rec->norm_bits = I->norms[I->max_iter - 1];
-        break;
-      }
-      const uint64_t b = I->norms[jj];
-      if (b < I->tol_bits || b >= INF_BITS) {
-        rec->stop_iter = jj;
-        rec->norm_bits = b;
-        break;
+// One block: every instance's stop record for the chunk just run, mirrored
+// into pinned host memory, then the host-visible chunk counter.
+__global__ __launch_bounds__(256) void k_chunk_end(InstDev* const* insts, int n, int K,
+                                                   uint32_t* __restrict__ seq_dev,
+                                                   uint32_t* __restrict__ seq_host) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    InstDev* I = insts[i];
+    StopRec* rec = I->rec;
+    const int base = *I->iter_base;
+    const int before = rec->stop_iter;
+    if (rec->stop_iter < 0 && base < I->max_iter + 1) {
+      for (int jj = base; jj < base + K; ++jj) {
+        if (jj >= I->max_iter) {
+          rec->stop_iter = I->max_iter;
+          rec->norm_bits = I->norms[I->max_iter - 1];
+          break;
+        }
+        const uint64_t b = I->norms[jj];
+        if (b < I->tol_bits || b >= INF_BITS) {
+          rec->stop_iter = jj;
+          rec->norm_bits = b;
+          break;
+        }
       }
     }
+    rec->flags |= *I->flags;
+    const bool stop = rec->stop_iter >= 0 || (rec->flags & FLAG_PRECOND);
+    *I->iter_base = stop ? I->max_iter + 1 : base + K;
+    // the accept that follows in the graph copies a solution once, in the
+    // chunk that ended its solve
+    const bool ended = before < 0 && rec->stop_iter >= 0;
+    I->acc_now = ended ? I->acc_dst : nullptr;
+    I->acc_lnow = ended ? I->acc_ldst : nullptr;
+    *I->rec_host = *rec;  // the host polls this copy
   }
-  rec->flags |= *I->flags;
-  const bool stop = rec->stop_iter >= 0 || (rec->flags & FLAG_PRECOND);
-  *I->iter_base = stop ? I->max_iter + 1 : base + K;
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t v = *seq_dev + 1;
+    *seq_dev = v;
+    *seq_host = v;
+    __threadfence_system();
+  }
 }
 
-constexpr int ACC_BLOCKS = 64, ACC_THREADS = 256;
+constexpr int ACC_BLOCKS = 1024, ACC_THREADS = 256;
 
 // Accept: copy every converged instance's solution x_{stop+1} to its new
 // u^n slot (dsts[i]; null = not accepted) and, if part is given, write
-// ACC_BLOCKS partial sums of it per instance (fixed order).
+// gridDim.x partial sums of it per instance (fixed order).
 // Up to ACC_INLINE destinations travel by value with the launch.
 constexpr int ACC_INLINE = 16;
 struct AccDsts {
   double* p[ACC_INLINE];
 };
+// check >= 1: accept only an instance whose solve has ended well (the test
+// the host applies to the same record), so the accept can run behind the
+// iterations before the host has seen the outcome; accepting the same
+// solution twice writes the same values.  check = 2 (inside the chunk
+// graph): the destination is the one the step set-up published, in the chunk
+// that ended the solve only (null otherwise, and for solves that are not
+// accepted this way).
 __global__ __launch_bounds__(ACC_THREADS) void k_accept(InstDev* const* __restrict__ insts,
                                                         double* const* __restrict__ dsts,
-                                                        double* __restrict__ part, AccDsts inl) {
+                                                        double* __restrict__ part, AccDsts inl, int check) {
   __shared__ double red[ACC_THREADS / 64];
   const int i = blockIdx.y;
-  double* dst = dsts ? dsts[i] : inl.p[i];
+  double* dst = check == 2 ? insts[i]->acc_now : dsts ? dsts[i] : inl.p[i];
   if (!dst) return;
   const InstDev* I = insts[i];
+  if (check) {  // the same test as status_of on the host
+    const StopRec r = *I->rec;
+    if ((r.flags & FLAG_PRECOND) || r.stop_iter < 0 || r.stop_iter >= I->max_iter || r.norm_bits >= INF_BITS)
+      return;
+  }
   const int slot = (I->rec->stop_iter + 1) % 3;
   const GLB double* src = gp((const double*)I->X[slot]);
   GLB double* d = gp(dst);
@@ -89,17 +120,28 @@ __global__ __launch_bounds__(ACC_THREADS) void k_accept(InstDev* const* __restri
     d[k] = v;
     s += v;
   }
+  if (check == 2 && I->acc_lnow) {  // FCH: keep the solution's Laplacian too
+    const GLB double* ls = gp((const double*)I->DX[slot]);
+    GLB double* ld = gp(I->acc_lnow);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+      ld[k] = ls[k];
+  }
   const double b = block_sum(s, red);
   if (threadIdx.x == 0 && part) part[(int64_t)i * gridDim.x + blockIdx.x] = b;
 }
 
-__global__ void k_sum_parts(const double* __restrict__ part, int nb, int n, const double* scale,
-                            double* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One block per instance: its nb partial sums in a fixed order (strided per
+// thread, then the block's fixed reduction tree).
+__global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int nb, int n,
+                                                   const double* scale, double* out) {
+  __shared__ double red[4];
+  const int i = blockIdx.x;
   if (i >= n) return;
   double s = 0.0;
-  for (int k = 0; k < nb; ++k) s += part[(int64_t)i * nb + k];
-  out[i] = s * scale[i];
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) s += part[(int64_t)i * nb + k];
+  const double b = block_sum(s, red);
+  if (threadIdx.x == 0) out[i] = b * scale[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -120,6 +162,8 @@ struct Instance {
   InstDev* dev = nullptr;  // device descriptor
   InstDev** d_solo = nullptr;  // device array {dev}: single-instance launches
   double* U[2] = {nullptr, nullptr};
+  double* dU[2] = {nullptr, nullptr};  // FCH: Laplacians of U, kept by pfch_step's accept
+  int lap_levels = 0;                  // how many of dU match the history
   int ucur = 0;
   bool has_prev = false;
   double t = 0.0, dt_prev = 0.0;
@@ -186,7 +230,12 @@ struct pfch_ctx {
   std::vector<Group> groups;
   InstDev** d_ptrs = nullptr;  // all instances
   StopRec* d_recs = nullptr;
-  StopRec* h_recs = nullptr;   // pinned
+  StopRec* h_recs = nullptr;   // pinned; written by the chunk-end kernel
+  int32_t* h_scratch = nullptr;  // pinned staging for small uploads
+  uint32_t* d_seq = nullptr;     // chunk counter (device) and its pinned mirror
+  uint32_t* h_seq = nullptr;
+  uint32_t seq = 0;              // chunks launched
+  int acc_blocks = 1;            // accept blocks per instance (<= ACC_BLOCKS)
   double** d_dsts = nullptr;   // accept destinations
   double** h_dsts = nullptr;   // pinned
   double* d_part = nullptr;    // [n][ACC_BLOCKS]
@@ -359,6 +408,10 @@ int setup_instance(pfch_ctx* ctx, Instance& I, int nparts) {
   for (int i = 0; i < 2; ++i) {
     if ((rc = dalloc(I.allocs, &p, rbytes))) return rc;
     I.U[i] = (double*)p;
+    if (fch && I.nz == 1) {
+      if ((rc = dalloc(I.allocs, &p, rbytes))) return rc;
+      I.dU[i] = (double*)p;
+    }
   }
   if ((rc = dalloc(I.allocs, &p, sbytes * nfs))) return rc;
   h.S = (c2*)p;
@@ -471,14 +524,31 @@ int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
     InstDev** ptrs = ctx->d_ptrs;
     int n = (int)ctx->inst.size();
     int k = K;
-    void* args[] = {&ptrs, &n, &k};
+    uint32_t* dseq = ctx->d_seq;
+    uint32_t* hseq = nullptr;
+    HIPCHK(hipHostGetDevicePointer((void**)&hseq, ctx->h_seq, 0));
+    void* args[] = {&ptrs, &n, &k, &dseq, &hseq};
     p.func = (void*)&k_chunk_end;
-    p.gridDim = dim3((n + 63) / 64);
-    p.blockDim = dim3(64);
+    p.gridDim = dim3(1);
+    p.blockDim = dim3(256);
     p.sharedMemBytes = 0;
     p.kernelParams = args;
     hipGraphNode_t node;
     HIPCHK(hipGraphAddKernelNode(&node, g, tails.data(), tails.size(), &p));
+    // accept of the instances whose set-up published a destination
+    hipKernelNodeParams q{};
+    double** nodsts = nullptr;
+    double* part = ctx->d_part;
+    AccDsts none{};
+    int check = 2;
+    void* qargs[] = {&ptrs, &nodsts, &part, &none, &check};
+    q.func = (void*)&k_accept;
+    q.gridDim = dim3(ctx->acc_blocks, n);
+    q.blockDim = dim3(ACC_THREADS);
+    q.sharedMemBytes = 0;
+    q.kernelParams = qargs;
+    hipGraphNode_t anode;
+    HIPCHK(hipGraphAddKernelNode(&anode, g, &node, 1, &q));
   }
   hipGraphExec_t ex;
   HIPCHK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
@@ -505,6 +575,10 @@ struct StepSetup {
   const double* unm1;
   const double* xin;
   double a, b, c, theta, rho;
+  double* acc_dst = nullptr;
+  const double* lun = nullptr;
+  const double* lunm1 = nullptr;
+  double* acc_ldst = nullptr;
 };
 
 StepArgs to_args(const StepSetup& ss) {
@@ -517,6 +591,10 @@ StepArgs to_args(const StepSetup& ss) {
   sa.theta = ss.theta;
   sa.gu = ss.b - ss.a * (1.0 - ss.theta) / ss.theta;
   sa.gm = ss.c;
+  sa.acc_dst = ss.acc_dst;
+  sa.lun = ss.lun;
+  sa.lunm1 = ss.lunm1;
+  sa.acc_ldst = ss.acc_ldst;
   return sa;
 }
 
@@ -550,8 +628,11 @@ StepSetup step_setup_for(const Instance& I, double dt) {
 
 // Setup kernels for `nm` instances of group G described by the device arrays
 // (grp, args).
+// start_fch: some instance takes Delta x0 from transforms (k_row_setup,
+// k_row_start_fch); lap: some instance takes it from kept Laplacians
+// (k_row_setup_lap).  Each row set-up kernel skips the other's instances.
 int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, unsigned nm,
-                 const StepArgsInline* inl = nullptr) {
+                 const StepArgsInline* inl = nullptr, bool start_fch = true, bool lap = false) {
   int rc;
   int rbpi = G.srow_bpi, cbpi = G.scol_bpi;
   StepArgsInline il{};
@@ -559,9 +640,13 @@ int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, u
     il = *inl;
     args = nullptr;
   }
-  {
+  if (start_fch || G.model != PFCH_FCH) {
     void* a[] = {&grp, &args, &rbpi, &il};
     if ((rc = launch(G.rs.setup, dim3(nm * rbpi), G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
+  }
+  if (lap && G.model == PFCH_FCH) {
+    void* a[] = {&grp, &args, &rbpi, &il};
+    if ((rc = launch(G.rs.setup_lap, dim3(nm * rbpi), G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
   }
   if (G.ndim == 3) {
     int ybpi = G.y3_bpi, zbpi = G.z3_bpi;
@@ -575,7 +660,7 @@ int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, u
     void* a[] = {&grp, &cbpi};
     if ((rc = launch(G.cs.setup, dim3(nm * cbpi), G.scol_block, G.scol_lds, a, ctx->stream))) return rc;
   }
-  if (G.model == PFCH_FCH) {
+  if (G.model == PFCH_FCH && start_fch) {
     void* a[] = {&grp, &rbpi};
     if ((rc = launch(G.rs.start_fch, dim3(nm * rbpi), G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
   }
@@ -585,10 +670,38 @@ int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, u
 int launch_setup_solo(pfch_ctx* ctx, Instance& I, const StepSetup& ss) {
   StepArgsInline inl{};
   inl.a[0] = to_args(ss);
-  return launch_setup(ctx, ctx->groups[I.group], I.d_solo, nullptr, 1, &inl);
+  return launch_setup(ctx, ctx->groups[I.group], I.d_solo, nullptr, 1, &inl, ss.lun == nullptr,
+                      ss.lun != nullptr);
 }
 
-// Replay iteration chunks until every instance in `active` has stopped.
+int launch_accept(pfch_ctx* ctx, AccDsts inl, double** dsts, double* part, int check) {
+  InstDev** ptrs = ctx->d_ptrs;
+  void* a[] = {&ptrs, &dsts, &part, &inl, &check};
+  return launch((const void*)&k_accept, dim3(ctx->acc_blocks, (unsigned)ctx->inst.size()), dim3(ACC_THREADS), 0, a,
+                ctx->stream);
+}
+
+// Wait for chunk number `want`: watch the pinned counter the chunk-end kernel
+// writes (a chunk takes tens of microseconds; a stream synchronisation would
+// add its own wake-up latency), then fall back to synchronising the stream,
+// which also reports any error.  Work queued after the chunk (the graph's
+// accept) keeps running in stream order.
+int wait_chunk(pfch_ctx* ctx, uint32_t want) {
+  const volatile uint32_t* seq = ctx->h_seq;
+  for (long k = 0; k < 2000000; ++k) {  // bounded: about a millisecond or more
+    if ((int32_t)(*seq - want) >= 0) return PFCH_OK;
+#if defined(__x86_64__)
+    __builtin_ia32_pause();
+#endif
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return PFCH_OK;
+}
+
+// Replay iteration chunks until every instance in `active` has stopped.  The
+// chunk graph ends with the stop records mirrored into pinned host memory and
+// a progress counter the host waits on, then the accept of instances whose
+// set-up published a destination.
 int run_iterations(pfch_ctx* ctx, const std::vector<int>& active) {
   int predicted = 1;
   bool known = true;
@@ -597,15 +710,12 @@ int run_iterations(pfch_ctx* ctx, const std::vector<int>& active) {
     known = known && ctx->inst[i].last_iters > 0;
   }
   int K = chunk_len(known ? predicted : 16);
-  const int n = (int)ctx->inst.size();
   for (;;) {
     hipGraphExec_t ex;
     int rc = get_graph(ctx, K, &ex);
     if (rc) return rc;
     HIPCHK(hipGraphLaunch(ex, ctx->stream));
-    HIPCHK(hipMemcpyAsync(ctx->h_recs, ctx->d_recs, sizeof(StopRec) * n, hipMemcpyDeviceToHost,
-                          ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if ((rc = wait_chunk(ctx, ++ctx->seq))) return rc;
     bool all = true;
     for (int i : active) {
       const StopRec& r = ctx->h_recs[i];
@@ -1229,7 +1339,7 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
         if (f && G.scol_lds > 65536)
           (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.scol_lds);
     }
-    const void* fs[] = {G.rs.iter, G.rs.setup, G.rs.start_fch};
+    const void* fs[] = {G.rs.iter, G.rs.setup, G.rs.start_fch, G.rs.setup_lap};
     for (const void* f : fs)
       if (f && G.row_lds > 65536)
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.row_lds);
@@ -1244,6 +1354,10 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   ctx->d_ptrs = (InstDev**)p;
   if ((rc = dalloc(ctx->allocs, &p, sizeof(double*) * n_inst))) goto fail;
   ctx->d_dsts = (double**)p;
+  for (int i = 0; i < n_inst; ++i)  // about eight points per thread, at most ACC_BLOCKS blocks
+    ctx->acc_blocks = std::max(ctx->acc_blocks,
+                               (int)std::min<int64_t>(ACC_BLOCKS, (ctx->inst[i].npts + 8 * ACC_THREADS - 1) /
+                                                                      (8 * ACC_THREADS)));
   if ((rc = dalloc(ctx->allocs, &p, sizeof(double) * n_inst * ACC_BLOCKS))) goto fail;
   ctx->d_part = (double*)p;
   if ((rc = dalloc(ctx->allocs, &p, sizeof(double) * n_inst))) goto fail;
@@ -1252,6 +1366,17 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   ctx->d_mass = (double*)p;
   if ((rc = halloc(ctx->host_allocs, &p, sizeof(StopRec) * n_inst))) goto fail;
   ctx->h_recs = (StopRec*)p;
+  if ((rc = halloc(ctx->host_allocs, &p, 64))) goto fail;
+  ctx->h_scratch = (int32_t*)p;
+  if ((rc = halloc(ctx->host_allocs, &p, 64))) goto fail;
+  ctx->h_seq = (uint32_t*)p;
+  *ctx->h_seq = 0;
+  if ((rc = dalloc(ctx->allocs, &p, 64))) goto fail;
+  ctx->d_seq = (uint32_t*)p;
+  if (hipMemset(ctx->d_seq, 0, 64) != hipSuccess) {
+    rc = PFCH_E_HIP;
+    goto fail;
+  }
   if ((rc = halloc(ctx->host_allocs, &p, sizeof(double*) * n_inst))) goto fail;
   ctx->h_dsts = (double**)p;
   if ((rc = halloc(ctx->host_allocs, &p, sizeof(double) * n_inst))) goto fail;
@@ -1271,6 +1396,14 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
       Instance& I = ctx->inst[i];
       if ((rc = setup_instance(ctx, I, ctx->groups[I.group].srow_bpi))) goto fail;
       I.h.rec = ctx->d_recs + i;
+      {
+        void* hp = nullptr;
+        if (hipHostGetDevicePointer(&hp, ctx->h_recs, 0) != hipSuccess) {
+          rc = PFCH_E_HIP;
+          goto fail;
+        }
+        I.h.rec_host = (StopRec*)hp + i;
+      }
       if (hipMemcpy(I.dev, &I.h, sizeof(InstDev), hipMemcpyHostToDevice) != hipSuccess) {
         rc = PFCH_E_HIP;
         goto fail;
@@ -1391,7 +1524,7 @@ int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
   if (rc) return rc;
   for (int k = 0; k < 4; ++k) out[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
   // park the instance so later chunk launches leave it alone
-  int32_t* park = (int32_t*)ctx->h_recs;  // pinned scratch, free until the next poll
+  int32_t* park = ctx->h_scratch;
   *park = I.d.max_iter + 1;
   HIPCHK(hipMemcpyAsync(I.h.iter_base, park, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1428,7 +1561,7 @@ int pfch_time_kernels_events(pfch_ctx* ctx, double dt, int32_t reps, double out[
   }
   for (auto& ev : e) (void)hipEventDestroy(ev);
   // park the instance so later chunk launches leave it alone
-  int32_t* park = (int32_t*)ctx->h_recs;  // pinned scratch, free until the next poll
+  int32_t* park = ctx->h_scratch;
   *park = I.d.max_iter + 1;
   HIPCHK(hipMemcpyAsync(I.h.iter_base, park, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1535,6 +1668,7 @@ int pfch_set_state(pfch_ctx* ctx, int32_t inst, const double* u_n, const double*
   I.step_index = step_index;
   I.hist = I.has_prev ? 2 : 1;
   I.r_valid = false;
+  I.lap_levels = 0;
   return PFCH_OK;
 }
 
@@ -1561,9 +1695,23 @@ struct SolveOut {
   std::vector<double> dn, a;
 };
 
+// Up to Nx = 1024 the fused set-up (one row kernel doing four transforms)
+// is faster than the three-kernel path; at 2048 its register use leaves one
+// wave per SIMD and the split path wins, so the Laplacians are not kept.
+bool lap_history_pays(const Instance& I) { return I.nx <= 1024; }
+
+// FCH with an extrapolated guess and two kept Laplacians: the set-up takes
+// Delta x0 from them instead of from transforms of x0.
+void lap_from_history(const Instance& I, StepSetup& ss) {
+  if (I.dU[0] && lap_history_pays(I) && I.lap_levels >= 2 && I.has_prev && !ss.xin) {
+    ss.lun = I.dU[I.ucur];
+    ss.lunm1 = I.dU[1 - I.ucur];
+  }
+}
+
 // Tentative solve of every instance at step size dt[i]: set-up, PAGD
 // iterations, and the learned-guess fallback.  Nothing is accepted.
-int solve_all(pfch_ctx* ctx, const double* dt, SolveOut& o) {
+int solve_all(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept = false) {
   const int n = (int)ctx->inst.size();
   o.status.assign(n, PFCH_OK);
   o.iters.assign(n, 0);
@@ -1577,23 +1725,33 @@ int solve_all(pfch_ctx* ctx, const double* dt, SolveOut& o) {
     for (size_t k = 0; k < G.members.size(); ++k) {
       Instance& I = ctx->inst[G.members[k]];
       StepSetup ss = step_setup_for(I, dt[G.members[k]]);
+      if (accept) {
+        ss.acc_dst = I.U[1 - I.ucur];
+        if (lap_history_pays(I)) ss.acc_ldst = I.dU[1 - I.ucur];
+      }
       if (I.fno && I.d.guess == 1 && I.has_prev) {
         if ((rc = learned_guess(ctx, I, ss.rho))) return rc;
         ss.xin = I.xguess;
         o.guess[G.members[k]] = 1;
       }
+      lap_from_history(I, ss);
       o.a[G.members[k]] = ss.a;
       G.h_args[k] = to_args(ss);
     }
     const unsigned nm = (unsigned)G.members.size();
+    bool start_fch = false, lap = false;
+    for (unsigned k = 0; k < nm; ++k) {
+      start_fch = start_fch || !G.h_args[k].lun;
+      lap = lap || G.h_args[k].lun;
+    }
     if (nm <= (unsigned)STEP_ARGS_INLINE) {
       StepArgsInline inl{};
       for (unsigned k = 0; k < nm; ++k) inl.a[k] = G.h_args[k];
-      if ((rc = launch_setup(ctx, G, G.d_members, nullptr, nm, &inl))) return rc;
+      if ((rc = launch_setup(ctx, G, G.d_members, nullptr, nm, &inl, start_fch, lap))) return rc;
     } else {
       HIPCHK(hipMemcpyAsync(G.d_args, G.h_args, sizeof(StepArgs) * nm, hipMemcpyHostToDevice,
                             ctx->stream));
-      if ((rc = launch_setup(ctx, G, G.d_members, G.d_args, nm))) return rc;
+      if ((rc = launch_setup(ctx, G, G.d_members, G.d_args, nm, nullptr, start_fch, lap))) return rc;
     }
   }
   if ((rc = run_iterations(ctx, active))) return rc;
@@ -1606,7 +1764,13 @@ int solve_all(pfch_ctx* ctx, const double* dt, SolveOut& o) {
     double d = 0.0;
     if (status_of(ctx->inst[i], ctx->h_recs[i], &it, &d) == PFCH_OK) continue;
     Instance& I = ctx->inst[i];
-    if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, dt[i])))) return rc;
+    StepSetup ss = step_setup_for(I, dt[i]);
+    if (accept) {
+      ss.acc_dst = I.U[1 - I.ucur];
+      if (lap_history_pays(I)) ss.acc_ldst = I.dU[1 - I.ucur];
+    }
+    lap_from_history(I, ss);
+    if ((rc = launch_setup_solo(ctx, I, ss))) return rc;
     o.guess[i] = 2;
     retry.push_back(i);
   }
@@ -1623,38 +1787,34 @@ const double* solution_of(const Instance& I, const StopRec& r) { return I.h.X[(r
 // and step counters advanced; with want_mass, the mean of each accepted
 // solution lands in ctx->h_mass after the stream is synchronised.
 int accept_solutions(pfch_ctx* ctx, const std::vector<char>& take, const double* dt, const SolveOut& o,
-                     bool want_mass, bool adaptive) {
+                     bool want_mass, bool adaptive, bool copied = false) {
   const int n = (int)ctx->inst.size();
   int rc;
-  for (int i = 0; i < n; ++i) {
-    Instance& I = ctx->inst[i];
-    ctx->h_dsts[i] = nullptr;
-    if (!take[i]) continue;
-    if (adaptive) std::swap(I.Um2, I.U[1 - I.ucur]);  // u^{n-1} becomes u^{n-2}
-    ctx->h_dsts[i] = I.U[1 - I.ucur];
-  }
-  AccDsts inl{};
-  double** dsts = nullptr;
-  if (n <= ACC_INLINE) {
-    for (int i = 0; i < n; ++i) inl.p[i] = ctx->h_dsts[i];
-  } else {
-    HIPCHK(hipMemcpyAsync(ctx->d_dsts, ctx->h_dsts, sizeof(double*) * n, hipMemcpyHostToDevice, ctx->stream));
-    dsts = ctx->d_dsts;
-  }
-  {
-    InstDev** ptrs = ctx->d_ptrs;
-    double* part = want_mass ? ctx->d_part : nullptr;
-    void* a[] = {&ptrs, &dsts, &part, &inl};
-    if ((rc = launch((const void*)&k_accept, dim3(ACC_BLOCKS, n), dim3(ACC_THREADS), 0, a, ctx->stream)))
-      return rc;
+  if (!copied) {  // else the checked accept inside the chunk graph has copied them
+    for (int i = 0; i < n; ++i) {
+      Instance& I = ctx->inst[i];
+      ctx->h_dsts[i] = nullptr;
+      if (!take[i]) continue;
+      if (adaptive) std::swap(I.Um2, I.U[1 - I.ucur]);  // u^{n-1} becomes u^{n-2}
+      ctx->h_dsts[i] = I.U[1 - I.ucur];
+    }
+    AccDsts inl{};
+    double** dsts = nullptr;
+    if (n <= ACC_INLINE) {
+      for (int i = 0; i < n; ++i) inl.p[i] = ctx->h_dsts[i];
+    } else {
+      HIPCHK(hipMemcpyAsync(ctx->d_dsts, ctx->h_dsts, sizeof(double*) * n, hipMemcpyHostToDevice, ctx->stream));
+      dsts = ctx->d_dsts;
+    }
+    if ((rc = launch_accept(ctx, inl, dsts, want_mass ? ctx->d_part : nullptr, 0))) return rc;
   }
   if (want_mass) {
     const double* part = ctx->d_part;
-    int nb = ACC_BLOCKS, nn = n;
+    int nb = ctx->acc_blocks, nn = n;
     const double* scale = ctx->d_scale;
     double* o2 = ctx->d_mass;
     void* a[] = {&part, &nb, &nn, &scale, &o2};
-    if ((rc = launch((const void*)&k_sum_parts, dim3((n + 63) / 64), dim3(64), 0, a, ctx->stream))) return rc;
+    if ((rc = launch((const void*)&k_sum_parts, dim3(n), dim3(256), 0, a, ctx->stream))) return rc;
     HIPCHK(hipMemcpyAsync(ctx->h_mass, ctx->d_mass, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
   }
   for (int i = 0; i < n; ++i) {
@@ -1668,6 +1828,8 @@ int accept_solutions(pfch_ctx* ctx, const std::vector<char>& take, const double*
       I.hist = 2;  // u^{n-2} is not kept by plain steps
       I.r_valid = false;
     }
+    // the in-graph accept of pfch_step also keeps the Laplacian (FCH)
+    I.lap_levels = copied && I.dU[0] && lap_history_pays(I) ? std::min(I.lap_levels + 1, 2) : 0;
     I.has_prev = true;
     I.dt_prev = dt[i];
     I.t += dt[i];
@@ -1789,15 +1951,17 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
     if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return PFCH_E_INVAL;
   SolveOut o;
   int rc;
-  if ((rc = solve_all(ctx, dt, o))) return rc;
+  const bool want_mass = st && ctx->stats_detail > 0;
+  // every instance's accept runs inside the chunk graph, checked on the
+  // device against the same stop record the host reads afterwards
+  if ((rc = solve_all(ctx, dt, o, true))) return rc;
   int first_err = PFCH_OK;
   std::vector<char> take(n);
   for (int i = 0; i < n; ++i) {
     take[i] = o.status[i] == PFCH_OK;
     if (!take[i] && first_err == PFCH_OK) first_err = o.status[i];
   }
-  const bool want_mass = st && ctx->stats_detail > 0;
-  if ((rc = accept_solutions(ctx, take, dt, o, want_mass, false))) return rc;
+  if ((rc = accept_solutions(ctx, take, dt, o, want_mass, false, true))) return rc;
   if (st) {
     if (want_mass) HIPCHK(hipStreamSynchronize(ctx->stream));
     for (int i = 0; i < n; ++i)

@@ -39,6 +39,11 @@ struct InstDev {
   double a, theta, a_over_theta;
   double beta0, beta2;     // averaged-Newton constants (setup column kernel)
   const double* un;        // u^n used by the midpoint blend
+  double* acc_dst;         // accept destination of this step (null: the host accepts)
+  double* acc_now;         // acc_dst in the chunk whose end stopped the solve, else null
+  double* acc_ldst;        // FCH: where the Laplacian of the accepted solution goes
+  double* acc_lnow;        // acc_ldst like acc_now
+  int32_t lap_hist;        // FCH: this step's set-up took Delta x0 from the kept Laplacians
   // state buffers
   double* X[3];            // iterate ring x_j at X[j % 3]
   double* DX[3];           // FCH: Laplacian of the iterate, same ring
@@ -51,6 +56,7 @@ struct InstDev {
   int32_t* iter_base;      // first iteration index of the current chunk
   int32_t* flags;          // FLAG_* bits raised by kernels
   StopRec* rec;
+  StopRec* rec_host;       // pinned host mirror of *rec, written at each chunk end
   const c2* tw_x;          // twiddles for the x length
   const c2* tw_y;          // twiddles for the y length
   const c2* tw_z;          // twiddles for the z length (3D)

@@ -16,6 +16,7 @@ struct RowK {
   const void* iter = nullptr;
   const void* setup = nullptr;
   const void* start_fch = nullptr;
+  const void* setup_lap = nullptr;  // FCH set-up from kept Laplacians
   const void* rhs_fwd = nullptr;  // R(v) row passes (default plans only)
   const void* rhs_mid = nullptr;  // FCH
   const void* rhs_inv = nullptr;
@@ -48,6 +49,7 @@ RowK make_row() {
   k.iter = (const void*)&k_row_iter<P, MODEL, MPS>;
   k.setup = (const void*)&k_row_setup<P, MODEL>;
   if (MODEL == MODEL_FCH) k.start_fch = (const void*)&k_row_start_fch<P>;
+  if (MODEL == MODEL_FCH) k.setup_lap = (const void*)&k_row_setup_lap<P>;
   k.rhs_fwd = (const void*)&k_rhs_row_fwd<P, MODEL>;
   if (MODEL == MODEL_FCH) k.rhs_mid = (const void*)&k_rhs_row_mid<P>;
   k.rhs_inv = (const void*)&k_rhs_row_inv<P>;
