@@ -126,3 +126,40 @@ def test_failure_modes_leave_state_untouched():
     rc, st = ctx.step(0.1)
     assert rc in (pfch.PFCH_E_NONFINITE, pfch.PFCH_E_PRECOND)
     ctx.close()
+
+
+@pytest.mark.parametrize("scheme,shape", [("bdf2", (256, 256)), ("mp", (64, 64)), ("bdf2", (1024, 1024))])
+def test_kept_laplacian_setup_matches_transform_setup(scheme, shape):
+    """FCH steps from the third on take Delta x0 from the Laplacians kept by
+    the previous accepts (up to Nx = 1024); re-setting the state before
+    every step forces the transform path instead.  Both must give the same
+    iterations and states to rounding."""
+    import dataclasses
+    import math
+    import torch
+    from paper_2204_07247_amd import pfch
+    h = 4 * math.pi / 256
+    w = dataclasses.replace(W.FCH256_BDF2, scheme=scheme, shape=shape,
+                            lengths=(shape[0] * h, shape[1] * h), seeds=(7,))
+    print(f"kept laplacian {scheme} {shape}", flush=True)
+    u0 = torch.from_numpy(W.initial_condition(w)).cuda()
+    ctxs = [pfch.Context([desc_for(w)]) for _ in range(2)]
+    for c in ctxs:
+        c.set_state(0, u0)
+    un, unm1 = torch.empty_like(u0), torch.empty_like(u0)
+    for k in range(8):
+        rc, st = ctxs[0].step(w.dt)
+        assert rc == pfch.PFCH_OK
+        # second context: same history, but handed back through set_state
+        t, dtp, n = ctxs[1].get_state(0, un, unm1)
+        if k > 0:
+            ctxs[1].set_state(0, un, unm1, t, dtp, n)
+        rc2, st2 = ctxs[1].step(w.dt)
+        assert rc2 == pfch.PFCH_OK
+        assert st[0]["iters"] == st2[0]["iters"], k
+    a, b = torch.empty_like(u0), torch.empty_like(u0)
+    ctxs[0].get_state(0, a)
+    ctxs[1].get_state(0, b)
+    for c in ctxs:
+        c.close()
+    assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
