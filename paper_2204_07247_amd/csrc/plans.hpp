@@ -209,7 +209,8 @@ ColK make_col_fp() {
   return k;
 }
 #define PFCH_FP_PLANS(X) \
-  X(64, P64) X(64, A64a) X(128, P128) X(128, A128a) X(256, P256) X(256, A256a) X(512, P512) X(1024, P1024)
+  X(64, P64) X(64, A64a) X(128, P128) X(128, A128a) X(256, P256) X(256, A256a) X(512, P512) X(1024, P1024) \
+  X(1024, A1024b)
 
 template <int MODEL, bool MPS>
 void row_fp_alternatives(int n, std::vector<RowK>& out) {
