@@ -5,13 +5,13 @@ checks).  Not part of the paper: the learned warm start of the PAGD solve
 predicts a correction to the extrapolated initial guess.
 
 Network (width W, retained modes M per axis, L spectral layers), input
-x[b, 2, Ny, Nx]:
+x[b, 2, Ny, Nx] (2D) or x[b, 2, Nz, Ny, Nx] (3D):
     v0 = lift(x)            v0[b,o] = sum_i P[i,o] x[b,i] + pb[o]
     for l < L:
-        s  = K_l(v)         spectral convolution: rfft2 over (y, x), keep
-                            ky in {0..M-1} U {Ny-M..Ny-1}, kx in {0..M-1},
-                            multiply by R_l[i,o,ky,kx] summed over i, zero
-                            every other mode, irfft2
+        s  = K_l(v)         spectral convolution: real FFT over the grid axes,
+                            keep kx in {0..M-1} and, on every other axis, k in
+                            {0..M-1} U {N-M..N-1}, multiply by R_l[i,o,k]
+                            summed over i, zero every other mode, inverse FFT
         z  = s + sum_i W_l[i,o] v[b,i] + b_l[o]
         v  = gelu(z) for l < L-1, v = z for the last layer
     y[b] = sum_i Q[i] v[b,i] + qb                       (one output channel)
@@ -19,8 +19,10 @@ gelu(z) = z (1 + erf(z / sqrt 2)) / 2.  Loss: mean over all points of
 (y - t)^2.
 
 Flat parameter layout (float32 on the device, float64 here), in order:
-P[2][W], pb[W], then per layer R[W][W][2M][M][2] (re, im; index kyi < M is
-ky = kyi, kyi >= M is ky = Ny - 2M + kyi), Wl[W][W], bl[W]; then Q[W], qb[1].
+P[2][W], pb[W], then per layer R[W][W][2M][M][2] (2D) or
+R[W][W][2M][2M][M][2] (3D, kz then ky then kx) (re, im; on a full axis index
+ki < M is k = ki, ki >= M is k = N - 2M + ki), Wl[W][W], bl[W]; then Q[W],
+qb[1].
 """
 import math
 
@@ -28,13 +30,19 @@ import numpy as np
 from scipy.special import erf
 
 
-def n_params(width, modes, layers):
-    W, M = width, modes
-    return 2 * W + W + layers * (W * W * 2 * M * M * 2 + W * W + W) + W + 1
+def n_modes(modes, ndim=2):
+    """Retained complex modes per channel pair: (2M)^(ndim-1) M."""
+    return (2 * modes) ** (ndim - 1) * modes
 
 
-def unpack(theta, width, modes, layers):
+def n_params(width, modes, layers, ndim=2):
+    W = width
+    return 2 * W + W + layers * (W * W * n_modes(modes, ndim) * 2 + W * W + W) + W + 1
+
+
+def unpack(theta, width, modes, layers, ndim=2):
     W, M = width, modes
+    rshape = (W, W) + (2 * M,) * (ndim - 1) + (M, 2)
     p = {}
     o = 0
 
@@ -48,7 +56,7 @@ def unpack(theta, width, modes, layers):
     p["pb"] = take(W, (W,))
     p["R"], p["W"], p["b"] = [], [], []
     for _ in range(layers):
-        r = take(W * W * 2 * M * M * 2, (W, W, 2 * M, M, 2))
+        r = take(W * W * n_modes(M, ndim) * 2, rshape)
         p["R"].append(r[..., 0] + 1j * r[..., 1])
         p["W"].append(take(W * W, (W, W)))
         p["b"].append(take(W, (W,)))
@@ -58,21 +66,28 @@ def unpack(theta, width, modes, layers):
     return p
 
 
-def init_params(width, modes, layers, seed=0):
+def init_params(width, modes, layers, seed=0, ndim=2):
     """Deterministic initial weights (scaled uniform)."""
     rng = np.random.default_rng(seed)
     W, M = width, modes
     parts = [rng.uniform(-1, 1, 2 * W) / math.sqrt(2), np.zeros(W)]
     for _ in range(layers):
-        parts.append(rng.uniform(0, 1, W * W * 2 * M * M * 2) / (W * W))
+        parts.append(rng.uniform(0, 1, W * W * n_modes(M, ndim) * 2) / (W * W))
         parts.append(rng.uniform(-1, 1, W * W) / math.sqrt(W))
         parts.append(np.zeros(W))
     parts += [rng.uniform(-1, 1, W) / math.sqrt(W), np.zeros(1)]
     return np.concatenate(parts)
 
 
-def _kept_ky(ny, modes):
-    return np.concatenate([np.arange(modes), np.arange(ny - modes, ny)])
+def _kept(n, modes):
+    return np.concatenate([np.arange(modes), np.arange(n - modes, n)])
+
+
+def _kept_index(shape, modes):
+    """Index tuple selecting the retained modes of a real-FFT array whose
+    last len(shape) axes are the grid axes (x last, half spectrum)."""
+    full = [np.ix_(*([_kept(n, modes) for n in shape[:-1]] + [np.arange(modes)]))]
+    return (Ellipsis,) + tuple(full[0])
 
 
 def gelu(z):
@@ -84,28 +99,32 @@ def gelu_grad(z):
 
 
 def spectral(v, R, modes):
-    """K v for v[b, i, Ny, Nx] with weights R[i, o, 2M, M] (complex)."""
-    b, _, ny, nx = v.shape
-    ky = _kept_ky(ny, modes)
-    vh = np.fft.rfft2(v)[:, :, ky, :modes]
-    yh = np.einsum("bikl,iokl->bokl", vh, R)
-    full = np.zeros((b, R.shape[1], ny, nx // 2 + 1), dtype=np.complex128)
-    full[:, :, ky, :modes] = yh
-    return np.fft.irfft2(full, s=(ny, nx))
+    """K v for v[b, i, *grid] with weights R[i, o, *kept modes] (complex)."""
+    grid = v.shape[2:]
+    axes = tuple(range(2, v.ndim))
+    sel = _kept_index(grid, modes)
+    vh = np.fft.rfftn(v, axes=axes)[sel]
+    yh = np.einsum("bi...,io...->bo...", vh, R)
+    full = np.zeros((v.shape[0], R.shape[1]) + grid[:-1] + (grid[-1] // 2 + 1,), dtype=np.complex128)
+    full[sel] = yh
+    return np.fft.irfftn(full, s=grid, axes=axes)
 
 
 def forward(theta, x, width, modes, layers):
-    """Returns (y[b, Ny, Nx], cache)."""
-    p = unpack(theta, width, modes, layers)
-    v = np.einsum("bixy,io->boxy", x, p["P"]) + p["pb"][None, :, None, None]
+    """Returns (y[b, *grid], cache); 2D or 3D from x's rank."""
+    ndim = x.ndim - 2
+    p = unpack(theta, width, modes, layers, ndim)
+    lift = lambda a, w: np.einsum("bi...,io->bo...", a, w)
+    chan = lambda c: c.reshape((1, -1) + (1,) * ndim)
+    v = lift(x, p["P"]) + chan(p["pb"])
     cache = {"x": x, "v": [v], "z": []}
     for l in range(layers):
         s = spectral(v, p["R"][l], modes)
-        z = s + np.einsum("bixy,io->boxy", v, p["W"][l]) + p["b"][l][None, :, None, None]
+        z = s + lift(v, p["W"][l]) + chan(p["b"][l])
         cache["z"].append(z)
         v = gelu(z) if l < layers - 1 else z
         cache["v"].append(v)
-    y = np.einsum("bixy,i->bxy", v, p["Q"]) + p["qb"][0]
+    y = np.einsum("bi...,i->b...", v, p["Q"]) + p["qb"][0]
     return y, cache
 
 
@@ -116,45 +135,51 @@ def loss(theta, x, t, width, modes, layers):
 
 def backward(theta, x, t, width, modes, layers):
     """Gradient of the loss with respect to the flat parameter vector."""
-    p = unpack(theta, width, modes, layers)
+    ndim = x.ndim - 2
+    p = unpack(theta, width, modes, layers, ndim)
     y, c = forward(theta, x, width, modes, layers)
-    b, _, ny, nx = x.shape
-    ky = _kept_ky(ny, modes)
+    grid = x.shape[2:]
+    axes = tuple(range(2, x.ndim))
+    sum_axes = (0,) + axes
+    npts = int(np.prod(grid))
+    sel = _kept_index(grid, modes)
     dy = 2.0 * (y - t) / y.size
     g = {"R": [None] * layers, "W": [None] * layers, "b": [None] * layers}
     v_last = c["v"][-1]
-    g["Q"] = np.einsum("bixy,bxy->i", v_last, dy)
+    flat = lambda a: a.reshape(a.shape[:a.ndim - ndim] + (-1,))  # grid axes -> one
+    g["Q"] = np.einsum("bip,bp->i", flat(v_last), flat(dy))
     g["qb"] = np.array([dy.sum()])
-    dv = np.einsum("bxy,i->bixy", dy, p["Q"])
+    dv = np.einsum("b...,i->bi...", dy, p["Q"])
+    nxh = grid[-1] // 2 + 1
+    wk = np.full(nxh, 2.0)
+    wk[0] = 1.0
+    if grid[-1] % 2 == 0:
+        wk[-1] = 1.0
     for l in reversed(range(layers)):
         z = c["z"][l]
         dz = dv * gelu_grad(z) if l < layers - 1 else dv
         v_in = c["v"][l]
-        g["b"][l] = dz.sum(axis=(0, 2, 3))
-        g["W"][l] = np.einsum("bixy,boxy->io", v_in, dz)
-        dv_in = np.einsum("boxy,io->bixy", dz, p["W"][l])
-        # spectral path: s = irfft2(place(vh_kept @ R)); real loss gradient
-        # through irfft2 is rfft2 with the Hermitian weights of the half
-        # spectrum (1/(Ny Nx) per mode, doubled for 0 < kx < Nx/2).
-        dfull = np.fft.rfft2(dz) / (ny * nx)
-        wk = np.full(nx // 2 + 1, 2.0)
-        wk[0] = 1.0
-        if nx % 2 == 0:
-            wk[-1] = 1.0
-        dyh = np.conj(dfull[:, :, ky, :modes]) * wk[None, None, None, :modes]
+        g["b"][l] = dz.sum(axis=sum_axes)
+        g["W"][l] = np.einsum("bip,bop->io", flat(v_in), flat(dz))
+        dv_in = np.einsum("bo...,io->bi...", dz, p["W"][l])
+        # spectral path: s = irfftn(place(vh_kept @ R)); the real loss
+        # gradient through irfftn is rfftn with the Hermitian weights of the
+        # half spectrum (1/P per mode, doubled for 0 < kx < Nx/2).
+        dfull = np.fft.rfftn(dz, axes=axes) / npts
+        dyh = np.conj(dfull[sel]) * wk[:modes]
         # dyh holds dL/d(yh) in the convention dL = Re(sum dyh * d yh)
-        vh = np.fft.rfft2(v_in)[:, :, ky, :modes]
+        vh = np.fft.rfftn(v_in, axes=axes)[sel]
         # yh = sum_i vh R  ->  dR = sum_b vh * dyh  (same convention)
-        g["R"][l] = np.einsum("bikl,bokl->iokl", vh, dyh)
-        dvh = np.einsum("bokl,iokl->bikl", dyh, p["R"][l])
+        g["R"][l] = np.einsum("bi...,bo...->io...", vh, dyh)
+        dvh = np.einsum("bo...,io...->bi...", dyh, p["R"][l])
         # vh_k = sum_x v e^{-i phi_k}, so d(Re sum_k dvh_k vh_k)/dv(x) =
-        # Re(sum_k dvh_k e^{-i phi_k}): a forward fft2 of the zero-padded
+        # Re(sum_k dvh_k e^{-i phi_k}): a forward FFT of the zero-padded
         # array of dvh over the kept modes.
-        full = np.zeros((b, width, ny, nx), dtype=np.complex128)
-        full[:, :, ky, :modes] = dvh
-        dv = dv_in + np.real(np.fft.fft2(full))
-    g["pb"] = dv.sum(axis=(0, 2, 3))
-    g["P"] = np.einsum("bixy,boxy->io", x, dv)
+        full = np.zeros(x.shape[:1] + (width,) + grid, dtype=np.complex128)
+        full[sel] = dvh
+        dv = dv_in + np.real(np.fft.fftn(full, axes=axes))
+    g["pb"] = dv.sum(axis=sum_axes)
+    g["P"] = np.einsum("bip,bop->io", flat(x), flat(dv))
     # pack, R gradient as (re, im) of the conjugate convention: for a real
     # loss, dL/dRe = Re(dR), dL/dIm = -Im(dR) with dL = Re(sum dR * dR_param)
     parts = [g["P"].ravel(), g["pb"]]
@@ -165,4 +190,3 @@ def backward(theta, x, t, width, modes, layers):
         parts.append(g["b"][l])
     parts += [g["Q"], g["qb"]]
     return np.concatenate(parts), float(np.mean((y - t) ** 2))
-
