@@ -402,7 +402,7 @@ def learned_comparison(epochs, eval_steps, deploy_steps):
     log("[bench] learned guess: FCH 256^2 plain vs learned")
     res[base.name] = _learned_vs_plain(base, tr.fno, lambda un, unm1: tr.norm, eval_steps)
     pfc = WORKLOADS["pfc1024"]
-    f = learned.deploy(tr, *pfc.shape, cfg)
+    f = learned.deploy(tr, *pfc.shape, cfg=cfg)
     ratio = tr.norm[3] / tr.norm[2]
 
     def pfc_norm(un, unm1):

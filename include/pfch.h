@@ -68,7 +68,7 @@ enum { PFCH_BDF2 = 0, PFCH_MP = 1, PFCH_LBDF2 = 2, PFCH_LMP = 3 };  /* time sche
  * input x_0, extrapolation as in Sec. 3.1); 1 = learned guess when a network
  * is attached with pfch_set_fno (otherwise extrapolated).  reserved must be 0.
  * Grids: ndim = 2 with Nx, Ny powers of two in [8, 2048] or 192; ndim = 3
- * (PFC only, extrapolated guess) with Nx as in 2D and Ny, Nz in
+ * (PFC only) with Nx as in 2D and Ny, Nz in
  * {8, 16, 32, 64, 128, 192, 256}.  Other valid descriptors give
  * PFCH_E_UNSUPPORTED.
  */
@@ -240,24 +240,40 @@ int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]);
  *
  * Network: lift 2 -> W channels, L spectral layers
  *   z = K v + W_l^T v + b_l,  v <- gelu(z) (no gelu after the last layer),
- * K keeping kx in [0, M) and ky in {0..M-1} U {Ny-M..Ny-1} of the 2D real
- * transform with complex per-mode channel mixing, then projection W -> 1.
+ * K keeping kx in [0, M) and, on y (and z in 3D), k in {0..M-1} U
+ * {N-M..N-1} of the real transform with complex per-mode channel mixing,
+ * then projection W -> 1.
  * Flat float32 parameter vector, in order: P[2][W], pb[W], per layer
- * R[W][W][2M][M][re, im] (row kyi >= M holds ky = Ny - 2M + kyi), Wl[W][W],
- * bl[W]; then Q[W], qb.  All fields are [B][C][Ny][Nx] float32, x fastest.
- * One network object is used by one stream at a time (its activations live
- * in the object).
+ * R[W][W][modes][re, im] with modes [2M][M] (2D: ky, kx) or [2M][2M][M]
+ * (3D: kz, ky, kx; index ki >= M on a full axis holds k = N - 2M + ki),
+ * Wl[W][W], bl[W]; then Q[W], qb.  All fields are [B][C][Ny][Nx] (2D) or
+ * [B][C][Nz][Ny][Nx] (3D) float32, x fastest.  One network object is used by
+ * one stream at a time (its activations live in the object).  The learned
+ * guess only changes PAGD's starting point; the paper's own guess is the
+ * extrapolation.
  */
 typedef struct pfch_fno pfch_fno; /* opaque; owned by the library */
 
-/* Number of parameters, or PFCH_E_INVAL for invalid sizes. */
+/* Number of parameters of a 2D / 3D network, or PFCH_E_INVAL for invalid
+ * sizes (W in [1, 64], M in [1, 64], L in [1, 16]). */
 int64_t pfch_fno_num_params(int32_t width, int32_t modes, int32_t layers);
+int64_t pfch_fno_num_params_3d(int32_t width, int32_t modes, int32_t layers);
 
 /* Create a network of width W <= 64, M modes (2M <= Ny, M <= Nx/2), L
  * layers, for Ny x Nx fields and batches of at most max_batch samples.
- * Parameters start at zero (see pfch_fno_init_params). */
+ * Parameters start at zero (see pfch_fno_init_params).  The network lives
+ * on `hip_stream` (NULL: the default stream).  PFCH_E_INVAL for invalid
+ * sizes, PFCH_E_UNSUPPORTED when a product would exceed the launch limits
+ * (B W Ny > 2^21, B W > 65535, 2M^2 > 65535), PFCH_E_NOMEM / PFCH_E_HIP on
+ * allocation or copy failure; *out is NULL on error. */
 int pfch_fno_create(int32_t width, int32_t modes, int32_t layers, int32_t ny, int32_t nx,
                     int32_t max_batch, void* hip_stream, pfch_fno** out);
+
+/* The same for Nz x Ny x Nx fields (2M <= Nz as well; limits B W Nz Ny
+ * <= 2^21, B W Nz <= 65535, 4M^3 <= 65535).  Every other pfch_fno_* call
+ * takes either kind; a 3D network attaches to 3D instances only. */
+int pfch_fno_create_3d(int32_t width, int32_t modes, int32_t layers, int32_t nz, int32_t ny,
+                       int32_t nx, int32_t max_batch, void* hip_stream, pfch_fno** out);
 
 /* Deterministic pseudo-random initial parameters (scaled uniform). */
 int pfch_fno_init_params(pfch_fno* f, uint64_t seed);
@@ -266,10 +282,10 @@ int pfch_fno_init_params(pfch_fno* f, uint64_t seed);
 int pfch_fno_set_params(pfch_fno* f, const float* theta, int64_t n);
 int pfch_fno_get_params(pfch_fno* f, float* theta, int64_t n);
 
-/* y[batch][Ny][Nx] = network(x[batch][2][Ny][Nx]); device arrays. */
+/* y[batch][grid] = network(x[batch][2][grid]); device arrays. */
 int pfch_fno_forward(pfch_fno* f, const float* x, float* y, int32_t batch);
 
-/* Mean squared error of the network on (x, t[batch][Ny][Nx]) and its
+/* Mean squared error of the network on (x, t[batch][grid]) and its
  * gradient with respect to the parameters, kept for pfch_fno_adam_step and
  * copied to `grad` (device, n floats) when it is not NULL.  `loss` (host) is
  * written when not NULL, which synchronises the stream. */
@@ -280,7 +296,7 @@ int pfch_fno_grad(pfch_fno* f, const float* x, const float* t, int32_t batch, fl
  * cleared at step 1). */
 int pfch_fno_adam_step(pfch_fno* f, float lr, float beta1, float beta2, float eps, int32_t step);
 
-/* Network input x[2][Ny][Nx] (and, when u_np1 and t are not NULL, the
+/* Network input x[2][grid] (and, when u_np1 and t are not NULL, the
  * training target t = (u^{n+1} - u^n - rho (u^n - u^{n-1}))/so) of one
  * sample from float64 device fields. */
 int pfch_fno_prepare(pfch_fno* f, const double* u_nm1, const double* u_n, const double* u_np1,

@@ -2,18 +2,20 @@
 // forward, backward (mean squared error) and Adam, written as HIP kernels.
 //
 // Network (width W, retained modes M per axis, L spectral layers) on fields
-// [B][C][Ny][Nx]:
+// [B][C][Ny][Nx] (2D) or [B][C][Nz][Ny][Nx] (3D):
 //   v0 = P^T x + pb                          (lift, 2 -> W channels)
 //   z_l = K_l v_l + W_l^T v_l + b_l,  v_{l+1} = gelu(z_l)  (last layer: no gelu)
 //   y = Q^T v_L + qb                         (projection, W -> 1)
-// K_l keeps kx in [0, M) and ky in {0..M-1} U {Ny-M..Ny-1} of the real 2D
-// transform and mixes channels per mode with complex weights R_l[i][o][mode].
-// The truncated transforms are dense products with DFT matrices (M << N), so
-// every step of the layer and of its adjoint is one strided batched complex
-// GEMM (k_gemm).
+// K_l keeps kx in [0, M) and, on y (and z), k in {0..M-1} U {N-M..N-1} of
+// the real transform and mixes channels per mode with complex weights
+// R_l[i][o][mode].  The truncated transforms are dense products with DFT
+// matrices (M << N), so every step of the layer and of its adjoint is one
+// strided batched complex GEMM (k_gemm): x, then y per (b, c, z), then z per
+// (b, c), and back in reverse order.
 //
 // Flat parameter layout (shared with the float64 reference of the tests):
-// P[2][W], pb[W], per layer R[W][W][2M][M][re,im], Wl[W][W], bl[W]; Q[W], qb.
+// P[2][W], pb[W], per layer R[W][W][modes][re,im] with modes [2M][M] (2D)
+// or [2M][2M][M] (3D, kz, ky, kx), Wl[W][W], bl[W]; Q[W], qb.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -360,13 +362,18 @@ __global__ void k_fno_inputs(const double* __restrict__ unm1, const double* __re
 }
 
 struct Fno {
-  int W = 0, M = 0, L = 0, ny = 0, nx = 0, maxb = 0;
-  long long P = 0, n = 0, MM2 = 0;
+  int W = 0, M = 0, L = 0, nz = 1, ny = 0, nx = 0, maxb = 0, ndim = 2;
+  long long P = 0, n = 0, MM = 0;  // P grid points, MM retained modes (2M^2 or 4M^3)
   hipStream_t s = nullptr;
   float *theta = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
-  float *Fx = nullptr, *Fy = nullptr, *Gy = nullptr, *Gx = nullptr;  // complex DFT matrices
+  // complex DFT matrices: Fx [Nx][M], Fy [2M][Ny], Fz [2M][Nz] forward;
+  // Gz [Nz][2M], Gy [Ny][2M], Gx [M][Nx] inverse (Gx carries 1/P and the
+  // weight 2 of the kx > 0 half-spectrum columns)
+  float *Fx = nullptr, *Fy = nullptr, *Fz = nullptr, *Gz = nullptr, *Gy = nullptr, *Gx = nullptr;
   std::vector<float*> v, z, vh;  // v[0..L], z[0..L-1], vh[0..L-1]
-  float *S1 = nullptr, *Yb = nullptr, *Yb2 = nullptr;
+  // S1 [B][W][Nz][Ny][M] after the x transform, S2 [B][W][Nz][2M][M] after
+  // the y transform (3D only), Yb / Yb2 [B][W][modes]
+  float *S1 = nullptr, *S2 = nullptr, *Yb = nullptr, *Yb2 = nullptr;
   float *xin = nullptr, *y = nullptr, *dy = nullptr, *dvA = nullptr, *dvB = nullptr;
   float *wpart = nullptr, *lpart = nullptr;
   double *loss = nullptr, *h_loss = nullptr, *ypart = nullptr;
@@ -377,8 +384,10 @@ struct Fno {
   std::vector<long long> oR, oW, ob;
 };
 
-inline long long fno_count(long long W, long long M, long long L) {
-  return 2 * W + W + L * (W * W * 2 * M * M * 2 + W * W + W) + W + 1;
+inline long long fno_modes(long long M, int ndim) { return ndim == 3 ? 4 * M * M * M : 2 * M * M; }
+
+inline long long fno_count(long long W, long long M, long long L, int ndim = 2) {
+  return 2 * W + W + L * (W * W * fno_modes(M, ndim) * 2 + W * W + W) + W + 1;
 }
 
 constexpr int FNO_LOSS_BLOCKS = 256, FNO_SUM_BLOCKS = 256;
@@ -423,10 +432,12 @@ inline GemmP gp_make(long long M, long long N, long long K, const float* A, long
 
 inline unsigned blocks_for(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-// Forward pass for `B` samples x[B][2][ny][nx]; keeps every layer's input,
-// pre-activation and retained spectrum for the backward pass; y[B][ny][nx].
+// Forward pass for `B` samples x[B][2][grid]; keeps every layer's input,
+// pre-activation and retained spectrum for the backward pass; y[B][grid].
 inline hipError_t fno_forward(Fno& F, const float* x, int B, hipStream_t s) {
-  const long long W = F.W, M = F.M, P = F.P, ny = F.ny, nx = F.nx, MM2 = F.MM2;
+  const long long W = F.W, M = F.M, P = F.P, nz = F.nz, ny = F.ny, nx = F.nx, MM = F.MM;
+  const long long M2 = 2 * M * M;  // modes of one (b, c, z) after the y transform
+  const bool d3 = F.ndim == 3;
   const float* th = F.theta;
   // lift
   FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(
@@ -435,22 +446,31 @@ inline hipError_t fno_forward(Fno& F, const float* x, int B, hipStream_t s) {
                      th + F.opb, (int)W, P, B * W * P, 0);
   for (int l = 0; l < F.L; ++l) {
     const float* vin = F.v[l];
-    // A1 = v Fx over x
+    float* yk = d3 ? F.S2 : F.vh[l];  // y-transform output
+    // S1 = v Fx over x
     FNO_CHK((gemm_launch<false, true, false, false, true, 64, 16>(
-        gp_make(B * W * ny, M, nx, vin, 0, nx, 1, F.Fx, 0, M, 1, F.S1, 0, M, 1, 0), 1, s)));
-    // vh = Fy A1 over y (retained ky rows)
+        gp_make(B * W * nz * ny, M, nx, vin, 0, nx, 1, F.Fx, 0, M, 1, F.S1, 0, M, 1, 0), 1, s)));
+    // Fy S1 over y (retained ky rows), per (b, c, z)
     FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
-        gp_make(2 * M, M, ny, F.Fy, 0, ny, 1, F.S1, ny * M, M, 1, F.vh[l], MM2, M, 1, 0), B * W, s)));
+        gp_make(2 * M, M, ny, F.Fy, 0, ny, 1, F.S1, ny * M, M, 1, yk, M2, M, 1, 0), B * W * nz, s)));
+    // 3D: vh = Fz S2 over z (retained kz rows), per (b, c)
+    if (d3)
+      FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
+          gp_make(2 * M, M2, nz, F.Fz, 0, nz, 1, F.S2, nz * M2, M2, 1, F.vh[l], MM, M2, 1, 0), B * W, s)));
     // per-mode channel mixing Y[b][o] = sum_i vh[b][i] R[i][o]
     FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
-        gp_make(B, W, W, F.vh[l], 1, W * MM2, MM2, th + F.oR[l], 1, W * MM2, MM2, F.Yb, 1, W * MM2, MM2, 0),
-        MM2, s)));
-    // B1 = Gy Y over y
+        gp_make(B, W, W, F.vh[l], 1, W * MM, MM, th + F.oR[l], 1, W * MM, MM, F.Yb, 1, W * MM, MM, 0), MM, s)));
+    // 3D: S2 = Gz Y over z
+    if (d3)
+      FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
+          gp_make(nz, M2, 2 * M, F.Gz, 0, 2 * M, 1, F.Yb, MM, M2, 1, F.S2, nz * M2, M2, 1, 0), B * W, s)));
+    // S1 = Gy (Y or S2) over y
     FNO_CHK((gemm_launch<true, true, false, false, true, 64, 16>(
-        gp_make(ny, M, 2 * M, F.Gy, 0, 2 * M, 1, F.Yb, MM2, M, 1, F.S1, ny * M, M, 1, 0), B * W, s)));
-    // z = Re(B1 Gx) over x
+        gp_make(ny, M, 2 * M, F.Gy, 0, 2 * M, 1, d3 ? F.S2 : F.Yb, M2, M, 1, F.S1, ny * M, M, 1, 0), B * W * nz,
+        s)));
+    // z = Re(S1 Gx) over x
     FNO_CHK((gemm_launch<true, true, false, false, false, 32, 64>(
-        gp_make(B * W * ny, nx, M, F.S1, 0, M, 1, F.Gx, 0, nx, 1, F.z[l], 0, nx, 1, 0), 1, s)));
+        gp_make(B * W * nz * ny, nx, M, F.S1, 0, M, 1, F.Gx, 0, nx, 1, F.z[l], 0, nx, 1, 0), 1, s)));
     // z += W_l^T v
     FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(
         gp_make(W, P, W, th + F.oW[l], 0, 1, W, vin, W * P, P, 1, F.z[l], W * P, P, 1, 1), B, s)));
@@ -471,12 +491,15 @@ inline hipError_t wgrad(Fno& F, const float* X, int CX, const float* Y, int CY, 
   return hipGetLastError();
 }
 
-// Forward, mean squared error against t[B][ny][nx] and the gradient of the
+// Forward, mean squared error against t[B][grid] and the gradient of the
 // loss with respect to every parameter (into F.grad).  F.loss receives the
-// loss (device float64).
+// loss (device float64).  The complex adjoints carry the conjugate of the
+// gradient, so every transform's adjoint is its plain transpose.
 inline hipError_t fno_backward(Fno& F, const float* x, const float* t, int B, hipStream_t s) {
   FNO_CHK(fno_forward(F, x, B, s));
-  const long long W = F.W, M = F.M, P = F.P, ny = F.ny, nx = F.nx, MM2 = F.MM2;
+  const long long W = F.W, M = F.M, P = F.P, nz = F.nz, ny = F.ny, nx = F.nx, MM = F.MM;
+  const long long M2 = 2 * M * M;
+  const bool d3 = F.ndim == 3;
   const long long nB = (long long)B * P;
   const float* th = F.theta;
   float* g = F.grad;
@@ -494,30 +517,38 @@ inline hipError_t fno_backward(Fno& F, const float* x, const float* t, int B, hi
                          (const float*)F.z[l], dv, B * W * P);
     const float* dz = dv;
     const float* vin = F.v[l];
+    float* yk = d3 ? F.S2 : F.Yb;  // adjoint of the y transform, per (b, c, z)
     FNO_CHK(wgrad(F, vin, (int)W, dz, (int)W, nB, g + F.oW[l], g + F.ob[l], s));
     // dvin = W_l dz
     FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(
         gp_make(W, P, W, th + F.oW[l], 0, W, 1, dz, W * P, P, 1, dvin, W * P, P, 1, 0), B, s)));
-    // D_B1 = dz Gx^T
+    // D_S1 = dz Gx^T
     FNO_CHK((gemm_launch<false, true, false, false, true, 64, 16>(
-        gp_make(B * W * ny, M, nx, dz, 0, nx, 1, F.Gx, 0, 1, nx, F.S1, 0, M, 1, 0), 1, s)));
-    // D_Y = Gy^T D_B1
+        gp_make(B * W * nz * ny, M, nx, dz, 0, nx, 1, F.Gx, 0, 1, nx, F.S1, 0, M, 1, 0), 1, s)));
+    // Gy^T D_S1
     FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
-        gp_make(2 * M, M, ny, F.Gy, 0, 1, 2 * M, F.S1, ny * M, M, 1, F.Yb, MM2, M, 1, 0), B * W, s)));
+        gp_make(2 * M, M, ny, F.Gy, 0, 1, 2 * M, F.S1, ny * M, M, 1, yk, M2, M, 1, 0), B * W * nz, s)));
+    // 3D: D_Y = Gz^T D_S2
+    if (d3)
+      FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
+          gp_make(2 * M, M2, nz, F.Gz, 0, 1, 2 * M, F.S2, nz * M2, M2, 1, F.Yb, MM, M2, 1, 0), B * W, s)));
     // grad R = conj(sum_b vh[b][i] D_Y[b][o]) per mode, stored (re, im)
     FNO_CHK((gemm_launch<true, true, true, true, true, 32, 32>(
-        gp_make(W, W, B, F.vh[l], 1, MM2, W * MM2, F.Yb, 1, W * MM2, MM2, g + F.oR[l], 1, W * MM2, MM2, 0),
-        MM2, s)));
+        gp_make(W, W, B, F.vh[l], 1, MM, W * MM, F.Yb, 1, W * MM, MM, g + F.oR[l], 1, W * MM, MM, 0), MM, s)));
     // D_vh[b][i] = sum_o D_Y[b][o] R[i][o]
     FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
-        gp_make(B, W, W, F.Yb, 1, W * MM2, MM2, th + F.oR[l], 1, MM2, W * MM2, F.Yb2, 1, W * MM2, MM2, 0),
-        MM2, s)));
-    // D_A1 = Fy^T D_vh
+        gp_make(B, W, W, F.Yb, 1, W * MM, MM, th + F.oR[l], 1, MM, W * MM, F.Yb2, 1, W * MM, MM, 0), MM, s)));
+    // 3D: D_S2 = Fz^T D_vh
+    if (d3)
+      FNO_CHK((gemm_launch<true, true, false, false, true, 32, 32>(
+          gp_make(nz, M2, 2 * M, F.Fz, 0, 1, nz, F.Yb2, MM, M2, 1, F.S2, nz * M2, M2, 1, 0), B * W, s)));
+    // D_S1 = Fy^T (D_vh or D_S2)
     FNO_CHK((gemm_launch<true, true, false, false, true, 64, 16>(
-        gp_make(ny, M, 2 * M, F.Fy, 0, 1, ny, F.Yb2, MM2, M, 1, F.S1, ny * M, M, 1, 0), B * W, s)));
-    // dvin += Re(D_A1 Fx^T)
+        gp_make(ny, M, 2 * M, F.Fy, 0, 1, ny, d3 ? F.S2 : F.Yb2, M2, M, 1, F.S1, ny * M, M, 1, 0), B * W * nz,
+        s)));
+    // dvin += Re(D_S1 Fx^T)
     FNO_CHK((gemm_launch<true, true, false, false, false, 32, 64>(
-        gp_make(B * W * ny, nx, M, F.S1, 0, M, 1, F.Fx, 0, 1, M, dvin, 0, nx, 1, 1), 1, s)));
+        gp_make(B * W * nz * ny, nx, M, F.S1, 0, M, 1, F.Fx, 0, 1, M, dvin, 0, nx, 1, 1), 1, s)));
     float* tmp = dv;
     dv = dvin;
     dvin = tmp;

@@ -1161,8 +1161,8 @@ int pfch_validate_desc(const pfch_instance_desc* d) {
   if (d->guess != 0 && d->guess != 1) return PFCH_E_INVAL;
   if (scheme_imex(d->scheme) && d->guess != 0) return PFCH_E_INVAL;  // no solve to warm-start
   if (d->ndim == 3) {
-    // 3D: PFC, x length as in 2D, y and z lengths of the 3D passes, rows even
-    if (d->model != PFCH_PFC || d->guess != 0) return PFCH_E_UNSUPPORTED;
+    // 3D: PFC, x length as in 2D, y and z lengths of the 3D passes
+    if (d->model != PFCH_PFC) return PFCH_E_UNSUPPORTED;
     if (!supported_len(d->n[0]) || !supported_len3(d->n[1]) || !supported_len3(d->n[2]))
       return PFCH_E_UNSUPPORTED;
     return PFCH_OK;
@@ -2150,7 +2150,12 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
 
 int64_t pfch_fno_num_params(int32_t width, int32_t modes, int32_t layers) {
   if (width < 1 || width > WG_MAXC || modes < 1 || modes > 64 || layers < 1 || layers > 16) return PFCH_E_INVAL;
-  return fno_count(width, modes, layers);
+  return fno_count(width, modes, layers, 2);
+}
+
+int64_t pfch_fno_num_params_3d(int32_t width, int32_t modes, int32_t layers) {
+  if (width < 1 || width > WG_MAXC || modes < 1 || modes > 64 || layers < 1 || layers > 16) return PFCH_E_INVAL;
+  return fno_count(width, modes, layers, 3);
 }
 
 void pfch_fno_destroy(pfch_fno* f) {
@@ -2161,26 +2166,35 @@ void pfch_fno_destroy(pfch_fno* f) {
   delete f;
 }
 
-int pfch_fno_create(int32_t width, int32_t modes, int32_t layers, int32_t ny, int32_t nx, int32_t max_batch,
-                    void* hip_stream, pfch_fno** out) {
+}  // extern "C"
+
+namespace {
+
+// Network on an Nz x Ny x Nx grid (ndim 3) or an Ny x Nx grid (ndim 2, nz 1).
+int fno_create(int ndim, int32_t width, int32_t modes, int32_t layers, int32_t nz, int32_t ny, int32_t nx,
+               int32_t max_batch, void* hip_stream, pfch_fno** out) {
   if (!out) return PFCH_E_INVAL;
   *out = nullptr;
   if (pfch_fno_num_params(width, modes, layers) < 0) return PFCH_E_INVAL;
-  if (ny < 2 || nx < 2 || 2 * modes > ny || 2 * modes > nx || max_batch < 1) return PFCH_E_INVAL;
-  const long long W = width, M = modes, P = (long long)ny * nx, B = max_batch;
+  if (ny < 2 || nx < 2 || nz < 1 || 2 * modes > ny || 2 * modes > nx || max_batch < 1) return PFCH_E_INVAL;
+  if (ndim == 3 ? (nz < 2 || 2 * modes > nz) : nz != 1) return PFCH_E_INVAL;
+  const long long W = width, M = modes, P = (long long)nz * ny * nx, B = max_batch;
+  const long long MM = fno_modes(M, ndim), M2 = 2 * M * M;
   // launch limits of the strided products (grid y and z extents)
-  if ((B * W * ny + 31) / 32 > 65535 || B * W > 65535 || 2 * M * M > 65535) return PFCH_E_UNSUPPORTED;
+  if ((B * W * nz * ny + 31) / 32 > 65535 || B * W * nz > 65535 || MM > 65535) return PFCH_E_UNSUPPORTED;
   pfch_fno* h = new pfch_fno();
   Fno& F = h->f;
   F.W = width;
   F.M = modes;
   F.L = layers;
+  F.ndim = ndim;
+  F.nz = nz;
   F.ny = ny;
   F.nx = nx;
   F.maxb = max_batch;
   F.P = P;
-  F.MM2 = 2 * M * M;
-  F.n = fno_count(W, M, layers);
+  F.MM = MM;
+  F.n = fno_count(W, M, layers, ndim);
   F.s = (hipStream_t)hip_stream;
   long long o = 0;
   F.oP = o;
@@ -2189,7 +2203,7 @@ int pfch_fno_create(int32_t width, int32_t modes, int32_t layers, int32_t ny, in
   o += W;
   for (int l = 0; l < layers; ++l) {
     F.oR.push_back(o);
-    o += W * W * F.MM2 * 2;
+    o += W * W * MM * 2;
     F.oW.push_back(o);
     o += W * W;
     F.ob.push_back(o);
@@ -2216,15 +2230,18 @@ int pfch_fno_create(int32_t width, int32_t modes, int32_t layers, int32_t ny, in
   if ((rc = fal(&F.Fx, 2 * nx * M)) || (rc = fal(&F.Fy, 2 * 2 * M * ny)) || (rc = fal(&F.Gy, 2 * ny * 2 * M)) ||
       (rc = fal(&F.Gx, 2 * M * nx)))
     return fail(rc);
+  if (ndim == 3 && ((rc = fal(&F.Fz, 2 * 2 * M * nz)) || (rc = fal(&F.Gz, 2 * nz * 2 * M)) ||
+                    (rc = fal(&F.S2, 2 * B * W * nz * M2))))
+    return fail(rc);
   F.v.assign(layers + 1, nullptr);
   F.z.assign(layers, nullptr);
   F.vh.assign(layers, nullptr);
   for (int l = 0; l <= layers; ++l)
     if ((rc = fal(&F.v[l], field))) return fail(rc);
   for (int l = 0; l < layers; ++l)
-    if ((rc = fal(&F.z[l], field)) || (rc = fal(&F.vh[l], 2 * B * W * F.MM2))) return fail(rc);
-  if ((rc = fal(&F.S1, 2 * B * W * ny * M)) || (rc = fal(&F.Yb, 2 * B * W * F.MM2)) ||
-      (rc = fal(&F.Yb2, 2 * B * W * F.MM2)))
+    if ((rc = fal(&F.z[l], field)) || (rc = fal(&F.vh[l], 2 * B * W * MM))) return fail(rc);
+  if ((rc = fal(&F.S1, 2 * B * W * nz * ny * M)) || (rc = fal(&F.Yb, 2 * B * W * MM)) ||
+      (rc = fal(&F.Yb2, 2 * B * W * MM)))
     return fail(rc);
   if ((rc = fal(&F.xin, B * 2 * P)) || (rc = fal(&F.y, B * P)) || (rc = fal(&F.dy, B * P)) ||
       (rc = fal(&F.dvA, field)) || (rc = fal(&F.dvB, field)))
@@ -2243,29 +2260,41 @@ int pfch_fno_create(int32_t width, int32_t modes, int32_t layers, int32_t ny, in
   // DFT matrices, angles reduced exactly in integers before the float64 sin/cos
   {
     const double tp = 2.0 * M_PI;
-    std::vector<float> fx(2 * nx * M), fy(2 * 2 * M * ny), gy(2 * ny * 2 * M), gx(2 * M * nx);
-    auto kyv = [&](long long kyi) { return kyi < M ? kyi : ny - 2 * M + kyi; };
+    std::vector<float> fx(2 * nx * M), gx(2 * M * nx);
     for (long long x = 0; x < nx; ++x)
       for (long long kx = 0; kx < M; ++kx) {
         const double ang = tp * (double)((kx * x) % nx) / nx;
         fx[2 * (x * M + kx)] = (float)std::cos(ang);
         fx[2 * (x * M + kx) + 1] = (float)-std::sin(ang);
-        const double c = (kx == 0 || 2 * kx == nx ? 1.0 : 2.0) / ((double)nx * ny);
+        const double c = (kx == 0 || 2 * kx == nx ? 1.0 : 2.0) / (double)P;
         gx[2 * (kx * nx + x)] = (float)(c * std::cos(ang));
         gx[2 * (kx * nx + x) + 1] = (float)(c * std::sin(ang));
       }
-    for (long long kyi = 0; kyi < 2 * M; ++kyi)
-      for (long long y = 0; y < ny; ++y) {
-        const double ang = tp * (double)((kyv(kyi) * y) % ny) / ny;
-        fy[2 * (kyi * ny + y)] = (float)std::cos(ang);
-        fy[2 * (kyi * ny + y) + 1] = (float)-std::sin(ang);
-        gy[2 * (y * 2 * M + kyi)] = (float)std::cos(ang);
-        gy[2 * (y * 2 * M + kyi) + 1] = (float)std::sin(ang);
+    // full axis of length n: forward [2M][n], inverse [n][2M]; row ki >= M
+    // holds k = n - 2M + ki
+    auto full_axis = [&](long long n, std::vector<float>& fw, std::vector<float>& iv) {
+      fw.assign(2 * 2 * M * n, 0.f);
+      iv.assign(2 * n * 2 * M, 0.f);
+      for (long long ki = 0; ki < 2 * M; ++ki) {
+        const long long k = ki < M ? ki : n - 2 * M + ki;
+        for (long long y = 0; y < n; ++y) {
+          const double ang = tp * (double)((k * y) % n) / n;
+          fw[2 * (ki * n + y)] = (float)std::cos(ang);
+          fw[2 * (ki * n + y) + 1] = (float)-std::sin(ang);
+          iv[2 * (y * 2 * M + ki)] = (float)std::cos(ang);
+          iv[2 * (y * 2 * M + ki) + 1] = (float)std::sin(ang);
+        }
       }
+    };
+    std::vector<float> fy, gy, fz, gz;
+    full_axis(ny, fy, gy);
+    if (ndim == 3) full_axis(nz, fz, gz);
     if (hipMemcpy(F.Fx, fx.data(), fx.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(F.Fy, fy.data(), fy.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(F.Gy, gy.data(), gy.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(F.Gx, gx.data(), gx.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        (ndim == 3 && (hipMemcpy(F.Fz, fz.data(), fz.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                       hipMemcpy(F.Gz, gz.data(), gz.size() * 4, hipMemcpyHostToDevice) != hipSuccess)) ||
         hipMemset(F.theta, 0, sizeof(float) * F.n) != hipSuccess ||
         hipMemset(F.am, 0, sizeof(float) * F.n) != hipSuccess ||
         hipMemset(F.av, 0, sizeof(float) * F.n) != hipSuccess)
@@ -2273,6 +2302,20 @@ int pfch_fno_create(int32_t width, int32_t modes, int32_t layers, int32_t ny, in
   }
   *out = h;
   return PFCH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pfch_fno_create(int32_t width, int32_t modes, int32_t layers, int32_t ny, int32_t nx, int32_t max_batch,
+                    void* hip_stream, pfch_fno** out) {
+  return fno_create(2, width, modes, layers, 1, ny, nx, max_batch, hip_stream, out);
+}
+
+int pfch_fno_create_3d(int32_t width, int32_t modes, int32_t layers, int32_t nz, int32_t ny, int32_t nx,
+                       int32_t max_batch, void* hip_stream, pfch_fno** out) {
+  return fno_create(3, width, modes, layers, nz, ny, nx, max_batch, hip_stream, out);
 }
 
 int pfch_fno_init_params(pfch_fno* f, uint64_t seed) {
@@ -2291,7 +2334,7 @@ int pfch_fno_init_params(pfch_fno* f, uint64_t seed) {
   const double W = F.W;
   for (long long k = 0; k < 2 * F.W; ++k) th[F.oP + k] = (float)(uni() / std::sqrt(2.0));
   for (int l = 0; l < F.L; ++l) {
-    for (long long k = 0; k < (long long)F.W * F.W * F.MM2 * 2; ++k)
+    for (long long k = 0; k < (long long)F.W * F.W * F.MM * 2; ++k)
       th[F.oR[l] + k] = (float)((uni() + 1.0) / (2.0 * W * W));
     for (long long k = 0; k < (long long)F.W * F.W; ++k) th[F.oW[l] + k] = (float)(uni() / std::sqrt(W));
   }
@@ -2372,7 +2415,7 @@ int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4])
   }
   if (!norm || !(norm[1] > 0.0) || !(norm[2] > 0.0) || !(norm[3] > 0.0) || !std::isfinite(norm[0]))
     return PFCH_E_INVAL;
-  if (f->f.ny != I.ny || f->f.nx != I.nx || I.nz != 1) return PFCH_E_INVAL;
+  if (f->f.nz != I.nz || f->f.ny != I.ny || f->f.nx != I.nx) return PFCH_E_INVAL;
   int rc;
   if (!I.xguess) {
     void* q = nullptr;

@@ -44,10 +44,10 @@ def desc_of(w, guess=0):
 
 def trajectories(ws, u0s, steps):
     """Advance the instances `ws` (one batched context) `steps` plain steps
-    from u0s; returns a float64 GPU tensor [len(ws)][steps + 1][Ny][Nx]."""
+    from u0s; returns a float64 GPU tensor [len(ws)][steps + 1][*grid]."""
     import torch
-    ny, nx = ws[0].shape
-    out = torch.empty((len(ws), steps + 1, ny, nx), dtype=torch.float64, device="cuda")
+    shape = tuple(ws[0].shape)
+    out = torch.empty((len(ws), steps + 1) + shape, dtype=torch.float64, device="cuda")
     ctx = pfch.Context([desc_of(w) for w in ws])
     ctx.set_stats_detail(0)
     for i, u in enumerate(u0s):
@@ -76,13 +76,14 @@ def normalisation(states):
 
 
 def dataset(fno, states, norm, rho=1.0):
-    """Network inputs X [N][2][Ny][Nx] and targets T [N][Ny][Nx] (float32,
+    """Network inputs X [N][2][*grid] and targets T [N][*grid] (float32,
     GPU) for every triple (u^{n-1}, u^n, u^{n+1}) of the trajectories."""
     import torch
-    ni, nt, ny, nx = states.shape
+    ni, nt = states.shape[:2]
+    grid = tuple(states.shape[2:])
     n = ni * (nt - 2)
-    X = torch.empty((n, 2, ny, nx), dtype=torch.float32, device="cuda")
-    T = torch.empty((n, ny, nx), dtype=torch.float32, device="cuda")
+    X = torch.empty((n, 2) + grid, dtype=torch.float32, device="cuda")
+    T = torch.empty((n,) + grid, dtype=torch.float32, device="cuda")
     k = 0
     for i in range(ni):
         for j in range(1, nt - 1):
@@ -95,10 +96,9 @@ def train(ws, u0s, steps, cfg=TrainConfig(), log=None):
     """Generate trajectories of the instances `ws` with the solver, then
     train an FNO on their triples; returns a Trained record."""
     import torch
-    ny, nx = ws[0].shape
     states = trajectories(ws, u0s, steps)
     norm = normalisation(states)
-    fno = pfch.Fno(cfg.width, cfg.modes, cfg.layers, ny, nx, max_batch=cfg.batch)
+    fno = pfch.Fno(cfg.width, cfg.modes, cfg.layers, *ws[0].shape, max_batch=cfg.batch)
     fno.init_params(cfg.seed)
     X, T = dataset(fno, states, norm)
     del states
@@ -138,9 +138,9 @@ def train(ws, u0s, steps, cfg=TrainConfig(), log=None):
                    n_train=len(tr_idx), n_val=n_val)
 
 
-def deploy(trained, ny, nx, cfg=TrainConfig()):
-    """A copy of the trained network for another grid (the weights act on
-    mode indices and channels, so they transfer unchanged)."""
-    f = pfch.Fno(cfg.width, cfg.modes, cfg.layers, ny, nx, max_batch=1)
+def deploy(trained, *shape, cfg=TrainConfig()):
+    """A copy of the trained network for another grid of the same rank (the
+    weights act on mode indices and channels, so they transfer unchanged)."""
+    f = pfch.Fno(cfg.width, cfg.modes, cfg.layers, *shape, max_batch=1)
     f.set_params(trained.fno.get_params())
     return f

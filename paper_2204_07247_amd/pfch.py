@@ -35,7 +35,7 @@ EXPORTED = (
     "pfch_fno_num_params", "pfch_fno_create", "pfch_fno_init_params", "pfch_fno_set_params",
     "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad", "pfch_fno_adam_step",
     "pfch_fno_prepare", "pfch_fno_destroy", "pfch_set_fno", "pfch_get_plan", "pfch_set_plan",
-    "pfch_step_adaptive", "pfch_rhs",
+    "pfch_step_adaptive", "pfch_rhs", "pfch_fno_num_params_3d", "pfch_fno_create_3d",
 )
 
 
@@ -129,6 +129,9 @@ def lib():
         L.pfch_fno_num_params.argtypes = [i32, i32, i32]
         L.pfch_fno_num_params.restype = ctypes.c_int64
         L.pfch_fno_create.argtypes = [i32, i32, i32, i32, i32, i32, vp, ctypes.POINTER(vp)]
+        L.pfch_fno_num_params_3d.argtypes = [i32, i32, i32]
+        L.pfch_fno_num_params_3d.restype = ctypes.c_int64
+        L.pfch_fno_create_3d.argtypes = [i32, i32, i32, i32, i32, i32, i32, vp, ctypes.POINTER(vp)]
         L.pfch_fno_init_params.argtypes = [fp, ctypes.c_uint64]
         L.pfch_fno_set_params.argtypes = [fp, vp, ctypes.c_int64]
         L.pfch_fno_get_params.argtypes = [fp, vp, ctypes.c_int64]
@@ -148,7 +151,7 @@ def lib():
         L.pfch_rhs.argtypes = [vp, i32, vp, vp]
         L.pfch_rhs.restype = ctypes.c_int
         L.pfch_set_plan.restype = ctypes.c_int
-        for name in ("pfch_fno_create", "pfch_fno_init_params", "pfch_fno_set_params",
+        for name in ("pfch_fno_create", "pfch_fno_create_3d", "pfch_fno_init_params", "pfch_fno_set_params",
                      "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad",
                      "pfch_fno_adam_step", "pfch_fno_prepare", "pfch_set_fno"):
             getattr(L, name).restype = ctypes.c_int
@@ -358,27 +361,33 @@ class Context:
         return rc, st.as_dict()
 
 
-def fno_num_params(width, modes, layers):
-    return int(lib().pfch_fno_num_params(width, modes, layers))
+def fno_num_params(width, modes, layers, ndim=2):
+    f = lib().pfch_fno_num_params_3d if ndim == 3 else lib().pfch_fno_num_params
+    return int(f(width, modes, layers))
 
 
 class Fno:
     """Float32 Fourier neural operator on the GPU (pfch_fno_* entry points).
-    Arrays are contiguous float32 GPU tensors: x [B, 2, Ny, Nx], y/t
-    [B, Ny, Nx], parameters [n]."""
+    `shape` is the grid, (Ny, Nx) or (Nz, Ny, Nx).  Arrays are contiguous
+    float32 GPU tensors: x [B, 2, *shape], y/t [B, *shape], parameters [n]."""
 
-    def __init__(self, width, modes, layers, ny, nx, max_batch=1, stream=None):
+    def __init__(self, width, modes, layers, *shape, max_batch=1, stream=None):
+        if len(shape) not in (2, 3):
+            raise ValueError("Fno grid must be (Ny, Nx) or (Nz, Ny, Nx)")
         L = lib()
         h = ctypes.c_void_p()
         s = _stream_handle() if stream is None else ctypes.c_void_p(stream)
-        rc = L.pfch_fno_create(width, modes, layers, ny, nx, max_batch, s, ctypes.byref(h))
+        if len(shape) == 3:
+            rc = L.pfch_fno_create_3d(width, modes, layers, *shape, max_batch, s, ctypes.byref(h))
+        else:
+            rc = L.pfch_fno_create(width, modes, layers, *shape, max_batch, s, ctypes.byref(h))
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_fno_create")
         self._h = h
         self.width, self.modes, self.layers = width, modes, layers
-        self.shape = (ny, nx)
+        self.shape = tuple(int(n) for n in shape)
         self.max_batch = max_batch
-        self.n_params = fno_num_params(width, modes, layers)
+        self.n_params = fno_num_params(width, modes, layers, len(shape))
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -426,7 +435,7 @@ class Fno:
                     "pfch_fno_adam_step")
 
     def prepare(self, u_nm1, u_n, u_np1, rho, norm, x, t=None):
-        """Fill x [2, Ny, Nx] (and t [Ny, Nx]) of one sample from float64 fields."""
+        """Fill x [2, *shape] (and t [*shape]) of one sample from float64 fields."""
         nrm = (ctypes.c_double * 4)(*norm)
         self._check(lib().pfch_fno_prepare(self._h, _ptr(u_nm1), _ptr(u_n), _ptr(u_np1), float(rho),
                                            nrm, _fptr(x), _fptr(t)), "pfch_fno_prepare")

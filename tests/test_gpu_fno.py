@@ -1,10 +1,10 @@
 """Float32 FNO kernels against the float64 reference network, and the learned
 initial guess inside pfch_step.
 
-Forward and gradient are compared on tiny networks at float32-scaled
-tolerances; the learned guess must leave the converged step within the PAGD
-tolerance of the extrapolated-guess step, with the same mass, and fall back
-to the extrapolated guess when its own solve fails."""
+Forward and gradient are compared on tiny 2D and 3D networks at
+float32-scaled tolerances; the learned guess must leave the converged step
+within the PAGD tolerance of the extrapolated-guess step, with the same
+mass, and fall back to the extrapolated guess when its own solve fails."""
 import dataclasses
 
 import numpy as np
@@ -23,23 +23,36 @@ NETS = [  # (width, modes, layers, ny, nx, batch)
 ]
 
 
-def _inputs(w, m, l, ny, nx, b, seed):
+NETS3 = [  # (width, modes, layers, nz, ny, nx, batch)
+    (3, 2, 2, 6, 8, 10, 2),
+    (4, 2, 3, 4, 6, 8, 1),   # 2M == Nz: every kz kept
+    (2, 3, 2, 8, 6, 12, 2),  # 2M == Ny
+]
+
+
+def _split(net):
+    """(width, modes, layers, grid, batch) of a 2D or 3D net tuple."""
+    return net[0], net[1], net[2], tuple(net[3:-1]), net[-1]
+
+
+def _inputs(net, seed):
+    w, m, l, grid, b = _split(net)
     rng = np.random.default_rng(seed)
-    theta = ofno.init_params(w, m, l, seed=seed)
-    x = rng.normal(size=(b, 2, ny, nx))
-    t = rng.normal(size=(b, ny, nx)) * 0.5
+    theta = ofno.init_params(w, m, l, seed=seed, ndim=len(grid))
+    x = rng.normal(size=(b, 2) + grid)
+    t = rng.normal(size=(b,) + grid) * 0.5
     # round to float32 first so both sides see the same numbers
     return theta.astype(np.float32), x.astype(np.float32), t.astype(np.float32)
 
 
-def _groups(w, m, l):
+def _groups(w, m, l, ndim=2):
     """(name, slice) of each parameter block in the flat layout."""
     out, o = [], 0
     for name, n in [("P", 2 * w), ("pb", w)]:
         out.append((name, slice(o, o + n)))
         o += n
     for k in range(l):
-        for name, n in [(f"R{k}", w * w * 2 * m * m * 2), (f"W{k}", w * w), (f"b{k}", w)]:
+        for name, n in [(f"R{k}", w * w * ofno.n_modes(m, ndim) * 2), (f"W{k}", w * w), (f"b{k}", w)]:
             out.append((name, slice(o, o + n)))
             o += n
     for name, n in [("Q", w), ("qb", 1)]:
@@ -48,10 +61,12 @@ def _groups(w, m, l):
     return out
 
 
-def _net(w, m, l, ny, nx, b, theta):
+def _net(net, theta):
     import torch
     from paper_2204_07247_amd import pfch
-    f = pfch.Fno(w, m, l, ny, nx, max_batch=b)
+    w, m, l, grid, b = _split(net)
+    f = pfch.Fno(w, m, l, *grid, max_batch=b)
+    assert f.n_params == theta.size
     f.set_params(torch.from_numpy(theta).cuda())
     return f
 
@@ -60,35 +75,45 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
 
 
-@pytest.mark.parametrize("net", NETS, ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("net", NETS + NETS3, ids=lambda n: "x".join(map(str, n)))
 def test_forward_matches_reference(net):
     import torch
-    w, m, l, ny, nx, b = net
-    theta, x, _ = _inputs(*net, seed=11)
+    w, m, l, grid, b = _split(net)
+    theta, x, _ = _inputs(net, seed=11)
     print(f"fno forward {net}", flush=True)
-    f = _net(*net, theta)
+    f = _net(net, theta)
     y = f.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     ref, _ = ofno.forward(theta.astype(np.float64), x.astype(np.float64), w, m, l)
+    assert y.shape == ref.shape
     assert _rel(y, ref) <= 1e-5, _rel(y, ref)
     f.close()
 
 
-@pytest.mark.parametrize("net", NETS, ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("net", NETS + NETS3, ids=lambda n: "x".join(map(str, n)))
 def test_gradient_matches_reference(net):
     import torch
-    w, m, l, ny, nx, b = net
-    theta, x, t = _inputs(*net, seed=12)
+    w, m, l, grid, b = _split(net)
+    theta, x, t = _inputs(net, seed=12)
     print(f"fno grad {net}", flush=True)
-    f = _net(*net, theta)
+    f = _net(net, theta)
     loss, g = f.grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
     g = g.cpu().numpy().astype(np.float64)
     gref, lref = ofno.backward(theta.astype(np.float64), x.astype(np.float64), t.astype(np.float64),
                                w, m, l)
     assert abs(loss - lref) <= 1e-5 * abs(lref)
     assert _rel(g, gref) <= 1e-4, _rel(g, gref)
-    for name, sl in _groups(w, m, l):
+    for name, sl in _groups(w, m, l, len(grid)):
         assert _rel(g[sl], gref[sl]) <= 1e-3, (name, _rel(g[sl], gref[sl]))
     f.close()
+
+
+def test_3d_network_rejects_mismatched_sizes():
+    from paper_2204_07247_amd import pfch
+    with pytest.raises(pfch.PfchError):
+        pfch.Fno(4, 3, 1, 4, 8, 8)      # 2M > Nz
+    with pytest.raises(pfch.PfchError):
+        pfch.Fno(4, 2, 1, 8, 8, 3)      # M > Nx / 2
+    assert pfch.fno_num_params(4, 2, 1, ndim=3) == ofno.n_params(4, 2, 1, ndim=3)
 
 
 def test_adam_update_and_training_reduce_loss():
@@ -96,10 +121,9 @@ def test_adam_update_and_training_reduce_loss():
     a few dozen updates on a fixed batch cut the loss."""
     import torch
     net = (4, 3, 2, 12, 12, 4)
-    w, m, l, ny, nx, b = net
-    theta, x, _ = _inputs(*net, seed=13)
+    theta, x, _ = _inputs(net, seed=13)
     t = (0.5 * x[:, 0] - 0.3 * x[:, 1]).astype(np.float32)  # a target the network can fit
-    f = _net(*net, theta)
+    f = _net(net, theta)
     xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
     loss0, g = f.grad(xd, td)
     lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
@@ -155,7 +179,8 @@ def _one_step(w, un, unm1, dtp, k, fno=None, norm=None, guess=0, max_iter=None):
 @pytest.mark.parametrize("w", [
     dataclasses.replace(W.PFC64_MP, seeds=(0,)),
     dataclasses.replace(W.FCH256_BDF2, shape=(64, 64), seeds=(1,)),
-], ids=lambda w: f"{w.model}-{w.scheme}")
+    dataclasses.replace(W.PFC192_3D, shape=(16, 16, 32), lengths=(16.0, 16.0, 32.0), seeds=(2,)),
+], ids=lambda w: f"{w.model}-{w.scheme}-{len(w.shape)}d")
 def test_learned_guess_step_within_tolerance(w):
     """From the same state, the learned-guess step and the extrapolated-guess
     step both converge; the solutions differ within the PAGD tolerance and
@@ -163,8 +188,7 @@ def test_learned_guess_step_within_tolerance(w):
     from paper_2204_07247_amd import pfch
     print(f"learned guess {w.model} {w.scheme} {w.shape}", flush=True)
     un, unm1, dtp, k = _history(w, 3)
-    ny, nx = w.shape
-    fno = pfch.Fno(8, 4, 2, ny, nx)
+    fno = pfch.Fno(8, 4, 2, *w.shape)
     fno.init_params(seed=5)
     u = un.cpu().numpy()
     du = (un - unm1).cpu().numpy()
@@ -189,8 +213,7 @@ def test_failed_learned_guess_falls_back_to_extrapolation():
     from paper_2204_07247_amd import pfch
     w = dataclasses.replace(W.PFC64_MP, seeds=(2,))
     un, unm1, dtp, k = _history(w, 2)
-    ny, nx = w.shape
-    fno = pfch.Fno(4, 3, 1, ny, nx)
+    fno = pfch.Fno(4, 3, 1, *w.shape)
     fno.init_params(seed=9)
     norm = (0.0, 1.0, 1.0, 1e150)  # correction of order 1e150: the cubic term overflows
     rc_p, st_p, plain = _one_step(w, un, unm1, dtp, k, max_iter=60)
@@ -200,3 +223,22 @@ def test_failed_learned_guess_falls_back_to_extrapolation():
     assert st_l["iters"] == st_p["iters"]
     assert np.array_equal(learned, plain)
     fno.close()
+
+
+def test_network_grid_must_match_instance():
+    """A 2D network does not attach to a 3D instance and vice versa."""
+    from paper_2204_07247_amd import pfch
+    w3 = dataclasses.replace(W.PFC192_3D, shape=(16, 16, 32), lengths=(16.0, 16.0, 32.0))
+    ctx = pfch.Context([desc_for(w3, guess=1)])
+    norm = (0.0, 1.0, 1.0, 1.0)
+    f2 = pfch.Fno(4, 2, 1, 16, 32)
+    f3 = pfch.Fno(4, 2, 1, 16, 16, 32)
+    f3b = pfch.Fno(4, 2, 1, 8, 16, 32)
+    with pytest.raises(pfch.PfchError):
+        ctx.set_fno(0, f2, norm)
+    with pytest.raises(pfch.PfchError):
+        ctx.set_fno(0, f3b, norm)
+    ctx.set_fno(0, f3, norm)
+    ctx.close()
+    for f in (f2, f3, f3b):
+        f.close()
