@@ -369,6 +369,14 @@ def _learned_vs_plain(w, fno, norm_fn, steps):
         res[mode] = dict(steps_per_s=round(steps / el, 2), iters_per_step=round(float(np.mean(its)), 3))
         if mode == "learned":
             res[mode]["fallbacks"] = int(sum(k == 2 for k in kinds))
+    x = torch.zeros((1, 2) + tuple(w.shape), dtype=torch.float32, device="cuda")
+    fno.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        fno.forward(x)
+    torch.cuda.synchronize()
+    res["fno_forward_ms"] = round(1e3 * (time.perf_counter() - t0) / 10, 3)
     res["steps"] = steps
     res["learned_over_plain_steps_per_s"] = round(res["learned"]["steps_per_s"] / res["plain"]["steps_per_s"], 3)
     res["final_max_abs_diff"] = float((finals["learned"] - finals["plain"]).abs().max().item())
@@ -417,6 +425,38 @@ def learned_comparison(epochs, eval_steps, deploy_steps):
     return res
 
 
+def learned3d_comparison(epochs, traj_steps, eval_steps):
+    """FNO warm start (width 16, 8 modes per axis, 4 layers) trained on
+    solver trajectories of the PFC 192^3 generator (seeds 100-103,
+    `traj_steps` steps each, 10% of the triples held out), then plain vs
+    learned guess on PFC 192^3 (seed 0)."""
+    import dataclasses
+
+    import torch
+    from paper_2204_07247_amd import learned
+    base = W.PFC192_3D
+    ws = [dataclasses.replace(base, seeds=(s,)) for s in range(100, 104)]
+    u0s = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    cfg = learned.TrainConfig(width=16, modes=8, layers=4, batch=4, epochs=epochs)
+    log(f"[bench] learned guess 3D: trajectories and training ({epochs} epochs)")
+    t0 = time.perf_counter()
+    tr = learned.train(ws, u0s, traj_steps, cfg, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del u0s
+    res = dict(network=dict(width=cfg.width, modes=cfg.modes, layers=cfg.layers, dtype="f32",
+                            params=tr.fno.n_params),
+               training=dict(data=f"{len(ws)} x {traj_steps} steps of {base.name} (seeds 100-103)",
+                             triples=tr.n_train + tr.n_val, held_out=tr.n_val, epochs=epochs,
+                             batch=cfg.batch, lr=cfg.lr, seconds=round(t_train, 1),
+                             train_loss=[round(v, 5) for v in tr.train_loss],
+                             held_out_loss=[round(v, 5) for v in tr.val_loss]))
+    log("[bench] learned guess 3D: PFC 192^3 plain vs learned")
+    res[base.name] = _learned_vs_plain(base, tr.fno, lambda un, unm1: tr.norm, eval_steps)
+    tr.fno.close()
+    return res
+
+
 def cpu_baseline(w, max_steps, budget_s):
     """The CPU oracle on the same workload, first steps of the same trajectory."""
     from oracle import driver, models, spectral
@@ -450,6 +490,8 @@ def main():
     ap.add_argument("--ensemble", type=int, default=64, help="instances in the batched comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
     ap.add_argument("--learned-epochs", type=int, default=8)
+    ap.add_argument("--learned3d-epochs", type=int, default=6,
+                    help="epochs of the PFC 192^3 learned-guess comparison (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the run, copy a MIB-sized float64 buffer three times "
                          "(a plain copy kernel of known traffic for counter calibration)")
@@ -510,6 +552,9 @@ def main():
     learned_res = None
     if not args.no_learned and not args.no_compare:
         learned_res = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=20)
+        if args.learned3d_epochs > 0:
+            learned_res["pfc3d"] = learned3d_comparison(args.learned3d_epochs, traj_steps=40,
+                                                        eval_steps=40)
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")

@@ -264,13 +264,13 @@ int64_t pfch_fno_num_params_3d(int32_t width, int32_t modes, int32_t layers);
  * Parameters start at zero (see pfch_fno_init_params).  The network lives
  * on `hip_stream` (NULL: the default stream).  PFCH_E_INVAL for invalid
  * sizes, PFCH_E_UNSUPPORTED when a product would exceed the launch limits
- * (B W Ny > 2^21, B W > 65535, 2M^2 > 65535), PFCH_E_NOMEM / PFCH_E_HIP on
+ * (B W > 65535, 2M^2 > 65535), PFCH_E_NOMEM / PFCH_E_HIP on
  * allocation or copy failure; *out is NULL on error. */
 int pfch_fno_create(int32_t width, int32_t modes, int32_t layers, int32_t ny, int32_t nx,
                     int32_t max_batch, void* hip_stream, pfch_fno** out);
 
-/* The same for Nz x Ny x Nx fields (2M <= Nz as well; limits B W Nz Ny
- * <= 2^21, B W Nz <= 65535, 4M^3 <= 65535).  Every other pfch_fno_* call
+/* The same for Nz x Ny x Nx fields (2M <= Nz as well; limits B W Nz
+ * <= 65535, 4M^3 <= 65535).  Every other pfch_fno_* call
  * takes either kind; a 3D network attaches to 3D instances only. */
 int pfch_fno_create_3d(int32_t width, int32_t modes, int32_t layers, int32_t nz, int32_t ny,
                        int32_t nx, int32_t max_batch, void* hip_stream, pfch_fno** out);

@@ -19,6 +19,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <vector>
@@ -392,12 +393,22 @@ inline long long fno_count(long long W, long long M, long long L, int ndim = 2) 
 
 constexpr int FNO_LOSS_BLOCKS = 256, FNO_SUM_BLOCKS = 256;
 
+// Launches k_gemm; an M beyond the grid's y extent (65535 tiles) is split
+// into row chunks, each a launch on offset A and C.
 template <bool AC, bool BC, bool CJA, bool CJB, bool CC, int BM, int BN>
 inline hipError_t gemm_launch(const GemmP& p, long long Z, hipStream_t s) {
-  const long long gy = (p.M + BM - 1) / BM, gx = (p.N + BN - 1) / BN;
-  if (gy > 65535 || Z > 65535 || gx > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_gemm<AC, BC, CJA, CJB, CC, BM, BN>), dim3((unsigned)gx, (unsigned)gy, (unsigned)Z),
-                     dim3(256), 0, s, p);
+  const long long gx = (p.N + BN - 1) / BN;
+  if (Z > 65535 || gx > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  constexpr long long CHUNK = 65535LL * BM;
+  for (long long m0 = 0; m0 < p.M; m0 += CHUNK) {
+    GemmP q = p;
+    q.M = (int)std::min<long long>(CHUNK, p.M - m0);
+    q.A = p.A + (AC ? 2 : 1) * m0 * p.sAm;
+    q.C = p.C + (CC ? 2 : 1) * m0 * p.sCm;
+    const long long gy = (q.M + BM - 1) / BM;
+    hipLaunchKernelGGL((k_gemm<AC, BC, CJA, CJB, CC, BM, BN>), dim3((unsigned)gx, (unsigned)gy, (unsigned)Z),
+                       dim3(256), 0, s, q);
+  }
   return hipGetLastError();
 }
 

@@ -2180,8 +2180,10 @@ int fno_create(int ndim, int32_t width, int32_t modes, int32_t layers, int32_t n
   if (ndim == 3 ? (nz < 2 || 2 * modes > nz) : nz != 1) return PFCH_E_INVAL;
   const long long W = width, M = modes, P = (long long)nz * ny * nx, B = max_batch;
   const long long MM = fno_modes(M, ndim), M2 = 2 * M * M;
-  // launch limits of the strided products (grid y and z extents)
-  if ((B * W * nz * ny + 31) / 32 > 65535 || B * W * nz > 65535 || MM > 65535) return PFCH_E_UNSUPPORTED;
+  // launch limits of the strided products (batch counts in the grid's z
+  // extent) and 32-bit row counts
+  if (B * W * nz > 65535 || MM > 65535 || B * W * nz * ny > 0x7fffffffLL || B * W * P > (1LL << 40))
+    return PFCH_E_UNSUPPORTED;
   pfch_fno* h = new pfch_fno();
   Fno& F = h->f;
   F.W = width;
