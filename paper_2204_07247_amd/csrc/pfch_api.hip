@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -266,11 +267,17 @@ int dalloc(std::vector<void*>& list, void** p, size_t bytes) {
   return PFCH_OK;
 }
 
-int halloc(std::vector<void*>& list, void** p, size_t bytes) {
-  if (hipHostMalloc(p, bytes, 0) != hipSuccess) {
+// Pinned host memory, zero-filled.  coherent: kernels write into it while
+// the host polls it (stop records, the chunk counter), so device writes must
+// reach host memory in the order their fences give, with no caching in the
+// device's L2.
+int halloc(std::vector<void*>& list, void** p, size_t bytes, bool coherent = false) {
+  const unsigned flags = coherent ? hipHostMallocMapped | hipHostMallocCoherent : hipHostMallocDefault;
+  if (hipHostMalloc(p, bytes, flags) != hipSuccess) {
     *p = nullptr;
     return PFCH_E_NOMEM;
   }
+  std::memset(*p, 0, bytes);
   list.push_back(*p);
   return PFCH_OK;
 }
@@ -689,7 +696,11 @@ int launch_accept(pfch_ctx* ctx, AccDsts inl, double** dsts, double* part, int c
 int wait_chunk(pfch_ctx* ctx, uint32_t want) {
   const volatile uint32_t* seq = ctx->h_seq;
   for (long k = 0; k < 2000000; ++k) {  // bounded: about a millisecond or more
-    if ((int32_t)(*seq - want) >= 0) return PFCH_OK;
+    if ((int32_t)(*seq - want) >= 0) {
+      // the stop records written before the counter are read after it
+      std::atomic_thread_fence(std::memory_order_acquire);
+      return PFCH_OK;
+    }
 #if defined(__x86_64__)
     __builtin_ia32_pause();
 #endif
@@ -1364,11 +1375,12 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   ctx->d_scale = (double*)p;
   if ((rc = dalloc(ctx->allocs, &p, sizeof(double) * n_inst))) goto fail;
   ctx->d_mass = (double*)p;
-  if ((rc = halloc(ctx->host_allocs, &p, sizeof(StopRec) * n_inst))) goto fail;
+  if ((rc = halloc(ctx->host_allocs, &p, sizeof(StopRec) * n_inst, true))) goto fail;
   ctx->h_recs = (StopRec*)p;
+  for (int i = 0; i < n_inst; ++i) ctx->h_recs[i].stop_iter = -1;  // not stopped until a chunk says so
   if ((rc = halloc(ctx->host_allocs, &p, 64))) goto fail;
   ctx->h_scratch = (int32_t*)p;
-  if ((rc = halloc(ctx->host_allocs, &p, 64))) goto fail;
+  if ((rc = halloc(ctx->host_allocs, &p, 64, true))) goto fail;
   ctx->h_seq = (uint32_t*)p;
   *ctx->h_seq = 0;
   if ((rc = dalloc(ctx->allocs, &p, 64))) goto fail;
