@@ -492,6 +492,9 @@ def main():
     ap.add_argument("--learned-epochs", type=int, default=8)
     ap.add_argument("--learned3d-epochs", type=int, default=6,
                     help="epochs of the PFC 192^3 learned-guess comparison (0 skips it)")
+    ap.add_argument("--tune-file", default=os.path.join(ROOT, "paper_2204_07247_amd", "tune_mi355x.txt"),
+                    help="plan choices of the autotuner to reuse (PFCH_TUNE_FILE; an already set "
+                         "environment variable wins; '' times every plan afresh)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the run, copy a MIB-sized float64 buffer three times "
                          "(a plain copy kernel of known traffic for counter calibration)")
@@ -501,6 +504,8 @@ def main():
               "instances shard across GPUs without communication, see DESIGN.md",
               file=sys.stderr)
         sys.exit(2)
+    if args.tune_file and "PFCH_TUNE_FILE" not in os.environ:
+        os.environ["PFCH_TUNE_FILE"] = args.tune_file
     w = WORKLOADS[args.workload]
     if args.copy_calibration:
         import torch
@@ -513,6 +518,8 @@ def main():
         log(f"[bench] calibration copy: 3 x {args.copy_calibration} MiB read + write")
         del src, dst
     elapsed, iters, timing, cfg = gpu_run(w, args.steps, args.warmup, not args.no_kernel_timing)
+    if os.environ.get("PFCH_TUNE_FILE"):
+        cfg["tune_file"] = os.path.relpath(os.environ["PFCH_TUNE_FILE"], ROOT)
     value = args.steps / elapsed
     ab = algorithmic_bytes(w)
     roof = None

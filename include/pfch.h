@@ -315,7 +315,10 @@ int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4])
  * `inst`'s group (all instances of one model, scheme and grid share them),
  * as chosen by the autotuner at pfch_create, which times the candidates on
  * the device and keeps the choice for the process (set PFCH_AUTOTUNE=0 in
- * the environment to keep the defaults).  out[37]:
+ * the environment to keep the defaults).  With PFCH_TUNE_FILE naming a text
+ * file, a valid choice recorded there for the group's (model, scheme, Nx,
+ * Ny, Nz) is used without timing and new choices are appended, so that
+ * separate processes run the same kernels.  out[37]:
  *   0 row plan alternative (-1 = default), 1 row pairs per block,
  *   2 column plan alternative (2D), 3 columns per block (2D),
  *   4 y-pass plan alternative (3D), 5 y-pass columns per block (3D),

@@ -257,9 +257,19 @@ struct pfch_ctx {
 
 namespace {
 
+// With PFCH_DEBUG set in the environment, failed allocations are reported
+// on stderr with the runtime's error string.
+void alloc_failed(const char* what, size_t bytes, hipError_t e) {
+  const char* dbg = std::getenv("PFCH_DEBUG");
+  if (dbg && dbg[0] && dbg[0] != '0')
+    std::fprintf(stderr, "pfch: %s of %zu bytes failed: %s\n", what, bytes, hipGetErrorString(e));
+}
+
 int dalloc(std::vector<void*>& list, void** p, size_t bytes) {
   if (bytes == 0) bytes = 8;
-  if (hipMalloc(p, bytes) != hipSuccess) {
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    alloc_failed("hipMalloc", bytes, e);
     *p = nullptr;
     return PFCH_E_NOMEM;
   }
@@ -273,7 +283,9 @@ int dalloc(std::vector<void*>& list, void** p, size_t bytes) {
 // device's L2.
 int halloc(std::vector<void*>& list, void** p, size_t bytes, bool coherent = false) {
   const unsigned flags = coherent ? hipHostMallocMapped | hipHostMallocCoherent : hipHostMallocDefault;
-  if (hipHostMalloc(p, bytes, flags) != hipSuccess) {
+  const hipError_t e = hipHostMalloc(p, bytes, flags);
+  if (e != hipSuccess) {
+    alloc_failed("hipHostMalloc", bytes, e);
     *p = nullptr;
     return PFCH_E_NOMEM;
   }
@@ -934,6 +946,72 @@ void apply_z3(Group& G, const Z3K& k, int kyb) {
     if (G.z3_lds > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.z3_lds);
 }
 
+// A choice the group's kernels can run: alternatives in range, geometry
+// within the launch and LDS limits.
+bool choice_ok(const Group& G, const TuneChoice& c) {
+  if (c.row_alt < -1 || c.row_alt >= (int)G.ralts.size()) return false;
+  const RowK& rk = c.row_alt < 0 ? G.rs : G.ralts[c.row_alt];
+  if (c.teams < 1 || (c.teams & (c.teams - 1)) || !row_geometry_ok(G, rk, c.teams)) return false;
+  if (G.ndim == 3) {
+    if (c.y3_alt < -1 || c.y3_alt >= (int)G.y3alts.size() || c.z3_alt < -1 || c.z3_alt >= (int)G.z3alts.size())
+      return false;
+    return y3_geometry_ok(G, c.y3_alt < 0 ? G.y3d : G.y3alts[c.y3_alt], c.cy) &&
+           z3_geometry_ok(G, c.z3_alt < 0 ? G.z3d : G.z3alts[c.z3_alt], c.kyb);
+  }
+  if (c.col_alt < -1 || c.col_alt >= (int)G.calts.size()) return false;
+  const ColK& ck = c.col_alt < 0 ? G.cs : G.calts[c.col_alt];
+  if (c.cb != 1 && c.cb != 2 && c.cb != 4) return false;
+  return col_geometry_ok(G, ck, c.cb) && !(ck.fp && c.persist);
+}
+
+// Tuning file: with PFCH_TUNE_FILE set, a choice recorded there for the
+// group's (model, scheme, Nx, Ny, Nz) is used instead of timing, and a new
+// choice is appended.  One line per entry:
+//   model scheme nx ny nz  row_alt teams col_alt cb persist cy kyb y3_alt z3_alt
+// (the last valid line for a key wins).
+using TuneKey = std::tuple<int, int, int, int, int>;
+
+bool tune_file_lookup(const TuneKey& key, TuneChoice* out) {
+  const char* path = std::getenv("PFCH_TUNE_FILE");
+  if (!path || !path[0]) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[256];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    int v[14];
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5],
+                    &v[6], &v[7], &v[8], &v[9], &v[10], &v[11], &v[12], &v[13]) != 14)
+      continue;
+    if (std::make_tuple(v[0], v[1], v[2], v[3], v[4]) != key) continue;
+    TuneChoice c;
+    c.row_alt = v[5];
+    c.teams = v[6];
+    c.col_alt = v[7];
+    c.cb = v[8];
+    c.persist = v[9] != 0;
+    c.cy = v[10];
+    c.kyb = v[11];
+    c.y3_alt = v[12];
+    c.z3_alt = v[13];
+    *out = c;
+    found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_file_store(const TuneKey& key, const TuneChoice& c) {
+  const char* path = std::getenv("PFCH_TUNE_FILE");
+  if (!path || !path[0]) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%d %d %d %d %d  %d %d %d %d %d %d %d %d %d\n", std::get<0>(key), std::get<1>(key), std::get<2>(key),
+               std::get<3>(key), std::get<4>(key), c.row_alt, c.teams, c.col_alt, c.cb, c.persist ? 1 : 0, c.cy,
+               c.kyb, c.y3_alt, c.z3_alt);
+  std::fclose(f);
+}
+
 void apply_choice(Group& G, const TuneChoice& c) {
   apply_row(G, c.row_alt < 0 ? G.rs : G.ralts[c.row_alt], c.teams);
   if (G.ndim == 3) {
@@ -1032,6 +1110,14 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
     apply_choice(G, it->second);
     return PFCH_OK;
   }
+  {
+    TuneChoice fc;
+    if (tune_file_lookup(key, &fc) && choice_ok(G, fc)) {
+      apply_choice(G, fc);
+      cache[key] = fc;
+      return PFCH_OK;
+    }
+  }
   if (G.ndim == 3) {
     TuneChoice c;
     c.teams = (int)(G.row_block.x / G.rk.T);
@@ -1041,6 +1127,7 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
     int rc;
     if ((rc = tune_group3(ctx, G, c))) return rc;
     cache[key] = c;
+    tune_file_store(key, c);
     return PFCH_OK;
   }
   TuneChoice def;
@@ -1111,6 +1198,7 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
   (void)hipEventDestroy(e1);
   apply_choice(G, best);
   cache[key] = best;
+  tune_file_store(key, best);
   return PFCH_OK;
 }
 
@@ -1642,20 +1730,7 @@ int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]) {
   c.z3_alt = choice[6];
   c.kyb = choice[7];
   c.persist = choice[8] != 0;
-  if (c.row_alt < -1 || c.row_alt >= (int)G.ralts.size()) return PFCH_E_INVAL;
-  const RowK& rk = c.row_alt < 0 ? G.rs : G.ralts[c.row_alt];
-  if (c.teams < 1 || (c.teams & (c.teams - 1)) || !row_geometry_ok(G, rk, c.teams)) return PFCH_E_INVAL;
-  if (G.ndim == 3) {
-    if (c.y3_alt < -1 || c.y3_alt >= (int)G.y3alts.size() || c.z3_alt < -1 || c.z3_alt >= (int)G.z3alts.size())
-      return PFCH_E_INVAL;
-    if (!y3_geometry_ok(G, c.y3_alt < 0 ? G.y3d : G.y3alts[c.y3_alt], c.cy)) return PFCH_E_INVAL;
-    if (!z3_geometry_ok(G, c.z3_alt < 0 ? G.z3d : G.z3alts[c.z3_alt], c.kyb)) return PFCH_E_INVAL;
-  } else {
-    if (c.col_alt < -1 || c.col_alt >= (int)G.calts.size()) return PFCH_E_INVAL;
-    const ColK& ck = c.col_alt < 0 ? G.cs : G.calts[c.col_alt];
-    if (c.cb != 1 && c.cb != 2 && c.cb != 4) return PFCH_E_INVAL;
-    if (!col_geometry_ok(G, ck, c.cb) || (ck.fp && c.persist)) return PFCH_E_INVAL;
-  }
+  if (!choice_ok(G, c)) return PFCH_E_INVAL;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
   for (auto g : ctx->graph_defs) (void)hipGraphDestroy(g);

@@ -106,6 +106,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2204_07247_amd.build`")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded, so that both share one runtime and one device context
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
         L.pfch_validate_desc.argtypes = [ctypes.POINTER(InstanceDesc)]
