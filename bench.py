@@ -421,8 +421,7 @@ def learned_comparison(epochs, eval_steps, deploy_steps):
     log("[bench] learned guess: PFC 1024^2 with the FCH-trained weights")
     res[pfc.name + "_fch_trained"] = _learned_vs_plain(pfc, f, pfc_norm, deploy_steps)
     f.close()
-    tr.fno.close()
-    return res
+    return res, tr, cfg
 
 
 def learned3d_comparison(epochs, traj_steps, eval_steps):
@@ -453,7 +452,66 @@ def learned3d_comparison(epochs, traj_steps, eval_steps):
                              held_out_loss=[round(v, 5) for v in tr.val_loss]))
     log("[bench] learned guess 3D: PFC 192^3 plain vs learned")
     res[base.name] = _learned_vs_plain(base, tr.fno, lambda un, unm1: tr.norm, eval_steps)
-    tr.fno.close()
+    return res, tr, cfg
+
+
+def batched_learned(tr2, cfg2, tr3, steps, warmup):
+    """The combined set (8 FCH 1024^2 + 8 FCH 2048^2 + PFC 192^3) in one
+    context, plain and with the learned guess on every instance: the FCH
+    instances share the FCH 256^2-trained weights (one network object per
+    grid), the 3D instance uses the PFC 192^3 network.  Each instance's
+    input normalisation comes from its own state after the warm-up steps,
+    with the training set's ratio of correction to increment spread."""
+    import torch
+    from paper_2204_07247_amd import learned, pfch
+    ws = W.fch_ensemble() + [W.PFC192_3D]
+    u0 = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    nets = {}
+    for w in ws:
+        if len(w.shape) == 2 and tuple(w.shape) not in nets:
+            nets[tuple(w.shape)] = learned.deploy(tr2, *w.shape, cfg=cfg2)
+    res = {}
+    for mode in ("plain", "learned"):
+        ctx = pfch.Context([learned.desc_of(w, guess=1 if mode == "learned" else 0) for w in ws])
+        ctx.set_stats_detail(0)
+        for i, u in enumerate(u0):
+            ctx.set_state(i, u)
+        for _ in range(warmup):
+            ctx.step([w.dt for w in ws])
+        if mode == "learned":
+            for i, w in enumerate(ws):
+                un, unm1 = torch.empty_like(u0[i]), torch.empty_like(u0[i])
+                ctx.get_state(i, un, unm1)
+                tr = tr3 if len(w.shape) == 3 else tr2
+                d = un - unm1
+                sd = float(d.std().item()) or 1.0
+                norm = (float(un.mean().item()), float(un.std().item()) or 1.0, sd,
+                        tr.norm[3] / tr.norm[2] * sd)
+                ctx.set_fno(i, tr3.fno if len(w.shape) == 3 else nets[tuple(w.shape)], norm)
+        its = np.zeros(len(ws))
+        kinds = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rc, st = ctx.step([w.dt for w in ws])
+            if rc != pfch.PFCH_OK:
+                raise RuntimeError(f"batched {mode} step failed: {pfch.strerror(rc)}")
+            its += [x["iters"] for x in st]
+            kinds += [x["guess"] for x in st]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx.close()
+        res[mode] = dict(instance_steps_per_s=round(len(ws) * steps / el, 2),
+                         ms_per_step=round(1e3 * el / steps, 3),
+                         iters_per_step_mean=round(float(its.sum() / (len(ws) * steps)), 3))
+        if mode == "learned":
+            res[mode]["learned_guesses"] = int(sum(k == 1 for k in kinds))
+            res[mode]["fallbacks"] = int(sum(k == 2 for k in kinds))
+    for f in nets.values():
+        f.close()
+    res.update(workload="fch2d_8x1024_8x2048_bdf2 + pfc3d_192_bdf2", instances=len(ws), steps=steps,
+               learned_over_plain=round(res["learned"]["instance_steps_per_s"] /
+                                        res["plain"]["instance_steps_per_s"], 3))
     return res
 
 
@@ -558,10 +616,14 @@ def main():
                     adaptive_run(W.PFC64_MP, 1e-4, 1e-4, 0.5, attempts=200)]
     learned_res = None
     if not args.no_learned and not args.no_compare:
-        learned_res = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=20)
+        learned_res, tr2, cfg2 = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=20)
         if args.learned3d_epochs > 0:
-            learned_res["pfc3d"] = learned3d_comparison(args.learned3d_epochs, traj_steps=40,
-                                                        eval_steps=40)
+            learned_res["pfc3d"], tr3, _ = learned3d_comparison(args.learned3d_epochs, traj_steps=40,
+                                                                eval_steps=40)
+            log("[bench] batched + learned: FCH 8x1024^2 + 8x2048^2 + PFC 192^3")
+            learned_res["batched"] = batched_learned(tr2, cfg2, tr3, steps=5, warmup=2)
+            tr3.fno.close()
+        tr2.fno.close()
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
