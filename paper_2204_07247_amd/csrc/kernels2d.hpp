@@ -1150,6 +1150,137 @@ __global__ __launch_bounds__(256) void k_row_setup_lap(InstDev* const* __restric
   }
 }
 
+// Field-parallel form of k_row_setup_lap for one row pair per block: four
+// teams, one per transformed field (0: F', 1: p, 2: v_breve, 3: g), so the
+// four forward transforms run side by side.  Team 0 forms x0 and v_breve
+// (and the averaged-Newton sums), team 1 Delta x0 and Delta v_breve, team 3
+// g; after a block barrier each team builds its field from the shared
+// v_breve rows and transforms it.  Same outputs as k_row_setup_lap; one
+// partial-sum slot per block.
+template <class PX>
+__global__ __launch_bounds__(256) void k_row_setup_lap_fp(InstDev* const* __restrict__ grp,
+                                                          const StepArgs* __restrict__ args, int bpi,
+                                                          StepArgsInline inl) {
+  extern __shared__ c2 smem[];
+  __shared__ double red[4];
+  const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
+  InstDev* __restrict__ I = grp[gi];
+  const StepArgs sa = args ? args[gi] : inl.a[gi];
+  if (!sa.lun) return;  // k_row_setup's instance
+  constexpr int N = PX::N, T = PX::T, RM = PX::RMAX, NT = 4;
+  const int role = threadIdx.x / T;
+  const int t = threadIdx.x - role * T;
+  c2* lds = smem + role * lds_len(N);
+  // v_breve of rows r0, r0 + 1, then Delta v_breve of both rows
+  double* ex = (double*)(smem + NT * lds_len(N) + tw_lds_count<PX>());
+  const int r0 = 2 * lb;
+  const int rows = I->rows;
+  const uint32_t fs = (uint32_t)I->field_stride;
+  const double th = sa.theta;
+  Twiddles<PX> tw;
+  load_twiddles<PX>(tw, I->tw_x, t);
+
+  if (lb == 0 && threadIdx.x == 0) {
+    I->a = sa.a;
+    I->theta = sa.theta;
+    I->a_over_theta = sa.a / sa.theta;
+    I->un = sa.un;
+    I->acc_dst = sa.acc_dst;
+    I->acc_ldst = sa.acc_ldst;
+    I->lap_hist = 1;
+    *I->iter_base = 0;
+    *I->flags = 0;
+    I->rec->stop_iter = -1;
+    I->rec->flags = 0;
+    I->rec->norm_bits = 0;
+  }
+  {  // clear the per-iteration norm slots
+    const int nthreads = bpi * blockDim.x;
+    for (int i = lb * blockDim.x + threadIdx.x; i < I->max_iter; i += nthreads) I->norms[i] = 0;
+  }
+
+  double s0 = 0.0, s1 = 0.0;
+  const double tau = I->tau, e2 = I->eps * I->eps, eta2 = I->eta2;
+  c2 z[RM];
+  if (role == 0) {
+#pragma unroll
+    for (int row = 0; row < 2; ++row) {
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+        const double u = gp(sa.un)[idx], um = gp(sa.unm1)[idx];
+        const double x0 = u + sa.rho * (u - um);
+        gp(I->X[0])[idx] = x0;
+        gp(I->X[2])[idx] = x0;
+        const double v = th * x0 + (1.0 - th) * u;
+        ex[row * N + t + m * T] = v;
+        const double f1 = (v * v - 1.0) * (v + tau);
+        const double f2 = 3.0 * v * v - 1.0 + 2.0 * tau * v;
+        const double f3 = 6.0 * v + 2.0 * tau;
+        s0 += f2 * f2 - eta2 * f2 + f3 * f1;
+        s1 += e2 * f2 - I->eta1 * e2;
+      }
+    }
+  } else if (role == 1) {
+#pragma unroll
+    for (int row = 0; row < 2; ++row) {
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+        const double lu = gp(sa.lun)[idx], lum = gp(sa.lunm1)[idx];
+        const double lx0 = lu + sa.rho * (lu - lum);
+        gp(I->DX[0])[idx] = lx0;
+        gp(I->DX[2])[idx] = lx0;
+        if (th != 1.0) gp(I->dun)[idx] = lu;
+        ex[(2 + row) * N + t + m * T] = th * lx0 + (1.0 - th) * lu;
+      }
+    }
+  } else if (role == 3) {
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      double g[2];
+#pragma unroll
+      for (int row = 0; row < 2; ++row) {
+        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+        g[row] = sa.gu * gp(sa.un)[idx] + sa.gm * gp(sa.unm1)[idx];
+      }
+      z[m] = c2{g[0], g[1]};
+    }
+  }
+  __syncthreads();
+  if (role < 3) {
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      const int k = t + m * T;
+      double f[2];
+#pragma unroll
+      for (int row = 0; row < 2; ++row) {
+        const double u = ex[row * N + k];
+        const double f1 = (u * u - 1.0) * (u + tau);
+        if (role == 0) {
+          f[row] = f1;
+        } else if (role == 1) {
+          const double f2 = 3.0 * u * u - 1.0 + 2.0 * tau * u;
+          const double om = e2 * ex[(2 + row) * N + k] - f1;
+          f[row] = -f2 * om - eta2 * f1;
+        } else {
+          f[row] = u;
+        }
+      }
+      z[m] = c2{f[0], f[1]};
+    }
+  }
+  fft<PX, false>(z, lds, tw, t);
+  GLB c2* dst = role == 3 ? gp(I->G) : gp(I->S) + role * fs;
+  unpack_store<PX>(z, lds, dst, r0, dst, r0 + 1, rows, t);
+  const double bs0 = block_sum(s0, red);
+  const double bs1 = block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    gp(I->part)[2 * lb] = bs0;
+    gp(I->part)[2 * lb + 1] = bs1;
+  }
+}
+
 // Step setup, column part: g^ (stored for the whole step, column 0 packed
 // like every spectral field); FCH also the Laplacians of x0 (and of u^n for
 // the midpoint rule) back as spectral rows.  Block 0 sums the averaged-Newton

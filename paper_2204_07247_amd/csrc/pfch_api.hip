@@ -665,7 +665,12 @@ int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, u
   }
   if (lap && G.model == PFCH_FCH) {
     void* a[] = {&grp, &args, &rbpi, &il};
-    if ((rc = launch(G.rs.setup_lap, dim3(nm * rbpi), G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
+    if (G.rs.setup_lap_fp && rbpi == G.rows / 2) {  // one row pair per block: one partial-sum slot each
+      const size_t lds = (size_t)G.rs.setup_fp_elems * sizeof(c2);
+      if ((rc = launch(G.rs.setup_lap_fp, dim3(nm * rbpi), dim3(4 * G.rs.T), lds, a, ctx->stream))) return rc;
+    } else if ((rc = launch(G.rs.setup_lap, dim3(nm * rbpi), G.srow_block, G.srow_lds, a, ctx->stream))) {
+      return rc;
+    }
   }
   if (G.ndim == 3) {
     int ybpi = G.y3_bpi, zbpi = G.z3_bpi;

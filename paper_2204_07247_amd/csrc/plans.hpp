@@ -17,6 +17,8 @@ struct RowK {
   const void* setup = nullptr;
   const void* start_fch = nullptr;
   const void* setup_lap = nullptr;  // FCH set-up from kept Laplacians
+  const void* setup_lap_fp = nullptr;  // its field-parallel form (one row pair, four teams per block)
+  int setup_fp_elems = 0;              // LDS elements of setup_lap_fp
   const void* rhs_fwd = nullptr;  // R(v) row passes (default plans only)
   const void* rhs_mid = nullptr;  // FCH
   const void* rhs_inv = nullptr;
@@ -50,6 +52,10 @@ RowK make_row() {
   k.setup = (const void*)&k_row_setup<P, MODEL>;
   if (MODEL == MODEL_FCH) k.start_fch = (const void*)&k_row_start_fch<P>;
   if (MODEL == MODEL_FCH) k.setup_lap = (const void*)&k_row_setup_lap<P>;
+  if constexpr (MODEL == MODEL_FCH && 4 * P::T <= 256 && P::N <= 512) {
+    k.setup_lap_fp = (const void*)&k_row_setup_lap_fp<P>;
+    k.setup_fp_elems = 4 * lds_len(P::N) + tw_lds_count<P>() + 2 * P::N;  // + 4 real rows
+  }
   k.rhs_fwd = (const void*)&k_rhs_row_fwd<P, MODEL>;
   if (MODEL == MODEL_FCH) k.rhs_mid = (const void*)&k_rhs_row_mid<P>;
   k.rhs_inv = (const void*)&k_rhs_row_inv<P>;
