@@ -580,10 +580,12 @@ int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
 // Iterations per graph launch.  Every launch ends with one host
 // synchronisation, and iterations past the stop still cost their (empty)
 // launches, so the first chunk covers the predicted count exactly and
-// further chunks are short.  Lengths are rounded to a small set so few
-// graphs get built.
+// further chunks are short.  Every length up to 32 has its own graph (the
+// common iteration counts, built when first needed); longer ones are
+// rounded to a small set.
 int chunk_len(int want) {
-  static const int lens[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 64};
+  if (want <= 32) return want < 1 ? 1 : want;
+  static const int lens[] = {40, 48, 56, 64};
   for (int k : lens)
     if (k >= want) return k;
   return 64;
