@@ -1279,7 +1279,9 @@ int pfch_validate_desc(const pfch_instance_desc* d) {
 
 void pfch_destroy(pfch_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  // work queued by the last step (its accept copy) may still be running; the
+  // null stream (0) is synchronised like any other
+  (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
   for (auto g : ctx->graph_defs) (void)hipGraphDestroy(g);
   for (auto& I : ctx->inst)
@@ -2254,7 +2256,7 @@ int64_t pfch_fno_num_params_3d(int32_t width, int32_t modes, int32_t layers) {
 
 void pfch_fno_destroy(pfch_fno* f) {
   if (!f) return;
-  if (f->f.s) (void)hipStreamSynchronize(f->f.s);
+  (void)hipStreamSynchronize(f->f.s);
   for (void* p : f->f.allocs) (void)hipFree(p);
   for (void* p : f->f.host_allocs) (void)hipHostFree(p);
   delete f;
