@@ -531,7 +531,8 @@ def cpu_baseline(w, max_steps, budget_s):
     el = time.perf_counter() - t0
     return dict(value=n / el, unit="time-steps/s", cores=1, kind="oracle",
                 sample=f"first {n} of {max_steps} steps of {w.name} (seed {w.seeds[0]}), "
-                       f"{el:.1f} s, NumPy float64 pocketfft, single thread")
+                       f"{el:.1f} s, NumPy float64 pocketfft, single thread",
+                host_cpus=os.cpu_count(), host_cpus_usable=len(os.sched_getaffinity(0)))
 
 
 def main():
