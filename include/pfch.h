@@ -331,7 +331,9 @@ int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4])
 int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[37]);
 
 /* Override that choice: choice = out[0..7] of pfch_get_plan plus choice[8]
- * = 1 for looping column blocks (2D); entries that do not apply to the
+ * for looping column blocks (2D): 0 one block per column block; 1, 2, 3
+ * fewer blocks that loop over the column blocks, as many as fit on the
+ * device, one per compute unit, two per compute unit; entries that do not apply to the
  * grid's dimension are ignored.  Each is validated against the kernels'
  * limits (PFCH_E_INVAL otherwise).  Results of different plans agree to
  * rounding. */

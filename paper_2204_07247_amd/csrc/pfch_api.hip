@@ -832,7 +832,7 @@ int learned_guess(pfch_ctx* ctx, Instance& I, double rho) {
 // ---------------------------------------------------------------------------
 struct TuneChoice {
   int row_alt = -1, teams = 0;  // alt -1: default plan
-  int col_alt = -1, cb = 0, persist = 0;
+  int col_alt = -1, cb = 0, persist = 0;  // persist: level of apply_col
   int cy = 0, kyb = 0;          // 3D: y-pass columns per block, z-pass ky per block
   int y3_alt = -1, z3_alt = -1;  // 3D: y- and z-pass plans
 };
@@ -874,8 +874,12 @@ void apply_row(Group& G, const RowK& k, int teams) {
   if (G.row_lds > 65536)
     (void)hipFuncSetAttribute(k.iter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.row_lds);
 }
-// persist: launch only as many column blocks as fit on the device at once,
-// each looping over items (next item's first field prefetched).
+// persist > 0: launch fewer column blocks, each looping over items (next
+// item's first field prefetched): 1 as many as fit on the device at once,
+// 2 one per compute unit, 3 two per compute unit (fewer blocks than fit
+// trade parallelism for overlap of one item's transforms with the next
+// item's loads).
+constexpr int PERSIST_LEVELS = 3;
 void apply_col(Group& G, const ColK& k, int cb, int persist = 0) {
   G.ck = k;
   G.col_block = dim3(k.T * cb);
@@ -887,8 +891,10 @@ void apply_col(Group& G, const ColK& k, int cb, int persist = 0) {
   if (persist) {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.iter, (int)G.col_block.x, G.col_lds) == hipSuccess &&
-        nb > 0 && G.num_cus > 0)
-      G.col_cap = nb * G.num_cus;
+        nb > 0 && G.num_cus > 0) {
+      const int per_cu = persist == 1 ? nb : std::min(nb, persist - 1);
+      G.col_cap = per_cu * G.num_cus;
+    }
   }
 }
 
@@ -968,6 +974,7 @@ bool choice_ok(const Group& G, const TuneChoice& c) {
   if (c.col_alt < -1 || c.col_alt >= (int)G.calts.size()) return false;
   const ColK& ck = c.col_alt < 0 ? G.cs : G.calts[c.col_alt];
   if (c.cb != 1 && c.cb != 2 && c.cb != 4) return false;
+  if (c.persist < 0 || c.persist > PERSIST_LEVELS) return false;
   return col_geometry_ok(G, ck, c.cb) && !(ck.fp && c.persist);
 }
 
@@ -996,7 +1003,7 @@ bool tune_file_lookup(const TuneKey& key, TuneChoice* out) {
     c.teams = v[6];
     c.col_alt = v[7];
     c.cb = v[8];
-    c.persist = v[9] != 0;
+    c.persist = v[9];
     c.cy = v[10];
     c.kyb = v[11];
     c.y3_alt = v[12];
@@ -1014,7 +1021,7 @@ void tune_file_store(const TuneKey& key, const TuneChoice& c) {
   FILE* f = std::fopen(path, "a");
   if (!f) return;
   std::fprintf(f, "%d %d %d %d %d  %d %d %d %d %d %d %d %d %d\n", std::get<0>(key), std::get<1>(key), std::get<2>(key),
-               std::get<3>(key), std::get<4>(key), c.row_alt, c.teams, c.col_alt, c.cb, c.persist ? 1 : 0, c.cy,
+               std::get<3>(key), std::get<4>(key), c.row_alt, c.teams, c.col_alt, c.cb, c.persist, c.cy,
                c.kyb, c.y3_alt, c.z3_alt);
   std::fclose(f);
 }
@@ -1185,10 +1192,13 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
     for (int alt = -1; alt < (int)G.calts.size(); ++alt) {
       const ColK& k = alt < 0 ? G.cs : G.calts[alt];
       for (int cb = 1; cb <= 4; cb *= 2) {
-        for (int persist = 0; persist <= 1; ++persist) {
+        int prev_cap = -1;
+        for (int persist = 0; persist <= PERSIST_LEVELS; ++persist) {
           if (!col_geometry_ok(G, k, cb) || (alt < 0 && cb == def.cb && !persist) || (k.fp && persist)) continue;
           apply_col(G, k, cb, persist);
-          if (persist && G.col_cap == 0) continue;
+          // a looping grid must loop (fewer blocks than items) and differ from the last one tried
+          if (persist && (G.col_cap == 0 || G.col_cap >= (int)G.col_bpi || G.col_cap == prev_cap)) continue;
+          if (persist) prev_cap = G.col_cap;
           float t = 0.f;
           if ((rc = time_iter_kernel(ctx, G, I, 0, e0, e1, &t))) return rc;
           if (t < TUNE_MARGIN * t_def_col && t < t_best) {
@@ -1738,7 +1748,7 @@ int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]) {
   c.cy = choice[5];
   c.z3_alt = choice[6];
   c.kyb = choice[7];
-  c.persist = choice[8] != 0;
+  c.persist = choice[8];
   if (!choice_ok(G, c)) return PFCH_E_INVAL;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
