@@ -424,6 +424,40 @@ def learned_comparison(epochs, eval_steps, deploy_steps):
     return res, tr, cfg
 
 
+def learned_pfc_trained(epochs, eval_steps, deploy_steps):
+    """The PFC-trained variant: the same network trained on trajectories of
+    PFC 256^2 (L = 256, the grid spacing of PFC 1024^2; MP, dt = 0.2; seeds
+    100-119, 100 steps each), then plain vs learned guess on PFC 256^2
+    (seed 0) and, with the same weights, on PFC 1024^2."""
+    import dataclasses
+
+    import torch
+    from paper_2204_07247_amd import learned
+    big = WORKLOADS["pfc1024"]
+    base = dataclasses.replace(big, name="pfc2d_256_mp", shape=(256, 256), lengths=(256.0, 256.0),
+                               steps=100)
+    ws = [dataclasses.replace(base, seeds=(s,)) for s in range(100, 120)]
+    u0s = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    cfg = learned.TrainConfig(epochs=epochs)
+    log(f"[bench] learned guess, PFC-trained: trajectories and training ({epochs} epochs)")
+    t0 = time.perf_counter()
+    tr = learned.train(ws, u0s, base.steps, cfg, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del u0s
+    res = dict(training=dict(data=f"{len(ws)} x {base.steps} steps of {base.name} (seeds 100-119)",
+                             triples=tr.n_train + tr.n_val, held_out=tr.n_val, epochs=epochs,
+                             seconds=round(t_train, 1),
+                             held_out_loss=[round(v, 5) for v in tr.val_loss]))
+    log("[bench] learned guess, PFC-trained: PFC 256^2 and PFC 1024^2 plain vs learned")
+    res[base.name] = _learned_vs_plain(base, tr.fno, lambda un, unm1: tr.norm, eval_steps)
+    f = learned.deploy(tr, *big.shape, cfg=cfg)
+    res[big.name] = _learned_vs_plain(big, f, lambda un, unm1: tr.norm, deploy_steps)
+    f.close()
+    tr.fno.close()
+    return res
+
+
 def learned3d_comparison(epochs, traj_steps, eval_steps):
     """FNO warm start (width 16, 8 modes per axis, 4 layers) trained on
     solver trajectories of the PFC 192^3 generator (seeds 100-103,
@@ -618,6 +652,8 @@ def main():
     learned_res = None
     if not args.no_learned and not args.no_compare:
         learned_res, tr2, cfg2 = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=20)
+        learned_res["pfc_trained"] = learned_pfc_trained(args.learned_epochs, eval_steps=100,
+                                                         deploy_steps=20)
         if args.learned3d_epochs > 0:
             learned_res["pfc3d"], tr3, _ = learned3d_comparison(args.learned3d_epochs, traj_steps=40,
                                                                 eval_steps=40)

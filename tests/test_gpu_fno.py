@@ -242,3 +242,45 @@ def test_network_grid_must_match_instance():
     ctx.close()
     for f in (f2, f3, f3b):
         f.close()
+
+
+def test_trained_network_gains_over_extrapolation():
+    """Trained on solver trajectories (PFC 64^2, MP), the network's guess is
+    closer to the converged u^{n+1} than the extrapolated guess on states it
+    was not trained on, and the learned step converges to the plain step's
+    solution within the tolerance."""
+    import torch
+    from paper_2204_07247_amd import learned, pfch
+    base = W.PFC64_MP
+    ws = [dataclasses.replace(base, seeds=(s,)) for s in range(100, 104)]
+    u0s = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    cfg = learned.TrainConfig(width=8, modes=8, layers=2, batch=8, epochs=25, lr=3e-3, seed=1)
+    print("train on 4 x 30 steps of pfc64", flush=True)
+    tr = learned.train(ws, u0s, 30, cfg)
+    assert tr.val_loss[-1] < tr.val_loss[0]
+    # held-out trajectory: seed 7, states after 10 steps
+    w = dataclasses.replace(base, seeds=(7,))
+    states = learned.trajectories([w], [torch.from_numpy(W.initial_condition(w)).cuda()], 14)[0]
+    mu, su, sd, so = tr.norm
+    x = torch.empty((1, 2) + tuple(w.shape), dtype=torch.float32, device="cuda")
+    gains = []
+    for n in range(10, 13):
+        unm1, un, unp1 = states[n - 1], states[n], states[n + 1]
+        tr.fno.prepare(unm1, un, None, 1.0, tr.norm, x[0])
+        y = tr.fno.forward(x)[0].double()
+        extrap = 2.0 * un - unm1
+        guess = extrap + so * (y - y.mean())
+        e_plain = float((extrap - unp1).norm())
+        e_learned = float((guess - unp1).norm())
+        gains.append(e_plain / e_learned)
+        assert abs(float(guess.mean() - extrap.mean())) <= 1e-14
+    print(f"guess error, extrapolated / learned: {gains}", flush=True)
+    assert min(gains) > 1.5, gains
+    # the learned step itself: converged, and within the tolerance of the plain step
+    un, unm1, dtp, k = states[12].clone(), states[11].clone(), w.dt, 12
+    rc_p, st_p, plain = _one_step(w, un, unm1, dtp, k)
+    rc_l, st_l, got = _one_step(w, un, unm1, dtp, k, fno=tr.fno, norm=tr.norm, guess=1)
+    assert rc_p == pfch.PFCH_OK and rc_l == pfch.PFCH_OK and st_l["guess"] == 1
+    assert np.max(np.abs(got - plain)) <= 1e-9
+    print(f"iterations plain {st_p['iters']}, learned {st_l['iters']}", flush=True)
+    tr.fno.close()
