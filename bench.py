@@ -593,9 +593,9 @@ def main():
                          "(a plain copy kernel of known traffic for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); independent "
-              "instances shard across GPUs without communication, see DESIGN.md",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the library runs on one "
+              "device; independent instances would shard across GPUs with no communication, "
+              "which is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.tune_file and "PFCH_TUNE_FILE" not in os.environ:
         os.environ["PFCH_TUNE_FILE"] = args.tune_file
