@@ -104,6 +104,11 @@ def test_fno_sizes_and_argument_checks_on_host():
     assert L.pfch_fno_create(4, 3, 2, 12, 4, 1, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
     assert L.pfch_fno_create(4, 3, 2, 12, 12, 0, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
     assert L.pfch_fno_create(4, 3, 2, 12, 12, 1, None, None) == pfch.PFCH_E_INVAL
+    for w, m, l in ((16, 8, 4), (3, 2, 2)):
+        assert pfch.fno_num_params(w, m, l, ndim=3) == ofno.n_params(w, m, l, ndim=3)
+    # 3D: 2M > Nz, null output
+    assert L.pfch_fno_create_3d(4, 3, 2, 4, 12, 12, 1, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
+    assert L.pfch_fno_create_3d(4, 3, 2, 12, 12, 12, 1, None, None) == pfch.PFCH_E_INVAL
     assert L.pfch_fno_forward(None, None, None, 1) == pfch.PFCH_E_INVAL
     assert L.pfch_fno_adam_step(None, 1e-3, 0.9, 0.999, 1e-8, 1) == pfch.PFCH_E_INVAL
     assert L.pfch_set_fno(None, 0, None, None) == pfch.PFCH_E_INVAL
@@ -123,3 +128,24 @@ def test_create_rejects_bad_arguments_before_device_work():
     res = (pfch.AdaptResult * 1)()
     assert L.pfch_step_adaptive(None, ctypes.byref(ad), res) == pfch.PFCH_E_INVAL
     assert L.pfch_rhs(None, 0, None, None) == pfch.PFCH_E_INVAL
+
+
+@pytest.mark.parametrize("compiler,std", [("gcc", "-std=c99"), ("g++", "-std=c++11")])
+def test_header_compiles_as_c_and_cxx(tmp_path, compiler, std):
+    """The public header is plain C (usable without HIP or C++ headers)."""
+    import shutil
+    import subprocess
+    cc = shutil.which(compiler)
+    if cc is None:
+        pytest.skip(f"{compiler} not available")
+    src = tmp_path / ("h.c" if compiler == "gcc" else "h.cpp")
+    src.write_text('#include "pfch.h"\n'
+                   "int main(void) {\n"
+                   "  pfch_instance_desc d;\n"
+                   "  pfch_stats s;\n"
+                   "  (void)d; (void)s;\n"
+                   "  return pfch_version() > 0 ? 0 : 1;\n"
+                   "}\n")
+    r = subprocess.run([cc, std, "-Wall", "-Wextra", "-Werror", "-pedantic", "-fsyntax-only",
+                        "-I", os.path.dirname(HEADER), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
