@@ -227,6 +227,13 @@ struct pfch_fno {
 
 struct pfch_ctx {
   hipStream_t stream = nullptr;
+  // Set-up of the next step enqueued at the end of pfch_step (same dt as
+  // the last two calls): the next pfch_step with that dt skips it.  Every
+  // other call that touches instance state or workspaces drops it.
+  bool spec = false;
+  std::vector<double> last_dt;  // step sizes of the last pfch_step
+  std::vector<int> spec_guess;
+  std::vector<double> spec_a;
   std::vector<Instance> inst;
   std::vector<Group> groups;
   InstDev** d_ptrs = nullptr;  // all instances
@@ -1472,10 +1479,10 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   ctx->d_ptrs = (InstDev**)p;
   if ((rc = dalloc(ctx->allocs, &p, sizeof(double*) * n_inst))) goto fail;
   ctx->d_dsts = (double**)p;
-  for (int i = 0; i < n_inst; ++i)  // about eight points per thread, at most ACC_BLOCKS blocks
+  for (int i = 0; i < n_inst; ++i)  // about two points per thread, at most ACC_BLOCKS blocks
     ctx->acc_blocks = std::max(ctx->acc_blocks,
-                               (int)std::min<int64_t>(ACC_BLOCKS, (ctx->inst[i].npts + 8 * ACC_THREADS - 1) /
-                                                                      (8 * ACC_THREADS)));
+                               (int)std::min<int64_t>(ACC_BLOCKS, (ctx->inst[i].npts + 2 * ACC_THREADS - 1) /
+                                                                      (2 * ACC_THREADS)));
   if ((rc = dalloc(ctx->allocs, &p, sizeof(double) * n_inst * ACC_BLOCKS))) goto fail;
   ctx->d_part = (double*)p;
   if ((rc = dalloc(ctx->allocs, &p, sizeof(double) * n_inst))) goto fail;
@@ -1594,6 +1601,7 @@ int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail) {
 
 int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
   if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
+  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   Instance& I = ctx->inst[0];
   const Group& G = ctx->groups[I.group];
   Stage st[4];
@@ -1652,6 +1660,7 @@ int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
 
 int pfch_time_kernels_events(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
   if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
+  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   Instance& I = ctx->inst[0];
   const Group& G = ctx->groups[I.group];
   int rc;
@@ -1738,6 +1747,7 @@ int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[37]) {
 
 int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]) {
   if (!ctx || !choice || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
+  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   Group& G = ctx->groups[ctx->inst[inst].group];
   TuneChoice c;
   c.row_alt = choice[0];
@@ -1762,6 +1772,7 @@ int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]) {
 int pfch_set_state(pfch_ctx* ctx, int32_t inst, const double* u_n, const double* u_nm1, double t,
                    double dt_prev, int32_t step_index) {
   if (!ctx || inst < 0 || inst >= (int)ctx->inst.size() || !u_n) return PFCH_E_INVAL;
+  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   Instance& I = ctx->inst[inst];
   if (u_nm1 && !(dt_prev > 0.0)) return PFCH_E_INVAL;
   const size_t bytes = sizeof(double) * (size_t)I.npts;
@@ -1815,18 +1826,17 @@ void lap_from_history(const Instance& I, StepSetup& ss) {
   }
 }
 
-// Tentative solve of every instance at step size dt[i]: set-up, PAGD
-// iterations, and the learned-guess fallback.  Nothing is accepted.
-int solve_all(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept = false) {
+// Set-up of every instance's tentative solve at step size dt[i] (guess,
+// averaged-Newton constants, transforms that start iteration 0); o gets the
+// guess kind and a of each instance and empty results.
+int launch_step_setups(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept) {
   const int n = (int)ctx->inst.size();
   o.status.assign(n, PFCH_OK);
   o.iters.assign(n, 0);
   o.guess.assign(n, 0);  // 0 extrapolated, 1 learned, 2 learned then extrapolated
   o.dn.assign(n, 0.0);
   o.a.assign(n, 0.0);
-  std::vector<int> active(n);
   int rc;
-  for (int i = 0; i < n; ++i) active[i] = i;
   for (auto& G : ctx->groups) {
     for (size_t k = 0; k < G.members.size(); ++k) {
       Instance& I = ctx->inst[G.members[k]];
@@ -1860,6 +1870,17 @@ int solve_all(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept = false)
       if ((rc = launch_setup(ctx, G, G.d_members, G.d_args, nm, nullptr, start_fch, lap))) return rc;
     }
   }
+  return PFCH_OK;
+}
+
+// PAGD iterations of every instance after launch_step_setups, and the
+// learned-guess fallback.  Nothing is accepted here (in-graph accepts of
+// the set-up's published destinations aside).
+int finish_solve(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept) {
+  const int n = (int)ctx->inst.size();
+  std::vector<int> active(n);
+  int rc;
+  for (int i = 0; i < n; ++i) active[i] = i;
   if ((rc = run_iterations(ctx, active))) return rc;
   // A learned guess that does not lead to convergence falls back to the
   // extrapolated guess: the step is solved again from it.
@@ -1883,6 +1904,15 @@ int solve_all(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept = false)
   if (!retry.empty() && (rc = run_iterations(ctx, retry))) return rc;
   for (int i = 0; i < n; ++i) o.status[i] = status_of(ctx->inst[i], ctx->h_recs[i], &o.iters[i], &o.dn[i]);
   return PFCH_OK;
+}
+
+// Tentative solve of every instance at step size dt[i]: set-up, PAGD
+// iterations, and the learned-guess fallback.  Nothing is accepted.
+int solve_all(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept = false) {
+  ctx->spec = false;
+  int rc;
+  if ((rc = launch_step_setups(ctx, dt, o, accept))) return rc;
+  return finish_solve(ctx, dt, o, accept);
 }
 
 // The converged iterate of instance I after solve_all.
@@ -2058,9 +2088,20 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
   SolveOut o;
   int rc;
   const bool want_mass = st && ctx->stats_detail > 0;
+  const bool same_dt = (int)ctx->last_dt.size() == n && std::equal(dt, dt + n, ctx->last_dt.begin());
   // every instance's accept runs inside the chunk graph, checked on the
   // device against the same stop record the host reads afterwards
-  if ((rc = solve_all(ctx, dt, o, true))) return rc;
+  if (ctx->spec && same_dt) {  // the set-up was enqueued by the previous call
+    ctx->spec = false;
+    o.status.assign(n, PFCH_OK);
+    o.iters.assign(n, 0);
+    o.dn.assign(n, 0.0);
+    o.guess = ctx->spec_guess;
+    o.a = ctx->spec_a;
+    if ((rc = finish_solve(ctx, dt, o, true))) return rc;
+  } else if ((rc = solve_all(ctx, dt, o, true))) {
+    return rc;
+  }
   int first_err = PFCH_OK;
   std::vector<char> take(n);
   for (int i = 0; i < n; ++i) {
@@ -2073,11 +2114,25 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
     for (int i = 0; i < n; ++i)
       if ((rc = fill_stats(ctx, o, i, want_mass, take[i], st[i]))) return rc;
   }
+  // A loop at a fixed step size: enqueue the next step's set-up now, so that
+  // it runs while control is with the caller.  Only when every instance
+  // advanced and none uses a learned guess (its network may be shared).
+  bool speculate = same_dt && first_err == PFCH_OK;
+  for (int i = 0; i < n && speculate; ++i) speculate = !(ctx->inst[i].fno && ctx->inst[i].d.guess == 1);
+  ctx->last_dt.assign(dt, dt + n);
+  if (speculate) {
+    SolveOut nx;
+    if ((rc = launch_step_setups(ctx, dt, nx, true))) return rc;
+    ctx->spec = true;
+    ctx->spec_guess = nx.guess;
+    ctx->spec_a = nx.a;
+  }
   return first_err;
 }
 
 int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_result* res) {
   if (!ctx || !ad || !res) return PFCH_E_INVAL;
+  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   if (!(ad->tol > 0.0) || !std::isfinite(ad->tol) || !(ad->dt_min > 0.0) || !std::isfinite(ad->dt_max) ||
       !(ad->dt_max >= ad->dt_min) || ad->estimator < PFCH_EST_AUTO || ad->estimator > PFCH_EST_MIDAB2 ||
       ad->reserved != 0)
@@ -2197,6 +2252,7 @@ int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_resu
 
 int pfch_rhs(pfch_ctx* ctx, int32_t inst, const double* v, double* out) {
   if (!ctx || inst < 0 || inst >= (int)ctx->inst.size() || !v || !out || v == out) return PFCH_E_INVAL;
+  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   Instance& I = ctx->inst[inst];
   if (I.nz > 1) return PFCH_E_UNSUPPORTED;
   std::vector<const double*> src{v};
@@ -2210,6 +2266,7 @@ int pfch_rhs(pfch_ctx* ctx, int32_t inst, const double* v, double* out) {
 int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const double* u_n,
                const double* u_nm1, double* x, pfch_stats* st) {
   if (!ctx || inst < 0 || inst >= (int)ctx->inst.size() || !u_n || !x) return PFCH_E_INVAL;
+  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   if (!(a > 0.0) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c)) return PFCH_E_INVAL;
   if (c != 0.0 && !u_nm1) return PFCH_E_INVAL;
   Instance& I = ctx->inst[inst];
@@ -2516,6 +2573,7 @@ int pfch_fno_prepare(pfch_fno* f, const double* u_nm1, const double* u_n, const 
 
 int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4]) {
   if (!ctx || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
+  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   Instance& I = ctx->inst[inst];
   if (!f) {
     I.fno = nullptr;

@@ -163,3 +163,51 @@ def test_kept_laplacian_setup_matches_transform_setup(scheme, shape):
     for c in ctxs:
         c.close()
     assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
+
+
+@pytest.mark.parametrize("w", [W.FCH256_BDF2, W.PFC64_MP], ids=["fch256_bdf2", "pfc64_mp"])
+def test_interleaved_calls_match_fresh_runs(w):
+    """A context stepping at a fixed step size enqueues the next step's
+    set-up at the end of each step; calls in between (pfch_rhs, which uses
+    the same workspaces, pfch_set_state, a different step size) must leave
+    the following steps exactly as a fresh context computes them."""
+    torch = _torch()
+    from paper_2204_07247_amd import pfch
+    print(f"interleaved calls {w.name}", flush=True)
+    u0 = W.initial_condition(w, seed=5)
+    ud = torch.from_numpy(u0).cuda()
+    out = torch.empty_like(ud)
+    # reference: 4 steps, then 2 steps of dt/2, from a fresh context
+    ref_ctx = pfch.Context([desc_for(w)])
+    ref_ctx.set_state(0, ud)
+    for _ in range(4):
+        assert ref_ctx.step(w.dt)[0] == pfch.PFCH_OK
+    for _ in range(2):
+        assert ref_ctx.step(0.5 * w.dt)[0] == pfch.PFCH_OK
+    ref = torch.empty_like(ud)
+    ref_ctx.get_state(0, ref)
+    ref_ctx.close()
+    ctx = pfch.Context([desc_for(w)])
+    ctx.set_state(0, ud)
+    for _ in range(3):
+        assert ctx.step(w.dt)[0] == pfch.PFCH_OK
+    r = torch.empty_like(ud)
+    ctx.rhs(0, ud, r)                    # uses the spectral workspace
+    assert ctx.step(w.dt)[0] == pfch.PFCH_OK  # same size as before the call
+    for _ in range(2):
+        assert ctx.step(0.5 * w.dt)[0] == pfch.PFCH_OK
+    ctx.get_state(0, out)
+    assert torch.equal(out, ref)
+    # set_state after steps at a fixed size: the next steps start afresh
+    ctx.set_state(0, ud)
+    again = pfch.Context([desc_for(w)])
+    again.set_state(0, ud)
+    for _ in range(2):
+        assert ctx.step(w.dt)[0] == pfch.PFCH_OK
+        assert again.step(w.dt)[0] == pfch.PFCH_OK
+    a, b = torch.empty_like(ud), torch.empty_like(ud)
+    ctx.get_state(0, a)
+    again.get_state(0, b)
+    assert torch.equal(a, b)
+    ctx.close()
+    again.close()
