@@ -206,33 +206,57 @@ __device__ __forceinline__ void betas(const InstDev* I, double& bm2, double& b0,
 // Called by every thread of one block.  The partial sums are added in index
 // order by one thread (the order the host's report uses), staged through LDS
 // in chunks so that the loads are issued by the whole block.
-__device__ __forceinline__ void finish_betas(InstDev* I) {
+// The step's averaged-Newton constants from the set-up's partial sums
+// (strided per thread, then the block's fixed reduction tree, so every block
+// gets the same value), returned to every thread of the block (all must
+// call it).
+__device__ __forceinline__ void sum_betas(const InstDev* I, double& b0, double& b2) {
   if (I->imex) {
-    if (threadIdx.x == 0) {
-      I->beta0 = I->imex_b0;
-      I->beta2 = I->imex_b2;
-    }
+    b0 = I->imex_b0;
+    b2 = I->imex_b2;
     return;
   }
-  constexpr int CH = 256;  // partial-sum pairs per chunk
-  __shared__ double buf[2 * CH];
+  __shared__ double red[16];
+  __shared__ double out[2];
   double s0 = 0.0, s1 = 0.0;
   const int np = I->nparts;
-  for (int base = 0; base < np; base += CH) {
-    const int cnt = np - base < CH ? np - base : CH;
-    for (int k = threadIdx.x; k < 2 * cnt; k += blockDim.x) buf[k] = I->part[2 * base + k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int i = 0; i < cnt; ++i) {
-        s0 += buf[2 * i];
-        s1 += buf[2 * i + 1];
-      }
-    }
-    __syncthreads();
+  for (int k = threadIdx.x; k < np; k += blockDim.x) {
+    s0 += I->part[2 * k];
+    s1 += I->part[2 * k + 1];
   }
+  const double t0 = block_sum(s0, red);
+  const double t1 = block_sum(s1, red + 8);
   if (threadIdx.x == 0) {
-    I->beta0 = fabs(s0 * I->inv_p);
-    I->beta2 = fabs(s1 * I->inv_p);
+    out[0] = fabs(t0 * I->inv_p);
+    out[1] = fabs(t1 * I->inv_p);
+  }
+  __syncthreads();
+  b0 = out[0];
+  b2 = out[1];
+  __syncthreads();
+}
+
+__device__ __forceinline__ void finish_betas(InstDev* I) {
+  double b0, b2;
+  sum_betas(I, b0, b2);
+  if (threadIdx.x == 0) {
+    I->beta0 = b0;
+    I->beta2 = b2;
+  }
+}
+
+// First column iteration of a step whose column set-up was folded in: the
+// constants come from the partial sums (block 0 also stores them for the
+// later iterations).  Uniform per block: every thread calls it.
+__device__ __forceinline__ void fold_betas(const InstDev* I, bool blk0, double& b0, double& b2) {
+  double f0, f2;
+  sum_betas(I, f0, f2);
+  b0 = f0;
+  if (I->model == MODEL_FCH) b2 = f2;
+  if (blk0 && threadIdx.x == 0) {
+    InstDev* W = const_cast<InstDev*>(I);
+    W->beta0 = f0;
+    W->beta2 = f2;
   }
 }
 
@@ -347,6 +371,10 @@ __global__ __launch_bounds__(512) void k_col_iter(const InstDev* const* __restri
 
     double bm2, b0, b2, b4;
     betas(I, bm2, b0, b2, b4);
+    // the step's first iteration without a column set-up: g^ and the
+    // averaged-Newton constants are formed here
+    const bool first = *I->iter_base + l == 0 && I->fold_g;
+    if (first) fold_betas(I, blk0, b0, b2);
     const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
     const double inv_p = I->inv_p;
     const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
@@ -378,9 +406,9 @@ __global__ __launch_bounds__(512) void k_col_iter(const InstDev* const* __restri
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
 #pragma unroll
-      for (int m = 0; m < RM; ++m)  // prefetch the next field, then g^
+      for (int m = 0; m < RM; ++m)  // prefetch the next field, then g^ (first: g, transformed below)
         nxt[m] = f + 1 < NF ? gload(S + (f + 1) * fs + sidx(rows, t + m * T, kp))
-                            : gload(gp(I->ghat) + sidx(rows, t + m * T, kp));
+                            : gload(gp(first ? I->G : I->ghat) + sidx(rows, t + m * T, kp));
       fft<PY, false>(v, lds, tw, t);
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
@@ -395,6 +423,11 @@ __global__ __launch_bounds__(512) void k_col_iter(const InstDev* const* __restri
         });
 #pragma unroll
       for (int m = 0; m < RM; ++m) v[m] = nxt[m];
+    }
+    if (first) {  // g^ for this and the step's later iterations
+      fft<PY, false>(v, lds, tw, t);
+#pragma unroll
+      for (int m = 0; m < RM; ++m) gstore(gp(I->ghat) + sidx(rows, t + m * T, kp), v[m]);
     }
     // g^ enters with the same coefficient 1/M on both logical columns.
 #pragma unroll
@@ -838,6 +871,10 @@ __global__ __launch_bounds__(512) void k_col_iter_fp(const InstDev* const* __res
   load_twiddles<PY>(tw, I->tw_y, t);
   double bm2, b0, b2, b4;
   betas(I, bm2, b0, b2, b4);
+  // the step's first iteration without a column set-up: g^ and the
+  // averaged-Newton constants are formed here
+  const bool first = j == 0 && I->fold_g;
+  if (first) fold_betas(I, blk0, b0, b2);
   const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
   const double inv_p = I->inv_p;
   const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
@@ -863,7 +900,16 @@ __global__ __launch_bounds__(512) void k_col_iter_fp(const InstDev* const* __res
   c2 v[RM], acc[RM], gh[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) v[m] = gload(S + role * fs + sidx(rows, t + m * T, kp));
-  if (role == NT - 1) {
+  if (first) {  // g^ = y-transform of the set-up's g rows (every team transforms; the last keeps it)
+#pragma unroll
+    for (int m = 0; m < RM; ++m)
+      gh[m] = role == NT - 1 ? gload(gp(I->G) + sidx(rows, t + m * T, kp)) : c2{0.0, 0.0};
+    fft<PY, false>(gh, lds, tw, t);
+    if (role == NT - 1) {
+#pragma unroll
+      for (int m = 0; m < RM; ++m) gstore(gp(I->ghat) + sidx(rows, t + m * T, kp), gh[m]);
+    }
+  } else if (role == NT - 1) {
 #pragma unroll
     for (int m = 0; m < RM; ++m) gh[m] = gload(gp(I->ghat) + sidx(rows, t + m * T, kp));
   }
@@ -957,6 +1003,7 @@ struct StepArgs {
   const double* lun;
   const double* lunm1;
   double* acc_ldst;
+  int32_t fold;        // no column set-up: the first column iteration does its part
 };
 
 // Up to STEP_ARGS_INLINE instances' arguments travel by value with the
@@ -998,6 +1045,7 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* const* __restrict__ 
     I->acc_dst = sa.acc_dst;
     I->acc_ldst = sa.acc_ldst;
     I->lap_hist = sa.lun != nullptr;
+    I->fold_g = sa.fold;
     *I->iter_base = 0;
     *I->flags = 0;
     I->rec->stop_iter = -1;
@@ -1093,6 +1141,7 @@ __global__ __launch_bounds__(256) void k_row_setup_lap(InstDev* const* __restric
     I->acc_dst = sa.acc_dst;
     I->acc_ldst = sa.acc_ldst;
     I->lap_hist = 1;
+    I->fold_g = sa.fold;
     *I->iter_base = 0;
     *I->flags = 0;
     I->rec->stop_iter = -1;
@@ -1188,6 +1237,7 @@ __global__ __launch_bounds__(256) void k_row_setup_lap_fp(InstDev* const* __rest
     I->acc_dst = sa.acc_dst;
     I->acc_ldst = sa.acc_ldst;
     I->lap_hist = 1;
+    I->fold_g = sa.fold;
     *I->iter_base = 0;
     *I->flags = 0;
     I->rec->stop_iter = -1;

@@ -610,7 +610,7 @@ struct StepSetup {
 };
 
 StepArgs to_args(const StepSetup& ss) {
-  StepArgs sa;
+  StepArgs sa{};
   sa.un = ss.un;
   sa.unm1 = ss.unm1 ? ss.unm1 : ss.un;
   sa.xin = ss.xin;
@@ -659,13 +659,24 @@ StepSetup step_setup_for(const Instance& I, double dt) {
 // start_fch: some instance takes Delta x0 from transforms (k_row_setup,
 // k_row_start_fch); lap: some instance takes it from kept Laplacians
 // (k_row_setup_lap).  Each row set-up kernel skips the other's instances.
+// 2D groups without the transform path of the FCH set-up (PFC, and FCH
+// from kept Laplacians) launch no column set-up: the step's first column
+// iteration transforms g and sums the averaged-Newton partials itself.
+bool setup_folds(const Group& G, bool start_fch) { return G.ndim == 2 && (G.model != PFCH_FCH || !start_fch); }
+
+// A device array `args` must already carry fold = setup_folds(G, start_fch).
+// allow_fold = false keeps the column set-up (kernel timing: the iteration
+// kernels then run without the folded set-up work).
 int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, unsigned nm,
-                 const StepArgsInline* inl = nullptr, bool start_fch = true, bool lap = false) {
+                 const StepArgsInline* inl = nullptr, bool start_fch = true, bool lap = false,
+                 bool allow_fold = true) {
   int rc;
   int rbpi = G.srow_bpi, cbpi = G.scol_bpi;
+  const bool fold = allow_fold && setup_folds(G, start_fch);
   StepArgsInline il{};
   if (inl) {
     il = *inl;
+    for (unsigned k = 0; k < nm; ++k) il.a[k].fold = fold ? 1 : 0;
     args = nullptr;
   }
   if (start_fch || G.model != PFCH_FCH) {
@@ -689,7 +700,7 @@ int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, u
     if ((rc = launch(G.z3.setup, dim3(nm * zbpi), G.z3_block, G.z3_lds, b, ctx->stream))) return rc;
     return PFCH_OK;
   }
-  {
+  if (!fold) {
     void* a[] = {&grp, &cbpi};
     if ((rc = launch(G.cs.setup, dim3(nm * cbpi), G.scol_block, G.scol_lds, a, ctx->stream))) return rc;
   }
@@ -700,11 +711,11 @@ int launch_setup(pfch_ctx* ctx, const Group& G, InstDev** grp, StepArgs* args, u
   return PFCH_OK;
 }
 
-int launch_setup_solo(pfch_ctx* ctx, Instance& I, const StepSetup& ss) {
+int launch_setup_solo(pfch_ctx* ctx, Instance& I, const StepSetup& ss, bool allow_fold = true) {
   StepArgsInline inl{};
   inl.a[0] = to_args(ss);
   return launch_setup(ctx, ctx->groups[I.group], I.d_solo, nullptr, 1, &inl, ss.lun == nullptr,
-                      ss.lun != nullptr);
+                      ss.lun != nullptr, allow_fold);
 }
 
 int launch_accept(pfch_ctx* ctx, AccDsts inl, double** dsts, double* part, int check) {
@@ -1052,7 +1063,7 @@ int tune_group3(pfch_ctx* ctx, Group& G, TuneChoice& best) {
   HIPCHK(hipMemsetAsync(I.U[1], 0, bytes, ctx->stream));
   I.has_prev = false;
   int rc;
-  if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, 1e-3)))) return rc;
+  if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, 1e-3), false))) return rc;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1165,7 +1176,7 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
   HIPCHK(hipMemsetAsync(I.U[1], 0, bytes, ctx->stream));
   I.has_prev = false;
   int rc;
-  if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, 1e-3)))) return rc;
+  if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, 1e-3), false))) return rc;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1616,7 +1627,7 @@ int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
   int rc = PFCH_OK;
   InstDev** grp = I.d_solo;
   for (int r = 0; r < reps && rc == PFCH_OK; ++r) {
-    if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, dt)))) break;
+    if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, dt), false))) break;
     for (int j = 0; j < nit && rc == PFCH_OK; ++j)
       for (int k = 0; k < ns; ++k) {
         int bpi = st[k].bpi, lv = j, total = bpi;
@@ -1664,7 +1675,7 @@ int pfch_time_kernels_events(pfch_ctx* ctx, double dt, int32_t reps, double out[
   Instance& I = ctx->inst[0];
   const Group& G = ctx->groups[I.group];
   int rc;
-  if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, dt)))) return rc;
+  if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, dt), false))) return rc;
   Stage st[4];
   const int ns = iter_stages(G, st);
   hipEvent_t e[5];
@@ -1865,6 +1876,7 @@ int launch_step_setups(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept
       for (unsigned k = 0; k < nm; ++k) inl.a[k] = G.h_args[k];
       if ((rc = launch_setup(ctx, G, G.d_members, nullptr, nm, &inl, start_fch, lap))) return rc;
     } else {
+      for (unsigned k = 0; k < nm; ++k) G.h_args[k].fold = setup_folds(G, start_fch) ? 1 : 0;
       HIPCHK(hipMemcpyAsync(G.d_args, G.h_args, sizeof(StepArgs) * nm, hipMemcpyHostToDevice,
                             ctx->stream));
       if ((rc = launch_setup(ctx, G, G.d_members, G.d_args, nm, nullptr, start_fch, lap))) return rc;

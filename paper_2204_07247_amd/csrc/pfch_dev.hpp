@@ -44,6 +44,8 @@ struct InstDev {
   double* acc_ldst;        // FCH: where the Laplacian of the accepted solution goes
   double* acc_lnow;        // acc_ldst like acc_now
   int32_t lap_hist;        // FCH: this step's set-up took Delta x0 from the kept Laplacians
+  int32_t fold_g;          // 2D: no column set-up ran; the step's first column iteration
+                           // transforms g and sums the averaged-Newton partials itself
   // state buffers
   double* X[3];            // iterate ring x_j at X[j % 3]
   double* DX[3];           // FCH: Laplacian of the iterate, same ring
