@@ -1,6 +1,7 @@
 """Parity at the bench sizes, in the launch configuration the bench uses
 (autotuned plans, the same context set-up): the first step of PFC 1024^2
-(implicit midpoint) and of FCH 2048^2 (backward Euler) against the oracle,
+(implicit midpoint) and of FCH 1024^2 and 2048^2 (backward Euler) against
+the oracle,
 field by field; then properties that hold at any size over further steps
 (convergence to the tolerance, exact mass; energy decrease for BDF2)."""
 import numpy as np
@@ -24,7 +25,7 @@ def _ctx(w):
     return ctx, u0
 
 
-@pytest.mark.parametrize("name", ["pfc1024", "fch2048"])
+@pytest.mark.parametrize("name", ["pfc1024", "fch1024", "fch2048"])
 def test_first_step_matches_oracle_at_full_size(name):
     import torch
     from paper_2204_07247_amd import pfch
@@ -41,7 +42,7 @@ def test_first_step_matches_oracle_at_full_size(name):
     assert rel_l2(out.cpu().numpy(), ref) <= 1e-9
 
 
-@pytest.mark.parametrize("name", ["pfc1024", "fch2048"])
+@pytest.mark.parametrize("name", ["pfc1024", "fch1024", "fch2048"])
 def test_properties_over_steps_at_full_size(name):
     import torch
     from paper_2204_07247_amd import pfch
