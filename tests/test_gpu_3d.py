@@ -22,6 +22,8 @@ SHAPES = [  # (Nz, Ny, Nx)
     (192, 8, 16),
     (8, 192, 16),
     (8, 8, 192),
+    (256, 8, 8),      # longest z pass
+    (8, 256, 8),      # longest y pass
 ]
 
 
