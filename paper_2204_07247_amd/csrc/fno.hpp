@@ -35,7 +35,17 @@ struct GemmP {
   float* C;
   long long sCz, sCm, sCn;
   int accumulate;  // 1: C += A B
+  // real C only: C[m][n] += bias[m] after the product, and vout (laid out
+  // like C) = gelu(C) (act = 1) or C (act = 0); null bias: no epilogue
+  const float* bias = nullptr;
+  float* vout = nullptr;
+  int act = 0;
 };
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
 
 struct f2 {
   float x, y;
@@ -140,29 +150,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmP p) {
           C[2 * o + 1] = acc[i][j].y;
         }
       } else {
-        if (p.accumulate)
-          C[o] += acc[i][j].x;
-        else
-          C[o] = acc[i][j].x;
+        float val = p.accumulate ? C[o] + acc[i][j].x : acc[i][j].x;
+        if (p.bias) {
+          val += p.bias[m];
+          if (p.vout) p.vout[z * p.sCz + o] = p.act ? gelu_f(val) : val;
+        }
+        C[o] = val;
       }
     }
   }
-}
-
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad_f(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
-}
-
-// z[b][c][p] += bias[c]; v = gelu(z) (or z).  One thread per element.
-__global__ void k_bias_act(float* __restrict__ z, float* __restrict__ v, const float* __restrict__ bias,
-                           int C, long long P, long long n, int gelu) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = (int)((i / P) % C);
-  const float zz = z[i] + bias[c];
-  z[i] = zz;
-  if (v) v[i] = gelu ? gelu_f(zz) : zz;
 }
 
 __global__ void k_gelu_bwd(const float* __restrict__ dv, const float* __restrict__ z, float* __restrict__ dz,
@@ -405,6 +401,8 @@ inline hipError_t gemm_launch(const GemmP& p, long long Z, hipStream_t s) {
     q.M = (int)std::min<long long>(CHUNK, p.M - m0);
     q.A = p.A + (AC ? 2 : 1) * m0 * p.sAm;
     q.C = p.C + (CC ? 2 : 1) * m0 * p.sCm;
+    if (p.bias) q.bias = p.bias + m0;
+    if (p.vout) q.vout = p.vout + m0 * p.sCm;
     const long long gy = (q.M + BM - 1) / BM;
     hipLaunchKernelGGL((k_gemm<AC, BC, CJA, CJB, CC, BM, BN>), dim3((unsigned)gx, (unsigned)gy, (unsigned)Z),
                        dim3(256), 0, s, q);
@@ -450,11 +448,10 @@ inline hipError_t fno_forward(Fno& F, const float* x, int B, hipStream_t s) {
   const long long M2 = 2 * M * M;  // modes of one (b, c, z) after the y transform
   const bool d3 = F.ndim == 3;
   const float* th = F.theta;
-  // lift
-  FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(
-      gp_make(W, P, 2, th + F.oP, 0, 1, W, x, 2 * P, P, 1, F.v[0], W * P, P, 1, 0), B, s)));
-  hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * W * P)), dim3(256), 0, s, F.v[0], (float*)nullptr,
-                     th + F.opb, (int)W, P, B * W * P, 0);
+  // lift, with its bias in the product's epilogue
+  GemmP lift = gp_make(W, P, 2, th + F.oP, 0, 1, W, x, 2 * P, P, 1, F.v[0], W * P, P, 1, 0);
+  lift.bias = th + F.opb;
+  FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(lift, B, s)));
   for (int l = 0; l < F.L; ++l) {
     const float* vin = F.v[l];
     float* yk = d3 ? F.S2 : F.vh[l];  // y-transform output
@@ -482,11 +479,13 @@ inline hipError_t fno_forward(Fno& F, const float* x, int B, hipStream_t s) {
     // z = Re(S1 Gx) over x
     FNO_CHK((gemm_launch<true, true, false, false, false, 32, 64>(
         gp_make(B * W * nz * ny, nx, M, F.S1, 0, M, 1, F.Gx, 0, nx, 1, F.z[l], 0, nx, 1, 0), 1, s)));
-    // z += W_l^T v
-    FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(
-        gp_make(W, P, W, th + F.oW[l], 0, 1, W, vin, W * P, P, 1, F.z[l], W * P, P, 1, 1), B, s)));
-    hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * W * P)), dim3(256), 0, s, F.z[l], F.v[l + 1],
-                       th + F.ob[l], (int)W, P, B * W * P, l < F.L - 1 ? 1 : 0);
+    // z += W_l^T v + b_l and v_{l+1} = gelu(z) (z for the last layer), in
+    // the product's epilogue
+    GemmP cv = gp_make(W, P, W, th + F.oW[l], 0, 1, W, vin, W * P, P, 1, F.z[l], W * P, P, 1, 1);
+    cv.bias = th + F.ob[l];
+    cv.vout = F.v[l + 1];
+    cv.act = l < F.L - 1 ? 1 : 0;
+    FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(cv, B, s)));
   }
   hipLaunchKernelGGL(k_project, dim3(blocks_for(B * P)), dim3(256), 0, s, (const float*)F.v[F.L], th + F.oQ,
                      th + F.oqb, F.y, (int)W, P, B * P);
