@@ -57,6 +57,21 @@ __device__ __forceinline__ GroupPos group_pos(const InstDev* const* __restrict__
   return GroupPos{grp[gi], (int)blockIdx.x - gi * bpi};
 }
 
+// The instance record copied into LDS at kernel entry: all of its fields in
+// one round trip of vector loads (which see what earlier kernels of the
+// same graph wrote), after which every field read is an LDS read rather
+// than a dependent global load.  Every thread of the block calls it; the
+// record is read-only here (writes go to the global record).
+__device__ __forceinline__ const InstDev* stage_record(const InstDev* g, InstDev* rec) {
+  static_assert(sizeof(InstDev) % 8 == 0, "the record is staged in 8-byte words");
+  constexpr int W = (int)(sizeof(InstDev) / 8);
+  const GLB uint64_t* src = gp(reinterpret_cast<const uint64_t*>(g));
+  uint64_t* dst = reinterpret_cast<uint64_t*>(rec);
+  for (int w = threadIdx.x; w < W; w += blockDim.x) dst[w] = src[w];
+  __syncthreads();
+  return rec;
+}
+
 // True when iteration j must not run: the cap is reached, or iteration j-1
 // met the tolerance or produced a non-finite norm.  Iterations that were
 // skipped leave their norm slot at 0, which also reads as "stopped".
@@ -247,16 +262,17 @@ __device__ __forceinline__ void finish_betas(InstDev* I) {
 
 // First column iteration of a step whose column set-up was folded in: the
 // constants come from the partial sums (block 0 also stores them for the
-// later iterations).  Uniform per block: every thread calls it.
-__device__ __forceinline__ void fold_betas(const InstDev* I, bool blk0, double& b0, double& b2) {
+// later iterations in `home`, the instance's global record).  Uniform per
+// block: every thread calls it.
+__device__ __forceinline__ void fold_betas(const InstDev* I, InstDev* home, bool blk0, double& b0,
+                                           double& b2) {
   double f0, f2;
   sum_betas(I, f0, f2);
   b0 = f0;
   if (I->model == MODEL_FCH) b2 = f2;
   if (blk0 && threadIdx.x == 0) {
-    InstDev* W = const_cast<InstDev*>(I);
-    W->beta0 = f0;
-    W->beta2 = f2;
+    home->beta0 = f0;
+    home->beta2 = f2;
   }
 }
 
@@ -374,7 +390,7 @@ __global__ __launch_bounds__(512) void k_col_iter(const InstDev* const* __restri
     // the step's first iteration without a column set-up: g^ and the
     // averaged-Newton constants are formed here
     const bool first = *I->iter_base + l == 0 && I->fold_g;
-    if (first) fold_betas(I, blk0, b0, b2);
+    if (first) fold_betas(I, const_cast<InstDev*>(I), blk0, b0, b2);
     const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
     const double inv_p = I->inv_p;
     const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
@@ -572,8 +588,9 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
                                                   int l, int /*total*/) {
   extern __shared__ c2 smem[];
   __shared__ uint64_t red[4];
+  __shared__ InstDev rec;
   const GroupPos gpos = group_pos(grp, bpi);
-  const InstDev* __restrict__ I = gpos.I;
+  const InstDev* __restrict__ I = stage_record(gpos.I, &rec);
   const int j = *I->iter_base + l;
   if (stopped_before(I, j)) return;
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
@@ -729,8 +746,9 @@ __global__ __launch_bounds__(256) void k_row_iter_fp(const InstDev* const* __res
                                                      int l, int /*total*/) {
   extern __shared__ c2 smem[];
   __shared__ uint64_t red[4];
+  __shared__ InstDev rec;
   const GroupPos gpos = group_pos(grp, bpi);
-  const InstDev* __restrict__ I = gpos.I;
+  const InstDev* __restrict__ I = stage_record(gpos.I, &rec);
   const int j = *I->iter_base + l;
   if (stopped_before(I, j)) return;
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX, NT = fp_teams<MODEL>();
@@ -840,8 +858,9 @@ template <class PY, int MODEL>
 __global__ __launch_bounds__(512) void k_col_iter_fp(const InstDev* const* __restrict__ grp, int bpi, int l,
                                                      int /*total*/) {
   extern __shared__ c2 smem[];
+  __shared__ InstDev rec;
   const GroupPos gpos = group_pos(grp, bpi);
-  const InstDev* __restrict__ I = gpos.I;
+  const InstDev* __restrict__ I = stage_record(gpos.I, &rec);
   const int j = *I->iter_base + l;
   if (stopped_before(I, j)) return;
   constexpr int N = PY::N, T = PY::T, RM = PY::RMAX, NT = fp_teams<MODEL>();
@@ -874,7 +893,7 @@ __global__ __launch_bounds__(512) void k_col_iter_fp(const InstDev* const* __res
   // the step's first iteration without a column set-up: g^ and the
   // averaged-Newton constants are formed here
   const bool first = j == 0 && I->fold_g;
-  if (first) fold_betas(I, blk0, b0, b2);
+  if (first) fold_betas(I, const_cast<InstDev*>(gpos.I), blk0, b0, b2);
   const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
   const double inv_p = I->inv_p;
   const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);

@@ -103,8 +103,9 @@ template <class PY, bool INV>
 __global__ __launch_bounds__(512) void k_y3_iter(const InstDev* const* __restrict__ grp, int bpi, int l,
                                                  int /*total*/) {
   extern __shared__ c2 smem[];
+  __shared__ InstDev rec;
   const GroupPos gpos = group_pos(grp, bpi);
-  const InstDev* __restrict__ I = gpos.I;
+  const InstDev* __restrict__ I = stage_record(gpos.I, &rec);
   const int j = *I->iter_base + l;
   if (stopped_before(I, j)) return;
   constexpr int N = PY::N, T = PY::T, RM = PY::RMAX;
@@ -205,8 +206,9 @@ template <class PZ>
 __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restrict__ grp, int bpi, int l,
                                                  int /*total*/) {
   extern __shared__ c2 smem[];
+  __shared__ InstDev rec;
   const GroupPos gpos = group_pos(grp, bpi);
-  const InstDev* __restrict__ I = gpos.I;
+  const InstDev* __restrict__ I = stage_record(gpos.I, &rec);
   const int j = *I->iter_base + l;
   if (stopped_before(I, j)) return;
   constexpr int N = PZ::N, T = PZ::T, RM = PZ::RMAX;
