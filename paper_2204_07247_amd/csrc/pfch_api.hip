@@ -36,39 +36,70 @@ inline bool scheme_imex(int s) { return s == PFCH_LBDF2 || s == PFCH_LMP; }
 // Small kernels: end of a chunk of iterations, accept, mass reduction.
 // ---------------------------------------------------------------------------
 // One block: every instance's stop record for the chunk just run, mirrored
-// into pinned host memory, then the host-visible chunk counter.
-__global__ __launch_bounds__(256) void k_chunk_end(InstDev* const* insts, int n, int K,
-                                                   uint32_t* __restrict__ seq_dev,
-                                                   uint32_t* __restrict__ seq_host) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+// into pinned host memory, then the host-visible chunk counter.  A group of
+// S lanes (a power of two up to 64, S >= K where the block allows) scans an
+// instance's chunk: each lane tests one iteration's norm and a ballot picks
+// the first that stops the solve, so the norms are read in parallel rather
+// than one dependent load per iteration.
+__device__ __forceinline__ int chunk_group_size(int K, int n) {
+  int S = 1;
+  while (S < K && S < 64) S *= 2;
+  while (S > 1 && (long long)S * n > 1024) S /= 2;
+  return S;
+}
+
+__global__ __launch_bounds__(1024) void k_chunk_end(InstDev* const* insts, int n, int K,
+                                                    uint32_t* __restrict__ seq_dev,
+                                                    uint32_t* __restrict__ seq_host) {
+  const int S = chunk_group_size(K, n);
+  const int g = threadIdx.x / S, r = threadIdx.x % S, ngroups = blockDim.x / S;
+  const int wl = threadIdx.x & 63, gbase = wl - r;  // group's first lane in the wave
+  const uint64_t gmask = S == 64 ? ~0ull : ((1ull << S) - 1) << gbase;
+  for (int i = g; i < n; i += ngroups) {
     InstDev* I = insts[i];
     StopRec* rec = I->rec;
     const int base = *I->iter_base;
     const int before = rec->stop_iter;
-    if (rec->stop_iter < 0 && base < I->max_iter + 1) {
-      for (int jj = base; jj < base + K; ++jj) {
-        if (jj >= I->max_iter) {
-          rec->stop_iter = I->max_iter;
-          rec->norm_bits = I->norms[I->max_iter - 1];
-          break;
+    const int maxit = I->max_iter;
+    int stop = -1;
+    uint64_t nb = 0;
+    if (before < 0 && base < maxit + 1) {
+      for (int j0 = base; j0 < base + K && stop < 0; j0 += S) {
+        const int jj = j0 + r;
+        bool hit = false;
+        uint64_t b = 0;
+        if (jj < base + K) {
+          if (jj >= maxit) {
+            hit = true;  // the cap: stop at max_iter with the last norm
+            b = I->norms[maxit - 1];
+          } else {
+            b = I->norms[jj];
+            hit = b < I->tol_bits || b >= INF_BITS;
+          }
         }
-        const uint64_t b = I->norms[jj];
-        if (b < I->tol_bits || b >= INF_BITS) {
-          rec->stop_iter = jj;
-          rec->norm_bits = b;
-          break;
+        const uint64_t m = (uint64_t)__ballot(hit) & gmask;
+        if (m) {
+          const int f = __ffsll((long long)m) - 1;  // lane in the wave
+          stop = min(j0 + (f - gbase), maxit);
+          nb = __shfl(b, f);
         }
       }
     }
-    rec->flags |= *I->flags;
-    const bool stop = rec->stop_iter >= 0 || (rec->flags & FLAG_PRECOND);
-    *I->iter_base = stop ? I->max_iter + 1 : base + K;
-    // the accept that follows in the graph copies a solution once, in the
-    // chunk that ended its solve
-    const bool ended = before < 0 && rec->stop_iter >= 0;
-    I->acc_now = ended ? I->acc_dst : nullptr;
-    I->acc_lnow = ended ? I->acc_ldst : nullptr;
-    *I->rec_host = *rec;  // the host polls this copy
+    if (r == 0) {
+      if (stop >= 0) {
+        rec->stop_iter = stop;
+        rec->norm_bits = nb;
+      }
+      rec->flags |= *I->flags;
+      const bool stopped = rec->stop_iter >= 0 || (rec->flags & FLAG_PRECOND);
+      *I->iter_base = stopped ? maxit + 1 : base + K;
+      // the accept that follows in the graph copies a solution once, in the
+      // chunk that ended its solve
+      const bool ended = before < 0 && rec->stop_iter >= 0;
+      I->acc_now = ended ? I->acc_dst : nullptr;
+      I->acc_lnow = ended ? I->acc_ldst : nullptr;
+      *I->rec_host = *rec;  // the host polls this copy
+    }
   }
   __threadfence_system();
   __syncthreads();
@@ -78,6 +109,16 @@ __global__ __launch_bounds__(256) void k_chunk_end(InstDev* const* insts, int n,
     *seq_host = v;
     __threadfence_system();
   }
+}
+
+// Threads of the chunk-end block: one group of S lanes per instance (up to
+// 1024 threads; more instances loop), whole waves.
+inline int chunk_end_threads(int K, int n) {
+  int S = 1;
+  while (S < K && S < 64) S *= 2;
+  while (S > 1 && (long long)S * n > 1024) S /= 2;
+  const long long t = std::min<long long>(1024, (long long)S * n);
+  return (int)((t + 63) / 64 * 64);
 }
 
 constexpr int ACC_BLOCKS = 1024, ACC_THREADS = 256;
@@ -556,7 +597,7 @@ int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
     void* args[] = {&ptrs, &n, &k, &dseq, &hseq};
     p.func = (void*)&k_chunk_end;
     p.gridDim = dim3(1);
-    p.blockDim = dim3(256);
+    p.blockDim = dim3(chunk_end_threads(k, n));
     p.sharedMemBytes = 0;
     p.kernelParams = args;
     hipGraphNode_t node;
