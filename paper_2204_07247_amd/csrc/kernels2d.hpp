@@ -67,7 +67,11 @@ __device__ __forceinline__ const InstDev* stage_record(const InstDev* g, InstDev
   constexpr int W = (int)(sizeof(InstDev) / 8);
   const GLB uint64_t* src = gp(reinterpret_cast<const uint64_t*>(g));
   uint64_t* dst = reinterpret_cast<uint64_t*>(rec);
-  for (int w = threadIdx.x; w < W; w += blockDim.x) dst[w] = src[w];
+  // unconditional (threads past the record repeat its last word), so that
+  // the record's load is not held behind a branch on the block size
+  const int w0 = min((int)threadIdx.x, W - 1);
+  dst[w0] = src[w0];
+  for (int w = threadIdx.x + blockDim.x; w < W; w += blockDim.x) dst[w] = src[w];
   __syncthreads();
   return rec;
 }
