@@ -183,7 +183,10 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ pa
   double s = 0.0;
   for (int k = threadIdx.x; k < nb; k += blockDim.x) s += part[(int64_t)i * nb + k];
   const double b = block_sum(s, red);
-  if (threadIdx.x == 0) out[i] = b * scale[i];
+  if (threadIdx.x == 0) {
+    out[i] = b * scale[i];
+    __threadfence_system();  // out may be pinned host memory
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -289,8 +292,8 @@ struct pfch_ctx {
   double** h_dsts = nullptr;   // pinned
   double* d_part = nullptr;    // [n][ACC_BLOCKS]
   double* d_scale = nullptr;   // 1/P per instance
-  double* d_mass = nullptr;
-  double* h_mass = nullptr;    // pinned
+  double* d_mass = nullptr;    // device address of h_mass
+  double* h_mass = nullptr;    // pinned, coherent
   EstArgs* d_est = nullptr;    // adaptive error estimate, per instance
   EstArgs* h_est = nullptr;    // pinned
   double* d_est_part = nullptr;  // [n][2][EST_BLOCKS]
@@ -1539,8 +1542,6 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   ctx->d_part = (double*)p;
   if ((rc = dalloc(ctx->allocs, &p, sizeof(double) * n_inst))) goto fail;
   ctx->d_scale = (double*)p;
-  if ((rc = dalloc(ctx->allocs, &p, sizeof(double) * n_inst))) goto fail;
-  ctx->d_mass = (double*)p;
   if ((rc = halloc(ctx->host_allocs, &p, sizeof(StopRec) * n_inst, true))) goto fail;
   ctx->h_recs = (StopRec*)p;
   for (int i = 0; i < n_inst; ++i) ctx->h_recs[i].stop_iter = -1;  // not stopped until a chunk says so
@@ -1557,8 +1558,13 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   }
   if ((rc = halloc(ctx->host_allocs, &p, sizeof(double*) * n_inst))) goto fail;
   ctx->h_dsts = (double**)p;
-  if ((rc = halloc(ctx->host_allocs, &p, sizeof(double) * n_inst))) goto fail;
+  // coherent: the mass kernel writes the pinned buffer directly
+  if ((rc = halloc(ctx->host_allocs, &p, sizeof(double) * n_inst, true))) goto fail;
   ctx->h_mass = (double*)p;
+  if (hipHostGetDevicePointer((void**)&ctx->d_mass, ctx->h_mass, 0) != hipSuccess) {
+    rc = PFCH_E_HIP;
+    goto fail;
+  }
   if ((rc = dalloc(ctx->allocs, &p, sizeof(EstArgs) * n_inst))) goto fail;
   ctx->d_est = (EstArgs*)p;
   if ((rc = halloc(ctx->host_allocs, &p, sizeof(EstArgs) * n_inst))) goto fail;
@@ -2003,8 +2009,9 @@ int accept_solutions(pfch_ctx* ctx, const std::vector<char>& take, const double*
     const double* scale = ctx->d_scale;
     double* o2 = ctx->d_mass;
     void* a[] = {&part, &nb, &nn, &scale, &o2};
+    // written straight into the pinned host buffer (read after the stream
+    // is synchronised)
     if ((rc = launch((const void*)&k_sum_parts, dim3(n), dim3(256), 0, a, ctx->stream))) return rc;
-    HIPCHK(hipMemcpyAsync(ctx->h_mass, ctx->d_mass, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
   }
   for (int i = 0; i < n; ++i) {
     if (!take[i]) continue;
