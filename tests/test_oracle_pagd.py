@@ -57,11 +57,15 @@ def test_gradient_identity_with_step_residual():
     assert np.allclose(P.gradient(v), g.inv_neg_lap(g.proj0(F)) / P.M, atol=1e-10)
 
 
+def _sweep():
+    with open(os.path.join(GOLDEN, "friction_sweep.json")) as fh:
+        return json.load(fh)
+
+
 def test_friction_sweep_from_printed_settings():
     """eta = sqrt of five equally spaced values in [0.1, 2], s = 0.9 (Table
     tab:setting-benchmark): lambda decreases through 0 where eta sqrt(s) = 1."""
-    with open(os.path.join(GOLDEN, "friction_sweep.json")) as fh:
-        fx = json.load(fh)
+    fx = _sweep()
     etas = [np.sqrt(v) for v in fx["eta_squared"]]
     lam = pagd.friction_lambdas(fx["s"], etas)
     assert np.allclose(fx["eta_squared"], np.linspace(0.1, 2.0, 5))
@@ -71,18 +75,33 @@ def test_friction_sweep_from_printed_settings():
         assert (l > 0) == (e * np.sqrt(fx["s"]) < 1)
 
 
+def test_friction_lambdas_match_hand_worked_values():
+    """lambda_j of Alg. 2 at the printed sweep and s = 0.9 against values
+    worked out by hand (7/13 and (3 sqrt5 - 7)/2 exactly; the rest in decimal
+    arithmetic), so that eta s in place of eta sqrt(s), a swapped sign or a
+    dropped term fails."""
+    fx = _sweep()
+    lam = pagd.friction_lambdas(fx["s"], [np.sqrt(v) for v in fx["eta_squared"]])
+    assert abs(fx["lambda"][0] - 7.0 / 13.0) <= 1e-16
+    assert abs(fx["lambda"][4] - (3.0 * np.sqrt(5.0) - 7.0) / 2.0) <= 1e-15
+    for got, want in zip(lam, fx["lambda"]):
+        assert abs(got - want) <= 2e-16, (got, want)
+
+
 @pytest.mark.parametrize("accelerated", [True, False])
 def test_pagd_iterates_on_a_diagonal_quadratic(accelerated):
     """On G(x) = sum h_k x_k^2 / 2 - b_k x_k with diagonal L, each component's
     error obeys e_{i+1} = (1 - s h/l)((1 + lambda_i) e_i - lambda_i e_{i-1}),
-    e_{-1} = e_0 (Alg. 2 with x_{-1} = x_0); lambda = 0 gives PGD (Alg. 1)."""
+    e_{-1} = e_0 (Alg. 2 with x_{-1} = x_0); lambda = 0 gives PGD (Alg. 1).
+    The lambda_i come from the hand-worked table, not from the oracle."""
     rng = np.random.default_rng(0)
     h = rng.uniform(0.5, 3.0, 12)
     ell = rng.uniform(0.8, 2.5, 12)
     bvec = rng.standard_normal(12)
     xstar = bvec / h
     s = 0.9
-    etas = [np.sqrt(v) for v in (0.1, 0.575, 1.05, 1.525, 2.0)]
+    fx = _sweep()
+    etas = [np.sqrt(v) for v in fx["eta_squared"]]
     x0 = rng.standard_normal(12)
     hist = []
     iters = 23
@@ -92,7 +111,7 @@ def test_pagd_iterates_on_a_diagonal_quadratic(accelerated):
     e_prev = e = x0 - xstar
     q = 1.0 - s * h / ell
     for i in range(iters):
-        lam = (1 - etas[i % 5] * np.sqrt(s)) / (1 + etas[i % 5] * np.sqrt(s)) if accelerated else 0.0
+        lam = fx["lambda"][i % 5] if accelerated else 0.0
         ey = (1 + lam) * e - lam * e_prev
         d = -h * ey / ell
         assert abs(np.max(np.abs(d)) - hist[i]) <= 1e-13 * max(1.0, hist[i])
@@ -297,3 +316,34 @@ def test_dense_mu_jacobian_matches_finite_differences(kind, params):
     fd = (m.mu(g, u + h * v) - m.mu(g, u - h * v)) / (2 * h)
     an = (J @ v.ravel()).reshape(g.shape)
     assert np.max(np.abs(fd - an)) <= 1e-6 * np.max(np.abs(an))
+
+
+def _two_valued_cases():
+    with open(os.path.join(GOLDEN, "averaged_newton_two_valued.json")) as fh:
+        return json.load(fh)["cases"]
+
+
+@pytest.mark.parametrize("case", _two_valued_cases(), ids=lambda c: c["name"])
+def test_averaged_newton_betas_on_two_valued_fields(case):
+    """Sec. 3.4.1's grid means on a field that takes u1 on one half of the grid
+    and u2 on the other, against the hand-worked values: a square of the mean
+    in place of the mean of squares, an absolute value moved inside the mean,
+    or the wrong evaluation point (x0 instead of the midpoint) changes them."""
+    shape = (8, 6)
+    g = spectral.Grid(shape, (3.0, 2.0))
+    if case["model"] == "pfc":
+        m = models.make_model("pfc", eps=case["eps"])
+    else:
+        m = models.make_model("fch", eps=case["eps"], eta1=case["eta1"], eta2=case["eta2"],
+                              tau=case["tau"])
+    x0 = np.empty(shape)
+    x0[: shape[0] // 2] = case["x0"][0]
+    x0[shape[0] // 2:] = case["x0"][1]
+    un = x0 if case["un"] is None else np.full(shape, case["un"])
+    a = 7.5
+    P = pagd.StepProblem(g, m, a, -a, 0.0, case["theta"], un, None)
+    bm2, b0, b2, b4 = pagd.averaged_newton_betas(P, x0)
+    assert bm2 == a
+    assert abs(b0 - case["beta0"]) <= 1e-14 * abs(case["beta0"])
+    assert abs(b2 - case["beta2"]) <= 1e-13 * abs(case["beta2"])
+    assert abs(b4 - case["beta4"]) <= 1e-15
