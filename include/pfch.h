@@ -37,7 +37,9 @@ enum {
   PFCH_E_NOCONV = -4,      /* PAGD reached max_iter without ||d||_inf < tol */
   PFCH_E_NONFINITE = -5,   /* ||d||_inf became Inf or NaN */
   PFCH_E_PRECOND = -6,     /* averaged-Newton symbol not positive on some mode */
-  PFCH_E_UNSUPPORTED = -7  /* valid but not supported (grid size, ndim) */
+  PFCH_E_UNSUPPORTED = -7, /* valid but not supported (grid size, ndim) */
+  PFCH_E_INTERNAL = -8     /* internal inconsistency: a solve's stop record was not
+                              final when read; no result is reported or accepted */
 };
 
 enum { PFCH_PFC = 0, PFCH_FCH = 1 };  /* model */
@@ -84,9 +86,13 @@ typedef struct pfch_instance_desc {
 
 /* Per-instance result of one step or solve. */
 typedef struct pfch_stats {
-  double dnorm_inf; /* ||d||_inf of the last iteration */
+  double dnorm_inf; /* ||d||_inf of the last iteration (Alg. 2's stopping test) */
   double beta[4];   /* beta_-2, beta_0, beta_2, beta_4 used for this step */
   double mass;      /* mean of the accepted solution (NaN if not computed) */
+  double rnorm_inf; /* ||r||_inf, r = -G'(x) of eq. obj:G' at the returned
+                       solution x (the residual of the step problem, without
+                       the preconditioner); NaN unless statistics detail 2 was
+                       set and the solve converged; NaN for the IMEX schemes */
   int32_t iters;    /* PAGD iterations */
   int32_t fft_pairs;/* 2D transform pairs of real fields used (setup + iterations) */
   int32_t status;   /* PFCH_OK or the error of this instance */
@@ -102,21 +108,34 @@ typedef struct pfch_ctx pfch_ctx; /* opaque; owned by the library */
 int pfch_validate_desc(const pfch_instance_desc* desc);
 
 /* Create a context holding n_inst instances that advance together in each
- * pfch_step.  `hip_stream` is a hipStream_t (NULL = default stream).  All
- * workspaces, transform tables and launch graphs are allocated here and
- * owned by the context.  The initial state of every instance is undefined
- * until pfch_set_state. */
+ * pfch_step.  Each instance is one discrete problem of Sec. 3.2 (periodic
+ * Fourier collocation of the model on its grid) stepped by the scheme of
+ * Sec. 3.1 with the solver of Alg. 2; descs is a host array of n_inst
+ * descriptors, copied.  `hip_stream` is a hipStream_t (NULL = default
+ * stream).  All workspaces, transform tables and launch graphs are
+ * allocated here and owned by the context; *out is NULL on error.  Errors:
+ * PFCH_E_INVAL / PFCH_E_UNSUPPORTED for a descriptor pfch_validate_desc
+ * rejects, PFCH_E_NOMEM, PFCH_E_HIP.  The initial state of every instance is
+ * undefined until pfch_set_state. */
 int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_stream,
                 pfch_ctx** out);
 
-/* Set u^n (and u^{n-1}, or NULL when there is no history yet) of instance
- * `inst` from device arrays; t, dt_prev (step that produced u^n, ignored when
- * u_nm1 is NULL) and the step index n are host values.  The data are copied. */
+/* Set the step history of instance `inst`: the data a multistep scheme
+ * needs to take its next step (Sec. 3.1; the inputs u^n, u^{n-1} and the
+ * previous step size of Alg. 3).  u^n (and u^{n-1}, or NULL when there is no
+ * history yet, so that the next BDF2 step is backward Euler) are device
+ * arrays of Nx*Ny(*Nz) doubles, copied; t, dt_prev (the step that produced
+ * u^n, > 0, ignored when u_nm1 is NULL) and the step index n are host
+ * values.  Discards a queued set-up.  PFCH_E_INVAL for a bad instance index
+ * or null u_n. */
 int pfch_set_state(pfch_ctx* ctx, int32_t inst, const double* u_n, const double* u_nm1,
                    double t, double dt_prev, int32_t step_index);
 
-/* Copy the state of instance `inst` out; any pointer may be NULL.  u_nm1 is
- * left untouched when the instance has no history. */
+/* Copy the step history of instance `inst` (u^n, u^{n-1}, t, the last step
+ * size and the step index; Sec. 3.1 and Alg. 3) out to caller-owned device
+ * arrays and host scalars; any pointer may be NULL.  u_nm1 is left untouched
+ * when the instance has no history.  PFCH_E_INVAL for a bad instance
+ * index. */
 int pfch_get_state(pfch_ctx* ctx, int32_t inst, double* u_n, double* u_nm1, double* t,
                    double* dt_prev, int32_t* step_index);
 
@@ -200,10 +219,14 @@ int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* a, pfch_adapt_resul
  * not changed. */
 int pfch_rhs(pfch_ctx* ctx, int32_t inst, const double* v, double* out);
 
-/* Statistics detail of pfch_step when st != NULL: 0 = iterations, status and
- * ||d||_inf only (read from the convergence records, no extra
- * synchronisation); 1 (default) = also beta and the mass of the accepted
- * solution (one extra reduction and synchronisation per step). */
+/* Statistics detail of pfch_step, pfch_step_adaptive and pfch_solve when
+ * st != NULL: 0 = iterations, status and ||d||_inf only (read from the
+ * convergence records, no extra synchronisation); 1 (default) = also beta
+ * and the mass of the accepted solution (one extra reduction and
+ * synchronisation per step); 2 = also ||r||_inf of each converged solution
+ * (one more evaluation of the residual per instance: the set-up and one
+ * iteration of the solver's kernels with the identity in place of the
+ * preconditioner, and one synchronisation per instance). */
 int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail);
 
 /* Kernel timing for measurement.  Solves `reps` times the step of size dt
@@ -342,6 +365,19 @@ int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[37]);
  * limits (PFCH_E_INVAL otherwise).  Results of different plans agree to
  * rounding. */
 int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]);
+
+/* The host's decision on a solve's stop record, exported so that it can be
+ * checked without a GPU.  stop_iter is -1 while the solve runs, j when
+ * ||d_j||_inf decided the stop (Alg. 2: the solve returns x_{j+1} after j+1
+ * iterations), max_iter at the iteration cap; flags bit 0 = the
+ * averaged-Newton symbol was not positive (Sec. 3.4.1); norm_bits =
+ * ||d_j||_inf as IEEE bits.  Returns PFCH_E_PRECOND, PFCH_E_NOCONV,
+ * PFCH_E_NONFINITE, PFCH_OK, or PFCH_E_INTERNAL for a record still marked
+ * running (never reported as a result); *iters and *dnorm_inf (host) get
+ * the iteration count and the norm.  PFCH_E_INVAL for null outputs or
+ * max_iter < 1.  Needs no GPU. */
+int pfch_stop_status(int32_t stop_iter, int32_t flags, uint64_t norm_bits, int32_t max_iter,
+                     int32_t* iters, double* dnorm_inf);
 
 void pfch_destroy(pfch_ctx* ctx);
 const char* pfch_strerror(int code);

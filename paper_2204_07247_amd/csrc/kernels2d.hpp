@@ -210,6 +210,13 @@ __device__ __forceinline__ double wavenum2(const InstDev* I, int kx, int ky, int
 // summed once per step in a fixed order by the setup column kernel.
 __device__ __forceinline__ void betas(const InstDev* I, double& bm2, double& b0, double& b2,
                                       double& b4) {
+  if (I->resid) {  // identity preconditioner (Lq = q): d^ = r^, the residual itself
+    bm2 = 0.0;
+    b0 = 1.0 / I->theta_l;
+    b2 = 0.0;
+    b4 = 0.0;
+    return;
+  }
   bm2 = I->a / I->mobility;
   b0 = I->beta0;
   if (I->model == MODEL_PFC) {
@@ -272,8 +279,10 @@ __device__ __forceinline__ void fold_betas(const InstDev* I, InstDev* home, bool
                                            double& b2) {
   double f0, f2;
   sum_betas(I, f0, f2);
-  b0 = f0;
-  if (I->model == MODEL_FCH) b2 = f2;
+  if (!I->resid) {
+    b0 = f0;
+    if (I->model == MODEL_FCH) b2 = f2;
+  }
   if (blk0 && threadIdx.x == 0) {
     home->beta0 = f0;
     home->beta2 = f2;
@@ -1027,6 +1036,7 @@ struct StepArgs {
   const double* lunm1;
   double* acc_ldst;
   int32_t fold;        // no column set-up: the first column iteration does its part
+  int32_t resid;       // evaluate ||r(x0)||_inf instead of solving (see InstDev::resid)
 };
 
 // Up to STEP_ARGS_INLINE instances' arguments travel by value with the
@@ -1069,6 +1079,7 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* const* __restrict__ 
     I->acc_ldst = sa.acc_ldst;
     I->lap_hist = sa.lun != nullptr;
     I->fold_g = sa.fold;
+    I->resid = sa.resid;
     *I->iter_base = 0;
     *I->flags = 0;
     I->rec->stop_iter = -1;
@@ -1165,6 +1176,7 @@ __global__ __launch_bounds__(256) void k_row_setup_lap(InstDev* const* __restric
     I->acc_ldst = sa.acc_ldst;
     I->lap_hist = 1;
     I->fold_g = sa.fold;
+    I->resid = sa.resid;
     *I->iter_base = 0;
     *I->flags = 0;
     I->rec->stop_iter = -1;
@@ -1261,6 +1273,7 @@ __global__ __launch_bounds__(256) void k_row_setup_lap_fp(InstDev* const* __rest
     I->acc_ldst = sa.acc_ldst;
     I->lap_hist = 1;
     I->fold_g = sa.fold;
+    I->resid = sa.resid;
     *I->iter_base = 0;
     *I->flags = 0;
     I->rec->stop_iter = -1;

@@ -41,6 +41,13 @@ inline bool scheme_imex(int s) { return s == PFCH_LBDF2 || s == PFCH_LMP; }
 // instance's chunk: each lane tests one iteration's norm and a ballot picks
 // the first that stops the solve, so the norms are read in parallel rather
 // than one dependent load per iteration.
+//
+// Host-visible writes, in this order, each group separated from the next by
+// a system-scope fence and a block barrier: (1) every mirror's stop_iter,
+// flags and norm; (2) every mirror's chunk number; (3) the chunk counter.
+// The host waits for (3) and then uses a mirror only if its chunk number
+// (2) is the chunk it waited for, so a record from an earlier chunk is never
+// taken for this chunk's.
 __device__ __forceinline__ int chunk_group_size(int K, int n) {
   int S = 1;
   while (S < K && S < 64) S *= 2;
@@ -54,6 +61,7 @@ __global__ __launch_bounds__(1024) void k_chunk_end(InstDev* const* insts, int n
   const int S = chunk_group_size(K, n);
   const int g = threadIdx.x / S, r = threadIdx.x % S, ngroups = blockDim.x / S;
   const int wl = threadIdx.x & 63, gbase = wl - r;  // group's first lane in the wave
+  const uint32_t tag = *seq_dev + 1;  // this chunk's number (seq_dev changes only below)
   const uint64_t gmask = S == 64 ? ~0ull : ((1ull << S) - 1) << gbase;
   for (int i = g; i < n; i += ngroups) {
     InstDev* I = insts[i];
@@ -98,17 +106,37 @@ __global__ __launch_bounds__(1024) void k_chunk_end(InstDev* const* insts, int n
       const bool ended = before < 0 && rec->stop_iter >= 0;
       I->acc_now = ended ? I->acc_dst : nullptr;
       I->acc_lnow = ended ? I->acc_ldst : nullptr;
-      *I->rec_host = *rec;  // the host polls this copy
+      StopRec* h = I->rec_host;  // the host polls this copy
+      h->stop_iter = rec->stop_iter;
+      h->flags = rec->flags;
+      h->norm_bits = rec->norm_bits;
     }
   }
   __threadfence_system();
   __syncthreads();
+  if (r == 0)
+    for (int i = g; i < n; i += ngroups) insts[i]->rec_host->seq = tag;
+  __threadfence_system();
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t v = *seq_dev + 1;
-    *seq_dev = v;
-    *seq_host = v;
+    *seq_dev = tag;
+    *seq_host = tag;
     __threadfence_system();
   }
+}
+
+// Park instances: no iteration kernel works on them and no in-graph accept
+// copies for them until their next set-up.  Used when a queued set-up is
+// discarded and after a residual evaluation.  One thread per instance.
+__global__ __launch_bounds__(256) void k_park(InstDev* const* insts, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  InstDev* I = insts[i];
+  *I->iter_base = I->max_iter + 1;
+  I->acc_dst = nullptr;
+  I->acc_ldst = nullptr;
+  I->acc_now = nullptr;
+  I->acc_lnow = nullptr;
 }
 
 // Threads of the chunk-end block: one group of S lanes per instance (up to
@@ -224,6 +252,7 @@ struct Instance {
   int hist = 1;              // solutions held: u^n, u^{n-1}, u^{n-2}
   bool r_valid = false;      // R[0] (and R[1] when hist >= 2) match the history
   double dt_nm1 = 0.0;       // dt_{n-1}, valid when hist == 3
+  double* uprobe = nullptr;  // statistics detail 2: u^{n-1} of the step being taken
   std::vector<void*> allocs;
 };
 
@@ -283,6 +312,7 @@ struct pfch_ctx {
   InstDev** d_ptrs = nullptr;  // all instances
   StopRec* d_recs = nullptr;
   StopRec* h_recs = nullptr;   // pinned; written by the chunk-end kernel
+  std::vector<StopRec> recs;   // the records of the last chunk, copied once its number checked
   int32_t* h_scratch = nullptr;  // pinned staging for small uploads
   uint32_t* d_seq = nullptr;     // chunk counter (device) and its pinned mirror
   uint32_t* h_seq = nullptr;
@@ -762,6 +792,25 @@ int launch_setup_solo(pfch_ctx* ctx, Instance& I, const StepSetup& ss, bool allo
                       ss.lun != nullptr, allow_fold);
 }
 
+// Park instances (all of them when insts is the context's array) so that
+// later chunk graphs neither iterate nor accept for them.
+int launch_park(pfch_ctx* ctx, InstDev** insts, int n) {
+  void* a[] = {&insts, &n};
+  return launch((const void*)&k_park, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, a, ctx->stream);
+}
+
+// Discard a set-up queued by the previous pfch_step.  That set-up marked
+// every instance's record running and published its accept destination
+// (the u^{n-1} slot), so the next chunk graph, replayed for whichever
+// instances a later call solves, would otherwise iterate every instance and
+// copy its solution over its history: the instances are parked on the
+// device first, in stream order behind the queued set-up.
+int drop_spec(pfch_ctx* ctx) {
+  if (!ctx->spec) return PFCH_OK;
+  ctx->spec = false;
+  return launch_park(ctx, ctx->d_ptrs, (int)ctx->inst.size());
+}
+
 int launch_accept(pfch_ctx* ctx, AccDsts inl, double** dsts, double* part, int check) {
   InstDev** ptrs = ctx->d_ptrs;
   void* a[] = {&ptrs, &dsts, &part, &inl, &check};
@@ -790,6 +839,42 @@ int wait_chunk(pfch_ctx* ctx, uint32_t want) {
   return PFCH_OK;
 }
 
+// Copy the mirrored stop records of chunk `want` into ctx->recs.  Each
+// mirror carries the number of the chunk that wrote it, written after its
+// other fields; a mirror from an earlier chunk is not used: the stream is
+// synchronised (the chunk has then ended) and the mirrors read again.  A
+// mirror that still carries another number is an internal error.
+int take_records(pfch_ctx* ctx, uint32_t want) {
+  const int n = (int)ctx->inst.size();
+  ctx->recs.resize(n);
+  for (int pass = 0; pass < 2; ++pass) {
+    bool all = true;
+    for (int i = 0; i < n; ++i) {
+      const volatile StopRec* h = ctx->h_recs + i;
+      const uint32_t tag = h->seq;
+      std::atomic_thread_fence(std::memory_order_acquire);
+      if (tag != want) {
+        all = false;
+        continue;
+      }
+      StopRec r{};
+      r.stop_iter = h->stop_iter;
+      r.flags = h->flags;
+      r.norm_bits = h->norm_bits;
+      r.seq = tag;
+      ctx->recs[i] = r;
+    }
+    if (all) return PFCH_OK;
+    if (pass == 0) {
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      const char* dbg = std::getenv("PFCH_DEBUG");
+      if (dbg && dbg[0] && dbg[0] != '0')
+        std::fprintf(stderr, "pfch: stop records behind chunk %u; read again after synchronising\n", want);
+    }
+  }
+  return PFCH_E_INTERNAL;
+}
+
 // Replay iteration chunks until every instance in `active` has stopped.  The
 // chunk graph ends with the stop records mirrored into pinned host memory and
 // a progress counter the host waits on, then the accept of instances whose
@@ -808,9 +893,10 @@ int run_iterations(pfch_ctx* ctx, const std::vector<int>& active) {
     if (rc) return rc;
     HIPCHK(hipGraphLaunch(ex, ctx->stream));
     if ((rc = wait_chunk(ctx, ++ctx->seq))) return rc;
+    if ((rc = take_records(ctx, ctx->seq))) return rc;
     bool all = true;
     for (int i : active) {
-      const StopRec& r = ctx->h_recs[i];
+      const StopRec& r = ctx->recs[i];
       if (r.stop_iter < 0 && !(r.flags & FLAG_PRECOND)) all = false;
     }
     if (all) return PFCH_OK;
@@ -818,20 +904,30 @@ int run_iterations(pfch_ctx* ctx, const std::vector<int>& active) {
   }
 }
 
-int status_of(const Instance& I, const StopRec& r, int* iters, double* dnorm) {
-  const double nv = double_of(r.norm_bits);
+// The host's decision on a final stop record (Alg. 2's stopping rule, the
+// iteration cap, a non-finite norm, the preconditioner check).  A record
+// still marked running is never a result.
+int stop_status(int32_t stop_iter, int32_t flags, uint64_t norm_bits, int32_t max_iter, int* iters,
+                double* dnorm) {
+  const double nv = double_of(norm_bits);
   *dnorm = nv;
-  if (r.flags & FLAG_PRECOND) {
-    *iters = 0;
-    return PFCH_E_PRECOND;
+  *iters = 0;
+  if (flags & FLAG_PRECOND) return PFCH_E_PRECOND;
+  if (stop_iter < 0) {
+    *dnorm = NAN;
+    return PFCH_E_INTERNAL;
   }
-  if (r.stop_iter >= I.d.max_iter) {
-    *iters = I.d.max_iter;
+  if (stop_iter >= max_iter) {
+    *iters = max_iter;
     return PFCH_E_NOCONV;
   }
-  *iters = r.stop_iter + 1;
+  *iters = stop_iter + 1;
   if (!std::isfinite(nv)) return PFCH_E_NONFINITE;
   return PFCH_OK;
+}
+
+int status_of(const Instance& I, const StopRec& r, int* iters, double* dnorm) {
+  return stop_status(r.stop_iter, r.flags, r.norm_bits, I.d.max_iter, iters, dnorm);
 }
 
 int betas_host(pfch_ctx* ctx, Instance& I, double a, double out[4]) {
@@ -1311,8 +1407,20 @@ const char* pfch_strerror(int code) {
     case PFCH_E_NONFINITE: return "non-finite value in the PAGD iteration";
     case PFCH_E_PRECOND: return "averaged-Newton preconditioner not positive";
     case PFCH_E_UNSUPPORTED: return "unsupported configuration";
+    case PFCH_E_INTERNAL: return "internal error: a solve record was not final";
     default: return "unknown error";
   }
+}
+
+int pfch_stop_status(int32_t stop_iter, int32_t flags, uint64_t norm_bits, int32_t max_iter, int32_t* iters,
+                     double* dnorm_inf) {
+  if (!iters || !dnorm_inf || max_iter < 1) return PFCH_E_INVAL;
+  int it = 0;
+  double dn = 0.0;
+  const int rc = stop_status(stop_iter, flags, norm_bits, max_iter, &it, &dn);
+  *iters = it;
+  *dnorm_inf = dn;
+  return rc;
 }
 
 int pfch_validate_desc(const pfch_instance_desc* d) {
@@ -1545,6 +1653,7 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
   if ((rc = halloc(ctx->host_allocs, &p, sizeof(StopRec) * n_inst, true))) goto fail;
   ctx->h_recs = (StopRec*)p;
   for (int i = 0; i < n_inst; ++i) ctx->h_recs[i].stop_iter = -1;  // not stopped until a chunk says so
+  ctx->recs.assign(n_inst, StopRec{-1, 0, 0, 0, 0});
   if ((rc = halloc(ctx->host_allocs, &p, 64))) goto fail;
   ctx->h_scratch = (int32_t*)p;
   if ((rc = halloc(ctx->host_allocs, &p, 64, true))) goto fail;
@@ -1652,14 +1761,23 @@ fail:
 }
 
 int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail) {
-  if (!ctx || detail < 0 || detail > 1) return PFCH_E_INVAL;
+  if (!ctx || detail < 0 || detail > 2) return PFCH_E_INVAL;
+  if (detail == 2) {  // the residual needs u^{n-1} after the accept has replaced it
+    for (auto& I : ctx->inst) {
+      if (I.uprobe) continue;
+      void* p = nullptr;
+      int rc = dalloc(I.allocs, &p, sizeof(double) * (size_t)I.npts);
+      if (rc) return rc;
+      I.uprobe = (double*)p;
+    }
+  }
   ctx->stats_detail = detail;
   return PFCH_OK;
 }
 
 int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
   if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
-  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
+  if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
   Instance& I = ctx->inst[0];
   const Group& G = ctx->groups[I.group];
   Stage st[4];
@@ -1718,7 +1836,7 @@ int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
 
 int pfch_time_kernels_events(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
   if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
-  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
+  if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
   Instance& I = ctx->inst[0];
   const Group& G = ctx->groups[I.group];
   int rc;
@@ -1805,7 +1923,7 @@ int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[37]) {
 
 int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]) {
   if (!ctx || !choice || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
-  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
+  if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
   Group& G = ctx->groups[ctx->inst[inst].group];
   TuneChoice c;
   c.row_alt = choice[0];
@@ -1830,9 +1948,9 @@ int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]) {
 int pfch_set_state(pfch_ctx* ctx, int32_t inst, const double* u_n, const double* u_nm1, double t,
                    double dt_prev, int32_t step_index) {
   if (!ctx || inst < 0 || inst >= (int)ctx->inst.size() || !u_n) return PFCH_E_INVAL;
-  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   Instance& I = ctx->inst[inst];
   if (u_nm1 && !(dt_prev > 0.0)) return PFCH_E_INVAL;
+  if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
   const size_t bytes = sizeof(double) * (size_t)I.npts;
   HIPCHK(hipMemcpyAsync(I.U[I.ucur], u_n, bytes, hipMemcpyDeviceToDevice, ctx->stream));
   if (u_nm1) HIPCHK(hipMemcpyAsync(I.U[1 - I.ucur], u_nm1, bytes, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1948,7 +2066,7 @@ int finish_solve(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept) {
     if (o.guess[i] != 1) continue;
     int it = 0;
     double d = 0.0;
-    if (status_of(ctx->inst[i], ctx->h_recs[i], &it, &d) == PFCH_OK) continue;
+    if (status_of(ctx->inst[i], ctx->recs[i], &it, &d) == PFCH_OK) continue;
     Instance& I = ctx->inst[i];
     StepSetup ss = step_setup_for(I, dt[i]);
     if (accept) {
@@ -1961,21 +2079,27 @@ int finish_solve(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept) {
     retry.push_back(i);
   }
   if (!retry.empty() && (rc = run_iterations(ctx, retry))) return rc;
-  for (int i = 0; i < n; ++i) o.status[i] = status_of(ctx->inst[i], ctx->h_recs[i], &o.iters[i], &o.dn[i]);
+  for (int i = 0; i < n; ++i) o.status[i] = status_of(ctx->inst[i], ctx->recs[i], &o.iters[i], &o.dn[i]);
   return PFCH_OK;
 }
 
 // Tentative solve of every instance at step size dt[i]: set-up, PAGD
 // iterations, and the learned-guess fallback.  Nothing is accepted.
 int solve_all(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept = false) {
-  ctx->spec = false;
+  ctx->spec = false;  // every instance's set-up follows: a queued one needs no parking
   int rc;
   if ((rc = launch_step_setups(ctx, dt, o, accept))) return rc;
   return finish_solve(ctx, dt, o, accept);
 }
 
-// The converged iterate of instance I after solve_all.
-const double* solution_of(const Instance& I, const StopRec& r) { return I.h.X[(r.stop_iter + 1) % 3]; }
+// The converged iterate of instance I after solve_all; null unless the
+// record is a final, converged one.
+const double* solution_of(const Instance& I, const StopRec& r) {
+  int it = 0;
+  double dn = 0.0;
+  if (status_of(I, r, &it, &dn) != PFCH_OK) return nullptr;
+  return I.h.X[(r.stop_iter + 1) % 3];
+}
 
 // Accept the tentative solutions of the instances with take[i]: u^{n+1}
 // into the history (with u^{n-2} kept for the adaptive estimators), time
@@ -2044,12 +2168,63 @@ int fill_stats(pfch_ctx* ctx, const SolveOut& o, int i, bool want_mass, bool acc
   s.fft_pairs = fft_pairs_of(I, o.iters[i]);
   s.guess = o.guess[i];
   s.mass = (want_mass && accepted) ? ctx->h_mass[i] : NAN;
+  s.rnorm_inf = NAN;
   if (ctx->stats_detail > 0) {
     int rc = betas_host(ctx, I, o.a[i], s.beta);
     if (rc) return rc;
   } else {
     for (double& b : s.beta) b = NAN;
   }
+  return PFCH_OK;
+}
+
+// Coefficients of a step of size dt from instance I's current history.
+struct Coef {
+  double a, b, c, theta;
+};
+Coef coef_of(const Instance& I, double dt) {
+  const StepSetup ss = step_setup_for(I, dt);
+  return Coef{ss.a, ss.b, ss.c, ss.theta};
+}
+
+// ||r(x)||_inf, r = -G'(x) of the step problem with coefficients k and
+// history (un, unm1): the step set-up from x with the residual flag, then
+// one iteration of the instance's iteration kernels, whose preconditioner is
+// then the identity, so that the first norm slot holds ||r(x)||_inf.  Uses
+// the instance's iteration workspaces (not its state); the instance is
+// parked afterwards.  Synchronises the stream.  NaN for the IMEX schemes.
+int residual_norm(pfch_ctx* ctx, Instance& I, const double* x, const double* un, const double* unm1,
+                  const Coef& k, double* out) {
+  *out = NAN;
+  if (scheme_imex(I.d.scheme)) return PFCH_OK;
+  StepSetup ss{};
+  ss.un = un;
+  ss.unm1 = unm1 ? unm1 : un;
+  ss.xin = x;
+  ss.a = k.a;
+  ss.b = k.b;
+  ss.c = k.c;
+  ss.theta = k.theta;
+  ss.rho = 0.0;
+  StepArgsInline inl{};
+  inl.a[0] = to_args(ss);
+  inl.a[0].resid = 1;
+  const Group& G = ctx->groups[I.group];
+  int rc;
+  if ((rc = launch_setup(ctx, G, I.d_solo, nullptr, 1, &inl, true, false))) return rc;
+  Stage st[4];
+  const int ns = iter_stages(G, st);
+  InstDev** grp = I.d_solo;
+  for (int q = 0; q < ns; ++q) {
+    int bpi = st[q].bpi, l = 0, total = bpi;
+    void* a[] = {&grp, &bpi, &l, &total};
+    if ((rc = launch(st[q].f, dim3(stage_grid(st[q], 1)), st[q].block, st[q].lds, a, ctx->stream))) return rc;
+  }
+  if ((rc = launch_park(ctx, I.d_solo, 1))) return rc;
+  uint64_t* bits = reinterpret_cast<uint64_t*>(ctx->h_scratch);
+  HIPCHK(hipMemcpyAsync(bits, I.h.norms, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *out = double_of(*bits);
   return PFCH_OK;
 }
 
@@ -2149,6 +2324,20 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
   int rc;
   const bool want_mass = st && ctx->stats_detail > 0;
   const bool same_dt = (int)ctx->last_dt.size() == n && std::equal(dt, dt + n, ctx->last_dt.begin());
+  // statistics detail 2: the residual of each solution afterwards needs this
+  // step's coefficients and u^{n-1}, which the accept replaces
+  const bool want_resid = st && ctx->stats_detail > 1;
+  std::vector<Coef> coefs;
+  if (want_resid) {
+    coefs.resize(n);
+    for (int i = 0; i < n; ++i) {
+      Instance& I = ctx->inst[i];
+      coefs[i] = coef_of(I, dt[i]);
+      if (coefs[i].c != 0.0)
+        HIPCHK(hipMemcpyAsync(I.uprobe, I.U[1 - I.ucur], sizeof(double) * (size_t)I.npts,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+    }
+  }
   // every instance's accept runs inside the chunk graph, checked on the
   // device against the same stop record the host reads afterwards
   if (ctx->spec && same_dt) {  // the set-up was enqueued by the previous call
@@ -2173,6 +2362,14 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
     if (want_mass) HIPCHK(hipStreamSynchronize(ctx->stream));
     for (int i = 0; i < n; ++i)
       if ((rc = fill_stats(ctx, o, i, want_mass, take[i], st[i]))) return rc;
+    for (int i = 0; i < n && want_resid; ++i) {
+      if (!take[i]) continue;
+      Instance& I = ctx->inst[i];  // accepted: u^{n+1} = U[ucur], u^n = U[1 - ucur]
+      const double* un = I.U[1 - I.ucur];
+      if ((rc = residual_norm(ctx, I, I.U[I.ucur], un, coefs[i].c != 0.0 ? I.uprobe : un, coefs[i],
+                              &st[i].rnorm_inf)))
+        return rc;
+    }
   }
   // A loop at a fixed step size: enqueue the next step's set-up now, so that
   // it runs while control is with the caller.  Only when every instance
@@ -2192,7 +2389,6 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
 
 int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_result* res) {
   if (!ctx || !ad || !res) return PFCH_E_INVAL;
-  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   if (!(ad->tol > 0.0) || !std::isfinite(ad->tol) || !(ad->dt_min > 0.0) || !std::isfinite(ad->dt_max) ||
       !(ad->dt_max >= ad->dt_min) || ad->estimator < PFCH_EST_AUTO || ad->estimator > PFCH_EST_MIDAB2 ||
       ad->reserved != 0)
@@ -2205,6 +2401,7 @@ int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_resu
     if (ctx->inst[i].nz > 1) return PFCH_E_UNSUPPORTED;
   }
   int rc;
+  if ((rc = drop_spec(ctx))) return rc;  // instance state or workspaces change
   if ((rc = prepare_adaptive(ctx))) return rc;
   SolveOut o;
   if ((rc = solve_all(ctx, dt.data(), o))) return rc;
@@ -2217,7 +2414,8 @@ int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_resu
     for (unsigned k = 0; k < nm; ++k) {
       const int i = G.members[k];
       if (o.status[i] != PFCH_OK) continue;
-      src[k] = solution_of(ctx->inst[i], ctx->h_recs[i]);
+      src[k] = solution_of(ctx->inst[i], ctx->recs[i]);
+      if (!src[k]) return PFCH_E_INTERNAL;
       dst[k] = ctx->inst[i].R[2];
       any = true;
     }
@@ -2232,7 +2430,8 @@ int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_resu
     std::memset(&A, 0, sizeof(A));
     A.n = I.npts;
     if (o.status[i] != PFCH_OK) continue;
-    A.ut = solution_of(I, ctx->h_recs[i]);
+    A.ut = solution_of(I, ctx->recs[i]);
+    if (!A.ut) return PFCH_E_INTERNAL;
     const bool mid = (ad->estimator == PFCH_EST_MIDAB2 ||
                       (ad->estimator == PFCH_EST_AUTO && I.d.scheme == PFCH_MP)) &&
                      I.hist >= 3;
@@ -2289,6 +2488,8 @@ int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_resu
     if (o.status[i] != PFCH_OK && dt[i] <= ad->dt_min && ret == PFCH_OK) ret = o.status[i];
   }
   const bool want_mass = ctx->stats_detail > 0;
+  std::vector<Coef> coefs(n);
+  for (int i = 0; i < n; ++i) coefs[i] = coef_of(ctx->inst[i], dt[i]);  // before the history moves
   if ((rc = accept_solutions(ctx, take, dt.data(), o, want_mass, true))) return rc;
   if (want_mass) HIPCHK(hipStreamSynchronize(ctx->stream));
   for (int i = 0; i < n; ++i) {
@@ -2307,14 +2508,24 @@ int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_resu
     r.dt_try = next_dt(err[i], ad->tol, dt[i], ad->dt_min, ad->dt_max);
     if ((rc = fill_stats(ctx, o, i, want_mass, take[i], r.solve))) return rc;
   }
+  // statistics detail 2: residual of each accepted solution (the accept
+  // kept u^n in U[1 - ucur] and u^{n-1} in Um2)
+  for (int i = 0; i < n && ctx->stats_detail > 1; ++i) {
+    if (!take[i]) continue;
+    Instance& I = ctx->inst[i];
+    const double* un = I.U[1 - I.ucur];
+    if ((rc = residual_norm(ctx, I, I.U[I.ucur], un, coefs[i].c != 0.0 ? I.Um2 : un, coefs[i],
+                            &res[i].solve.rnorm_inf)))
+      return rc;
+  }
   return ret;
 }
 
 int pfch_rhs(pfch_ctx* ctx, int32_t inst, const double* v, double* out) {
   if (!ctx || inst < 0 || inst >= (int)ctx->inst.size() || !v || !out || v == out) return PFCH_E_INVAL;
-  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   Instance& I = ctx->inst[inst];
   if (I.nz > 1) return PFCH_E_UNSUPPORTED;
+  if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
   std::vector<const double*> src{v};
   std::vector<double*> dst{out};
   int rc = rhs_launch(ctx, ctx->groups[I.group], I.d_solo, 1, src, dst);
@@ -2326,9 +2537,9 @@ int pfch_rhs(pfch_ctx* ctx, int32_t inst, const double* v, double* out) {
 int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const double* u_n,
                const double* u_nm1, double* x, pfch_stats* st) {
   if (!ctx || inst < 0 || inst >= (int)ctx->inst.size() || !u_n || !x) return PFCH_E_INVAL;
-  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
   if (!(a > 0.0) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c)) return PFCH_E_INVAL;
   if (c != 0.0 && !u_nm1) return PFCH_E_INVAL;
+  if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
   Instance& I = ctx->inst[inst];
   StepSetup ss{};
   ss.un = u_n;
@@ -2345,9 +2556,9 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
   if ((rc = run_iterations(ctx, active))) return rc;
   int iters = 0;
   double dn = 0.0;
-  const int status = status_of(I, ctx->h_recs[inst], &iters, &dn);
+  const int status = status_of(I, ctx->recs[inst], &iters, &dn);
   if (status == PFCH_OK || status == PFCH_E_NOCONV || status == PFCH_E_NONFINITE) {
-    const StopRec& r = ctx->h_recs[inst];
+    const StopRec& r = ctx->recs[inst];
     const int last = status == PFCH_E_NOCONV ? I.d.max_iter : r.stop_iter + 1;
     const size_t bytes = sizeof(double) * (size_t)I.npts;
     HIPCHK(hipMemcpyAsync(x, I.h.X[last % 3], bytes, hipMemcpyDeviceToDevice, ctx->stream));
@@ -2361,7 +2572,11 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
     st->dnorm_inf = dn;
     st->fft_pairs = fft_pairs_of(I, iters);
     st->mass = NAN;
+    st->rnorm_inf = NAN;
     if ((rc = betas_host(ctx, I, a, st->beta))) return rc;
+    if (ctx->stats_detail > 1 && status == PFCH_OK &&
+        (rc = residual_norm(ctx, I, x, u_n, u_nm1, Coef{a, b, c, ss.theta}, &st->rnorm_inf)))
+      return rc;
   }
   return status;
 }
@@ -2633,7 +2848,7 @@ int pfch_fno_prepare(pfch_fno* f, const double* u_nm1, const double* u_n, const 
 
 int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4]) {
   if (!ctx || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
-  ctx->spec = false;  // instance state or workspaces change: drop an enqueued set-up
+  if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
   Instance& I = ctx->inst[inst];
   if (!f) {
     I.fno = nullptr;

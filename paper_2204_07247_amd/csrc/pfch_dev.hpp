@@ -12,12 +12,16 @@ enum { FLAG_PRECOND = 1 };
 
 constexpr uint64_t INF_BITS = 0x7ff0000000000000ull;
 
-// Per-instance stop record, written by the chunk-end kernel.
+// Per-instance stop record, written by the chunk-end kernel.  The host
+// mirror also carries the number of the chunk that wrote it: the host uses a
+// mirrored record only when that number is the chunk it waited for.
 struct StopRec {
   int32_t stop_iter;   // -1 while running; j when ||d_j|| decided the stop;
                        // max_iter when the iteration cap was reached
   int32_t flags;       // FLAG_PRECOND
   uint64_t norm_bits;  // ||d_j||_inf as IEEE bits at the stop
+  uint32_t seq;        // host mirror: chunk number of the write (device record: unused)
+  int32_t reserved;
 };
 
 struct InstDev {
@@ -46,6 +50,8 @@ struct InstDev {
   int32_t lap_hist;        // FCH: this step's set-up took Delta x0 from the kept Laplacians
   int32_t fold_g;          // 2D: no column set-up ran; the step's first column iteration
                            // transforms g and sums the averaged-Newton partials itself
+  int32_t resid;           // residual evaluation: the preconditioner is replaced by the
+                           // identity, so d_0 = r(x0) = -G'(x0) and norms[0] = ||r(x0)||_inf
   // state buffers
   double* X[3];            // iterate ring x_j at X[j % 3]
   double* DX[3];           // FCH: Laplacian of the iterate, same ring

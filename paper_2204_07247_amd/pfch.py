@@ -19,6 +19,7 @@ PFCH_E_NOCONV = -4
 PFCH_E_NONFINITE = -5
 PFCH_E_PRECOND = -6
 PFCH_E_UNSUPPORTED = -7
+PFCH_E_INTERNAL = -8
 
 PFC, FCH = 0, 1
 BDF2, MP, LBDF2, LMP = 0, 1, 2, 3
@@ -36,7 +37,12 @@ EXPORTED = (
     "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad", "pfch_fno_adam_step",
     "pfch_fno_prepare", "pfch_fno_destroy", "pfch_set_fno", "pfch_get_plan", "pfch_set_plan",
     "pfch_step_adaptive", "pfch_rhs", "pfch_fno_num_params_3d", "pfch_fno_create_3d",
+    "pfch_stop_status",
 )
+
+
+# codes that are errors of the call, not per-instance solver outcomes
+_HARD_ERRORS = (PFCH_E_INVAL, PFCH_E_NOMEM, PFCH_E_HIP, PFCH_E_UNSUPPORTED, PFCH_E_INTERNAL)
 
 
 class InstanceDesc(ctypes.Structure):
@@ -58,6 +64,7 @@ class Stats(ctypes.Structure):
         ("dnorm_inf", ctypes.c_double),
         ("beta", ctypes.c_double * 4),
         ("mass", ctypes.c_double),
+        ("rnorm_inf", ctypes.c_double),
         ("iters", ctypes.c_int32),
         ("fft_pairs", ctypes.c_int32),
         ("status", ctypes.c_int32),
@@ -67,7 +74,7 @@ class Stats(ctypes.Structure):
     def as_dict(self):
         return dict(iters=self.iters, status=self.status, dnorm=self.dnorm_inf,
                     betas=tuple(self.beta), mass=self.mass, fft_pairs=self.fft_pairs,
-                    guess=self.guess)
+                    guess=self.guess, rnorm=self.rnorm_inf)
 
 
 class AdaptDesc(ctypes.Structure):
@@ -154,6 +161,9 @@ def lib():
         L.pfch_rhs.argtypes = [vp, i32, vp, vp]
         L.pfch_rhs.restype = ctypes.c_int
         L.pfch_set_plan.restype = ctypes.c_int
+        L.pfch_stop_status.argtypes = [i32, i32, ctypes.c_uint64, i32, ctypes.POINTER(i32),
+                                       ctypes.POINTER(dbl)]
+        L.pfch_stop_status.restype = ctypes.c_int
         for name in ("pfch_fno_create", "pfch_fno_create_3d", "pfch_fno_init_params", "pfch_fno_set_params",
                      "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad",
                      "pfch_fno_adam_step", "pfch_fno_prepare", "pfch_set_fno"):
@@ -168,6 +178,15 @@ def lib():
 
 def strerror(code):
     return lib().pfch_strerror(int(code)).decode()
+
+
+def stop_status(stop_iter, flags, norm_bits, max_iter):
+    """The host's decision on a stop record (pfch_stop_status): (code, iters, dnorm)."""
+    it = ctypes.c_int32()
+    dn = ctypes.c_double()
+    rc = lib().pfch_stop_status(int(stop_iter), int(flags), int(norm_bits), int(max_iter),
+                                ctypes.byref(it), ctypes.byref(dn))
+    return rc, it.value, dn.value
 
 
 def make_desc(model, scheme, shape, lengths, eps, eta1=0.0, eta2=0.0, tau=0.0,
@@ -299,7 +318,7 @@ class Context:
         dts = (ctypes.c_double * self.n)(*dt)
         st = (Stats * self.n)() if stats else None
         rc = lib().pfch_step(self._h, dts, st)
-        if rc in (PFCH_E_INVAL, PFCH_E_NOMEM, PFCH_E_HIP, PFCH_E_UNSUPPORTED):
+        if rc in _HARD_ERRORS:
             raise PfchError(rc, "pfch_step")
         return rc, ([s.as_dict() for s in st] if stats else None)
 
@@ -315,7 +334,7 @@ class Context:
         for i, d in enumerate(dt_try):
             res[i].dt_try = float(d)
         rc = lib().pfch_step_adaptive(self._h, ctypes.byref(ad), res)
-        if rc in (PFCH_E_INVAL, PFCH_E_NOMEM, PFCH_E_HIP, PFCH_E_UNSUPPORTED):
+        if rc in _HARD_ERRORS:
             raise PfchError(rc, "pfch_step_adaptive")
         return rc, [r.as_dict() for r in res]
 
@@ -359,7 +378,7 @@ class Context:
         st = Stats()
         rc = lib().pfch_solve(self._h, inst, float(a), float(b), float(c), _ptr(u_n),
                               _ptr(u_nm1), _ptr(x), ctypes.byref(st))
-        if rc in (PFCH_E_INVAL, PFCH_E_NOMEM, PFCH_E_HIP, PFCH_E_UNSUPPORTED):
+        if rc in _HARD_ERRORS:
             raise PfchError(rc, "pfch_solve")
         return rc, st.as_dict()
 

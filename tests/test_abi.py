@@ -37,7 +37,9 @@ def test_struct_sizes_match_header_layout():
     from paper_2204_07247_amd import pfch
     # 3 + 5 + 3 + 8 doubles, then 6 + 3 + 1 int32
     assert ctypes.sizeof(pfch.InstanceDesc) == 19 * 8 + 10 * 4
-    assert ctypes.sizeof(pfch.Stats) == 6 * 8 + 4 * 4
+    # dnorm, beta[4], mass, rnorm; iters, fft_pairs, status, guess
+    assert ctypes.sizeof(pfch.Stats) == 7 * 8 + 4 * 4
+    assert pfch.Stats.rnorm_inf.offset == 6 * 8
 
 
 def _desc(**kw):
@@ -123,6 +125,7 @@ def test_create_rejects_bad_arguments_before_device_work():
     assert L.pfch_create(ctypes.byref(_desc()), 0, None, ctypes.byref(h)) == pfch.PFCH_E_INVAL
     assert L.pfch_step(None, None, None) == pfch.PFCH_E_INVAL
     assert L.pfch_set_stats_detail(None, 1) == pfch.PFCH_E_INVAL
+    assert L.pfch_set_stats_detail(None, 2) == pfch.PFCH_E_INVAL
     assert L.pfch_time_kernels(None, 0.1, 1, None) == pfch.PFCH_E_INVAL
     ad = pfch.AdaptDesc(1e-4, 1e-3, 1.0, pfch.EST_AUTO, 0)
     res = (pfch.AdaptResult * 1)()
@@ -149,3 +152,44 @@ def test_header_compiles_as_c_and_cxx(tmp_path, compiler, std):
     r = subprocess.run([cc, std, "-Wall", "-Wextra", "-Werror", "-pedantic", "-fsyntax-only",
                         "-I", os.path.dirname(HEADER), str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def _bits(x):
+    import struct
+    return struct.unpack("<Q", struct.pack("<d", x))[0]
+
+
+def test_stop_record_decision_on_the_host():
+    """The host's reading of a solve's stop record (Alg. 2's stopping rule):
+    a record still marked running is never reported as a result, with zero
+    iterations or otherwise; a stop at j means j + 1 iterations; the cap,
+    a non-finite norm and the preconditioner flag map to their errors."""
+    from paper_2204_07247_amd import pfch
+    tol_hit = _bits(7.5e-11)
+    # running record (stop_iter -1, norm 0): internal error, not OK
+    rc, it, dn = pfch.stop_status(-1, 0, 0, 1000)
+    assert rc == pfch.PFCH_E_INTERNAL and it == 0
+    rc, it, dn = pfch.stop_status(-1, 0, tol_hit, 1000)
+    assert rc == pfch.PFCH_E_INTERNAL
+    # stopped at j = 11: twelve iterations, the norm reported
+    rc, it, dn = pfch.stop_status(11, 0, tol_hit, 1000)
+    assert (rc, it, dn) == (pfch.PFCH_OK, 12, 7.5e-11)
+    rc, it, dn = pfch.stop_status(0, 0, tol_hit, 1000)
+    assert (rc, it) == (pfch.PFCH_OK, 1)
+    # the cap
+    rc, it, dn = pfch.stop_status(1000, 0, _bits(3e-6), 1000)
+    assert (rc, it) == (pfch.PFCH_E_NOCONV, 1000)
+    # non-finite norms
+    for bad in (float("inf"), float("nan")):
+        rc, it, dn = pfch.stop_status(4, 0, _bits(bad), 1000)
+        assert (rc, it) == (pfch.PFCH_E_NONFINITE, 5)
+    # preconditioner flag wins, also on a record that never started
+    rc, it, dn = pfch.stop_status(-1, 1, 0, 1000)
+    assert (rc, it) == (pfch.PFCH_E_PRECOND, 0)
+    # argument checks
+    L = pfch.lib()
+    i = ctypes.c_int32()
+    d = ctypes.c_double()
+    assert L.pfch_stop_status(0, 0, 0, 0, ctypes.byref(i), ctypes.byref(d)) == pfch.PFCH_E_INVAL
+    assert L.pfch_stop_status(0, 0, 0, 10, None, ctypes.byref(d)) == pfch.PFCH_E_INVAL
+    assert "internal" in pfch.strerror(pfch.PFCH_E_INTERNAL)
