@@ -38,8 +38,10 @@ enum {
   PFCH_E_NONFINITE = -5,   /* ||d||_inf became Inf or NaN */
   PFCH_E_PRECOND = -6,     /* averaged-Newton symbol not positive on some mode */
   PFCH_E_UNSUPPORTED = -7, /* valid but not supported (grid size, ndim) */
-  PFCH_E_INTERNAL = -8     /* internal inconsistency: a solve's stop record was not
+  PFCH_E_INTERNAL = -8,    /* internal inconsistency: a solve's stop record was not
                               final when read; no result is reported or accepted */
+  PFCH_E_SCRATCH = -9      /* the grid needs more than the static scratch of
+                              pfch_rhs_noalloc holds */
 };
 
 enum { PFCH_PFC = 0, PFCH_FCH = 1 };  /* model */
@@ -218,6 +220,22 @@ int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* a, pfch_adapt_resul
  * not alias); 2D only.  Uses the instance's transform workspace; its state is
  * not changed. */
 int pfch_rhs(pfch_ctx* ctx, int32_t inst, const double* v, double* out);
+
+/* Allocation-free variant of pfch_rhs, for callers that cannot allocate or
+ * synchronise (code under HIP graph capture, tight serving loops).  Same
+ * arguments and result, bitwise, as pfch_rhs; it allocates nothing, makes
+ * no runtime look-up and does not synchronise: the result is ready in
+ * stream order on the context's stream.  Its spectral workspace is a static
+ * device array of 32 MiB (plus 256 bytes for the source and destination
+ * pointers) that each device holds until the process ends; grids needing
+ * more (PFC: 2 fields, FCH: 3 fields of Ny*Nx/2 complex doubles, e.g. FCH
+ * beyond 1024 x 1024 points) give PFCH_E_SCRATCH.  Unlike pfch_rhs it
+ * leaves the context's workspaces untouched (a queued set-up is kept).
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (on different streams, or from different contexts) race, and
+ * the caller must order them.  2D only (PFCH_E_UNSUPPORTED for 3D);
+ * PFCH_E_INVAL for a bad instance, null or aliasing v and out. */
+int pfch_rhs_noalloc(pfch_ctx* ctx, int32_t inst, const double* v, double* out);
 
 /* Statistics detail of pfch_step, pfch_step_adaptive and pfch_solve when
  * st != NULL: 0 = iterations, status and ||d||_inf only (read from the

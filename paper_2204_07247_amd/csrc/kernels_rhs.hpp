@@ -16,19 +16,34 @@
 //        rows  R  <- inverse x of S0
 // The 1/(Nx Ny) of the inverse transform is applied in k-space.  Every
 // kernel takes a per-instance source (or destination) pointer; a null one
-// skips the instance.
+// skips the instance.  `spec`, when not null, replaces S (three fields of
+// the instance's tiled spectral size) for every instance of the launch.
 #pragma once
 #include "kernels2d.hpp"
 
 namespace pfch {
 
+// The instance record staged in LDS, with the spectral workspace replaced by
+// `spec` when that is not null (the allocation-free entry point passes its
+// static scratch there).  Every thread of the block calls it.
+__device__ __forceinline__ const InstDev* rhs_record(const InstDev* g, InstDev* rec, c2* spec) {
+  stage_record(g, rec);
+  if (spec) {
+    if (threadIdx.x == 0) rec->S = spec;
+    __syncthreads();
+  }
+  return rec;
+}
+
 template <class PX, int MODEL>
 __global__ __launch_bounds__(256) void k_rhs_row_fwd(InstDev* const* __restrict__ grp,
-                                                     const double* const* __restrict__ src, int bpi) {
+                                                     const double* const* __restrict__ src, int bpi,
+                                                     c2* spec) {
   extern __shared__ c2 smem[];
+  __shared__ InstDev rec;
   const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
   if (!src[gi]) return;
-  const InstDev* __restrict__ I = grp[gi];
+  const InstDev* __restrict__ I = rhs_record(grp[gi], &rec, spec);
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
   const int teams = blockDim.x / T;
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;
@@ -55,11 +70,13 @@ __global__ __launch_bounds__(256) void k_rhs_row_fwd(InstDev* const* __restrict_
 // their forward x-transforms into S0, S1, S2.
 template <class PX>
 __global__ __launch_bounds__(256) void k_rhs_row_mid(InstDev* const* __restrict__ grp,
-                                                     const double* const* __restrict__ src, int bpi) {
+                                                     const double* const* __restrict__ src, int bpi,
+                                                     c2* spec) {
   extern __shared__ c2 smem[];
+  __shared__ InstDev rec;
   const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
   if (!src[gi]) return;
-  const InstDev* __restrict__ I = grp[gi];
+  const InstDev* __restrict__ I = rhs_record(grp[gi], &rec, spec);
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
   const int teams = blockDim.x / T;
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;
@@ -86,11 +103,13 @@ __global__ __launch_bounds__(256) void k_rhs_row_mid(InstDev* const* __restrict_
 // Last row pass: R <- inverse x-transform of S0.
 template <class PX>
 __global__ __launch_bounds__(256) void k_rhs_row_inv(InstDev* const* __restrict__ grp,
-                                                     double* const* __restrict__ dst, int bpi) {
+                                                     double* const* __restrict__ dst, int bpi,
+                                                     c2* spec) {
   extern __shared__ c2 smem[];
+  __shared__ InstDev rec;
   const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
   if (!dst[gi]) return;
-  const InstDev* __restrict__ I = grp[gi];
+  const InstDev* __restrict__ I = rhs_record(grp[gi], &rec, spec);
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
   const int teams = blockDim.x / T;
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;
@@ -116,11 +135,13 @@ __global__ __launch_bounds__(256) void k_rhs_row_inv(InstDev* const* __restrict_
 //   STAGE 2 (FCH): fields S0 = F'^, S1 = p^, S2 = v^.
 template <class PY, int MODEL, int STAGE>
 __global__ __launch_bounds__(512) void k_rhs_col(InstDev* const* __restrict__ grp,
-                                                 const double* const* __restrict__ src, int bpi) {
+                                                 const double* const* __restrict__ src, int bpi,
+                                                 c2* spec) {
   extern __shared__ c2 smem[];
+  __shared__ InstDev rec;
   const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
   if (!src[gi]) return;
-  const InstDev* __restrict__ I = grp[gi];
+  const InstDev* __restrict__ I = rhs_record(grp[gi], &rec, spec);
   constexpr int N = PY::N, T = PY::T, RM = PY::RMAX;
   constexpr int F0 = STAGE == 1 ? 2 : 0;
   constexpr int F1 = MODEL == MODEL_PFC ? 2 : 3;  // fields F0 .. F1-1

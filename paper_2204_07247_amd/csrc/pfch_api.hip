@@ -218,6 +218,24 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ pa
 }
 
 // ---------------------------------------------------------------------------
+// Static scratch of the allocation-free R(v) entry point (pfch_rhs_noalloc):
+// the source and destination pointers in the first 256 bytes, then up to
+// three tiled spectral fields.  Each device holds its own copy until the
+// process ends; host code uses only the per-device address that
+// hipGetSymbolAddress returns (scratch_for_device), never the array's name.
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_SPECTRAL_BYTES = (size_t)32 << 20;
+constexpr size_t SCRATCH_PTR_BYTES = 256;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_PTR_BYTES + SCRATCH_SPECTRAL_BYTES];
+
+__global__ __launch_bounds__(64) void k_rhs_ptrs(const double** slot, const double* src, double* dst) {
+  if (threadIdx.x == 0) {
+    slot[0] = src;
+    slot[1] = dst;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host structures.
 // ---------------------------------------------------------------------------
 #define HIPCHK(x)                            \
@@ -332,6 +350,8 @@ struct pfch_ctx {
   std::map<int, hipGraphExec_t> graphs;  // key: chunk length K
   std::vector<hipGraph_t> graph_defs;
   int stats_detail = 1;
+  int device = -1;             // device current at pfch_create
+  void* scratch = nullptr;     // that device's address of the static scratch
   std::vector<void*> allocs;
   std::vector<void*> host_allocs;
 };
@@ -372,6 +392,28 @@ int halloc(std::vector<void*>& list, void** p, size_t bytes, bool coherent = fal
   }
   std::memset(*p, 0, bytes);
   list.push_back(*p);
+  return PFCH_OK;
+}
+
+// Address of `scratch` on device `dev`, looked up once per device (with
+// that device current) and kept for the process.
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex& scratch_mutex() {
+  static std::mutex m;
+  return m;
+}
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+int scratch_for_device(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return PFCH_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(scratch_mutex());
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return PFCH_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
   return PFCH_OK;
 }
 
@@ -1408,6 +1450,7 @@ const char* pfch_strerror(int code) {
     case PFCH_E_PRECOND: return "averaged-Newton preconditioner not positive";
     case PFCH_E_UNSUPPORTED: return "unsupported configuration";
     case PFCH_E_INTERNAL: return "internal error: a solve record was not final";
+    case PFCH_E_SCRATCH: return "grid too large for the static scratch of the allocation-free entry point";
     default: return "unknown error";
   }
 }
@@ -1478,8 +1521,16 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
     int rc = pfch_validate_desc(&descs[i]);
     if (rc) return rc;
   }
+  // the static scratch of pfch_rhs_noalloc on this device, resolved here so
+  // that the entry point itself makes no runtime look-up
+  int dev = -1;
+  void* scr = nullptr;
+  if (hipGetDevice(&dev) != hipSuccess) return PFCH_E_HIP;
+  if (int rc0 = scratch_for_device(dev, &scr)) return rc0;
   auto ctx = new (std::nothrow) pfch_ctx();
   if (!ctx) return PFCH_E_NOMEM;
+  ctx->device = dev;
+  ctx->scratch = scr;
   ctx->stream = (hipStream_t)hip_stream;
   ctx->inst.resize(n_inst);
   int rc = PFCH_OK;
@@ -2231,6 +2282,34 @@ int residual_norm(pfch_ctx* ctx, Instance& I, const double* x, const double* un,
 // R(v) = M Delta mu(v) for the members of group G with a non-null src[k]
 // (device field of member k) into dst[k].  Uses the members' spectral
 // workspaces.
+// The kernels of R(v) for the nm members of G: sources ps[k], destinations
+// pd[k] (device arrays of nm pointers), spectral workspace `spec` (null: each
+// instance's own).
+int rhs_kernels(pfch_ctx* ctx, Group& G, InstDev** grp, unsigned nm, const double** ps, double** pd,
+                c2* spec) {
+  int rbpi = G.srow_bpi, cbpi = G.scol_bpi, rc;
+  const dim3 rg(nm * rbpi), cg(nm * cbpi);
+  {
+    void* a[] = {&grp, &ps, &rbpi, &spec};
+    if ((rc = launch(G.rs.rhs_fwd, rg, G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
+  }
+  if (G.model == PFCH_FCH) {
+    void* a[] = {&grp, &ps, &cbpi, &spec};
+    if ((rc = launch(G.cs.rhs_lap, cg, G.scol_block, G.scol_lds, a, ctx->stream))) return rc;
+    void* b[] = {&grp, &ps, &rbpi, &spec};
+    if ((rc = launch(G.rs.rhs_mid, rg, G.srow_block, G.srow_lds, b, ctx->stream))) return rc;
+  }
+  {
+    void* a[] = {&grp, &ps, &cbpi, &spec};
+    if ((rc = launch(G.cs.rhs, cg, G.scol_block, G.scol_lds, a, ctx->stream))) return rc;
+  }
+  {
+    void* a[] = {&grp, &pd, &rbpi, &spec};
+    if ((rc = launch(G.rs.rhs_inv, rg, G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
+  }
+  return PFCH_OK;
+}
+
 int rhs_launch(pfch_ctx* ctx, Group& G, InstDev** grp, unsigned nm, const std::vector<const double*>& src,
                const std::vector<double*>& dst) {
   for (unsigned k = 0; k < nm; ++k) {
@@ -2239,29 +2318,7 @@ int rhs_launch(pfch_ctx* ctx, Group& G, InstDev** grp, unsigned nm, const std::v
   }
   HIPCHK(hipMemcpyAsync(G.d_rptr, G.h_rptr, sizeof(double*) * 2 * nm, hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));  // the pinned staging is reused
-  const double** ps = G.d_rptr;
-  double** pd = (double**)(G.d_rptr + nm);
-  int rbpi = G.srow_bpi, cbpi = G.scol_bpi, rc;
-  const dim3 rg(nm * rbpi), cg(nm * cbpi);
-  {
-    void* a[] = {&grp, &ps, &rbpi};
-    if ((rc = launch(G.rs.rhs_fwd, rg, G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
-  }
-  if (G.model == PFCH_FCH) {
-    void* a[] = {&grp, &ps, &cbpi};
-    if ((rc = launch(G.cs.rhs_lap, cg, G.scol_block, G.scol_lds, a, ctx->stream))) return rc;
-    void* b[] = {&grp, &ps, &rbpi};
-    if ((rc = launch(G.rs.rhs_mid, rg, G.srow_block, G.srow_lds, b, ctx->stream))) return rc;
-  }
-  {
-    void* a[] = {&grp, &ps, &cbpi};
-    if ((rc = launch(G.cs.rhs, cg, G.scol_block, G.scol_lds, a, ctx->stream))) return rc;
-  }
-  {
-    void* a[] = {&grp, &pd, &rbpi};
-    if ((rc = launch(G.rs.rhs_inv, rg, G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
-  }
-  return PFCH_OK;
+  return rhs_kernels(ctx, G, grp, nm, G.d_rptr, (double**)(G.d_rptr + nm), nullptr);
 }
 
 // Buffers of the adaptive estimators, and R(u^n), R(u^{n-1}) of every
@@ -2532,6 +2589,24 @@ int pfch_rhs(pfch_ctx* ctx, int32_t inst, const double* v, double* out) {
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return PFCH_OK;
+}
+
+int pfch_rhs_noalloc(pfch_ctx* ctx, int32_t inst, const double* v, double* out) {
+  if (!ctx || inst < 0 || inst >= (int)ctx->inst.size() || !v || !out || v == out) return PFCH_E_INVAL;
+  Instance& I = ctx->inst[inst];
+  if (I.nz > 1) return PFCH_E_UNSUPPORTED;
+  const size_t fields = I.d.model == PFCH_FCH ? 3 : 2;
+  if (fields * sizeof(c2) * (size_t)I.h.field_stride > SCRATCH_SPECTRAL_BYTES) return PFCH_E_SCRATCH;
+  if (!ctx->scratch) return PFCH_E_HIP;
+  unsigned char* base = static_cast<unsigned char*>(ctx->scratch);
+  const double** slot = reinterpret_cast<const double**>(base);
+  {
+    void* a[] = {&slot, &v, &out};
+    int rc = launch((const void*)&k_rhs_ptrs, dim3(1), dim3(64), 0, a, ctx->stream);
+    if (rc) return rc;
+  }
+  return rhs_kernels(ctx, ctx->groups[I.group], I.d_solo, 1, slot, const_cast<double**>(slot + 1),
+                     reinterpret_cast<c2*>(base + SCRATCH_PTR_BYTES));
 }
 
 int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const double* u_n,

@@ -20,6 +20,7 @@ PFCH_E_NONFINITE = -5
 PFCH_E_PRECOND = -6
 PFCH_E_UNSUPPORTED = -7
 PFCH_E_INTERNAL = -8
+PFCH_E_SCRATCH = -9
 
 PFC, FCH = 0, 1
 BDF2, MP, LBDF2, LMP = 0, 1, 2, 3
@@ -37,7 +38,7 @@ EXPORTED = (
     "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad", "pfch_fno_adam_step",
     "pfch_fno_prepare", "pfch_fno_destroy", "pfch_set_fno", "pfch_get_plan", "pfch_set_plan",
     "pfch_step_adaptive", "pfch_rhs", "pfch_fno_num_params_3d", "pfch_fno_create_3d",
-    "pfch_stop_status",
+    "pfch_stop_status", "pfch_rhs_noalloc",
 )
 
 
@@ -160,6 +161,8 @@ def lib():
         L.pfch_step_adaptive.restype = ctypes.c_int
         L.pfch_rhs.argtypes = [vp, i32, vp, vp]
         L.pfch_rhs.restype = ctypes.c_int
+        L.pfch_rhs_noalloc.argtypes = [vp, i32, vp, vp]
+        L.pfch_rhs_noalloc.restype = ctypes.c_int
         L.pfch_set_plan.restype = ctypes.c_int
         L.pfch_stop_status.argtypes = [i32, i32, ctypes.c_uint64, i32, ctypes.POINTER(i32),
                                        ctypes.POINTER(dbl)]
@@ -343,6 +346,11 @@ class Context:
         rc = lib().pfch_rhs(self._h, int(inst), _ptr(v), _ptr(out))
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_rhs")
+
+    def rhs_noalloc(self, inst, v, out):
+        """pfch_rhs_noalloc: out = M Delta mu(v) in the library's static
+        scratch, with no allocation or synchronisation; returns the code."""
+        return lib().pfch_rhs_noalloc(self._h, int(inst), _ptr(v), _ptr(out))
 
     def plan(self, inst=0):
         """Iteration-kernel plans of the instance's group (see pfch_get_plan)."""
