@@ -39,7 +39,7 @@ __device__ __forceinline__ const GLB T* gp(const T* p) {
   return (const GLB T*)p;
 }
 
-struct c2 {
+struct alignas(16) c2 {
   double x, y;
 };
 
@@ -178,9 +178,13 @@ __device__ __forceinline__ void dft(c2* x) {
   }
 }
 
-// LDS index with one pad element per 16 to break power-of-two strides.
-__device__ __forceinline__ int lds_idx(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int lds_len(int n) { return n + (n >> 4) + 1; }
+// LDS index with one pad element per 2^PFCH_LDS_PAD_SHIFT to break
+// power-of-two strides.
+#ifndef PFCH_LDS_PAD_SHIFT
+#define PFCH_LDS_PAD_SHIFT 4
+#endif
+__device__ __forceinline__ int lds_idx(int i) { return i + (i >> PFCH_LDS_PAD_SHIFT); }
+__host__ __device__ constexpr int lds_len(int n) { return n + (n >> PFCH_LDS_PAD_SHIFT) + 1; }
 
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 constexpr int clcm(int a, int b) { return a / cgcd(a, b) * b; }
