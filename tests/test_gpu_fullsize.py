@@ -64,3 +64,96 @@ def test_properties_over_steps_at_full_size(name):
             assert e <= e_prev + 1e-12 * abs(e_prev)
         e_prev = e
     ctx.close()
+
+
+# --- the batched and 3D configurations at their real sizes -----------------
+
+def _tuned():
+    """The plan choices bench.py runs with (recorded autotuner output)."""
+    import os
+    os.environ.setdefault("PFCH_TUNE_FILE", os.path.join(
+        os.path.dirname(bench.__file__), "paper_2204_07247_amd", "tune_mi355x.txt"))
+
+
+def _run_set(ws, nsteps):
+    """All of ws in one context, nsteps steps: final states and iteration counts."""
+    import torch
+    from paper_2204_07247_amd import pfch
+    ctx = pfch.Context([bench._desc(w) for w in ws])
+    ctx.set_stats_detail(0)
+    us = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    for i, u in enumerate(us):
+        ctx.set_state(i, u)
+    iters = [[] for _ in ws]
+    for _ in range(nsteps):
+        rc, st = ctx.step([w.dt for w in ws])
+        assert rc == pfch.PFCH_OK, pfch.strerror(rc)
+        for i, s in enumerate(st):
+            iters[i].append(s["iters"])
+    outs = []
+    for i, u in enumerate(us):
+        ctx.get_state(i, u)
+        outs.append(u)
+    ctx.close()
+    return outs, iters
+
+
+def test_3d_first_step_matches_oracle_at_full_size():
+    """PFC 192^3 (the 3D instance of the combined set): the first step
+    (backward Euler) field by field against the oracle."""
+    _tuned()
+    w = W.PFC192_3D
+    print(f"full size {w.name}", flush=True)
+    (got,), (iters,) = _run_set([w], 1)
+    ref, ref_iters = oracle_run(w, W.initial_condition(w), 1)
+    assert iters == ref_iters
+    assert rel_l2(got.cpu().numpy(), ref) <= 1e-9
+
+
+def test_combined_set_batched_equals_solo_and_oracle():
+    """The combined set (8 FCH 1024^2 + 8 FCH 2048^2 with drawn eps and mean,
+    PFC 192^3) in one context for two steps (backward Euler, then BDF2):
+    every instance bitwise equal to its own solo run; the first FCH 1024^2
+    instance against the oracle."""
+    import torch
+    _tuned()
+    ws = W.fch_ensemble() + [W.PFC192_3D]
+    print(f"combined set: {len(ws)} instances, 2 steps", flush=True)
+    batch, biters = _run_set(ws, 2)
+    for w, got, it in zip(ws, batch, biters):
+        print(f"solo {w.name}", flush=True)
+        (solo,), (siters,) = _run_set([w], 2)
+        assert it == siters, w.name
+        assert torch.equal(got, solo), w.name
+    w0 = ws[0]
+    ref, ref_iters = oracle_run(w0, W.initial_condition(w0), 2)
+    assert biters[0] == ref_iters
+    assert rel_l2(batch[0].cpu().numpy(), ref) <= 1e-9
+
+
+def test_pfc_ensemble_at_real_sizes():
+    """The 64-instance PFC ensemble (Nx, Ny in {128, 256, 512}, drawn eps and
+    mean, MP) in one context for two steps: every instance bitwise equal to
+    its solo run; a sample (the 512 x 512 instances' first, the rectangles
+    512 x 128 and 128 x 512, a 256 x 256 one) against the oracle."""
+    import torch
+    _tuned()
+    ens = W.pfc_ensemble(count=64, steps=2)
+    print(f"pfc ensemble: {len(ens)} instances, 2 steps", flush=True)
+    batch, biters = _run_set(ens, 2)
+    for w, got, it in zip(ens, batch, biters):
+        (solo,), (siters,) = _run_set([w], 2)
+        assert it == siters, w.name
+        assert torch.equal(got, solo), w.name
+    picks = []
+    for shape in ((512, 512), (512, 128), (128, 512), (256, 256)):
+        idx = [i for i, w in enumerate(ens) if tuple(w.shape) == shape]
+        if idx:
+            picks.append(idx[0])
+    assert len(picks) >= 3
+    for i in picks:
+        w = ens[i]
+        print(f"oracle {w.name}", flush=True)
+        ref, ref_iters = oracle_run(w, W.initial_condition(w), 2)
+        assert biters[i] == ref_iters, w.name
+        assert rel_l2(batch[i].cpu().numpy(), ref) <= 1e-9, w.name
