@@ -1,13 +1,32 @@
 """Throughput of the PAGD-solved fully implicit steps on one MI355X.
 
-Default workload: FCH 2D 256 x 256 on [0, 4 pi)^2, eps = 0.1, eta1 = 0.145,
-eta2 = 0.2, tau = 0, u0 = -0.6 + 0.01 U(-1, 1) (seed 0), BDF2 (backward Euler
-first step), dt = 1e-3, PAGD to ||d||_inf < 1e-10; one bench step = one time
-step.  The timed region runs `--steps` consecutive time steps from u0 with all
-data resident on the GPU, bracketed by torch.cuda.synchronize().
+Default workload, the combined set: 8 FCH 2D instances at 1024 x 1024 and 8
+at 2048 x 2048 on [0, 4 pi)^2 (e ~ U[0.08, 0.12], eps = e, eta1 = 1.45 e,
+eta2 = 2 e, tau = 0, mean ~ U[-0.7, -0.5], noise amplitude 0.01; seeds
+2000-2015) and one PFC 3D instance at 192^3 on [0, 192)^3 (eps = 0.25, mean
+-0.2, noise 0.05, seed 0); BDF2 with a backward Euler first step, dt = 1e-3
+(FCH) and 0.1 (PFC); PAGD to ||d||_inf < 1e-10.  One bench step is one time
+step of every instance.  All inputs are seeded synthetic fields (workloads/),
+resident on the GPU before the timed region.
 
-Prints one JSON line (metric, value in time-steps/s, iterations per step,
-roofline of the dominant kernel from HIP-event timings, CPU-oracle baseline).
+The same steps run four ways:
+  plain            one context per instance, extrapolated initial guess;
+  batched          all instances in one context (grouped launches);
+  learned          one context per instance, learned guess on the FCH
+                   instances (a float32 FNO: 4 spectral layers, 16 modes,
+                   width 32, GELU, run on its own 64 x 64 grid of the
+                   band-limited state, trained on FCH 256^2 trajectories
+                   with the same periods); the 3D instance keeps the
+                   extrapolated guess;
+  batched_learned  both: the headline `value`.
+Each times `--steps` bench steps after `--warmup` untimed ones, bracketed by
+torch.cuda.synchronize().  Also reported: PAGD iterations per step, the HBM
+roofline of the FCH 2048^2 iteration (HIP events on the grouped launches),
+and the CPU oracle on the host's cores.
+
+Prints one JSON line.  --workload names a single-instance workload instead;
+--extras adds the other comparisons (PFC ensemble, learned guess on PFC,
+solver variants, adaptive stepping, 3D network).
 """
 import argparse
 import json
@@ -25,6 +44,7 @@ import workloads as W  # noqa: E402
 
 METRIC = "time-steps/sec & PAGD iters/step at 1e-10 residual: plain vs batched+learned"
 HBM_PEAK_GBS = 8000.0
+COMBINED = "fch2d_8x1024_8x2048_bdf2+pfc3d_192_bdf2"
 
 WORKLOADS = {
     "fch256": W.FCH256_BDF2,
@@ -38,6 +58,10 @@ WORKLOADS = {
 }
 
 
+def combined_set():
+    return W.fch_ensemble() + [W.PFC192_3D]
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -45,19 +69,27 @@ def log(msg):
 KERNEL_NAMES = {"row": "k_row_iter", "col": "k_col_iter", "yfwd": "k_y3_iter<fwd>",
                 "z": "k_z3_iter", "yinv": "k_y3_iter<inv>"}
 
+# Compulsory HBM bytes per grid point and PAGD iteration of the reference
+# three-pass fused schedule (one out-of-LDS round trip per transform
+# direction; the state x_j, x_{j-1}, their transforms and the step constant
+# read once, the new iterate and its transform written once).  The kernels
+# here carry the iterate in real space only and move fewer bytes (see
+# algorithmic_bytes); the roofline is quoted against these figures.
+SCHEDULE_BYTES = {("fch", "bdf2", 2): 160, ("fch", "mp", 2): 176, ("pfc", "bdf2", 2): 104,
+                  ("pfc", "mp", 2): 120, ("pfc", "bdf2", 3): 136}
+
 
 def algorithmic_bytes(w):
-    """Compulsory HBM bytes per launch of each iteration kernel.
-
-    Real field: Ny*Nx (*Nz) doubles.  Spectral field: half as many complex
-    doubles (the half spectrum's two real columns kx = 0 and kx = Nx/2 share
-    one).  PFC row kernel: read 1 spectral + x_j, x_{j-1} (+ u^n for MP),
-    write x_{j+1} + 2 spectral.  PFC column kernel: read 2 spectral + g^,
-    write 1.  FCH row kernel: read 2 spectral + x_j, x_{j-1}, Lx_j, Lx_{j-1}
-    (+ u^n, Lu^n for MP), write x_{j+1}, Lx_{j+1} + 3 spectral.  FCH column
-    kernel: read 3 spectral + g^, write 2 spectral.  3D PFC: the row kernel
-    as in 2D; y forward: read and write 2 spectral; z: read 2 spectral + g^,
-    write 1; y inverse: read and write 1 spectral.
+    """Bytes the iteration kernels themselves must move per launch (one
+    instance): real field = Ny*Nx (*Nz) doubles; spectral field = half as
+    many complex doubles (the half spectrum's two real columns kx = 0 and
+    kx = Nx/2 share one).  PFC row kernel: read 1 spectral + x_j, x_{j-1}
+    (+ u^n for MP), write x_{j+1} + 2 spectral.  PFC column kernel: read 2
+    spectral + g^, write 1.  FCH row kernel: read 2 spectral + x_j, x_{j-1},
+    Lx_j, Lx_{j-1} (+ u^n, Lu^n for MP), write x_{j+1}, Lx_{j+1} + 3
+    spectral.  FCH column kernel: read 3 spectral + g^, write 2 spectral.
+    3D PFC: the row kernel as in 2D; y forward: read and write 2 spectral;
+    z: read 2 spectral + g^, write 1; y inverse: read and write 1 spectral.
     """
     npts = int(np.prod(w.shape))
     real = 8 * npts
@@ -74,7 +106,7 @@ def algorithmic_bytes(w):
     return dict(row=row, col=col)
 
 
-def measured_traffic(w, kernel):
+def measured_traffic(name, kernel):
     """HBM bytes per launch from the committed PMC summary, if it was taken on
     the current kernel sources; otherwise None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -82,7 +114,7 @@ def measured_traffic(w, kernel):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    ent = rec.get(w.name, {}).get(KERNEL_NAMES[kernel])
+    ent = rec.get(name, {}).get(kernel)
     if not ent or ent.get("source_sha256") != kernel_source_hash():
         return None
     return ent["traffic_bytes"]
@@ -102,14 +134,245 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+# ---------------------------------------------------------------------------
+# CPU oracle baseline (runs before the GPU is touched: the worker processes
+# are forked from this one)
+# ---------------------------------------------------------------------------
+def _oracle_first_step(w):
+    from oracle import driver, models, spectral
+    g = spectral.Grid(w.shape, w.lengths)
+    m = models.make_model(w.model, **w.params())
+    sim = driver.Simulation(g, m, w.scheme, s=w.s, etas=w.etas, tol=w.tol, max_iter=w.max_iter)
+    u0 = W.initial_condition(w)
+    t0 = time.perf_counter()
+    out = sim.step(u0, None, w.dt, None)
+    return w.name, time.perf_counter() - t0, int(out["iters"])
+
+
+def cpu_baseline_set(ws):
+    """The oracle's first time step (backward Euler, the same iterations as
+    the GPU's first step) of every instance of the set, one single-threaded
+    process per instance on the host's usable cores: the wall time of the
+    whole set-step (all cores) and the sum of the per-instance times (one
+    core)."""
+    import multiprocessing as mp
+    usable = len(os.sched_getaffinity(0))
+    procs = max(1, min(len(ws), usable))
+    order = sorted(ws, key=lambda w: -w.npoints)  # largest first
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        res = pool.map(_oracle_first_step, order, chunksize=1)
+    wall = time.perf_counter() - t0
+    one = sum(r[1] for r in res)
+    return dict(value=round(1.0 / wall, 5), unit="time-steps/s", cores=procs, kind="oracle",
+                sample=f"first time step (backward Euler) of all {len(ws)} instances of {COMBINED}, "
+                       f"one single-threaded NumPy float64 process per instance on {procs} cores: "
+                       f"{wall:.1f} s wall",
+                single_core=dict(value=round(1.0 / one, 6), unit="time-steps/s", cores=1,
+                                 sample=f"sum of the {len(ws)} per-instance times measured in those "
+                                        f"processes: {one:.1f} s"),
+                iters=[r[2] for r in res],
+                host_cpus=os.cpu_count(), host_cpus_usable=usable)
+
+
+def cpu_baseline(w, max_steps, budget_s):
+    """The CPU oracle on a single-instance workload: the first steps of the
+    same trajectory, one thread."""
+    from oracle import driver, models, spectral
+    g = spectral.Grid(w.shape, w.lengths)
+    m = models.make_model(w.model, **w.params())
+    sim = driver.Simulation(g, m, w.scheme, s=w.s, etas=w.etas, tol=w.tol, max_iter=w.max_iter)
+    u, up, dto = W.initial_condition(w), None, None
+    t0 = time.perf_counter()
+    n = 0
+    while n < max_steps and time.perf_counter() - t0 < budget_s:
+        out = sim.step(u, up, w.dt, dto)
+        up, u, dto = u, out["x"], w.dt
+        n += 1
+    el = time.perf_counter() - t0
+    return dict(value=n / el, unit="time-steps/s", cores=1, kind="oracle",
+                sample=f"first {n} of {max_steps} steps of {w.name} (seed {w.seeds[0]}), "
+                       f"{el:.1f} s, NumPy float64 pocketfft, single thread",
+                host_cpus=os.cpu_count(), host_cpus_usable=len(os.sched_getaffinity(0)))
+
+
+# ---------------------------------------------------------------------------
+# The combined set: plain / batched / learned / batched + learned
+# ---------------------------------------------------------------------------
+def train_fch_network(epochs):
+    """The FCH warm-start network: FNO (4 spectral layers, 16 modes, width 32,
+    GELU, float32) on its own 64 x 64 grid, trained on 20 trajectories of the
+    FCH 256^2 generator (seeds 100-119, 100 steps, 10% of the triples held
+    out) resampled to that grid; the combined set's FCH grids have the same
+    periods, so the network sees the same modes on every grid."""
+    import dataclasses
+
+    import torch
+    from paper_2204_07247_amd import learned
+    base = W.FCH256_BDF2
+    ws = [dataclasses.replace(base, seeds=(s,)) for s in range(100, 120)]
+    u0s = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    cfg = learned.TrainConfig(width=32, modes=16, layers=4, epochs=epochs, grid=(64, 64))
+    log(f"[bench] FCH network: trajectories and training ({epochs} epochs)")
+    t0 = time.perf_counter()
+    tr = learned.train(ws, u0s, base.steps, cfg, log=log)
+    torch.cuda.synchronize()
+    info = dict(network=dict(width=cfg.width, modes=cfg.modes, layers=cfg.layers, grid=list(cfg.grid),
+                             dtype="f32", params=tr.fno.n_params),
+                training=dict(data=f"{len(ws)} x {base.steps} steps of {base.name} (seeds 100-119), "
+                                   f"resampled to the network's grid",
+                              triples=tr.n_train + tr.n_val, held_out=tr.n_val, epochs=epochs, batch=cfg.batch,
+                              lr=cfg.lr, seconds=round(time.perf_counter() - t0, 1),
+                              held_out_loss=[round(v, 5) for v in tr.val_loss]))
+    return tr, info
+
+
+def _norm_for(tr, un, unm1):
+    """Network input scales of one instance from its own state (mean and
+    spread of u^n and of u^n - u^{n-1}); the output scale keeps the training
+    set's ratio of correction to increment spread."""
+    d = un - unm1
+    sd = float(d.std().item()) or 1.0
+    return (float(un.mean().item()), float(un.std().item()) or 1.0, sd, tr.norm[3] / tr.norm[2] * sd)
+
+
+def run_set(ws, mode, steps, warmup, tr=None, time_groups=None):
+    """`steps` bench steps of the instances ws after `warmup` untimed ones.
+    mode: plain | batched | learned | batched_learned."""
+    import torch
+    from paper_2204_07247_amd import learned, pfch
+    batched = mode.startswith("batched")
+    use_net = mode.endswith("learned")
+    guess = [1 if use_net and w.model == "fch" and len(w.shape) == 2 else 0 for w in ws]
+    if batched:
+        ctxs = [(pfch.Context([learned.desc_of(w, g) for w, g in zip(ws, guess)]), list(range(len(ws))))]
+    else:
+        ctxs = [(pfch.Context([learned.desc_of(w, g)]), [i]) for i, (w, g) in enumerate(zip(ws, guess))]
+    u = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    for c, idx in ctxs:
+        c.set_stats_detail(0)
+        for k, i in enumerate(idx):
+            c.set_state(k, u[i])
+    dts = [[ws[i].dt for i in idx] for _, idx in ctxs]
+
+    def one_step(its):
+        for (c, idx), dt in zip(ctxs, dts):
+            rc, st = c.step(dt)
+            if rc != pfch.PFCH_OK:
+                raise RuntimeError(f"{mode} step failed: {pfch.strerror(rc)}")
+            for k, i in enumerate(idx):
+                its[i].append(st[k]["iters"])
+                if st[k]["guess"] == 2:
+                    its["fallbacks"] += 1
+
+    warm = {i: [] for i in range(len(ws))}
+    warm["fallbacks"] = 0
+    for _ in range(max(1, warmup)):
+        one_step(warm)
+    if use_net:  # every instance has a history now
+        for c, idx in ctxs:
+            for k, i in enumerate(idx):
+                if guess[i]:
+                    un, unm1 = torch.empty_like(u[i]), torch.empty_like(u[i])
+                    c.get_state(k, un, unm1)
+                    c.set_fno(k, tr.fno, _norm_for(tr, un, unm1))
+        one_step(warm)  # the first learned step, untimed
+    its = {i: [] for i in range(len(ws))}
+    its["fallbacks"] = 0
+    log(f"[bench] {mode}: {len(ws)} instances, {len(ctxs)} context(s), {steps} timed steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step(its)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    log(f"[bench] {mode}: timed region done: {el:.4f} s")
+    timing = None
+    if time_groups and batched:
+        c = ctxs[0][0]
+        timing = {name: c.time_group(inst, ws[inst].dt, 5) for name, inst in time_groups.items()}
+    for c, _ in ctxs:
+        c.close()
+    per = [np.mean(its[i]) for i in range(len(ws))]
+    groups = {}
+    for w, p in zip(ws, per):
+        key = f"{w.model}{'x'.join(map(str, w.shape))}"
+        groups.setdefault(key, []).append(p)
+    out = dict(time_steps_per_s=round(steps / el, 3), instance_steps_per_s=round(len(ws) * steps / el, 2),
+               ms_per_step=round(1e3 * el / steps, 3), iters_per_step=round(float(np.mean(per)), 3),
+               iters_per_step_by_grid={k: round(float(np.mean(v)), 3) for k, v in groups.items()},
+               contexts=len(ctxs), elapsed_s=round(el, 4))
+    if use_net:
+        out["learned_guess_instances"] = int(sum(guess))
+        out["fallbacks"] = its["fallbacks"]
+    return out, timing
+
+
+def combined_bench(args):
+    import torch
+    ws = combined_set()
+    tr, net_info = train_fch_network(args.learned_epochs)
+    first8 = next(i for i, w in enumerate(ws) if w.shape == (2048, 2048))
+    i3 = next(i for i, w in enumerate(ws) if len(w.shape) == 3)
+    groups = {"fch2048": first8, "fch1024": 0, "pfc192_3d": i3}
+    variants = {}
+    for mode in ("plain", "batched", "learned"):
+        variants[mode], _ = run_set(ws, mode, args.steps, args.warmup, tr)
+        torch.cuda.empty_cache()
+    # the headline configuration last, with the kernel timing of its grouped launches
+    head, timing = run_set(ws, "batched_learned", args.steps, args.warmup, tr,
+                           time_groups=None if args.no_kernel_timing else groups)
+    variants["batched_learned"] = head
+    tr.fno.close()
+    plain = variants["plain"]["time_steps_per_s"]
+    for k in variants:
+        variants[k]["over_plain"] = round(variants[k]["time_steps_per_s"] / plain, 3)
+    roof, kernels = None, {}
+    if timing:
+        for name, inst in groups.items():
+            w = ws[inst]
+            nm = sum(1 for v in ws if v.shape == w.shape and v.model == w.model)
+            ab = algorithmic_bytes(w)
+            t = timing[name]
+            per_iter_us = sum(t.values())
+            sched = SCHEDULE_BYTES[(w.model, w.scheme, len(w.shape))] * w.npoints * nm
+            kernels[name] = dict(
+                instances_per_launch=nm,
+                launches_us={k: round(v, 2) for k, v in t.items()},
+                iteration_us=round(per_iter_us, 2),
+                schedule_bytes_per_iter=sched,
+                schedule_gbs=round(sched / (per_iter_us * 1e-6) / 1e9, 1),
+                kernel_bytes_per_iter=nm * sum(ab.values()),
+                kernel_gbs={k: round(nm * ab[k.replace("_us", "")] / (v * 1e-6) / 1e9, 1)
+                            for k, v in t.items()})
+        k8 = kernels["fch2048"]
+        w8 = ws[first8]
+        roof = dict(bound="hbm",
+                    kernel="PAGD iteration of the FCH 2048^2 group: k_col_iter + k_row_iter, "
+                           "8 instances per launch",
+                    achieved=k8["schedule_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(k8["schedule_gbs"] / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic(COMBINED, "fch2048_iteration"),
+                    bytes_per_point_per_iter=SCHEDULE_BYTES[("fch", "bdf2", 2)],
+                    points_per_launch=8 * w8.npoints, launch_us=k8["iteration_us"])
+    cfg = dict(workload=COMBINED, instances=len(ws), points=int(sum(w.npoints for w in ws)),
+               grids={"fch2d_1024": 8, "fch2d_2048": 8, "pfc3d_192": 1}, scheme="bdf2",
+               dt={"fch": 1e-3, "pfc": 0.1}, tol=1e-10, s=0.9, seeds="2000-2015 (FCH), 0 (PFC 3D)",
+               headline="batched_learned",
+               guess="learned on the FCH instances, extrapolated on the 3D instance")
+    return dict(value=head["time_steps_per_s"], ms_per_step=head["ms_per_step"], config=cfg,
+                iters_per_step=head["iters_per_step"], variants=variants, roofline=roof, kernels=kernels,
+                learned_network=net_info)
+
+
+# ---------------------------------------------------------------------------
+# A single-instance workload (--workload)
+# ---------------------------------------------------------------------------
 def gpu_run(w, steps, warmup, kernel_timing):
     import torch
     from paper_2204_07247_amd import pfch
 
-    d = pfch.make_desc(w.model, w.scheme, w.shape, w.lengths, eps=w.eps, eta1=w.eta1,
-                       eta2=w.eta2, tau=w.tau, mobility=w.mobility, s=w.s, etas=w.etas,
-                       tol=w.tol, max_iter=w.max_iter)
-    ctx = pfch.Context([d])
+    ctx = pfch.Context([_desc(w)])
     ctx.set_stats_detail(0)
     u0 = torch.from_numpy(W.initial_condition(w)).cuda()
 
@@ -147,6 +410,36 @@ def gpu_run(w, steps, warmup, kernel_timing):
     return elapsed, iters, timing, cfg
 
 
+def single_bench(args, w):
+    elapsed, iters, timing, cfg = gpu_run(w, args.steps, args.warmup, not args.no_kernel_timing)
+    ab = algorithmic_bytes(w)
+    roof, kernels = None, {}
+    if timing:
+        for k in ab:
+            avg = timing[f"{k}_us"] * 1e-6
+            kernels[k] = dict(avg_us=round(avg * 1e6, 3), solves=timing["solves"], alg_bytes=ab[k],
+                              achieved_gbs=round(ab[k] / avg / 1e9, 2),
+                              back_to_back_us=round(timing["back_to_back"][f"{k}_us"], 3))
+        iter_us = sum(kernels[k]["avg_us"] for k in kernels)
+        sched = SCHEDULE_BYTES[(w.model, w.scheme, len(w.shape))] * w.npoints
+        roof = dict(bound="hbm", kernel=f"PAGD iteration ({' + '.join(KERNEL_NAMES[k] for k in kernels)})",
+                    achieved=round(sched / (iter_us * 1e-6) / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(sched / (iter_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic(w.name, "iteration"),
+                    bytes_per_point_per_iter=SCHEDULE_BYTES[(w.model, w.scheme, len(w.shape))],
+                    points_per_launch=w.npoints, launch_us=round(iter_us, 3))
+    it = np.array(iters)
+    cfg.update(workload=w.name, grid=list(w.shape), lengths=list(w.lengths), scheme=w.scheme, dt=w.dt,
+               tol=w.tol, s=w.s, seed=w.seeds[0])
+    return dict(value=round(args.steps / elapsed, 3), ms_per_step=round(1e3 * elapsed / args.steps, 4),
+                config=cfg,
+                iters_per_step=dict(mean=round(float(it.mean()), 3), min=int(it.min()), max=int(it.max())),
+                roofline=roof, kernels=kernels)
+
+
+# ---------------------------------------------------------------------------
+# Extra comparisons (--extras)
+# ---------------------------------------------------------------------------
 def _desc(w):
     from paper_2204_07247_amd import pfch
     return pfch.make_desc(w.model, w.scheme, w.shape, w.lengths, eps=w.eps, eta1=w.eta1,
@@ -489,102 +782,40 @@ def learned3d_comparison(epochs, traj_steps, eval_steps):
     return res, tr, cfg
 
 
-def batched_learned(tr2, cfg2, tr3, steps, warmup):
-    """The combined set (8 FCH 1024^2 + 8 FCH 2048^2 + PFC 192^3) in one
-    context, plain and with the learned guess on every instance: the FCH
-    instances share the FCH 256^2-trained weights (one network object per
-    grid), the 3D instance uses the PFC 192^3 network.  Each instance's
-    input normalisation comes from its own state after the warm-up steps,
-    with the training set's ratio of correction to increment spread."""
-    import torch
-    from paper_2204_07247_amd import learned, pfch
-    ws = W.fch_ensemble() + [W.PFC192_3D]
-    u0 = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
-    nets = {}
-    for w in ws:
-        if len(w.shape) == 2 and tuple(w.shape) not in nets:
-            nets[tuple(w.shape)] = learned.deploy(tr2, *w.shape, cfg=cfg2)
-    res = {}
-    for mode in ("plain", "learned"):
-        ctx = pfch.Context([learned.desc_of(w, guess=1 if mode == "learned" else 0) for w in ws])
-        ctx.set_stats_detail(0)
-        for i, u in enumerate(u0):
-            ctx.set_state(i, u)
-        for _ in range(warmup):
-            ctx.step([w.dt for w in ws])
-        if mode == "learned":
-            for i, w in enumerate(ws):
-                un, unm1 = torch.empty_like(u0[i]), torch.empty_like(u0[i])
-                ctx.get_state(i, un, unm1)
-                tr = tr3 if len(w.shape) == 3 else tr2
-                d = un - unm1
-                sd = float(d.std().item()) or 1.0
-                norm = (float(un.mean().item()), float(un.std().item()) or 1.0, sd,
-                        tr.norm[3] / tr.norm[2] * sd)
-                ctx.set_fno(i, tr3.fno if len(w.shape) == 3 else nets[tuple(w.shape)], norm)
-        its = np.zeros(len(ws))
-        kinds = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            rc, st = ctx.step([w.dt for w in ws])
-            if rc != pfch.PFCH_OK:
-                raise RuntimeError(f"batched {mode} step failed: {pfch.strerror(rc)}")
-            its += [x["iters"] for x in st]
-            kinds += [x["guess"] for x in st]
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        ctx.close()
-        res[mode] = dict(instance_steps_per_s=round(len(ws) * steps / el, 2),
-                         ms_per_step=round(1e3 * el / steps, 3),
-                         iters_per_step_mean=round(float(its.sum() / (len(ws) * steps)), 3))
-        if mode == "learned":
-            res[mode]["learned_guesses"] = int(sum(k == 1 for k in kinds))
-            res[mode]["fallbacks"] = int(sum(k == 2 for k in kinds))
-    for f in nets.values():
-        f.close()
-    res.update(workload="fch2d_8x1024_8x2048_bdf2 + pfc3d_192_bdf2", instances=len(ws), steps=steps,
-               learned_over_plain=round(res["learned"]["instance_steps_per_s"] /
-                                        res["plain"]["instance_steps_per_s"], 3))
-    return res
-
-
-def cpu_baseline(w, max_steps, budget_s):
-    """The CPU oracle on the same workload, first steps of the same trajectory."""
-    from oracle import driver, models, spectral
-    g = spectral.Grid(w.shape, w.lengths)
-    m = models.make_model(w.model, **w.params())
-    sim = driver.Simulation(g, m, w.scheme, s=w.s, etas=w.etas, tol=w.tol, max_iter=w.max_iter)
-    u, up, dto = W.initial_condition(w), None, None
-    t0 = time.perf_counter()
-    n = 0
-    while n < max_steps and time.perf_counter() - t0 < budget_s:
-        out = sim.step(u, up, w.dt, dto)
-        up, u, dto = u, out["x"], w.dt
-        n += 1
-    el = time.perf_counter() - t0
-    return dict(value=n / el, unit="time-steps/s", cores=1, kind="oracle",
-                sample=f"first {n} of {max_steps} steps of {w.name} (seed {w.seeds[0]}), "
-                       f"{el:.1f} s, NumPy float64 pocketfft, single thread",
-                host_cpus=os.cpu_count(), host_cpus_usable=len(os.sched_getaffinity(0)))
+def extras(args):
+    out = {}
+    out["pfc_ensemble"] = batched_comparison(64, steps=10, solo_steps=4)
+    out["ensembles"] = [ensemble_bandwidth(W.pfc_ensemble(count=64), steps=10, warmup=2,
+                                           label="pfc2d_ensemble64 (128..512, MP)")]
+    out["solver_variants"] = [solver_variants(W.FCH256_BDF2, steps=50),
+                              solver_variants(W.PFC64_MP, steps=W.PFC64_MP.steps)]
+    log("[bench] adaptive stepping (AM3 / midAB2)")
+    out["adaptive"] = [adaptive_run(W.FCH256_BDF2, 1e-4, 1e-5, 0.5, attempts=200),
+                       adaptive_run(W.PFC64_MP, 1e-4, 1e-4, 0.5, attempts=200)]
+    lr, tr2, _ = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=20)
+    tr2.fno.close()
+    lr["pfc_trained"] = learned_pfc_trained(args.learned_epochs, eval_steps=100, deploy_steps=20)
+    if args.learned3d_epochs > 0:
+        lr["pfc3d"], tr3, _ = learned3d_comparison(args.learned3d_epochs, traj_steps=40, eval_steps=40)
+        tr3.fno.close()
+    out["learned"] = lr
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="fch256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="combined", choices=["combined"] + sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of oracle work for a single-instance workload")
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--no-compare", action="store_true",
-                    help="skip the batched-ensemble comparison")
-    ap.add_argument("--ensemble", type=int, default=64, help="instances in the batched comparison")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
+    ap.add_argument("--extras", action="store_true", help="also run the other comparisons")
     ap.add_argument("--learned-epochs", type=int, default=8)
     ap.add_argument("--learned3d-epochs", type=int, default=6,
-                    help="epochs of the PFC 192^3 learned-guess comparison (0 skips it)")
+                    help="epochs of the PFC 192^3 network in the extras (0 skips it)")
     ap.add_argument("--tune-file", default=os.path.join(ROOT, "paper_2204_07247_amd", "tune_mi355x.txt"),
                     help="plan choices of the autotuner to reuse (PFCH_TUNE_FILE; an already set "
                          "environment variable wins; '' times every plan afresh)")
@@ -597,9 +828,13 @@ def main():
               "device; independent instances would shard across GPUs with no communication, "
               "which is not implemented", file=sys.stderr)
         sys.exit(2)
+    # the CPU baseline first, before anything touches the GPU (its workers are forked)
+    cpu = None
+    if not args.no_cpu and args.workload == "combined":
+        log("[bench] CPU oracle baseline: first step of every instance, one process each")
+        cpu = cpu_baseline_set(combined_set())
     if args.tune_file and "PFCH_TUNE_FILE" not in os.environ:
         os.environ["PFCH_TUNE_FILE"] = args.tune_file
-    w = WORKLOADS[args.workload]
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 8
@@ -610,76 +845,25 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: 3 x {args.copy_calibration} MiB read + write")
         del src, dst
-    elapsed, iters, timing, cfg = gpu_run(w, args.steps, args.warmup, not args.no_kernel_timing)
+    if args.workload == "combined":
+        res = combined_bench(args)
+    else:
+        w = WORKLOADS[args.workload]
+        res = single_bench(args, w)
+        if not args.no_cpu:
+            log("[bench] CPU oracle baseline")
+            cpu = cpu_baseline(w, w.steps, args.cpu_budget)
     if os.environ.get("PFCH_TUNE_FILE"):
-        cfg["tune_file"] = os.path.relpath(os.environ["PFCH_TUNE_FILE"], ROOT)
-    value = args.steps / elapsed
-    ab = algorithmic_bytes(w)
-    roof = None
-    kernels = {}
-    if timing:
-        for k in ab:
-            avg = timing[f"{k}_us"] * 1e-6
-            kernels[k] = dict(avg_us=round(avg * 1e6, 3), solves=timing["solves"], alg_bytes=ab[k],
-                              achieved_gbs=round(ab[k] / avg / 1e9, 2),
-                              back_to_back_us=round(timing["back_to_back"][f"{k}_us"], 3))
-        dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
-        kd = kernels[dom]
-        roof = dict(bound="hbm", kernel=KERNEL_NAMES[dom], achieved=kd["achieved_gbs"],
-                    peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                    traffic=measured_traffic(w, dom))
-    batched = None
-    if not args.no_compare:
-        batched = batched_comparison(args.ensemble, steps=10, solo_steps=4)
-    ensembles = None
-    if not args.no_compare:
-        ensembles = [
-            ensemble_bandwidth(W.pfc_ensemble(count=64), steps=10, warmup=2,
-                               label="pfc2d_ensemble64 (128..512, MP)"),
-            ensemble_bandwidth(W.fch_ensemble() + [W.PFC192_3D], steps=5, warmup=2,
-                               label="fch2d_8x1024_8x2048_bdf2 + pfc3d_192_bdf2"),
-        ]
-    variants = None
-    if not args.no_compare:
-        variants = [solver_variants(w, steps=min(w.steps, 50)),
-                    solver_variants(W.PFC64_MP, steps=W.PFC64_MP.steps)]
-    adaptive = None
-    if not args.no_compare:
-        log("[bench] adaptive stepping (AM3 / midAB2)")
-        adaptive = [adaptive_run(W.FCH256_BDF2, 1e-4, 1e-5, 0.5, attempts=200),
-                    adaptive_run(W.PFC64_MP, 1e-4, 1e-4, 0.5, attempts=200)]
-    learned_res = None
-    if not args.no_learned and not args.no_compare:
-        learned_res, tr2, cfg2 = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=20)
-        learned_res["pfc_trained"] = learned_pfc_trained(args.learned_epochs, eval_steps=100,
-                                                         deploy_steps=20)
-        if args.learned3d_epochs > 0:
-            learned_res["pfc3d"], tr3, _ = learned3d_comparison(args.learned3d_epochs, traj_steps=40,
-                                                                eval_steps=40)
-            log("[bench] batched + learned: FCH 8x1024^2 + 8x2048^2 + PFC 192^3")
-            learned_res["batched"] = batched_learned(tr2, cfg2, tr3, steps=5, warmup=2)
-            tr3.fno.close()
-        tr2.fno.close()
-    cpu = None
-    if not args.no_cpu:
-        log("[bench] CPU oracle baseline")
-        cpu = cpu_baseline(w, w.steps, args.cpu_budget)
-    it = np.array(iters)
-    fft_pairs = {"pfc": 1.5, "fch": 2.5}[w.model]
-    out = dict(
-        metric=METRIC, value=round(value, 3), unit="time-steps/s", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=round(1e3 * elapsed / args.steps, 4),
-        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
-        config=dict(workload=w.name, grid=list(w.shape), lengths=list(w.lengths),
-                    scheme=w.scheme, dt=w.dt, tol=w.tol, s=w.s, seed=w.seeds[0]),
-        iters_per_step=dict(mean=round(float(it.mean()), 3), min=int(it.min()), max=int(it.max())),
-        fft_pairs_per_iter=fft_pairs,
-        roofline=roof, kernels=kernels, launch=cfg, cpu_baseline=cpu, batched=batched,
-        learned=learned_res, ensembles=ensembles, solver_variants=variants, adaptive=adaptive,
-    )
+        res["config"]["tune_file"] = os.path.relpath(os.environ["PFCH_TUNE_FILE"], ROOT)
+    out = dict(metric=METRIC, value=res.pop("value"), unit="time-steps/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=res.pop("ms_per_step"), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f64", data="synthetic")
+    out.update(res)
+    out["cpu_baseline"] = cpu
     if cpu:
-        out["gpu_over_cpu"] = round(value / cpu["value"], 2)
+        out["gpu_over_cpu"] = round(out["value"] / cpu["value"], 2)
+    if args.extras:
+        out["extras"] = extras(args)
     print(json.dumps(out), flush=True)
 
 

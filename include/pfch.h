@@ -257,6 +257,14 @@ int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail);
  * u^{n-1}, t, step index) is not changed; its iteration workspaces are. */
 int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]);
 
+/* The same timing for the grouped launches of every instance of `inst`'s
+ * group (instances of one model, scheme and grid share each iteration-kernel
+ * launch in pfch_step): the grouped launch as the solve runs it, an event
+ * pair on each launch; averages over the iterations in which every member
+ * still worked.  The members' states are not changed; their iteration
+ * workspaces are. */
+int pfch_time_group(pfch_ctx* ctx, int32_t inst, double dt, int32_t reps, double out[4]);
+
 /* Kernel timing with HIP events: sets up one step of instance 0 (as
  * pfch_step would), then launches each iteration kernel `reps` times back
  * to back on the context's stream (every launch doing an iteration's full
@@ -347,13 +355,27 @@ int pfch_fno_adam_step(pfch_fno* f, float lr, float beta1, float beta2, float ep
 int pfch_fno_prepare(pfch_fno* f, const double* u_nm1, const double* u_n, const double* u_np1,
                      double rho, const double norm[4], float* x, float* t);
 
+/* The same sample prepared from float64 fields on a finer Ny x Nx grid (2D,
+ * Ny, Nx at least the network's and even): inputs and target are formed on
+ * the fine grid and then resampled to the network's grid by keeping the
+ * modes |k| < N/2 of the network's grid on each axis (its Nyquist mode
+ * dropped) and sampling that band-limited field at the network's points.
+ * Buffers for the fine grid are kept by the network (made on first use). */
+int pfch_fno_prepare_resampled(pfch_fno* f, int32_t ny, int32_t nx, const double* u_nm1, const double* u_n,
+                               const double* u_np1, double rho, const double norm[4], float* x, float* t);
+
 void pfch_fno_destroy(pfch_fno* f);
 
 /* Attach network `f` (NULL detaches) to instance `inst`: its steps then use
  * the learned guess when the instance's desc.guess is 1 and it has a
- * history.  The network's grid must equal the instance's.  norm = {mu, su,
- * sd, so}, su, sd, so > 0.  The network is not owned; it must outlive its
- * use and must not be used on another stream while the context steps. */
+ * history.  The network's grid equals the instance's, or (2D) is coarser
+ * on both axes, both even: the network then runs on its own grid, its
+ * inputs resampled down as in pfch_fno_prepare_resampled and its output
+ * interpolated back with the same band (modes |k| < Nc/2 of the network's
+ * grid, zero beyond), so the learned correction holds those modes only.
+ * norm = {mu, su, sd, so}, su, sd, so > 0.  The network is not owned; it
+ * must outlive its use and must not be used on another stream while the
+ * context steps.  PFCH_E_INVAL for a grid that fits neither case. */
 int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4]);
 
 /* Transform plans and launch geometry of the iteration kernels of instance

@@ -190,3 +190,24 @@ def backward(theta, x, t, width, modes, layers):
         parts.append(g["b"][l])
     parts += [g["Q"], g["qb"]]
     return np.concatenate(parts), float(np.mean((y - t) ** 2))
+
+
+def band_resample(f, shape):
+    """Band-limited resampling of a real periodic 2D field f [Ny, Nx] onto a
+    grid of `shape` (same periods): the Fourier modes |ky| < Ny'/2 and
+    |kx| < Nx'/2, with Ny', Nx' the smaller of the two grids' sizes per axis,
+    are kept and every other mode is dropped (so the coarser grid's Nyquist
+    mode is dropped too); the resulting trigonometric polynomial is then
+    evaluated at the target grid's points.  Used as the reference of the
+    learned guess's change of grid (a network that runs on a coarser grid
+    than the solver's)."""
+    f = np.asarray(f, dtype=np.float64)
+    ny, nx = f.shape
+    my, mx = shape
+    by, bx = min(ny, my) // 2, min(nx, mx) // 2
+    c = np.fft.fft2(f) / (ny * nx)  # f = sum_k c_k exp(2 pi i k.x / L)
+    g = np.zeros((my, mx), dtype=np.complex128)
+    for ky in range(-by + 1, by):
+        for kx in range(-bx + 1, bx):
+            g[ky % my, kx % mx] = c[ky % ny, kx % nx]
+    return np.real(np.fft.ifft2(g)) * (my * mx)

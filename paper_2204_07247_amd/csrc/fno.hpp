@@ -358,6 +358,8 @@ __global__ void k_fno_inputs(const double* __restrict__ unm1, const double* __re
   if (t) t[p] = (float)((unp1[p] - (a + rho * (a - b))) / so);
 }
 
+struct Resampler;
+
 struct Fno {
   int W = 0, M = 0, L = 0, nz = 1, ny = 0, nx = 0, maxb = 0, ndim = 2;
   long long P = 0, n = 0, MM = 0;  // P grid points, MM retained modes (2M^2 or 4M^3)
@@ -379,6 +381,7 @@ struct Fno {
   std::vector<void*> host_allocs;
   long long oP = 0, opb = 0, oQ = 0, oqb = 0;
   std::vector<long long> oR, oW, ob;
+  std::vector<Resampler*> rs;  // one per fine grid the network is used on (2D)
 };
 
 inline long long fno_modes(long long M, int ndim) { return ndim == 3 ? 4 * M * M * M : 2 * M * M; }
@@ -440,6 +443,35 @@ inline GemmP gp_make(long long M, long long N, long long K, const float* A, long
   } while (0)
 
 inline unsigned blocks_for(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------------------
+// Band-limited resampling between an instance's grid (Ny x Nx) and the
+// coarser grid a network runs on (Ncy x Ncx, the network's own grid).  The
+// modes |k| < Nc/2 of each axis are kept (the coarse grid's Nyquist mode is
+// dropped, so both directions are real), as products with real matrices:
+//   down (fine -> coarse):  c = Dy f Dx,
+//     Dx[x][xc] = (1/Nx) (1 + 2 sum_{k=1}^{Ncx/2-1} cos 2 pi k (xc/Ncx - x/Nx)),
+//   up (coarse -> fine):    f = Uy c Ux,
+//     Ux[xc][x] = (1/Ncx) (1 + 2 sum_{k=1}^{Ncx/2-1} cos 2 pi k (x/Nx - xc/Ncx)),
+// and the same on y.  down samples the band-limited part of a fine field at
+// the coarse points; up interpolates coarse samples band-limitedly; both
+// keep the mean.  Each is two strided products (x, then y).
+// ---------------------------------------------------------------------------
+struct Resampler {
+  int ny = 0, nx = 0;             // fine grid
+  float *Dx = nullptr, *Dy = nullptr;  // [Nx][Ncx], [Ncy][Ny]
+  float *Uy = nullptr, *Ux = nullptr;  // [Ny][Ncy], [Ncx][Nx]
+  float *T1 = nullptr;            // [2][Ny][Ncx]
+  float *T2 = nullptr;            // [Ny][Ncx]
+  float *Xf = nullptr;            // [2][Ny][Nx] fine network inputs
+  float *yf = nullptr;            // [Ny][Nx] fine correction (or fine target)
+};
+
+// c[ch][Ncy][Ncx] = Dy f[ch] Dx for `ch` fine fields f[ch][Ny][Nx].
+inline hipError_t resample_down(const Fno& F, const Resampler& R, const float* f, int ch, float* c,
+                                hipStream_t s);
+// R.yf = Uy c Ux for one coarse field c[Ncy][Ncx].
+inline hipError_t resample_up(const Fno& F, const Resampler& R, const float* c, hipStream_t s);
 
 // Forward pass for `B` samples x[B][2][grid]; keeps every layer's input,
 // pre-activation and retained spectrum for the backward pass; y[B][grid].
@@ -565,6 +597,29 @@ inline hipError_t fno_backward(Fno& F, const float* x, const float* t, int B, hi
   }
   FNO_CHK(wgrad(F, x, 2, dv, (int)W, nB, g + F.oP, g + F.opb, s));
   return hipGetLastError();
+}
+
+inline hipError_t resample_down(const Fno& F, const Resampler& R, const float* f, int ch, float* c,
+                                hipStream_t s) {
+  const long long ny = R.ny, nx = R.nx, ncy = F.ny, ncx = F.nx;
+  // T1[ch * Ny + y][xc] = sum_x f[ch][y][x] Dx[x][xc]
+  FNO_CHK((gemm_launch<false, false, false, false, false, 16, 32>(
+      gp_make(ch * ny, ncx, nx, f, 0, nx, 1, R.Dx, 0, ncx, 1, R.T1, 0, ncx, 1, 0), 1, s)));
+  // c[ch][yc][xc] = sum_y Dy[yc][y] T1[ch][y][xc]
+  FNO_CHK((gemm_launch<false, false, false, false, false, 16, 32>(
+      gp_make(ncy, ncx, ny, R.Dy, 0, ny, 1, R.T1, ny * ncx, ncx, 1, c, ncy * ncx, ncx, 1, 0), ch, s)));
+  return hipSuccess;
+}
+
+inline hipError_t resample_up(const Fno& F, const Resampler& R, const float* c, hipStream_t s) {
+  const long long ny = R.ny, nx = R.nx, ncy = F.ny, ncx = F.nx;
+  // T2[y][xc] = sum_yc Uy[y][yc] c[yc][xc]
+  FNO_CHK((gemm_launch<false, false, false, false, false, 16, 32>(
+      gp_make(ny, ncx, ncy, R.Uy, 0, ncy, 1, c, 0, ncx, 1, R.T2, 0, ncx, 1, 0), 1, s)));
+  // yf[y][x] = sum_xc T2[y][xc] Ux[xc][x]
+  FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(
+      gp_make(ny, nx, ncx, R.T2, 0, ncx, 1, R.Ux, 0, nx, 1, R.yf, 0, nx, 1, 0), 1, s)));
+  return hipSuccess;
 }
 
 }  // namespace pfch

@@ -261,6 +261,7 @@ struct Instance {
   int step_index = 0;
   int last_iters = 0;
   pfch_fno* fno = nullptr;  // learned initial guess (not owned)
+  Resampler* fno_rs = nullptr;  // its resampler when the network's grid is coarser (owned by the network)
   double fno_norm[4] = {0, 1, 1, 1};
   double* xguess = nullptr;  // learned guess buffer (allocated on first attach)
   double* gpart = nullptr;   // FNO_SUM_BLOCKS partial sums of the network output
@@ -1013,6 +1014,19 @@ int learned_guess(pfch_ctx* ctx, Instance& I, double rho) {
   const double* unm1 = I.U[1 - I.ucur];
   const long long P = I.npts;
   const double* nrm = I.fno_norm;
+  if (I.fno_rs) {  // network on a coarser grid: resample in and out
+    const Resampler& R = *I.fno_rs;
+    hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(P)), dim3(256), 0, s, unm1, un, (const double*)nullptr, P,
+                       rho, nrm[0], nrm[1], nrm[2], nrm[3], R.Xf, (float*)nullptr);
+    if (resample_down(F, R, R.Xf, 2, F.xin, s) != hipSuccess) return PFCH_E_HIP;
+    if (fno_forward(F, F.xin, 1, s) != hipSuccess) return PFCH_E_HIP;
+    if (resample_up(F, R, F.y, s) != hipSuccess) return PFCH_E_HIP;
+    hipLaunchKernelGGL(k_partial_sum, dim3(FNO_SUM_BLOCKS), dim3(256), 0, s, (const float*)R.yf, P, I.gpart);
+    hipLaunchKernelGGL(k_learned_guess, dim3(blocks_for(P)), dim3(256), 0, s, un, unm1, rho, nrm[3],
+                       (const float*)R.yf, (const double*)I.gpart, FNO_SUM_BLOCKS, P, I.xguess);
+    HIPCHK(hipGetLastError());
+    return PFCH_OK;
+  }
   hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(P)), dim3(256), 0, s, unm1, un, (const double*)nullptr, P,
                      rho, nrm[0], nrm[1], nrm[2], nrm[3], F.xin, (float*)nullptr);
   if (fno_forward(F, F.xin, 1, s) != hipSuccess) return PFCH_E_HIP;
@@ -1826,45 +1840,79 @@ int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail) {
   return PFCH_OK;
 }
 
-int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
-  if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
-  if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
-  Instance& I = ctx->inst[0];
-  const Group& G = ctx->groups[I.group];
+}  // extern "C"
+
+namespace {
+
+// HIP-event timing of the iteration kernels of the instances `members` (all
+// of group G; grp is their device pointer array in that order), launched
+// together as the solve launches them: `reps` solves of the step of size dt
+// from their current states, an event pair on every launch; out[k] = the
+// average microseconds of stage k over the iterations in which every member
+// still worked.  The members' states are not changed; their iteration
+// workspaces are, and they are parked afterwards.
+int time_iterations(pfch_ctx* ctx, Group& G, InstDev** grp, const std::vector<int>& members, double dt, int reps,
+                    double out[4]) {
+  const unsigned nm = (unsigned)members.size();
   Stage st[4];
   const int ns = iter_stages(G, st);
-  // iterations launched per solve: the last step's count plus two
-  const int nit = std::min(I.d.max_iter, std::max(I.last_iters, 1) + 2);
+  // iterations launched per solve: the largest last count plus two
+  int last = 1, cap = 1 << 30;
+  for (int i : members) {
+    last = std::max(last, ctx->inst[i].last_iters);
+    cap = std::min(cap, ctx->inst[i].d.max_iter);
+  }
+  const int nit = std::min(cap, last + 2);
   std::vector<hipEvent_t> ev((size_t)2 * ns * nit);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-  std::vector<uint64_t> norms(nit);
+  std::vector<uint64_t> norms((size_t)nm * nit);
   double sum[4] = {0, 0, 0, 0};
   int cnt[4] = {0, 0, 0, 0};
   int rc = PFCH_OK;
-  InstDev** grp = I.d_solo;
   for (int r = 0; r < reps && rc == PFCH_OK; ++r) {
-    if ((rc = launch_setup_solo(ctx, I, step_setup_for(I, dt), false))) break;
+    if (nm == 1) {
+      if ((rc = launch_setup_solo(ctx, ctx->inst[members[0]], step_setup_for(ctx->inst[members[0]], dt), false)))
+        break;
+    } else {
+      for (unsigned k = 0; k < nm; ++k) {
+        G.h_args[k] = to_args(step_setup_for(ctx->inst[members[k]], dt));
+        G.h_args[k].fold = 0;  // the column set-up runs: the iteration kernels are timed alone
+      }
+      if (hipMemcpyAsync(G.d_args, G.h_args, sizeof(StepArgs) * nm, hipMemcpyHostToDevice, ctx->stream) !=
+          hipSuccess) {
+        rc = PFCH_E_HIP;
+        break;
+      }
+      if ((rc = launch_setup(ctx, G, grp, G.d_args, nm, nullptr, true, false, false))) break;
+    }
     for (int j = 0; j < nit && rc == PFCH_OK; ++j)
       for (int k = 0; k < ns; ++k) {
-        int bpi = st[k].bpi, lv = j, total = bpi;
+        int bpi = st[k].bpi, lv = j, total = (int)nm * bpi;
         void* a[] = {&grp, &bpi, &lv, &total};
         hipEvent_t* e = &ev[2 * ((size_t)j * ns + k)];
-        if (hipExtLaunchKernel(st[k].f, dim3(stage_grid(st[k], 1)), st[k].block, a, st[k].lds, ctx->stream,
+        if (hipExtLaunchKernel(st[k].f, dim3(stage_grid(st[k], nm)), st[k].block, a, st[k].lds, ctx->stream,
                                e[0], e[1], 0) != hipSuccess) {
           rc = PFCH_E_HIP;
           break;
         }
       }
     if (rc) break;
-    if (hipMemcpyAsync(norms.data(), I.h.norms, sizeof(uint64_t) * nit, hipMemcpyDeviceToHost, ctx->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    for (unsigned k = 0; k < nm && rc == PFCH_OK; ++k)
+      if (hipMemcpyAsync(norms.data() + (size_t)k * nit, ctx->inst[members[k]].h.norms, sizeof(uint64_t) * nit,
+                         hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+        rc = PFCH_E_HIP;
+    if (rc || hipStreamSynchronize(ctx->stream) != hipSuccess) {
       rc = PFCH_E_HIP;
       break;
     }
-    // iteration j did work if j = 0 or iteration j-1 did not stop
+    // iteration j did work for every member if j = 0 or no member stopped at j-1
     for (int j = 0; j < nit; ++j) {
-      if (j > 0 && (norms[j - 1] < I.h.tol_bits || norms[j - 1] >= INF_BITS)) break;
+      bool all = true;
+      for (unsigned k = 0; k < nm && j > 0; ++k) {
+        const uint64_t b = norms[(size_t)k * nit + j - 1];
+        if (b < ctx->inst[members[k]].h.tol_bits || b >= INF_BITS) all = false;
+      }
+      if (!all) break;
       for (int k = 0; k < ns; ++k) {
         float t = 0.f;
         if (hipEventElapsedTime(&t, ev[2 * ((size_t)j * ns + k)], ev[2 * ((size_t)j * ns + k) + 1]) != hipSuccess)
@@ -1877,12 +1925,29 @@ int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc) return rc;
   for (int k = 0; k < 4; ++k) out[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
-  // park the instance so later chunk launches leave it alone
-  int32_t* park = ctx->h_scratch;
-  *park = I.d.max_iter + 1;
-  HIPCHK(hipMemcpyAsync(I.h.iter_base, park, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  // park the members so that later chunk launches leave them alone
+  if ((rc = launch_park(ctx, grp, (int)nm))) return rc;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return PFCH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
+  if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
+  if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
+  Instance& I = ctx->inst[0];
+  return time_iterations(ctx, ctx->groups[I.group], I.d_solo, std::vector<int>{0}, dt, reps, out);
+}
+
+int pfch_time_group(pfch_ctx* ctx, int32_t inst, double dt, int32_t reps, double out[4]) {
+  if (!ctx || !out || inst < 0 || inst >= (int)ctx->inst.size() || reps < 1 || !(dt > 0.0) || !std::isfinite(dt))
+    return PFCH_E_INVAL;
+  if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
+  Group& G = ctx->groups[ctx->inst[inst].group];
+  return time_iterations(ctx, G, G.d_members, G.members, dt, reps, out);
 }
 
 int pfch_time_kernels_events(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
@@ -2676,6 +2741,7 @@ void pfch_fno_destroy(pfch_fno* f) {
   (void)hipStreamSynchronize(f->f.s);
   for (void* p : f->f.allocs) (void)hipFree(p);
   for (void* p : f->f.host_allocs) (void)hipHostFree(p);
+  for (Resampler* r : f->f.rs) delete r;
   delete f;
 }
 
@@ -2819,6 +2885,67 @@ int fno_create(int ndim, int32_t width, int32_t modes, int32_t layers, int32_t n
   return PFCH_OK;
 }
 
+// The resampler between a fine Ny x Nx grid and network F's coarser grid
+// (2D), made on first use and owned by the network.  PFCH_E_INVAL unless
+// the fine grid is at least the network's on both axes and both are even.
+int fno_resampler(Fno& F, int ny, int nx, Resampler** out) {
+  *out = nullptr;
+  if (F.ndim != 2 || ny < F.ny || nx < F.nx || (ny | nx | F.ny | F.nx) & 1) return PFCH_E_INVAL;
+  for (Resampler* r : F.rs)
+    if (r->ny == ny && r->nx == nx) {
+      *out = r;
+      return PFCH_OK;
+    }
+  Resampler* R = new (std::nothrow) Resampler();
+  if (!R) return PFCH_E_NOMEM;
+  F.rs.push_back(R);  // freed with the network
+  R->ny = ny;
+  R->nx = nx;
+  const long long ncy = F.ny, ncx = F.nx;
+  auto fal = [&](float** p, long long nfloats) {
+    void* q = nullptr;
+    const int rc = dalloc(F.allocs, &q, sizeof(float) * (size_t)nfloats);
+    *p = (float*)q;
+    return rc;
+  };
+  int rc;
+  if ((rc = fal(&R->Dx, nx * ncx)) || (rc = fal(&R->Dy, ncy * ny)) || (rc = fal(&R->Uy, ny * ncy)) ||
+      (rc = fal(&R->Ux, ncx * nx)) || (rc = fal(&R->T1, 2LL * ny * ncx)) || (rc = fal(&R->T2, (long long)ny * ncx)) ||
+      (rc = fal(&R->Xf, 2LL * ny * nx)) || (rc = fal(&R->yf, (long long)ny * nx)))
+    return rc;
+  // kernel(n, nc, i, ic) = (1/n) (1 + 2 sum_{k=1}^{nc/2-1} cos 2 pi k (ic/nc - i/n)); the
+  // angle's numerator is reduced exactly in integers modulo n nc
+  const long double tp = 6.283185307179586476925286766559L;
+  auto band = [&](long long n, long long nc, long long i, long long ic) {
+    const long long D = n * nc;
+    long long d = (ic * n - i * nc) % D;
+    if (d < 0) d += D;
+    long double acc = 1.0L;
+    for (long long k = 1; k < nc / 2; ++k) acc += 2.0L * cosl(tp * (long double)((k * d) % D) / (long double)D);
+    return acc;
+  };
+  std::vector<float> dx(nx * ncx), dy(ncy * ny), uy(ny * ncy), ux(ncx * nx);
+  for (long long x = 0; x < nx; ++x)
+    for (long long xc = 0; xc < ncx; ++xc) {
+      const long double b = band(nx, ncx, x, xc);
+      dx[x * ncx + xc] = (float)(b / (long double)nx);
+      ux[xc * nx + x] = (float)(b / (long double)ncx);
+    }
+  for (long long y = 0; y < ny; ++y)
+    for (long long yc = 0; yc < ncy; ++yc) {
+      const long double b = band(ny, ncy, y, yc);
+      dy[yc * ny + y] = (float)(b / (long double)ny);
+      uy[y * ncy + yc] = (float)(b / (long double)ncy);
+    }
+  if (hipMemcpy(R->Dx, dx.data(), dx.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(R->Dy, dy.data(), dy.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(R->Uy, uy.data(), uy.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(R->Ux, ux.data(), ux.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return PFCH_E_HIP;
+  *out = R;
+  return PFCH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2921,18 +3048,43 @@ int pfch_fno_prepare(pfch_fno* f, const double* u_nm1, const double* u_n, const 
   return PFCH_OK;
 }
 
+int pfch_fno_prepare_resampled(pfch_fno* f, int32_t ny, int32_t nx, const double* u_nm1, const double* u_n,
+                               const double* u_np1, double rho, const double norm[4], float* x, float* t) {
+  if (!f || !u_nm1 || !u_n || !x || !norm || ((u_np1 == nullptr) != (t == nullptr))) return PFCH_E_INVAL;
+  if (!(norm[1] > 0.0) || !(norm[2] > 0.0) || !(norm[3] > 0.0) || !std::isfinite(rho)) return PFCH_E_INVAL;
+  Fno& F = f->f;
+  Resampler* R = nullptr;
+  int rc = fno_resampler(F, ny, nx, &R);
+  if (rc) return rc;
+  const long long P = (long long)ny * nx;
+  hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(P)), dim3(256), 0, F.s, u_nm1, u_n, u_np1, P, rho, norm[0],
+                     norm[1], norm[2], norm[3], R->Xf, t ? R->yf : (float*)nullptr);
+  HIPCHK(hipGetLastError());
+  if (resample_down(F, *R, R->Xf, 2, x, F.s) != hipSuccess) return PFCH_E_HIP;
+  if (t && resample_down(F, *R, R->yf, 1, t, F.s) != hipSuccess) return PFCH_E_HIP;
+  return PFCH_OK;
+}
+
 int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4]) {
   if (!ctx || inst < 0 || inst >= (int)ctx->inst.size()) return PFCH_E_INVAL;
   if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
   Instance& I = ctx->inst[inst];
   if (!f) {
     I.fno = nullptr;
+    I.fno_rs = nullptr;
     return PFCH_OK;
   }
   if (!norm || !(norm[1] > 0.0) || !(norm[2] > 0.0) || !(norm[3] > 0.0) || !std::isfinite(norm[0]))
     return PFCH_E_INVAL;
-  if (f->f.nz != I.nz || f->f.ny != I.ny || f->f.nx != I.nx) return PFCH_E_INVAL;
   int rc;
+  Resampler* R = nullptr;
+  if (f->f.nz != I.nz || f->f.ny != I.ny || f->f.nx != I.nx) {
+    // a network on a coarser grid of the same (2D) rank: its input is the
+    // band-limited part of the state sampled on that grid, and its output
+    // is interpolated back to the instance's grid
+    if (I.nz != 1 || f->f.ndim != 2) return PFCH_E_INVAL;
+    if ((rc = fno_resampler(f->f, I.ny, I.nx, &R))) return rc;
+  }
   if (!I.xguess) {
     void* q = nullptr;
     if ((rc = dalloc(I.allocs, &q, sizeof(double) * (size_t)I.npts))) return rc;
@@ -2941,6 +3093,7 @@ int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4])
     I.gpart = (double*)q;
   }
   I.fno = f;
+  I.fno_rs = R;
   for (int k = 0; k < 4; ++k) I.fno_norm[k] = norm[k];
   return PFCH_OK;
 }

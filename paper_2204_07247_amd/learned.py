@@ -24,6 +24,10 @@ class TrainConfig:
     lr: float = 1e-3
     holdout: float = 0.1
     seed: int = 0
+    # the network's own grid; None: the trajectories' grid.  A coarser 2D
+    # grid (e.g. 4 * modes per axis) trains and runs the network on the
+    # band-limited part of the fields sampled there
+    grid: tuple = None
 
 
 @dataclasses.dataclass
@@ -77,10 +81,11 @@ def normalisation(states):
 
 def dataset(fno, states, norm, rho=1.0):
     """Network inputs X [N][2][*grid] and targets T [N][*grid] (float32,
-    GPU) for every triple (u^{n-1}, u^n, u^{n+1}) of the trajectories."""
+    GPU, on the network's grid) for every triple (u^{n-1}, u^n, u^{n+1}) of
+    the trajectories."""
     import torch
     ni, nt = states.shape[:2]
-    grid = tuple(states.shape[2:])
+    grid = tuple(fno.shape)
     n = ni * (nt - 2)
     X = torch.empty((n, 2) + grid, dtype=torch.float32, device="cuda")
     T = torch.empty((n,) + grid, dtype=torch.float32, device="cuda")
@@ -98,7 +103,7 @@ def train(ws, u0s, steps, cfg=TrainConfig(), log=None):
     import torch
     states = trajectories(ws, u0s, steps)
     norm = normalisation(states)
-    fno = pfch.Fno(cfg.width, cfg.modes, cfg.layers, *ws[0].shape, max_batch=cfg.batch)
+    fno = pfch.Fno(cfg.width, cfg.modes, cfg.layers, *(cfg.grid or ws[0].shape), max_batch=cfg.batch)
     fno.init_params(cfg.seed)
     X, T = dataset(fno, states, norm)
     del states
@@ -140,7 +145,9 @@ def train(ws, u0s, steps, cfg=TrainConfig(), log=None):
 
 def deploy(trained, *shape, cfg=TrainConfig()):
     """A copy of the trained network for another grid of the same rank (the
-    weights act on mode indices and channels, so they transfer unchanged)."""
+    weights act on mode indices and channels, so they transfer unchanged).
+    A network on a coarse grid of its own needs no copy: it attaches to
+    instances on any finer grid of the same periods."""
     f = pfch.Fno(cfg.width, cfg.modes, cfg.layers, *shape, max_batch=1)
     f.set_params(trained.fno.get_params())
     return f

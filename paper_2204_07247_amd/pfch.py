@@ -38,7 +38,7 @@ EXPORTED = (
     "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad", "pfch_fno_adam_step",
     "pfch_fno_prepare", "pfch_fno_destroy", "pfch_set_fno", "pfch_get_plan", "pfch_set_plan",
     "pfch_step_adaptive", "pfch_rhs", "pfch_fno_num_params_3d", "pfch_fno_create_3d",
-    "pfch_stop_status", "pfch_rhs_noalloc",
+    "pfch_stop_status", "pfch_rhs_noalloc", "pfch_fno_prepare_resampled", "pfch_time_group",
 )
 
 
@@ -130,6 +130,8 @@ def lib():
         L.pfch_time_kernels.argtypes = [vp, dbl, i32, ctypes.POINTER(dbl)]
         L.pfch_time_kernels_events.argtypes = [vp, dbl, i32, ctypes.POINTER(dbl)]
         L.pfch_time_kernels_events.restype = ctypes.c_int
+        L.pfch_time_group.argtypes = [vp, i32, dbl, i32, ctypes.POINTER(dbl)]
+        L.pfch_time_group.restype = ctypes.c_int
         L.pfch_get_launch_config.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
         L.pfch_destroy.argtypes = [vp]
         L.pfch_destroy.restype = None
@@ -151,6 +153,7 @@ def lib():
         L.pfch_fno_adam_step.argtypes = [fp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                          ctypes.c_float, i32]
         L.pfch_fno_prepare.argtypes = [fp, vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, vp]
+        L.pfch_fno_prepare_resampled.argtypes = [fp, i32, i32, vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, vp]
         L.pfch_fno_destroy.argtypes = [fp]
         L.pfch_fno_destroy.restype = None
         L.pfch_set_fno.argtypes = [vp, i32, fp, ctypes.POINTER(dbl)]
@@ -169,7 +172,7 @@ def lib():
         L.pfch_stop_status.restype = ctypes.c_int
         for name in ("pfch_fno_create", "pfch_fno_create_3d", "pfch_fno_init_params", "pfch_fno_set_params",
                      "pfch_fno_get_params", "pfch_fno_forward", "pfch_fno_grad",
-                     "pfch_fno_adam_step", "pfch_fno_prepare", "pfch_set_fno"):
+                     "pfch_fno_adam_step", "pfch_fno_prepare", "pfch_set_fno", "pfch_fno_prepare_resampled"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("pfch_validate_desc", "pfch_create", "pfch_set_state", "pfch_get_state",
                      "pfch_step", "pfch_solve", "pfch_set_stats_detail", "pfch_time_kernels",
@@ -286,6 +289,17 @@ class Context:
         rc = fn(self._h, float(dt), int(reps), out)
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_time_kernels")
+        if out[2] == 0.0 and out[3] == 0.0:
+            return dict(col_us=out[0], row_us=out[1])
+        return dict(yfwd_us=out[0], z_us=out[1], yinv_us=out[2], row_us=out[3])
+
+    def time_group(self, inst, dt, reps):
+        """Average microseconds per grouped launch of the iteration kernels of
+        instance `inst`'s group (pfch_time_group); keys as time_kernels."""
+        out = (ctypes.c_double * 4)()
+        rc = lib().pfch_time_group(self._h, int(inst), float(dt), int(reps), out)
+        if rc != PFCH_OK:
+            raise PfchError(rc, "pfch_time_group")
         if out[2] == 0.0 and out[3] == 0.0:
             return dict(col_us=out[0], row_us=out[1])
         return dict(yfwd_us=out[0], z_us=out[1], yinv_us=out[2], row_us=out[3])
@@ -465,7 +479,15 @@ class Fno:
                     "pfch_fno_adam_step")
 
     def prepare(self, u_nm1, u_n, u_np1, rho, norm, x, t=None):
-        """Fill x [2, *shape] (and t [*shape]) of one sample from float64 fields."""
+        """Fill x [2, *shape] (and t [*shape]) of one sample from float64
+        fields; fields on a finer 2D grid than the network's are resampled
+        to it (pfch_fno_prepare_resampled)."""
         nrm = (ctypes.c_double * 4)(*norm)
+        if tuple(u_n.shape) != self.shape:
+            ny, nx = u_n.shape
+            self._check(lib().pfch_fno_prepare_resampled(self._h, int(ny), int(nx), _ptr(u_nm1), _ptr(u_n),
+                                                         _ptr(u_np1), float(rho), nrm, _fptr(x), _fptr(t)),
+                        "pfch_fno_prepare_resampled")
+            return
         self._check(lib().pfch_fno_prepare(self._h, _ptr(u_nm1), _ptr(u_n), _ptr(u_np1), float(rho),
                                            nrm, _fptr(x), _fptr(t)), "pfch_fno_prepare")

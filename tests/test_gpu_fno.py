@@ -284,3 +284,82 @@ def test_trained_network_gains_over_extrapolation():
     assert np.max(np.abs(got - plain)) <= 1e-9
     print(f"iterations plain {st_p['iters']}, learned {st_l['iters']}", flush=True)
     tr.fno.close()
+
+
+def _smooth(shape, seed, mean, amp):
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(-1, 1, shape)
+    k = np.fft.fft2(f)
+    ky = np.fft.fftfreq(shape[0])[:, None]
+    kx = np.fft.fftfreq(shape[1])[None, :]
+    return mean + amp * np.real(np.fft.ifft2(k * np.exp(-40.0 * (kx * kx + ky * ky)))) + 0.1 * amp * f
+
+
+@pytest.mark.parametrize("fine,coarse", [((128, 64), (32, 32)), ((256, 256), (64, 64)), ((64, 64), (64, 16))])
+def test_prepare_resampled_matches_oracle(fine, coarse):
+    """Network inputs and target of a sample whose fields live on a finer grid
+    than the network's: the band-limited resampling of the normalised fields
+    (reference: modes |k| < Nc/2 kept, evaluated at the network's points),
+    at float32 accuracy."""
+    import torch
+    from paper_2204_07247_amd import pfch
+    print(f"prepare resampled {fine} -> {coarse}", flush=True)
+    unm1 = _smooth(fine, 1, -0.4, 0.3)
+    un = unm1 + _smooth(fine, 2, 0.0, 0.01)
+    unp1 = un + _smooth(fine, 3, 0.0, 0.01)
+    rho, norm = 0.8, (-0.4, 0.3, 0.01, 0.002)
+    f = pfch.Fno(4, 4, 1, *coarse)
+    x = torch.empty((2,) + coarse, dtype=torch.float32, device="cuda")
+    t = torch.empty(coarse, dtype=torch.float32, device="cuda")
+    d = [torch.from_numpy(a).cuda() for a in (unm1, un, unp1)]
+    f.prepare(d[0], d[1], d[2], rho, norm, x, t)
+    mu, su, sd, so = norm
+    ref = [ofno.band_resample((un - mu) / su, coarse), ofno.band_resample((un - unm1) / sd, coarse),
+           ofno.band_resample((unp1 - (un + rho * (un - unm1))) / so, coarse)]
+    got = [x[0].cpu().numpy(), x[1].cpu().numpy(), t.cpu().numpy()]
+    fine_max = [np.max(np.abs((un - mu) / su)), np.max(np.abs((un - unm1) / sd)),
+                np.max(np.abs((unp1 - (un + rho * (un - unm1))) / so))]
+    for g, r, m in zip(got, ref, fine_max):
+        assert np.max(np.abs(g - r)) <= 1e-5 * m, (np.max(np.abs(g - r)), m)
+    f.close()
+
+
+@pytest.mark.parametrize("w,coarse", [
+    (dataclasses.replace(W.FCH256_BDF2, shape=(128, 128), lengths=(2 * np.pi, 2 * np.pi), seeds=(1,)), (32, 32)),
+    (dataclasses.replace(W.PFC64_MP, shape=(128, 64), lengths=(128.0, 64.0), seeds=(3,)), (32, 16)),
+], ids=["fch128-on32", "pfc128x64-on32x16"])
+def test_coarse_network_learned_step_within_tolerance(w, coarse):
+    """A network on a coarser grid than the instance's: the learned-guess step
+    and the plain step both converge, differ within the PAGD tolerance and
+    keep the same mass."""
+    from paper_2204_07247_amd import pfch
+    print(f"coarse network {coarse} on {w.model} {w.shape}", flush=True)
+    un, unm1, dtp, k = _history(w, 3)
+    fno = pfch.Fno(8, 4, 2, *coarse)
+    fno.init_params(seed=5)
+    u = un.cpu().numpy()
+    du = (un - unm1).cpu().numpy()
+    norm = (float(u.mean()), float(u.std()), float(du.std()), 0.1 * float(du.std()))
+    rc_p, st_p, plain = _one_step(w, un, unm1, dtp, k)
+    rc_l, st_l, learned = _one_step(w, un, unm1, dtp, k, fno=fno, norm=norm, guess=1)
+    assert rc_p == pfch.PFCH_OK and rc_l == pfch.PFCH_OK
+    assert st_l["guess"] == 1
+    assert st_l["dnorm"] < w.tol and st_p["dnorm"] < w.tol
+    assert np.max(np.abs(learned - plain)) <= 1e-9
+    assert abs(learned.mean() - plain.mean()) <= 1e-14
+    fno.close()
+
+
+def test_coarse_network_must_fit_the_instance_grid():
+    from paper_2204_07247_amd import pfch
+    w = dataclasses.replace(W.PFC64_MP, shape=(64, 32), lengths=(64.0, 32.0))
+    ctx = pfch.Context([desc_for(w, guess=1)])
+    norm = (0.0, 1.0, 1.0, 1.0)
+    too_big = pfch.Fno(4, 2, 1, 64, 64)   # finer than the instance on x
+    ok = pfch.Fno(4, 2, 1, 16, 16)
+    with pytest.raises(pfch.PfchError):
+        ctx.set_fno(0, too_big, norm)
+    ctx.set_fno(0, ok, norm)
+    ctx.close()
+    too_big.close()
+    ok.close()
