@@ -1004,36 +1004,52 @@ int betas_host(pfch_ctx* ctx, Instance& I, double a, double out[4]) {
   return PFCH_OK;
 }
 
-// Learned initial guess of instance I for a step of size dt: network inputs
-// from (u^n, u^{n-1}), one forward pass on the context's stream, then
-// x0 = extrapolation + Pi_0(so * y) into I.xguess.
-int learned_guess(pfch_ctx* ctx, Instance& I, double rho) {
-  Fno& F = I.fno->f;
+// Learned initial guesses of the instances `ids` (extrapolation factors
+// rho[k]): network inputs from (u^n, u^{n-1}) (resampled to the network's
+// grid when it is coarser), one forward pass per network and batch of up to
+// its max_batch instances, then per instance x0 = extrapolation +
+// Pi_0(so * y) (y interpolated back to the instance's grid) into I.xguess;
+// all on the context's stream.
+int learned_guesses(pfch_ctx* ctx, const std::vector<int>& ids, const std::vector<double>& rho) {
   hipStream_t s = ctx->stream;
-  const double* un = I.U[I.ucur];
-  const double* unm1 = I.U[1 - I.ucur];
-  const long long P = I.npts;
-  const double* nrm = I.fno_norm;
-  if (I.fno_rs) {  // network on a coarser grid: resample in and out
-    const Resampler& R = *I.fno_rs;
-    hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(P)), dim3(256), 0, s, unm1, un, (const double*)nullptr, P,
-                       rho, nrm[0], nrm[1], nrm[2], nrm[3], R.Xf, (float*)nullptr);
-    if (resample_down(F, R, R.Xf, 2, F.xin, s) != hipSuccess) return PFCH_E_HIP;
-    if (fno_forward(F, F.xin, 1, s) != hipSuccess) return PFCH_E_HIP;
-    if (resample_up(F, R, F.y, s) != hipSuccess) return PFCH_E_HIP;
-    hipLaunchKernelGGL(k_partial_sum, dim3(FNO_SUM_BLOCKS), dim3(256), 0, s, (const float*)R.yf, P, I.gpart);
-    hipLaunchKernelGGL(k_learned_guess, dim3(blocks_for(P)), dim3(256), 0, s, un, unm1, rho, nrm[3],
-                       (const float*)R.yf, (const double*)I.gpart, FNO_SUM_BLOCKS, P, I.xguess);
+  std::vector<char> done(ids.size(), 0);
+  for (size_t a = 0; a < ids.size(); ++a) {
+    if (done[a]) continue;
+    pfch_fno* net = ctx->inst[ids[a]].fno;
+    Fno& F = net->f;
+    std::vector<size_t> chunk;
+    for (size_t b = a; b < ids.size() && (int)chunk.size() < F.maxb; ++b)
+      if (!done[b] && ctx->inst[ids[b]].fno == net) {
+        chunk.push_back(b);
+        done[b] = 1;
+      }
+    for (size_t k = 0; k < chunk.size(); ++k) {
+      Instance& I = ctx->inst[ids[chunk[k]]];
+      const double* nrm = I.fno_norm;
+      const long long P = I.npts;
+      float* xin = F.xin + (long long)k * 2 * F.P;
+      float* dst = I.fno_rs ? I.fno_rs->Xf : xin;
+      hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(P)), dim3(256), 0, s, I.U[1 - I.ucur], I.U[I.ucur],
+                         (const double*)nullptr, P, rho[chunk[k]], nrm[0], nrm[1], nrm[2], nrm[3], dst,
+                         (float*)nullptr);
+      if (I.fno_rs && resample_down(F, *I.fno_rs, I.fno_rs->Xf, 2, xin, s) != hipSuccess) return PFCH_E_HIP;
+    }
+    if (fno_forward(F, F.xin, (int)chunk.size(), s) != hipSuccess) return PFCH_E_HIP;
+    for (size_t k = 0; k < chunk.size(); ++k) {
+      Instance& I = ctx->inst[ids[chunk[k]]];
+      const long long P = I.npts;
+      const float* y = F.y + (long long)k * F.P;
+      if (I.fno_rs) {
+        if (resample_up(F, *I.fno_rs, y, s) != hipSuccess) return PFCH_E_HIP;
+        y = I.fno_rs->yf;
+      }
+      hipLaunchKernelGGL(k_partial_sum, dim3(FNO_SUM_BLOCKS), dim3(256), 0, s, y, P, I.gpart);
+      hipLaunchKernelGGL(k_learned_guess, dim3(blocks_for(P)), dim3(256), 0, s, (const double*)I.U[I.ucur],
+                         (const double*)I.U[1 - I.ucur], rho[chunk[k]], I.fno_norm[3], y, (const double*)I.gpart,
+                         FNO_SUM_BLOCKS, P, I.xguess);
+    }
     HIPCHK(hipGetLastError());
-    return PFCH_OK;
   }
-  hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(P)), dim3(256), 0, s, unm1, un, (const double*)nullptr, P,
-                     rho, nrm[0], nrm[1], nrm[2], nrm[3], F.xin, (float*)nullptr);
-  if (fno_forward(F, F.xin, 1, s) != hipSuccess) return PFCH_E_HIP;
-  hipLaunchKernelGGL(k_partial_sum, dim3(FNO_SUM_BLOCKS), dim3(256), 0, s, (const float*)F.y, P, I.gpart);
-  hipLaunchKernelGGL(k_learned_guess, dim3(blocks_for(P)), dim3(256), 0, s, un, unm1, rho, nrm[3],
-                     (const float*)F.y, (const double*)I.gpart, FNO_SUM_BLOCKS, P, I.xguess);
-  HIPCHK(hipGetLastError());
   return PFCH_OK;
 }
 
@@ -2129,6 +2145,18 @@ int launch_step_setups(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept
   o.dn.assign(n, 0.0);
   o.a.assign(n, 0.0);
   int rc;
+  // the learned guesses first: one network call per batch of instances
+  std::vector<int> lids;
+  std::vector<double> lrho;
+  for (int i = 0; i < n; ++i) {
+    const Instance& I = ctx->inst[i];
+    if (I.fno && I.d.guess == 1 && I.has_prev) {
+      lids.push_back(i);
+      lrho.push_back(step_setup_for(I, dt[i]).rho);
+      o.guess[i] = 1;
+    }
+  }
+  if (!lids.empty() && (rc = learned_guesses(ctx, lids, lrho))) return rc;
   for (auto& G : ctx->groups) {
     for (size_t k = 0; k < G.members.size(); ++k) {
       Instance& I = ctx->inst[G.members[k]];
@@ -2137,11 +2165,7 @@ int launch_step_setups(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept
         ss.acc_dst = I.U[1 - I.ucur];
         if (lap_history_pays(I)) ss.acc_ldst = I.dU[1 - I.ucur];
       }
-      if (I.fno && I.d.guess == 1 && I.has_prev) {
-        if ((rc = learned_guess(ctx, I, ss.rho))) return rc;
-        ss.xin = I.xguess;
-        o.guess[G.members[k]] = 1;
-      }
+      if (o.guess[G.members[k]] == 1) ss.xin = I.xguess;
       lap_from_history(I, ss);
       o.a[G.members[k]] = ss.a;
       G.h_args[k] = to_args(ss);

@@ -363,3 +363,48 @@ def test_coarse_network_must_fit_the_instance_grid():
     ctx.close()
     too_big.close()
     ok.close()
+
+
+def test_batched_learned_guesses_match_solo():
+    """Instances that share a network get their learned guesses from one
+    batched forward pass: each equals its run alone (the network's products
+    do not depend on the batch size), bit for bit."""
+    import torch
+    from paper_2204_07247_amd import pfch
+    w = dataclasses.replace(W.FCH256_BDF2, shape=(64, 64), lengths=(np.pi, np.pi))
+    print("batched learned guesses", flush=True)
+    fno = pfch.Fno(8, 4, 2, 32, 32, max_batch=2)   # three instances: batches of 2 and 1
+    fno.init_params(seed=11)
+    seeds = (21, 22, 23)
+    u0 = [torch.from_numpy(W.initial_condition(w, seed=s)).cuda() for s in seeds]
+
+    def run(idx):
+        ctx = pfch.Context([desc_for(w, guess=1) for _ in idx])
+        for k, i in enumerate(idx):
+            ctx.set_state(k, u0[i])
+        assert ctx.step(w.dt)[0] == pfch.PFCH_OK
+        for k, i in enumerate(idx):
+            un, unm1 = torch.empty_like(u0[i]), torch.empty_like(u0[i])
+            ctx.get_state(k, un, unm1)
+            d = un - unm1
+            ctx.set_fno(k, fno, (float(un.mean()), float(un.std()), float(d.std()), 0.1 * float(d.std())))
+        its = []
+        for _ in range(3):
+            rc, st = ctx.step(w.dt)
+            assert rc == pfch.PFCH_OK
+            assert all(s["guess"] == 1 for s in st)
+            its.append([s["iters"] for s in st])
+        out = []
+        for k in range(len(idx)):
+            o = torch.empty_like(u0[0])
+            ctx.get_state(k, o)
+            out.append(o)
+        ctx.close()
+        return out, its
+
+    batch, bits = run([0, 1, 2])
+    for i in range(3):
+        solo, sits = run([i])
+        assert [x[i] for x in bits] == [x[0] for x in sits]
+        assert torch.equal(batch[i], solo[0])
+    fno.close()
