@@ -317,6 +317,8 @@ def combined_bench(args):
     groups = {"fch2048": first8, "fch1024": 0, "pfc192_3d": i3}
     variants = {}
     for mode in ("plain", "batched", "learned"):
+        if args.only and args.only != mode:
+            continue
         variants[mode], _ = run_set(ws, mode, args.steps, args.warmup, tr)
         torch.cuda.empty_cache()
     # the headline configuration last, with the kernel timing of its grouped launches
@@ -324,9 +326,10 @@ def combined_bench(args):
                            time_groups=None if args.no_kernel_timing else groups)
     variants["batched_learned"] = head
     tr.fno.close()
-    plain = variants["plain"]["time_steps_per_s"]
-    for k in variants:
-        variants[k]["over_plain"] = round(variants[k]["time_steps_per_s"] / plain, 3)
+    if "plain" in variants:
+        plain = variants["plain"]["time_steps_per_s"]
+        for k in variants:
+            variants[k]["over_plain"] = round(variants[k]["time_steps_per_s"] / plain, 3)
     roof, kernels = None, {}
     if timing:
         for name, inst in groups.items():
@@ -813,6 +816,9 @@ def main():
                     help="seconds of oracle work for a single-instance workload")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also run the other comparisons")
+    ap.add_argument("--only", choices=["plain", "batched", "learned"],
+                    help="combined set: run this variant besides the headline batched_learned "
+                         "(profiling runs)")
     ap.add_argument("--learned-epochs", type=int, default=8)
     ap.add_argument("--learned3d-epochs", type=int, default=6,
                     help="epochs of the PFC 192^3 network in the extras (0 skips it)")

@@ -148,7 +148,7 @@ int pfch_get_state(pfch_ctx* ctx, int32_t inst, double* u_n, double* u_nm1, doub
  * instance whose solve fails keeps its state (the step is transactional per
  * instance); the return value is the first failing instance's code.
  * `st` is a host array of n_inst or NULL.  After a step whose sizes equal
- * the previous call's (and no learned guess), the next step's set-up is
+ * the previous call's, the next step's set-up (with its learned guesses) is
  * already queued on the context's stream when this returns; a following
  * pfch_step with the same sizes uses it, any other call on the context that
  * changes its state discards it.  Results do not depend on this. */

@@ -18,7 +18,7 @@ def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     src = os.path.join(CSRC, "pfch_api.hip")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, src, "-o", tmp]
+    cmd = [hipcc, *HIPCC_FLAGS, src, "-o", tmp, "-L/opt/rocm/lib", "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -18,6 +18,7 @@
 // or [2M][2M][M] (3D, kz, ky, kx), Wl[W][W], bl[W]; Q[W], qb.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -328,20 +329,27 @@ __global__ __launch_bounds__(256) void k_partial_sum(const float* __restrict__ y
 // Learned initial guess: x0 = u^n + rho (u^n - u^{n-1}) + so (y - mean(y)).
 // The correction is projected to zero mean so that x0 keeps the mass of the
 // extrapolation (the solve preserves the mean of its initial guess).
-__global__ void k_learned_guess(const double* __restrict__ un, const double* __restrict__ unm1, double rho,
-                                double so, const float* __restrict__ y, const double* __restrict__ part,
-                                int nparts, long long n, double* __restrict__ x0) {
-  __shared__ double mean;
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int k = 0; k < nparts; ++k) s += part[k];
-    mean = s / (double)n;
-  }
+// Launched with 256 threads per block; every block forms the mean from the
+// partial sums in the same fixed order (whole block, then a tree).
+__global__ __launch_bounds__(256) void k_learned_guess(const double* __restrict__ un,
+                                                       const double* __restrict__ unm1, double rho, double so,
+                                                       const float* __restrict__ y,
+                                                       const double* __restrict__ part, int nparts, long long n,
+                                                       double* __restrict__ x0) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += 256) s += part[k];
+  red[threadIdx.x] = s;
   __syncthreads();
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const double u = un[p];
-  x0[p] = u + rho * (u - unm1[p]) + so * ((double)y[p] - mean);
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double mean = red[0] / (double)n;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+    const double u = un[p];
+    x0[p] = u + rho * (u - unm1[p]) + so * ((double)y[p] - mean);
+  }
 }
 
 // Network inputs and (optional) targets from float64 fields:
@@ -382,6 +390,7 @@ struct Fno {
   long long oP = 0, opb = 0, oQ = 0, oqb = 0;
   std::vector<long long> oR, oW, ob;
   std::vector<Resampler*> rs;  // one per fine grid the network is used on (2D)
+  rocblas_handle blas = nullptr;  // the resampling products (made with the first resampler)
 };
 
 inline long long fno_modes(long long M, int ndim) { return ndim == 3 ? 4 * M * M * M : 2 * M * M; }
@@ -455,7 +464,8 @@ inline unsigned blocks_for(long long n, int t = 256) { return (unsigned)((n + t 
 //     Ux[xc][x] = (1/Ncx) (1 + 2 sum_{k=1}^{Ncx/2-1} cos 2 pi k (x/Nx - xc/Ncx)),
 // and the same on y.  down samples the band-limited part of a fine field at
 // the coarse points; up interpolates coarse samples band-limitedly; both
-// keep the mean.  Each is two strided products (x, then y).
+// keep the mean.  Each is two plain float32 matrix products (x, then y),
+// done by rocBLAS on the network's stream.
 // ---------------------------------------------------------------------------
 struct Resampler {
   int ny = 0, nx = 0;             // fine grid
@@ -599,26 +609,33 @@ inline hipError_t fno_backward(Fno& F, const float* x, const float* t, int B, hi
   return hipGetLastError();
 }
 
+// Row-major C[M][N] = A[M][K] B[K][N] (lda = K, ldb = N, ldc = N), `batch`
+// products with strides sA, sB, sC: column-major rocBLAS computes C^T = B^T A^T.
+inline hipError_t sgemm_rm(const Fno& F, int M, int N, int K, const float* A, long long sA, const float* B,
+                           long long sB, float* C, long long sC, int batch, hipStream_t s) {
+  const float one = 1.0f, zero = 0.0f;
+  if (rocblas_set_stream(F.blas, s) != rocblas_status_success) return hipErrorUnknown;
+  const rocblas_status st = rocblas_sgemm_strided_batched(F.blas, rocblas_operation_none, rocblas_operation_none, N, M,
+                                                          K, &one, B, N, sB, A, K, sA, &zero, C, N, sC, batch);
+  return st == rocblas_status_success ? hipSuccess : hipErrorUnknown;
+}
+
 inline hipError_t resample_down(const Fno& F, const Resampler& R, const float* f, int ch, float* c,
                                 hipStream_t s) {
-  const long long ny = R.ny, nx = R.nx, ncy = F.ny, ncx = F.nx;
+  const int ny = R.ny, nx = R.nx, ncy = F.ny, ncx = F.nx;
   // T1[ch * Ny + y][xc] = sum_x f[ch][y][x] Dx[x][xc]
-  FNO_CHK((gemm_launch<false, false, false, false, false, 16, 32>(
-      gp_make(ch * ny, ncx, nx, f, 0, nx, 1, R.Dx, 0, ncx, 1, R.T1, 0, ncx, 1, 0), 1, s)));
+  FNO_CHK(sgemm_rm(F, ch * ny, ncx, nx, f, 0, R.Dx, 0, R.T1, 0, 1, s));
   // c[ch][yc][xc] = sum_y Dy[yc][y] T1[ch][y][xc]
-  FNO_CHK((gemm_launch<false, false, false, false, false, 16, 32>(
-      gp_make(ncy, ncx, ny, R.Dy, 0, ny, 1, R.T1, ny * ncx, ncx, 1, c, ncy * ncx, ncx, 1, 0), ch, s)));
+  FNO_CHK(sgemm_rm(F, ncy, ncx, ny, R.Dy, 0, R.T1, (long long)ny * ncx, c, (long long)ncy * ncx, ch, s));
   return hipSuccess;
 }
 
 inline hipError_t resample_up(const Fno& F, const Resampler& R, const float* c, hipStream_t s) {
-  const long long ny = R.ny, nx = R.nx, ncy = F.ny, ncx = F.nx;
+  const int ny = R.ny, nx = R.nx, ncy = F.ny, ncx = F.nx;
   // T2[y][xc] = sum_yc Uy[y][yc] c[yc][xc]
-  FNO_CHK((gemm_launch<false, false, false, false, false, 16, 32>(
-      gp_make(ny, ncx, ncy, R.Uy, 0, ncy, 1, c, 0, ncx, 1, R.T2, 0, ncx, 1, 0), 1, s)));
+  FNO_CHK(sgemm_rm(F, ny, ncx, ncy, R.Uy, 0, c, 0, R.T2, 0, 1, s));
   // yf[y][x] = sum_xc T2[y][xc] Ux[xc][x]
-  FNO_CHK((gemm_launch<false, false, false, false, false, 32, 64>(
-      gp_make(ny, nx, ncx, R.T2, 0, ncx, 1, R.Ux, 0, nx, 1, R.yf, 0, nx, 1, 0), 1, s)));
+  FNO_CHK(sgemm_rm(F, ny, nx, ncx, R.T2, 0, R.Ux, 0, R.yf, 0, 1, s));
   return hipSuccess;
 }
 

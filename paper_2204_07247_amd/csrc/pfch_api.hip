@@ -1044,7 +1044,8 @@ int learned_guesses(pfch_ctx* ctx, const std::vector<int>& ids, const std::vecto
         y = I.fno_rs->yf;
       }
       hipLaunchKernelGGL(k_partial_sum, dim3(FNO_SUM_BLOCKS), dim3(256), 0, s, y, P, I.gpart);
-      hipLaunchKernelGGL(k_learned_guess, dim3(blocks_for(P)), dim3(256), 0, s, (const double*)I.U[I.ucur],
+      hipLaunchKernelGGL(k_learned_guess, dim3(std::min(blocks_for(P), 4096u)), dim3(256), 0, s,
+                         (const double*)I.U[I.ucur],
                          (const double*)I.U[1 - I.ucur], rho[chunk[k]], I.fno_norm[3], y, (const double*)I.gpart,
                          FNO_SUM_BLOCKS, P, I.xguess);
     }
@@ -2519,9 +2520,10 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
   }
   // A loop at a fixed step size: enqueue the next step's set-up now, so that
   // it runs while control is with the caller.  Only when every instance
-  // advanced and none uses a learned guess (its network may be shared).
-  bool speculate = same_dt && first_err == PFCH_OK;
-  for (int i = 0; i < n && speculate; ++i) speculate = !(ctx->inst[i].fno && ctx->inst[i].d.guess == 1);
+  // advanced.  A learned guess is formed then too (into the instance's own
+  // guess buffer, in stream order, so later use of the network on this
+  // stream does not change it).
+  const bool speculate = same_dt && first_err == PFCH_OK;
   ctx->last_dt.assign(dt, dt + n);
   if (speculate) {
     SolveOut nx;
@@ -2766,6 +2768,7 @@ void pfch_fno_destroy(pfch_fno* f) {
   for (void* p : f->f.allocs) (void)hipFree(p);
   for (void* p : f->f.host_allocs) (void)hipHostFree(p);
   for (Resampler* r : f->f.rs) delete r;
+  if (f->f.blas) (void)rocblas_destroy_handle(f->f.blas);
   delete f;
 }
 
@@ -2920,6 +2923,10 @@ int fno_resampler(Fno& F, int ny, int nx, Resampler** out) {
       *out = r;
       return PFCH_OK;
     }
+  if (!F.blas && rocblas_create_handle(&F.blas) != rocblas_status_success) {
+    F.blas = nullptr;
+    return PFCH_E_HIP;
+  }
   Resampler* R = new (std::nothrow) Resampler();
   if (!R) return PFCH_E_NOMEM;
   F.rs.push_back(R);  // freed with the network
