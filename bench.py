@@ -294,6 +294,10 @@ def run_set(ws, mode, steps, warmup, tr=None, time_groups=None):
     for c, _ in ctxs:
         c.close()
     per = [np.mean(its[i]) for i in range(len(ws))]
+    # whole-solve bandwidth: the schedule's bytes of every iteration run,
+    # over the wall time (set-ups, accepts and host round trips included)
+    moved = sum(SCHEDULE_BYTES[(w.model, w.scheme, len(w.shape))] * w.npoints * sum(its[i])
+                for i, w in enumerate(ws))
     groups = {}
     for w, p in zip(ws, per):
         key = f"{w.model}{'x'.join(map(str, w.shape))}"
@@ -301,7 +305,8 @@ def run_set(ws, mode, steps, warmup, tr=None, time_groups=None):
     out = dict(time_steps_per_s=round(steps / el, 3), instance_steps_per_s=round(len(ws) * steps / el, 2),
                ms_per_step=round(1e3 * el / steps, 3), iters_per_step=round(float(np.mean(per)), 3),
                iters_per_step_by_grid={k: round(float(np.mean(v)), 3) for k, v in groups.items()},
-               contexts=len(ctxs), elapsed_s=round(el, 4))
+               contexts=len(ctxs), elapsed_s=round(el, 4),
+               effective_gbs=round(moved / el / 1e9, 1), effective_frac=round(moved / el / 1e9 / HBM_PEAK_GBS, 4))
     if use_net:
         out["learned_guess_instances"] = int(sum(guess))
         out["fallbacks"] = its["fallbacks"]
@@ -311,21 +316,24 @@ def run_set(ws, mode, steps, warmup, tr=None, time_groups=None):
 def combined_bench(args):
     import torch
     ws = combined_set()
-    tr, net_info = train_fch_network(args.learned_epochs)
+    tr, net_info = (None, None) if args.no_learned else train_fch_network(args.learned_epochs)
     first8 = next(i for i, w in enumerate(ws) if w.shape == (2048, 2048))
     i3 = next(i for i, w in enumerate(ws) if len(w.shape) == 3)
     groups = {"fch2048": first8, "fch1024": 0, "pfc192_3d": i3}
     variants = {}
+    headline = "batched" if tr is None else "batched_learned"
     for mode in ("plain", "batched", "learned"):
-        if args.only and args.only != mode:
+        if (args.only and args.only != mode) or (tr is None and mode == "learned") or mode == headline:
             continue
         variants[mode], _ = run_set(ws, mode, args.steps, args.warmup, tr)
         torch.cuda.empty_cache()
-    # the headline configuration last, with the kernel timing of its grouped launches
-    head, timing = run_set(ws, "batched_learned", args.steps, args.warmup, tr,
+    # the headline configuration last, with the kernel timing of its grouped
+    # launches (without a network: the batched run)
+    head, timing = run_set(ws, headline, args.steps, args.warmup, tr,
                            time_groups=None if args.no_kernel_timing else groups)
-    variants["batched_learned"] = head
-    tr.fno.close()
+    variants[headline] = head
+    if tr is not None:
+        tr.fno.close()
     if "plain" in variants:
         plain = variants["plain"]["time_steps_per_s"]
         for k in variants:
@@ -361,8 +369,9 @@ def combined_bench(args):
     cfg = dict(workload=COMBINED, instances=len(ws), points=int(sum(w.npoints for w in ws)),
                grids={"fch2d_1024": 8, "fch2d_2048": 8, "pfc3d_192": 1}, scheme="bdf2",
                dt={"fch": 1e-3, "pfc": 0.1}, tol=1e-10, s=0.9, seeds="2000-2015 (FCH), 0 (PFC 3D)",
-               headline="batched_learned",
-               guess="learned on the FCH instances, extrapolated on the 3D instance")
+               headline=headline,
+               guess="extrapolated" if tr is None else
+               "learned on the FCH instances, extrapolated on the 3D instance")
     return dict(value=head["time_steps_per_s"], ms_per_step=head["ms_per_step"], config=cfg,
                 iters_per_step=head["iters_per_step"], variants=variants, roofline=roof, kernels=kernels,
                 learned_network=net_info)
@@ -816,6 +825,8 @@ def main():
                     help="seconds of oracle work for a single-instance workload")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also run the other comparisons")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="combined set: no network (headline = batched; counter runs)")
     ap.add_argument("--only", choices=["plain", "batched", "learned"],
                     help="combined set: run this variant besides the headline batched_learned "
                          "(profiling runs)")
