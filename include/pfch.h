@@ -394,7 +394,9 @@ int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4])
  *   12..19 row radices, 20..27 column (2D) or y-pass (3D) radices,
  *   28..35 z-pass radices (unused passes have radix 1),
  *   36 column-kernel grid when its blocks loop over several column blocks
- *      (0: one block per column block). */
+ *      (0: one block per column block); used for launches of one instance,
+ *      while launches that cover several instances of the group use one
+ *      block per column block. */
 int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[37]);
 
 /* Override that choice: choice = out[0..7] of pfch_get_plan plus choice[8]

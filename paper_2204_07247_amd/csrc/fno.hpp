@@ -274,20 +274,30 @@ __global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ X, int 
   }
 }
 
-// Sum the per-block partials of k_wgrad in block order: out_w[i][j] for
-// i < CX, out_b[j] for the bias row.
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int nblk, int CX, int CY, float* __restrict__ out_w,
-                               float* __restrict__ out_b) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum the per-block partials of k_wgrad: out_w[i][j] for i < CX, out_b[j]
+// for the bias row.  Blocks of 64 x 16 threads: each of the 16 slices sums
+// the partials k = slice (mod 16) in order, then the slices are added in
+// order (a fixed order, independent of timing).
+constexpr int WG_RED_SLICES = 16;
+__global__ __launch_bounds__(64 * WG_RED_SLICES) void k_wgrad_reduce(const float* __restrict__ part, int nblk,
+                                                                     int CX, int CY, float* __restrict__ out_w,
+                                                                     float* __restrict__ out_b) {
+  __shared__ float red[WG_RED_SLICES][64];
+  const int o = blockIdx.x * 64 + threadIdx.x;
   const int nout = (CX + 1) * CY;
-  if (o >= nout) return;
   float s = 0.f;
-  for (int k = 0; k < nblk; ++k) s += part[(long long)k * nout + o];
+  if (o < nout)
+    for (int k = threadIdx.y; k < nblk; k += WG_RED_SLICES) s += part[(long long)k * nout + o];
+  red[threadIdx.y][threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.y != 0 || o >= nout) return;
+  float t = 0.f;
+  for (int q = 0; q < WG_RED_SLICES; ++q) t += red[q][threadIdx.x];
   const int i = o / CY, j = o % CY;
   if (i < CX)
-    out_w[o] = s;
+    out_w[o] = t;
   else
-    out_b[j] = s;
+    out_b[j] = t;
 }
 
 // y[b][p] = sum_i Q[i] v[b][i][p] + qb
@@ -538,7 +548,7 @@ inline hipError_t wgrad(Fno& F, const float* X, int CX, const float* Y, int CY, 
                         float* out_b, hipStream_t s) {
   hipLaunchKernelGGL(k_wgrad, dim3(F.wg_blocks), dim3(256), 0, s, X, CX, Y, CY, F.P, total, F.wpart);
   const int nout = (CX + 1) * CY;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(nout)), dim3(256), 0, s, (const float*)F.wpart,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 63) / 64), dim3(64, WG_RED_SLICES), 0, s, (const float*)F.wpart,
                      F.wg_blocks, CX, CY, out_w, out_b);
   return hipGetLastError();
 }

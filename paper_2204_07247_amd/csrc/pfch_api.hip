@@ -611,7 +611,8 @@ unsigned stage_grid(const Stage& st, unsigned nm) {
   const unsigned tot = nm * (unsigned)st.bpi;
   return st.cap > 0 && (unsigned)st.cap < tot ? (unsigned)st.cap : tot;
 }
-int iter_stages(const Group& G, Stage* st) {
+// nm: instances per launch.
+int iter_stages(const Group& G, Stage* st, unsigned nm = 1) {
   if (G.ndim == 3) {
     st[0] = Stage{G.y3.fwd, G.y3_bpi, G.y3_block, G.y3_lds, 0};
     st[1] = Stage{G.z3.iter, G.z3_bpi, G.z3_block, G.z3_lds, 0};
@@ -619,7 +620,12 @@ int iter_stages(const Group& G, Stage* st) {
     st[3] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds, 0};
     return 4;
   }
-  st[0] = Stage{G.ck.iter, G.col_bpi, G.col_block, G.col_lds, G.col_cap};
+  // A looping column grid (tuned on one instance) only for launches of one
+  // instance: in a grouped launch the four blocks that share a 4-column tile
+  // drift apart over their many items and the shared lines are fetched
+  // again (FCH 2048^2, 8 members: 529 us looping, 481 us with one block per
+  // column block).  The arithmetic per column is the same either way.
+  st[0] = Stage{G.ck.iter, G.col_bpi, G.col_block, G.col_lds, nm > 1 ? 0 : G.col_cap};
   st[1] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds, 0};
   return 2;
 }
@@ -640,7 +646,7 @@ int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
     hipGraphNode_t prev = nullptr;
     const unsigned nm = (unsigned)G.members.size();
     Stage st[4];
-    const int ns = iter_stages(G, st);
+    const int ns = iter_stages(G, st, nm);
     for (int l = 0; l < K; ++l) {
       for (int k = 0; k < ns; ++k) {
         hipKernelNodeParams p{};
@@ -1872,7 +1878,7 @@ int time_iterations(pfch_ctx* ctx, Group& G, InstDev** grp, const std::vector<in
                     double out[4]) {
   const unsigned nm = (unsigned)members.size();
   Stage st[4];
-  const int ns = iter_stages(G, st);
+  const int ns = iter_stages(G, st, nm);
   // iterations launched per solve: the largest last count plus two
   int last = 1, cap = 1 << 30;
   for (int i : members) {
@@ -2012,7 +2018,7 @@ int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]) {
   out[0] = nm * G.row_bpi;
   out[1] = G.row_block.x;
   out[2] = (int64_t)G.row_lds;
-  out[3] = G.col_cap > 0 && G.col_cap < nm * G.col_bpi ? G.col_cap : nm * G.col_bpi;
+  out[3] = nm == 1 && G.col_cap > 0 && G.col_cap < G.col_bpi ? G.col_cap : nm * G.col_bpi;
   out[4] = G.col_block.x;
   out[5] = (int64_t)G.col_lds;
   return PFCH_OK;
