@@ -393,18 +393,16 @@ int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4])
  *   8..11 numbers of row, column, y and z alternatives,
  *   12..19 row radices, 20..27 column (2D) or y-pass (3D) radices,
  *   28..35 z-pass radices (unused passes have radix 1),
- *   36 column-kernel grid when its blocks loop over several column blocks
- *      (0: one block per column block); used for launches of one instance,
- *      while launches that cover several instances of the group use one
- *      block per column block. */
+ *   36 reserved (0).
+ * Every launch has one block per row-pair block and per column block of
+ * each instance it covers, so an instance's arithmetic does not depend on
+ * how many instances share the launch. */
 int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[37]);
 
-/* Override that choice: choice = out[0..7] of pfch_get_plan plus choice[8]
- * for looping column blocks (2D): 0 one block per column block; 1, 2, 3
- * fewer blocks that loop over the column blocks, as many as fit on the
- * device, one per compute unit, two per compute unit; entries that do not apply to the
- * grid's dimension are ignored.  Each is validated against the kernels'
- * limits (PFCH_E_INVAL otherwise).  Results of different plans agree to
+/* Override that choice: choice = out[0..7] of pfch_get_plan plus choice[8],
+ * reserved, which must be 0; entries that do not apply to the grid's
+ * dimension are ignored.  Each is validated against the kernels' limits
+ * (PFCH_E_INVAL otherwise).  Results of different plans agree to
  * rounding. */
 int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]);
 

@@ -211,6 +211,17 @@ struct Plan {
   }
   static_assert(NPASS >= 1 && NPASS <= 8, "one to eight passes");
   static_assert(ns(NPASS) == N, "radices must multiply to N");
+  static constexpr bool TW_LDS = false;  // twiddles in the LDS table whatever their count
+  static constexpr int MIN_WAVES = 1;    // waves per SIMD a kernel of this plan may ask the compiler for
+};
+
+// The same radix schedule with its twiddles in the LDS table (freeing the
+// registers that hold them) and a kernel register budget for at least
+// MINW waves per SIMD.
+template <class P, int MINW>
+struct LdsTw : P {
+  static constexpr bool TW_LDS = true;
+  static constexpr int MIN_WAVES = MINW;
 };
 
 // Twiddles live in LDS, after the block's transform buffers: for every pass
@@ -242,7 +253,7 @@ constexpr int tw_per_thread() {
 }
 template <class P>
 constexpr bool tw_in_lds() {
-  return tw_per_thread<P>() > 4;
+  return P::TW_LDS || tw_per_thread<P>() > 4;
 }
 // LDS entries the plan's twiddle table needs (0 in register mode).
 template <class P>

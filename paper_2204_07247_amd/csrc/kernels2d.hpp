@@ -46,6 +46,24 @@ __device__ __forceinline__ uint32_t sidx(int rows, int row, int kp) {
 // barriers).
 __device__ __forceinline__ int opaque(int v) { return opaque_i(v); }
 
+// Block-uniform copies (the value of the first active lane) of values every
+// lane of the block has read alike: held in scalar registers rather than one
+// vector register per lane.  Applied to values already loaded (from the LDS
+// copy of the instance record), so that no record field is ever read
+// through the scalar cache, which does not see what earlier kernels of the
+// same graph wrote.
+__device__ __forceinline__ int uni_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni_u64(uint64_t b) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double uni_d(double v) { return __longlong_as_double((long long)uni_u64(dbits(v))); }
+template <class T>
+__device__ __forceinline__ T* uni_p(T* p) {
+  return (T*)(uintptr_t)uni_u64((uint64_t)(uintptr_t)p);
+}
+
 // Grouped launches: one launch covers every instance of a group (same model
 // and grid); block b works on instance b / bpi as its local block b % bpi.
 struct GroupPos {
@@ -355,169 +373,167 @@ __device__ __forceinline__ void col0_mirror(const c2 (&v)[P::RMAX], c2* lds0, bo
 //   PFC: q mu~^ = q N^ + q (1 - eps - 2q + q^2) v^,
 //   FCH: q mu~^ = eps^2 q^2 F'^ + q p^ + q (eps^4 q^2 - eps^2 eta1 q) v^,
 // and d^ = 0 at k = 0.  The bracket is accumulated field by field as it
-// comes out of its y-transform.
-// ---------------------------------------------------------------------------
+// comes out of its y-transform (the next field's load in flight meanwhile).
 //
-// Blocks loop over the items (instance, column block) b, b + gridDim.x, ...
-// of the group: launched with one block per item this is the plain kernel;
-// launched with fewer blocks, each block loads the first field of its next
-// item while it finishes the current one (inverse transforms and stores).
+// One block per column block (cb physical columns of one instance).  The
+// instance record is staged in LDS and its scalars are held in scalar
+// registers, the field pointers are scalar bases with 32-bit offsets, and
+// |k|^2 is recomputed per use from an opaque copy of the thread index
+// instead of being held across the transforms: with its twiddles in LDS the
+// FCH 2048 plan fits 168 registers per lane (three waves per SIMD, two
+// otherwise) and the radix-4 1024 plan 128 (four).
+// ---------------------------------------------------------------------------
 template <class PY, int MODEL>
-__global__ __launch_bounds__(512) void k_col_iter(const InstDev* const* __restrict__ grp, int bpi, int l,
-                                                  int total) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PY::MIN_WAVES))) void k_col_iter(
+    const InstDev* const* __restrict__ grp, int bpi, int l, int /*total*/) {
   extern __shared__ c2 smem[];
+  __shared__ InstDev rec;
   constexpr int N = PY::N, T = PY::T, RM = PY::RMAX;
   constexpr int NF = MODEL == MODEL_PFC ? 2 : 3;  // transformed fields; the last is v_breve
   const int rows = N;
-  // the next active item at or after `item` (total if none)
-  auto next_active = [&](int item) {
-    for (; item < total; item += gridDim.x) {
-      const InstDev* J = grp[item / bpi];
-      if (!stopped_before(J, *J->iter_base + l)) break;
-    }
-    return item;
-  };
-  int item = next_active(blockIdx.x);
-  if (item >= total) return;
+  const GroupPos gpos = group_pos(grp, bpi);
+  const InstDev* __restrict__ I = stage_record(gpos.I, &rec);
+  const int j = uni_i(*I->iter_base + l);
+  if (uni_i(stopped_before(I, j))) return;
+  const int lbi = uni_i(gpos.lb);
+  const ColPos pos = col_pos(T, uni_i(I->nh) / TW, lbi);
+  const int t = pos.t, kp = pos.kp;
+  c2* lds = smem + pos.c * lds_len(N);
+  const bool special = kp == 0;  // this thread's column holds kx = 0 and kx = nx/2
+  const bool blk0 = lbi == 0;    // the block holding physical column 0
+  const uint32_t fs = (uint32_t)uni_u64((uint64_t)I->field_stride);
+  GLB c2* S = gp(uni_p(I->S));
   Twiddles<PY> tw;
-  bool have_tw = false;
+  load_twiddles<PY>(tw, I->tw_y, t);
+
+  double bm2, b0, b2, b4;
+  betas(I, bm2, b0, b2, b4);
+  // the step's first iteration without a column set-up: g^ and the
+  // averaged-Newton constants are formed here
+  const bool first = uni_i(j == 0 && I->fold_g);
+  if (first) fold_betas(I, const_cast<InstDev*>(gpos.I), blk0, b0, b2);
+  bm2 = uni_d(bm2);
+  b0 = uni_d(b0);
+  b2 = uni_d(b2);
+  b4 = uni_d(b4);
+  const double thl = uni_d(I->theta_l), inv_m = uni_d(I->inv_mobility), aot = uni_d(I->a_over_theta);
+  const double inv_p = uni_d(I->inv_p);
+  const double kxs = uni_d(I->kx_scale), kys = uni_d(I->ky_scale);
+  const double hx = 0.5 * uni_i(I->nx) * kxs;
+  const double kxn2 = hx * hx;
+  const double kx2 = (kp * kxs) * (kp * kxs);
+  auto q_at = [&](int ky) {  // |k|^2 of this thread's logical column (kx = 0 for column 0)
+    const double a = (ky <= N / 2 ? ky : ky - N) * kys;
+    return kx2 + a * a;
+  };
+  auto q_col0 = [&](int ky) {  // |k|^2 at kx = 0
+    const double a = (ky <= N / 2 ? ky : ky - N) * kys;
+    return a * a;
+  };
+  const double eps = uni_d(I->eps);
+  const double e2 = eps * eps, e4 = e2 * e2, e2h1 = e2 * uni_d(I->eta1), e1 = 1.0 - eps;
+  auto coef = [&](int f, double q) -> double {
+    if (f == NF - 1) {
+      const double lin = MODEL == MODEL_PFC ? e1 - 2.0 * q + q * q : e4 * q * q - e2h1 * q;
+      return inv_m * aot + q * lin;
+    }
+    if (MODEL == MODEL_FCH && f == 0) return e2 * q * q;
+    return q;
+  };
+  GLB c2* gsrc = gp(uni_p(first ? I->G : I->ghat));
+  GLB c2* ghat = gp(uni_p(I->ghat));
+
   c2 v[RM], nxt[RM], acc[RM];
-  bool pre = false;  // v holds the current item's field 0
-  for (; item < total;) {
-    const int gi = item / bpi, lbi = item - gi * bpi;
-    const InstDev* __restrict__ I = grp[gi];
-    const ColPos pos = col_pos(T, I->nh / TW, lbi);
-    const int t = pos.t, kp = pos.kp;
-    c2* lds = smem + pos.c * lds_len(N);
-    const bool special = kp == 0;  // this thread's column holds kx = 0 and kx = nx/2
-    const bool blk0 = lbi == 0;    // the block holding physical column 0
-    const uint32_t fs = (uint32_t)I->field_stride;
-    GLB c2* S = gp(I->S);
-    if (!have_tw) {
-      load_twiddles<PY>(tw, I->tw_y, t);
-      have_tw = true;
-    }
-
-    double bm2, b0, b2, b4;
-    betas(I, bm2, b0, b2, b4);
-    // the step's first iteration without a column set-up: g^ and the
-    // averaged-Newton constants are formed here
-    const bool first = *I->iter_base + l == 0 && I->fold_g;
-    if (first) fold_betas(I, const_cast<InstDev*>(I), blk0, b0, b2);
-    const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
-    const double inv_p = I->inv_p;
-    const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
-    const double kx2 = (kp * I->kx_scale) * (kp * I->kx_scale);
-    auto q_of = [&](int m) {  // |k|^2 of this thread's logical column (kx = 0 for column 0)
-      const int ky = t + m * T;
-      const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
-      return kx2 + a * a;
-    };
-    auto q_col0 = [&](int ky) {  // |k|^2 at kx = 0
-      const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
-      return a * a;
-    };
-    const double e2 = I->eps * I->eps, e4 = e2 * e2, e2h1 = e2 * I->eta1, e1 = 1.0 - I->eps;
-    auto coef = [&](int f, double q) -> double {
-      if (f == NF - 1) {
-        const double lin = MODEL == MODEL_PFC ? e1 - 2.0 * q + q * q : e4 * q * q - e2h1 * q;
-        return inv_m * aot + q * lin;
-      }
-      if (MODEL == MODEL_FCH && f == 0) return e2 * q * q;
-      return q;
-    };
-
 #pragma unroll
-    for (int m = 0; m < RM; ++m) {
-      if (!pre) v[m] = gload(S + sidx(rows, t + m * T, kp));
-      acc[m] = c2{0.0, 0.0};
-    }
+  for (int m = 0; m < RM; ++m) {
+    v[m] = gload(S + sidx(rows, t + m * T, kp));
+    acc[m] = c2{0.0, 0.0};
+  }
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
+  for (int f = 0; f < NF; ++f) {
+    {
+      const int tl = opaque(t);
 #pragma unroll
       for (int m = 0; m < RM; ++m)  // prefetch the next field, then g^ (first: g, transformed below)
-        nxt[m] = f + 1 < NF ? gload(S + (f + 1) * fs + sidx(rows, t + m * T, kp))
-                            : gload(gp(first ? I->G : I->ghat) + sidx(rows, t + m * T, kp));
-      fft<PY, false>(v, lds, tw, t);
+        nxt[m] = f + 1 < NF ? gload(S + (f + 1) * fs + sidx(rows, tl + m * T, kp))
+                            : gload(gsrc + sidx(rows, tl + m * T, kp));
+    }
+    fft<PY, false>(v, lds, tw, t);
+    {
+      const int tl = opaque(t);
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const double q = q_of(m);
+        const double q = q_at(tl + m * T);
         const double c = special ? 0.5 * (coef(f, q) + coef(f, q + kxn2)) : coef(f, q);
         acc[m] = cadd(acc[m], cscale(v[m], c));
       }
-      if (blk0)
-        col0_mirror<PY>(v, smem, special, t, [&](int m, c2 w) {
-          const double q = q_col0(opaque(t + m * T));
-          acc[m] = cadd(acc[m], cscale(w, 0.5 * (coef(f, q) - coef(f, q + kxn2))));
-        });
-#pragma unroll
-      for (int m = 0; m < RM; ++m) v[m] = nxt[m];
     }
-    if (first) {  // g^ for this and the step's later iterations
-      fft<PY, false>(v, lds, tw, t);
+    if (blk0)
+      col0_mirror<PY>(v, smem, special, t, [&](int m, c2 w) {
+        const double q = q_col0(opaque(t + m * T));
+        acc[m] = cadd(acc[m], cscale(w, 0.5 * (coef(f, q) - coef(f, q + kxn2))));
+      });
 #pragma unroll
-      for (int m = 0; m < RM; ++m) gstore(gp(I->ghat) + sidx(rows, t + m * T, kp), v[m]);
-    }
-    // g^ enters with the same coefficient 1/M on both logical columns.
+    for (int m = 0; m < RM; ++m) v[m] = nxt[m];
+  }
+  if (first) {  // g^ for this and the step's later iterations
+    fft<PY, false>(v, lds, tw, t);
+    const int tl = opaque(t);
 #pragma unroll
-    for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(v[m], inv_m));
+    for (int m = 0; m < RM; ++m) gstore(ghat + sidx(rows, tl + m * T, kp), v[m]);
+  }
+  // g^ enters with the same coefficient 1/M on both logical columns.
+#pragma unroll
+  for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(v[m], inv_m));
 
-    // next item: its first field streams in during the inverse transforms
-    const int nitem = next_active(item + gridDim.x);
-    pre = nitem < total;
-    if (pre) {
-      const int ngi = nitem / bpi;
-      const InstDev* In = grp[ngi];
-      const ColPos np = col_pos(T, In->nh / TW, nitem - ngi * bpi);
-      const GLB c2* Sn = gp(In->S);
+  // scale by -1/(P Lq), zero at k = 0
+  int bad = 0;
+  auto scale = [&](double q) -> double {
+    if (!(q > 0.0)) return 0.0;
+    const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
+    bad |= !(Lq > 0.0);
+    return -inv_p * rcp_pos(Lq);
+  };
+  {
+    const int tl = opaque(t);
 #pragma unroll
-      for (int m = 0; m < RM; ++m) nxt[m] = gload(Sn + sidx(rows, np.t + m * T, np.kp));
+    for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], scale(q_at(tl + m * T)));
+  }
+  if (blk0)
+    col0_mirror<PY>(acc, smem, special, t, [&](int m, c2 w) {
+      const double q = q_col0(opaque(t + m * T));
+      const double s0 = scale(q), sn = scale(q + kxn2);
+      v[m] = cadd(cscale(acc[m], 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn)));
+    });
+  if constexpr (MODEL == MODEL_FCH) {
+    // keep d^ for the Laplacian field: acc <- d^ (packed for column 0)
+#pragma unroll
+    for (int m = 0; m < RM; ++m) acc[m] = v[m];
+  }
+  fft<PY, true>(v, lds, tw, t);
+  {
+    const int tl = opaque(t);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) gstore(S + sidx(rows, tl + m * T, kp), v[m]);
+  }
+  if constexpr (MODEL == MODEL_FCH) {
+    // Delta d: symbol -q on each logical column
+    {
+      const int tl = opaque(t);
+#pragma unroll
+      for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], -q_at(tl + m * T));
     }
-
-    // scale by -1/(P Lq), zero at k = 0
-    int bad = 0;
-    auto scale = [&](double q) -> double {
-      if (!(q > 0.0)) return 0.0;
-      const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
-      bad |= !(Lq > 0.0);
-      return -inv_p * rcp_pos(Lq);
-    };
-#pragma unroll
-    for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], scale(q_of(m)));
     if (blk0)
       col0_mirror<PY>(acc, smem, special, t, [&](int m, c2 w) {
         const double q = q_col0(opaque(t + m * T));
-        const double s0 = scale(q), sn = scale(q + kxn2);
-        v[m] = cadd(cscale(acc[m], 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn)));
+        v[m] = cadd(cscale(acc[m], -(q + 0.5 * kxn2)), cscale(w, 0.5 * kxn2));
       });
-    if constexpr (MODEL == MODEL_FCH) {
-      // keep d^ for the Laplacian field: acc <- d^ (packed for column 0)
-#pragma unroll
-      for (int m = 0; m < RM; ++m) acc[m] = v[m];
-    }
     fft<PY, true>(v, lds, tw, t);
+    const int tl = opaque(t);
 #pragma unroll
-    for (int m = 0; m < RM; ++m) gstore(S + sidx(rows, t + m * T, kp), v[m]);
-    if constexpr (MODEL == MODEL_FCH) {
-      // Delta d: symbol -q on each logical column
-#pragma unroll
-      for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], -q_of(m));
-      if (blk0)
-        col0_mirror<PY>(acc, smem, special, t, [&](int m, c2 w) {
-          const double q = q_col0(opaque(t + m * T));
-          v[m] = cadd(cscale(acc[m], -(q + 0.5 * kxn2)), cscale(w, 0.5 * kxn2));
-        });
-      fft<PY, true>(v, lds, tw, t);
-#pragma unroll
-      for (int m = 0; m < RM; ++m) gstore(S + fs + sidx(rows, t + m * T, kp), v[m]);
-    }
-    if (bad) atomicOr(I->flags, FLAG_PRECOND);
-    if (pre) {
-#pragma unroll
-      for (int m = 0; m < RM; ++m) v[m] = nxt[m];
-    }
-    item = nitem;
+    for (int m = 0; m < RM; ++m) gstore(S + fs + sidx(rows, tl + m * T, kp), v[m]);
   }
+  if (bad) atomicOr(I->flags, FLAG_PRECOND);
 }
 
 // ---------------------------------------------------------------------------

@@ -283,8 +283,6 @@ struct Group {
   dim3 row_block, col_block;
   int row_bpi = 0, col_bpi = 0;  // blocks per instance
   size_t row_lds = 0, col_lds = 0;
-  int col_cap = 0;               // column kernel: > 0 = persistent grid size
-  int num_cus = 0;
   // step-setup kernels: always the default plan and geometry, so that the
   // partial sums of the averaged-Newton constants do not depend on tuning
   RowK rs;
@@ -604,29 +602,19 @@ struct Stage {
   int bpi;
   dim3 block;
   size_t lds;
-  int cap;  // > 0: at most this many blocks, each looping over items
 };
-// Grid of a stage launched for `nm` instances.
-unsigned stage_grid(const Stage& st, unsigned nm) {
-  const unsigned tot = nm * (unsigned)st.bpi;
-  return st.cap > 0 && (unsigned)st.cap < tot ? (unsigned)st.cap : tot;
-}
-// nm: instances per launch.
-int iter_stages(const Group& G, Stage* st, unsigned nm = 1) {
+// Grid of a stage launched for `nm` instances: one block per item.
+unsigned stage_grid(const Stage& st, unsigned nm) { return nm * (unsigned)st.bpi; }
+int iter_stages(const Group& G, Stage* st) {
   if (G.ndim == 3) {
-    st[0] = Stage{G.y3.fwd, G.y3_bpi, G.y3_block, G.y3_lds, 0};
-    st[1] = Stage{G.z3.iter, G.z3_bpi, G.z3_block, G.z3_lds, 0};
-    st[2] = Stage{G.y3.inv, G.y3_bpi, G.y3_block, G.y3_lds, 0};
-    st[3] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds, 0};
+    st[0] = Stage{G.y3.fwd, G.y3_bpi, G.y3_block, G.y3_lds};
+    st[1] = Stage{G.z3.iter, G.z3_bpi, G.z3_block, G.z3_lds};
+    st[2] = Stage{G.y3.inv, G.y3_bpi, G.y3_block, G.y3_lds};
+    st[3] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds};
     return 4;
   }
-  // A looping column grid (tuned on one instance) only for launches of one
-  // instance: in a grouped launch the four blocks that share a 4-column tile
-  // drift apart over their many items and the shared lines are fetched
-  // again (FCH 2048^2, 8 members: 529 us looping, 481 us with one block per
-  // column block).  The arithmetic per column is the same either way.
-  st[0] = Stage{G.ck.iter, G.col_bpi, G.col_block, G.col_lds, nm > 1 ? 0 : G.col_cap};
-  st[1] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds, 0};
+  st[0] = Stage{G.ck.iter, G.col_bpi, G.col_block, G.col_lds};
+  st[1] = Stage{G.rk.iter, G.row_bpi, G.row_block, G.row_lds};
   return 2;
 }
 
@@ -646,7 +634,7 @@ int get_graph(pfch_ctx* ctx, int K, hipGraphExec_t* out) {
     hipGraphNode_t prev = nullptr;
     const unsigned nm = (unsigned)G.members.size();
     Stage st[4];
-    const int ns = iter_stages(G, st, nm);
+    const int ns = iter_stages(G, st);
     for (int l = 0; l < K; ++l) {
       for (int k = 0; k < ns; ++k) {
         hipKernelNodeParams p{};
@@ -1069,7 +1057,7 @@ int learned_guesses(pfch_ctx* ctx, const std::vector<int>& ids, const std::vecto
 // ---------------------------------------------------------------------------
 struct TuneChoice {
   int row_alt = -1, teams = 0;  // alt -1: default plan
-  int col_alt = -1, cb = 0, persist = 0;  // persist: level of apply_col
+  int col_alt = -1, cb = 0;
   int cy = 0, kyb = 0;          // 3D: y-pass columns per block, z-pass ky per block
   int y3_alt = -1, z3_alt = -1;  // 3D: y- and z-pass plans
 };
@@ -1111,28 +1099,13 @@ void apply_row(Group& G, const RowK& k, int teams) {
   if (G.row_lds > 65536)
     (void)hipFuncSetAttribute(k.iter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.row_lds);
 }
-// persist > 0: launch fewer column blocks, each looping over items (next
-// item's first field prefetched): 1 as many as fit on the device at once,
-// 2 one per compute unit, 3 two per compute unit (fewer blocks than fit
-// trade parallelism for overlap of one item's transforms with the next
-// item's loads).
-constexpr int PERSIST_LEVELS = 3;
-void apply_col(Group& G, const ColK& k, int cb, int persist = 0) {
+void apply_col(Group& G, const ColK& k, int cb) {
   G.ck = k;
   G.col_block = dim3(k.T * cb);
   G.col_bpi = (G.nx / 2) / cb;
   G.col_lds = ((size_t)cb * k.lds_elems + k.tw_elems) * sizeof(c2);
   if (G.col_lds > 65536)
     (void)hipFuncSetAttribute(k.iter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.col_lds);
-  G.col_cap = 0;
-  if (persist) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k.iter, (int)G.col_block.x, G.col_lds) == hipSuccess &&
-        nb > 0 && G.num_cus > 0) {
-      const int per_cu = persist == 1 ? nb : std::min(nb, persist - 1);
-      G.col_cap = per_cu * G.num_cus;
-    }
-  }
 }
 
 // Milliseconds per launch of one iteration stage on instance I alone.
@@ -1211,15 +1184,15 @@ bool choice_ok(const Group& G, const TuneChoice& c) {
   if (c.col_alt < -1 || c.col_alt >= (int)G.calts.size()) return false;
   const ColK& ck = c.col_alt < 0 ? G.cs : G.calts[c.col_alt];
   if (c.cb != 1 && c.cb != 2 && c.cb != 4) return false;
-  if (c.persist < 0 || c.persist > PERSIST_LEVELS) return false;
-  return col_geometry_ok(G, ck, c.cb) && !(ck.fp && c.persist);
+  return col_geometry_ok(G, ck, c.cb);
 }
 
 // Tuning file: with PFCH_TUNE_FILE set, a choice recorded there for the
 // group's (model, scheme, Nx, Ny, Nz) is used instead of timing, and a new
 // choice is appended.  One line per entry:
-//   model scheme nx ny nz  row_alt teams col_alt cb persist cy kyb y3_alt z3_alt
-// (the last valid line for a key wins).
+//   model scheme nx ny nz  row_alt teams col_alt cb 0 cy kyb y3_alt z3_alt
+// (the last valid line for a key wins; the tenth field is reserved and must
+// be 0).
 using TuneKey = std::tuple<int, int, int, int, int>;
 
 bool tune_file_lookup(const TuneKey& key, TuneChoice* out) {
@@ -1234,13 +1207,12 @@ bool tune_file_lookup(const TuneKey& key, TuneChoice* out) {
     if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5],
                     &v[6], &v[7], &v[8], &v[9], &v[10], &v[11], &v[12], &v[13]) != 14)
       continue;
-    if (std::make_tuple(v[0], v[1], v[2], v[3], v[4]) != key) continue;
+    if (std::make_tuple(v[0], v[1], v[2], v[3], v[4]) != key || v[9] != 0) continue;
     TuneChoice c;
     c.row_alt = v[5];
     c.teams = v[6];
     c.col_alt = v[7];
     c.cb = v[8];
-    c.persist = v[9];
     c.cy = v[10];
     c.kyb = v[11];
     c.y3_alt = v[12];
@@ -1258,7 +1230,7 @@ void tune_file_store(const TuneKey& key, const TuneChoice& c) {
   FILE* f = std::fopen(path, "a");
   if (!f) return;
   std::fprintf(f, "%d %d %d %d %d  %d %d %d %d %d %d %d %d %d\n", std::get<0>(key), std::get<1>(key), std::get<2>(key),
-               std::get<3>(key), std::get<4>(key), c.row_alt, c.teams, c.col_alt, c.cb, c.persist, c.cy,
+               std::get<3>(key), std::get<4>(key), c.row_alt, c.teams, c.col_alt, c.cb, 0, c.cy,
                c.kyb, c.y3_alt, c.z3_alt);
   std::fclose(f);
 }
@@ -1269,7 +1241,7 @@ void apply_choice(Group& G, const TuneChoice& c) {
     apply_y3(G, c.y3_alt < 0 ? G.y3d : G.y3alts[c.y3_alt], c.cy);
     apply_z3(G, c.z3_alt < 0 ? G.z3d : G.z3alts[c.z3_alt], c.kyb);
   } else {
-    apply_col(G, c.col_alt < 0 ? G.cs : G.calts[c.col_alt], c.cb, c.persist);
+    apply_col(G, c.col_alt < 0 ? G.cs : G.calts[c.col_alt], c.cb);
   }
 }
 
@@ -1429,21 +1401,14 @@ int tune_group(pfch_ctx* ctx, Group& G, bool* used_instance) {
     for (int alt = -1; alt < (int)G.calts.size(); ++alt) {
       const ColK& k = alt < 0 ? G.cs : G.calts[alt];
       for (int cb = 1; cb <= 4; cb *= 2) {
-        int prev_cap = -1;
-        for (int persist = 0; persist <= PERSIST_LEVELS; ++persist) {
-          if (!col_geometry_ok(G, k, cb) || (alt < 0 && cb == def.cb && !persist) || (k.fp && persist)) continue;
-          apply_col(G, k, cb, persist);
-          // a looping grid must loop (fewer blocks than items) and differ from the last one tried
-          if (persist && (G.col_cap == 0 || G.col_cap >= (int)G.col_bpi || G.col_cap == prev_cap)) continue;
-          if (persist) prev_cap = G.col_cap;
-          float t = 0.f;
-          if ((rc = time_iter_kernel(ctx, G, I, 0, e0, e1, &t))) return rc;
-          if (t < TUNE_MARGIN * t_def_col && t < t_best) {
-            t_best = t;
-            best.col_alt = alt;
-            best.cb = cb;
-            best.persist = persist;
-          }
+        if (!col_geometry_ok(G, k, cb) || (alt < 0 && cb == def.cb)) continue;
+        apply_col(G, k, cb);
+        float t = 0.f;
+        if ((rc = time_iter_kernel(ctx, G, I, 0, e0, e1, &t))) return rc;
+        if (t < TUNE_MARGIN * t_def_col && t < t_best) {
+          t_best = t;
+          best.col_alt = alt;
+          best.cb = cb;
         }
       }
     }
@@ -1594,12 +1559,6 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
       G.ny = I.ny;
       G.nz = I.nz;
       G.rows = I.rows;
-      {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&G.num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-          G.num_cus = 0;
-      }
       G.ndim = I.d.ndim;
       const bool mps = scheme_mp(I.d.scheme);
       bool ok;
@@ -1878,7 +1837,7 @@ int time_iterations(pfch_ctx* ctx, Group& G, InstDev** grp, const std::vector<in
                     double out[4]) {
   const unsigned nm = (unsigned)members.size();
   Stage st[4];
-  const int ns = iter_stages(G, st, nm);
+  const int ns = iter_stages(G, st);
   // iterations launched per solve: the largest last count plus two
   int last = 1, cap = 1 << 30;
   for (int i : members) {
@@ -2018,7 +1977,7 @@ int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]) {
   out[0] = nm * G.row_bpi;
   out[1] = G.row_block.x;
   out[2] = (int64_t)G.row_lds;
-  out[3] = nm == 1 && G.col_cap > 0 && G.col_cap < G.col_bpi ? G.col_cap : nm * G.col_bpi;
+  out[3] = nm * G.col_bpi;
   out[4] = G.col_block.x;
   out[5] = (int64_t)G.col_lds;
   return PFCH_OK;
@@ -2032,8 +1991,7 @@ int pfch_get_plan(pfch_ctx* ctx, int32_t inst, int32_t out[37]) {
       if (get(alts[k]) == f) return k;
     return -1;
   };
-  for (int k = 0; k < 37; ++k) out[k] = 0;
-  out[36] = G.col_cap;
+  for (int k = 0; k < 37; ++k) out[k] = 0;  // out[36]: reserved
   out[0] = find(G.ralts, G.rk.iter, [](const RowK& k) { return k.iter; });
   out[1] = G.rk.T > 0 ? (int32_t)(G.row_block.x / G.rk.T) : 0;
   out[8] = (int32_t)G.ralts.size();
@@ -2073,8 +2031,7 @@ int pfch_set_plan(pfch_ctx* ctx, int32_t inst, const int32_t choice[9]) {
   c.cy = choice[5];
   c.z3_alt = choice[6];
   c.kyb = choice[7];
-  c.persist = choice[8];
-  if (!choice_ok(G, c)) return PFCH_E_INVAL;
+  if (choice[8] != 0 || !choice_ok(G, c)) return PFCH_E_INVAL;  // choice[8]: reserved
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
   for (auto g : ctx->graph_defs) (void)hipGraphDestroy(g);

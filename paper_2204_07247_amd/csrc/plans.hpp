@@ -76,10 +76,24 @@ RowK make_row_iter() {
   plan_radices<P>(k.radix);
   return k;
 }
+// Plan of the column iteration kernel: the radix schedule P, with the
+// twiddles moved to LDS and a register budget for more waves per SIMD where
+// that fits without spilling (specialised below).  The set-up and R(v)
+// column kernels keep P itself; the LDS reserved for twiddles covers both.
+template <class P>
+struct ColPlan {
+  using type = P;
+};
+template <class P>
+constexpr int col_tw_elems() {
+  constexpr int a = tw_lds_count<P>(), b = tw_lds_count<typename ColPlan<P>::type>();
+  return a > b ? a : b;
+}
+
 template <class P, int MODEL>
 ColK make_col() {
   ColK k;
-  k.iter = (const void*)&k_col_iter<P, MODEL>;
+  k.iter = (const void*)&k_col_iter<typename ColPlan<P>::type, MODEL>;
   k.setup = (const void*)&k_col_setup<P, MODEL>;
   if (MODEL == MODEL_FCH) {
     k.rhs_lap = (const void*)&k_rhs_col<P, MODEL, 1>;
@@ -89,17 +103,17 @@ ColK make_col() {
   }
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
-  k.tw_elems = tw_lds_count<P>();
+  k.tw_elems = col_tw_elems<P>();
   plan_radices<P>(k.radix);
   return k;
 }
 template <class P, int MODEL>
 ColK make_col_iter() {
   ColK k;
-  k.iter = (const void*)&k_col_iter<P, MODEL>;
+  k.iter = (const void*)&k_col_iter<typename ColPlan<P>::type, MODEL>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
-  k.tw_elems = tw_lds_count<P>();
+  k.tw_elems = col_tw_elems<P>();
   plan_radices<P>(k.radix);
   return k;
 }
@@ -117,6 +131,12 @@ using P512 = Plan<512, 8, 8, 8>;
 using P1024 = Plan<1024, 8, 8, 4, 4>;
 using P2048 = Plan<2048, 8, 8, 8, 4>;
 using P192 = Plan<192, 3, 4, 4, 4>;  // 12 elements per thread
+// FCH 2048 (three transformed fields, eight elements per thread): 168
+// registers, three waves per SIMD, with the twiddles in LDS.
+template <>
+struct ColPlan<P2048> {
+  using type = LdsTw<P2048, 3>;
+};
 
 template <int MODEL, bool MPS>
 bool row_kernels(int n, RowK& k) {
@@ -165,6 +185,11 @@ using A1024a = Plan<1024, 16, 16, 4>;
 using A1024b = Plan<1024, 4, 4, 4, 4, 4>;
 using A2048a = Plan<2048, 16, 16, 8>;
 using A192a = Plan<192, 3, 2, 2, 2, 2, 2, 2>;  // 6 elements per thread
+// radix 4 at 1024 (four elements per thread): 128 registers, four waves per SIMD
+template <>
+struct ColPlan<A1024b> {
+  using type = LdsTw<A1024b, 4>;
+};
 #define PFCH_ALT_PLANS(X)                                                                          \
   X(64, A64a) X(64, A64b) X(128, A128a) X(128, A128b) X(256, A256a) X(256, A256b) X(512, A512a)   \
   X(1024, A1024a) X(1024, A1024b) X(2048, A2048a) X(192, A192a)

@@ -377,11 +377,11 @@ class Context:
                     y_alt=out[4], y_cb=out[5], z_alt=out[6], z_kyb=out[7],
                     n_row_alts=out[8], n_col_alts=out[9], n_y_alts=out[10], n_z_alts=out[11],
                     row_radices=rad(out[12:20]), col_radices=rad(out[20:28]),
-                    z_radices=rad(out[28:36]), col_persistent_grid=out[36])
+                    z_radices=rad(out[28:36]))
 
     def set_plan(self, inst, row_alt, teams, col_alt=-1, cb=1, y_alt=-1, y_cb=1, z_alt=-1,
-                 z_kyb=1, col_persist=0):
-        ch = (ctypes.c_int32 * 9)(row_alt, teams, col_alt, cb, y_alt, y_cb, z_alt, z_kyb, col_persist)
+                 z_kyb=1):
+        ch = (ctypes.c_int32 * 9)(row_alt, teams, col_alt, cb, y_alt, y_cb, z_alt, z_kyb, 0)
         rc = lib().pfch_set_plan(self._h, inst, ch)
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_set_plan")

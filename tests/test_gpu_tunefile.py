@@ -42,7 +42,7 @@ print(json.dumps([run((64, 128)), run((128, 64))]), flush=True)
 def test_tune_file_choice_is_used_and_new_choices_appended(tmp_path):
     from paper_2204_07247_amd import pfch
     path = tmp_path / "tune.txt"
-    # model scheme nx ny nz  row_alt teams col_alt cb persist cy kyb y3_alt z3_alt
+    # model scheme nx ny nz  row_alt teams col_alt cb 0 cy kyb y3_alt z3_alt
     path.write_text(f"# comment lines are skipped\n"
                     f"{pfch.PFC} {pfch.MP} 128 64 1  -1 4 0 2 0 0 0 -1 -1\n"
                     f"{pfch.PFC} {pfch.MP} 64 128 1  -1 3 -1 1 0 0 0 -1 -1\n")  # 3 row pairs per block: invalid
