@@ -559,14 +559,15 @@ template <class PX>
 __device__ __forceinline__ void pfc_forward_pair(const InstDev* I, const double (&vb)[2][PX::RMAX],
                                                  const Twiddles<PX>& tw, c2* lds, int r0, int t) {
   constexpr int RM = PX::RMAX;
-  GLB c2* S = gp(I->S);
-  const uint32_t fs = (uint32_t)I->field_stride;
+  GLB c2* S = gp(uni_p(I->S));
+  const uint32_t fs = (uint32_t)uni_u64((uint64_t)I->field_stride);
+  const int rows = uni_i(I->rows);
   c2 z[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) z[m] = c2{vb[0][m] * vb[0][m] * vb[0][m], vb[1][m] * vb[1][m] * vb[1][m]};
   fft<PX, false>(z, lds, tw, t);
-  unpack_store<PX>(z, lds, S, r0, S, r0 + 1, I->rows, t);
-  pair_forward<PX>(vb[0], vb[1], tw, lds, S + fs, r0, S + fs, r0 + 1, I->rows, t);
+  unpack_store<PX>(z, lds, S, r0, S, r0 + 1, rows, t);
+  pair_forward<PX>(vb[0], vb[1], tw, lds, S + fs, r0, S + fs, r0 + 1, rows, t);
 }
 
 // FCH pointwise terms at v_breve with Laplacian lv:
@@ -579,10 +580,11 @@ __device__ __forceinline__ void fch_forward_pair(const InstDev* I, const double 
                                                  const double (&lv)[2][PX::RMAX], const Twiddles<PX>& tw,
                                                  c2* lds, int r0, int t) {
   constexpr int RM = PX::RMAX;
-  const double e2 = I->eps * I->eps, tau = I->tau, eta2 = I->eta2;
-  GLB c2* S = gp(I->S);
-  const uint32_t fs = (uint32_t)I->field_stride;
-  const int rows = I->rows;
+  const double eps = uni_d(I->eps);
+  const double e2 = eps * eps, tau = uni_d(I->tau), eta2 = uni_d(I->eta2);
+  GLB c2* S = gp(uni_p(I->S));
+  const uint32_t fs = (uint32_t)uni_u64((uint64_t)I->field_stride);
+  const int rows = uni_i(I->rows);
   c2 z[RM];
   // p first: lv is no longer needed once it is formed.
 #pragma unroll
@@ -612,31 +614,42 @@ __device__ __forceinline__ void fch_forward_pair(const InstDev* I, const double 
 
 // MPS: implicit midpoint (the nonlinear terms are taken at
 // theta y + (1 - theta) u^n); otherwise theta = 1 and u^n is not read.
+// The plan's register budget, except for the FCH midpoint form, which holds
+// u^n and its Laplacian besides and would spill under it.
 template <class PX, int MODEL, bool MPS>
-__global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restrict__ grp, int bpi,
+constexpr int row_min_waves() {
+  return MODEL == MODEL_FCH && MPS ? 1 : PX::MIN_WAVES;
+}
+
+template <class PX, int MODEL, bool MPS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(row_min_waves<PX, MODEL, MPS>()))) void k_row_iter(
+    const InstDev* const* __restrict__ grp, int bpi,
                                                   int l, int /*total*/) {
   extern __shared__ c2 smem[];
   __shared__ uint64_t red[4];
   __shared__ InstDev rec;
   const GroupPos gpos = group_pos(grp, bpi);
   const InstDev* __restrict__ I = stage_record(gpos.I, &rec);
-  const int j = *I->iter_base + l;
-  if (stopped_before(I, j)) return;
+  const int j = uni_i(*I->iter_base + l);
+  if (uni_i(stopped_before(I, j))) return;
   constexpr int N = PX::N, T = PX::T, RM = PX::RMAX;
   const int teams = blockDim.x / T;
   const int team = threadIdx.x / T, t = threadIdx.x - team * T;
   c2* lds = smem + team * lds_len(N);
   const int r0 = 2 * (gpos.lb * teams + team);
-  const int rows = I->rows;
-  const uint32_t fs = (uint32_t)I->field_stride;
-  const int ne = I->n_eta;
-  const double lam = I->lam[j % ne], lamn = I->lam[(j + 1) % ne];
-  const double s = I->s, th = I->theta;
+  // record scalars and field bases in scalar registers; element offsets
+  // from opaque copies of t, formed where they are used
+  const int rows = uni_i(I->rows);
+  const uint32_t fs = (uint32_t)uni_u64((uint64_t)I->field_stride);
+  const int ne = uni_i(I->n_eta);
+  const double lam = uni_d(I->lam[j % ne]), lamn = uni_d(I->lam[(j + 1) % ne]);
+  const double s = uni_d(I->s), th = uni_d(I->theta);
   constexpr bool mp = MPS;
-  const auto xj = gp(I->X[j % 3]);
-  const auto xm = gp(I->X[(j + 2) % 3]);
-  auto xn = gp(I->X[(j + 1) % 3]);
-  const auto un = gp(I->un);
+  const auto xj = gp(uni_p(I->X[j % 3]));
+  const auto xm = gp(uni_p(I->X[(j + 2) % 3]));
+  auto xn = gp(uni_p(I->X[(j + 1) % 3]));
+  const auto un = gp(uni_p(I->un));
+  GLB c2* Sg = gp(uni_p(I->S));
   uint64_t dmax = 0;
   Twiddles<PX> tw;
   load_twiddles<PX>(tw, I->tw_x, t);
@@ -654,14 +667,15 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
       }
     }
     c2 v[RM];
-    load_pack<PX>(v, gp(I->S), r0, gp(I->S), r0 + 1, rows, t);
+    load_pack<PX>(v, Sg, r0, Sg, r0 + 1, rows, t);
     fft<PX, true>(v, lds, tw, t);
     double vb[2][RM];
+    const int tl = opaque(t);
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+        const uint32_t idx = (uint32_t)(r0 + row) * N + tl + m * T;
         const double d = row ? v[m].y : v[m].x;
         const double y = a[row][m] + lam * (a[row][m] - b[row][m]);
         const double x1 = y + s * d;
@@ -674,10 +688,10 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
     }
     pfc_forward_pair<PX>(I, vb, tw, lds, r0, t);
   } else {
-    const auto dxj = gp(I->DX[j % 3]);
-    const auto dxm = gp(I->DX[(j + 2) % 3]);
-    auto dxn = gp(I->DX[(j + 1) % 3]);
-    const auto dun = gp(I->dun);
+    const auto dxj = gp(uni_p(I->DX[j % 3]));
+    const auto dxm = gp(uni_p(I->DX[(j + 2) % 3]));
+    auto dxn = gp(uni_p(I->DX[(j + 1) % 3]));
+    const auto dun = gp(uni_p(I->dun));
     // Both real rows of the pair at once, one transform per spectral field:
     // the direction d (field 0) first, then its Laplacian (field 1), so
     // every spectral read covers whole 128-byte lines of the tiled layout.
@@ -688,11 +702,12 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
     double vbs[2][RM], lv[2][RM];
     double a[2][RM], b[2][RM], uu[2][RM], la[2][RM], lb[2][RM], lu[2][RM];
     auto load_x = [&]() {
+      const int tl = opaque(t);
 #pragma unroll
       for (int row = 0; row < 2; ++row) {
 #pragma unroll
         for (int m = 0; m < RM; ++m) {
-          const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+          const uint32_t idx = (uint32_t)(r0 + row) * N + tl + m * T;
           a[row][m] = xj[idx];
           b[row][m] = xm[idx];
           uu[row][m] = mp ? un[idx] : 0.0;
@@ -700,11 +715,12 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
       }
     };
     auto load_l = [&]() {
+      const int tl = opaque(t);
 #pragma unroll
       for (int row = 0; row < 2; ++row) {
 #pragma unroll
         for (int m = 0; m < RM; ++m) {
-          const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+          const uint32_t idx = (uint32_t)(r0 + row) * N + tl + m * T;
           la[row][m] = dxj[idx];
           lb[row][m] = dxm[idx];
           lu[row][m] = mp ? dun[idx] : 0.0;
@@ -712,19 +728,20 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
       }
     };
     c2 v[RM], w[RM];
-    load_pack<PX>(v, gp(I->S), r0, gp(I->S), r0 + 1, rows, t);
+    load_pack<PX>(v, Sg, r0, Sg, r0 + 1, rows, t);
     if constexpr (EARLY) {
-      load_pack<PX>(w, gp(I->S) + fs, r0, gp(I->S) + fs, r0 + 1, rows, t);
+      load_pack<PX>(w, Sg + fs, r0, Sg + fs, r0 + 1, rows, t);
       load_x();
       load_l();
     }
     fft<PX, true>(v, lds, tw, t);
     if constexpr (!EARLY) load_x();
+    const int tx = opaque(t);
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+        const uint32_t idx = (uint32_t)(r0 + row) * N + tx + m * T;
         const double d = row ? v[m].y : v[m].x;
         const double y = a[row][m] + lam * (a[row][m] - b[row][m]);
         const double x1 = y + s * d;
@@ -735,14 +752,15 @@ __global__ __launch_bounds__(256) void k_row_iter(const InstDev* const* __restri
         vbs[row][m] = mp ? th * yn + (1.0 - th) * uu[row][m] : yn;
       }
     }
-    if constexpr (!EARLY) load_pack<PX>(w, gp(I->S) + fs, r0, gp(I->S) + fs, r0 + 1, rows, t);
+    if constexpr (!EARLY) load_pack<PX>(w, Sg + fs, r0, Sg + fs, r0 + 1, rows, opaque(t));
     fft<PX, true>(w, lds, tw, t);
     if constexpr (!EARLY) load_l();
+    const int tw2 = opaque(t);
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
+        const uint32_t idx = (uint32_t)(r0 + row) * N + tw2 + m * T;
         const double ld = row ? w[m].y : w[m].x;
         const double ly = la[row][m] + lam * (la[row][m] - lb[row][m]);
         const double lx1 = ly + s * ld;
