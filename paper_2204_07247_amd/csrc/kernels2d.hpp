@@ -1223,40 +1223,59 @@ __global__ __launch_bounds__(256) void k_row_setup_lap(InstDev* const* __restric
   }
 
   double s0 = 0.0, s1 = 0.0;
-  double gv[2][RM], vb[2][RM];
-  const double tau = I->tau, e2 = I->eps * I->eps;
+  const double tau = uni_d(I->tau), eps = uni_d(I->eps), e2 = eps * eps;
+  const double eta1 = uni_d(I->eta1), eta2 = uni_d(I->eta2);
+  const auto un = gp(sa.un), unm1 = gp(sa.unm1);
+  {  // g first, alone: u^n and u^{n-1} are read again below (from L2)
+    double gv[2][RM];
+    const int tl = opaque(t);
 #pragma unroll
-  for (int row = 0; row < 2; ++row) {
+    for (int row = 0; row < 2; ++row) {
 #pragma unroll
-    for (int m = 0; m < RM; ++m) {
-      const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
-      const double u = gp(sa.un)[idx], um = gp(sa.unm1)[idx];
-      const double x0 = u + sa.rho * (u - um);
-      gp(I->X[0])[idx] = x0;
-      gp(I->X[2])[idx] = x0;
-      gv[row][m] = sa.gu * u + sa.gm * um;
-      const double v = th * x0 + (1.0 - th) * u;
-      vb[row][m] = v;
-      const double f1 = (v * v - 1.0) * (v + tau);
-      const double f2 = 3.0 * v * v - 1.0 + 2.0 * tau * v;
-      const double f3 = 6.0 * v + 2.0 * tau;
-      s0 += f2 * f2 - I->eta2 * f2 + f3 * f1;
-      s1 += e2 * f2 - I->eta1 * e2;
+      for (int m = 0; m < RM; ++m) {
+        const uint32_t idx = (uint32_t)(r0 + row) * N + tl + m * T;
+        gv[row][m] = sa.gu * un[idx] + sa.gm * unm1[idx];
+      }
+    }
+    pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, gp(I->G), r0 + 1, rows, t);
+  }
+  double vb[2][RM];
+  {
+    const int tl = opaque(t);
+#pragma unroll
+    for (int row = 0; row < 2; ++row) {
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const uint32_t idx = (uint32_t)(r0 + row) * N + tl + m * T;
+        const double u = un[idx], um = unm1[idx];
+        const double x0 = u + sa.rho * (u - um);
+        gp(I->X[0])[idx] = x0;
+        gp(I->X[2])[idx] = x0;
+        const double v = th * x0 + (1.0 - th) * u;
+        vb[row][m] = v;
+        const double f1 = (v * v - 1.0) * (v + tau);
+        const double f2 = 3.0 * v * v - 1.0 + 2.0 * tau * v;
+        const double f3 = 6.0 * v + 2.0 * tau;
+        s0 += f2 * f2 - eta2 * f2 + f3 * f1;
+        s1 += e2 * f2 - eta1 * e2;
+      }
     }
   }
-  pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, gp(I->G), r0 + 1, rows, t);
   double lv[2][RM];
+  {
+    const int tl = opaque(t);
 #pragma unroll
-  for (int row = 0; row < 2; ++row) {
+    for (int row = 0; row < 2; ++row) {
 #pragma unroll
-    for (int m = 0; m < RM; ++m) {
-      const uint32_t idx = (uint32_t)(r0 + row) * N + t + m * T;
-      const double lu = gp(sa.lun)[idx], lum = gp(sa.lunm1)[idx];
-      const double lx0 = lu + sa.rho * (lu - lum);
-      gp(I->DX[0])[idx] = lx0;
-      gp(I->DX[2])[idx] = lx0;
-      if (th != 1.0) gp(I->dun)[idx] = lu;
-      lv[row][m] = th * lx0 + (1.0 - th) * lu;
+      for (int m = 0; m < RM; ++m) {
+        const uint32_t idx = (uint32_t)(r0 + row) * N + tl + m * T;
+        const double lu = gp(sa.lun)[idx], lum = gp(sa.lunm1)[idx];
+        const double lx0 = lu + sa.rho * (lu - lum);
+        gp(I->DX[0])[idx] = lx0;
+        gp(I->DX[2])[idx] = lx0;
+        if (th != 1.0) gp(I->dun)[idx] = lu;
+        lv[row][m] = th * lx0 + (1.0 - th) * lu;
+      }
     }
   }
   fch_forward_pair<PX>(I, vb, lv, tw, lds, r0, t);

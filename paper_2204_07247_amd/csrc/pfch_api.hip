@@ -2084,10 +2084,15 @@ struct SolveOut {
   std::vector<double> dn, a;
 };
 
-// Up to Nx = 1024 the fused set-up (one row kernel doing four transforms)
-// is faster than the three-kernel path; at 2048 its register use leaves one
-// wave per SIMD and the split path wins, so the Laplacians are not kept.
-bool lap_history_pays(const Instance& I) { return I.nx <= 1024; }
+// The fused set-up (one row kernel doing four transforms, the column set-up
+// folded into the first column iteration) is faster than the three-kernel
+// path at every supported row length once its register use allows two waves
+// per SIMD (g is transformed on its own, before x0 and v_breve are formed:
+// 236 registers at 2048, 302 when they were all live at once).  Combined
+// FCH 1024^2 + 2048^2 + PFC 192^3 set, batched: 68.5 -> 69.3 time-steps/s
+// with the Laplacians kept at 2048 too, although the accept then also
+// copies the Laplacian.
+bool lap_history_pays(const Instance& I) { return I.nx <= 2048; }
 
 // FCH with an extrapolated guess and two kept Laplacians: the set-up takes
 // Delta x0 from them instead of from transforms of x0.

@@ -88,6 +88,23 @@ def test_trajectory_matches_oracle(w, nsteps):
     assert rel_l2(got, ref) <= 1e-9
 
 
+@pytest.mark.parametrize("nx", [1024, 2048])
+def test_long_rows_trajectory_with_kept_laplacians(nx):
+    """FCH BDF2 on a 16 x Nx grid (the grid spacing of the 256^2 workload),
+    five steps: from the third step on the set-up takes Delta x0 from the
+    Laplacians the earlier accepts kept (the one-kernel set-up at the longest
+    rows).  Identical iteration counts and rel L2 <= 1e-9 against the
+    oracle."""
+    h = W.FCH256_BDF2.lengths[0] / W.FCH256_BDF2.shape[0]
+    w = dataclasses.replace(W.FCH256_BDF2, shape=(16, nx), lengths=(16 * h, nx * h), seeds=(5,))
+    u0 = W.initial_condition(w)
+    print(f"case fch 16x{nx} steps=5", flush=True)
+    ref, ref_iters = oracle_run(w, u0, 5)
+    got, iters = run_gpu(w, u0, 5)
+    assert iters == ref_iters
+    assert rel_l2(got, ref) <= 1e-9
+
+
 def test_two_runs_are_bitwise_identical():
     w = W.FCH256_BDF2
     u0 = W.initial_condition(w, seed=3)
