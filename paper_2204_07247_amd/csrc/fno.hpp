@@ -479,19 +479,22 @@ inline unsigned blocks_for(long long n, int t = 256) { return (unsigned)((n + t 
 // ---------------------------------------------------------------------------
 struct Resampler {
   int ny = 0, nx = 0;             // fine grid
+  int nb = 0;                     // samples the buffers below hold (the network's batch)
   float *Dx = nullptr, *Dy = nullptr;  // [Nx][Ncx], [Ncy][Ny]
   float *Uy = nullptr, *Ux = nullptr;  // [Ny][Ncy], [Ncx][Nx]
-  float *T1 = nullptr;            // [2][Ny][Ncx]
-  float *T2 = nullptr;            // [Ny][Ncx]
-  float *Xf = nullptr;            // [2][Ny][Nx] fine network inputs
-  float *yf = nullptr;            // [Ny][Nx] fine correction (or fine target)
+  float *T1 = nullptr;            // [nb][2][Ny][Ncx]
+  float *T2 = nullptr;            // [nb][Ny][Ncx]
+  float *Xf = nullptr;            // [nb][2][Ny][Nx] fine network inputs
+  float *yf = nullptr;            // [nb][Ny][Nx] fine corrections (or fine targets)
 };
 
-// c[ch][Ncy][Ncx] = Dy f[ch] Dx for `ch` fine fields f[ch][Ny][Nx].
-inline hipError_t resample_down(const Fno& F, const Resampler& R, const float* f, int ch, float* c,
+// c[b][ch][Ncy][Ncx] = Dy f[b][ch] Dx for nb samples of `ch` fine fields
+// f[b][ch][Ny][Nx]: one strided batched product per stage, each sample's
+// product of the same shape whatever nb is.
+inline hipError_t resample_down(const Fno& F, const Resampler& R, const float* f, int ch, float* c, int nb,
                                 hipStream_t s);
-// R.yf = Uy c Ux for one coarse field c[Ncy][Ncx].
-inline hipError_t resample_up(const Fno& F, const Resampler& R, const float* c, hipStream_t s);
+// R.yf[b] = Uy c[b] Ux for nb coarse fields c[b] = c + b P (P coarse points).
+inline hipError_t resample_up(const Fno& F, const Resampler& R, const float* c, int nb, hipStream_t s);
 
 // Forward pass for `B` samples x[B][2][grid]; keeps every layer's input,
 // pre-activation and retained spectrum for the backward pass; y[B][grid].
@@ -630,22 +633,22 @@ inline hipError_t sgemm_rm(const Fno& F, int M, int N, int K, const float* A, lo
   return st == rocblas_status_success ? hipSuccess : hipErrorUnknown;
 }
 
-inline hipError_t resample_down(const Fno& F, const Resampler& R, const float* f, int ch, float* c,
+inline hipError_t resample_down(const Fno& F, const Resampler& R, const float* f, int ch, float* c, int nb,
                                 hipStream_t s) {
-  const int ny = R.ny, nx = R.nx, ncy = F.ny, ncx = F.nx;
-  // T1[ch * Ny + y][xc] = sum_x f[ch][y][x] Dx[x][xc]
-  FNO_CHK(sgemm_rm(F, ch * ny, ncx, nx, f, 0, R.Dx, 0, R.T1, 0, 1, s));
-  // c[ch][yc][xc] = sum_y Dy[yc][y] T1[ch][y][xc]
-  FNO_CHK(sgemm_rm(F, ncy, ncx, ny, R.Dy, 0, R.T1, (long long)ny * ncx, c, (long long)ncy * ncx, ch, s));
+  const long long ny = R.ny, nx = R.nx, ncy = F.ny, ncx = F.nx;
+  // T1[b][ch * Ny + y][xc] = sum_x f[b][ch][y][x] Dx[x][xc]
+  FNO_CHK(sgemm_rm(F, (int)(ch * ny), (int)ncx, (int)nx, f, ch * ny * nx, R.Dx, 0, R.T1, ch * ny * ncx, nb, s));
+  // c[b][ch][yc][xc] = sum_y Dy[yc][y] T1[b][ch][y][xc]
+  FNO_CHK(sgemm_rm(F, (int)ncy, (int)ncx, (int)ny, R.Dy, 0, R.T1, ny * ncx, c, ncy * ncx, nb * ch, s));
   return hipSuccess;
 }
 
-inline hipError_t resample_up(const Fno& F, const Resampler& R, const float* c, hipStream_t s) {
-  const int ny = R.ny, nx = R.nx, ncy = F.ny, ncx = F.nx;
-  // T2[y][xc] = sum_yc Uy[y][yc] c[yc][xc]
-  FNO_CHK(sgemm_rm(F, ny, ncx, ncy, R.Uy, 0, c, 0, R.T2, 0, 1, s));
-  // yf[y][x] = sum_xc T2[y][xc] Ux[xc][x]
-  FNO_CHK(sgemm_rm(F, ny, nx, ncx, R.T2, 0, R.Ux, 0, R.yf, 0, 1, s));
+inline hipError_t resample_up(const Fno& F, const Resampler& R, const float* c, int nb, hipStream_t s) {
+  const long long ny = R.ny, nx = R.nx, ncy = F.ny, ncx = F.nx;
+  // T2[b][y][xc] = sum_yc Uy[y][yc] c[b][yc][xc]
+  FNO_CHK(sgemm_rm(F, (int)ny, (int)ncx, (int)ncy, R.Uy, 0, c, F.P, R.T2, ny * ncx, nb, s));
+  // yf[b][y][x] = sum_xc T2[b][y][xc] Ux[xc][x]
+  FNO_CHK(sgemm_rm(F, (int)ny, (int)nx, (int)ncx, R.T2, ny * ncx, R.Ux, 0, R.yf, ny * nx, nb, s));
   return hipSuccess;
 }
 

@@ -1017,25 +1017,48 @@ int learned_guesses(pfch_ctx* ctx, const std::vector<int>& ids, const std::vecto
         chunk.push_back(b);
         done[b] = 1;
       }
-    for (size_t k = 0; k < chunk.size(); ++k) {
-      Instance& I = ctx->inst[ids[chunk[k]]];
-      const double* nrm = I.fno_norm;
-      const long long P = I.npts;
-      float* xin = F.xin + (long long)k * 2 * F.P;
-      float* dst = I.fno_rs ? I.fno_rs->Xf : xin;
-      hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(P)), dim3(256), 0, s, I.U[1 - I.ucur], I.U[I.ucur],
-                         (const double*)nullptr, P, rho[chunk[k]], nrm[0], nrm[1], nrm[2], nrm[3], dst,
-                         (float*)nullptr);
-      if (I.fno_rs && resample_down(F, *I.fno_rs, I.fno_rs->Xf, 2, xin, s) != hipSuccess) return PFCH_E_HIP;
+    // batch slots ordered by fine grid, so that the resampling products of
+    // the instances on one fine grid are one batched call per stage
+    std::stable_sort(chunk.begin(), chunk.end(), [&](size_t x, size_t y) {
+      return (uintptr_t)ctx->inst[ids[x]].fno_rs < (uintptr_t)ctx->inst[ids[y]].fno_rs;
+    });
+    // runs[r] = (first slot, count) of instances sharing one resampler (or none)
+    std::vector<std::pair<size_t, size_t>> runs;
+    for (size_t k = 0; k < chunk.size(); ++k)
+      if (k == 0 || ctx->inst[ids[chunk[k]]].fno_rs != ctx->inst[ids[chunk[k - 1]]].fno_rs)
+        runs.push_back({k, 1});
+      else
+        ++runs.back().second;
+    for (const auto& run : runs) {
+      Resampler* R = ctx->inst[ids[chunk[run.first]]].fno_rs;
+      for (size_t j = 0; j < run.second; ++j) {
+        const size_t k = run.first + j;
+        Instance& I = ctx->inst[ids[chunk[k]]];
+        const double* nrm = I.fno_norm;
+        const long long P = I.npts;
+        float* dst = R ? R->Xf + (long long)j * 2 * P : F.xin + (long long)k * 2 * F.P;
+        hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(P)), dim3(256), 0, s, I.U[1 - I.ucur], I.U[I.ucur],
+                           (const double*)nullptr, P, rho[chunk[k]], nrm[0], nrm[1], nrm[2], nrm[3], dst,
+                           (float*)nullptr);
+      }
+      if (R && resample_down(F, *R, R->Xf, 2, F.xin + (long long)run.first * 2 * F.P, (int)run.second, s) !=
+                   hipSuccess)
+        return PFCH_E_HIP;
     }
     if (fno_forward(F, F.xin, (int)chunk.size(), s) != hipSuccess) return PFCH_E_HIP;
+    for (const auto& run : runs) {
+      Resampler* R = ctx->inst[ids[chunk[run.first]]].fno_rs;
+      if (R && resample_up(F, *R, F.y + (long long)run.first * F.P, (int)run.second, s) != hipSuccess)
+        return PFCH_E_HIP;
+    }
     for (size_t k = 0; k < chunk.size(); ++k) {
       Instance& I = ctx->inst[ids[chunk[k]]];
       const long long P = I.npts;
       const float* y = F.y + (long long)k * F.P;
       if (I.fno_rs) {
-        if (resample_up(F, *I.fno_rs, y, s) != hipSuccess) return PFCH_E_HIP;
-        y = I.fno_rs->yf;
+        size_t first = k;
+        while (first > 0 && ctx->inst[ids[chunk[first - 1]]].fno_rs == I.fno_rs) --first;
+        y = I.fno_rs->yf + (long long)(k - first) * P;
       }
       hipLaunchKernelGGL(k_partial_sum, dim3(FNO_SUM_BLOCKS), dim3(256), 0, s, y, P, I.gpart);
       hipLaunchKernelGGL(k_learned_guess, dim3(std::min(blocks_for(P), 4096u)), dim3(256), 0, s,
@@ -2900,7 +2923,8 @@ int fno_resampler(Fno& F, int ny, int nx, Resampler** out) {
   F.rs.push_back(R);  // freed with the network
   R->ny = ny;
   R->nx = nx;
-  const long long ncy = F.ny, ncx = F.nx;
+  R->nb = F.maxb;
+  const long long ncy = F.ny, ncx = F.nx, nb = F.maxb;
   auto fal = [&](float** p, long long nfloats) {
     void* q = nullptr;
     const int rc = dalloc(F.allocs, &q, sizeof(float) * (size_t)nfloats);
@@ -2909,8 +2933,9 @@ int fno_resampler(Fno& F, int ny, int nx, Resampler** out) {
   };
   int rc;
   if ((rc = fal(&R->Dx, nx * ncx)) || (rc = fal(&R->Dy, ncy * ny)) || (rc = fal(&R->Uy, ny * ncy)) ||
-      (rc = fal(&R->Ux, ncx * nx)) || (rc = fal(&R->T1, 2LL * ny * ncx)) || (rc = fal(&R->T2, (long long)ny * ncx)) ||
-      (rc = fal(&R->Xf, 2LL * ny * nx)) || (rc = fal(&R->yf, (long long)ny * nx)))
+      (rc = fal(&R->Ux, ncx * nx)) || (rc = fal(&R->T1, 2LL * nb * ny * ncx)) ||
+      (rc = fal(&R->T2, (long long)nb * ny * ncx)) || (rc = fal(&R->Xf, 2LL * nb * ny * nx)) ||
+      (rc = fal(&R->yf, (long long)nb * ny * nx)))
     return rc;
   // kernel(n, nc, i, ic) = (1/n) (1 + 2 sum_{k=1}^{nc/2-1} cos 2 pi k (ic/nc - i/n)); the
   // angle's numerator is reduced exactly in integers modulo n nc
@@ -3059,8 +3084,8 @@ int pfch_fno_prepare_resampled(pfch_fno* f, int32_t ny, int32_t nx, const double
   hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(P)), dim3(256), 0, F.s, u_nm1, u_n, u_np1, P, rho, norm[0],
                      norm[1], norm[2], norm[3], R->Xf, t ? R->yf : (float*)nullptr);
   HIPCHK(hipGetLastError());
-  if (resample_down(F, *R, R->Xf, 2, x, F.s) != hipSuccess) return PFCH_E_HIP;
-  if (t && resample_down(F, *R, R->yf, 1, t, F.s) != hipSuccess) return PFCH_E_HIP;
+  if (resample_down(F, *R, R->Xf, 2, x, 1, F.s) != hipSuccess) return PFCH_E_HIP;
+  if (t && resample_down(F, *R, R->yf, 1, t, 1, F.s) != hipSuccess) return PFCH_E_HIP;
   return PFCH_OK;
 }
 
