@@ -253,9 +253,13 @@ int pfch_set_stats_detail(pfch_ctx* ctx, int32_t detail);
  * HIP start/stop event pair attached to every iteration-kernel launch
  * (hipExtLaunchKernel).  out[k] = average microseconds of the k-th iteration
  * kernel over the launches that did an iteration's work: 2D {column, row,
- * 0, 0}; 3D {y forward, z, y inverse, row}.  The instance's state (u^n,
- * u^{n-1}, t, step index) is not changed; its iteration workspaces are. */
-int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]);
+ * 0, 0}; 3D {y forward, z, y inverse, row}.  Then solves it `reps` times
+ * more with one event before the first launch and one after the last
+ * iteration in which every instance worked: out[4] = microseconds per
+ * iteration of that chain of launches (no per-launch events; the gaps
+ * between launches included).  The instance's state (u^n, u^{n-1}, t, step
+ * index) is not changed; its iteration workspaces are. */
+int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[5]);
 
 /* The same timing for the grouped launches of every instance of `inst`'s
  * group (instances of one model, scheme and grid share each iteration-kernel
@@ -263,7 +267,7 @@ int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]);
  * pair on each launch; averages over the iterations in which every member
  * still worked.  The members' states are not changed; their iteration
  * workspaces are. */
-int pfch_time_group(pfch_ctx* ctx, int32_t inst, double dt, int32_t reps, double out[4]);
+int pfch_time_group(pfch_ctx* ctx, int32_t inst, double dt, int32_t reps, double out[5]);
 
 /* Kernel timing with HIP events: sets up one step of instance 0 (as
  * pfch_step would), then launches each iteration kernel `reps` times back

@@ -1857,7 +1857,7 @@ namespace {
 // still worked.  The members' states are not changed; their iteration
 // workspaces are, and they are parked afterwards.
 int time_iterations(pfch_ctx* ctx, Group& G, InstDev** grp, const std::vector<int>& members, double dt, int reps,
-                    double out[4]) {
+                    double out[5]) {
   const unsigned nm = (unsigned)members.size();
   Stage st[4];
   const int ns = iter_stages(G, st);
@@ -1873,8 +1873,15 @@ int time_iterations(pfch_ctx* ctx, Group& G, InstDev** grp, const std::vector<in
   std::vector<uint64_t> norms((size_t)nm * nit);
   double sum[4] = {0, 0, 0, 0};
   int cnt[4] = {0, 0, 0, 0};
+  int work = nit;  // iterations in which every member worked (the same in every solve)
+  double chain_sum = 0.0;
+  int chain_cnt = 0;
   int rc = PFCH_OK;
-  for (int r = 0; r < reps && rc == PFCH_OK; ++r) {
+  // reps solves with an event pair on every launch, then reps solves with one
+  // event before the first launch and one after the last working iteration
+  for (int r = 0; r < 2 * reps && rc == PFCH_OK; ++r) {
+    const bool chained = r >= reps;
+    if (chained && work < 1) break;
     if (nm == 1) {
       if ((rc = launch_setup_solo(ctx, ctx->inst[members[0]], step_setup_for(ctx->inst[members[0]], dt), false)))
         break;
@@ -1890,17 +1897,19 @@ int time_iterations(pfch_ctx* ctx, Group& G, InstDev** grp, const std::vector<in
       }
       if ((rc = launch_setup(ctx, G, grp, G.d_args, nm, nullptr, true, false, false))) break;
     }
-    for (int j = 0; j < nit && rc == PFCH_OK; ++j)
-      for (int k = 0; k < ns; ++k) {
+    for (int j = 0; j < nit && rc == PFCH_OK; ++j) {
+      if (chained && j == 0 && hipEventRecord(ev[0], ctx->stream) != hipSuccess) rc = PFCH_E_HIP;
+      for (int k = 0; k < ns && rc == PFCH_OK; ++k) {
         int bpi = st[k].bpi, lv = j, total = (int)nm * bpi;
         void* a[] = {&grp, &bpi, &lv, &total};
         hipEvent_t* e = &ev[2 * ((size_t)j * ns + k)];
         if (hipExtLaunchKernel(st[k].f, dim3(stage_grid(st[k], nm)), st[k].block, a, st[k].lds, ctx->stream,
-                               e[0], e[1], 0) != hipSuccess) {
+                               chained ? nullptr : e[0], chained ? nullptr : e[1], 0) != hipSuccess)
           rc = PFCH_E_HIP;
-          break;
-        }
       }
+      if (chained && j == work - 1 && rc == PFCH_OK && hipEventRecord(ev[1], ctx->stream) != hipSuccess)
+        rc = PFCH_E_HIP;
+    }
     if (rc) break;
     for (unsigned k = 0; k < nm && rc == PFCH_OK; ++k)
       if (hipMemcpyAsync(norms.data() + (size_t)k * nit, ctx->inst[members[k]].h.norms, sizeof(uint64_t) * nit,
@@ -1910,8 +1919,17 @@ int time_iterations(pfch_ctx* ctx, Group& G, InstDev** grp, const std::vector<in
       rc = PFCH_E_HIP;
       break;
     }
+    if (chained) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[0], ev[1]) == hipSuccess) {
+        chain_sum += 1e3 * t / work;
+        chain_cnt += 1;
+      }
+      continue;
+    }
     // iteration j did work for every member if j = 0 or no member stopped at j-1
-    for (int j = 0; j < nit; ++j) {
+    int j = 0;
+    for (; j < nit; ++j) {
       bool all = true;
       for (unsigned k = 0; k < nm && j > 0; ++k) {
         const uint64_t b = norms[(size_t)k * nit + j - 1];
@@ -1926,10 +1944,12 @@ int time_iterations(pfch_ctx* ctx, Group& G, InstDev** grp, const std::vector<in
         cnt[k] += 1;
       }
     }
+    work = std::min(work, j);
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc) return rc;
   for (int k = 0; k < 4; ++k) out[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+  out[4] = chain_cnt ? chain_sum / chain_cnt : 0.0;
   // park the members so that later chunk launches leave them alone
   if ((rc = launch_park(ctx, grp, (int)nm))) return rc;
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1940,14 +1960,14 @@ int time_iterations(pfch_ctx* ctx, Group& G, InstDev** grp, const std::vector<in
 
 extern "C" {
 
-int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[4]) {
+int pfch_time_kernels(pfch_ctx* ctx, double dt, int32_t reps, double out[5]) {
   if (!ctx || !out || reps < 1 || !(dt > 0.0) || !std::isfinite(dt)) return PFCH_E_INVAL;
   if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
   Instance& I = ctx->inst[0];
   return time_iterations(ctx, ctx->groups[I.group], I.d_solo, std::vector<int>{0}, dt, reps, out);
 }
 
-int pfch_time_group(pfch_ctx* ctx, int32_t inst, double dt, int32_t reps, double out[4]) {
+int pfch_time_group(pfch_ctx* ctx, int32_t inst, double dt, int32_t reps, double out[5]) {
   if (!ctx || !out || inst < 0 || inst >= (int)ctx->inst.size() || reps < 1 || !(dt > 0.0) || !std::isfinite(dt))
     return PFCH_E_INVAL;
   if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change

@@ -244,6 +244,16 @@ def _stream_handle():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _timing(out, chained):
+    if out[2] == 0.0 and out[3] == 0.0:
+        d = dict(col_us=out[0], row_us=out[1])
+    else:
+        d = dict(yfwd_us=out[0], z_us=out[1], yinv_us=out[2], row_us=out[3])
+    if chained:
+        d["iteration_us"] = out[4]
+    return d
+
+
 class Context:
     """A set of instances that advance together (pfch_create ... pfch_destroy)."""
 
@@ -283,26 +293,24 @@ class Context:
         """Average microseconds per launch of instance 0's iteration kernels:
         HIP events on every launch of `reps` solves (default), or HIP events
         around `reps` back-to-back launches of each kernel (events=True).
-        2D {col_us, row_us}; 3D {yfwd_us, z_us, yinv_us, row_us}."""
-        out = (ctypes.c_double * 4)()
+        2D {col_us, row_us}; 3D {yfwd_us, z_us, yinv_us, row_us}; with the
+        solve's timing also iteration_us, the time per iteration of the
+        chain of launches without per-launch events."""
+        out = (ctypes.c_double * 5)()
         fn = lib().pfch_time_kernels_events if events else lib().pfch_time_kernels
         rc = fn(self._h, float(dt), int(reps), out)
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_time_kernels")
-        if out[2] == 0.0 and out[3] == 0.0:
-            return dict(col_us=out[0], row_us=out[1])
-        return dict(yfwd_us=out[0], z_us=out[1], yinv_us=out[2], row_us=out[3])
+        return _timing(out, not events)
 
     def time_group(self, inst, dt, reps):
         """Average microseconds per grouped launch of the iteration kernels of
         instance `inst`'s group (pfch_time_group); keys as time_kernels."""
-        out = (ctypes.c_double * 4)()
+        out = (ctypes.c_double * 5)()
         rc = lib().pfch_time_group(self._h, int(inst), float(dt), int(reps), out)
         if rc != PFCH_OK:
             raise PfchError(rc, "pfch_time_group")
-        if out[2] == 0.0 and out[3] == 0.0:
-            return dict(col_us=out[0], row_us=out[1])
-        return dict(yfwd_us=out[0], z_us=out[1], yinv_us=out[2], row_us=out[3])
+        return _timing(out, True)
 
     def launch_config(self, inst=0):
         out = (ctypes.c_int64 * 6)()
