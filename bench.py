@@ -801,17 +801,20 @@ def learned3d_comparison(epochs, traj_steps, eval_steps):
 
 def extras(args):
     out = {}
-    out["pfc_ensemble"] = batched_comparison(64, steps=10, solo_steps=4)
-    out["ensembles"] = [ensemble_bandwidth(W.pfc_ensemble(count=64), steps=10, warmup=2,
+    # the PFC ensemble over its full 200 steps (one context per instance:
+    # the first 20)
+    out["pfc_ensemble"] = batched_comparison(64, steps=200, solo_steps=20)
+    out["ensembles"] = [ensemble_bandwidth(W.pfc_ensemble(count=64), steps=200, warmup=2,
                                            label="pfc2d_ensemble64 (128..512, MP)")]
     out["solver_variants"] = [solver_variants(W.FCH256_BDF2, steps=50),
                               solver_variants(W.PFC64_MP, steps=W.PFC64_MP.steps)]
     log("[bench] adaptive stepping (AM3 / midAB2)")
     out["adaptive"] = [adaptive_run(W.FCH256_BDF2, 1e-4, 1e-5, 0.5, attempts=200),
                        adaptive_run(W.PFC64_MP, 1e-4, 1e-4, 0.5, attempts=200)]
-    lr, tr2, _ = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=20)
+    # PFC 1024^2 deployments over the learned-guess workload's 500 steps
+    lr, tr2, _ = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=500)
     tr2.fno.close()
-    lr["pfc_trained"] = learned_pfc_trained(args.learned_epochs, eval_steps=100, deploy_steps=20)
+    lr["pfc_trained"] = learned_pfc_trained(args.learned_epochs, eval_steps=100, deploy_steps=500)
     if args.learned3d_epochs > 0:
         lr["pfc3d"], tr3, _ = learned3d_comparison(args.learned3d_epochs, traj_steps=40, eval_steps=40)
         tr3.fno.close()
