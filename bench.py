@@ -810,7 +810,8 @@ def extras(args):
                               solver_variants(W.PFC64_MP, steps=W.PFC64_MP.steps)]
     log("[bench] adaptive stepping (AM3 / midAB2)")
     out["adaptive"] = [adaptive_run(W.FCH256_BDF2, 1e-4, 1e-5, 0.5, attempts=200),
-                       adaptive_run(W.PFC64_MP, 1e-4, 1e-4, 0.5, attempts=200)]
+                       adaptive_run(W.PFC64_MP, 1e-4, 1e-4, 0.5, attempts=200),
+                       adaptive_run(W.PFC192_3D, 1e-4, 1e-4, 0.5, attempts=100)]
     # PFC 1024^2 deployments over the learned-guess workload's 500 steps
     lr, tr2, _ = learned_comparison(args.learned_epochs, eval_steps=100, deploy_steps=500)
     tr2.fno.close()
@@ -819,6 +820,18 @@ def extras(args):
         lr["pfc3d"], tr3, _ = learned3d_comparison(args.learned3d_epochs, traj_steps=40, eval_steps=40)
         tr3.fno.close()
     out["learned"] = lr
+    # the combined set over its full 300 steps, batched, without and with the
+    # learned guess (the headline runs the driver's step count)
+    log("[bench] combined set, 300 steps: batched and batched + learned")
+    import torch
+    ws = combined_set()
+    tr, _ = train_fch_network(args.learned_epochs)
+    long = {}
+    for mode in ("batched", "batched_learned"):
+        long[mode], _ = run_set(ws, mode, 300, args.warmup, tr)
+        torch.cuda.empty_cache()
+    tr.fno.close()
+    out["combined_300"] = long
     return out
 
 

@@ -164,7 +164,7 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
                const double* u_nm1, double* x, pfch_stats* st);
 
 /*
- * Adaptive time stepping (Sec. 3.1.2, Alg. 3), 2D grids.
+ * Adaptive time stepping (Sec. 3.1.2, Alg. 3), 2D grids and 3D PFC.
  *
  * One call is one pass of the loop body of Alg. 3 for every instance: a
  * tentative solve with step size res[i].dt_try, an error estimate ERR, the
@@ -191,8 +191,7 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
  * fixed order, so results do not depend on batching.
  * res: host array of n_inst; dt_try is read (> 0) and written.  Returns
  * PFCH_OK, or the solve's error code when an instance's solve failed at
- * dt~ <= dt_min (that instance cannot advance).  3D instances:
- * PFCH_E_UNSUPPORTED.
+ * dt~ <= dt_min (that instance cannot advance).
  */
 enum { PFCH_EST_AUTO = 0, PFCH_EST_AM3 = 1, PFCH_EST_MIDAB2 = 2 };
 
@@ -216,9 +215,9 @@ typedef struct pfch_adapt_result {
 int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* a, pfch_adapt_result* res);
 
 /* R(v) = M Delta mu(v) (the right-hand side of the PDE, Sec. 2) of instance
- * `inst`'s model on its grid, v and out device arrays of Nx*Ny doubles (may
- * not alias); 2D only.  Uses the instance's transform workspace; its state is
- * not changed. */
+ * `inst`'s model on its grid, v and out device arrays of Nx*Ny (3D:
+ * Nx*Ny*Nz) doubles (may not alias).  Uses the instance's transform
+ * workspace; its state is not changed. */
 int pfch_rhs(pfch_ctx* ctx, int32_t inst, const double* v, double* out);
 
 /* Allocation-free variant of pfch_rhs, for callers that cannot allocate or

@@ -1,6 +1,6 @@
-// Right-hand side R(v) = M Delta mu(v) of the PDE on 2D grids, and the
-// error estimate of the adaptive step control (Sec. 3.1.2): the AM3 value
-// needs R at the tentative and the two previous solutions.
+// Right-hand side R(v) = M Delta mu(v) of the PDE on 2D grids and 3D PFC
+// grids, and the error estimate of the adaptive step control (Sec. 3.1.2):
+// the AM3 value needs R at the tentative and the two previous solutions.
 //
 // The transforms run in the instance's spectral workspace S (free between
 // solves), with the tiled layout, column-0 packing and row pairing of the
@@ -14,12 +14,18 @@
 //              S2 <- v^x (p = -F'' omega - eta2 F', omega = eps^2 Delta v - F')
 //        cols  S0 <- R^ = -M q (eps^2 q F'^ + p^ + (eps^4 q^2 - eps^2 eta1 q) v^)
 //        rows  R  <- inverse x of S0
-// The 1/(Nx Ny) of the inverse transform is applied in k-space.  Every
+//   PFC 3D: rows  S0 <- (v^3)^x, S1 <- v^x (rows = Ny Nz, as above)
+//           y     S0, S1 <- forward y-transforms (column 0 split)
+//           z     S0 <- R^ = -M q (N^ + (1 - eps - 2q + q^2) v^), inverse in z
+//           y     S0 <- inverse y-transform (column 0 merged)
+//           rows  R  <- inverse x of S0
+// The 1/(Nx Ny Nz) of the inverse transform is applied in k-space.  Every
 // kernel takes a per-instance source (or destination) pointer; a null one
 // skips the instance.  `spec`, when not null, replaces S (three fields of
 // the instance's tiled spectral size) for every instance of the launch.
 #pragma once
 #include "kernels2d.hpp"
+#include "kernels3d.hpp"
 
 namespace pfch {
 
@@ -202,6 +208,95 @@ __global__ __launch_bounds__(512) void k_rhs_col(InstDev* const* __restrict__ gr
   const int ts = opaque(t);
 #pragma unroll
   for (int m = 0; m < RM; ++m) gstore(S + sidx(rows, ts + m * T, kp), acc[m]);
+}
+
+// 3D y-pass of R(v): forward y-transforms of S0 and S1 with column 0 split,
+// or (INV) column 0 merged and the inverse y-transform of S0; the geometry
+// of k_y3_iter.
+template <class PY, bool INV>
+__global__ __launch_bounds__(512) void k_rhs_y3(InstDev* const* __restrict__ grp,
+                                                const double* const* __restrict__ src, int bpi, c2* spec) {
+  extern __shared__ c2 smem[];
+  __shared__ InstDev rec;
+  const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
+  if (!src[gi]) return;
+  const InstDev* __restrict__ I = rhs_record(grp[gi], &rec, spec);
+  constexpr int N = PY::N, T = PY::T, RM = PY::RMAX;
+  const int rows = I->rows;
+  const Y3Pos pos = y3_pos(T, I->nh / TW, lb);
+  const int t = pos.t, kp = pos.kp, r0 = pos.z * N;
+  c2* lds = smem + pos.c * lds_len(N);
+  const bool col0 = kp == 0;
+  const uint32_t fs = (uint32_t)I->field_stride;
+  GLB c2* S = gp(I->S);
+  Twiddles<PY> tw;
+  load_twiddles<PY>(tw, I->tw_y, t);
+  constexpr int NF = INV ? 1 : 2;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    GLB c2* F = S + f * fs;
+    c2 v[RM];
+#pragma unroll
+    for (int m = 0; m < RM; ++m) v[m] = gload(F + sidx(rows, r0 + t + m * T, kp));
+    if (INV && pos.has_col0) col0_merge<PY>(v, smem, col0, t);
+    fft<PY, INV>(v, lds, tw, t);
+    if (!INV && pos.has_col0) col0_split<PY>(v, smem, col0, t);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) gstore(F + sidx(rows, r0 + t + m * T, kp), v[m]);
+  }
+}
+
+// 3D z-pass of R(v): forward z-transforms of N^ (S0) and v^ (S1), the
+// symbol of R per logical column (packed slots through the mirror kz -> -kz,
+// as in k_z3_iter), inverse z-transform into S0.
+template <class PZ>
+__global__ __launch_bounds__(512) void k_rhs_z3(InstDev* const* __restrict__ grp,
+                                                const double* const* __restrict__ src, int bpi, c2* spec) {
+  extern __shared__ c2 smem[];
+  __shared__ InstDev rec;
+  const int gi = blockIdx.x / bpi, lb = blockIdx.x - gi * bpi;
+  if (!src[gi]) return;
+  const InstDev* __restrict__ I = rhs_record(grp[gi], &rec, spec);
+  constexpr int N = PZ::N, T = PZ::T, RM = PZ::RMAX;
+  const int rows = I->rows, ny = I->ny;
+  const Z3Pos pos = z3_pos(T, I->nh / TW, ny, lb);
+  const int t = pos.t, kp = pos.kp, ky = pos.ky;
+  c2* lds = smem + pos.c * lds_len(N);
+  const bool pair = kp == 0 && (ky == 0 || 2 * ky == ny);
+  const uint32_t fs = (uint32_t)I->field_stride;
+  GLB c2* S = gp(I->S);
+  Twiddles<PZ> tw;
+  load_twiddles<PZ>(tw, I->tw_z, t);
+  const double mp = -I->mobility * I->inv_p, e1 = 1.0 - I->eps;
+  const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
+  auto at = [&](int tt, int m) { return sidx(rows, ky + (tt + m * T) * ny, kp); };
+  auto coef = [&](int f, double q) -> double { return f == 0 ? mp * q : mp * q * (e1 - 2.0 * q + q * q); };
+  c2 v[RM], acc[RM];
+#pragma unroll
+  for (int m = 0; m < RM; ++m) acc[m] = c2{0.0, 0.0};
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const int tl = opaque(t);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) v[m] = gload(S + f * fs + at(tl, m));
+    fft<PZ, false>(v, lds, tw, t);
+    const int tf = opaque(t);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      const double q = q3(I, kp, ky, tf + m * T);
+      const double c = pair ? 0.5 * (coef(f, q) + coef(f, q + kxn2)) : coef(f, q);
+      acc[m] = cadd(acc[m], cscale(v[m], c));
+    }
+    if (pos.has_pair)
+      col0_mirror<PZ>(v, lds, pair, t, [&](int m, c2 w) {
+        const double q = q3(I, 0, ky, opaque(t + m * T));
+        acc[m] = cadd(acc[m], cscale(w, 0.5 * (coef(f, q) - coef(f, q + kxn2))));
+      });
+  }
+  fft<PZ, true>(acc, lds, tw, t);
+  const int ts = opaque(t);
+#pragma unroll
+  for (int m = 0; m < RM; ++m) gstore(S + at(ts, m), acc[m]);
 }
 
 // Error estimate of one attempt: u^ = sum_k w[k] f[k] over up to six fields

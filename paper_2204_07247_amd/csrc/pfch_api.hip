@@ -1178,7 +1178,7 @@ void apply_y3(Group& G, const Y3K& k, int cy) {
   G.y3_block = dim3(G.y3.T * cy);
   G.y3_bpi = G.nz * (G.nx / 2) / cy;
   G.y3_lds = ((size_t)cy * G.y3.lds_elems + G.y3.tw_elems) * sizeof(c2);
-  const void* fs[] = {G.y3.fwd, G.y3.inv, G.y3.setup};
+  const void* fs[] = {G.y3.fwd, G.y3.inv, G.y3.setup, G.y3.rhs_fwd, G.y3.rhs_inv};
   for (const void* f : fs)
     if (G.y3_lds > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.y3_lds);
 }
@@ -1187,7 +1187,7 @@ void apply_z3(Group& G, const Z3K& k, int kyb) {
   G.z3_block = dim3(G.z3.T * TW * kyb);
   G.z3_bpi = (G.nx / 2 / TW) * (G.ny / kyb);
   G.z3_lds = ((size_t)TW * kyb * G.z3.lds_elems + G.z3.tw_elems) * sizeof(c2);
-  const void* fs[] = {G.z3.iter, G.z3.setup};
+  const void* fs[] = {G.z3.iter, G.z3.setup, G.z3.rhs};
   for (const void* f : fs)
     if (G.z3_lds > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.z3_lds);
 }
@@ -1659,11 +1659,11 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
         rc = PFCH_E_UNSUPPORTED;
         goto fail;
       }
-      const void* ys[] = {G.y3.fwd, G.y3.inv, G.y3.setup};
+      const void* ys[] = {G.y3.fwd, G.y3.inv, G.y3.setup, G.y3.rhs_fwd, G.y3.rhs_inv};
       for (const void* f : ys)
         if (G.y3_lds > 65536)
           (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.y3_lds);
-      const void* zs[] = {G.z3.iter, G.z3.setup};
+      const void* zs[] = {G.z3.iter, G.z3.setup, G.z3.rhs};
       for (const void* f : zs)
         if (G.z3_lds > 65536)
           (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.z3_lds);
@@ -2394,6 +2394,16 @@ int rhs_kernels(pfch_ctx* ctx, Group& G, InstDev** grp, unsigned nm, const doubl
     void* a[] = {&grp, &ps, &rbpi, &spec};
     if ((rc = launch(G.rs.rhs_fwd, rg, G.srow_block, G.srow_lds, a, ctx->stream))) return rc;
   }
+  if (G.ndim == 3) {  // PFC: y forward, z (symbol and inverse), y inverse, then the rows
+    int ybpi = G.y3_bpi, zbpi = G.z3_bpi;
+    void* y[] = {&grp, &ps, &ybpi, &spec};
+    void* z[] = {&grp, &ps, &zbpi, &spec};
+    if ((rc = launch(G.y3.rhs_fwd, dim3(nm * ybpi), G.y3_block, G.y3_lds, y, ctx->stream))) return rc;
+    if ((rc = launch(G.z3.rhs, dim3(nm * zbpi), G.z3_block, G.z3_lds, z, ctx->stream))) return rc;
+    if ((rc = launch(G.y3.rhs_inv, dim3(nm * ybpi), G.y3_block, G.y3_lds, y, ctx->stream))) return rc;
+    void* a[] = {&grp, &pd, &rbpi, &spec};
+    return launch(G.rs.rhs_inv, rg, G.srow_block, G.srow_lds, a, ctx->stream);
+  }
   if (G.model == PFCH_FCH) {
     void* a[] = {&grp, &ps, &cbpi, &spec};
     if ((rc = launch(G.cs.rhs_lap, cg, G.scol_block, G.scol_lds, a, ctx->stream))) return rc;
@@ -2557,7 +2567,6 @@ int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_resu
   for (int i = 0; i < n; ++i) {
     dt[i] = res[i].dt_try;
     if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return PFCH_E_INVAL;
-    if (ctx->inst[i].nz > 1) return PFCH_E_UNSUPPORTED;
   }
   int rc;
   if ((rc = drop_spec(ctx))) return rc;  // instance state or workspaces change
@@ -2683,7 +2692,6 @@ int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_resu
 int pfch_rhs(pfch_ctx* ctx, int32_t inst, const double* v, double* out) {
   if (!ctx || inst < 0 || inst >= (int)ctx->inst.size() || !v || !out || v == out) return PFCH_E_INVAL;
   Instance& I = ctx->inst[inst];
-  if (I.nz > 1) return PFCH_E_UNSUPPORTED;
   if (int rc_ = drop_spec(ctx)) return rc_;  // instance state or workspaces change
   std::vector<const double*> src{v};
   std::vector<double*> dst{out};

@@ -283,6 +283,8 @@ struct Y3K {
   const void* fwd = nullptr;
   const void* inv = nullptr;
   const void* setup = nullptr;
+  const void* rhs_fwd = nullptr;  // R(v) y-passes
+  const void* rhs_inv = nullptr;
   int T = 0;
   int lds_elems = 0;
   int tw_elems = 0;
@@ -291,6 +293,7 @@ struct Y3K {
 struct Z3K {
   const void* iter = nullptr;
   const void* setup = nullptr;
+  const void* rhs = nullptr;  // R(v) z-pass
   int T = 0;
   int lds_elems = 0;
   int tw_elems = 0;
@@ -302,6 +305,8 @@ Y3K make_y3() {
   k.fwd = (const void*)&k_y3_iter<P, false>;
   k.inv = (const void*)&k_y3_iter<P, true>;
   k.setup = (const void*)&k_y3_setup<P>;
+  k.rhs_fwd = (const void*)&k_rhs_y3<P, false>;
+  k.rhs_inv = (const void*)&k_rhs_y3<P, true>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
   k.tw_elems = tw_lds_count<P>();
@@ -313,6 +318,7 @@ Z3K make_z3() {
   Z3K k;
   k.iter = (const void*)&k_z3_iter<P>;
   k.setup = (const void*)&k_z3_setup<P>;
+  k.rhs = (const void*)&k_rhs_z3<P>;
   k.T = P::T;
   k.lds_elems = lds_len(P::N);
   k.tw_elems = tw_lds_count<P>();
