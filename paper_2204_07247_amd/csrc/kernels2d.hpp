@@ -363,6 +363,31 @@ __device__ __forceinline__ void col0_mirror(const c2 (&v)[P::RMAX], c2* lds0, bo
   __syncthreads();
 }
 
+// As col0_mirror, handing `use` the own value P^(ky) read back from LDS
+// together with conj(P^(-ky)), so that the caller's registers of v are free
+// across the exchange.
+template <class P, class F>
+__device__ __forceinline__ void col0_pair(const c2 (&v)[P::RMAX], c2* lds0, bool mine, int t, F use) {
+  constexpr int N = P::N, T = P::T;
+  if (mine) {
+    const int ts = opaque_i(t);
+#pragma unroll
+    for (int m = 0; m < P::RMAX; ++m) lds0[lds_idx(ts + m * T)] = v[m];
+  }
+  __syncthreads();
+  if (mine) {
+    const int tl = opaque_i(t);
+#pragma unroll
+    for (int m = 0; m < P::RMAX; ++m) {
+      const int ky = tl + m * T;
+      const c2 own = lds0[lds_idx(ky)];
+      const c2 w = lds0[lds_idx(ky == 0 ? 0 : N - ky)];
+      use(m, own, c2{w.x, -w.y});
+    }
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Column kernel of one PAGD iteration.
 //
@@ -442,6 +467,27 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PY::MIN_WAV
   };
   GLB c2* gsrc = gp(uni_p(first ? I->G : I->ghat));
   GLB c2* ghat = gp(uni_p(I->ghat));
+  // scale by -1/(P Lq), zero at k = 0 (without a branch: one inside the
+  // unrolled column-0 loops costs spills)
+  int bad = 0;
+  auto scale = [&](double q) -> double {
+    const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
+    const bool pos = q > 0.0;
+    bad |= pos & !(Lq > 0.0);
+    const double r = -inv_p * rcp_pos(Lq);
+    return pos ? r : 0.0;
+  };
+  // Column 0 packs kx = 0 with kx = Nx/2, whose symbols differ by many
+  // orders of magnitude at large Nx (eps^4 q^3 at q = (pi/h)^2).  Mixing the
+  // packed values with the bracket's symbols and scaling afterwards would
+  // recover the kx = 0 part as a difference of terms of the size of the
+  // kx = Nx/2 symbol, and the rounding of that difference would set a floor
+  // for ||d||_inf.  Column 0 therefore takes the product of symbol and
+  // scale per logical column (of moderate size on both), all of it inside
+  // the mirror exchange (its own values and their mirror together), and is
+  // not scaled again; `keep` is 0 on column 0 and 1 elsewhere.
+  auto sig = [&](int f, double q) { return coef(f, q) * scale(q); };
+  const double keep = special ? 0.0 : 1.0;
 
   c2 v[RM], nxt[RM], acc[RM];
 #pragma unroll
@@ -463,15 +509,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PY::MIN_WAV
       const int tl = opaque(t);
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const double q = q_at(tl + m * T);
-        const double c = special ? 0.5 * (coef(f, q) + coef(f, q + kxn2)) : coef(f, q);
-        acc[m] = cadd(acc[m], cscale(v[m], c));
+        acc[m] = cadd(acc[m], cscale(v[m], keep * coef(f, q_at(tl + m * T))));
       }
     }
     if (blk0)
-      col0_mirror<PY>(v, smem, special, t, [&](int m, c2 w) {
+      col0_pair<PY>(v, smem, special, t, [&](int m, c2 own, c2 w) {
         const double q = q_col0(opaque(t + m * T));
-        acc[m] = cadd(acc[m], cscale(w, 0.5 * (coef(f, q) - coef(f, q + kxn2))));
+        const double s0 = sig(f, q), sn = sig(f, q + kxn2);
+        acc[m] = cadd(acc[m], cadd(cscale(own, 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn))));
       });
 #pragma unroll
     for (int m = 0; m < RM; ++m) v[m] = nxt[m];
@@ -482,29 +527,24 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PY::MIN_WAV
 #pragma unroll
     for (int m = 0; m < RM; ++m) gstore(ghat + sidx(rows, tl + m * T, kp), v[m]);
   }
-  // g^ enters with the same coefficient 1/M on both logical columns.
-#pragma unroll
-  for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(v[m], inv_m));
-
-  // scale by -1/(P Lq), zero at k = 0
-  int bad = 0;
-  auto scale = [&](double q) -> double {
-    if (!(q > 0.0)) return 0.0;
-    const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
-    bad |= !(Lq > 0.0);
-    return -inv_p * rcp_pos(Lq);
-  };
+  // g^ enters with the coefficient 1/M on both logical columns (column 0:
+  // times each one's scale, as above)
   {
     const int tl = opaque(t);
 #pragma unroll
-    for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], scale(q_at(tl + m * T)));
+    for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(v[m], keep * inv_m));
   }
   if (blk0)
-    col0_mirror<PY>(acc, smem, special, t, [&](int m, c2 w) {
+    col0_pair<PY>(v, smem, special, t, [&](int m, c2 own, c2 w) {
       const double q = q_col0(opaque(t + m * T));
-      const double s0 = scale(q), sn = scale(q + kxn2);
-      v[m] = cadd(cscale(acc[m], 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn)));
+      const double s0 = inv_m * scale(q), sn = inv_m * scale(q + kxn2);
+      acc[m] = cadd(acc[m], cadd(cscale(own, 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn))));
     });
+  {
+    const int tl = opaque(t);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) v[m] = special ? acc[m] : cscale(acc[m], scale(q_at(tl + m * T)));
+  }
   if constexpr (MODEL == MODEL_FCH) {
     // keep d^ for the Laplacian field: acc <- d^ (packed for column 0)
 #pragma unroll
@@ -941,26 +981,44 @@ __global__ __launch_bounds__(512) void k_col_iter_fp(const InstDev* const* __res
   // averaged-Newton constants are formed here
   const bool first = j == 0 && I->fold_g;
   if (first) fold_betas(I, const_cast<InstDev*>(gpos.I), blk0, b0, b2);
-  const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
-  const double inv_p = I->inv_p;
-  const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
-  const double kx2 = (kp * I->kx_scale) * (kp * I->kx_scale);
+  // the record's scalars in scalar registers
+  bm2 = uni_d(bm2);
+  b0 = uni_d(b0);
+  b2 = uni_d(b2);
+  b4 = uni_d(b4);
+  const double thl = uni_d(I->theta_l), inv_m = uni_d(I->inv_mobility), aot = uni_d(I->a_over_theta);
+  const double inv_p = uni_d(I->inv_p);
+  const double kxs = uni_d(I->kx_scale), kys = uni_d(I->ky_scale);
+  const double hx = 0.5 * uni_i(I->nx) * kxs;
+  const double kxn2 = hx * hx;
+  const double kx2 = (kp * kxs) * (kp * kxs);
   auto q_of = [&](int ky) {
-    const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
+    const double a = (ky <= N / 2 ? ky : ky - N) * kys;
     return kx2 + a * a;
   };
   auto q_col0 = [&](int ky) {
-    const double a = (ky <= N / 2 ? ky : ky - N) * I->ky_scale;
+    const double a = (ky <= N / 2 ? ky : ky - N) * kys;
     return a * a;
   };
-  const double e2 = I->eps * I->eps, e4 = e2 * e2, e2h1 = e2 * I->eta1, e1 = 1.0 - I->eps;
-  auto coef = [&](double q) -> double {
-    if (role == NT - 1) {  // v_breve
+  const double eps = uni_d(I->eps);
+  const double e2 = eps * eps, e4 = e2 * e2, e2h1 = e2 * uni_d(I->eta1), e1 = 1.0 - eps;
+  auto coef_f = [&](int f, double q) -> double {
+    if (f == NT - 1) {  // v_breve
       const double lin = fch ? e4 * q * q - e2h1 * q : e1 - 2.0 * q + q * q;
       return inv_m * aot + q * lin;
     }
-    if (fch && role == 0) return e2 * q * q;
+    if (fch && f == 0) return e2 * q * q;
     return q;
+  };
+  auto coef = [&](double q) { return coef_f(role, q); };
+  // scale by -1/(P Lq), zero at k = 0
+  int bad = 0;
+  auto scale = [&](double q) -> double {
+    const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
+    const bool pos = q > 0.0;
+    bad |= pos & !(Lq > 0.0);
+    const double r = -inv_p * rcp_pos(Lq);
+    return pos ? r : 0.0;
   };
 
   c2 v[RM], acc[RM], gh[RM];
@@ -983,50 +1041,67 @@ __global__ __launch_bounds__(512) void k_col_iter_fp(const InstDev* const* __res
   {
     const int tf = opaque(t);
 #pragma unroll
-    for (int m = 0; m < RM; ++m) {
-      const double q = q_of(tf + m * T);
-      const double c = special ? 0.5 * (coef(q) + coef(q + kxn2)) : coef(q);
-      acc[m] = cscale(v[m], c);
-    }
+    for (int m = 0; m < RM; ++m) acc[m] = cscale(v[m], coef(q_of(tf + m * T)));
   }
-  if (blk0)
-    col0_mirror<PY>(v, lds, special, t, [&](int m, c2 w) {
-      const double q = q_col0(opaque(t + m * T));
-      acc[m] = cadd(acc[m], cscale(w, 0.5 * (coef(q) - coef(q + kxn2))));
-    });
   if (role == NT - 1) {
-    // g^ enters with the same coefficient 1/M on both logical columns
+    // g^ enters with the coefficient 1/M
 #pragma unroll
     for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(gh[m], inv_m));
   }
-#pragma unroll
-  for (int m = 0; m < RM; ++m) ex[role * N + t + m * T] = acc[m];
-  __syncthreads();
+  // Column 0 (kx = 0 and kx = nx/2 packed) keeps its transforms as they are
+  // and g^ besides, in the last team's transform buffer once every
+  // transform is done; the symbols of the two logical columns differ by
+  // orders of magnitude, so each is multiplied by its scale before the two
+  // are combined, and the result is not scaled again.
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
-    const int k = t + m * T;
-    acc[m] = fch ? cadd(cadd(ex[k], ex[N + k]), ex[2 * N + k]) : cadd(ex[k], ex[N + k]);
+    c2 x = acc[m];
+    if (special) x = v[m];
+    ex[role * N + t + m * T] = x;
   }
+  if (blk0) {
+    __syncthreads();
+    if (special && role == NT - 1) {
+      const int ts = opaque(t);
+#pragma unroll
+      for (int m = 0; m < RM; ++m) lds[lds_idx(ts + m * T)] = gh[m];
+    }
+  }
+  __syncthreads();
+  if (!special) {
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      const int k = t + m * T;
+      acc[m] = fch ? cadd(cadd(ex[k], ex[N + k]), ex[2 * N + k]) : cadd(ex[k], ex[N + k]);
+    }
+  } else {
+    const c2* gl = smem + (NT - 1) * lds_len(N);
+    const int tc = opaque(t);
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      const int k = tc + m * T, km = k == 0 ? 0 : N - k;
+      const double q = q_col0(k);
+      const double s0 = scale(q), sn = scale(q + kxn2);
+      // c0 F0^ + i cN FN^ = (c0 + cN)/2 P^(ky) + (c0 - cN)/2 conj(P^(-ky))
+      auto term = [&](c2 own, c2 mir, double c0, double cn) {
+        return cadd(cscale(own, 0.5 * (c0 + cn)), cscale(c2{mir.x, -mir.y}, 0.5 * (c0 - cn)));
+      };
+      c2 a = term(gl[lds_idx(k)], gl[lds_idx(km)], inv_m * s0, inv_m * sn);
+#pragma unroll
+      for (int f = 0; f < NT; ++f)
+        a = cadd(a, term(ex[f * N + k], ex[f * N + km], coef_f(f, q) * s0, coef_f(f, q + kxn2) * sn));
+      acc[m] = a;
+    }
+  }
+  // every team has read g^ from the last team's buffer before any team
+  // writes its own buffer again
+  if (blk0) __syncthreads();
 
-  // scale by -1/(P Lq), zero at k = 0
-  int bad = 0;
-  auto scale = [&](double q) -> double {
-    if (!(q > 0.0)) return 0.0;
-    const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
-    bad |= !(Lq > 0.0);
-    return -inv_p * rcp_pos(Lq);
-  };
   {
     const int tf = opaque(t);
 #pragma unroll
-    for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], scale(q_of(tf + m * T)));
+    for (int m = 0; m < RM; ++m) v[m] = special ? acc[m] : cscale(acc[m], scale(q_of(tf + m * T)));
   }
-  if (blk0)
-    col0_mirror<PY>(acc, lds, special, t, [&](int m, c2 w) {
-      const double q = q_col0(opaque(t + m * T));
-      const double s0 = scale(q), sn = scale(q + kxn2);
-      v[m] = cadd(cscale(acc[m], 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn)));
-    });
   if constexpr (fch) {
     // team 0 keeps d^, the others take -q d^ (team 2's copy is unused)
     if (role > 0) {

@@ -223,9 +223,22 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
   load_twiddles<PZ>(tw, I->tw_z, t);
   double bm2, b0, b2, b4;
   betas(I, bm2, b0, b2, b4);
-  const double thl = I->theta_l, inv_m = I->inv_mobility, aot = I->a_over_theta;
-  const double inv_p = I->inv_p, e1 = 1.0 - I->eps;
-  const double kxn2 = (0.5 * I->nx * I->kx_scale) * (0.5 * I->nx * I->kx_scale);
+  // the record's scalars in scalar registers
+  bm2 = uni_d(bm2);
+  b0 = uni_d(b0);
+  b2 = uni_d(b2);
+  b4 = uni_d(b4);
+  const double thl = uni_d(I->theta_l), inv_m = uni_d(I->inv_mobility), aot = uni_d(I->a_over_theta);
+  const double inv_p = uni_d(I->inv_p), e1 = 1.0 - uni_d(I->eps);
+  const double hx = 0.5 * uni_i(I->nx) * uni_d(I->kx_scale);
+  const double kxn2 = hx * hx;
+  // |k|^2 at kx = 0 of a pair slot (ky = 0 or ny/2) at kz
+  const double kyp = ky * uni_d(I->ky_scale), kzs = uni_d(I->kz_scale);
+  const int nzu = uni_i(I->nz);
+  auto q_pair = [&](int kz) {
+    const double c = (kz <= nzu / 2 ? kz : kz - nzu) * kzs;
+    return kyp * kyp + c * c;
+  };
   // Element m of this thread: z index tt + m T for a thread index tt.  Each
   // phase takes its own opaque copy of t so that addresses and wavenumbers
   // are recomputed there instead of being held live across the transforms.
@@ -233,6 +246,20 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
   auto coef = [&](int f, double q) -> double {
     return f == 1 ? inv_m * aot + q * (e1 - 2.0 * q + q * q) : q;
   };
+  // scale by -1/(P Lq), zero at k = 0
+  int bad = 0;
+  auto scale = [&](double q) -> double {
+    const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
+    const bool pos = q > 0.0;
+    bad |= pos & !(Lq > 0.0);
+    const double r = -inv_p * rcp_pos(Lq);
+    return pos ? r : 0.0;
+  };
+  // The pair slots take symbol times scale per logical column (kx = 0 and
+  // kx = nx/2, whose symbols differ by orders of magnitude) inside the
+  // mirror exchanges and are not scaled again; `keep` is 0 there.
+  auto sig = [&](int f, double q) { return coef(f, q) * scale(q); };
+  const double keep = pair ? 0.0 : 1.0;
 
   // With up to 8 elements per thread the next field is loaded before the
   // transform of the current one; with more, after it (registers).
@@ -252,15 +279,12 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
     fft<PZ, false>(v, lds, tw, t);
     const int tf = opaque(t);
 #pragma unroll
-    for (int m = 0; m < RM; ++m) {
-      const double q = q3(I, kp, ky, tf + m * T);
-      const double c = pair ? 0.5 * (coef(f, q) + coef(f, q + kxn2)) : coef(f, q);
-      acc[m] = cadd(acc[m], cscale(v[m], c));
-    }
+    for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(v[m], keep * coef(f, q3(I, kp, ky, tf + m * T))));
     if (pos.has_pair)
-      col0_mirror<PZ>(v, lds, pair, t, [&](int m, c2 w) {
-        const double q = q3(I, 0, ky, opaque(t + m * T));
-        acc[m] = cadd(acc[m], cscale(w, 0.5 * (coef(f, q) - coef(f, q + kxn2))));
+      col0_pair<PZ>(v, lds, pair, t, [&](int m, c2 own, c2 w) {
+        const double q = q_pair(opaque(t + m * T));
+        const double s0 = sig(f, q), sn = sig(f, q + kxn2);
+        acc[m] = cadd(acc[m], cadd(cscale(own, 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn))));
       });
 #pragma unroll
     for (int m = 0; m < RM; ++m) {
@@ -271,24 +295,16 @@ __global__ __launch_bounds__(512) void k_z3_iter(const InstDev* const* __restric
     }
   }
 #pragma unroll
-  for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(v[m], inv_m));
-
-  int bad = 0;
-  auto scale = [&](double q) -> double {
-    if (!(q > 0.0)) return 0.0;
-    const double Lq = bm2 + thl * q * (b0 + b2 * q + b4 * q * q);
-    bad |= !(Lq > 0.0);
-    return -inv_p * rcp_pos(Lq);
-  };
+  for (int m = 0; m < RM; ++m) acc[m] = cadd(acc[m], cscale(v[m], keep * inv_m));
+  if (pos.has_pair)
+    col0_pair<PZ>(v, lds, pair, t, [&](int m, c2 own, c2 w) {
+      const double q = q_pair(opaque(t + m * T));
+      const double s0 = inv_m * scale(q), sn = inv_m * scale(q + kxn2);
+      acc[m] = cadd(acc[m], cadd(cscale(own, 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn))));
+    });
   const int te = opaque(t);
 #pragma unroll
-  for (int m = 0; m < RM; ++m) v[m] = cscale(acc[m], scale(q3(I, kp, ky, te + m * T)));
-  if (pos.has_pair)
-    col0_mirror<PZ>(acc, lds, pair, t, [&](int m, c2 w) {
-      const double q = q3(I, 0, ky, opaque(t + m * T));
-      const double s0 = scale(q), sn = scale(q + kxn2);
-      v[m] = cadd(cscale(acc[m], 0.5 * (s0 + sn)), cscale(w, 0.5 * (s0 - sn)));
-    });
+  for (int m = 0; m < RM; ++m) v[m] = pair ? acc[m] : cscale(acc[m], scale(q3(I, kp, ky, te + m * T)));
   fft<PZ, true>(v, lds, tw, t);
   const int ts = opaque(t);
 #pragma unroll
