@@ -5,8 +5,8 @@ at 2048 x 2048 on [0, 4 pi)^2 (e ~ U[0.08, 0.12], eps = e, eta1 = 1.45 e,
 eta2 = 2 e, tau = 0, mean ~ U[-0.7, -0.5], noise amplitude 0.01; seeds
 2000-2015) and one PFC 3D instance at 192^3 on [0, 192)^3 (eps = 0.25, mean
 -0.2, noise 0.05, seed 0); BDF2 with a backward Euler first step, dt = 1e-3
-(FCH) and 0.1 (PFC); PAGD to ||d||_inf < 1e-10.  One bench step is one time
-step of every instance.  All inputs are seeded synthetic fields (workloads/),
+(FCH) and 0.1 (PFC); PAGD to ||d||_inf < 1e-10; 300 steps.  One bench step is
+one time step of every instance.  All inputs are seeded synthetic fields (workloads/),
 resident on the GPU before the timed region.
 
 The same steps run four ways:
@@ -19,8 +19,9 @@ The same steps run four ways:
                    with the same periods); the 3D instance keeps the
                    extrapolated guess;
   batched_learned  both: the headline `value`.
-Each times `--steps` bench steps after `--warmup` untimed ones, bracketed by
-torch.cuda.synchronize().  Also reported: PAGD iterations per step, the HBM
+Each times `--steps` bench steps (default: the configuration's 300) from the
+initial conditions, bracketed by torch.cuda.synchronize(), after `--warmup`
+untimed steps whose states are discarded.  Also reported: PAGD iterations per step, the HBM
 roofline of the FCH 2048^2 iteration (HIP events on the grouped launches),
 and the CPU oracle on the host's cores.
 
@@ -45,6 +46,7 @@ import workloads as W  # noqa: E402
 METRIC = "time-steps/sec & PAGD iters/step at 1e-10 residual: plain vs batched+learned"
 HBM_PEAK_GBS = 8000.0
 COMBINED = "fch2d_8x1024_8x2048_bdf2+pfc3d_192_bdf2"
+COMBINED_STEPS = 300
 
 WORKLOADS = {
     "fch256": W.FCH256_BDF2,
@@ -237,8 +239,10 @@ def _norm_for(tr, un, unm1):
 
 
 def run_set(ws, mode, steps, warmup, tr=None, time_groups=None):
-    """`steps` bench steps of the instances ws after `warmup` untimed ones.
-    mode: plain | batched | learned | batched_learned."""
+    """`steps` bench steps of the instances ws from their initial conditions
+    (the configuration's steps 1 .. steps), after `warmup` untimed ones
+    that are then discarded.  mode: plain | batched | learned |
+    batched_learned."""
     import torch
     from paper_2204_07247_amd import learned, pfch
     batched = mode.startswith("batched")
@@ -277,6 +281,12 @@ def run_set(ws, mode, steps, warmup, tr=None, time_groups=None):
                     c.get_state(k, un, unm1)
                     c.set_fno(k, tr.fno, _norm_for(tr, un, unm1))
         one_step(warm)  # the first learned step, untimed
+    # back to the initial conditions: the timed steps are the configuration's
+    # first `steps` steps (a step without history is backward Euler with the
+    # extrapolated guess; the network is used from the second step on)
+    for c, idx in ctxs:
+        for k, i in enumerate(idx):
+            c.set_state(k, u[i])
     its = {i: [] for i in range(len(ws))}
     its["fallbacks"] = 0
     log(f"[bench] {mode}: {len(ws)} instances, {len(ctxs)} context(s), {steps} timed steps")
@@ -820,25 +830,15 @@ def extras(args):
         lr["pfc3d"], tr3, _ = learned3d_comparison(args.learned3d_epochs, traj_steps=40, eval_steps=40)
         tr3.fno.close()
     out["learned"] = lr
-    # the combined set over its full 300 steps, batched, without and with the
-    # learned guess (the headline runs the driver's step count)
-    log("[bench] combined set, 300 steps: batched and batched + learned")
-    import torch
-    ws = combined_set()
-    tr, _ = train_fch_network(args.learned_epochs)
-    long = {}
-    for mode in ("batched", "batched_learned"):
-        long[mode], _ = run_set(ws, mode, 300, args.warmup, tr)
-        torch.cuda.empty_cache()
-    tr.fno.close()
-    out["combined_300"] = long
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps from the initial conditions (default: the workload's "
+                         "configured length, 300 for the combined set)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="combined", choices=["combined"] + sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
@@ -861,6 +861,8 @@ def main():
                     help="before the run, copy a MIB-sized float64 buffer three times "
                          "(a plain copy kernel of known traffic for counter calibration)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = COMBINED_STEPS if args.workload == "combined" else WORKLOADS[args.workload].steps
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the library runs on one "
               "device; independent instances would shard across GPUs with no communication, "
