@@ -144,10 +144,11 @@ using P512 = Plan<512, 8, 8, 8>;
 using P1024 = Plan<1024, 8, 8, 4, 4>;
 using P2048 = Plan<2048, 8, 8, 8, 4>;
 using P192 = Plan<192, 3, 4, 4, 4>;  // 12 elements per thread
-// FCH 2048 (three transformed fields, eight elements per thread): 168
+// FCH 2048 (three transformed fields, eight elements per thread): 158
 // registers, three waves per SIMD, with the twiddles in LDS.  (The 2048 row
-// kernel is left as it is: with its twiddles in LDS it ran 4% slower, and
-// held to three waves per SIMD it spills.)
+// kernel is left as it is, 201 registers and two waves: with its twiddles
+// in LDS it ran 4% slower, and held to three waves per SIMD with them it
+// spills 7 registers and ran 1.4% slower.)
 template <>
 struct ColPlan<P2048> {
   using type = LdsTw<P2048, 3>;
