@@ -34,11 +34,24 @@ constexpr int TW = 4;
 
 __device__ __forceinline__ uint64_t dbits(double v) { return (uint64_t)__double_as_longlong(v); }
 
-// Element offset of (row, kp) in a spectral field.  32-bit: a field holds
+// Element offset of (row, kp) in a spectral field: tiles of TW = 4 physical
+// columns, each tile's rows in order, and in a 128-byte line the row pair
+// (2i, 2i + 1) of the tile's four columns, column-major (the two rows of one
+// column adjacent).  A column pass then reads and writes 32 contiguous bytes
+// per line and column, a row-pair pass whole lines.  32-bit: a field holds
 // at most rows * H <= 2^31 / 16 elements, which keeps the base pointer in
 // scalar registers and one offset register per access.
 __device__ __forceinline__ uint32_t sidx(int rows, int row, int kp) {
-  return ((uint32_t)(kp >> 2) * (uint32_t)rows + (uint32_t)row) * TW + (uint32_t)(kp & 3);
+  return ((uint32_t)(kp >> 2) * (uint32_t)rows + (uint32_t)(row & ~1)) * TW + (uint32_t)(kp & 3) * 2 +
+         (uint32_t)(row & 1);
+}
+
+// The value of lane ^ 1 (both lanes active).
+__device__ __forceinline__ double lane_pair_swap(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0xB1, 0xF, 0xF, false);  // quad_perm(1,0,3,2)
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // An opaque copy of v: keeps the compiler from hoisting work that depends
@@ -154,29 +167,38 @@ __device__ __forceinline__ uint64_t block_max_bits(uint64_t v, uint64_t* red) {
 // ---------------------------------------------------------------------------
 // Row-side packing.
 // ---------------------------------------------------------------------------
-// Half-spectrum entry A[k], 0 <= k <= N/2, of `row` of field F.
-template <int N>
-__device__ __forceinline__ c2 spec_get(const GLB c2* __restrict__ F, int rows, int row, int k) {
-  if (k == 0 || k == N / 2) {
-    const c2 p = gload(F + sidx(rows, row, 0));
-    return c2{k == 0 ? p.x : p.y, 0.0};
-  }
-  return gload(F + sidx(rows, row, k));
-}
-
-// Z[k] = A[k] + i B[k] over the full length from two Hermitian half spectra
-// (row ra of FA and row rb of FB).
+// Z[k] = A[k] + i B[k] over the full length from the Hermitian half spectra
+// of rows r0 (A) and r0 + 1 (B) of F, r0 even.  With an even team size the
+// lanes of a pair (k, k + 1, k even) load the columns of both their elements
+// as two 32-byte pieces (each lane one row of each) and exchange the halves
+// they hold for each other.
 template <class P>
-__device__ __forceinline__ void load_pack(c2 (&v)[P::RMAX], const GLB c2* __restrict__ FA, int ra,
-                                          const GLB c2* __restrict__ FB, int rb, int rows, int t) {
+__device__ __forceinline__ void load_pack(c2 (&v)[P::RMAX], const GLB c2* __restrict__ F, int r0, int rows,
+                                          int t) {
   constexpr int N = P::N, T = P::T;
+  auto col = [](int k) { return k == N / 2 ? 0 : (k > N / 2 ? N - k : k); };
 #pragma unroll
   for (int m = 0; m < P::RMAX; ++m) {
     const int k = t + m * T;
-    const bool hi = k > N / 2;
-    const int kk = hi ? N - k : k;
-    c2 a = spec_get<N>(FA, rows, ra, kk), b = spec_get<N>(FB, rows, rb, kk);
-    if (hi) {
+    c2 a, b;
+    if constexpr (T % 2 == 0) {
+      const bool odd = k & 1;
+      const int ke = k & ~1;
+      const int row = r0 + (odd ? 1 : 0);
+      const c2 v1 = gload(F + sidx(rows, row, col(ke)));
+      const c2 v2 = gload(F + sidx(rows, row, col(ke + 1)));
+      const c2 send = odd ? v1 : v2;
+      const c2 recv = c2{lane_pair_swap(send.x), lane_pair_swap(send.y)};
+      a = odd ? recv : v1;
+      b = odd ? v2 : recv;
+    } else {
+      a = gload(F + sidx(rows, r0, col(k)));
+      b = gload(F + sidx(rows, r0 + 1, col(k)));
+    }
+    if (k == 0 || k == N / 2) {  // column 0 holds (A[0], A[N/2]) and (B[0], B[N/2])
+      a = c2{k == 0 ? a.x : a.y, 0.0};
+      b = c2{k == 0 ? b.x : b.y, 0.0};
+    } else if (k > N / 2) {
       a.y = -a.y;
       b.y = -b.y;
     }
@@ -184,31 +206,52 @@ __device__ __forceinline__ void load_pack(c2 (&v)[P::RMAX], const GLB c2* __rest
   }
 }
 
-// After the forward transform of Z = a + i b (a, b real rows): store the half
-// spectra A[k] = (Z[k] + conj Z[N-k]) / 2 and B[k] = -i (Z[k] - conj Z[N-k]) / 2
-// into row ra of FA and row rb of FB (k = 0 and N/2 packed in column 0).
+// After the forward transform of Z = a + i b (a, b the real rows r0, r0 + 1,
+// r0 even): store the half spectra A[k] = (Z[k] + conj Z[N-k]) / 2 into row
+// r0 and B[k] = -i (Z[k] - conj Z[N-k]) / 2 into row r0 + 1 of F (k = 0 and
+// N/2 packed in column 0).  With an even team size, lane s of round m takes
+// the s-th 16-byte slot of the row pair's lines (k = s / 2, row r0 + s % 2),
+// so that each store instruction writes whole lines; the lanes of a pair read
+// Z[k] and Z[N-k] from LDS and exchange them.
 template <class P>
-__device__ __forceinline__ void unpack_store(const c2 (&v)[P::RMAX], c2* lds, GLB c2* __restrict__ FA,
-                                             int ra, GLB c2* __restrict__ FB, int rb, int rows, int t) {
+__device__ __forceinline__ void unpack_store(const c2 (&v)[P::RMAX], c2* lds, GLB c2* __restrict__ F, int r0,
+                                             int rows, int t) {
   constexpr int N = P::N, T = P::T;
 #pragma unroll
   for (int m = 0; m < P::RMAX; ++m) lds[lds_idx(t + m * T)] = v[m];
   __syncthreads();
+  if constexpr (T % 2 == 0) {
 #pragma unroll
-  for (int m = 0; m < P::RMAX / 2; ++m) {
-    const int k = t + m * T;
-    const c2 z = lds[lds_idx(k)];
-    const c2 w = lds[lds_idx(k == 0 ? N / 2 : N - k)];
-    c2 A, B;
-    if (k == 0) {
-      A = c2{z.x, w.x};  // (Re Z[0], Re Z[N/2])
-      B = c2{z.y, w.y};  // (Im Z[0], Im Z[N/2])
-    } else {
-      A = c2{0.5 * (z.x + w.x), 0.5 * (z.y - w.y)};
-      B = c2{0.5 * (z.y + w.y), -0.5 * (z.x - w.x)};
+    for (int m = 0; m < P::RMAX; ++m) {
+      const int sl = t + m * T, k = sl >> 1;
+      const bool odd = sl & 1;
+      const c2 mine = lds[lds_idx(odd ? (k == 0 ? N / 2 : N - k) : k)];
+      const c2 other = c2{lane_pair_swap(mine.x), lane_pair_swap(mine.y)};
+      const c2 z = odd ? other : mine, w = odd ? mine : other;
+      c2 out;
+      if (k == 0)
+        out = odd ? c2{z.y, w.y} : c2{z.x, w.x};  // (Im / Re Z[0], Im / Re Z[N/2])
+      else
+        out = odd ? c2{0.5 * (z.y + w.y), -0.5 * (z.x - w.x)} : c2{0.5 * (z.x + w.x), 0.5 * (z.y - w.y)};
+      gstore(F + sidx(rows, r0 + (odd ? 1 : 0), k), out);
     }
-    gstore(FA + sidx(rows, ra, k), A);
-    gstore(FB + sidx(rows, rb, k), B);
+  } else {
+#pragma unroll
+    for (int m = 0; m < P::RMAX / 2; ++m) {
+      const int k = t + m * T;
+      const c2 z = lds[lds_idx(k)];
+      const c2 w = lds[lds_idx(k == 0 ? N / 2 : N - k)];
+      c2 A, B;
+      if (k == 0) {
+        A = c2{z.x, w.x};
+        B = c2{z.y, w.y};
+      } else {
+        A = c2{0.5 * (z.x + w.x), 0.5 * (z.y - w.y)};
+        B = c2{0.5 * (z.y + w.y), -0.5 * (z.x - w.x)};
+      }
+      gstore(F + sidx(rows, r0, k), A);
+      gstore(F + sidx(rows, r0 + 1, k), B);
+    }
   }
   __syncthreads();
 }
@@ -581,14 +624,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PY::MIN_WAV
 // ---------------------------------------------------------------------------
 template <class PX>
 __device__ __forceinline__ void pair_forward(const double (&a)[PX::RMAX], const double (&b)[PX::RMAX],
-                                             const Twiddles<PX>& tw, c2* lds, GLB c2* FA, int ra,
-                                             GLB c2* FB, int rb, int rows, int t) {
+                                             const Twiddles<PX>& tw, c2* lds, GLB c2* F, int r0, int rows,
+                                             int t) {
   constexpr int RM = PX::RMAX;
   c2 z[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) z[m] = c2{a[m], b[m]};
   fft<PX, false>(z, lds, tw, t);
-  unpack_store<PX>(z, lds, FA, ra, FB, rb, rows, t);
+  unpack_store<PX>(z, lds, F, r0, rows, t);
 }
 
 // The forward transforms that start a PFC iteration, for the two real rows
@@ -606,8 +649,8 @@ __device__ __forceinline__ void pfc_forward_pair(const InstDev* I, const double 
 #pragma unroll
   for (int m = 0; m < RM; ++m) z[m] = c2{vb[0][m] * vb[0][m] * vb[0][m], vb[1][m] * vb[1][m] * vb[1][m]};
   fft<PX, false>(z, lds, tw, t);
-  unpack_store<PX>(z, lds, S, r0, S, r0 + 1, rows, t);
-  pair_forward<PX>(vb[0], vb[1], tw, lds, S + fs, r0, S + fs, r0 + 1, rows, t);
+  unpack_store<PX>(z, lds, S, r0, rows, t);
+  pair_forward<PX>(vb[0], vb[1], tw, lds, S + fs, r0, rows, t);
 }
 
 // FCH pointwise terms at v_breve with Laplacian lv:
@@ -641,15 +684,15 @@ __device__ __forceinline__ void fch_forward_pair(const InstDev* I, const double 
     z[m] = c2{pr[0], pr[1]};
   }
   fft<PX, false>(z, lds, tw, t);
-  unpack_store<PX>(z, lds, S + fs, r0, S + fs, r0 + 1, rows, t);
+  unpack_store<PX>(z, lds, S + fs, r0, rows, t);
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
     const double u0 = vb[0][m], u1 = vb[1][m];
     z[m] = c2{(u0 * u0 - 1.0) * (u0 + tau), (u1 * u1 - 1.0) * (u1 + tau)};
   }
   fft<PX, false>(z, lds, tw, t);
-  unpack_store<PX>(z, lds, S, r0, S, r0 + 1, rows, t);
-  pair_forward<PX>(vb[0], vb[1], tw, lds, S + 2 * fs, r0, S + 2 * fs, r0 + 1, rows, t);
+  unpack_store<PX>(z, lds, S, r0, rows, t);
+  pair_forward<PX>(vb[0], vb[1], tw, lds, S + 2 * fs, r0, rows, t);
 }
 
 // MPS: implicit midpoint (the nonlinear terms are taken at
@@ -707,7 +750,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(row_min_wav
       }
     }
     c2 v[RM];
-    load_pack<PX>(v, Sg, r0, Sg, r0 + 1, rows, t);
+    load_pack<PX>(v, Sg, r0, rows, t);
     fft<PX, true>(v, lds, tw, t);
     double vb[2][RM];
     const int tl = opaque(t);
@@ -768,9 +811,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(row_min_wav
       }
     };
     c2 v[RM], w[RM];
-    load_pack<PX>(v, Sg, r0, Sg, r0 + 1, rows, t);
+    load_pack<PX>(v, Sg, r0, rows, t);
     if constexpr (EARLY) {
-      load_pack<PX>(w, Sg + fs, r0, Sg + fs, r0 + 1, rows, t);
+      load_pack<PX>(w, Sg + fs, r0, rows, t);
       load_x();
       load_l();
     }
@@ -792,7 +835,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(row_min_wav
         vbs[row][m] = mp ? th * yn + (1.0 - th) * uu[row][m] : yn;
       }
     }
-    if constexpr (!EARLY) load_pack<PX>(w, Sg + fs, r0, Sg + fs, r0 + 1, rows, opaque(t));
+    if constexpr (!EARLY) load_pack<PX>(w, Sg + fs, r0, rows, opaque(t));
     fft<PX, true>(w, lds, tw, t);
     if constexpr (!EARLY) load_l();
     const int tw2 = opaque(t);
@@ -867,7 +910,7 @@ __global__ __launch_bounds__(256) void k_row_iter_fp(const InstDev* const* __res
   const GLB double* xb = gp(role == 0 ? I->X[(j + 2) % 3] : I->DX[(j + 2) % 3]);
   const GLB double* xu = gp(role == 0 ? I->un : I->dun);
   if (role < NINV) {
-    load_pack<PX>(v, S + role * fs, r0, S + role * fs, r0 + 1, rows, t);
+    load_pack<PX>(v, S + role * fs, r0, rows, t);
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
 #pragma unroll
@@ -933,7 +976,7 @@ __global__ __launch_bounds__(256) void k_row_iter_fp(const InstDev* const* __res
     z[m] = c2{f[0], f[1]};
   }
   fft<PX, false>(z, lds, tw, t);
-  unpack_store<PX>(z, lds, S + role * fs, r0, S + role * fs, r0 + 1, rows, t);
+  unpack_store<PX>(z, lds, S + role * fs, r0, rows, t);
   const uint64_t bm = block_max_bits(dmax, red);
   if (threadIdx.x == 0) atomicMax((unsigned long long*)&I->norms[j], (unsigned long long)bm);
 }
@@ -1228,7 +1271,7 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* const* __restrict__ 
     }
   }
   if constexpr (MODEL == MODEL_PFC) {
-    pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, gp(I->G), r0 + 1, rows, t);
+    pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, rows, t);
     double vb[2][RM];
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
@@ -1237,9 +1280,9 @@ __global__ __launch_bounds__(256) void k_row_setup(InstDev* const* __restrict__ 
     }
     pfc_forward_pair<PX>(I, vb, tw, lds, r0, t);
   } else {
-    pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, gp(I->G), r0 + 1, rows, t);
-    pair_forward<PX>(x0v[0], x0v[1], tw, lds, gp(I->G) + fs, r0, gp(I->G) + fs, r0 + 1, rows, t);
-    if (th != 1.0) pair_forward<PX>(uv[0], uv[1], tw, lds, gp(I->G) + 2 * fs, r0, gp(I->G) + 2 * fs, r0 + 1, rows, t);
+    pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, rows, t);
+    pair_forward<PX>(x0v[0], x0v[1], tw, lds, gp(I->G) + fs, r0, rows, t);
+    if (th != 1.0) pair_forward<PX>(uv[0], uv[1], tw, lds, gp(I->G) + 2 * fs, r0, rows, t);
   }
   const double bs0 = block_sum(s0, red);
   const double bs1 = block_sum(s1, red);
@@ -1312,7 +1355,7 @@ __global__ __launch_bounds__(256) void k_row_setup_lap(InstDev* const* __restric
         gv[row][m] = sa.gu * un[idx] + sa.gm * unm1[idx];
       }
     }
-    pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, gp(I->G), r0 + 1, rows, t);
+    pair_forward<PX>(gv[0], gv[1], tw, lds, gp(I->G), r0, rows, t);
   }
   double vb[2][RM];
   {
@@ -1486,7 +1529,7 @@ __global__ __launch_bounds__(256) void k_row_setup_lap_fp(InstDev* const* __rest
   }
   fft<PX, false>(z, lds, tw, t);
   GLB c2* dst = role == 3 ? gp(I->G) : gp(I->S) + role * fs;
-  unpack_store<PX>(z, lds, dst, r0, dst, r0 + 1, rows, t);
+  unpack_store<PX>(z, lds, dst, r0, rows, t);
   const double bs0 = block_sum(s0, red);
   const double bs1 = block_sum(s1, red);
   if (threadIdx.x == 0) {
@@ -1565,7 +1608,7 @@ __global__ __launch_bounds__(256) void k_row_start_fch(const InstDev* const* __r
   load_twiddles<PX>(tw, I->tw_x, t);
   double lx[2][RM], lu[2][RM];
   c2 v[RM];
-  load_pack<PX>(v, gp(I->G) + fs, r0, gp(I->G) + fs, r0 + 1, rows, t);
+  load_pack<PX>(v, gp(I->G) + fs, r0, rows, t);
   fft<PX, true>(v, lds, tw, t);
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
@@ -1575,7 +1618,7 @@ __global__ __launch_bounds__(256) void k_row_start_fch(const InstDev* const* __r
     lu[1][m] = 0.0;
   }
   if (mp) {
-    load_pack<PX>(v, gp(I->G) + 2 * fs, r0, gp(I->G) + 2 * fs, r0 + 1, rows, t);
+    load_pack<PX>(v, gp(I->G) + 2 * fs, r0, rows, t);
     fft<PX, true>(v, lds, tw, t);
 #pragma unroll
     for (int m = 0; m < RM; ++m) {

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_rhs_row_fwd(InstDev* const* __restrict_
     pfc_forward_pair<PX>(I, vb, tw, lds, r0, t);
   } else {
     GLB c2* S2 = gp(I->S) + 2 * I->field_stride;
-    pair_forward<PX>(vb[0], vb[1], tw, lds, S2, r0, S2, r0 + 1, I->rows, t);
+    pair_forward<PX>(vb[0], vb[1], tw, lds, S2, r0, I->rows, t);
   }
 }
 
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_rhs_row_mid(InstDev* const* __restrict_
   Twiddles<PX> tw;
   load_twiddles<PX>(tw, I->tw_x, t);
   c2 z[RM];
-  load_pack<PX>(z, gp(I->S), r0, gp(I->S), r0 + 1, I->rows, t);
+  load_pack<PX>(z, gp(I->S), r0, I->rows, t);
   fft<PX, true>(z, lds, tw, t);
   double vb[2][RM], lv[2][RM];
 #pragma unroll
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_rhs_row_inv(InstDev* const* __restrict_
   Twiddles<PX> tw;
   load_twiddles<PX>(tw, I->tw_x, t);
   c2 z[RM];
-  load_pack<PX>(z, gp(I->S), r0, gp(I->S), r0 + 1, I->rows, t);
+  load_pack<PX>(z, gp(I->S), r0, I->rows, t);
   fft<PX, true>(z, lds, tw, t);
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
