@@ -617,14 +617,17 @@ def adaptive_run(w, tol, dt_min, dt_max, attempts):
 
 def ensemble_bandwidth(ws, steps, warmup, label):
     """All instances in one context (grouped launches): time-steps/s of the
-    whole set and the effective bandwidth algorithmic bytes x iterations /
-    wall time (setup, accept and host polls included)."""
+    whole set and the effective bandwidth bytes x iterations / wall time
+    (setup, accept and host polls included), on the schedule's bytes per
+    point and iteration (as the combined set's variants report it) and on
+    the bytes the iteration kernels themselves move."""
     import torch
     from paper_2204_07247_amd import pfch
     ctx = pfch.Context([_desc(w) for w in ws])
     ctx.set_stats_detail(0)
     u0 = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
     per_iter = [sum(algorithmic_bytes(w).values()) for w in ws]
+    per_iter_sched = [SCHEDULE_BYTES[(w.model, w.scheme, len(w.shape))] * w.npoints for w in ws]
 
     def run(n):
         for i, u in enumerate(u0):
@@ -646,12 +649,15 @@ def ensemble_bandwidth(ws, steps, warmup, label):
     el = time.perf_counter() - t0
     ctx.close()
     moved = float(np.dot(per_iter, its))
+    sched = float(np.dot(per_iter_sched, its))
     return dict(workload=label, instances=len(ws), points=int(sum(w.npoints for w in ws)),
                 steps=steps, instance_steps_per_s=round(len(ws) * steps / el, 2),
                 ms_per_step=round(1e3 * el / steps, 3),
                 iters_per_step_mean=round(float(its.sum() / (len(ws) * steps)), 3),
-                effective_gbs=round(moved / el / 1e9, 1),
-                effective_frac=round(moved / el / 1e9 / HBM_PEAK_GBS, 4))
+                effective_gbs=round(sched / el / 1e9, 1),
+                effective_frac=round(sched / el / 1e9 / HBM_PEAK_GBS, 4),
+                kernel_bytes_gbs=round(moved / el / 1e9, 1),
+                kernel_bytes_frac=round(moved / el / 1e9 / HBM_PEAK_GBS, 4))
 
 
 def _learned_vs_plain(w, fno, norm_fn, steps):
