@@ -15,9 +15,11 @@ The same steps run four ways:
   learned          one context per instance, learned guess on the FCH
                    instances (a float32 FNO: 4 spectral layers, 16 modes,
                    width 32, GELU, run on its own 64 x 64 grid of the
-                   band-limited state, trained on FCH 256^2 trajectories
-                   with the same periods); the 3D instance keeps the
-                   extrapolated guess;
+                   band-limited state, trained on 300-step FCH 256^2
+                   trajectories with the set's parameter spread and the
+                   same periods, and fed with the training set's
+                   normalisation); the 3D instance keeps the extrapolated
+                   guess;
   batched_learned  both: the headline `value`.
 Each times `--steps` bench steps (default: the configuration's 300) from the
 initial conditions, bracketed by torch.cuda.synchronize(), after `--warmup`
@@ -203,39 +205,33 @@ def cpu_baseline(w, max_steps, budget_s):
 # ---------------------------------------------------------------------------
 def train_fch_network(epochs):
     """The FCH warm-start network: FNO (4 spectral layers, 16 modes, width 32,
-    GELU, float32) on its own 64 x 64 grid, trained on 20 trajectories of the
-    FCH 256^2 generator (seeds 100-119, 100 steps, 10% of the triples held
-    out) resampled to that grid; the combined set's FCH grids have the same
-    periods, so the network sees the same modes on every grid."""
-    import dataclasses
-
+    GELU, float32) on its own 64 x 64 grid, trained on 16 trajectories of
+    300 steps of FCH 256^2 instances on the combined set's period with the
+    set's parameter spread (e ~ U[0.08, 0.12], mean ~ U[-0.7, -0.5]; seeds
+    100-115), resampled to that grid, 10% of the triples held out.  The
+    trajectories cover the horizon the network is deployed on, and the
+    deployed guesses use the training set's normalisation."""
     import torch
     from paper_2204_07247_amd import learned
-    base = W.FCH256_BDF2
-    ws = [dataclasses.replace(base, seeds=(s,)) for s in range(100, 120)]
+    ws = W.fch_ensemble(count_per_size=16, sizes=(256,), steps=COMBINED_STEPS, base_seed=100)
     u0s = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
     cfg = learned.TrainConfig(width=32, modes=16, layers=4, epochs=epochs, grid=(64, 64))
     log(f"[bench] FCH network: trajectories and training ({epochs} epochs)")
     t0 = time.perf_counter()
-    tr = learned.train(ws, u0s, base.steps, cfg, log=log)
+    tr = learned.train(ws, u0s, COMBINED_STEPS, cfg, log=log)
+    del u0s
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     info = dict(network=dict(width=cfg.width, modes=cfg.modes, layers=cfg.layers, grid=list(cfg.grid),
                              dtype="f32", params=tr.fno.n_params),
-                training=dict(data=f"{len(ws)} x {base.steps} steps of {base.name} (seeds 100-119), "
+                training=dict(data=f"{len(ws)} x {COMBINED_STEPS} steps of FCH 256^2 on [0, 4 pi)^2 with "
+                                   f"e ~ U[0.08, 0.12], mean ~ U[-0.7, -0.5] (seeds 100-{100 + len(ws) - 1}), "
                                    f"resampled to the network's grid",
                               triples=tr.n_train + tr.n_val, held_out=tr.n_val, epochs=epochs, batch=cfg.batch,
                               lr=cfg.lr, seconds=round(time.perf_counter() - t0, 1),
-                              held_out_loss=[round(v, 5) for v in tr.val_loss]))
+                              held_out_loss=[round(v, 5) for v in tr.val_loss],
+                              normalisation=[float(v) for v in tr.norm]))
     return tr, info
-
-
-def _norm_for(tr, un, unm1):
-    """Network input scales of one instance from its own state (mean and
-    spread of u^n and of u^n - u^{n-1}); the output scale keeps the training
-    set's ratio of correction to increment spread."""
-    d = un - unm1
-    sd = float(d.std().item()) or 1.0
-    return (float(un.mean().item()), float(un.std().item()) or 1.0, sd, tr.norm[3] / tr.norm[2] * sd)
 
 
 def run_set(ws, mode, steps, warmup, tr=None, time_groups=None):
@@ -273,13 +269,11 @@ def run_set(ws, mode, steps, warmup, tr=None, time_groups=None):
     warm["fallbacks"] = 0
     for _ in range(max(1, warmup)):
         one_step(warm)
-    if use_net:  # every instance has a history now
+    if use_net:  # the network with the training set's normalisation
         for c, idx in ctxs:
             for k, i in enumerate(idx):
                 if guess[i]:
-                    un, unm1 = torch.empty_like(u[i]), torch.empty_like(u[i])
-                    c.get_state(k, un, unm1)
-                    c.set_fno(k, tr.fno, _norm_for(tr, un, unm1))
+                    c.set_fno(k, tr.fno, tr.norm)
         one_step(warm)  # the first learned step, untimed
     # back to the initial conditions: the timed steps are the configuration's
     # first `steps` steps (a step without history is backward Euler with the
