@@ -95,6 +95,8 @@ typedef struct pfch_stats {
                        solution x (the residual of the step problem, without
                        the preconditioner); NaN unless statistics detail 2 was
                        set and the solve converged; NaN for the IMEX schemes */
+  double gain;      /* gain g of the learned correction this step's guess
+                       used (see pfch_set_fno); NaN unless guess is 1 */
   int32_t iters;    /* PAGD iterations */
   int32_t fft_pairs;/* 2D transform pairs of real fields used (setup + iterations) */
   int32_t status;   /* PFCH_OK or the error of this instance */
@@ -128,8 +130,8 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
  * history yet, so that the next BDF2 step is backward Euler) are device
  * arrays of Nx*Ny(*Nz) doubles, copied; t, dt_prev (the step that produced
  * u^n, > 0, ignored when u_nm1 is NULL) and the step index n are host
- * values.  Discards a queued set-up.  PFCH_E_INVAL for a bad instance index
- * or null u_n. */
+ * values.  Discards a queued set-up and sets the gain of a learned
+ * correction to 1.  PFCH_E_INVAL for a bad instance index or null u_n. */
 int pfch_set_state(pfch_ctx* ctx, int32_t inst, const double* u_n, const double* u_nm1,
                    double t, double dt_prev, int32_t step_index);
 
@@ -286,10 +288,16 @@ int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]);
  *
  * The network maps (u^n, u^{n-1}) to a correction of the extrapolated guess:
  *   input  x[0] = (u^n - mu)/su,  x[1] = (u^n - u^{n-1})/sd
- *   guess  x_0 = u^n + rho (u^n - u^{n-1}) + so * Pi_0 y
+ *   guess  x_0 = u^n + rho (u^n - u^{n-1}) + g so * Pi_0 y
  * where Pi_0 removes the mean (the PAGD solve keeps the mean of its initial
- * guess, so the mass stays that of the extrapolation) and norm = {mu, su, sd,
- * so}.  PAGD still iterates to ||d||_inf < tol from this guess, so the
+ * guess, so the mass stays that of the extrapolation), norm = {mu, su, sd,
+ * so}, and g is the instance's gain on the correction: 1 after
+ * pfch_set_state or pfch_set_fno; after each pfch_step that took the learned
+ * guess and accepted the solution x it reached, the least-squares gain of
+ * that step's correction c = so Pi_0 y against x - (u^n + rho (u^n -
+ * u^{n-1})), clamped to [0, 1], is the next guess's g (steps of
+ * pfch_step_adaptive leave g as it is).  PAGD still iterates to
+ * ||d||_inf < tol from this guess, so the
  * solution differs from the extrapolated-guess solution only within that
  * tolerance; a guess from which the solve fails is replaced by the
  * extrapolated one.
@@ -376,9 +384,10 @@ void pfch_fno_destroy(pfch_fno* f);
  * inputs resampled down as in pfch_fno_prepare_resampled and its output
  * interpolated back with the same band (modes |k| < Nc/2 of the network's
  * grid, zero beyond), so the learned correction holds those modes only.
- * norm = {mu, su, sd, so}, su, sd, so > 0.  The network is not owned; it
- * must outlive its use and must not be used on another stream while the
- * context steps.  PFCH_E_INVAL for a grid that fits neither case. */
+ * norm = {mu, su, sd, so}, su, sd, so > 0; the gain of the correction is
+ * set to 1.  The network is not owned; it must outlive its use and must not
+ * be used on another stream while the context steps.  PFCH_E_INVAL for a
+ * grid that fits neither case. */
 int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4]);
 
 /* Transform plans and launch geometry of the iteration kernels of instance

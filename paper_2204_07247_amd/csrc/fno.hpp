@@ -336,29 +336,91 @@ __global__ __launch_bounds__(256) void k_partial_sum(const float* __restrict__ y
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// Learned initial guess: x0 = u^n + rho (u^n - u^{n-1}) + so (y - mean(y)).
-// The correction is projected to zero mean so that x0 keeps the mass of the
-// extrapolation (the solve preserves the mean of its initial guess).
-// Launched with 256 threads per block; every block forms the mean from the
-// partial sums in the same fixed order (whole block, then a tree).
+// Per-block partial sums of c (x - x0) and c^2, where x0 = e + g c was a
+// learned guess (e the extrapolation, c the network's correction, g its
+// gain) and x the solution the step reached from it: the least-squares gain
+// of that step's correction is g + sum c (x - x0) / sum c^2.  Fixed grid and
+// order (every call with the same inputs gives the same sums).
+__global__ __launch_bounds__(256) void k_gain_partials(const double* __restrict__ x0,
+                                                       const double* __restrict__ x,
+                                                       const float* __restrict__ c, long long n,
+                                                       double* __restrict__ part) {
+  __shared__ double r1[256], r2[256];
+  double s1 = 0.0, s2 = 0.0;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const double cv = (double)c[p];
+    s1 += cv * (x[p] - x0[p]);
+    s2 += cv * cv;
+  }
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+      r2[threadIdx.x] += r2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r1[0];
+    part[2 * blockIdx.x + 1] = r2[0];
+  }
+}
+
+// Learned initial guess: x0 = u^n + rho (u^n - u^{n-1}) + g c with the
+// correction c = so (y - mean(y)), projected to zero mean so that x0 keeps
+// the mass of the extrapolation (the solve preserves the mean of its
+// initial guess), and its gain g: gain_in[0], or, when the previous step's
+// gain partials are given (ngp blocks of k_gain_partials), that step's
+// least-squares gain clamped to [0, 1]; written to gain_out[0] and to
+// gain_pub[0] (pinned host memory, for the step's statistics).  c is kept
+// (float) in c_out for the next step's gain.  Launched with 256 threads per
+// block; every block forms the mean and the gain from the partial sums in
+// the same fixed order (whole block, then a tree).
 __global__ __launch_bounds__(256) void k_learned_guess(const double* __restrict__ un,
                                                        const double* __restrict__ unm1, double rho, double so,
                                                        const float* __restrict__ y,
                                                        const double* __restrict__ part, int nparts, long long n,
-                                                       double* __restrict__ x0) {
-  __shared__ double red[256];
+                                                       double* __restrict__ x0, float* __restrict__ c_out,
+                                                       const double* __restrict__ gain_in,
+                                                       double* __restrict__ gain_out, double* gain_pub,
+                                                       const double* __restrict__ gpart, int ngp) {
+  __shared__ double red[256], red2[256];
   double s = 0.0;
   for (int k = threadIdx.x; k < nparts; k += 256) s += part[k];
   red[threadIdx.x] = s;
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = threadIdx.x; k < ngp; k += 256) {
+    s1 += gpart[2 * k];
+    s2 += gpart[2 * k + 1];
+  }
+  __shared__ double red1[256];
+  red1[threadIdx.x] = s1;
+  red2[threadIdx.x] = s2;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if (threadIdx.x < o) {
+      red[threadIdx.x] += red[threadIdx.x + o];
+      red1[threadIdx.x] += red1[threadIdx.x + o];
+      red2[threadIdx.x] += red2[threadIdx.x + o];
+    }
     __syncthreads();
   }
   const double mean = red[0] / (double)n;
+  double g = gain_in[0];
+  if (ngp > 0 && red2[0] > 0.0) g = fmin(1.0, fmax(0.0, g + red1[0] / red2[0]));
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    gain_out[0] = g;
+    gain_pub[0] = g;
+    __threadfence_system();
+  }
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
     const double u = un[p];
-    x0[p] = u + rho * (u - unm1[p]) + so * ((double)y[p] - mean);
+    const double c = so * ((double)y[p] - mean);
+    x0[p] = u + rho * (u - unm1[p]) + g * c;
+    c_out[p] = (float)c;
   }
 }
 

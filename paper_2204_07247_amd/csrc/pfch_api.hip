@@ -265,6 +265,14 @@ struct Instance {
   double fno_norm[4] = {0, 1, 1, 1};
   double* xguess = nullptr;  // learned guess buffer (allocated on first attach)
   double* gpart = nullptr;   // FNO_SUM_BLOCKS partial sums of the network output
+  // gain of the learned correction: gbuf[0..1] the gain (read one, written
+  // the other, gain_par the one to read), then 2 FNO_SUM_BLOCKS partials;
+  // gcor the last guess's correction; gain_ready: the last step took its
+  // learned guess and was accepted, so the next guess can update the gain
+  double* gbuf = nullptr;
+  float* gcor = nullptr;
+  int gain_par = 0;
+  bool gain_ready = false;
   // adaptive stepping (buffers allocated on first use)
   double* Um2 = nullptr;     // u^{n-2}
   double* R[3] = {nullptr, nullptr, nullptr};  // R(u^n), R(u^{n-1}), R(u~)
@@ -341,6 +349,8 @@ struct pfch_ctx {
   double* d_scale = nullptr;   // 1/P per instance
   double* d_mass = nullptr;    // device address of h_mass
   double* h_mass = nullptr;    // pinned, coherent
+  double* d_gain = nullptr;    // device address of h_gain
+  double* h_gain = nullptr;    // pinned, coherent: gain of each instance's last learned guess
   EstArgs* d_est = nullptr;    // adaptive error estimate, per instance
   EstArgs* h_est = nullptr;    // pinned
   double* d_est_part = nullptr;  // [n][2][EST_BLOCKS]
@@ -998,12 +1008,25 @@ int betas_host(pfch_ctx* ctx, Instance& I, double a, double out[4]) {
   return PFCH_OK;
 }
 
+// The gain of an instance's learned correction back to 1 (after a new
+// history or network).
+int reset_gain(pfch_ctx* ctx, Instance& I) {
+  static const double one[2] = {1.0, 1.0};
+  I.gain_ready = false;
+  I.gain_par = 0;
+  if (I.gbuf) HIPCHK(hipMemcpyAsync(I.gbuf, one, sizeof(one), hipMemcpyHostToDevice, ctx->stream));
+  return PFCH_OK;
+}
+
 // Learned initial guesses of the instances `ids` (extrapolation factors
 // rho[k]): network inputs from (u^n, u^{n-1}) (resampled to the network's
 // grid when it is coarser), one forward pass per network and batch of up to
 // its max_batch instances, then per instance x0 = extrapolation +
-// Pi_0(so * y) (y interpolated back to the instance's grid) into I.xguess;
-// all on the context's stream.
+// g Pi_0(so * y) (y interpolated back to the instance's grid) into
+// I.xguess, g the instance's gain: 1 after pfch_set_state or pfch_set_fno,
+// then after every fixed-size step that took the learned guess the least
+// squares gain of that step's correction against the solution it reached,
+// clamped to [0, 1]; all on the context's stream.
 int learned_guesses(pfch_ctx* ctx, const std::vector<int>& ids, const std::vector<double>& rho) {
   hipStream_t s = ctx->stream;
   std::vector<char> done(ids.size(), 0);
@@ -1061,10 +1084,21 @@ int learned_guesses(pfch_ctx* ctx, const std::vector<int>& ids, const std::vecto
         y = I.fno_rs->yf + (long long)(k - first) * P;
       }
       hipLaunchKernelGGL(k_partial_sum, dim3(FNO_SUM_BLOCKS), dim3(256), 0, s, y, P, I.gpart);
+      // the previous step's guess (still in xguess) against the solution it
+      // reached (now u^n): the gain of this step's correction
+      int ngp = 0;
+      if (I.gain_ready) {
+        hipLaunchKernelGGL(k_gain_partials, dim3(FNO_SUM_BLOCKS), dim3(256), 0, s, (const double*)I.xguess,
+                           (const double*)I.U[I.ucur], (const float*)I.gcor, P, I.gbuf + 2);
+        ngp = FNO_SUM_BLOCKS;
+        I.gain_ready = false;
+      }
       hipLaunchKernelGGL(k_learned_guess, dim3(std::min(blocks_for(P), 4096u)), dim3(256), 0, s,
                          (const double*)I.U[I.ucur],
                          (const double*)I.U[1 - I.ucur], rho[chunk[k]], I.fno_norm[3], y, (const double*)I.gpart,
-                         FNO_SUM_BLOCKS, P, I.xguess);
+                         FNO_SUM_BLOCKS, P, I.xguess, I.gcor, (const double*)I.gbuf + I.gain_par,
+                         I.gbuf + (1 - I.gain_par), ctx->d_gain + ids[chunk[k]], (const double*)I.gbuf + 2, ngp);
+      I.gain_par ^= 1;
     }
     HIPCHK(hipGetLastError());
   }
@@ -1744,6 +1778,13 @@ int pfch_create(const pfch_instance_desc* descs, int32_t n_inst, void* hip_strea
     rc = PFCH_E_HIP;
     goto fail;
   }
+  // coherent too: the learned-guess kernel writes each instance's gain here
+  if ((rc = halloc(ctx->host_allocs, &p, sizeof(double) * n_inst, true))) goto fail;
+  ctx->h_gain = (double*)p;
+  if (hipHostGetDevicePointer((void**)&ctx->d_gain, ctx->h_gain, 0) != hipSuccess) {
+    rc = PFCH_E_HIP;
+    goto fail;
+  }
   if ((rc = dalloc(ctx->allocs, &p, sizeof(EstArgs) * n_inst))) goto fail;
   ctx->d_est = (EstArgs*)p;
   if ((rc = halloc(ctx->host_allocs, &p, sizeof(EstArgs) * n_inst))) goto fail;
@@ -2101,7 +2142,7 @@ int pfch_set_state(pfch_ctx* ctx, int32_t inst, const double* u_n, const double*
   I.hist = I.has_prev ? 2 : 1;
   I.r_valid = false;
   I.lap_levels = 0;
-  return PFCH_OK;
+  return reset_gain(ctx, I);
 }
 
 int pfch_get_state(pfch_ctx* ctx, int32_t inst, double* u_n, double* u_nm1, double* t, double* dt_prev,
@@ -2321,6 +2362,7 @@ int fill_stats(pfch_ctx* ctx, const SolveOut& o, int i, bool want_mass, bool acc
   s.guess = o.guess[i];
   s.mass = (want_mass && accepted) ? ctx->h_mass[i] : NAN;
   s.rnorm_inf = NAN;
+  s.gain = o.guess[i] == 1 ? ctx->h_gain[i] : NAN;
   if (ctx->stats_detail > 0) {
     int rc = betas_host(ctx, I, o.a[i], s.beta);
     if (rc) return rc;
@@ -2544,6 +2586,9 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
   // advanced.  A learned guess is formed then too (into the instance's own
   // guess buffer, in stream order, so later use of the network on this
   // stream does not change it).
+  // the next learned guess may take this step's gain (learned guess taken
+  // and accepted)
+  for (int i = 0; i < n; ++i) ctx->inst[i].gain_ready = ctx->inst[i].gbuf && o.guess[i] == 1 && take[i];
   const bool speculate = same_dt && first_err == PFCH_OK;
   ctx->last_dt.assign(dt, dt + n);
   if (speculate) {
@@ -2573,6 +2618,7 @@ int pfch_step_adaptive(pfch_ctx* ctx, const pfch_adapt_desc* ad, pfch_adapt_resu
   if ((rc = prepare_adaptive(ctx))) return rc;
   SolveOut o;
   if ((rc = solve_all(ctx, dt.data(), o))) return rc;
+  for (auto& I : ctx->inst) I.gain_ready = false;  // accepts here do not feed the gain
   // R(u~) of every converged instance
   for (auto& G : ctx->groups) {
     const unsigned nm = (unsigned)G.members.size();
@@ -2758,6 +2804,7 @@ int pfch_solve(pfch_ctx* ctx, int32_t inst, double a, double b, double c, const 
     st->fft_pairs = fft_pairs_of(I, iters);
     st->mass = NAN;
     st->rnorm_inf = NAN;
+    st->gain = NAN;
     if ((rc = betas_host(ctx, I, a, st->beta))) return rc;
     if (ctx->stats_detail > 1 && status == PFCH_OK &&
         (rc = residual_norm(ctx, I, x, u_n, u_nm1, Coef{a, b, c, ss.theta}, &st->rnorm_inf)))
@@ -3143,11 +3190,15 @@ int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4])
     I.xguess = (double*)q;
     if ((rc = dalloc(I.allocs, &q, sizeof(double) * FNO_SUM_BLOCKS))) return rc;
     I.gpart = (double*)q;
+    if ((rc = dalloc(I.allocs, &q, sizeof(double) * (2 + 2 * FNO_SUM_BLOCKS)))) return rc;
+    I.gbuf = (double*)q;
+    if ((rc = dalloc(I.allocs, &q, sizeof(float) * (size_t)I.npts))) return rc;
+    I.gcor = (float*)q;
   }
   I.fno = f;
   I.fno_rs = R;
   for (int k = 0; k < 4; ++k) I.fno_norm[k] = norm[k];
-  return PFCH_OK;
+  return reset_gain(ctx, I);
 }
 
 }  // extern "C"

@@ -66,6 +66,7 @@ class Stats(ctypes.Structure):
         ("beta", ctypes.c_double * 4),
         ("mass", ctypes.c_double),
         ("rnorm_inf", ctypes.c_double),
+        ("gain", ctypes.c_double),
         ("iters", ctypes.c_int32),
         ("fft_pairs", ctypes.c_int32),
         ("status", ctypes.c_int32),
@@ -75,7 +76,7 @@ class Stats(ctypes.Structure):
     def as_dict(self):
         return dict(iters=self.iters, status=self.status, dnorm=self.dnorm_inf,
                     betas=tuple(self.beta), mass=self.mass, fft_pairs=self.fft_pairs,
-                    guess=self.guess, rnorm=self.rnorm_inf)
+                    guess=self.guess, rnorm=self.rnorm_inf, gain=self.gain)
 
 
 class AdaptDesc(ctypes.Structure):

@@ -37,9 +37,10 @@ def test_struct_sizes_match_header_layout():
     from paper_2204_07247_amd import pfch
     # 3 + 5 + 3 + 8 doubles, then 6 + 3 + 1 int32
     assert ctypes.sizeof(pfch.InstanceDesc) == 19 * 8 + 10 * 4
-    # dnorm, beta[4], mass, rnorm; iters, fft_pairs, status, guess
-    assert ctypes.sizeof(pfch.Stats) == 7 * 8 + 4 * 4
+    # dnorm, beta[4], mass, rnorm, gain; iters, fft_pairs, status, guess
+    assert ctypes.sizeof(pfch.Stats) == 8 * 8 + 4 * 4
     assert pfch.Stats.rnorm_inf.offset == 6 * 8
+    assert pfch.Stats.gain.offset == 7 * 8
 
 
 def _desc(**kw):

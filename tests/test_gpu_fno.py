@@ -206,6 +206,68 @@ def test_learned_guess_step_within_tolerance(w):
     fno.close()
 
 
+def test_learned_gain_is_the_last_steps_least_squares_gain():
+    """The first learned step after pfch_set_fno (or pfch_set_state) uses
+    gain 1; the next one the least-squares gain of the first step's
+    correction c = so (y - mean y) against the solution x it reached,
+    sum c (x - e) / sum c^2 with e the extrapolation, clamped to [0, 1],
+    recomputed here from the network's own forward pass on the same inputs.
+    After pfch_set_state the gain is 1 again and the first learned step
+    repeats bitwise; steps without the learned guess report no gain."""
+    import math
+
+    import torch
+    from paper_2204_07247_amd import pfch
+    w = dataclasses.replace(W.FCH256_BDF2, shape=(64, 64), seeds=(1,))
+    un, unm1, dtp, k = _history(w, 3)
+    fno = pfch.Fno(8, 4, 2, *w.shape)
+    rng = np.random.default_rng(11)
+    fno.set_params(torch.from_numpy(rng.normal(0.0, 0.3, fno.n_params).astype(np.float32)).cuda())
+    u = un.cpu().numpy()
+    du = (un - unm1).cpu().numpy()
+    norm = [float(u.mean()), float(u.std()), float(du.std()), 1.0]
+    # the network's output on the first step's inputs (dt equal to dt_prev:
+    # extrapolation factor 1); the output scale so makes the correction five
+    # times the largest |u^n - u^{n-1}|, far larger than the step's own
+    # correction, so that its least-squares gain lies well inside (0, 1)
+    X = torch.empty((1, 2) + tuple(w.shape), dtype=torch.float32, device="cuda")
+    fno.prepare(unm1, un, None, 1.0, norm, X[0])
+    y = fno.forward(X)[0].double().cpu().numpy()
+    norm[3] = so = 5.0 * float(np.abs(du).max()) / float(np.abs(y - y.mean()).max())
+    d = desc_for(w)
+    d.guess = 1
+    ctx = pfch.Context([d])
+    ctx.set_state(0, un, unm1, t=0.0, dt_prev=dtp, step_index=k)
+    ctx.set_fno(0, fno, norm)
+    rc, st = ctx.step(w.dt)
+    assert rc == pfch.PFCH_OK and st[0]["guess"] == 1 and st[0]["gain"] == 1.0
+    x1 = torch.empty_like(un)
+    ctx.get_state(0, x1)
+    c = so * (y - y.mean())
+    e = 2.0 * u - unm1.cpu().numpy()
+    x0 = e + c
+    cf = c.astype(np.float32).astype(np.float64)
+    raw = 1.0 + float(np.sum(cf * (x1.cpu().numpy() - x0)) / np.sum(cf * cf))
+    want = min(1.0, max(0.0, raw))
+    rc, st = ctx.step(w.dt)
+    assert rc == pfch.PFCH_OK and st[0]["guess"] == 1
+    print(f"gain of the second step {st[0]['gain']:.9f}, recomputed {want:.9f} (unclamped {raw:.9f})",
+          flush=True)
+    assert abs(st[0]["gain"] - want) <= 1e-6
+    assert 0.0 < st[0]["gain"] < 0.5
+    # a new history: gain 1, the first step again bit for bit
+    ctx.set_state(0, un, unm1, t=0.0, dt_prev=dtp, step_index=k)
+    rc, st = ctx.step(w.dt)
+    again = torch.empty_like(un)
+    ctx.get_state(0, again)
+    assert rc == pfch.PFCH_OK and st[0]["gain"] == 1.0 and torch.equal(again, x1)
+    ctx.close()
+    # the extrapolated guess reports no gain
+    rc, st, _ = _one_step(w, un, unm1, dtp, k)
+    assert rc == pfch.PFCH_OK and st["guess"] == 0 and math.isnan(st["gain"])
+    fno.close()
+
+
 def test_failed_learned_guess_falls_back_to_extrapolation():
     """A guess from which the solve fails (here: non-finite residual) is
     replaced by the extrapolated guess; the step then equals the plain step
