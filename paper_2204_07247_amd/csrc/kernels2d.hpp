@@ -168,10 +168,12 @@ __device__ __forceinline__ uint64_t block_max_bits(uint64_t v, uint64_t* red) {
 // Row-side packing.
 // ---------------------------------------------------------------------------
 // Z[k] = A[k] + i B[k] over the full length from the Hermitian half spectra
-// of rows r0 (A) and r0 + 1 (B) of F, r0 even.  With an even team size the
-// lanes of a pair (k, k + 1, k even) load the columns of both their elements
-// as two 32-byte pieces (each lane one row of each) and exchange the halves
-// they hold for each other.
+// of rows r0 (A) and r0 + 1 (B) of F, r0 even.  With teams of whole waves
+// the lanes of a pair (k, k + 1, k even) load the columns of both their
+// elements as two 32-byte pieces (each lane one row of each) and exchange
+// the halves they hold for each other; smaller teams (short rows, several
+// row pairs per wave) load A[k] and B[k] directly, which measured faster
+// there.
 template <class P>
 __device__ __forceinline__ void load_pack(c2 (&v)[P::RMAX], const GLB c2* __restrict__ F, int r0, int rows,
                                           int t) {
@@ -181,7 +183,7 @@ __device__ __forceinline__ void load_pack(c2 (&v)[P::RMAX], const GLB c2* __rest
   for (int m = 0; m < P::RMAX; ++m) {
     const int k = t + m * T;
     c2 a, b;
-    if constexpr (T % 2 == 0) {
+    if constexpr (T % 2 == 0 && T >= 64) {
       const bool odd = k & 1;
       const int ke = k & ~1;
       const int row = r0 + (odd ? 1 : 0);
@@ -209,10 +211,11 @@ __device__ __forceinline__ void load_pack(c2 (&v)[P::RMAX], const GLB c2* __rest
 // After the forward transform of Z = a + i b (a, b the real rows r0, r0 + 1,
 // r0 even): store the half spectra A[k] = (Z[k] + conj Z[N-k]) / 2 into row
 // r0 and B[k] = -i (Z[k] - conj Z[N-k]) / 2 into row r0 + 1 of F (k = 0 and
-// N/2 packed in column 0).  With an even team size, lane s of round m takes
-// the s-th 16-byte slot of the row pair's lines (k = s / 2, row r0 + s % 2),
-// so that each store instruction writes whole lines; the lanes of a pair read
-// Z[k] and Z[N-k] from LDS and exchange them.
+// N/2 packed in column 0).  With teams of whole waves, lane s of round m
+// takes the s-th 16-byte slot of the row pair's lines (k = s / 2, row
+// r0 + s % 2), so that each store instruction writes whole lines; the lanes
+// of a pair read Z[k] and Z[N-k] from LDS and exchange them.  Smaller teams
+// store A[k] and B[k] from one lane.
 template <class P>
 __device__ __forceinline__ void unpack_store(const c2 (&v)[P::RMAX], c2* lds, GLB c2* __restrict__ F, int r0,
                                              int rows, int t) {
@@ -220,7 +223,7 @@ __device__ __forceinline__ void unpack_store(const c2 (&v)[P::RMAX], c2* lds, GL
 #pragma unroll
   for (int m = 0; m < P::RMAX; ++m) lds[lds_idx(t + m * T)] = v[m];
   __syncthreads();
-  if constexpr (T % 2 == 0) {
+  if constexpr (T % 2 == 0 && T >= 64) {
 #pragma unroll
     for (int m = 0; m < P::RMAX; ++m) {
       const int sl = t + m * T, k = sl >> 1;
