@@ -781,9 +781,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(row_min_wav
     // Both real rows of the pair at once, one transform per spectral field:
     // the direction d (field 0) first, then its Laplacian (field 1), so
     // every spectral read covers whole 128-byte lines of the tiled layout.
-    // Large plans load the real-space operands of each half after its
-    // transform, which keeps them within the registers of two waves per
-    // SIMD; small plans (latency-bound grids) issue every load up front.
+    // Large plans issue the real-space loads of each half just before its
+    // transform, so that they are in flight during it (226 registers at
+    // 2048, two waves per SIMD; the second spectral field is loaded after
+    // the first half, which would not fit beside them); small plans
+    // (latency-bound grids) issue every load up front.
     constexpr bool EARLY = RM <= 4;
     double vbs[2][RM], lv[2][RM];
     double a[2][RM], b[2][RM], uu[2][RM], la[2][RM], lb[2][RM], lu[2][RM];
@@ -820,8 +822,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(row_min_wav
       load_x();
       load_l();
     }
-    fft<PX, true>(v, lds, tw, t);
     if constexpr (!EARLY) load_x();
+    fft<PX, true>(v, lds, tw, t);
     const int tx = opaque(t);
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
@@ -839,8 +841,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(row_min_wav
       }
     }
     if constexpr (!EARLY) load_pack<PX>(w, Sg + fs, r0, rows, opaque(t));
-    fft<PX, true>(w, lds, tw, t);
     if constexpr (!EARLY) load_l();
+    fft<PX, true>(w, lds, tw, t);
     const int tw2 = opaque(t);
 #pragma unroll
     for (int row = 0; row < 2; ++row) {
