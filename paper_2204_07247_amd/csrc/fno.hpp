@@ -319,108 +319,146 @@ __global__ void k_sum_parts_f(const float* __restrict__ part, int n, double scal
   *out = s * scale;
 }
 
-// Per-block float64 partial sums of a float field (fixed grid).
-__global__ __launch_bounds__(256) void k_partial_sum(const float* __restrict__ y, long long n,
-                                                     double* __restrict__ part) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    s += (double)y[i];
-  red[threadIdx.x] = s;
+// ---------------------------------------------------------------------------
+// Learned guess kernels.  The reductions run on a fixed grid of GUESS_BLOCKS
+// blocks of 256 threads (per-thread sums over a fixed stride, then the
+// block's tree), finished by one block in a fixed order, so a batched guess
+// equals the instance's solo guess.  Fields are read two points per lane
+// (P even: every grid has an even row length).
+// ---------------------------------------------------------------------------
+constexpr int GUESS_BLOCKS = 1024;
+
+// Tree sum of r[0..256) in LDS; the result is returned to every thread.
+__device__ __forceinline__ double guess_tree(double* r, double v) {
+  r[threadIdx.x] = v;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if (threadIdx.x < o) r[threadIdx.x] += r[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  const double t = r[0];
+  __syncthreads();
+  return t;
 }
 
-// Per-block partial sums of c (x - x0) and c^2, where x0 = e + g c was a
-// learned guess (e the extrapolation, c the network's correction, g its
-// gain) and x the solution the step reached from it: the least-squares gain
-// of that step's correction is g + sum c (x - x0) / sum c^2.  Fixed grid and
-// order (every call with the same inputs gives the same sums).
-__global__ __launch_bounds__(256) void k_gain_partials(const double* __restrict__ x0,
-                                                       const double* __restrict__ x,
-                                                       const float* __restrict__ c, long long n,
-                                                       double* __restrict__ part) {
-  __shared__ double r1[256], r2[256];
+// Network inputs of a learned guess from the step history:
+// x[0] = (u^n - mu)/su, x[1] = (u^n - u^{n-1})/sd (as k_fno_inputs).  With
+// x0 given (the last step's learned guess e + g c, c its correction kept in
+// float) also the per-block partial sums of c (u^n - x0) and c^2, u^n being
+// the solution that step reached: gpart[2b], gpart[2b + 1].
+__global__ __launch_bounds__(256) void k_guess_inputs(const double* __restrict__ unm1,
+                                                      const double* __restrict__ un, long long P, double mu,
+                                                      double su, double sd, float* __restrict__ x,
+                                                      const double* __restrict__ x0,
+                                                      const float* __restrict__ c, double* __restrict__ gpart) {
+  __shared__ double r[256];
+  const long long h = P >> 1;
+  const double2* __restrict__ a2 = reinterpret_cast<const double2*>(un);
+  const double2* __restrict__ b2 = reinterpret_cast<const double2*>(unm1);
+  float2* __restrict__ xa = reinterpret_cast<float2*>(x);
+  float2* __restrict__ xd = reinterpret_cast<float2*>(x + P);
   double s1 = 0.0, s2 = 0.0;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-       p += (long long)gridDim.x * blockDim.x) {
-    const double cv = (double)c[p];
-    s1 += cv * (x[p] - x0[p]);
-    s2 += cv * cv;
-  }
-  r1[threadIdx.x] = s1;
-  r2[threadIdx.x] = s2;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      r1[threadIdx.x] += r1[threadIdx.x + o];
-      r2[threadIdx.x] += r2[threadIdx.x + o];
+  const long long stride = (long long)GUESS_BLOCKS * 256;
+  if (x0) {
+    const double2* __restrict__ g2 = reinterpret_cast<const double2*>(x0);
+    const float2* __restrict__ c2v = reinterpret_cast<const float2*>(c);
+    for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < h; q += stride) {
+      const double2 a = a2[q], b = b2[q], g = g2[q];
+      const float2 cv = c2v[q];
+      xa[q] = make_float2((float)((a.x - mu) / su), (float)((a.y - mu) / su));
+      xd[q] = make_float2((float)((a.x - b.x) / sd), (float)((a.y - b.y) / sd));
+      const double c0 = (double)cv.x, c1 = (double)cv.y;
+      s1 += c0 * (a.x - g.x);
+      s1 += c1 * (a.y - g.y);
+      s2 += c0 * c0;
+      s2 += c1 * c1;
     }
-    __syncthreads();
+    const double t1 = guess_tree(r, s1);
+    const double t2 = guess_tree(r, s2);
+    if (threadIdx.x == 0) {
+      gpart[2 * blockIdx.x] = t1;
+      gpart[2 * blockIdx.x + 1] = t2;
+    }
+  } else {
+    for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < h; q += stride) {
+      const double2 a = a2[q], b = b2[q];
+      xa[q] = make_float2((float)((a.x - mu) / su), (float)((a.y - mu) / su));
+      xd[q] = make_float2((float)((a.x - b.x) / sd), (float)((a.y - b.y) / sd));
+    }
   }
+}
+
+// Per-block float64 partial sums of the network output y (float, P points).
+__global__ __launch_bounds__(256) void k_guess_ysum(const float* __restrict__ y, long long P,
+                                                    double* __restrict__ part) {
+  __shared__ double r[256];
+  const long long h = P >> 1;
+  const float2* __restrict__ y2 = reinterpret_cast<const float2*>(y);
+  double s = 0.0;
+  for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < h; q += (long long)GUESS_BLOCKS * 256) {
+    const float2 v = y2[q];
+    s += (double)v.x;
+    s += (double)v.y;
+  }
+  const double t = guess_tree(r, s);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// One block: the mean of y from its partials (ypart[0..GUESS_BLOCKS)) into
+// ypart[GUESS_BLOCKS], and the gain g of the correction: gain_in[0], or,
+// with the last step's gain partials given, that step's least-squares gain
+// g + sum c (x - x0) / sum c^2 clamped to [0, 1]; written to gain_out[0]
+// and to gain_pub[0] (pinned host memory, for the step's statistics).
+__global__ __launch_bounds__(256) void k_guess_scalars(double* __restrict__ ypart, long long P,
+                                                       const double* __restrict__ gain_in,
+                                                       const double* __restrict__ gpart,
+                                                       double* __restrict__ gain_out, double* gain_pub) {
+  __shared__ double r[256];
+  double s = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int k = threadIdx.x; k < GUESS_BLOCKS; k += 256) s += ypart[k];
+  if (gpart)
+    for (int k = threadIdx.x; k < GUESS_BLOCKS; k += 256) {
+      s1 += gpart[2 * k];
+      s2 += gpart[2 * k + 1];
+    }
+  const double t = guess_tree(r, s);
+  const double t1 = guess_tree(r, s1);
+  const double t2 = guess_tree(r, s2);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = r1[0];
-    part[2 * blockIdx.x + 1] = r2[0];
+    double g = gain_in[0];
+    if (gpart && t2 > 0.0) g = fmin(1.0, fmax(0.0, g + t1 / t2));
+    ypart[GUESS_BLOCKS] = t / (double)P;
+    gain_out[0] = g;
+    gain_pub[0] = g;
+    __threadfence_system();
   }
 }
 
 // Learned initial guess: x0 = u^n + rho (u^n - u^{n-1}) + g c with the
 // correction c = so (y - mean(y)), projected to zero mean so that x0 keeps
 // the mass of the extrapolation (the solve preserves the mean of its
-// initial guess), and its gain g: gain_in[0], or, when the previous step's
-// gain partials are given (ngp blocks of k_gain_partials), that step's
-// least-squares gain clamped to [0, 1]; written to gain_out[0] and to
-// gain_pub[0] (pinned host memory, for the step's statistics).  c is kept
-// (float) in c_out for the next step's gain.  Launched with 256 threads per
-// block; every block forms the mean and the gain from the partial sums in
-// the same fixed order (whole block, then a tree).
+// initial guess); mean and g from k_guess_scalars.  c is kept (float) in
+// c_out for the next step's gain.
 __global__ __launch_bounds__(256) void k_learned_guess(const double* __restrict__ un,
                                                        const double* __restrict__ unm1, double rho, double so,
                                                        const float* __restrict__ y,
-                                                       const double* __restrict__ part, int nparts, long long n,
-                                                       double* __restrict__ x0, float* __restrict__ c_out,
-                                                       const double* __restrict__ gain_in,
-                                                       double* __restrict__ gain_out, double* gain_pub,
-                                                       const double* __restrict__ gpart, int ngp) {
-  __shared__ double red[256], red2[256];
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nparts; k += 256) s += part[k];
-  red[threadIdx.x] = s;
-  double s1 = 0.0, s2 = 0.0;
-  for (int k = threadIdx.x; k < ngp; k += 256) {
-    s1 += gpart[2 * k];
-    s2 += gpart[2 * k + 1];
-  }
-  __shared__ double red1[256];
-  red1[threadIdx.x] = s1;
-  red2[threadIdx.x] = s2;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      red[threadIdx.x] += red[threadIdx.x + o];
-      red1[threadIdx.x] += red1[threadIdx.x + o];
-      red2[threadIdx.x] += red2[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
-  const double mean = red[0] / (double)n;
-  double g = gain_in[0];
-  if (ngp > 0 && red2[0] > 0.0) g = fmin(1.0, fmax(0.0, g + red1[0] / red2[0]));
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    gain_out[0] = g;
-    gain_pub[0] = g;
-    __threadfence_system();
-  }
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
-    const double u = un[p];
-    const double c = so * ((double)y[p] - mean);
-    x0[p] = u + rho * (u - unm1[p]) + g * c;
-    c_out[p] = (float)c;
+                                                       const double* __restrict__ mean_p,
+                                                       const double* __restrict__ gain_p, long long P,
+                                                       double* __restrict__ x0, float* __restrict__ c_out) {
+  const double mean = mean_p[0], g = gain_p[0];
+  const long long h = P >> 1;
+  const double2* __restrict__ a2 = reinterpret_cast<const double2*>(un);
+  const double2* __restrict__ b2 = reinterpret_cast<const double2*>(unm1);
+  const float2* __restrict__ y2 = reinterpret_cast<const float2*>(y);
+  double2* __restrict__ o2 = reinterpret_cast<double2*>(x0);
+  float2* __restrict__ c2v = reinterpret_cast<float2*>(c_out);
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < h;
+       q += (long long)gridDim.x * blockDim.x) {
+    const double2 a = a2[q], b = b2[q];
+    const float2 yv = y2[q];
+    const double c0 = so * ((double)yv.x - mean), c1 = so * ((double)yv.y - mean);
+    o2[q] = make_double2(a.x + rho * (a.x - b.x) + g * c0, a.y + rho * (a.y - b.y) + g * c1);
+    c2v[q] = make_float2((float)c0, (float)c1);
   }
 }
 
@@ -471,7 +509,7 @@ inline long long fno_count(long long W, long long M, long long L, int ndim = 2) 
   return 2 * W + W + L * (W * W * fno_modes(M, ndim) * 2 + W * W + W) + W + 1;
 }
 
-constexpr int FNO_LOSS_BLOCKS = 256, FNO_SUM_BLOCKS = 256;
+constexpr int FNO_LOSS_BLOCKS = 256;
 
 // Launches k_gemm; an M beyond the grid's y extent (65535 tiles) is split
 // into row chunks, each a launch on offset A and C.

@@ -264,9 +264,9 @@ struct Instance {
   Resampler* fno_rs = nullptr;  // its resampler when the network's grid is coarser (owned by the network)
   double fno_norm[4] = {0, 1, 1, 1};
   double* xguess = nullptr;  // learned guess buffer (allocated on first attach)
-  double* gpart = nullptr;   // FNO_SUM_BLOCKS partial sums of the network output
+  double* gpart = nullptr;   // GUESS_BLOCKS partial sums of the network output, then its mean
   // gain of the learned correction: gbuf[0..1] the gain (read one, written
-  // the other, gain_par the one to read), then 2 FNO_SUM_BLOCKS partials;
+  // the other, gain_par the one to read), then 2 GUESS_BLOCKS partials;
   // gcor the last guess's correction; gain_ready: the last step took its
   // learned guess and was accepted, so the next guess can update the gain
   double* gbuf = nullptr;
@@ -1045,6 +1045,7 @@ int learned_guesses(pfch_ctx* ctx, const std::vector<int>& ids, const std::vecto
     std::stable_sort(chunk.begin(), chunk.end(), [&](size_t x, size_t y) {
       return (uintptr_t)ctx->inst[ids[x]].fno_rs < (uintptr_t)ctx->inst[ids[y]].fno_rs;
     });
+    std::vector<char> gain_from(chunk.size(), 0);  // slot k: the gain from its last step's partials
     // runs[r] = (first slot, count) of instances sharing one resampler (or none)
     std::vector<std::pair<size_t, size_t>> runs;
     for (size_t k = 0; k < chunk.size(); ++k)
@@ -1060,9 +1061,15 @@ int learned_guesses(pfch_ctx* ctx, const std::vector<int>& ids, const std::vecto
         const double* nrm = I.fno_norm;
         const long long P = I.npts;
         float* dst = R ? R->Xf + (long long)j * 2 * P : F.xin + (long long)k * 2 * F.P;
-        hipLaunchKernelGGL(k_fno_inputs, dim3(blocks_for(P)), dim3(256), 0, s, I.U[1 - I.ucur], I.U[I.ucur],
-                           (const double*)nullptr, P, rho[chunk[k]], nrm[0], nrm[1], nrm[2], nrm[3], dst,
-                           (float*)nullptr);
+        // with the inputs, the previous step's guess (still in xguess) against
+        // the solution it reached (now u^n): partials of that step's gain
+        const bool gp = I.gain_ready;
+        gain_from[k] = gp ? 1 : 0;
+        I.gain_ready = false;
+        hipLaunchKernelGGL(k_guess_inputs, dim3(GUESS_BLOCKS), dim3(256), 0, s, (const double*)I.U[1 - I.ucur],
+                           (const double*)I.U[I.ucur], P, nrm[0], nrm[1], nrm[2], dst,
+                           gp ? (const double*)I.xguess : nullptr, gp ? (const float*)I.gcor : nullptr,
+                           I.gbuf + 2);
       }
       if (R && resample_down(F, *R, R->Xf, 2, F.xin + (long long)run.first * 2 * F.P, (int)run.second, s) !=
                    hipSuccess)
@@ -1083,21 +1090,14 @@ int learned_guesses(pfch_ctx* ctx, const std::vector<int>& ids, const std::vecto
         while (first > 0 && ctx->inst[ids[chunk[first - 1]]].fno_rs == I.fno_rs) --first;
         y = I.fno_rs->yf + (long long)(k - first) * P;
       }
-      hipLaunchKernelGGL(k_partial_sum, dim3(FNO_SUM_BLOCKS), dim3(256), 0, s, y, P, I.gpart);
-      // the previous step's guess (still in xguess) against the solution it
-      // reached (now u^n): the gain of this step's correction
-      int ngp = 0;
-      if (I.gain_ready) {
-        hipLaunchKernelGGL(k_gain_partials, dim3(FNO_SUM_BLOCKS), dim3(256), 0, s, (const double*)I.xguess,
-                           (const double*)I.U[I.ucur], (const float*)I.gcor, P, I.gbuf + 2);
-        ngp = FNO_SUM_BLOCKS;
-        I.gain_ready = false;
-      }
-      hipLaunchKernelGGL(k_learned_guess, dim3(std::min(blocks_for(P), 4096u)), dim3(256), 0, s,
-                         (const double*)I.U[I.ucur],
-                         (const double*)I.U[1 - I.ucur], rho[chunk[k]], I.fno_norm[3], y, (const double*)I.gpart,
-                         FNO_SUM_BLOCKS, P, I.xguess, I.gcor, (const double*)I.gbuf + I.gain_par,
-                         I.gbuf + (1 - I.gain_par), ctx->d_gain + ids[chunk[k]], (const double*)I.gbuf + 2, ngp);
+      hipLaunchKernelGGL(k_guess_ysum, dim3(GUESS_BLOCKS), dim3(256), 0, s, y, P, I.gpart);
+      hipLaunchKernelGGL(k_guess_scalars, dim3(1), dim3(256), 0, s, I.gpart, P, (const double*)I.gbuf + I.gain_par,
+                         gain_from[k] ? (const double*)I.gbuf + 2 : nullptr, I.gbuf + (1 - I.gain_par),
+                         ctx->d_gain + ids[chunk[k]]);
+      hipLaunchKernelGGL(k_learned_guess, dim3(std::min(blocks_for(P / 2), 4096u)), dim3(256), 0, s,
+                         (const double*)I.U[I.ucur], (const double*)I.U[1 - I.ucur], rho[chunk[k]], I.fno_norm[3],
+                         y, (const double*)I.gpart + GUESS_BLOCKS, (const double*)I.gbuf + (1 - I.gain_par), P,
+                         I.xguess, I.gcor);
       I.gain_par ^= 1;
     }
     HIPCHK(hipGetLastError());
@@ -3188,9 +3188,9 @@ int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4])
     void* q = nullptr;
     if ((rc = dalloc(I.allocs, &q, sizeof(double) * (size_t)I.npts))) return rc;
     I.xguess = (double*)q;
-    if ((rc = dalloc(I.allocs, &q, sizeof(double) * FNO_SUM_BLOCKS))) return rc;
+    if ((rc = dalloc(I.allocs, &q, sizeof(double) * (GUESS_BLOCKS + 1)))) return rc;
     I.gpart = (double*)q;
-    if ((rc = dalloc(I.allocs, &q, sizeof(double) * (2 + 2 * FNO_SUM_BLOCKS)))) return rc;
+    if ((rc = dalloc(I.allocs, &q, sizeof(double) * (2 + 2 * GUESS_BLOCKS)))) return rc;
     I.gbuf = (double*)q;
     if ((rc = dalloc(I.allocs, &q, sizeof(float) * (size_t)I.npts))) return rc;
     I.gcor = (float*)q;
