@@ -309,8 +309,9 @@ def test_network_grid_must_match_instance():
 def test_trained_network_gains_over_extrapolation():
     """Trained on solver trajectories (PFC 64^2, MP), the network's guess is
     closer to the converged u^{n+1} than the extrapolated guess on states it
-    was not trained on, and the learned step converges to the plain step's
-    solution within the tolerance."""
+    was not trained on, and the learned steps from those states converge to
+    the plain steps' solutions within the tolerance in fewer PAGD iterations
+    in total."""
     import torch
     from paper_2204_07247_amd import learned, pfch
     base = W.PFC64_MP
@@ -338,13 +339,19 @@ def test_trained_network_gains_over_extrapolation():
         assert abs(float(guess.mean() - extrap.mean())) <= 1e-14
     print(f"guess error, extrapolated / learned: {gains}", flush=True)
     assert min(gains) > 1.5, gains
-    # the learned step itself: converged, and within the tolerance of the plain step
-    un, unm1, dtp, k = states[12].clone(), states[11].clone(), w.dt, 12
-    rc_p, st_p, plain = _one_step(w, un, unm1, dtp, k)
-    rc_l, st_l, got = _one_step(w, un, unm1, dtp, k, fno=tr.fno, norm=tr.norm, guess=1)
-    assert rc_p == pfch.PFCH_OK and rc_l == pfch.PFCH_OK and st_l["guess"] == 1
-    assert np.max(np.abs(got - plain)) <= 1e-9
-    print(f"iterations plain {st_p['iters']}, learned {st_l['iters']}", flush=True)
+    # the learned steps themselves: converged, within the tolerance of the
+    # plain steps, and in fewer PAGD iterations over the held-out states
+    its_p, its_l = [], []
+    for n in range(10, 13):
+        un, unm1, dtp = states[n].clone(), states[n - 1].clone(), w.dt
+        rc_p, st_p, plain = _one_step(w, un, unm1, dtp, n)
+        rc_l, st_l, got = _one_step(w, un, unm1, dtp, n, fno=tr.fno, norm=tr.norm, guess=1)
+        assert rc_p == pfch.PFCH_OK and rc_l == pfch.PFCH_OK and st_l["guess"] == 1
+        assert np.max(np.abs(got - plain)) <= 1e-9
+        its_p.append(st_p["iters"])
+        its_l.append(st_l["iters"])
+    print(f"iterations plain {its_p}, learned {its_l}", flush=True)
+    assert sum(its_l) < sum(its_p), (its_p, its_l)
     tr.fno.close()
 
 
