@@ -25,7 +25,8 @@ Each times `--steps` bench steps (default: the configuration's 300) from the
 initial conditions, bracketed by torch.cuda.synchronize(), after `--warmup`
 untimed steps whose states are discarded.  Also reported: PAGD iterations per step, the HBM
 roofline of the FCH 2048^2 iteration (HIP events on the grouped launches),
-and the CPU oracle on the host's cores.
+the CPU oracle on the host's cores, and the paper's own timings as context
+(its hardware is not stated).
 
 Prints one JSON line.  --workload names a single-instance workload instead;
 --extras adds the other comparisons (PFC ensemble, learned guess on PFC,
@@ -81,6 +82,41 @@ KERNEL_NAMES = {"row": "k_row_iter", "col": "k_col_iter", "yfwd": "k_y3_iter<fwd
 # algorithmic_bytes); the roofline is quoted against these figures.
 SCHEDULE_BYTES = {("fch", "bdf2", 2): 160, ("fch", "mp", 2): 176, ("pfc", "bdf2", 2): 104,
                   ("pfc", "mp", 2): 120, ("pfc", "bdf2", 3): 136}
+
+
+# Transform pairs per PAGD iteration (one forward and one inverse transform
+# of a real field count as one pair): PFC 2 forward + 1 inverse, FCH 3 + 2.
+PAIRS_PER_ITER = {"pfc": 1.5, "fch": 2.5}
+
+# The paper's own timings, as context only: its benchmark table of the PAGD
+# solved MP and BDF2 runs (Table tab:expbenchmark_csv) gives FFT pairs and
+# wall-clock seconds per adaptive run; its hardware, FFT library and thread
+# count are not stated (CPU time is 5-10 times the wall time: a multicore
+# CPU).  Rates below are pairs / wall second, and grid points x pairs /
+# wall second.
+PAPER_RUNS = [  # (problem, scheme, N per axis, FFT pairs, wall s)
+    ("FCH1", "MP", 128, 43769, 14), ("FCH1", "BDF2", 128, 77385, 23),
+    ("FCH2", "MP", 256, 122049, 116), ("FCH2", "BDF2", 256, 106425, 90),
+    ("FCH3", "MP", 256, 113089, 112), ("FCH3", "BDF2", 256, 142293, 120),
+    ("PFC1", "MP", 512, 78289, 595), ("PFC1", "BDF2", 512, 82485, 437),
+    ("PFC2", "MP", 512, 25551, 77), ("PFC2", "BDF2", 512, 237792, 747),
+]
+
+
+def paper_context(point_pairs_per_s):
+    rates = [(p, sch, n, pairs / wall, n * n * pairs / wall) for p, sch, n, pairs, wall in PAPER_RUNS]
+    lo = min(r[4] for r in rates)
+    hi = max(r[4] for r in rates)
+    return dict(
+        source="the paper's benchmark table of PAGD-solved MP / BDF2 runs (Table tab:expbenchmark_csv)",
+        hardware="not stated (CPU time 5-10 x wall time: a multicore CPU)",
+        runs=[dict(problem=p, scheme=sch, grid=f"{n}^2", fft_pairs_per_s=round(r, 1),
+                   mpoint_pairs_per_s=round(q / 1e6, 1)) for p, sch, n, r, q in rates],
+        paper_mpoint_pairs_per_s=[round(lo / 1e6, 1), round(hi / 1e6, 1)],
+        unit_mpoint_pairs="10^6 grid points x transform pairs per wall second",
+        this_run_mpoint_pairs_per_s=round(point_pairs_per_s / 1e6, 1),
+        note="context, not a like-for-like comparison: other grids, problems and an adaptive step size there; "
+             "here the transform pairs of the PAGD iterations only")
 
 
 def algorithmic_bytes(w):
@@ -302,6 +338,7 @@ def run_set(ws, mode, steps, warmup, tr=None, time_groups=None):
     # over the wall time (set-ups, accepts and host round trips included)
     moved = sum(SCHEDULE_BYTES[(w.model, w.scheme, len(w.shape))] * w.npoints * sum(its[i])
                 for i, w in enumerate(ws))
+    pairs = sum(PAIRS_PER_ITER[w.model] * w.npoints * sum(its[i]) for i, w in enumerate(ws))
     groups = {}
     for w, p in zip(ws, per):
         key = f"{w.model}{'x'.join(map(str, w.shape))}"
@@ -310,7 +347,8 @@ def run_set(ws, mode, steps, warmup, tr=None, time_groups=None):
                ms_per_step=round(1e3 * el / steps, 3), iters_per_step=round(float(np.mean(per)), 3),
                iters_per_step_by_grid={k: round(float(np.mean(v)), 3) for k, v in groups.items()},
                contexts=len(ctxs), elapsed_s=round(el, 4),
-               effective_gbs=round(moved / el / 1e9, 1), effective_frac=round(moved / el / 1e9 / HBM_PEAK_GBS, 4))
+               effective_gbs=round(moved / el / 1e9, 1), effective_frac=round(moved / el / 1e9 / HBM_PEAK_GBS, 4),
+               point_pairs_per_s=round(pairs / el, 1))
     if use_net:
         out["learned_guess_instances"] = int(sum(guess))
         out["fallbacks"] = its["fallbacks"]
@@ -382,7 +420,7 @@ def combined_bench(args):
                "learned on the FCH instances, extrapolated on the 3D instance")
     return dict(value=head["time_steps_per_s"], ms_per_step=head["ms_per_step"], config=cfg,
                 iters_per_step=head["iters_per_step"], variants=variants, roofline=roof, kernels=kernels,
-                learned_network=net_info)
+                learned_network=net_info, paper_context=paper_context(head["point_pairs_per_s"]))
 
 
 # ---------------------------------------------------------------------------
@@ -455,7 +493,8 @@ def single_bench(args, w):
     return dict(value=round(args.steps / elapsed, 3), ms_per_step=round(1e3 * elapsed / args.steps, 4),
                 config=cfg,
                 iters_per_step=dict(mean=round(float(it.mean()), 3), min=int(it.min()), max=int(it.max())),
-                roofline=roof, kernels=kernels)
+                roofline=roof, kernels=kernels,
+                paper_context=paper_context(PAIRS_PER_ITER[w.model] * w.npoints * float(it.sum()) / elapsed))
 
 
 # ---------------------------------------------------------------------------
@@ -537,7 +576,7 @@ def solver_variants(w, steps):
     import torch
     from paper_2204_07247_amd import pfch
     u0 = torch.from_numpy(W.initial_condition(w)).cuda()
-    fft_pairs = {"pfc": 1.5, "fch": 2.5}[w.model]
+    fft_pairs = PAIRS_PER_ITER[w.model]
     variants = [("pagd_sweep", {}), ("pgd", dict(etas=()))]
     variants += [(f"pagd_eta{e * e:g}", dict(etas=(e,))) for e in w.etas]
     imex = "lbdf2" if w.scheme == "bdf2" else "lmp"
