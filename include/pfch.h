@@ -95,8 +95,10 @@ typedef struct pfch_stats {
                        solution x (the residual of the step problem, without
                        the preconditioner); NaN unless statistics detail 2 was
                        set and the solve converged; NaN for the IMEX schemes */
-  double gain;      /* gain g of the learned correction this step's guess
-                       used (see pfch_set_fno); NaN unless guess is 1 */
+  double gain;      /* gain g of the learned correction fitted for this
+                       step's guess (used if at least 0.98, else the
+                       correction is left out; see pfch_set_fno); NaN unless
+                       guess is 1 */
   int32_t iters;    /* PAGD iterations */
   int32_t fft_pairs;/* 2D transform pairs of real fields used (setup + iterations) */
   int32_t status;   /* PFCH_OK or the error of this instance */
@@ -296,7 +298,16 @@ int pfch_get_launch_config(pfch_ctx* ctx, int32_t inst, int64_t out[6]);
  * guess and accepted the solution x it reached, the least-squares gain of
  * that step's correction c = so Pi_0 y against x - (u^n + rho (u^n -
  * u^{n-1})), clamped to [0, 1], is the next guess's g (steps of
- * pfch_step_adaptive leave g as it is).  PAGD still iterates to
+ * pfch_step_adaptive leave g as it is); a fitted gain below 0.98 (the
+ * correction over-predicts the solutions) is applied as 0, the correction
+ * left out.  pfch_stats.gain reports the fitted gain.  Gate: when a
+ * pfch_step fitted a gain below 0.98, or when its learned guess was
+ * replaced (guess 2), the instance takes the extrapolated guess, with no
+ * network call, for the next 16 << min(f, 3) accepted fixed-size steps
+ * (f: probes in a row that closed the gate again); then two probe steps
+ * use the network again (the first with gain 0, the second with the gain
+ * fitted to the first, which reopens or closes the gate).  pfch_set_state
+ * and pfch_set_fno open the gate.  PAGD still iterates to
  * ||d||_inf < tol from this guess, so the
  * solution differs from the extrapolated-guess solution only within that
  * tolerance; a guess from which the solve fails is replaced by the

@@ -405,13 +405,18 @@ __global__ __launch_bounds__(256) void k_guess_ysum(const float* __restrict__ y,
 }
 
 // One block: the mean of y from its partials (ypart[0..GUESS_BLOCKS)) into
-// ypart[GUESS_BLOCKS], and the gain g of the correction: gain_in[0], or,
-// with the last step's gain partials given, that step's least-squares gain
-// g + sum c (x - x0) / sum c^2 clamped to [0, 1]; written to gain_out[0]
-// and to gain_pub[0] (pinned host memory, for the step's statistics).
+// ypart[GUESS_BLOCKS], and the gain of the correction.  Without the last
+// step's gain partials the gain is gain_in[0] (the gain the last guess
+// used).  With them, the fitted gain is that step's least-squares gain
+// gf = g + sum c (x - x0) / sum c^2 clamped to [0, 1] (g the gain the last
+// guess used: gf is the gain of the last correction against x - e whatever
+// g was), and the gain used is gf if gf >= gate, else 0 (the correction is
+// left out).  The gain used goes to gain_out[0]; the fitted gain (or
+// gain_in[0]) to gain_pub[0] (pinned host memory, for the statistics and
+// the host's gate).
 __global__ __launch_bounds__(256) void k_guess_scalars(double* __restrict__ ypart, long long P,
                                                        const double* __restrict__ gain_in,
-                                                       const double* __restrict__ gpart,
+                                                       const double* __restrict__ gpart, double gate,
                                                        double* __restrict__ gain_out, double* gain_pub) {
   __shared__ double r[256];
   double s = 0.0, s1 = 0.0, s2 = 0.0;
@@ -425,11 +430,14 @@ __global__ __launch_bounds__(256) void k_guess_scalars(double* __restrict__ ypar
   const double t1 = guess_tree(r, s1);
   const double t2 = guess_tree(r, s2);
   if (threadIdx.x == 0) {
-    double g = gain_in[0];
-    if (gpart && t2 > 0.0) g = fmin(1.0, fmax(0.0, g + t1 / t2));
+    double g = gain_in[0], gf = g;
+    if (gpart && t2 > 0.0) {
+      gf = fmin(1.0, fmax(0.0, g + t1 / t2));
+      g = gf >= gate ? gf : 0.0;
+    }
     ypart[GUESS_BLOCKS] = t / (double)P;
     gain_out[0] = g;
-    gain_pub[0] = g;
+    gain_pub[0] = gf;
     __threadfence_system();
   }
 }

@@ -273,6 +273,13 @@ struct Instance {
   float* gcor = nullptr;
   int gain_par = 0;
   bool gain_ready = false;
+  bool gain_fresh = false;  // the last learned guess's gain came from its previous step's partials
+  // gate of the learned guess: while off, steps take the extrapolated guess
+  // (no network call) and lg_wait counts the steps to the next probe
+  bool lg_off = false;
+  int lg_wait = 0;
+  int lg_probe = 0;  // learned steps left in a probe of the network
+  int lg_fails = 0;  // probes in a row that closed the gate again
   // adaptive stepping (buffers allocated on first use)
   double* Um2 = nullptr;     // u^{n-2}
   double* R[3] = {nullptr, nullptr, nullptr};  // R(u^n), R(u^{n-1}), R(u~)
@@ -1008,11 +1015,30 @@ int betas_host(pfch_ctx* ctx, Instance& I, double a, double out[4]) {
   return PFCH_OK;
 }
 
+// Gate of the learned guess.  The network's correction is used while the
+// least-squares gain fitted to it on the step before stays at LG_GAIN_ON or
+// above; a lower gain means the correction has stopped predicting the
+// solutions (it over-predicts them), and measured iteration counts rise
+// then even with the correction scaled down by the gain.  Such a step
+// leaves the correction out (gain 0, on the device), and the instance then
+// takes the extrapolated guess (the paper's, with no network call) for
+// LG_PROBE_AFTER << min(failed probes, 3) fixed-size steps before it probes
+// the network again: the first probe step adds the correction with gain 0
+// (its guess is the extrapolation), the second the gain fitted to the
+// first if that reaches LG_GAIN_ON, which also decides the gate.
+constexpr double LG_GAIN_ON = 0.98;
+constexpr int LG_PROBE_AFTER = 16;
+
 // The gain of an instance's learned correction back to 1 (after a new
-// history or network).
+// history or network), the gate open.
 int reset_gain(pfch_ctx* ctx, Instance& I) {
   static const double one[2] = {1.0, 1.0};
   I.gain_ready = false;
+  I.gain_fresh = false;
+  I.lg_off = false;
+  I.lg_wait = 0;
+  I.lg_probe = 0;
+  I.lg_fails = 0;
   I.gain_par = 0;
   if (I.gbuf) HIPCHK(hipMemcpyAsync(I.gbuf, one, sizeof(one), hipMemcpyHostToDevice, ctx->stream));
   return PFCH_OK;
@@ -1066,6 +1092,7 @@ int learned_guesses(pfch_ctx* ctx, const std::vector<int>& ids, const std::vecto
         const bool gp = I.gain_ready;
         gain_from[k] = gp ? 1 : 0;
         I.gain_ready = false;
+        I.gain_fresh = gp;
         hipLaunchKernelGGL(k_guess_inputs, dim3(GUESS_BLOCKS), dim3(256), 0, s, (const double*)I.U[1 - I.ucur],
                            (const double*)I.U[I.ucur], P, nrm[0], nrm[1], nrm[2], dst,
                            gp ? (const double*)I.xguess : nullptr, gp ? (const float*)I.gcor : nullptr,
@@ -1092,7 +1119,7 @@ int learned_guesses(pfch_ctx* ctx, const std::vector<int>& ids, const std::vecto
       }
       hipLaunchKernelGGL(k_guess_ysum, dim3(GUESS_BLOCKS), dim3(256), 0, s, y, P, I.gpart);
       hipLaunchKernelGGL(k_guess_scalars, dim3(1), dim3(256), 0, s, I.gpart, P, (const double*)I.gbuf + I.gain_par,
-                         gain_from[k] ? (const double*)I.gbuf + 2 : nullptr, I.gbuf + (1 - I.gain_par),
+                         gain_from[k] ? (const double*)I.gbuf + 2 : nullptr, LG_GAIN_ON, I.gbuf + (1 - I.gain_par),
                          ctx->d_gain + ids[chunk[k]]);
       hipLaunchKernelGGL(k_learned_guess, dim3(std::min(blocks_for(P / 2), 4096u)), dim3(256), 0, s,
                          (const double*)I.U[I.ucur], (const double*)I.U[1 - I.ucur], rho[chunk[k]], I.fno_norm[3],
@@ -2203,7 +2230,7 @@ int launch_step_setups(pfch_ctx* ctx, const double* dt, SolveOut& o, bool accept
   std::vector<double> lrho;
   for (int i = 0; i < n; ++i) {
     const Instance& I = ctx->inst[i];
-    if (I.fno && I.d.guess == 1 && I.has_prev) {
+    if (I.fno && I.d.guess == 1 && I.has_prev && !I.lg_off) {
       lids.push_back(i);
       lrho.push_back(step_setup_for(I, dt[i]).rho);
       o.guess[i] = 1;
@@ -2589,6 +2616,28 @@ int pfch_step(pfch_ctx* ctx, const double* dt, pfch_stats* st) {
   // the next learned guess may take this step's gain (learned guess taken
   // and accepted)
   for (int i = 0; i < n; ++i) ctx->inst[i].gain_ready = ctx->inst[i].gbuf && o.guess[i] == 1 && take[i];
+  // the gate: a learned step whose gain was fitted to the step before it
+  // closes it below LG_GAIN_ON (the gain is in pinned memory, written before
+  // the solve that the host has waited for); closed, accepted steps count
+  // down to the next probe
+  for (int i = 0; i < n; ++i) {
+    Instance& I = ctx->inst[i];
+    if (!take[i] || !I.fno || I.d.guess != 1) continue;
+    const bool fitted = o.guess[i] == 1 && I.gain_fresh;
+    if (o.guess[i] == 2 || (fitted && !(ctx->h_gain[i] >= LG_GAIN_ON))) {
+      // (guess 2: the learned guess did not lead to convergence)
+      if (I.lg_probe > 0) ++I.lg_fails;
+      I.lg_off = true;
+      I.lg_wait = LG_PROBE_AFTER << std::min(I.lg_fails, 3);
+      I.lg_probe = 0;
+    } else if (o.guess[i] == 1) {
+      if (fitted) I.lg_fails = 0;
+      if (I.lg_probe > 0) --I.lg_probe;
+    } else if (o.guess[i] == 0 && I.lg_off && --I.lg_wait <= 0) {
+      I.lg_off = false;
+      I.lg_probe = 2;
+    }
+  }
   const bool speculate = same_dt && first_err == PFCH_OK;
   ctx->last_dt.assign(dt, dt + n);
   if (speculate) {

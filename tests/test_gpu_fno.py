@@ -268,6 +268,58 @@ def test_learned_gain_is_the_last_steps_least_squares_gain():
     fno.close()
 
 
+def test_learned_gate_closes_below_the_gain_bound_and_probes():
+    """A learned step whose fitted gain is below 0.98 leaves the correction
+    out and closes the gate: the next 16 steps take the extrapolated guess
+    (no gain reported), then two probe steps take the network again (the
+    first adds its correction with gain 0, so that its solution is that of
+    the extrapolated guess within the tolerance; the second reports the
+    gain fitted to the first), and a probe gain below the bound closes the
+    gate again for twice as long; pfch_set_state opens it."""
+    import math
+
+    import torch
+    from paper_2204_07247_amd import pfch
+    w = dataclasses.replace(W.FCH256_BDF2, shape=(64, 64), seeds=(1,))
+    un, unm1, dtp, k = _history(w, 3)
+    fno = pfch.Fno(8, 4, 2, *w.shape)
+    rng = np.random.default_rng(11)
+    fno.set_params(torch.from_numpy(rng.normal(0.0, 0.3, fno.n_params).astype(np.float32)).cuda())
+    u = un.cpu().numpy()
+    du = (un - unm1).cpu().numpy()
+    norm = [float(u.mean()), float(u.std()), float(du.std()), 1.0]
+    X = torch.empty((1, 2) + tuple(w.shape), dtype=torch.float32, device="cuda")
+    fno.prepare(unm1, un, None, 1.0, norm, X[0])
+    y = fno.forward(X)[0].double().cpu().numpy()
+    # a correction five times the largest |u^n - u^{n-1}|: fitted gains far below 0.98
+    norm[3] = 5.0 * float(np.abs(du).max()) / float(np.abs(y - y.mean()).max())
+    d = desc_for(w)
+    d.guess = 1
+    ctx = pfch.Context([d])
+    ctx.set_state(0, un, unm1, t=0.0, dt_prev=dtp, step_index=k)
+    ctx.set_fno(0, fno, norm)
+    kinds = []
+    gains = []
+    for _ in range(2 + 16 + 2 + 32 + 2 + 1):
+        rc, st = ctx.step(w.dt)
+        assert rc == pfch.PFCH_OK
+        kinds.append(st[0]["guess"])
+        gains.append(st[0]["gain"])
+    print(f"guess kinds {kinds}, gains {[round(g, 4) for g in gains]}", flush=True)
+    assert kinds == [1, 1] + [0] * 16 + [1, 1] + [0] * 32 + [1, 1] + [0]
+    assert gains[0] == 1.0 and gains[1] < 0.98
+    off = gains[2:18] + gains[20:52] + gains[54:]
+    assert all(math.isnan(g) for g in off)
+    assert gains[18] == 0.0 and gains[52] == 0.0  # first probe steps: the correction with gain 0
+    assert gains[19] < 0.98 and gains[53] < 0.98
+    # a new history opens the gate
+    ctx.set_state(0, un, unm1, t=0.0, dt_prev=dtp, step_index=k)
+    rc, st = ctx.step(w.dt)
+    assert rc == pfch.PFCH_OK and st[0]["guess"] == 1 and st[0]["gain"] == 1.0
+    ctx.close()
+    fno.close()
+
+
 def test_failed_learned_guess_falls_back_to_extrapolation():
     """A guess from which the solve fails (here: non-finite residual) is
     replaced by the extrapolated guess; the step then equals the plain step
@@ -437,7 +489,8 @@ def test_coarse_network_must_fit_the_instance_grid():
 def test_batched_learned_guesses_match_solo():
     """Instances that share a network get their learned guesses from one
     batched forward pass: each equals its run alone (the network's products
-    do not depend on the batch size), bit for bit."""
+    do not depend on the batch size), bit for bit, with the same iteration
+    counts and guess kinds step by step."""
     import torch
     from paper_2204_07247_amd import pfch
     w = dataclasses.replace(W.FCH256_BDF2, shape=(64, 64), lengths=(np.pi, np.pi))
@@ -458,11 +511,12 @@ def test_batched_learned_guesses_match_solo():
             d = un - unm1
             ctx.set_fno(k, fno, (float(un.mean()), float(un.std()), float(d.std()), 0.1 * float(d.std())))
         its = []
-        for _ in range(3):
+        for step in range(3):
             rc, st = ctx.step(w.dt)
             assert rc == pfch.PFCH_OK
-            assert all(s["guess"] == 1 for s in st)
-            its.append([s["iters"] for s in st])
+            if step < 2:  # (an untrained network may close the gate after its fitted gain)
+                assert all(s["guess"] == 1 for s in st)
+            its.append([(s["iters"], s["guess"]) for s in st])
         out = []
         for k in range(len(idx)):
             o = torch.empty_like(u0[0])
