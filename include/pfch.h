@@ -396,9 +396,10 @@ void pfch_fno_destroy(pfch_fno* f);
  * interpolated back with the same band (modes |k| < Nc/2 of the network's
  * grid, zero beyond), so the learned correction holds those modes only.
  * norm = {mu, su, sd, so}, su, sd, so > 0; the gain of the correction is
- * set to 1.  The network is not owned; it must outlive its use and must not
- * be used on another stream while the context steps.  PFCH_E_INVAL for a
- * grid that fits neither case. */
+ * set to 1 and its gate opened.  The network is not owned; it must outlive
+ * its use and must not be used on another stream while the context steps.
+ * PFCH_E_INVAL for a grid that fits neither case; PFCH_E_UNSUPPORTED for an
+ * instance with an odd number of grid points (no supported grid has one). */
 int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4]);
 
 /* Transform plans and launch geometry of the iteration kernels of instance

@@ -3224,6 +3224,7 @@ int pfch_set_fno(pfch_ctx* ctx, int32_t inst, pfch_fno* f, const double norm[4])
   }
   if (!norm || !(norm[1] > 0.0) || !(norm[2] > 0.0) || !(norm[3] > 0.0) || !std::isfinite(norm[0]))
     return PFCH_E_INVAL;
+  if (I.npts & 1) return PFCH_E_UNSUPPORTED;  // the guess kernels read two points per lane
   int rc;
   Resampler* R = nullptr;
   if (f->f.nz != I.nz || f->f.ny != I.ny || f->f.nx != I.nx) {
