@@ -872,6 +872,62 @@ def extras(args):
     return out
 
 
+def per_step_comparison(args):
+    """The 16 FCH instances of the combined set in one context, extrapolated
+    against learned guess (the bench's network, with its gain and gate), over
+    the configuration's steps: per block of 20 steps the mean PAGD iterations
+    of the 1024^2 and 2048^2 instances both ways, the mean fitted gain of the
+    steps that ran the network, and the share of instance-steps that ran it."""
+    import torch
+    from paper_2204_07247_amd import learned, pfch
+    ws = [w for w in combined_set() if len(w.shape) == 2]
+    steps = args.steps or COMBINED_STEPS
+    tr, _ = train_fch_network(args.learned_epochs)
+    u = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    its, gains = {}, None
+    for mode in ("plain", "learned"):
+        g = 1 if mode == "learned" else 0
+        ctx = pfch.Context([learned.desc_of(w, g) for w in ws])
+        ctx.set_stats_detail(0)
+        for k in range(len(ws)):
+            ctx.set_state(k, u[k])
+            if g:
+                ctx.set_fno(k, tr.fno, tr.norm)
+        it = np.zeros((len(ws), steps))
+        gn = np.full((len(ws), steps), np.nan)
+        log(f"[bench] per-step {mode}: {len(ws)} instances, {steps} steps")
+        for n in range(steps):
+            rc, st = ctx.step([w.dt for w in ws])
+            if rc != pfch.PFCH_OK:
+                raise RuntimeError(f"per-step {mode}: {pfch.strerror(rc)}")
+            for k in range(len(ws)):
+                it[k, n] = st[k]["iters"]
+                if st[k]["guess"] == 1:
+                    gn[k, n] = st[k]["gain"]
+        ctx.close()
+        its[mode] = it
+        if g:
+            gains = gn
+    tr.fno.close()
+    by = {s: [i for i, w in enumerate(ws) if w.shape == (s, s)] for s in (1024, 2048)}
+    blocks = []
+    for a in range(0, steps, 20):
+        sl = slice(a, min(a + 20, steps))
+        blk = dict(steps=f"{a + 1}-{min(a + 20, steps)}")
+        for s, idx in by.items():
+            blk[f"fch{s}"] = [round(float(its["plain"][idx, sl].mean()), 2),
+                              round(float(its["learned"][idx, sl].mean()), 2)]
+        used = ~np.isnan(gains[:, sl])
+        blk["network_share"] = round(float(used.mean()), 3)
+        blk["mean_fitted_gain"] = round(float(np.nanmean(gains[:, sl])), 3) if used.any() else None
+        blocks.append(blk)
+    return dict(workload=COMBINED + " (its 16 FCH instances, one context)", steps=steps,
+                iters_per_step=dict(plain=round(float(its["plain"].mean()), 3),
+                                    learned=round(float(its["learned"].mean()), 3)),
+                network_share=round(float((~np.isnan(gains)).mean()), 3),
+                blocks_plain_vs_learned=blocks)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -885,6 +941,9 @@ def main():
                     help="seconds of oracle work for a single-instance workload")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also run the other comparisons")
+    ap.add_argument("--per-step", action="store_true",
+                    help="instead of the bench: per-step iterations of the combined set's FCH instances, "
+                         "extrapolated vs learned guess")
     ap.add_argument("--no-learned", action="store_true",
                     help="combined set: no network (headline = batched; counter runs)")
     ap.add_argument("--only", choices=["plain", "batched", "learned"],
@@ -907,6 +966,11 @@ def main():
               "device; independent instances would shard across GPUs with no communication, "
               "which is not implemented", file=sys.stderr)
         sys.exit(2)
+    if args.per_step:
+        if args.tune_file and "PFCH_TUNE_FILE" not in os.environ:
+            os.environ["PFCH_TUNE_FILE"] = args.tune_file
+        print(json.dumps(per_step_comparison(args)), flush=True)
+        return
     # the CPU baseline first, before anything touches the GPU (its workers are forked)
     cpu = None
     if not args.no_cpu and args.workload == "combined":
