@@ -12,7 +12,7 @@ import pytest
 
 import workloads as W
 from oracle import fno as ofno
-from tests._common import desc_for
+from tests._common import desc_for, oracle_run, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -405,6 +405,57 @@ def test_trained_network_gains_over_extrapolation():
     print(f"iterations plain {its_p}, learned {its_l}", flush=True)
     assert sum(its_l) < sum(its_p), (its_p, its_l)
     tr.fno.close()
+
+
+def test_learned_trajectory_matches_oracle_within_tolerance():
+    """A trained network's gated learned guess over steps 11-30 of a
+    held-out PFC 64^2 trajectory (steps 1-10 with the extrapolated guess):
+    every step converges, the network runs on most of them, the mass is the
+    oracle's, and the trajectory stays within the accumulated PAGD tolerance
+    of the oracle's (extrapolated-guess) trajectory.  Each step's solution, from either guess, lies within about
+    kappa tol of the step problem's solution (kappa the conditioning of the
+    preconditioned problem, a few units), and a stable scheme carries such
+    differences on without growth beyond 1 + O(dt) per step: after n = 20
+    learned steps they stay below 2 kappa tol n = 2e-8 for kappa = 5.  The
+    learned steps take fewer PAGD iterations in total than the oracle's
+    steps 11-30."""
+    import torch
+    from paper_2204_07247_amd import learned, pfch
+    base = W.PFC64_MP
+    ws = [dataclasses.replace(base, seeds=(s,)) for s in range(100, 104)]
+    u0s = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    cfg = learned.TrainConfig(width=8, modes=8, layers=2, batch=8, epochs=25, lr=3e-3, seed=1)
+    print("train on 4 x 30 steps of pfc64", flush=True)
+    tr = learned.train(ws, u0s, 30, cfg)
+    w = dataclasses.replace(base, seeds=(7,))
+    u0 = W.initial_condition(w)
+    n0, n = 10, 20
+    ref, ref_iters = oracle_run(w, u0, n0 + n)
+    ref_iters = ref_iters[n0:]
+    ctx = pfch.Context([desc_for(w, guess=1)])
+    ctx.set_state(0, torch.from_numpy(u0).cuda())
+    for _ in range(n0):  # no network attached yet: the extrapolated guess
+        rc, st = ctx.step(w.dt)
+        assert rc == pfch.PFCH_OK and st[0]["guess"] == 0
+    ctx.set_fno(0, tr.fno, tr.norm)
+    kinds, iters = [], []
+    for _ in range(n):
+        rc, st = ctx.step(w.dt)
+        assert rc == pfch.PFCH_OK
+        kinds.append(st[0]["guess"])
+        iters.append(st[0]["iters"])
+    got = torch.empty(w.shape, dtype=torch.float64, device="cuda")
+    ctx.get_state(0, got)
+    ctx.close()
+    tr.fno.close()
+    got = got.cpu().numpy()
+    diff = float(np.max(np.abs(got - ref)))
+    print(f"guess kinds {kinds}; iterations learned {sum(iters)}, oracle {sum(ref_iters)}; "
+          f"max |u - u_oracle| {diff:.3e}, rel L2 {rel_l2(got, ref):.3e}", flush=True)
+    assert kinds.count(1) >= n // 2
+    assert diff <= 2.0 * 5.0 * w.tol * n
+    assert abs(float(got.mean()) - float(ref.mean())) <= 1e-13
+    assert sum(iters) < sum(ref_iters)
 
 
 def _smooth(shape, seed, mean, amp):
