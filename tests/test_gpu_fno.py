@@ -503,6 +503,48 @@ def test_coarse_learned_trajectory_matches_oracle_within_tolerance():
     assert abs(float(got.mean()) - float(ref.mean())) <= 1e-13
 
 
+def test_3d_learned_trajectory_matches_oracle_within_tolerance():
+    """PFC 3D (16 x 16 x 32, BDF2) with a 3D network trained on 4 x 20
+    steps: steps 6-15 of a held-out trajectory with the gated learned guess
+    converge, keep the oracle's mass and stay within the accumulated PAGD
+    tolerance (2 kappa tol n, kappa = 5) of the oracle's trajectory."""
+    import torch
+    from paper_2204_07247_amd import learned, pfch
+    base = dataclasses.replace(W.PFC192_3D, shape=(16, 16, 32), lengths=(16.0, 16.0, 32.0))
+    ws = [dataclasses.replace(base, seeds=(s,)) for s in range(300, 304)]
+    u0s = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    cfg = learned.TrainConfig(width=8, modes=4, layers=2, batch=4, epochs=10, lr=3e-3, seed=3)
+    print("train on 4 x 20 steps of pfc 16x16x32", flush=True)
+    tr = learned.train(ws, u0s, 20, cfg)
+    w = dataclasses.replace(base, seeds=(11,))
+    u0 = W.initial_condition(w)
+    n0, n = 5, 10
+    ref, ref_iters = oracle_run(w, u0, n0 + n)
+    ctx = pfch.Context([desc_for(w, guess=1)])
+    ctx.set_state(0, torch.from_numpy(u0).cuda())
+    for _ in range(n0):
+        rc, st = ctx.step(w.dt)
+        assert rc == pfch.PFCH_OK and st[0]["guess"] == 0
+    ctx.set_fno(0, tr.fno, tr.norm)
+    kinds, iters = [], []
+    for _ in range(n):
+        rc, st = ctx.step(w.dt)
+        assert rc == pfch.PFCH_OK
+        kinds.append(st[0]["guess"])
+        iters.append(st[0]["iters"])
+    got = torch.empty(w.shape, dtype=torch.float64, device="cuda")
+    ctx.get_state(0, got)
+    ctx.close()
+    tr.fno.close()
+    got = got.cpu().numpy()
+    diff = float(np.max(np.abs(got - ref)))
+    print(f"guess kinds {kinds}; iterations learned {sum(iters)}, oracle {sum(ref_iters[n0:])}; "
+          f"max |u - u_oracle| {diff:.3e}, rel L2 {rel_l2(got, ref):.3e}", flush=True)
+    assert kinds[:2] == [1, 1]
+    assert diff <= 2.0 * 5.0 * w.tol * n
+    assert abs(float(got.mean()) - float(ref.mean())) <= 1e-13
+
+
 def _smooth(shape, seed, mean, amp):
     rng = np.random.default_rng(seed)
     f = rng.uniform(-1, 1, shape)
