@@ -3,7 +3,9 @@
 (implicit midpoint) and of FCH 1024^2 and 2048^2 (backward Euler) against
 the oracle,
 field by field; then properties that hold at any size over further steps
-(convergence to the tolerance, exact mass; energy decrease for BDF2)."""
+(convergence to the tolerance, exact mass; energy decrease for BDF2);
+and the combined set batched against solo runs, with and without the
+learned guess."""
 import numpy as np
 import pytest
 
@@ -157,3 +159,61 @@ def test_pfc_ensemble_at_real_sizes():
         ref, ref_iters = oracle_run(w, W.initial_condition(w), 2)
         assert biters[i] == ref_iters, w.name
         assert rel_l2(batch[i].cpu().numpy(), ref) <= 1e-9, w.name
+
+
+def _run_set_learned(ws, fno, nsteps):
+    """All of ws in one context with the learned guess: the first step
+    (backward Euler, no history) with the extrapolated guess, then the
+    network attached to every instance (normalisation from its own state)
+    for nsteps - 1 more steps.  Final states, iteration counts and guess
+    kinds."""
+    import torch
+    from paper_2204_07247_amd import learned, pfch
+    ctx = pfch.Context([learned.desc_of(w, 1) for w in ws])
+    ctx.set_stats_detail(0)
+    us = [torch.from_numpy(W.initial_condition(w)).cuda() for w in ws]
+    for i, u in enumerate(us):
+        ctx.set_state(i, u)
+    iters = [[] for _ in ws]
+    kinds = [[] for _ in ws]
+    for n in range(nsteps):
+        if n == 1:
+            for i, u in enumerate(us):
+                un, unm1 = torch.empty_like(u), torch.empty_like(u)
+                ctx.get_state(i, un, unm1)
+                d = un - unm1
+                ctx.set_fno(i, fno, (float(un.mean()), float(un.std()), float(d.std()), 0.1 * float(d.std())))
+        rc, st = ctx.step([w.dt for w in ws])
+        assert rc == pfch.PFCH_OK, pfch.strerror(rc)
+        for i, s in enumerate(st):
+            iters[i].append(s["iters"])
+            kinds[i].append(s["guess"])
+    outs = []
+    for i, u in enumerate(us):
+        ctx.get_state(i, u)
+        outs.append(u)
+    ctx.close()
+    return outs, iters, kinds
+
+
+def test_combined_set_learned_batched_equals_solo():
+    """The 16 FCH instances of the combined set (1024^2 and 2048^2) with a
+    network on a 64^2 grid (band-limited resampling in and out, one batched
+    forward pass for all 16) in one context for three steps: every instance
+    bitwise equal to its own solo run, with the same iteration counts and
+    guess kinds (the extrapolated first step, then two learned steps)."""
+    import torch
+    from paper_2204_07247_amd import pfch
+    _tuned()
+    ws = W.fch_ensemble()
+    fno = pfch.Fno(8, 4, 2, 64, 64, max_batch=len(ws))
+    fno.init_params(seed=13)
+    print(f"combined FCH set, learned: {len(ws)} instances, 3 steps", flush=True)
+    batch, biters, bkinds = _run_set_learned(ws, fno, 3)
+    for w, got, it, kd in zip(ws, batch, biters, bkinds):
+        assert kd == [0, 1, 1], (w.name, kd)
+        print(f"solo {w.name}", flush=True)
+        (solo,), (siters,), (skinds,) = _run_set_learned([w], fno, 3)
+        assert (it, kd) == (siters, skinds), w.name
+        assert torch.equal(got, solo), w.name
+    fno.close()
