@@ -1,7 +1,7 @@
 """Parity at the bench sizes, in the launch configuration the bench uses
 (autotuned plans, the same context set-up): the first step of PFC 1024^2
 (implicit midpoint) and of FCH 1024^2 (backward Euler), and the first two
-steps of FCH 2048^2 (backward Euler, then BDF2), against the oracle,
+steps of FCH 2048^2, PFC 1024^2 and PFC 192^3, against the oracle,
 field by field; then properties that hold at any size over further steps
 (convergence to the tolerance, exact mass; energy decrease for BDF2);
 and the combined set batched against solo runs, with and without the
@@ -44,13 +44,16 @@ def test_first_step_matches_oracle_at_full_size(name):
     assert rel_l2(out.cpu().numpy(), ref) <= 1e-9
 
 
-def test_two_steps_match_oracle_at_2048():
+@pytest.mark.parametrize("name", ["fch2048", "pfc1024"])
+def test_two_steps_match_oracle_at_full_size(name):
     """FCH 2048^2: the backward Euler first step (set-up from transforms of
-    x0) and the BDF2 second step (set-up from the kept Laplacians) against
-    the oracle: iteration counts equal, relative L2 within the parity bar."""
+    x0) and the BDF2 second step (set-up from the kept Laplacians); PFC
+    1024^2: two implicit midpoint steps, the second from the extrapolated
+    guess; against the oracle: iteration counts equal, relative L2 within
+    the parity bar."""
     import torch
     from paper_2204_07247_amd import pfch
-    w = bench.WORKLOADS["fch2048"]
+    w = bench.WORKLOADS[name]
     print(f"full size {w.name}, 2 steps", flush=True)
     ctx, u0 = _ctx(w)
     iters = []
@@ -122,14 +125,14 @@ def _run_set(ws, nsteps):
     return outs, iters
 
 
-def test_3d_first_step_matches_oracle_at_full_size():
-    """PFC 192^3 (the 3D instance of the combined set): the first step
-    (backward Euler) field by field against the oracle."""
+def test_3d_first_steps_match_oracle_at_full_size():
+    """PFC 192^3 (the 3D instance of the combined set): the first two steps
+    (backward Euler, then BDF2) field by field against the oracle."""
     _tuned()
     w = W.PFC192_3D
-    print(f"full size {w.name}", flush=True)
-    (got,), (iters,) = _run_set([w], 1)
-    ref, ref_iters = oracle_run(w, W.initial_condition(w), 1)
+    print(f"full size {w.name}, 2 steps", flush=True)
+    (got,), (iters,) = _run_set([w], 2)
+    ref, ref_iters = oracle_run(w, W.initial_condition(w), 2)
     assert iters == ref_iters
     assert rel_l2(got.cpu().numpy(), ref) <= 1e-9
 
